@@ -1,0 +1,175 @@
+/*
+ * rbmc.h -- C ABI of the MI355X (gfx950) overlapping Rao-Blackwellized Monte
+ * Carlo (RBMC) library: marginal variances diag(Q^-1) and log-determinant
+ * gradients tr(Q^-1 dQ/dtheta_j) of a space-time Gaussian Markov random field
+ *
+ *     Q(theta) = Q_t (x) Q_s + A^T Q_y A
+ *
+ * following Zhumekenov, Krainski & Rue, "Parallel Selected Inversion for
+ * Space-Time Gaussian Markov Random Fields" (arXiv 2309.05435):
+ *   - posterior precision Q = Q_x + A^T Q_y A and marginals diag(Q^-1):
+ *     Sec. 2.3, eq:lgm:2 and eq:lgm:3;
+ *   - gradients d log|Q| / dtheta_j = tr(Q^-1 dQ_j) = sum_ik (Q^-1)_ik (dQ_j)_ik:
+ *     eq:lgm:4, eq:hyperpar:3 and eq:hyperpar:4;
+ *   - the estimator: overlapping RBMC, Alg. 3 (blocks) and Alg. 4 (diagonal);
+ *   - samples x ~ N(0, Q^-1) by a Krylov solver, Sec. 3.3 (here conjugate
+ *     gradients on the perturbed system Q x = F z, Sec. 2.4).
+ *
+ * Model (the separable case of Sec. 2.2): an mx x my grid on the unit square,
+ * h = 1/(max(mx,my)-1), lumped mass C = h^2 I, G = 5-point Neumann graph
+ * Laplacian (stiffness), Q_s = tau (kappa^4 C + 2 kappa^2 G + G C^-1 G)
+ * (eq:spde:4 with alpha = 2, read linear in tau); Q_t = the precision of a
+ * stationary unit-variance AR(1) with correlation rho over T steps; Q_y =
+ * sigma^-2 I on the observed space-time nodes.  theta = (log kappa, log tau,
+ * rho, log sigma).  Node index i = t*mx*my + iy*mx + ix (space fastest).
+ *
+ * Conventions for every call:
+ *   - return value: rbmc_status; 0 = ok, > 0 = warning (outputs valid),
+ *     < 0 = error (outputs undefined); rbmc_last_error() gives a message;
+ *   - pointers documented "device" are hipMalloc'd (or torch CUDA/HIP tensor)
+ *     memory on the context's device; "host" pointers are ordinary memory;
+ *     the caller owns every buffer it passes; the library never frees them
+ *     and keeps no pointer to them after the call returns;
+ *   - multi-vectors are column-major n x n_rhs: vector k occupies
+ *     [k*n, (k+1)*n) (a torch tensor of shape (n_rhs, n));
+ *   - work is ordered on the context's HIP stream; calls that produce
+ *     outputs synchronize that stream before returning;
+ *   - a context and its models are not thread-safe.
+ */
+#ifndef RBMC_H
+#define RBMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RBMC_OK = 0,
+  RBMC_W_NOT_CONVERGED = 1, /* PCG hit pcg_maxit for some sample; outputs computed */
+  RBMC_E_ARG = -1,          /* invalid argument (message says which) */
+  RBMC_E_NOT_SPD = -2,      /* a dense block lost positive definiteness (report says where) */
+  RBMC_E_OOM = -3,          /* device allocation failed */
+  RBMC_E_DEVICE = -4,       /* HIP runtime error */
+  RBMC_E_UNSUPPORTED = -5   /* option not built */
+} rbmc_status;
+
+typedef struct rbmc_ctx rbmc_ctx;     /* device id, stream, workspace, kernels */
+typedef struct rbmc_model rbmc_model; /* stencil coefficients, plan, factors */
+
+/* The model.  theta enters through log_kappa (kappa = sqrt(8)/range),
+ * log_tau, rho (|rho| < 1) and log_sigma.  obs_mask: host, length
+ * n = mx*my*T, 1 = observed (copied at creation). */
+typedef struct {
+  int32_t mx, my, T;
+  double h;
+  double log_kappa, log_tau, rho, log_sigma;
+  const uint8_t* obs_mask;
+} rbmc_model_desc;
+
+/* Cores Omega_p = time slabs x spatial boxes (Alg. 4 partitions the graph of
+ * Q into non-overlapping parts): T is split into n_tslabs slabs, mx into
+ * n_tiles_x and my into n_tiles_y pieces; in each split the first
+ * (len mod parts) pieces get one extra element.  Core p =
+ * (slab * n_tiles_y + tile_y) * n_tiles_x + tile_x.  Each core is grown by
+ * overlap_hops rounds of graph neighbours of Q to Omega_p* (Alg. 4); the
+ * separator is S_p = N(Omega_p*) \ Omega_p*.  The block-Jacobi PCG
+ * preconditioner uses the same cores as its blocks. */
+typedef struct {
+  int32_t n_tslabs, n_tiles_x, n_tiles_y, overlap_hops;
+} rbmc_decomp_desc;
+
+enum { RBMC_FP64 = 0, RBMC_MIXED = 1 };
+enum { RBMC_PC_BJ = 0, RBMC_PC_BJ_LEARNED = 1 };
+enum { RBMC_GRAD_LOGKAPPA = 1, RBMC_GRAD_LOGTAU = 2, RBMC_GRAD_RHO = 4, RBMC_GRAD_LOGSIGMA = 8 };
+
+typedef struct {
+  int32_t n_samples;  /* n_k >= 0 (0: deterministic part only) */
+  int32_t pcg_maxit;  /* > 0 */
+  double pcg_rtol;    /* per-sample ||b - Q x||_2 / ||b||_2 target, > 0 */
+  int32_t precision;  /* RBMC_FP64 | RBMC_MIXED */
+  int32_t precond;    /* RBMC_PC_BJ | RBMC_PC_BJ_LEARNED */
+  uint32_t grad_mask; /* RBMC_GRAD_* bits; traces are written in bit order */
+  int32_t sample_chunk; /* reserved, 0 */
+} rbmc_est_opts;
+
+typedef struct {
+  double t_sample, t_factor, t_takahashi, t_correct, t_total; /* seconds */
+  int32_t pcg_it_max;      /* iterations of the slowest sample */
+  double pcg_it_mean;      /* mean iterations over samples */
+  double max_rel_residual; /* max_k ||b_k - Q x_k|| / ||b_k|| (recurrence) */
+  double err_estimate;     /* plug-in mean relative MC error of diag */
+  int64_t peak_bytes;      /* device workspace held by the model */
+  int32_t fail_subdomain, fail_block; /* where a dense block lost SPD, else -1 */
+} rbmc_report;
+
+/* Create a context on HIP device `device`; hip_stream is a hipStream_t (NULL
+ * = the default stream).  The stream is not owned. */
+rbmc_status rbmc_ctx_create(int device, void* hip_stream, rbmc_ctx** out);
+void rbmc_ctx_destroy(rbmc_ctx* ctx);
+
+/* Build Q(theta) matrix-free (stencil coefficients on the device) and plan
+ * the decomposition: cores, Omega_p* and S_p per Alg. 4, block-Jacobi cores.
+ * Errors: RBMC_E_ARG for mx,my < 2, T < 1, h <= 0, |rho| >= 1, non-finite
+ * theta, decomposition counts outside [1, len], overlap_hops < 0. */
+rbmc_status rbmc_model_create(rbmc_ctx* ctx, const rbmc_model_desc* desc,
+                              const rbmc_decomp_desc* decomp, rbmc_model** out);
+void rbmc_model_destroy(rbmc_model* m);
+
+/* Replace theta; the plan is kept, factors are recomputed on next use. */
+rbmc_status rbmc_model_set_theta(rbmc_model* m, double log_kappa, double log_tau, double rho,
+                                 double log_sigma);
+
+/* Operators for y = Op x (device x, y; n_rhs columns):
+ *   RBMC_OP_Q: Q (n -> n); RBMC_OP_F: the perturbation map F with F F^T = Q,
+ *   input [z1 (n) ; z2 (n_obs, ascending observed index)] (n + n_obs -> n);
+ *   RBMC_OP_DQ_*: dQ/dtheta_j (n -> n). */
+enum {
+  RBMC_OP_Q = 0,
+  RBMC_OP_DQ_LOGKAPPA = 1,
+  RBMC_OP_DQ_LOGTAU = 2,
+  RBMC_OP_DQ_RHO = 3,
+  RBMC_OP_DQ_LOGSIGMA = 4,
+  RBMC_OP_F = 5
+};
+rbmc_status rbmc_apply_op(rbmc_model* m, int op, const double* x, double* y, int32_t n_rhs);
+
+/* Samples x_k = Q^-1 F z_k by block-Jacobi preconditioned conjugate
+ * gradients (Sec. 3.3; perturbation form, Sec. 2.4), x0 = 0, stopping per
+ * sample at ||b - Q x|| <= pcg_rtol ||b||.
+ * z: device, (n + n_obs) x n_samples; x: device, n x n_samples.
+ * Returns RBMC_W_NOT_CONVERGED if some sample hit pcg_maxit. */
+rbmc_status rbmc_sample(rbmc_model* m, const rbmc_est_opts* opts, const double* z, double* x,
+                        rbmc_report* rep);
+
+/* The estimator from given samples (Alg. 4 for the diagonal; Alg. 3 rows
+ * with eq:hyperpar:4 for the traces): for each core p,
+ *   diag_i = (Q_AA^-1)_ii + (1/n_k) sum_k (mu_k)_i^2,  i in Omega_p,
+ *   mu_k = Q_AA^-1 Q_AB x_k|B,  A = Omega_p*, B = S_p,
+ *   trace_j = sum_p sum_{i in Omega_p, c in A}
+ *             [(Q_AA^-1)_ic + (1/n_k) sum_k (mu_k)_i (mu_k)_c] (dQ_j)_ic.
+ * x: device n x n_samples (ignored when n_samples = 0); diag_out: device, n;
+ * trace_out: host, popcount(grad_mask) values (may be NULL if grad_mask = 0). */
+rbmc_status rbmc_estimate_from_samples(rbmc_model* m, const rbmc_est_opts* opts, const double* x,
+                                       double* diag_out, double* trace_out, rbmc_report* rep);
+
+/* rbmc_sample followed by rbmc_estimate_from_samples (the full hot path).
+ * z: device (n + n_obs) x n_samples standard normals (required; seed is
+ * reserved).  Workspace for x is held by the model. */
+rbmc_status rbmc_estimate(rbmc_model* m, const rbmc_est_opts* opts, const double* z, uint64_t seed,
+                          double* diag_out, double* trace_out, rbmc_report* rep);
+
+/* Planner query, host only (no device needed): core label of every node
+ * (label_out, length n) and, for core p, the node state (state_out, length
+ * n: 1 core, 2 overlap, 3 separator, 0 outside). Either output may be NULL. */
+rbmc_status rbmc_plan_query(const rbmc_model_desc* desc, const rbmc_decomp_desc* decomp, int32_t p,
+                            int32_t* label_out, uint8_t* state_out);
+
+/* Thread-local message of the last failing call ("" if none). */
+const char* rbmc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RBMC_H */

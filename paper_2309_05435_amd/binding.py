@@ -1,0 +1,243 @@
+"""Thin ctypes binding of librbmc.so (the C ABI declared in include/rbmc.h).
+
+Argument marshalling only: every step of the estimator runs in the HIP
+library.  PyTorch provides device memory and the HIP stream.  Loading fails
+loudly when the built library is missing; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librbmc.so")
+
+RBMC_OK, RBMC_W_NOT_CONVERGED = 0, 1
+RBMC_E_ARG, RBMC_E_NOT_SPD, RBMC_E_OOM, RBMC_E_DEVICE, RBMC_E_UNSUPPORTED = -1, -2, -3, -4, -5
+RBMC_FP64, RBMC_MIXED = 0, 1
+RBMC_PC_BJ, RBMC_PC_BJ_LEARNED = 0, 1
+RBMC_GRAD_LOGKAPPA, RBMC_GRAD_LOGTAU, RBMC_GRAD_RHO, RBMC_GRAD_LOGSIGMA = 1, 2, 4, 8
+(RBMC_OP_Q, RBMC_OP_DQ_LOGKAPPA, RBMC_OP_DQ_LOGTAU, RBMC_OP_DQ_RHO, RBMC_OP_DQ_LOGSIGMA,
+ RBMC_OP_F) = range(6)
+
+# every symbol include/rbmc.h declares
+EXPORTS = ["rbmc_ctx_create", "rbmc_ctx_destroy", "rbmc_model_create", "rbmc_model_destroy",
+           "rbmc_model_set_theta", "rbmc_apply_op", "rbmc_sample", "rbmc_estimate_from_samples",
+           "rbmc_estimate", "rbmc_plan_query", "rbmc_last_error"]
+
+
+class rbmc_model_desc(C.Structure):
+    _fields_ = [("mx", C.c_int32), ("my", C.c_int32), ("T", C.c_int32), ("h", C.c_double),
+                ("log_kappa", C.c_double), ("log_tau", C.c_double), ("rho", C.c_double),
+                ("log_sigma", C.c_double), ("obs_mask", C.POINTER(C.c_uint8))]
+
+
+class rbmc_decomp_desc(C.Structure):
+    _fields_ = [("n_tslabs", C.c_int32), ("n_tiles_x", C.c_int32), ("n_tiles_y", C.c_int32),
+                ("overlap_hops", C.c_int32)]
+
+
+class rbmc_est_opts(C.Structure):
+    _fields_ = [("n_samples", C.c_int32), ("pcg_maxit", C.c_int32), ("pcg_rtol", C.c_double),
+                ("precision", C.c_int32), ("precond", C.c_int32), ("grad_mask", C.c_uint32),
+                ("sample_chunk", C.c_int32)]
+
+
+class rbmc_report(C.Structure):
+    _fields_ = [("t_sample", C.c_double), ("t_factor", C.c_double), ("t_takahashi", C.c_double),
+                ("t_correct", C.c_double), ("t_total", C.c_double), ("pcg_it_max", C.c_int32),
+                ("pcg_it_mean", C.c_double), ("max_rel_residual", C.c_double),
+                ("err_estimate", C.c_double), ("peak_bytes", C.c_int64),
+                ("fail_subdomain", C.c_int32), ("fail_block", C.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() or "
+                               "python paper_2309_05435_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.rbmc_ctx_create.argtypes = [C.c_int, vp, C.POINTER(vp)]
+        L.rbmc_ctx_destroy.argtypes = [vp]
+        L.rbmc_ctx_destroy.restype = None
+        L.rbmc_model_create.argtypes = [vp, C.POINTER(rbmc_model_desc),
+                                        C.POINTER(rbmc_decomp_desc), C.POINTER(vp)]
+        L.rbmc_model_destroy.argtypes = [vp]
+        L.rbmc_model_destroy.restype = None
+        L.rbmc_model_set_theta.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_double]
+        L.rbmc_apply_op.argtypes = [vp, C.c_int, vp, vp, C.c_int32]
+        L.rbmc_sample.argtypes = [vp, C.POINTER(rbmc_est_opts), vp, vp, C.POINTER(rbmc_report)]
+        L.rbmc_estimate_from_samples.argtypes = [vp, C.POINTER(rbmc_est_opts), vp, vp,
+                                                 C.POINTER(C.c_double), C.POINTER(rbmc_report)]
+        L.rbmc_estimate.argtypes = [vp, C.POINTER(rbmc_est_opts), vp, C.c_uint64, vp,
+                                    C.POINTER(C.c_double), C.POINTER(rbmc_report)]
+        L.rbmc_plan_query.argtypes = [C.POINTER(rbmc_model_desc), C.POINTER(rbmc_decomp_desc),
+                                      C.c_int32, vp, vp]
+        L.rbmc_last_error.restype = C.c_char_p
+        for name in EXPORTS:
+            if name not in ("rbmc_ctx_destroy", "rbmc_model_destroy", "rbmc_last_error"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+class RbmcError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"rbmc status {status}: {msg}")
+        self.status = status
+
+
+def check(st):
+    if st < 0:
+        raise RbmcError(st, lib().rbmc_last_error().decode())
+    return st
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+# ---- thin wrappers with the C names ----------------------------------------
+
+def rbmc_ctx_create(device: int = 0, stream=None):
+    out = C.c_void_p()
+    check(lib().rbmc_ctx_create(device, stream, C.byref(out)))
+    return out
+
+
+def rbmc_ctx_destroy(ctx):
+    lib().rbmc_ctx_destroy(ctx)
+
+
+def rbmc_model_create(ctx, desc: rbmc_model_desc, decomp: rbmc_decomp_desc):
+    out = C.c_void_p()
+    check(lib().rbmc_model_create(ctx, C.byref(desc), C.byref(decomp), C.byref(out)))
+    return out
+
+
+def rbmc_model_destroy(m):
+    lib().rbmc_model_destroy(m)
+
+
+def rbmc_model_set_theta(m, log_kappa, log_tau, rho, log_sigma):
+    return check(lib().rbmc_model_set_theta(m, log_kappa, log_tau, rho, log_sigma))
+
+
+def rbmc_apply_op(m, op, x, y, n_rhs):
+    return check(lib().rbmc_apply_op(m, op, _ptr(x), _ptr(y), n_rhs))
+
+
+def rbmc_sample(m, opts, z, x):
+    rep = rbmc_report()
+    st = check(lib().rbmc_sample(m, C.byref(opts), _ptr(z), _ptr(x), C.byref(rep)))
+    return st, rep
+
+
+def rbmc_estimate_from_samples(m, opts, x, diag_out, n_trace):
+    rep = rbmc_report()
+    tr = (C.c_double * max(n_trace, 1))()
+    st = check(lib().rbmc_estimate_from_samples(m, C.byref(opts), _ptr(x), _ptr(diag_out),
+                                                tr if n_trace else None, C.byref(rep)))
+    return st, list(tr)[:n_trace], rep
+
+
+def rbmc_estimate(m, opts, z, seed, diag_out, n_trace):
+    rep = rbmc_report()
+    tr = (C.c_double * max(n_trace, 1))()
+    st = check(lib().rbmc_estimate(m, C.byref(opts), _ptr(z), seed, _ptr(diag_out),
+                                   tr if n_trace else None, C.byref(rep)))
+    return st, list(tr)[:n_trace], rep
+
+
+def rbmc_plan_query(desc, decomp, p, label_out=None, state_out=None):
+    """label_out / state_out: numpy int32 / uint8 arrays of length n (host)."""
+    lp = None if label_out is None else label_out.ctypes.data_as(C.c_void_p)
+    sp = None if state_out is None else state_out.ctypes.data_as(C.c_void_p)
+    return check(lib().rbmc_plan_query(C.byref(desc), C.byref(decomp), p, lp, sp))
+
+
+# ---- convenience ------------------------------------------------------------
+
+def make_desc(mx, my, T, h, theta, mask):
+    """mask: numpy uint8 array (kept alive by the returned tuple)."""
+    import numpy as np
+    mask = np.ascontiguousarray(mask, dtype=np.uint8)
+    d = rbmc_model_desc(mx, my, T, h, theta[0], theta[1], theta[2], theta[3],
+                        mask.ctypes.data_as(C.POINTER(C.c_uint8)))
+    return d, mask
+
+
+def make_opts(n_samples, pcg_maxit=2000, pcg_rtol=1e-8, grad_mask=0b111,
+              precision=RBMC_FP64, precond=RBMC_PC_BJ):
+    return rbmc_est_opts(n_samples, pcg_maxit, pcg_rtol, precision, precond, grad_mask, 0)
+
+
+def popcount(mask: int) -> int:
+    return bin(mask).count("1")
+
+
+class Model:
+    """Owns a context + model; inputs/outputs are torch tensors on the device."""
+
+    def __init__(self, wl, mask=None, theta=None, device: int = 0, decomp=None):
+        import torch
+        self.wl = wl
+        self.torch = torch
+        self.dev = torch.device("cuda", device)
+        stream = torch.cuda.current_stream(self.dev).cuda_stream
+        self.ctx = rbmc_ctx_create(device, C.c_void_p(stream))
+        mask = wl.mask() if mask is None else mask
+        th = wl.theta if theta is None else theta
+        self.desc, self._mask = make_desc(wl.m, wl.m, wl.T, wl.h, th, mask)
+        if decomp is None:
+            decomp = (wl.n_tslabs, wl.n_tiles, wl.n_tiles, wl.n_l)
+        self.decomp = rbmc_decomp_desc(*decomp)
+        self.m = rbmc_model_create(self.ctx, self.desc, self.decomp)
+        self.n = wl.m * wl.m * wl.T
+        self.n_obs = int(self._mask.sum())
+
+    def close(self):
+        if getattr(self, "m", None):
+            rbmc_model_destroy(self.m)
+            self.m = None
+        if getattr(self, "ctx", None):
+            rbmc_ctx_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        self.close()
+
+    def apply(self, op, x):
+        x = x.contiguous()
+        n_rhs = x.shape[0]
+        y = self.torch.empty((n_rhs, self.n), dtype=self.torch.float64, device=self.dev)
+        rbmc_apply_op(self.m, op, x, y, n_rhs)
+        return y
+
+    def sample(self, z, rtol=1e-8, maxit=5000):
+        z = z.contiguous()
+        x = self.torch.empty((z.shape[0], self.n), dtype=self.torch.float64, device=self.dev)
+        st, rep = rbmc_sample(self.m, make_opts(z.shape[0], maxit, rtol), z, x)
+        return x, st, rep
+
+    def estimate_from_samples(self, x, grad_mask=0b111):
+        n_k = 0 if x is None else x.shape[0]
+        diag = self.torch.empty(self.n, dtype=self.torch.float64, device=self.dev)
+        st, tr, rep = rbmc_estimate_from_samples(
+            self.m, make_opts(n_k, grad_mask=grad_mask), None if x is None else x.contiguous(),
+            diag, popcount(grad_mask))
+        return diag, tr, st, rep
+
+    def estimate(self, z, grad_mask=0b111, rtol=1e-8, maxit=5000):
+        diag = self.torch.empty(self.n, dtype=self.torch.float64, device=self.dev)
+        st, tr, rep = rbmc_estimate(self.m, make_opts(z.shape[0], maxit, rtol, grad_mask),
+                                    z.contiguous(), 0, diag, popcount(grad_mask))
+        return diag, tr, st, rep

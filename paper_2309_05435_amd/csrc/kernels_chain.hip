@@ -1,0 +1,236 @@
+// Kernels on chain panels: gather/scatter between global multi-vectors and
+// padded region panels, the correction right-hand sides Q_AB x_B, and the
+// reductions that turn dense Q_AA^-1 blocks and correction panels into the
+// estimator's diagonal and trace contributions.
+#include "rbmc_impl.h"
+
+namespace rbmc {
+
+namespace {
+constexpr int PT_N = 64;   // nodes per panel tile
+constexpr int PT_K = 64;   // samples per panel tile
+}  // namespace
+
+int panel_tiles(int np, int n_k) { return (np / PT_N) * ((n_k + PT_K - 1) / PT_K); }
+
+__global__ __launch_bounds__(256) void k_panels(const PanelTask* __restrict__ tasks, int n_tasks,
+                                                const RegionDev* __restrict__ regs, DevModel m,
+                                                const double* __restrict__ X,
+                                                double* __restrict__ Xout, int n_k) {
+  int lo = 0, hi = n_tasks - 1;
+  const int b = blockIdx.x;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) / 2;
+    if (tasks[mid].tile_start <= b) lo = mid; else hi = mid - 1;
+  }
+  const PanelTask tk = tasks[lo];
+  const RegionDev rg = regs[tk.region];
+  const int tile = b - tk.tile_start;
+  const int tiles_k = (n_k + PT_K - 1) / PT_K;
+  const int a = (tile / tiles_k) * PT_N + (threadIdx.x & 63);
+  const int kbase = (tile % tiles_k) * PT_K;
+  const bool real = a < rg.nb;
+  const int node = real ? rg.nodes[a] : 0;
+  const size_t base = (size_t)tk.t * m.ns + node;
+
+  if (tk.mode == 0) {
+    for (int kk = threadIdx.x >> 6; kk < PT_K; kk += 4) {
+      const int k = kbase + kk;
+      if (k >= n_k) break;
+      tk.P[(size_t)k * rg.np + a] = real ? X[(size_t)k * m.n + base] : 0.0;
+    }
+  } else if (tk.mode == 1) {
+    if (!real) return;
+    for (int kk = threadIdx.x >> 6; kk < PT_K; kk += 4) {
+      const int k = kbase + kk;
+      if (k >= n_k) break;
+      Xout[(size_t)k * m.n + base] = tk.P[(size_t)k * rg.np + a];
+    }
+  } else {
+    // r_a = sum over neighbours j of (t, node) outside A = [t0, t0+T) x R of Q_aj x_j
+    int idx[3 * kNS];
+    double cf[3 * kNS];
+    int cnt = 0;
+    if (real) {
+      const int ix = node % m.mx, iy = node / m.mx;
+      for (int dt = -1; dt <= 1; ++dt) {
+        const int tt = tk.t + dt;
+        if (tt < 0 || tt >= m.T) continue;
+        const double wt = (dt == 0) ? m.qd[tk.t] : m.qo;
+        const bool t_in = (tt >= tk.t0 && tt < tk.t0 + tk.T);
+        for (int q = 0; q < kNS; ++q) {
+          const int jx = ix + kSdx[q], jy = iy + kSdy[q];
+          if (jx < 0 || jx >= m.mx || jy < 0 || jy >= m.my) continue;
+          const bool s_in = rg.nbr[a * kNS + q] >= 0;
+          if (t_in && s_in) continue;
+          idx[cnt] = tt * m.ns + jy * m.mx + jx;
+          cf[cnt] = wt * m.qs[(size_t)q * m.ns + node];
+          ++cnt;
+        }
+      }
+    }
+    for (int kk = threadIdx.x >> 6; kk < PT_K; kk += 4) {
+      const int k = kbase + kk;
+      if (k >= n_k) break;
+      double v = 0.0;
+      for (int c = 0; c < cnt; ++c) v += cf[c] * X[(size_t)k * m.n + idx[c]];
+      tk.P[(size_t)k * rg.np + a] = v;
+    }
+  }
+}
+
+void launch_panels(const PanelTask* d_tasks, int n_tasks, int total_tiles, const RegionDev* regs,
+                   const DevModel& m, const double* X, double* Xout, int n_k, hipStream_t s) {
+  if (total_tiles <= 0) return;
+  k_panels<<<total_tiles, 256, 0, s>>>(d_tasks, n_tasks, regs, m, X, Xout, n_k);
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic-part extraction. One workgroup per 256 region rows.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_extract(const ExtractTask* __restrict__ tasks,
+                                                 int n_tasks,
+                                                 const RegionDev* __restrict__ regs,
+                                                 const uint8_t* const* __restrict__ in_box,
+                                                 DevModel m, double* __restrict__ diag_out,
+                                                 double* __restrict__ partial, int nchunk_max) {
+  __shared__ double red[3][256];
+  int lo = 0, hi = n_tasks - 1;
+  const int b = blockIdx.x;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) / 2;
+    if (tasks[mid].tile_start <= b) lo = mid; else hi = mid - 1;
+  }
+  const ExtractTask tk = tasks[lo];
+  const RegionDev rg = regs[tk.region];
+  const int chunk = b - tk.tile_start;
+  const int a = chunk * 256 + threadIdx.x;
+  double sd = 0.0, sq = 0.0, sk = 0.0;
+  if (a < rg.nb && in_box[tk.region][a]) {
+    const int node = rg.nodes[a];
+    auto el = [&](int r, int c) {  // Sigma block entry (r, c) in region-local indices
+      return tk.trans ? tk.M[(size_t)r * tk.ld + c] : tk.M[(size_t)c * tk.ld + r];
+    };
+    for (int q = 0; q < kNS; ++q) {
+      const int c = rg.nbr[a * kNS + q];
+      if (c < 0) continue;
+      const double v = tk.sign * el(a, c);
+      sq += m.qs[(size_t)q * m.ns + node] * v;
+      if (q < kN5) sk += m.kk[(size_t)q * m.ns + node] * v;
+      if (q == 0 && tk.kind == 0) {
+        const size_t i = (size_t)tk.t * m.ns + node;
+        diag_out[i] = v;
+        sd = m.dvec[i] * v;
+      }
+    }
+  }
+  red[0][threadIdx.x] = sd;
+  red[1][threadIdx.x] = sq;
+  red[2][threadIdx.x] = sk;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st)
+      for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x < 3)
+    partial[((size_t)tk.out_slot * nchunk_max + chunk) * 3 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+void launch_extract(const ExtractTask* d_tasks, int n_tasks, int total_tiles,
+                    const RegionDev* regs, const uint8_t* const* in_box, const DevModel& m,
+                    double* diag_out, double* partial, int nchunk_max, hipStream_t s) {
+  if (total_tiles <= 0) return;
+  k_extract<<<total_tiles, 256, 0, s>>>(d_tasks, n_tasks, regs, in_box, m, diag_out, partial,
+                                       nchunk_max);
+}
+
+// ---------------------------------------------------------------------------
+// Monte Carlo part. Workgroup = 64 region rows x all samples (4 sample lanes
+// per row).  Outputs: diag on core rows and 7 partial sums per workgroup:
+//   [0..2] mu_t . (Q_s mu_{t-1,t,t+1}), [3..5] mu_t . (K mu_{t-1,t,t+1}),
+//   [6] sum D mu_t^2, all divided by n_k.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_mc(const McTask* __restrict__ tasks, int n_tasks,
+                                            const RegionDev* __restrict__ regs,
+                                            const uint8_t* const* __restrict__ in_box,
+                                            DevModel m, int n_k, double* __restrict__ diag_out,
+                                            double* __restrict__ partial, int nchunk_max) {
+  __shared__ double red[8][256];
+  int lo = 0, hi = n_tasks - 1;
+  const int b = blockIdx.x;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) / 2;
+    if (tasks[mid].tile_start <= b) lo = mid; else hi = mid - 1;
+  }
+  const McTask tk = tasks[lo];
+  const RegionDev rg = regs[tk.region];
+  const int chunk = b - tk.tile_start;
+  const int a = chunk * 64 + (threadIdx.x & 63);
+  const int ks = threadIdx.x >> 6;
+  double acc[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+  if (a < rg.nb && in_box[tk.region][a]) {
+    const int node = rg.nodes[a];
+    const size_t i = (size_t)tk.t * m.ns + node;
+    const double dv = m.dvec[i];
+    int nbr[kNS];
+    double cq[kNS], ck[kN5];
+#pragma unroll
+    for (int q = 0; q < kNS; ++q) {
+      nbr[q] = rg.nbr[a * kNS + q];
+      cq[q] = m.qs[(size_t)q * m.ns + node];
+      if (q < kN5) ck[q] = m.kk[(size_t)q * m.ns + node];
+    }
+    for (int k = ks; k < n_k; k += 4) {
+      const size_t off = (size_t)k * tk.np;
+      const double mu = tk.mu[1][off + a];
+      acc[7] += mu * mu;
+      acc[6] += dv * mu * mu;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const double* pm = tk.mu[d];
+        if (!pm) continue;
+        double vq = 0.0, vk = 0.0;
+#pragma unroll
+        for (int q = 0; q < kNS; ++q) {
+          if (nbr[q] < 0) continue;
+          const double y = pm[off + nbr[q]];
+          vq += cq[q] * y;
+          if (q < kN5) vk += ck[q] * y;
+        }
+        acc[d] += mu * vq;
+        acc[3 + d] += mu * vk;
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 8; ++c) red[c][threadIdx.x] = acc[c];
+  __syncthreads();
+  // diagonal: combine the 4 sample lanes of each row in a fixed order
+  if (threadIdx.x < 64 && a < rg.nb && in_box[tk.region][a]) {
+    const double s = (red[7][threadIdx.x] + red[7][threadIdx.x + 64]) +
+                     (red[7][threadIdx.x + 128] + red[7][threadIdx.x + 192]);
+    diag_out[(size_t)tk.t * m.ns + rg.nodes[a]] += s / n_k;
+  }
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st)
+      for (int c = 0; c < 7; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x < 7)
+    partial[((size_t)tk.out_slot * nchunk_max + chunk) * 7 + threadIdx.x] =
+        red[threadIdx.x][0] / n_k;
+}
+
+void launch_mc(const McTask* d_tasks, int n_tasks, int total_tiles, const RegionDev* regs,
+               const uint8_t* const* in_box, const DevModel& m, int n_k, double* diag_out,
+               double* partial, int nchunk_max, hipStream_t s) {
+  if (total_tiles <= 0) return;
+  k_mc<<<total_tiles, 256, 0, s>>>(d_tasks, n_tasks, regs, in_box, m, n_k, diag_out, partial,
+                                   nchunk_max);
+}
+
+}  // namespace rbmc

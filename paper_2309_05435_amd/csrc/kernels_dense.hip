@@ -1,0 +1,418 @@
+// Dense FP64 kernels for the spatial blocks of the block-tridiagonal chains:
+//   - grouped GEMM on the FP64 matrix cores (v_mfma_f64_16x16x4f64);
+//   - in-place inversion of SPD blocks by the block Gauss-Jordan sweep,
+//     whose rank-64 updates also run on the matrix cores;
+//   - products of the restricted 13-point stencil Q_R with dense blocks.
+// Dense blocks are column-major, padded to multiples of 64 with identity on
+// the padded diagonal.
+#include "rbmc_impl.h"
+
+namespace rbmc {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// FP64 16x16x4 matrix-core product. Lane l supplies A[l%16][l/16] and
+// B[l/16][l%16]; accumulator register i of lane l holds C[l/16 + 4 i][l%16].
+__device__ inline v4d mfma64(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// Grouped GEMM.  Workgroup tile 128 x 128 (four waves of 64 x 64), BK = 16.
+// LDS holds A and B tiles with k contiguous per row/column (stride 18 to
+// spread banks).  In MFMA step s lane group g = l/16 contributes k = 4g + s,
+// so each lane reads its four k values of a row with one 32-byte access.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int GBM = 128, GBN = 128, GBK = 16, GLDS = GBK + 2;
+}
+
+__global__ __launch_bounds__(256) void k_gemm_f64(const GemmTask* __restrict__ tasks,
+                                                  int n_tasks) {
+  __shared__ double As[GBM * GLDS];
+  __shared__ double Bs[GBN * GLDS];
+  // locate the task of this workgroup
+  int lo = 0, hi = n_tasks - 1;
+  const int b = blockIdx.x;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) / 2;
+    if (tasks[mid].tile_start <= b) lo = mid; else hi = mid - 1;
+  }
+  const GemmTask tk = tasks[lo];
+  const int tile = b - tk.tile_start;
+  const int m0 = (tile / tk.tiles_n) * GBM, n0 = (tile % tk.tiles_n) * GBN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int l16 = lane & 15, g = lane >> 4;
+
+  v4d acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+
+  for (int k0 = 0; k0 < tk.K; k0 += GBK) {
+    // ---- A tile: As[m][k] = op(A)[m0+m][k0+k]
+    if (!tk.transA) {
+      const int kk = tid >> 4, mm = (tid & 15) * 8;
+      const int gm = m0 + mm;
+      const double* src = tk.A + (size_t)(k0 + kk) * tk.lda + gm;
+#pragma unroll
+      for (int j = 0; j < 8; j += 2) {
+        double2 v = (gm + j < tk.M) ? *(const double2*)(src + j) : double2{0.0, 0.0};
+        As[(mm + j) * GLDS + kk] = v.x;
+        As[(mm + j + 1) * GLDS + kk] = v.y;
+      }
+    } else {
+      const int mm = tid >> 1, kk = (tid & 1) * 8;
+      const int gm = m0 + mm;
+      const double* src = tk.A + (size_t)gm * tk.lda + k0 + kk;
+#pragma unroll
+      for (int j = 0; j < 8; j += 2) {
+        double2 v = (gm < tk.M) ? *(const double2*)(src + j) : double2{0.0, 0.0};
+        *(double2*)&As[mm * GLDS + kk + j] = v;
+      }
+    }
+    // ---- B tile: Bs[n][k] = op(B)[k0+k][n0+n]
+    if (!tk.transB) {
+      const int nn = tid >> 1, kk = (tid & 1) * 8;
+      const int gn = n0 + nn;
+      const double* src = tk.B + (size_t)gn * tk.ldb + k0 + kk;
+#pragma unroll
+      for (int j = 0; j < 8; j += 2) {
+        double2 v = (gn < tk.N) ? *(const double2*)(src + j) : double2{0.0, 0.0};
+        *(double2*)&Bs[nn * GLDS + kk + j] = v;
+      }
+    } else {
+      const int kk = tid >> 4, nn = (tid & 15) * 8;
+      const int gn = n0 + nn;
+      const double* src = tk.B + (size_t)(k0 + kk) * tk.ldb + gn;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        double v = (gn + j < tk.N) ? src[j] : 0.0;
+        Bs[(nn + j) * GLDS + kk] = v;
+      }
+    }
+    __syncthreads();
+    double a[4][4], bb[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double* pa = &As[(wm + i * 16 + l16) * GLDS + 4 * g];
+      double2 x0 = *(const double2*)pa, x1 = *(const double2*)(pa + 2);
+      a[i][0] = x0.x; a[i][1] = x0.y; a[i][2] = x1.x; a[i][3] = x1.y;
+      const double* pb = &Bs[(wn + i * 16 + l16) * GLDS + 4 * g];
+      double2 y0 = *(const double2*)pb, y1 = *(const double2*)(pb + 2);
+      bb[i][0] = y0.x; bb[i][1] = y0.y; bb[i][2] = y1.x; bb[i][3] = y1.y;
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = mfma64(a[i][s], bb[j][s], acc[i][j]);
+    __syncthreads();
+  }
+  // ---- epilogue: C = alpha acc + beta Cin
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int gn = n0 + wn + j * 16 + l16;
+      if (gn >= tk.N) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + wm + i * 16 + g + 4 * r;
+        if (gm >= tk.M) continue;
+        double v = tk.alpha * acc[i][j][r];
+        if (tk.beta != 0.0) v += tk.beta * tk.Cin[(size_t)gn * tk.ldcin + gm];
+        tk.C[(size_t)gn * tk.ldc + gm] = v;
+      }
+    }
+}
+
+void launch_gemm(const GemmTask* d_tasks, int n_tasks, int total_tiles, hipStream_t s) {
+  if (total_tiles <= 0) return;
+  k_gemm_f64<<<total_tiles, 256, 0, s>>>(d_tasks, n_tasks);
+}
+
+// ---------------------------------------------------------------------------
+// SPD inversion by the block Gauss-Jordan sweep (block size 64).
+// Sweeping pivot block k of a symmetric M:
+//   M_kk <- -M_kk^-1, M_ik <- M_ik M_kk^-1, M_kj <- M_kk^-1 M_kj,
+//   M_ij <- M_ij - M_ik M_kk^-1 M_kj   (i, j != k);
+// after all pivots M holds -A^-1.  Pivot blocks are Schur complements of an
+// SPD matrix, hence SPD.  Only the lower block triangle is kept current.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int JB = 64;
+constexpr int JLD = JB + 1;
+
+// In-LDS sweep of a 64x64 SPD block P (ld JLD): P <- P^-1.  Returns false on
+// a non-positive pivot.
+__device__ bool lds_spd_inverse(double* P, double* rowp, double* colp, int tid) {
+  bool ok = true;
+  for (int p = 0; p < JB; ++p) {
+    __syncthreads();
+    const double piv = P[p * JLD + p];
+    if (!(piv > 0.0)) ok = false;
+    if (tid < JB) {
+      rowp[tid] = P[p * JLD + tid];
+      colp[tid] = P[tid * JLD + p];
+    }
+    __syncthreads();
+    const double ip = 1.0 / piv;
+    for (int e = tid; e < JB * JB; e += 256) {
+      const int r = e / JB, c = e % JB;
+      double v;
+      if (r == p && c == p) v = -ip;
+      else if (r == p) v = rowp[c] * ip;
+      else if (c == p) v = colp[r] * ip;
+      else v = P[r * JLD + c] - colp[r] * rowp[c] * ip;
+      P[r * JLD + c] = v;
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < JB * JB; e += 256) P[(e / JB) * JLD + e % JB] = -P[(e / JB) * JLD + e % JB];
+  __syncthreads();
+  return ok;
+}
+}  // namespace
+
+// Pivot/panel kernel: grid (np/64 row blocks, tasks).  Every workgroup
+// inverts the pivot block (cheap, avoids a launch), forms
+//   B_i = M_ik (lower-stored: i > k from M, i < k from M_ki^T, i = k: M_kk),
+//   U_i = B_i M_kk^-1  (U_k = M_kk^-1)
+// and writes B_i, U_i to the task's panels.
+__global__ __launch_bounds__(256) void k_gj_panel(const InvTask* __restrict__ tasks, int kblk) {
+  __shared__ double P[JB * JLD];
+  __shared__ double Bt[JB * JLD];
+  __shared__ double rowp[JB], colp[JB];
+  const InvTask tk = tasks[blockIdx.y];
+  const int nblk = tk.np / JB;
+  if (kblk >= nblk) return;
+  const int i = blockIdx.x;
+  if (i >= nblk) return;
+  const int tid = threadIdx.x;
+  const int kb = kblk * JB, ib = i * JB;
+  const int np = tk.np;
+  // pivot block from the lower triangle, symmetrized
+  for (int e = tid; e < JB * JB; e += 256) {
+    const int r = e % JB, c = e / JB;
+    const int rr = r > c ? r : c, cc = r > c ? c : r;
+    P[r * JLD + c] = tk.M[(size_t)(kb + cc) * np + kb + rr];
+  }
+  // B_i
+  for (int e = tid; e < JB * JB; e += 256) {
+    const int r = e % JB, c = e / JB;
+    double v;
+    if (i > kblk) v = tk.M[(size_t)(kb + c) * np + ib + r];
+    else if (i < kblk) v = tk.M[(size_t)(ib + r) * np + kb + c];
+    else {
+      const int rr = r > c ? r : c, cc = r > c ? c : r;
+      v = tk.M[(size_t)(kb + cc) * np + kb + rr];
+    }
+    Bt[r * JLD + c] = v;
+  }
+  const bool ok = lds_spd_inverse(P, rowp, colp, tid);
+  if (!ok && i == 0 && tid == 0) atomicCAS(tk.info, 0, kblk + 1);
+  // U_i = B_i P  (i != k);  U_k = P
+  for (int e = tid; e < JB * JB; e += 256) {
+    const int r = e % JB, c = e / JB;
+    double v = 0.0;
+    if (i == kblk) v = P[r * JLD + c];
+    else {
+      for (int q = 0; q < JB; ++q) v += Bt[r * JLD + q] * P[q * JLD + c];
+    }
+    tk.U[(size_t)c * np + ib + r] = v;
+    tk.Bp[(size_t)c * np + ib + r] = Bt[r * JLD + c];
+  }
+}
+
+// Rank-64 update of the lower block triangle: grid (lower tiles, tasks).
+//   tile (i, j), i >= j:
+//     i, j != k : M_ij -= U_i B_j^T
+//     i > k = j : M_ik  = U_i
+//     i = k > j : M_kj  = U_j^T
+//     i = j = k : M_kk  = -U_k
+__global__ __launch_bounds__(256) void k_gj_update(const InvTask* __restrict__ tasks, int kblk) {
+  __shared__ double Us[JB * JLD];
+  __shared__ double Bs[JB * JLD];
+  const InvTask tk = tasks[blockIdx.y];
+  const int nblk = tk.np / JB;
+  if (kblk >= nblk) return;
+  // lower-triangle tile index -> (i, j)
+  const int t = blockIdx.x;
+  if (t >= nblk * (nblk + 1) / 2) return;
+  int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((i + 1) * (i + 2) / 2 <= t) ++i;
+  while (i * (i + 1) / 2 > t) --i;
+  const int j = t - i * (i + 1) / 2;
+  const int np = tk.np, ib = i * JB, jb = j * JB;
+  const int tid = threadIdx.x;
+  double* Mt = tk.M;
+  if (i == kblk || j == kblk) {
+    for (int e = tid; e < JB * JB; e += 256) {
+      const int r = e % JB, c = e / JB;
+      double v;
+      if (i == kblk && j == kblk) v = -tk.U[(size_t)c * np + kblk * JB + r];
+      else if (j == kblk) v = tk.U[(size_t)c * np + ib + r];
+      else v = tk.U[(size_t)r * np + jb + c];
+      Mt[(size_t)(jb + c) * np + ib + r] = v;
+    }
+    return;
+  }
+  // stage U_i (rows of tile) and B_j with k contiguous: Us[r][q] = U[ib+r][q], Bs[c][q] = B[jb+c][q]
+  for (int e = tid; e < JB * JB; e += 256) {
+    const int r = e % JB, q = e / JB;
+    Us[r * JLD + q] = tk.U[(size_t)q * np + ib + r];
+    Bs[r * JLD + q] = tk.Bp[(size_t)q * np + jb + r];
+  }
+  __syncthreads();
+  // wave w owns rows 16w..16w+15 and all 64 columns (four 16x16 MFMA tiles)
+  const int lane = tid & 63, w = tid >> 6, l16 = lane & 15, g = lane >> 4;
+  v4d acc[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) acc[c] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < JB; k0 += 4) {
+    const double a = Us[(w * 16 + l16) * JLD + k0 + g];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] = mfma64(a, Bs[(c * 16 + l16) * JLD + k0 + g], acc[c]);
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = ib + w * 16 + g + 4 * r, col = jb + c * 16 + l16;
+      Mt[(size_t)col * np + row] -= acc[c][r];
+    }
+}
+
+// M (holding -A^-1 in its lower triangle) -> A^-1, full symmetric
+__global__ void k_gj_finish(const InvTask* __restrict__ tasks) {
+  const InvTask tk = tasks[blockIdx.y];
+  const int np = tk.np;
+  const size_t tot = (size_t)np * np;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e % np), c = (int)(e / np);
+    if (r >= c) {
+      const double v = -tk.M[(size_t)c * np + r];
+      tk.M[(size_t)c * np + r] = v;
+      if (r != c) tk.M[(size_t)r * np + c] = v;
+    }
+  }
+}
+
+void launch_spd_inverse(const std::vector<InvTask>& tasks, InvTask* d_tasks, hipStream_t s) {
+  if (tasks.empty()) return;
+  int maxblk = 0;
+  for (const InvTask& t : tasks) maxblk = std::max(maxblk, t.np / JB);
+  const int ntask = (int)tasks.size();
+  for (int k = 0; k < maxblk; ++k) {
+    k_gj_panel<<<dim3(maxblk, ntask), 256, 0, s>>>(d_tasks, k);
+    k_gj_update<<<dim3(maxblk * (maxblk + 1) / 2, ntask), 256, 0, s>>>(d_tasks, k);
+  }
+  k_gj_finish<<<dim3(1024, ntask), 256, 0, s>>>(d_tasks);
+}
+
+// ---------------------------------------------------------------------------
+// Restricted-stencil products: out = alpha Q_R op(M) + gamma Q_R + diag(dv)
+//                                    (+ I on the padded diagonal) + beta In
+// on 64 x 64 output tiles; rows are region nodes (padded to np).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_rstencil(const StencilTask* __restrict__ tasks,
+                                                  int n_tasks, const RegionDev* __restrict__ regs,
+                                                  const double* __restrict__ qs, int ns) {
+  __shared__ double tileT[64 * 65];
+  int lo = 0, hi = n_tasks - 1;
+  const int b = blockIdx.x;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) / 2;
+    if (tasks[mid].tile_start <= b) lo = mid; else hi = mid - 1;
+  }
+  const StencilTask tk = tasks[lo];
+  const RegionDev rg = regs[tk.region];
+  const int tile = b - tk.tile_start;
+  const int tiles_c = (tk.ncols + 63) / 64;
+  const int a0 = (tile / tiles_c) * 64, c0 = (tile % tiles_c) * 64;
+  const int tid = threadIdx.x;
+  const bool square = (tk.dv != nullptr) || tk.pad_identity || tk.gamma != 0.0;
+
+  auto extra = [&](int a, int c, double v) {
+    if (a < rg.nb) {
+      if (tk.gamma != 0.0 && c < rg.nb) {
+        const int node = rg.nodes[a];
+#pragma unroll
+        for (int q = 0; q < kNS; ++q)
+          if (rg.nbr[a * kNS + q] == c) v += tk.gamma * qs[(size_t)q * ns + node];
+      }
+      if (tk.dv && a == c) v += tk.dv[rg.nodes[a]];
+    } else if (tk.pad_identity && a == c) {
+      v += 1.0;
+    }
+    if (tk.beta != 0.0) v += tk.beta * tk.In[(size_t)c * tk.ldin + a];
+    return v;
+  };
+  (void)square;
+
+  if (!tk.trans) {
+    // thread -> row a (fast), 16 columns
+    const int a = a0 + (tid & 63);
+    int nbr[kNS];
+    double cf[kNS];
+    const bool real = a < rg.nb;
+    if (real) {
+      const int node = rg.nodes[a];
+#pragma unroll
+      for (int q = 0; q < kNS; ++q) {
+        nbr[q] = rg.nbr[a * kNS + q];
+        cf[q] = qs[(size_t)q * ns + node];
+      }
+    }
+    for (int cc = (tid >> 6); cc < 64; cc += 4) {
+      const int c = c0 + cc;
+      if (c >= tk.ncols) break;
+      double v = 0.0;
+      if (real && tk.alpha != 0.0) {
+        const double* mc = tk.M + (size_t)c * tk.ldm;
+#pragma unroll
+        for (int q = 0; q < kNS; ++q)
+          if (nbr[q] >= 0) v += cf[q] * mc[nbr[q]];
+        v *= tk.alpha;
+      }
+      tk.out[(size_t)c * tk.ldout + a] = extra(a, c, v);
+    }
+  } else {
+    // thread -> column c (fast), 16 rows; transpose through LDS for the store
+    const int cl = tid & 63, c = c0 + cl;
+    for (int ar = (tid >> 6); ar < 64; ar += 4) {
+      const int a = a0 + ar;
+      double v = 0.0;
+      if (a < rg.nb && c < tk.ncols && tk.alpha != 0.0) {
+        const int node = rg.nodes[a];
+#pragma unroll
+        for (int q = 0; q < kNS; ++q) {
+          const int nb = rg.nbr[a * kNS + q];
+          if (nb >= 0) v += qs[(size_t)q * ns + node] * tk.M[(size_t)nb * tk.ldm + c];
+        }
+        v *= tk.alpha;
+      }
+      tileT[ar * 65 + cl] = v;
+    }
+    __syncthreads();
+    const int al = tid & 63, a = a0 + al;
+    for (int cc = (tid >> 6); cc < 64; cc += 4) {
+      const int c2 = c0 + cc;
+      if (c2 >= tk.ncols) break;
+      tk.out[(size_t)c2 * tk.ldout + a] = extra(a, c2, tileT[al * 65 + cc]);
+    }
+  }
+}
+
+void launch_rstencil(const StencilTask* d_tasks, int n_tasks, int total_tiles,
+                     const RegionDev* d_regions, const double* qs, int ns, hipStream_t s) {
+  if (total_tiles <= 0) return;
+  k_rstencil<<<total_tiles, 256, 0, s>>>(d_tasks, n_tasks, d_regions, qs, ns);
+}
+
+}  // namespace rbmc

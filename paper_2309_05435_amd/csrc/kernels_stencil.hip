@@ -1,0 +1,308 @@
+// Matrix-free space-time operators and the PCG vector kernels.
+//
+// Q = Q_t (x) Q_s + D is applied as a 3-point time combination followed by
+// the 13-point spatial stencil of Q_s:
+//   (Q x)_t = Q_s (q_{t,t-1} x_{t-1} + q_{t,t} x_t + q_{t,t+1} x_{t+1}) + D_t x_t.
+// A workgroup owns a 32 x 16 spatial tile of one right-hand side and walks
+// through time, keeping the three time layers of the tile (with a halo of 2)
+// in LDS, so each x value is read from HBM once per application.
+#include "rbmc_impl.h"
+
+namespace rbmc {
+
+namespace {
+
+constexpr int TX = 32, TY = 16, HX = TX + 4, HY = TY + 4;
+constexpr int NTHR = 256;
+
+struct OpW {
+  int kind;  // 0: Q, 1: dlogkappa, 2: dlogtau, 3: drho, 4: dlogsigma, 5: F
+};
+
+// Weights of the time combination for output step t.
+__device__ inline void time_weights(const DevModel& m, int kind, int t, double& wm, double& w0,
+                                    double& wp) {
+  if (kind == 3) {
+    wm = m.dqo;
+    w0 = m.dqd[t];
+    wp = m.dqo;
+  } else if (kind == 5) {
+    wm = 0.0;  // F_t = L^T: (t,t) -> L_tt, (t,t+1) -> L_{t+1,t}
+    w0 = m.ld[t];
+    wp = m.lo;
+  } else if (kind == 4) {
+    wm = 0.0;
+    w0 = 0.0;
+    wp = 0.0;
+  } else {
+    wm = m.qo;
+    w0 = m.qd[t];
+    wp = m.qo;
+  }
+  if (t == 0) wm = 0.0;
+  if (t == m.T - 1) wp = 0.0;
+}
+
+template <int KIND, bool DOT>
+__global__ __launch_bounds__(NTHR) void k_space_time_op(DevModel m, const double* __restrict__ x,
+                                                        double* __restrict__ y, int ldx,
+                                                        double* __restrict__ partial,
+                                                        int nchunk) {
+  __shared__ double slot[3][HY][HX];
+  __shared__ double w[HY][HX];
+  __shared__ double red[NTHR];
+  const int ntx = (m.mx + TX - 1) / TX;
+  const int tile = blockIdx.x;
+  const int bx = (tile % ntx) * TX, by = (tile / ntx) * TY;
+  const int k = blockIdx.y;
+  const double* xk = x + (size_t)k * ldx;
+  double* yk = y + (size_t)k * m.n;
+  const int tid = threadIdx.x;
+  const int lx = tid % TX, ly = tid / TX;  // ly in [0, 8): rows ly and ly + 8
+
+  auto load_layer = [&](int buf, int t) {
+    for (int e = tid; e < HX * HY; e += NTHR) {
+      int hx = e % HX, hy = e / HX;
+      int gx = bx + hx - 2, gy = by + hy - 2;
+      double v = 0.0;
+      if (t >= 0 && t < m.T && gx >= 0 && gx < m.mx && gy >= 0 && gy < m.my)
+        v = xk[(size_t)t * m.ns + gy * m.mx + gx];
+      slot[buf][hy][hx] = v;
+    }
+  };
+
+  double acc = 0.0;
+  // the layer of step t lives in slot t mod 3 (step -1 in slot 2)
+  if (KIND != 4) {
+    load_layer(2, -1);
+    load_layer(0, 0);
+  }
+  for (int t = 0; t < m.T; ++t) {
+    const int bm = (t + 2) % 3, b0 = t % 3, bp = (t + 1) % 3;  // t-1, t, t+1
+    if (KIND != 4) {
+      load_layer(bp, t + 1);
+      __syncthreads();
+      double wm, w0, wp;
+      time_weights(m, KIND, t, wm, w0, wp);
+      for (int e = tid; e < HX * HY; e += NTHR) {
+        int hx = e % HX, hy = e / HX;
+        w[hy][hx] = wm * slot[bm][hy][hx] + w0 * slot[b0][hy][hx] + wp * slot[bp][hy][hx];
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      const int gx = bx + lx, gy = by + ly + 8 * half;
+      if (gx < m.mx && gy < m.my) {
+        const int s = gy * m.mx + gx;
+        const size_t i = (size_t)t * m.ns + s;
+        const int hx = lx + 2, hy = ly + 8 * half + 2;
+        double v = 0.0;
+        if (KIND == 0 || KIND == 2 || KIND == 3) {
+#pragma unroll
+          for (int q = 0; q < kNS; ++q) v += m.qs[(size_t)q * m.ns + s] * w[hy + kSdy[q]][hx + kSdx[q]];
+        } else if (KIND == 1) {
+#pragma unroll
+          for (int q = 0; q < kN5; ++q) v += m.kk[(size_t)q * m.ns + s] * w[hy + kSdy[q]][hx + kSdx[q]];
+        } else if (KIND == 5) {
+#pragma unroll
+          for (int q = 0; q < kN5; ++q) v += m.fs[(size_t)q * m.ns + s] * w[hy + kSdy[q]][hx + kSdx[q]];
+          int r = m.obs_rank[i];
+          if (r >= 0) v += sqrt(m.dvec[i]) * xk[(size_t)m.n + r];
+        }
+        if (KIND == 0) v += m.dvec[i] * slot[b0][hy][hx];
+        if (KIND == 4) v = -2.0 * m.dvec[i] * xk[i];
+        yk[i] = v;
+        if (DOT) acc += v * xk[i];
+      }
+    }
+    if (KIND != 4) __syncthreads();
+  }
+  if (DOT) {
+    red[tid] = acc;
+    __syncthreads();
+    for (int st = NTHR / 2; st > 0; st >>= 1) {
+      if (tid < st) red[tid] += red[tid + st];
+      __syncthreads();
+    }
+    if (tid == 0) partial[(size_t)k * nchunk + tile] = red[0];
+  }
+}
+
+int n_tiles(const DevModel& m) { return ((m.mx + TX - 1) / TX) * ((m.my + TY - 1) / TY); }
+
+}  // namespace
+
+void launch_apply_op(const DevModel& m, int op, const double* x, double* y, int n_rhs,
+                     hipStream_t s) {
+  dim3 grid(n_tiles(m), n_rhs);
+  int ldx = (op == RBMC_OP_F) ? m.n + m.n_obs : m.n;
+  switch (op) {
+    case RBMC_OP_Q: k_space_time_op<0, false><<<grid, NTHR, 0, s>>>(m, x, y, ldx, nullptr, 0); break;
+    case RBMC_OP_DQ_LOGKAPPA: k_space_time_op<1, false><<<grid, NTHR, 0, s>>>(m, x, y, ldx, nullptr, 0); break;
+    case RBMC_OP_DQ_LOGTAU: k_space_time_op<2, false><<<grid, NTHR, 0, s>>>(m, x, y, ldx, nullptr, 0); break;
+    case RBMC_OP_DQ_RHO: k_space_time_op<3, false><<<grid, NTHR, 0, s>>>(m, x, y, ldx, nullptr, 0); break;
+    case RBMC_OP_DQ_LOGSIGMA: k_space_time_op<4, false><<<grid, NTHR, 0, s>>>(m, x, y, ldx, nullptr, 0); break;
+    case RBMC_OP_F: k_space_time_op<5, false><<<grid, NTHR, 0, s>>>(m, x, y, ldx, nullptr, 0); break;
+    default: break;
+  }
+}
+
+int spmm_chunks(const DevModel& m) { return n_tiles(m); }
+
+void launch_spmm_dot(const DevModel& m, const double* p, double* q, double* partial, int n_rhs,
+                     hipStream_t s) {
+  dim3 grid(n_tiles(m), n_rhs);
+  k_space_time_op<0, true><<<grid, NTHR, 0, s>>>(m, p, q, m.n, partial, n_tiles(m));
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic per-column reductions: partial[k * nchunk + c] -> out[k]
+// ---------------------------------------------------------------------------
+
+__global__ void k_reduce_partials(const double* __restrict__ partial, int nchunk,
+                                  double* __restrict__ out) {
+  __shared__ double red[256];
+  const int k = blockIdx.x, tid = threadIdx.x;
+  double a = 0.0;
+  for (int c = tid; c < nchunk; c += 256) a += partial[(size_t)k * nchunk + c];
+  red[tid] = a;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (tid < st) red[tid] += red[tid + st];
+    __syncthreads();
+  }
+  if (tid == 0) out[k] = red[0];
+}
+
+void launch_reduce_partials(const double* partial, int nchunk, int n_rhs, double* out,
+                            hipStream_t s) {
+  k_reduce_partials<<<n_rhs, 256, 0, s>>>(partial, nchunk, out);
+}
+
+constexpr int kDotBlock = 256, kDotPer = 8;
+int dot_chunks(int n) { return (n + kDotBlock * kDotPer - 1) / (kDotBlock * kDotPer); }
+
+__global__ void k_dot_partials(const double* __restrict__ a, const double* __restrict__ b, int n,
+                               double* __restrict__ partial, int nchunk) {
+  __shared__ double red[kDotBlock];
+  const int k = blockIdx.y, c = blockIdx.x, tid = threadIdx.x;
+  const double* ak = a + (size_t)k * n;
+  const double* bk = b + (size_t)k * n;
+  double acc = 0.0;
+  const int base = c * kDotBlock * kDotPer;
+#pragma unroll
+  for (int j = 0; j < kDotPer; ++j) {
+    int i = base + j * kDotBlock + tid;
+    if (i < n) acc += ak[i] * bk[i];
+  }
+  red[tid] = acc;
+  __syncthreads();
+  for (int st = kDotBlock / 2; st > 0; st >>= 1) {
+    if (tid < st) red[tid] += red[tid + st];
+    __syncthreads();
+  }
+  if (tid == 0) partial[(size_t)k * nchunk + c] = red[0];
+}
+
+void launch_dot_partials(const double* a, const double* b, int n, int n_rhs, double* partial,
+                         int nchunk, hipStream_t s) {
+  dim3 grid(nchunk, n_rhs);
+  k_dot_partials<<<grid, kDotBlock, 0, s>>>(a, b, n, partial, nchunk);
+}
+
+// x += alpha p ; r -= alpha q ; partial sums of r.r   (alpha = rz / pq, 0 if inactive)
+__global__ void k_pcg_xr(const double* __restrict__ p, const double* __restrict__ q,
+                         double* __restrict__ x, double* __restrict__ r,
+                         const double* __restrict__ rz, const double* __restrict__ pq,
+                         const uint8_t* __restrict__ active, int n, double* __restrict__ partial,
+                         int nchunk) {
+  __shared__ double red[kDotBlock];
+  const int k = blockIdx.y, c = blockIdx.x, tid = threadIdx.x;
+  const double alpha = active[k] ? rz[k] / pq[k] : 0.0;
+  const size_t off = (size_t)k * n;
+  double acc = 0.0;
+  const int base = c * kDotBlock * kDotPer;
+#pragma unroll
+  for (int j = 0; j < kDotPer; ++j) {
+    int i = base + j * kDotBlock + tid;
+    if (i < n) {
+      double rv = r[off + i];
+      if (alpha != 0.0) {
+        x[off + i] += alpha * p[off + i];
+        rv -= alpha * q[off + i];
+        r[off + i] = rv;
+      }
+      acc += rv * rv;
+    }
+  }
+  red[tid] = acc;
+  __syncthreads();
+  for (int st = kDotBlock / 2; st > 0; st >>= 1) {
+    if (tid < st) red[tid] += red[tid + st];
+    __syncthreads();
+  }
+  if (tid == 0) partial[(size_t)k * nchunk + c] = red[0];
+}
+
+void launch_pcg_xr(const double* p, const double* q, double* x, double* r, const double* rz,
+                   const double* pq, const uint8_t* active, int n, int n_rhs, double* rr_partial,
+                   int nchunk, hipStream_t s) {
+  dim3 grid(nchunk, n_rhs);
+  k_pcg_xr<<<grid, kDotBlock, 0, s>>>(p, q, x, r, rz, pq, active, n, rr_partial, nchunk);
+}
+
+// p = z + beta p (first iteration: p = z); beta = rz_new / rz_old; active columns only
+__global__ void k_pcg_p(const double* __restrict__ z, double* __restrict__ p,
+                        const double* __restrict__ rz_new, const uint8_t* __restrict__ active,
+                        const double* __restrict__ rz_old, int n, int first) {
+  const int k = blockIdx.y;
+  if (!active[k]) return;
+  const double beta = first ? 0.0 : rz_new[k] / rz_old[k];
+  const size_t off = (size_t)k * n;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    p[off + i] = z[off + i] + beta * p[off + i];
+}
+
+__global__ void k_copy_scalars(const double* __restrict__ src, double* __restrict__ dst,
+                               const uint8_t* __restrict__ active, int n_rhs) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n_rhs && active[k]) dst[k] = src[k];
+}
+
+void launch_pcg_p(const double* z, double* p, const double* rz_new, double* rz_old,
+                  const uint8_t* active, int n, int n_rhs, int first, hipStream_t s) {
+  int bx = std::min((n + 255) / 256, 1024);
+  dim3 grid(bx, n_rhs);
+  k_pcg_p<<<grid, 256, 0, s>>>(z, p, rz_new, active, rz_old, n, first);
+  k_copy_scalars<<<(n_rhs + 255) / 256, 256, 0, s>>>(rz_new, rz_old, active, n_rhs);
+}
+
+// convergence test per column: active <- active && ||r|| > rtol ||b||; count iterations
+__global__ void k_pcg_check(const double* __restrict__ rr, const double* __restrict__ bb,
+                            double rtol, uint8_t* __restrict__ active, int* __restrict__ it_count,
+                            int* __restrict__ n_active, int n_rhs) {
+  __shared__ int cnt[256];
+  int tid = threadIdx.x, c = 0;
+  for (int k = tid; k < n_rhs; k += 256) {
+    if (active[k]) {
+      it_count[k] += 1;
+      if (!(sqrt(rr[k]) > rtol * sqrt(bb[k]))) active[k] = 0;
+    }
+    c += active[k] ? 1 : 0;
+  }
+  cnt[tid] = c;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (tid < st) cnt[tid] += cnt[tid + st];
+    __syncthreads();
+  }
+  if (tid == 0) *n_active = cnt[0];
+}
+
+void launch_pcg_check(const double* rr, const double* bb, double rtol, uint8_t* active,
+                      int* it_count, int* n_active, int n_rhs, hipStream_t s) {
+  k_pcg_check<<<1, 256, 0, s>>>(rr, bb, rtol, active, it_count, n_active, n_rhs);
+}
+
+}  // namespace rbmc

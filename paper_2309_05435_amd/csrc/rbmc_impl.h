@@ -1,0 +1,216 @@
+// Internal declarations of the RBMC library (host runtime + HIP kernels).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/rbmc.h"
+
+namespace rbmc {
+
+// 13-point spatial stencil of Q_s (|dx| + |dy| <= 2), fixed order.
+constexpr int kNS = 13;
+constexpr int kSdx[kNS] = {0, -1, 1, 0, 0, -2, 2, 0, 0, -1, 1, -1, 1};
+constexpr int kSdy[kNS] = {0, 0, 0, -1, 1, 0, 0, -2, 2, -1, -1, 1, 1};
+// the first 5 entries form the 5-point stencil of G, K_kappa and F_s
+constexpr int kN5 = 5;
+
+// Dense blocks are padded to multiples of this (identity on the padded diagonal).
+constexpr int kPad = 64;
+inline int pad_to(int n) { return (n + kPad - 1) / kPad * kPad; }
+
+// ---------------------------------------------------------------------------
+// Planner (host, integer)
+// ---------------------------------------------------------------------------
+
+struct Region {  // spatial node set R with its restricted 13-point stencil
+  int x0, x1, y0, y1, hops;      // core box and L1 growth 2*hops
+  std::vector<int> nodes;        // global spatial ids, ascending
+  std::vector<int> nbr;          // nodes.size() x kNS local ids, -1 = not in R
+  std::vector<uint8_t> in_box;   // node lies in the core box
+  int nb() const { return (int)nodes.size(); }
+};
+
+struct Chain {  // block-tridiagonal principal submatrix: time range x region
+  int region;
+  int t0, T;            // global time range [t0, t0+T)
+  int ct0, cT;          // core time range (global) within the chain
+  int core_id;          // core p (or -1)
+};
+
+struct Plan {
+  int mx, my, T, ns, n;
+  int P, ntx, nty, hops;
+  std::vector<int> slab_t0, slab_len, tile_x0, tile_xlen, tile_y0, tile_ylen;
+  std::vector<Region> regions;
+  std::vector<Chain> sub;  // RBMC subdomains Omega_p* (one per core)
+  std::vector<Chain> bj;   // block-Jacobi cores Omega_p
+};
+
+int piece_start(int idx_piece, int len, int parts);
+int piece_len(int idx_piece, int len, int parts);
+std::string make_plan(const rbmc_model_desc& d, const rbmc_decomp_desc& dc, Plan& plan);
+void plan_labels(const Plan& plan, int32_t* label);
+void plan_state(const Plan& plan, int p, uint8_t* state);
+
+// ---------------------------------------------------------------------------
+// Model coefficients
+// ---------------------------------------------------------------------------
+
+struct Coefs {
+  double kappa, tau, rho, sigma, h;
+  std::vector<double> qs;    // kNS x ns  Q_s
+  std::vector<double> kk;    // kN5 x ns  dQ_s/dlog kappa = tau (4 kappa^4 C + 4 kappa^2 G)
+  std::vector<double> fs;    // kN5 x ns  F_s = sqrt(tau) (kappa^2 C + G) C^-1/2
+  std::vector<double> qd, dqd, ld;  // per time step: Q_t diagonal, dQ_t/drho diagonal, L_tt
+  double qo, dqo, lo;        // Q_t off-diagonal, its rho-derivative, L_{t+1,t}
+  double dobs;               // sigma^-2
+};
+void make_coefs(int mx, int my, int T, double h, double log_kappa, double log_tau, double rho,
+                double log_sigma, Coefs& c);
+
+// ---------------------------------------------------------------------------
+// Kernel launch interfaces (kernels_*.hip)
+// ---------------------------------------------------------------------------
+
+struct DevModel {  // device views used by the stencil kernels
+  int mx, my, T, ns, n, n_obs;
+  const double* qs;   // kNS x ns
+  const double* kk;   // kN5 x ns
+  const double* fs;   // kN5 x ns
+  const double* qd;   // T
+  const double* dqd;  // T
+  const double* ld;   // T
+  double qo, dqo, lo;
+  const double* dvec;     // n: sigma^-2 * mask
+  const int* obs_rank;    // n: rank among observed (or -1)
+};
+
+// y = Op x for n_rhs columns (op = RBMC_OP_*); x ld = n (or n + n_obs for F)
+void launch_apply_op(const DevModel& m, int op, const double* x, double* y, int n_rhs,
+                     hipStream_t s);
+// q = Q p and partial sums of p.q per column: partial[k*nchunk + c]
+int spmm_chunks(const DevModel& m);
+void launch_spmm_dot(const DevModel& m, const double* p, double* q, double* partial, int n_rhs,
+                     hipStream_t s);
+
+// PCG helpers (per-column scalars on the device)
+void launch_reduce_partials(const double* partial, int nchunk, int n_rhs, double* out,
+                            hipStream_t s);
+void launch_dot_partials(const double* a, const double* b, int n, int n_rhs, double* partial,
+                         int nchunk, hipStream_t s);
+int dot_chunks(int n);
+void launch_pcg_xr(const double* p, const double* q, double* x, double* r, const double* rz,
+                   const double* pq, const uint8_t* active, int n, int n_rhs, double* rr_partial,
+                   int nchunk, hipStream_t s);
+void launch_pcg_p(const double* z, double* p, const double* rz_new, double* rz_old,
+                  const uint8_t* active, int n, int n_rhs, int first, hipStream_t s);
+void launch_pcg_check(const double* rr, const double* bb, double rtol, uint8_t* active,
+                      int* it_count, int* n_active, int n_rhs, hipStream_t s);
+
+// Chain-panel kernels (dense blocks padded to np = pad_to(nb), identity pad)
+struct RegionDev {
+  int nb, np;
+  const int* nodes;  // nb
+  const int* nbr;    // nb x kNS
+};
+
+// grouped GEMM: C = alpha * op(A) * op(B) + beta * Cin  (FP64 MFMA)
+struct GemmTask {
+  const double* A;
+  const double* B;
+  const double* Cin;
+  double* C;
+  int M, N, K;
+  int lda, ldb, ldc, ldcin;
+  double alpha, beta;
+  int transA, transB;
+  int tiles_n;
+  int tile_start;
+};
+void launch_gemm(const GemmTask* d_tasks, int n_tasks, int total_tiles, hipStream_t s);
+
+// Gauss-Jordan sweep inversion of SPD matrices (in place, lower-stored -> full symmetric)
+struct InvTask {
+  double* M;     // np x np col-major, ld = np; on exit M^-1 (full symmetric)
+  double* U;     // np x 64 workspace
+  double* Bp;    // np x 64 workspace
+  int np;
+  int* info;     // set to (block index + 1) on non-SPD pivot
+};
+void launch_spd_inverse(const std::vector<InvTask>& tasks, InvTask* d_tasks, hipStream_t s);
+
+// restricted-stencil products on dense column-major matrices (rows = region nodes):
+//   out = alpha * Q_R * op(M) + gamma * Q_R + diag(dv) (+ I on pad) + beta * In
+struct StencilTask {
+  const double* M;     // np x ncols (op N) or ncols x np (op T); may be null (alpha = 0)
+  const double* In;    // optional (beta)
+  double* out;
+  int ldm, ldin, ldout;
+  int ncols;           // number of columns of the result (np for square, n_k for panels)
+  int trans;           // op(M) = M^T
+  double alpha, beta, gamma;
+  const double* dv;    // optional diagonal (length nb), added on the diagonal (square only)
+  int pad_identity;    // add 1 on padded diagonal (square only)
+  int region;          // index into region table
+  int tile_start;
+};
+void launch_rstencil(const StencilTask* d_tasks, int n_tasks, int total_tiles,
+                     const RegionDev* d_regions, const double* qs, int ns, hipStream_t s);
+
+// Panel transfers between global multi-vectors (n x n_k) and chain panels
+// (np x n_k, ld np): mode 0 gather (pad rows zeroed), 1 scatter, 2 correction
+// right-hand side r = Q_AB x_B for the block at global time t of a chain whose
+// time range is [t0, t0 + T).
+struct PanelTask {
+  double* P;
+  int region;
+  int t;        // global time step of the block
+  int t0, T;    // chain time range (mode 2)
+  int mode;
+  int tile_start;
+};
+void launch_panels(const PanelTask* d_tasks, int n_tasks, int total_tiles, const RegionDev* regs,
+                   const DevModel& m, const double* X, double* Xout, int n_k, hipStream_t s);
+int panel_tiles(int np, int n_k);
+
+// Deterministic part of the outputs from dense blocks of Q_AA^-1:
+//   kind 0 (diagonal block Sigma_tt): diag_out[t*ns + node] = Sigma_aa on core
+//     nodes; out[0] = sum D_a Sigma_aa, out[1] = <Sigma, Q_s>_F, out[2] = <Sigma, K>_F
+//     over core rows;
+//   kind 1 (off-diagonal block given as X with Sigma_off = sign * op(X)):
+//     out[1], out[2] as above.
+struct ExtractTask {
+  const double* M;
+  int ld;
+  int region;
+  int t;          // global time of the rows
+  int kind;
+  int trans;
+  double sign;
+  int out_slot;   // partial sums at out[(out_slot * nchunk_max + chunk) * 3 + c]
+  int tile_start;
+};
+void launch_extract(const ExtractTask* d_tasks, int n_tasks, int total_tiles,
+                    const RegionDev* regs, const uint8_t* const* in_box, const DevModel& m,
+                    double* diag_out, double* partial, int nchunk_max, hipStream_t s);
+
+// Monte Carlo part from the correction panels mu_t (np x n_k) of a chain:
+//   diag_out[t*ns + node] += (1/n_k) sum_k mu_t[a,k]^2 on core nodes;
+//   partial sums of (1/n_k) sum_k mu_t[a,k] (S mu_t')[a,k] for t' = t-1, t, t+1,
+//   S in {Q_s, K}, and of (1/n_k) sum_k D_a mu_t[a,k]^2.
+struct McTask {
+  const double* mu[3];  // panels for t-1, t, t+1 (null if outside the chain)
+  int np;
+  int region;
+  int t;
+  int out_slot;         // out[(out_slot * nchunk_max + chunk) * 7 + c]
+  int tile_start;
+};
+void launch_mc(const McTask* d_tasks, int n_tasks, int total_tiles, const RegionDev* regs,
+               const uint8_t* const* in_box, const DevModel& m, int n_k, double* diag_out,
+               double* partial, int nchunk_max, hipStream_t s);
+
+}  // namespace rbmc

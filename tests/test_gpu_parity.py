@@ -1,0 +1,198 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs.  FP64 throughout; the bar is 1e-10 relative for the
+estimator from given samples (spec FP64 tolerance) and a
+residual-derived bound for quantities that pass through PCG."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2309_05435_amd.inputs import Workload, normals, obs_mask
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2309_05435_amd import binding as B  # noqa: E402
+
+RTOL = 1e-10
+
+
+def wl_of(m, T, P, tiles, n_l, frac=0.3, range_=0.3, rho=0.9, sigma=0.5, seed=11, mx=None):
+    return Workload(name="t", m=m, T=T, range_=range_, rho=rho, tau=1.0, sigma=sigma,
+                    obs_frac=frac, n_tslabs=P, n_tiles=tiles, n_l=n_l, n_k=0, rtol=1e-12,
+                    mask_seed=seed, z_seed=seed + 1)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def oracle_model(wl):
+    return O.OracleModel.from_workload(wl)
+
+
+CASES = [
+    # m, T, P, tiles, n_l  -- slabs, tiles, wider overlap, no overlap, single core
+    (12, 8, 3, 1, 1),
+    (14, 9, 3, 2, 1),
+    (11, 7, 2, 2, 2),
+    (10, 8, 4, 1, 0),
+    (9, 6, 1, 1, 1),
+    (13, 1, 1, 2, 1),
+]
+
+
+@pytest.mark.parametrize("op", [B.RBMC_OP_Q, B.RBMC_OP_DQ_LOGKAPPA, B.RBMC_OP_DQ_LOGTAU,
+                                B.RBMC_OP_DQ_RHO, B.RBMC_OP_DQ_LOGSIGMA, B.RBMC_OP_F])
+def test_apply_op_matches_oracle(op):
+    wl = wl_of(37, 5, 2, 1, 1)  # 37 x 37 spans 2 x 3 stencil tiles with ragged edges
+    say("apply_op", op, wl.m, wl.T)
+    M = oracle_model(wl)
+    gm = B.Model(wl)
+    ncol = M.n + M.n_obs if op == B.RBMC_OP_F else M.n
+    x = normals((3, ncol), 5)
+    which = {B.RBMC_OP_Q: O.Q, B.RBMC_OP_DQ_LOGKAPPA: O.DQ_LOGKAPPA, B.RBMC_OP_DQ_LOGTAU: O.DQ_LOGTAU,
+             B.RBMC_OP_DQ_RHO: O.DQ_RHO, B.RBMC_OP_DQ_LOGSIGMA: O.DQ_LOGSIGMA, B.RBMC_OP_F: O.F}[op]
+    ref = M.apply(which, x)
+    got = gm.apply(op, dev(x)).cpu().numpy()
+    scale = np.abs(ref).max()
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-13 * scale)
+    gm.close()
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_deterministic_part_matches_oracle(case):
+    m, T, P, tiles, n_l = case
+    wl = wl_of(m, T, P, tiles, n_l)
+    say("det", case)
+    M = oracle_model(wl)
+    lab = O.grid_cores(m, m, T, P, tiles, tiles)
+    ref = M.rbmc(lab, P * tiles * tiles, n_l, None, 0b1111)
+    gm = B.Model(wl)
+    diag, tr, st, rep = gm.estimate_from_samples(None, grad_mask=0b1111)
+    d = diag.cpu().numpy()
+    np.testing.assert_allclose(d, ref["diag_det"], rtol=RTOL)
+    np.testing.assert_allclose(tr, ref["trace_det"], rtol=RTOL)
+    gm.close()
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_estimator_from_samples_matches_oracle(case):
+    m, T, P, tiles, n_l = case
+    wl = wl_of(m, T, P, tiles, n_l)
+    say("from_samples", case)
+    M = oracle_model(wl)
+    lab = O.grid_cores(m, m, T, P, tiles, tiles)
+    x = normals((67, M.n), 21)   # 67 samples: one full 64-sample tile and a ragged tail
+    ref = M.rbmc(lab, P * tiles * tiles, n_l, x, 0b1111)
+    gm = B.Model(wl)
+    diag, tr, st, rep = gm.estimate_from_samples(dev(x), grad_mask=0b1111)
+    np.testing.assert_allclose(diag.cpu().numpy(), ref["diag"], rtol=RTOL)
+    np.testing.assert_allclose(tr, ref["trace"], rtol=RTOL)
+    gm.close()
+
+
+@pytest.mark.parametrize("case", [(12, 8, 3, 1, 1), (14, 9, 3, 2, 1), (11, 7, 2, 2, 2)])
+def test_sampler_matches_exact_solve(case):
+    """PCG x = Q^-1 F z against the oracle's banded-Cholesky solve; the error bound
+    follows from the stopping rule: ||x - x*|| <= kappa(Q) * rtol * ||x*||."""
+    m, T, P, tiles, n_l = case
+    wl = wl_of(m, T, P, tiles, n_l)
+    say("sampler", case)
+    M = oracle_model(wl)
+    z = normals((70, M.n + M.n_obs), 31)
+    x_ref = M.sample(z)
+    gm = B.Model(wl)
+    x, st, rep = gm.sample(dev(z), rtol=1e-13, maxit=5000)
+    assert st == B.RBMC_OK
+    x = x.cpu().numpy()
+    # residual computed by the oracle
+    b = M.rhs(z)
+    res = np.linalg.norm(M.apply(O.Q, x) - b, axis=1) / np.linalg.norm(b, axis=1)
+    assert res.max() < 1e-12
+    err = np.linalg.norm(x - x_ref, axis=1) / np.linalg.norm(x_ref, axis=1)
+    assert err.max() < 1e-9
+    assert rep.pcg_it_max >= 1 and rep.max_rel_residual <= 1e-13
+    gm.close()
+
+
+def test_full_estimate_matches_oracle_pipeline():
+    wl = wl_of(12, 8, 3, 1, 1)
+    say("estimate")
+    M = oracle_model(wl)
+    lab = O.grid_cores(12, 12, 8, 3, 1, 1)
+    z = normals((80, M.n + M.n_obs), 41)
+    ref = M.rbmc(lab, 3, 1, M.sample(z), 0b1111)
+    gm = B.Model(wl)
+    diag, tr, st, rep = gm.estimate(dev(z), grad_mask=0b1111, rtol=1e-13)
+    assert st == B.RBMC_OK
+    np.testing.assert_allclose(diag.cpu().numpy(), ref["diag"], rtol=1e-8)
+    np.testing.assert_allclose(tr, ref["trace"], rtol=1e-8)
+    gm.close()
+
+
+def test_single_core_is_exact_inverse():
+    wl = wl_of(10, 6, 1, 1, 1)
+    say("single core")
+    M = oracle_model(wl)
+    S = np.linalg.inv(M.csr(O.Q).dense())
+    gm = B.Model(wl)
+    x = normals((5, M.n), 2)
+    diag, tr, st, rep = gm.estimate_from_samples(dev(x), grad_mask=0b1111)
+    np.testing.assert_allclose(diag.cpu().numpy(), np.diag(S), rtol=1e-10)
+    for j, s in enumerate((O.DQ_LOGKAPPA, O.DQ_LOGTAU, O.DQ_RHO, O.DQ_LOGSIGMA)):
+        assert abs(tr[j] - np.sum(S * M.csr(s).dense())) < 1e-10 * abs(tr[j])
+    gm.close()
+
+
+def test_logtau_identity_on_gpu():
+    wl = wl_of(16, 10, 4, 2, 1)
+    say("identity")
+    gm = B.Model(wl)
+    x = normals((33, gm.n), 8)
+    diag, tr, st, rep = gm.estimate_from_samples(dev(x), grad_mask=0b1010)
+    D = wl.mask() / wl.sigma ** 2
+    s = np.sum(D * diag.cpu().numpy())
+    assert abs(tr[0] + s - gm.n) < 1e-9 * gm.n
+    assert abs(tr[1] + 2 * s) < 1e-10 * s
+    gm.close()
+
+
+def test_error_codes():
+    wl = wl_of(8, 4, 2, 1, 1)
+    say("errors")
+    mask = wl.mask()
+    ctx = B.rbmc_ctx_create(0, None)
+    for theta in [(1.0, 0.0, 1.0, 0.0), (float("nan"), 0.0, 0.5, 0.0)]:
+        desc, _m = B.make_desc(8, 8, 4, 1 / 7, theta, mask)
+        with pytest.raises(B.RbmcError) as e:
+            B.rbmc_model_create(ctx, desc, B.rbmc_decomp_desc(2, 1, 1, 1))
+        assert e.value.status == B.RBMC_E_ARG
+    desc, _m = B.make_desc(8, 8, 4, 1 / 7, wl.theta, mask)
+    with pytest.raises(B.RbmcError) as e:
+        B.rbmc_model_create(ctx, desc, B.rbmc_decomp_desc(2, 1, 1, -1))
+    assert e.value.status == B.RBMC_E_ARG
+    m = B.rbmc_model_create(ctx, desc, B.rbmc_decomp_desc(2, 1, 1, 1))
+    z = torch.zeros((4, 8 * 8 * 4 + int(mask.sum())), dtype=torch.float64, device="cuda")
+    z[:, :10] = 1.0
+    x = torch.empty((4, 8 * 8 * 4), dtype=torch.float64, device="cuda")
+    st, rep = B.rbmc_sample(m, B.make_opts(4, pcg_maxit=1, pcg_rtol=1e-14), z, x)
+    assert st == B.RBMC_W_NOT_CONVERGED
+    with pytest.raises(B.RbmcError) as e:
+        B.rbmc_sample(m, B.make_opts(4, pcg_maxit=0), z, x)
+    assert e.value.status == B.RBMC_E_ARG
+    with pytest.raises(B.RbmcError) as e:
+        B.rbmc_sample(m, B.make_opts(4, precision=B.RBMC_MIXED), z, x)
+    assert e.value.status == B.RBMC_E_UNSUPPORTED
+    B.rbmc_model_destroy(m)
+    B.rbmc_ctx_destroy(ctx)
