@@ -1,0 +1,172 @@
+"""Throughput benchmark of the RBMC hot path on one MI355X.
+
+A step is one full estimate on the 64 x 64 x 32 space-time workload
+(n = 131,072, 500 samples, 16 time slabs, 2-hop overlap, PCG to 1e-8):
+rebuild Q(theta), sample x = Q^-1 F z by block-Jacobi PCG, factor every
+overlapping subdomain, run the Takahashi sweep, the correction solves and
+the trace/diagonal accumulation.  Inputs (z) are resident in HBM before the
+timed region.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6    # MI355X dense FP64 (matrix and vector)
+PEAK_HBM_GBS = 8000.0      # MI355X HBM3E
+
+
+def kernel_sources_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2309_05435_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel: str, workload: str):
+    """HBM traffic per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("sources_hash") != kernel_sources_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(wl, m_sample: int):
+    """The CPU oracle, as it stands, on the same workload with the spatial grid
+    reduced to m_sample^2 (full pipeline: exact sampling + estimator)."""
+    import numpy as np
+    import oracle as O
+    sub = wl.replace(m=m_sample)
+    M = O.OracleModel.from_workload(sub)
+    lab = O.grid_cores(sub.m, sub.m, sub.T, sub.n_tslabs, sub.n_tiles, sub.n_tiles)
+    z = sub.z()
+    t0 = time.perf_counter()
+    x = M.sample(z)
+    M.rbmc(lab, sub.n_tslabs * sub.n_tiles * sub.n_tiles, sub.n_l, x, 0b111)
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": sub.n / dt, "unit": "entries/s", "cores": cores, "kind": "oracle",
+            "sample": (f"full oracle pipeline (banded-Cholesky sampling + estimator) on the "
+                       f"same workload with the grid reduced to {m_sample}x{m_sample} "
+                       f"(n={sub.n}, {sub.n_k} samples), {dt:.1f} s")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="slab64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-m", type=int, default=24)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              "(the library has no multi-GPU path)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2309_05435_amd import binding as B
+    from paper_2309_05435_amd.inputs import WORKLOADS
+
+    wl = WORKLOADS[args.workload]
+    torch.cuda.set_device(0)
+    gm = B.Model(wl)
+    z = torch.from_numpy(wl.z()).to("cuda")
+    diag = torch.empty(gm.n, dtype=torch.float64, device="cuda")
+    grad = 0b111
+    opts = B.make_opts(wl.n_k, pcg_maxit=5000, pcg_rtol=wl.rtol, grad_mask=grad)
+    theta = wl.theta
+
+    def step():
+        # rebuilding Q(theta) invalidates every factor: each step factors again
+        B.rbmc_model_set_theta(gm.m, *theta)
+        return B.rbmc_estimate(gm.m, opts, z, 0, diag, B.popcount(grad))
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    B.rbmc_ctx_profile(gm.ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = []
+    for _ in range(args.steps):
+        st, tr, rep = step()
+        reps.append(rep.as_dict())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stats = {B.KF_NAMES[f]: B.rbmc_ctx_profile_read(gm.ctx, f) for f in range(B.RBMC_KF_COUNT)}
+    B.rbmc_ctx_profile(gm.ctx, False)
+    ms = (t1 - t0) * 1000.0 / args.steps
+    value = gm.n / (ms / 1000.0)
+
+    # dominant kernel family by device time
+    dom = max(stats, key=lambda k: stats[k]["total_ms"])
+    s = stats[dom]
+    if dom in ("gemm", "spd_inverse"):
+        achieved = s["alg_flops"] / (s["total_ms"] * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS}
+    else:
+        achieved = s["alg_bytes"] / (s["total_ms"] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS}
+    roof["kernel"] = dom
+    roof["launches"] = s["launches"] // max(args.steps, 1)
+    roof["avg_launch_ms"] = s["total_ms"] / max(s["launches"], 1)
+    roof["traffic"] = traffic_for(dom, wl.name)
+
+    last = reps[-1]
+    out = {
+        "metric": "diag(Q^-1) entries/sec at <=1% rel err; PCG iters; learned+mixed vs plain",
+        "value": value,
+        "unit": "entries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "grid": f"{wl.m}x{wl.m}", "T": wl.T, "n": gm.n,
+                   "n_obs": gm.n_obs, "n_samples": wl.n_k, "n_tslabs": wl.n_tslabs,
+                   "n_tiles": wl.n_tiles, "overlap_hops": wl.n_l, "pcg_rtol": wl.rtol,
+                   "precision": "fp64", "precond": "block-jacobi", "traces": "logkappa,logtau,rho"},
+        "pcg_iters": {"mean": last["pcg_it_mean"], "max": last["pcg_it_max"]},
+        "err_estimate": last["err_estimate"],
+        "accuracy_gate_1pct": bool(last["err_estimate"] <= 0.01),
+        "phase_s": {k: last[k] for k in ("t_sample", "t_factor", "t_takahashi", "t_correct",
+                                         "t_total")},
+        "kernel_ms_per_step": {k: v["total_ms"] / args.steps for k, v in stats.items()},
+        "roofline": roof,
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_m)
+    gm.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -166,6 +166,37 @@ rbmc_status rbmc_estimate(rbmc_model* m, const rbmc_est_opts* opts, const double
 rbmc_status rbmc_plan_query(const rbmc_model_desc* desc, const rbmc_decomp_desc* decomp, int32_t p,
                             int32_t* label_out, uint8_t* state_out);
 
+/* Instrumentation (for throughput and roofline reporting, not part of the
+ * method).  While enabled, every launch of a kernel family is bracketed by
+ * HIP events on the context stream and its algorithmic work is counted:
+ *   RBMC_KF_GEMM         dense products on the matrix cores; flops = 2 M K N
+ *                        over the unpadded block sizes;
+ *   RBMC_KF_SPD_INVERSE  one Gauss-Jordan inversion batch; flops = sum n_b^3;
+ *   RBMC_KF_SPMM         q = Q p in the sampler; bytes = 16 per node and
+ *                        sample (read p, write q);
+ *   RBMC_KF_RSTENCIL     restricted-stencil products with dense blocks;
+ *                        bytes = 16 per output entry;
+ *   RBMC_KF_PANELS       gathers/scatters/right-hand sides; bytes = 16 per
+ *                        panel entry.
+ * rbmc_ctx_profile(ctx, 1) clears and enables, (ctx, 0) disables;
+ * rbmc_ctx_profile_read synchronizes the stream and sums the records. */
+enum {
+  RBMC_KF_GEMM = 0,
+  RBMC_KF_SPD_INVERSE = 1,
+  RBMC_KF_SPMM = 2,
+  RBMC_KF_RSTENCIL = 3,
+  RBMC_KF_PANELS = 4,
+  RBMC_KF_COUNT = 5
+};
+typedef struct {
+  int64_t launches;
+  double total_ms;
+  double alg_flops;
+  double alg_bytes;
+} rbmc_kernel_stats;
+rbmc_status rbmc_ctx_profile(rbmc_ctx* ctx, int enable);
+rbmc_status rbmc_ctx_profile_read(rbmc_ctx* ctx, int family, rbmc_kernel_stats* out);
+
 /* Thread-local message of the last failing call ("" if none). */
 const char* rbmc_last_error(void);
 

@@ -23,7 +23,16 @@ RBMC_GRAD_LOGKAPPA, RBMC_GRAD_LOGTAU, RBMC_GRAD_RHO, RBMC_GRAD_LOGSIGMA = 1, 2, 
 # every symbol include/rbmc.h declares
 EXPORTS = ["rbmc_ctx_create", "rbmc_ctx_destroy", "rbmc_model_create", "rbmc_model_destroy",
            "rbmc_model_set_theta", "rbmc_apply_op", "rbmc_sample", "rbmc_estimate_from_samples",
-           "rbmc_estimate", "rbmc_plan_query", "rbmc_last_error"]
+           "rbmc_estimate", "rbmc_plan_query", "rbmc_ctx_profile", "rbmc_ctx_profile_read",
+           "rbmc_last_error"]
+(RBMC_KF_GEMM, RBMC_KF_SPD_INVERSE, RBMC_KF_SPMM, RBMC_KF_RSTENCIL, RBMC_KF_PANELS,
+ RBMC_KF_COUNT) = range(6)
+KF_NAMES = ["gemm", "spd_inverse", "spmm", "rstencil", "panels"]
+
+
+class rbmc_kernel_stats(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("total_ms", C.c_double), ("alg_flops", C.c_double),
+                ("alg_bytes", C.c_double)]
 
 
 class rbmc_model_desc(C.Structure):
@@ -81,6 +90,8 @@ def lib():
                                     C.POINTER(C.c_double), C.POINTER(rbmc_report)]
         L.rbmc_plan_query.argtypes = [C.POINTER(rbmc_model_desc), C.POINTER(rbmc_decomp_desc),
                                       C.c_int32, vp, vp]
+        L.rbmc_ctx_profile.argtypes = [vp, C.c_int]
+        L.rbmc_ctx_profile_read.argtypes = [vp, C.c_int, C.POINTER(rbmc_kernel_stats)]
         L.rbmc_last_error.restype = C.c_char_p
         for name in EXPORTS:
             if name not in ("rbmc_ctx_destroy", "rbmc_model_destroy", "rbmc_last_error"):
@@ -162,6 +173,16 @@ def rbmc_plan_query(desc, decomp, p, label_out=None, state_out=None):
     lp = None if label_out is None else label_out.ctypes.data_as(C.c_void_p)
     sp = None if state_out is None else state_out.ctypes.data_as(C.c_void_p)
     return check(lib().rbmc_plan_query(C.byref(desc), C.byref(decomp), p, lp, sp))
+
+
+def rbmc_ctx_profile(ctx, enable: bool):
+    return check(lib().rbmc_ctx_profile(ctx, 1 if enable else 0))
+
+
+def rbmc_ctx_profile_read(ctx, family: int) -> dict:
+    st = rbmc_kernel_stats()
+    check(lib().rbmc_ctx_profile_read(ctx, family, C.byref(st)))
+    return {f: getattr(st, f) for f, _ in st._fields_}
 
 
 # ---- convenience ------------------------------------------------------------

@@ -31,9 +31,51 @@ static rbmc_status fail(rbmc_status st, const std::string& msg) {
                   std::string(#expr) + ": " + hipGetErrorString(e_));                      \
   } while (0)
 
+struct ProfRec {
+  int family;
+  hipEvent_t a, b;
+  double flops, bytes;
+};
+
 struct rbmc_ctx {
   int device;
   hipStream_t stream;
+  bool prof = false;
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> spare;
+
+  hipEvent_t ev() {
+    hipEvent_t e = nullptr;
+    if (!spare.empty()) {
+      e = spare.back();
+      spare.pop_back();
+    } else {
+      (void)hipEventCreate(&e);
+    }
+    return e;
+  }
+  // bracket a launch sequence of one kernel family
+  int begin(int family, double flops, double bytes) {
+    if (!prof) return -1;
+    ProfRec r{family, ev(), ev(), flops, bytes};
+    (void)hipEventRecord(r.a, stream);
+    recs.push_back(r);
+    return (int)recs.size() - 1;
+  }
+  void end(int id) {
+    if (id >= 0) (void)hipEventRecord(recs[id].b, stream);
+  }
+  void clear() {
+    for (ProfRec& r : recs) {
+      spare.push_back(r.a);
+      spare.push_back(r.b);
+    }
+    recs.clear();
+  }
+  ~rbmc_ctx() {
+    clear();
+    for (hipEvent_t e : spare) (void)hipEventDestroy(e);
+  }
 };
 
 namespace {
@@ -255,8 +297,11 @@ int gemm_tiles(int M, int N) { return ((M + 127) / 128) * ((N + 127) / 128); }
 struct GemmList {
   std::vector<GemmTask> v;
   int tiles = 0;
+  double flops = 0.0;  // algorithmic (unpadded) flops of the list
   void add(const double* A, const double* B, const double* Cin, double* C, int M, int N, int K,
-           int lda, int ldb, int ldc, double alpha, double beta, int tA, int tB) {
+           int lda, int ldb, int ldc, double alpha, double beta, int tA, int tB, int Mreal,
+           int Kreal) {
+    flops += 2.0 * Mreal * (double)N * Kreal;
     GemmTask t{};
     t.A = A;
     t.B = B;
@@ -283,9 +328,11 @@ struct GemmList {
 struct StencilList {
   std::vector<StencilTask> v;
   int tiles = 0;
-  void add(StencilTask t, int np) {
+  double bytes = 0.0;
+  void add(StencilTask t, int np, int nb) {
     t.tile_start = tiles;
     tiles += (np / 64) * ((t.ncols + 63) / 64);
+    bytes += 16.0 * nb * (double)t.ncols;
     v.push_back(t);
   }
 };
@@ -294,9 +341,11 @@ template <class T>
 struct TileList {
   std::vector<T> v;
   int tiles = 0;
-  void add(T t, int ntiles) {
+  double bytes = 0.0;
+  void add(T t, int ntiles, double b = 0.0) {
     t.tile_start = tiles;
     tiles += ntiles;
+    bytes += b;
     v.push_back(t);
   }
 };
@@ -314,6 +363,9 @@ struct Op {
   void* dst = nullptr;
   const void* src = nullptr;
   size_t bytes = 0;
+  // instrumentation: kernel family and algorithmic work of the launch
+  int family = -1;
+  double alg_flops = 0.0, alg_bytes = 0.0;
 };
 
 struct Program {
@@ -325,6 +377,8 @@ struct Program {
     o.off = a.push(g.v);
     o.n = (int)g.v.size();
     o.tiles = g.tiles;
+    o.family = RBMC_KF_GEMM;
+    o.alg_flops = g.flops;
     ops.push_back(std::move(o));
   }
   void stencil(Arena& a, StencilList& s) {
@@ -334,6 +388,8 @@ struct Program {
     o.off = a.push(s.v);
     o.n = (int)s.v.size();
     o.tiles = s.tiles;
+    o.family = RBMC_KF_RSTENCIL;
+    o.alg_bytes = s.bytes;
     ops.push_back(std::move(o));
   }
   void inverse(Arena& a, const std::vector<InvTask>& t) {
@@ -343,6 +399,8 @@ struct Program {
     o.off = a.push(t);
     o.n = (int)t.size();
     o.inv = t;
+    o.family = RBMC_KF_SPD_INVERSE;
+    for (const InvTask& it : t) o.alg_flops += (double)it.nb * it.nb * it.nb;
     ops.push_back(std::move(o));
   }
   void panels(Arena& a, TileList<PanelTask>& p, const double* X, double* Xout, int n_k) {
@@ -352,6 +410,8 @@ struct Program {
     o.off = a.push(p.v);
     o.n = (int)p.v.size();
     o.tiles = p.tiles;
+    o.family = RBMC_KF_PANELS;
+    o.alg_bytes = p.bytes;
     o.X = X;
     o.Xout = Xout;
     o.n_k = n_k;
@@ -396,6 +456,7 @@ rbmc_status run(rbmc_model* m, const Program& pg, const RunCtx& rc) {
   hipStream_t s = m->ctx->stream;
   Arena& a = m->arena;
   for (const Op& o : pg.ops) {
+    const int pid = (o.family >= 0) ? m->ctx->begin(o.family, o.alg_flops, o.alg_bytes) : -1;
     switch (o.kind) {
       case 0: launch_gemm(a.at<GemmTask>(o.off), o.n, o.tiles, s); break;
       case 1:
@@ -417,6 +478,7 @@ rbmc_status run(rbmc_model* m, const Program& pg, const RunCtx& rc) {
         break;
       case 6: HIPCHK(hipMemcpyAsync(o.dst, o.src, o.bytes, hipMemcpyDeviceToDevice, s)); break;
     }
+    m->ctx->end(pid);
   }
   HIPCHK(hipGetLastError());
   return RBMC_OK;
@@ -445,7 +507,7 @@ void build_factor(rbmc_model* m, ChainSet& cs, int info_base, Program& pg) {
         s1.ncols = np;
         s1.alpha = 1.0;
         s1.region = ch.region;
-        v1.add(s1, np);
+        v1.add(s1, np, m->regions[ch.region].nb);
       }
       StencilTask s2{};
       s2.M = (t > 0) ? cs.tmp[c] : nullptr;
@@ -459,12 +521,13 @@ void build_factor(rbmc_model* m, ChainSet& cs, int info_base, Program& pg) {
       s2.ldout = np;
       s2.ncols = np;
       s2.region = ch.region;
-      v2.add(s2, np);
+      v2.add(s2, np, m->regions[ch.region].nb);
       InvTask it{};
       it.M = St;
       it.U = cs.gjU[c];
       it.Bp = cs.gjB[c];
       it.np = np;
+      it.nb = m->regions[ch.region].nb;
       it.info = m->d_info + info_base + (int)c;
       inv.push_back(it);
     }
@@ -503,10 +566,10 @@ void build_solve(rbmc_model* m, ChainSet& cs, std::vector<std::vector<double*>>&
         s.ldout = np;
         s.ncols = n_k;
         s.region = ch.region;
-        sl.add(s, np);
+        sl.add(s, np, m->regions[ch.region].nb);
       }
       gl.add(cs.S[c] + blk * t, ytmp[c], nullptr, pan[c][t], np, n_k, np, np, np, np, 1.0, 0.0,
-             0, 0);
+             0, 0, m->regions[ch.region].nb, m->regions[ch.region].nb);
     }
     pg.stencil(a, sl);
     pg.gemm(a, gl);
@@ -527,9 +590,9 @@ void build_solve(rbmc_model* m, ChainSet& cs, std::vector<std::vector<double*>>&
       s.ldout = np;
       s.ncols = n_k;
       s.region = ch.region;
-      sl.add(s, np);
+      sl.add(s, np, m->regions[ch.region].nb);
       gl.add(cs.S[c] + blk * t, ytmp[c], pan[c][t], pan[c][t], np, n_k, np, np, np, np, -1.0,
-             1.0, 0, 0);
+             1.0, 0, 0, m->regions[ch.region].nb, m->regions[ch.region].nb);
     }
     pg.stencil(a, sl);
     pg.gemm(a, gl);
@@ -597,6 +660,31 @@ rbmc_status check_opts(const rbmc_est_opts* o, bool need_pcg) {
 extern "C" {
 
 const char* rbmc_last_error(void) { return g_err.c_str(); }
+
+rbmc_status rbmc_ctx_profile(rbmc_ctx* ctx, int enable) {
+  if (!ctx) return fail(RBMC_E_ARG, "ctx is NULL");
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  ctx->clear();
+  ctx->prof = enable != 0;
+  return RBMC_OK;
+}
+
+rbmc_status rbmc_ctx_profile_read(rbmc_ctx* ctx, int family, rbmc_kernel_stats* out) {
+  if (!ctx || !out) return fail(RBMC_E_ARG, "NULL argument");
+  if (family < 0 || family >= RBMC_KF_COUNT) return fail(RBMC_E_ARG, "unknown kernel family");
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  std::memset(out, 0, sizeof(*out));
+  for (const ProfRec& r : ctx->recs) {
+    if (r.family != family) continue;
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
+    out->launches += 1;
+    out->total_ms += ms;
+    out->alg_flops += r.flops;
+    out->alg_bytes += r.bytes;
+  }
+  return RBMC_OK;
+}
 
 rbmc_status rbmc_ctx_create(int device, void* hip_stream, rbmc_ctx** out) {
   if (!out) return fail(RBMC_E_ARG, "out is NULL");
@@ -803,11 +891,11 @@ static rbmc_status sample_impl(rbmc_model* m, const rbmc_est_opts* o, const doub
       pt.region = ch.region;
       pt.t = ch.t0 + t;
       pt.mode = 0;
-      g.add(pt, panel_tiles(np, nk));
+      g.add(pt, panel_tiles(np, nk), 16.0 * m->regions[ch.region].nb * nk);
       PanelTask ps = pt;
       ps.P = m->bj_pan[c][t];
       ps.mode = 1;
-      sc.add(ps, panel_tiles(np, nk));
+      sc.add(ps, panel_tiles(np, nk), 16.0 * m->regions[ch.region].nb * nk);
     }
   }
   gat.panels(m->arena, g, r, nullptr, nk);
@@ -843,7 +931,9 @@ static rbmc_status sample_impl(rbmc_model* m, const rbmc_est_opts* o, const doub
   for (int k = 0; k < nk; ++k) n_active += act[k];
   int it = 0;
   while (n_active > 0 && it < o->pcg_maxit) {
+    const int pid = m->ctx->begin(RBMC_KF_SPMM, 0.0, 16.0 * n * (double)nk);
     launch_spmm_dot(m->dm, p, q, m->w_part, nk, s);
+    m->ctx->end(pid);
     launch_reduce_partials(m->w_part, nsp, nk, pq, s);
     launch_pcg_xr(p, q, x, r, rz, pq, m->w_active, n, nk, m->w_part, nch, s);
     launch_reduce_partials(m->w_part, nch, nk, rr, s);
@@ -911,7 +1001,7 @@ static rbmc_status estimate_impl(rbmc_model* m, const rbmc_est_opts* o, const do
     return v;
   }();
   const size_t det_len = (size_t)nslots * nchunk_max * 3;
-  const size_t mc_len = (size_t)nslots * mc_chunks * 7;
+  const size_t mc_len = (size_t)nslots * mc_chunks * 8;
   const size_t need = det_len + mc_len;
   if (m->diag_part_len < need) {
     double* p = nullptr;
@@ -969,10 +1059,10 @@ static rbmc_status estimate_impl(rbmc_model* m, const rbmc_est_opts* o, const do
       v.ldout = np;
       v.ncols = np;
       v.region = ch.region;
-      s1.add(v, np);
+      s1.add(v, np, m->regions[ch.region].nb);
       // X = q_o V^T S_t^-1  (Sigma_{t+1,t} = -X)
       g1.add(cs.tmp[c], cs.S[c] + blk * t, nullptr, cs.xb[c], np, np, np, np, np, np, m->co.qo,
-             0.0, 1, 0);
+             0.0, 1, 0, m->regions[ch.region].nb, m->regions[ch.region].nb);
       if (is_core(c, t)) {  // rows at t, columns at t+1: Sigma_{t,t+1} = -X^T
         ExtractTask e{};
         e.M = cs.xb[c];
@@ -1006,9 +1096,9 @@ static rbmc_status estimate_impl(rbmc_model* m, const rbmc_est_opts* o, const do
         z.ldout = np;
         z.ncols = np;
         z.region = ch.region;
-        s2.add(z, np);
+        s2.add(z, np, m->regions[ch.region].nb);
         g2.add(cs.S[c] + blk * t, cs.tmp[c], cs.S[c] + blk * t, cs.sig[c], np, np, np, np, np,
-               np, 1.0, 1.0, 0, 0);
+               np, 1.0, 1.0, 0, 0, m->regions[ch.region].nb, m->regions[ch.region].nb);
         if (is_core(c, t)) {
           ExtractTask e{};
           e.M = cs.sig[c];
@@ -1044,7 +1134,7 @@ static rbmc_status estimate_impl(rbmc_model* m, const rbmc_est_opts* o, const do
         pt.t0 = ch.t0;
         pt.T = ch.T;
         pt.mode = 2;
-        rt.add(pt, panel_tiles(np, nk));
+        rt.add(pt, panel_tiles(np, nk), 16.0 * m->regions[ch.region].nb * nk);
       }
     }
     cor.panels(m->arena, rt, x, nullptr, nk);
@@ -1089,6 +1179,7 @@ static rbmc_status estimate_impl(rbmc_model* m, const rbmc_est_opts* o, const do
   HIPCHK(hipMemcpy(hmc.data(), mc_part, mc_len * 8, hipMemcpyDeviceToHost));
   const Coefs& co = m->co;
   double tr[4] = {0, 0, 0, 0};
+  double ratio_sum = 0.0;  // sum over nodes of (MC part) / (estimate)
   for (int c = 0; c < nchains; ++c) {
     const Chain& ch = cs.chains[c];
     for (int t = lc0(c); t <= lc1(c); ++t) {
@@ -1105,12 +1196,13 @@ static rbmc_status estimate_impl(rbmc_model* m, const rbmc_est_opts* o, const do
         }
       }
       // Monte Carlo: slot 3, components [t-1, t, t+1] for Q_s and K, then D
-      double G[7] = {0, 0, 0, 0, 0, 0, 0};
+      double G[8] = {0, 0, 0, 0, 0, 0, 0, 0};
       if (nk > 0) {
         const int slot = slot_base[c] + t * 4 + 3;
         for (int ch2 = 0; ch2 < mc_chunks; ++ch2)
-          for (int j = 0; j < 7; ++j) G[j] += hmc[((size_t)slot * mc_chunks + ch2) * 7 + j];
+          for (int j = 0; j < 8; ++j) G[j] += hmc[((size_t)slot * mc_chunks + ch2) * 8 + j];
       }
+      ratio_sum += G[7];
       const double wq0 = co.qd[tg], wqo = co.qo, wd0 = co.dqd[tg], wdo = co.dqo;
       const bool hm = (t - 1 >= 0), hp = (t + 1 < ch.T);
       // Q_s-weighted sums over (t,t), (t,t+1), (t,t-1)
@@ -1132,6 +1224,10 @@ static rbmc_status estimate_impl(rbmc_model* m, const rbmc_est_opts* o, const do
       if (o->grad_mask & (1u << b)) trace_out[j++] = tr[b];
   }
   if (rep) {
+    // plug-in MC error: m_i ~ E[mu_i^2] chi2_{n_k} / n_k, so the mean absolute relative
+    // error of the estimate is about sqrt(2/pi) sqrt(2/n_k) m_i / s2_i on average
+    rep->err_estimate =
+        nk > 0 ? std::sqrt(2.0 / M_PI) * std::sqrt(2.0 / nk) * ratio_sum / P.n : 0.0;
     rep->t_factor += t1 - t0;
     rep->t_takahashi = t2 - t1;
     rep->t_correct = t3 - t2;

@@ -208,20 +208,28 @@ __global__ __launch_bounds__(256) void k_mc(const McTask* __restrict__ tasks, in
 #pragma unroll
   for (int c = 0; c < 8; ++c) red[c][threadIdx.x] = acc[c];
   __syncthreads();
-  // diagonal: combine the 4 sample lanes of each row in a fixed order
+  // diagonal: combine the 4 sample lanes of each row in a fixed order; the
+  // ratio m_a / s2_a (MC part over estimate) feeds the plug-in error estimate
+  double ratio = 0.0;
   if (threadIdx.x < 64 && a < rg.nb && in_box[tk.region][a]) {
     const double s = (red[7][threadIdx.x] + red[7][threadIdx.x + 64]) +
                      (red[7][threadIdx.x + 128] + red[7][threadIdx.x + 192]);
-    diag_out[(size_t)tk.t * m.ns + rg.nodes[a]] += s / n_k;
+    const size_t i = (size_t)tk.t * m.ns + rg.nodes[a];
+    const double mhat = s / n_k;
+    const double est = diag_out[i] + mhat;
+    diag_out[i] = est;
+    ratio = est > 0.0 ? mhat * n_k / est : 0.0;  // scaled back by 1/n_k below
   }
+  __syncthreads();
+  red[7][threadIdx.x] = ratio;
   __syncthreads();
   for (int st = 128; st > 0; st >>= 1) {
     if (threadIdx.x < st)
-      for (int c = 0; c < 7; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + st];
+      for (int c = 0; c < 8; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + st];
     __syncthreads();
   }
-  if (threadIdx.x < 7)
-    partial[((size_t)tk.out_slot * nchunk_max + chunk) * 7 + threadIdx.x] =
+  if (threadIdx.x < 8)
+    partial[((size_t)tk.out_slot * nchunk_max + chunk) * 8 + threadIdx.x] =
         red[threadIdx.x][0] / n_k;
 }
 

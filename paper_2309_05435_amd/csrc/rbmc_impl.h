@@ -138,6 +138,7 @@ struct InvTask {
   double* U;     // np x 64 workspace
   double* Bp;    // np x 64 workspace
   int np;
+  int nb;        // unpadded size (for work accounting)
   int* info;     // set to (block index + 1) on non-SPD pivot
 };
 void launch_spd_inverse(const std::vector<InvTask>& tasks, InvTask* d_tasks, hipStream_t s);
