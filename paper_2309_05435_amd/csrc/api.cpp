@@ -150,7 +150,9 @@ struct ChainSet {
   std::vector<double*> S;          // T x np^2, S_t^-1 after factorization
   std::vector<double*> tmp;        // np^2 (Schur / Takahashi temporaries)
   std::vector<double*> sig, xb;    // np^2 (Takahashi Sigma and X), subdomains only
-  std::vector<double*> gjU, gjB;   // np x 64 Gauss-Jordan panels
+  std::vector<double*> gjU, gjB;   // np x 256 Gauss-Jordan panels
+  std::vector<double*> gjP, gjPi;  // 256 x 256 outer pivot block, 64 x 64 inner pivot inverse
+  std::vector<double*> gjUi, gjBi; // 256 x 64 inner panels
   int maxT = 0;
 };
 
@@ -240,10 +242,18 @@ rbmc_status alloc_chainset(rbmc_model* m, ChainSet& cs, const std::vector<Chain>
       HIPCHK(m->pool.alloc((void**)&p, blk * 8));
       cs.xb.push_back(p);
     }
-    HIPCHK(m->pool.alloc((void**)&p, (size_t)np * 64 * 8));
+    HIPCHK(m->pool.alloc((void**)&p, (size_t)np * 256 * 8));
     cs.gjU.push_back(p);
-    HIPCHK(m->pool.alloc((void**)&p, (size_t)np * 64 * 8));
+    HIPCHK(m->pool.alloc((void**)&p, (size_t)np * 256 * 8));
     cs.gjB.push_back(p);
+    HIPCHK(m->pool.alloc((void**)&p, (size_t)256 * 256 * 8));
+    cs.gjP.push_back(p);
+    HIPCHK(m->pool.alloc((void**)&p, (size_t)64 * 64 * 8));
+    cs.gjPi.push_back(p);
+    HIPCHK(m->pool.alloc((void**)&p, (size_t)256 * 64 * 8));
+    cs.gjUi.push_back(p);
+    HIPCHK(m->pool.alloc((void**)&p, (size_t)256 * 64 * 8));
+    cs.gjBi.push_back(p);
     cs.maxT = std::max(cs.maxT, c.T);
   }
   return RBMC_OK;
@@ -323,6 +333,32 @@ struct GemmList {
     tiles += gemm_tiles(M, N);
     v.push_back(t);
   }
+  // outer sweep update of the lower tiles: M -= U B^T outside rows/cols [kb, kb + w)
+  void add_sweep(double* Mx, int np, const double* U, const double* B, int w, int kb) {
+    GemmTask t{};
+    t.A = U;
+    t.B = B;
+    t.Cin = Mx;
+    t.C = Mx;
+    t.M = np;
+    t.N = np;
+    t.K = w;
+    t.lda = np;
+    t.ldb = np;
+    t.ldc = np;
+    t.ldcin = np;
+    t.alpha = -1.0;
+    t.beta = 1.0;
+    t.transA = 0;
+    t.transB = 1;
+    t.tiles_n = (np + 127) / 128;
+    t.lower = 1;
+    t.skip0 = kb;
+    t.skip1 = kb + w;
+    t.tile_start = tiles;
+    tiles += gemm_task_tiles(np, np, 1);
+    v.push_back(t);
+  }
 };
 
 struct StencilList {
@@ -351,11 +387,20 @@ struct TileList {
 };
 
 // Recorded program: a sequence of grouped launches over the arena.
+struct InvJob {  // one SPD block to invert in place, with its workspace
+  double* M;
+  int np, nb;
+  int* info;
+  double *B, *U, *P, *Pi, *Ui, *Bi;
+};
+
 struct Op {
-  int kind;  // 0 gemm, 1 stencil, 2 inverse(k-range whole), 3 panels, 4 extract, 5 mc, 6 copy
+  // 0 gemm, 1 stencil, 2 sweep step (rank 64), 3 panels, 4 extract, 5 mc, 6 copy,
+  // 7 outer gather, 8 outer fix, 9 sweep finish, 10 profile begin, 11 profile end
+  int kind;
   size_t off;
   int n, tiles;
-  std::vector<InvTask> inv;
+  int max_np = 0, kblk = 0;
   const double* X = nullptr;
   double* Xout = nullptr;
   int n_k = 0;
@@ -370,14 +415,14 @@ struct Op {
 
 struct Program {
   std::vector<Op> ops;
-  void gemm(Arena& a, GemmList& g) {
+  void gemm(Arena& a, GemmList& g, bool profiled = true) {
     if (g.v.empty()) return;
     Op o;
     o.kind = 0;
     o.off = a.push(g.v);
     o.n = (int)g.v.size();
     o.tiles = g.tiles;
-    o.family = RBMC_KF_GEMM;
+    o.family = profiled ? RBMC_KF_GEMM : -1;
     o.alg_flops = g.flops;
     ops.push_back(std::move(o));
   }
@@ -392,16 +437,111 @@ struct Program {
     o.alg_bytes = s.bytes;
     ops.push_back(std::move(o));
   }
-  void inverse(Arena& a, const std::vector<InvTask>& t) {
+  // rank-64 sweep of a list of blocks (all steps) followed by the finish pass
+  void sweep64(Arena& a, const std::vector<InvTask>& t) {
     if (t.empty()) return;
-    Op o;
-    o.kind = 2;
-    o.off = a.push(t);
-    o.n = (int)t.size();
-    o.inv = t;
-    o.family = RBMC_KF_SPD_INVERSE;
-    for (const InvTask& it : t) o.alg_flops += (double)it.nb * it.nb * it.nb;
-    ops.push_back(std::move(o));
+    const size_t off = a.push(t);
+    int max_np = 0;
+    for (const InvTask& it : t) max_np = std::max(max_np, it.np);
+    for (int k = 0; k < max_np / 64; ++k) {
+      Op o;
+      o.kind = 2;
+      o.off = off;
+      o.n = (int)t.size();
+      o.max_np = max_np;
+      o.kblk = k;
+      ops.push_back(std::move(o));
+    }
+    Op f;
+    f.kind = 9;
+    f.off = off;
+    f.n = (int)t.size();
+    ops.push_back(std::move(f));
+  }
+  // In-place inversion of SPD blocks: blocks up to 256 by the rank-64 sweep;
+  // larger ones by rank-256 outer sweeps (GEMM updates) whose 256 x 256 pivot
+  // blocks are inverted by the rank-64 sweep.
+  void inverse(Arena& a, const std::vector<InvJob>& jobs) {
+    if (jobs.empty()) return;
+    Op pb;
+    pb.kind = 10;
+    pb.family = RBMC_KF_SPD_INVERSE;
+    for (const InvJob& j : jobs) pb.alg_flops += (double)j.nb * j.nb * j.nb;
+    ops.push_back(pb);
+    std::vector<InvTask> small, big;
+    int max_big = 0;
+    for (const InvJob& j : jobs) {
+      InvTask t{};
+      t.M = j.M;
+      t.np = j.np;
+      t.nb = j.nb;
+      t.info = j.info;
+      t.U = j.U;
+      t.Bp = j.B;
+      t.Pi = j.Pi;
+      if (j.np <= 256) small.push_back(t);
+      else {
+        big.push_back(t);
+        max_big = std::max(max_big, j.np);
+      }
+    }
+    sweep64(a, small);
+    for (int kb = 0; kb < max_big; kb += 256) {
+      TileList<Gj2Task> gl;
+      std::vector<InvTask> inner;
+      GemmList gu, gm;
+      for (const InvJob& j : jobs) {
+        if (j.np <= 256 || kb >= j.np) continue;
+        const int w = std::min(256, j.np - kb);
+        Gj2Task g{};
+        g.M = j.M;
+        g.B = j.B;
+        g.U = j.U;
+        g.P = j.P;
+        g.np = j.np;
+        g.kb = kb;
+        g.w = w;
+        gl.add(g, gj2_tiles(j.np, w));
+        InvTask t{};
+        t.M = j.P;
+        t.np = w;
+        t.nb = w;
+        t.info = j.info;
+        t.U = j.Ui;
+        t.Bp = j.Bi;
+        t.Pi = j.Pi;
+        inner.push_back(t);
+        // U = B P^-1
+        gu.add(j.B, j.P, nullptr, j.U, j.np, w, w, j.np, w, j.np, 1.0, 0.0, 0, 0, j.np, w);
+        // M_lower -= U B^T outside the swept block row/column
+        gm.add_sweep(j.M, j.np, j.U, j.B, w, kb);
+      }
+      Op og;
+      og.kind = 7;
+      og.off = a.push(gl.v);
+      og.n = (int)gl.v.size();
+      og.tiles = gl.tiles;
+      ops.push_back(std::move(og));
+      sweep64(a, inner);
+      gemm(a, gu, false);
+      gemm(a, gm, false);
+      Op of;
+      of.kind = 8;
+      of.off = og.off;
+      of.n = og.n;
+      of.tiles = og.tiles;
+      ops.push_back(std::move(of));
+    }
+    if (!big.empty()) {
+      Op f;
+      f.kind = 9;
+      f.off = a.push(big);
+      f.n = (int)big.size();
+      ops.push_back(std::move(f));
+    }
+    Op pe;
+    pe.kind = 11;
+    ops.push_back(pe);
   }
   void panels(Arena& a, TileList<PanelTask>& p, const double* X, double* Xout, int n_k) {
     if (p.v.empty()) return;
@@ -455,6 +595,7 @@ struct RunCtx {
 rbmc_status run(rbmc_model* m, const Program& pg, const RunCtx& rc) {
   hipStream_t s = m->ctx->stream;
   Arena& a = m->arena;
+  std::vector<int> open_prof;  // records opened by profile-begin ops
   for (const Op& o : pg.ops) {
     const int pid = (o.family >= 0) ? m->ctx->begin(o.family, o.alg_flops, o.alg_bytes) : -1;
     switch (o.kind) {
@@ -463,7 +604,17 @@ rbmc_status run(rbmc_model* m, const Program& pg, const RunCtx& rc) {
         launch_rstencil(a.at<StencilTask>(o.off), o.n, o.tiles, m->d_regions, m->d_qs,
                         m->plan.ns, s);
         break;
-      case 2: launch_spd_inverse(o.inv, a.at<InvTask>(o.off), s); break;
+      case 2: launch_gj_step(a.at<InvTask>(o.off), o.n, o.max_np, o.kblk, s); break;
+      case 7: launch_gj2_gather(a.at<Gj2Task>(o.off), o.n, o.tiles, s); break;
+      case 8: launch_gj2_fix(a.at<Gj2Task>(o.off), o.n, o.tiles, s); break;
+      case 9: launch_gj_finish(a.at<InvTask>(o.off), o.n, s); break;
+      case 10: open_prof.push_back(pid); break;
+      case 11:
+        if (!open_prof.empty()) {
+          m->ctx->end(open_prof.back());
+          open_prof.pop_back();
+        }
+        break;
       case 3:
         launch_panels(a.at<PanelTask>(o.off), o.n, o.tiles, m->d_regions, m->dm, o.X, o.Xout,
                       o.n_k, s);
@@ -478,7 +629,7 @@ rbmc_status run(rbmc_model* m, const Program& pg, const RunCtx& rc) {
         break;
       case 6: HIPCHK(hipMemcpyAsync(o.dst, o.src, o.bytes, hipMemcpyDeviceToDevice, s)); break;
     }
-    m->ctx->end(pid);
+    if (o.kind != 10) m->ctx->end(pid);
   }
   HIPCHK(hipGetLastError());
   return RBMC_OK;
@@ -490,7 +641,7 @@ void build_factor(rbmc_model* m, ChainSet& cs, int info_base, Program& pg) {
   Arena& a = m->arena;
   for (int t = 0; t < cs.maxT; ++t) {
     StencilList v1, v2;
-    std::vector<InvTask> inv;
+    std::vector<InvJob> inv;
     for (size_t c = 0; c < cs.chains.size(); ++c) {
       const Chain& ch = cs.chains[c];
       if (t >= ch.T) continue;
@@ -522,13 +673,17 @@ void build_factor(rbmc_model* m, ChainSet& cs, int info_base, Program& pg) {
       s2.ncols = np;
       s2.region = ch.region;
       v2.add(s2, np, m->regions[ch.region].nb);
-      InvTask it{};
+      InvJob it{};
       it.M = St;
-      it.U = cs.gjU[c];
-      it.Bp = cs.gjB[c];
       it.np = np;
       it.nb = m->regions[ch.region].nb;
       it.info = m->d_info + info_base + (int)c;
+      it.B = cs.gjB[c];
+      it.U = cs.gjU[c];
+      it.P = cs.gjP[c];
+      it.Pi = cs.gjPi[c];
+      it.Ui = cs.gjUi[c];
+      it.Bi = cs.gjBi[c];
       inv.push_back(it);
     }
     pg.stencil(a, v1);
@@ -568,8 +723,7 @@ void build_solve(rbmc_model* m, ChainSet& cs, std::vector<std::vector<double*>>&
         s.region = ch.region;
         sl.add(s, np, m->regions[ch.region].nb);
       }
-      gl.add(cs.S[c] + blk * t, ytmp[c], nullptr, pan[c][t], np, n_k, np, np, np, np, 1.0, 0.0,
-             0, 0, m->regions[ch.region].nb, m->regions[ch.region].nb);
+      gl.add(cs.S[c] + blk * t, ytmp[c], nullptr, pan[c][t], np, n_k, np, np, np, np, 1.0, 0.0, 1, 0, m->regions[ch.region].nb, m->regions[ch.region].nb);
     }
     pg.stencil(a, sl);
     pg.gemm(a, gl);
@@ -592,7 +746,7 @@ void build_solve(rbmc_model* m, ChainSet& cs, std::vector<std::vector<double*>>&
       s.region = ch.region;
       sl.add(s, np, m->regions[ch.region].nb);
       gl.add(cs.S[c] + blk * t, ytmp[c], pan[c][t], pan[c][t], np, n_k, np, np, np, np, -1.0,
-             1.0, 0, 0, m->regions[ch.region].nb, m->regions[ch.region].nb);
+             1.0, 1, 0, m->regions[ch.region].nb, m->regions[ch.region].nb);
     }
     pg.stencil(a, sl);
     pg.gemm(a, gl);
@@ -1098,7 +1252,7 @@ static rbmc_status estimate_impl(rbmc_model* m, const rbmc_est_opts* o, const do
         z.region = ch.region;
         s2.add(z, np, m->regions[ch.region].nb);
         g2.add(cs.S[c] + blk * t, cs.tmp[c], cs.S[c] + blk * t, cs.sig[c], np, np, np, np, np,
-               np, 1.0, 1.0, 0, 0, m->regions[ch.region].nb, m->regions[ch.region].nb);
+               np, 1.0, 1.0, 1, 0, m->regions[ch.region].nb, m->regions[ch.region].nb);
         if (is_core(c, t)) {
           ExtractTask e{};
           e.M = cs.sig[c];

@@ -27,20 +27,120 @@ namespace {
 constexpr int GBM = 128, GBN = 128, GBK = 16, GLDS = GBK + 2;
 }
 
-__global__ __launch_bounds__(256) void k_gemm_f64(const GemmTask* __restrict__ tasks,
-                                                  int n_tasks) {
+// Each thread moves 8 doubles of the A tile and 8 of the B tile per K step.
+// Rows/columns that are contiguous in memory go to contiguous LDS (k-major
+// per row); the other orientation is written with a stride.
+struct TileRegs {
+  double2 v[4];
+};
+
+__device__ inline void load_a(const GemmTask& tk, int m0, int k0, int tid, TileRegs& r) {
+  if (!tk.transA) {  // column-major A: 8 consecutive rows of one column k
+    const int kk = tid >> 4, mm = (tid & 15) * 8, gm = m0 + mm;
+    const double* src = tk.A + (size_t)(k0 + kk) * tk.lda + gm;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = gm + 2 * j;
+      if (c + 1 < tk.M) r.v[j] = *(const double2*)(src + 2 * j);
+      else r.v[j] = double2{c < tk.M ? src[2 * j] : 0.0, 0.0};
+    }
+  } else {  // A^T stored column-major: 8 consecutive k of one row m
+    const int mm = tid >> 1, kk = (tid & 1) * 8, gm = m0 + mm;
+    const double* src = tk.A + (size_t)gm * tk.lda + k0 + kk;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      r.v[j] = (gm < tk.M) ? *(const double2*)(src + 2 * j) : double2{0.0, 0.0};
+  }
+}
+
+__device__ inline void store_a(const GemmTask& tk, int tid, const TileRegs& r, double* As) {
+  if (!tk.transA) {
+    const int kk = tid >> 4, mm = (tid & 15) * 8;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      As[(mm + 2 * j) * GLDS + kk] = r.v[j].x;
+      As[(mm + 2 * j + 1) * GLDS + kk] = r.v[j].y;
+    }
+  } else {
+    const int mm = tid >> 1, kk = (tid & 1) * 8;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) *(double2*)&As[mm * GLDS + kk + 2 * j] = r.v[j];
+  }
+}
+
+__device__ inline void load_b(const GemmTask& tk, int n0, int k0, int tid, TileRegs& r) {
+  if (!tk.transB) {  // column-major B: 8 consecutive k of one column n
+    const int nn = tid >> 1, kk = (tid & 1) * 8, gn = n0 + nn;
+    const double* src = tk.B + (size_t)gn * tk.ldb + k0 + kk;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      r.v[j] = (gn < tk.N) ? *(const double2*)(src + 2 * j) : double2{0.0, 0.0};
+  } else {  // B^T stored column-major: 8 consecutive n of one row k
+    const int kk = tid >> 4, nn = (tid & 15) * 8, gn = n0 + nn;
+    const double* src = tk.B + (size_t)(k0 + kk) * tk.ldb + gn;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = gn + 2 * j;
+      if (c + 1 < tk.N) r.v[j] = *(const double2*)(src + 2 * j);
+      else r.v[j] = double2{c < tk.N ? src[2 * j] : 0.0, 0.0};
+    }
+  }
+}
+
+__device__ inline void store_b(const GemmTask& tk, int tid, const TileRegs& r, double* Bs) {
+  if (!tk.transB) {
+    const int nn = tid >> 1, kk = (tid & 1) * 8;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) *(double2*)&Bs[nn * GLDS + kk + 2 * j] = r.v[j];
+  } else {
+    const int kk = tid >> 4, nn = (tid & 15) * 8;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      Bs[(nn + 2 * j) * GLDS + kk] = r.v[j].x;
+      Bs[(nn + 2 * j + 1) * GLDS + kk] = r.v[j].y;
+    }
+  }
+}
+
+int gemm_task_tiles(int M, int N, int lower) {
+  const int tm = (M + GBM - 1) / GBM, tn = (N + GBN - 1) / GBN;
+  return lower ? tm * (tm + 1) / 2 : tm * tn;
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs; the logical tile of
+// a workgroup is chosen so that each XCD walks a contiguous range of tiles
+// (neighbouring tiles share A row panels in its L2).  The K loop prefetches
+// the next A/B tiles into registers while the matrix cores consume the
+// current LDS tiles.
+__global__ __launch_bounds__(256, 2) void k_gemm_f64(const GemmTask* __restrict__ tasks,
+                                                     int n_tasks, int total_tiles, int per_xcd) {
   __shared__ double As[GBM * GLDS];
   __shared__ double Bs[GBN * GLDS];
-  // locate the task of this workgroup
+  const int b = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (b >= total_tiles) return;
   int lo = 0, hi = n_tasks - 1;
-  const int b = blockIdx.x;
   while (lo < hi) {
     int mid = (lo + hi + 1) / 2;
     if (tasks[mid].tile_start <= b) lo = mid; else hi = mid - 1;
   }
   const GemmTask tk = tasks[lo];
   const int tile = b - tk.tile_start;
-  const int m0 = (tile / tk.tiles_n) * GBM, n0 = (tile % tk.tiles_n) * GBN;
+  int tm, tn;
+  if (tk.lower) {  // enumerate (tm, tn), tm >= tn
+    tm = (int)((sqrt(8.0 * tile + 1.0) - 1.0) * 0.5);
+    while ((tm + 1) * (tm + 2) / 2 <= tile) ++tm;
+    while (tm * (tm + 1) / 2 > tile) --tm;
+    tn = tile - tm * (tm + 1) / 2;
+  } else {
+    tm = tile / tk.tiles_n;
+    tn = tile % tk.tiles_n;
+  }
+  const int m0 = tm * GBM, n0 = tn * GBN;
+  if (tk.skip1 > tk.skip0) {
+    const bool rows_hit = m0 < tk.skip1 && m0 + GBM > tk.skip0;
+    const bool cols_hit = n0 < tk.skip1 && n0 + GBN > tk.skip0;
+    if (rows_hit || cols_hit) return;
+  }
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
   const int l16 = lane & 15, g = lane >> 4;
@@ -51,49 +151,18 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const GemmTask* __restrict__ t
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
 
+  TileRegs ra, rb;
+  load_a(tk, m0, 0, tid, ra);
+  load_b(tk, n0, 0, tid, rb);
+  store_a(tk, tid, ra, As);
+  store_b(tk, tid, rb, Bs);
+  __syncthreads();
   for (int k0 = 0; k0 < tk.K; k0 += GBK) {
-    // ---- A tile: As[m][k] = op(A)[m0+m][k0+k]
-    if (!tk.transA) {
-      const int kk = tid >> 4, mm = (tid & 15) * 8;
-      const int gm = m0 + mm;
-      const double* src = tk.A + (size_t)(k0 + kk) * tk.lda + gm;
-#pragma unroll
-      for (int j = 0; j < 8; j += 2) {
-        double2 v = (gm + j < tk.M) ? *(const double2*)(src + j) : double2{0.0, 0.0};
-        As[(mm + j) * GLDS + kk] = v.x;
-        As[(mm + j + 1) * GLDS + kk] = v.y;
-      }
-    } else {
-      const int mm = tid >> 1, kk = (tid & 1) * 8;
-      const int gm = m0 + mm;
-      const double* src = tk.A + (size_t)gm * tk.lda + k0 + kk;
-#pragma unroll
-      for (int j = 0; j < 8; j += 2) {
-        double2 v = (gm < tk.M) ? *(const double2*)(src + j) : double2{0.0, 0.0};
-        *(double2*)&As[mm * GLDS + kk + j] = v;
-      }
+    const bool more = k0 + GBK < tk.K;
+    if (more) {
+      load_a(tk, m0, k0 + GBK, tid, ra);
+      load_b(tk, n0, k0 + GBK, tid, rb);
     }
-    // ---- B tile: Bs[n][k] = op(B)[k0+k][n0+n]
-    if (!tk.transB) {
-      const int nn = tid >> 1, kk = (tid & 1) * 8;
-      const int gn = n0 + nn;
-      const double* src = tk.B + (size_t)gn * tk.ldb + k0 + kk;
-#pragma unroll
-      for (int j = 0; j < 8; j += 2) {
-        double2 v = (gn < tk.N) ? *(const double2*)(src + j) : double2{0.0, 0.0};
-        *(double2*)&Bs[nn * GLDS + kk + j] = v;
-      }
-    } else {
-      const int kk = tid >> 4, nn = (tid & 15) * 8;
-      const int gn = n0 + nn;
-      const double* src = tk.B + (size_t)(k0 + kk) * tk.ldb + gn;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        double v = (gn + j < tk.N) ? src[j] : 0.0;
-        Bs[(nn + j) * GLDS + kk] = v;
-      }
-    }
-    __syncthreads();
     double a[4][4], bb[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -111,6 +180,11 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const GemmTask* __restrict__ t
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = mfma64(a[i][s], bb[j][s], acc[i][j]);
     __syncthreads();
+    if (more) {
+      store_a(tk, tid, ra, As);
+      store_b(tk, tid, rb, Bs);
+      __syncthreads();
+    }
   }
   // ---- epilogue: C = alpha acc + beta Cin
 #pragma unroll
@@ -132,7 +206,8 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const GemmTask* __restrict__ t
 
 void launch_gemm(const GemmTask* d_tasks, int n_tasks, int total_tiles, hipStream_t s) {
   if (total_tiles <= 0) return;
-  k_gemm_f64<<<total_tiles, 256, 0, s>>>(d_tasks, n_tasks);
+  const int per_xcd = (total_tiles + 7) / 8;
+  k_gemm_f64<<<per_xcd * 8, 256, 0, s>>>(d_tasks, n_tasks, total_tiles, per_xcd);
 }
 
 // ---------------------------------------------------------------------------
@@ -178,30 +253,36 @@ __device__ bool lds_spd_inverse(double* P, double* rowp, double* colp, int tid) 
 }
 }  // namespace
 
-// Pivot/panel kernel: grid (np/64 row blocks, tasks).  Every workgroup
-// inverts the pivot block (cheap, avoids a launch), forms
-//   B_i = M_ik (lower-stored: i > k from M, i < k from M_ki^T, i = k: M_kk),
-//   U_i = B_i M_kk^-1  (U_k = M_kk^-1)
-// and writes B_i, U_i to the task's panels.
-__global__ __launch_bounds__(256) void k_gj_panel(const InvTask* __restrict__ tasks, int kblk) {
+// Pivot kernel: one workgroup per task inverts the 64 x 64 pivot block k
+// (symmetrized from the lower triangle) into Pi.
+__global__ __launch_bounds__(256) void k_gj_pivot(const InvTask* __restrict__ tasks, int kblk) {
   __shared__ double P[JB * JLD];
-  __shared__ double Bt[JB * JLD];
   __shared__ double rowp[JB], colp[JB];
-  const InvTask tk = tasks[blockIdx.y];
-  const int nblk = tk.np / JB;
-  if (kblk >= nblk) return;
-  const int i = blockIdx.x;
-  if (i >= nblk) return;
-  const int tid = threadIdx.x;
-  const int kb = kblk * JB, ib = i * JB;
-  const int np = tk.np;
-  // pivot block from the lower triangle, symmetrized
+  const InvTask tk = tasks[blockIdx.x];
+  if (kblk >= tk.np / JB) return;
+  const int tid = threadIdx.x, kb = kblk * JB, np = tk.np;
   for (int e = tid; e < JB * JB; e += 256) {
     const int r = e % JB, c = e / JB;
     const int rr = r > c ? r : c, cc = r > c ? c : r;
     P[r * JLD + c] = tk.M[(size_t)(kb + cc) * np + kb + rr];
   }
-  // B_i
+  const bool ok = lds_spd_inverse(P, rowp, colp, tid);
+  if (!ok && tid == 0) atomicCAS(tk.info, 0, kblk + 1);
+  for (int e = tid; e < JB * JB; e += 256) tk.Pi[e] = P[(e % JB) * JLD + e / JB];
+}
+
+// Panel kernel: grid (np/64 row blocks, tasks).  B_i = M_ik (lower-stored: i > k
+// from M, i < k from M_ki^T, i = k the pivot block), U_i = B_i Pi (U_k = Pi),
+// on the matrix cores; B_i and U_i go to the task's panels.
+__global__ __launch_bounds__(256) void k_gj_panel(const InvTask* __restrict__ tasks, int kblk) {
+  __shared__ double Bt[JB * JLD];
+  __shared__ double Ps[JB * JLD];
+  const InvTask tk = tasks[blockIdx.y];
+  const int nblk = tk.np / JB;
+  const int i = blockIdx.x;
+  if (kblk >= nblk || i >= nblk) return;
+  const int tid = threadIdx.x;
+  const int kb = kblk * JB, ib = i * JB, np = tk.np;
   for (int e = tid; e < JB * JB; e += 256) {
     const int r = e % JB, c = e / JB;
     double v;
@@ -212,18 +293,36 @@ __global__ __launch_bounds__(256) void k_gj_panel(const InvTask* __restrict__ ta
       v = tk.M[(size_t)(kb + cc) * np + kb + rr];
     }
     Bt[r * JLD + c] = v;
+    Ps[c * JLD + r] = tk.Pi[(size_t)c * JB + r];  // Ps[col][row] : k contiguous per column
   }
-  const bool ok = lds_spd_inverse(P, rowp, colp, tid);
-  if (!ok && i == 0 && tid == 0) atomicCAS(tk.info, 0, kblk + 1);
-  // U_i = B_i P  (i != k);  U_k = P
+  __syncthreads();
+  const int lane = tid & 63, w = tid >> 6, l16 = lane & 15, g = lane >> 4;
+  if (i == kblk) {
+    for (int e = tid; e < JB * JB; e += 256) {
+      const int r = e % JB, c = e / JB;
+      tk.U[(size_t)c * np + ib + r] = tk.Pi[(size_t)c * JB + r];
+      tk.Bp[(size_t)c * np + ib + r] = Bt[r * JLD + c];
+    }
+    return;
+  }
+  // wave w: rows 16w..16w+15 of U_i = B_i Pi
+  v4d acc[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) acc[c] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < JB; k0 += 4) {
+    const double a = Bt[(w * 16 + l16) * JLD + k0 + g];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] = mfma64(a, Ps[(c * 16 + l16) * JLD + k0 + g], acc[c]);
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = w * 16 + g + 4 * r, col = c * 16 + l16;
+      tk.U[(size_t)col * np + ib + row] = acc[c][r];
+    }
   for (int e = tid; e < JB * JB; e += 256) {
     const int r = e % JB, c = e / JB;
-    double v = 0.0;
-    if (i == kblk) v = P[r * JLD + c];
-    else {
-      for (int q = 0; q < JB; ++q) v += Bt[r * JLD + q] * P[q * JLD + c];
-    }
-    tk.U[(size_t)c * np + ib + r] = v;
     tk.Bp[(size_t)c * np + ib + r] = Bt[r * JLD + c];
   }
 }
@@ -240,7 +339,6 @@ __global__ __launch_bounds__(256) void k_gj_update(const InvTask* __restrict__ t
   const InvTask tk = tasks[blockIdx.y];
   const int nblk = tk.np / JB;
   if (kblk >= nblk) return;
-  // lower-triangle tile index -> (i, j)
   const int t = blockIdx.x;
   if (t >= nblk * (nblk + 1) / 2) return;
   int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
@@ -261,14 +359,12 @@ __global__ __launch_bounds__(256) void k_gj_update(const InvTask* __restrict__ t
     }
     return;
   }
-  // stage U_i (rows of tile) and B_j with k contiguous: Us[r][q] = U[ib+r][q], Bs[c][q] = B[jb+c][q]
   for (int e = tid; e < JB * JB; e += 256) {
     const int r = e % JB, q = e / JB;
     Us[r * JLD + q] = tk.U[(size_t)q * np + ib + r];
     Bs[r * JLD + q] = tk.Bp[(size_t)q * np + jb + r];
   }
   __syncthreads();
-  // wave w owns rows 16w..16w+15 and all 64 columns (four 16x16 MFMA tiles)
   const int lane = tid & 63, w = tid >> 6, l16 = lane & 15, g = lane >> 4;
   v4d acc[4];
 #pragma unroll
@@ -303,16 +399,112 @@ __global__ void k_gj_finish(const InvTask* __restrict__ tasks) {
   }
 }
 
-void launch_spd_inverse(const std::vector<InvTask>& tasks, InvTask* d_tasks, hipStream_t s) {
-  if (tasks.empty()) return;
-  int maxblk = 0;
-  for (const InvTask& t : tasks) maxblk = std::max(maxblk, t.np / JB);
-  const int ntask = (int)tasks.size();
-  for (int k = 0; k < maxblk; ++k) {
-    k_gj_panel<<<dim3(maxblk, ntask), 256, 0, s>>>(d_tasks, k);
-    k_gj_update<<<dim3(maxblk * (maxblk + 1) / 2, ntask), 256, 0, s>>>(d_tasks, k);
+void launch_gj_step(const InvTask* d_tasks, int n_tasks, int max_np, int kblk, hipStream_t s) {
+  const int maxblk = max_np / JB;
+  if (n_tasks <= 0 || kblk >= maxblk) return;
+  k_gj_pivot<<<n_tasks, 256, 0, s>>>(d_tasks, kblk);
+  k_gj_panel<<<dim3(maxblk, n_tasks), 256, 0, s>>>(d_tasks, kblk);
+  k_gj_update<<<dim3(maxblk * (maxblk + 1) / 2, n_tasks), 256, 0, s>>>(d_tasks, kblk);
+}
+
+void launch_gj_finish(const InvTask* d_tasks, int n_tasks, hipStream_t s) {
+  if (n_tasks <= 0) return;
+  k_gj_finish<<<dim3(1024, n_tasks), 256, 0, s>>>(d_tasks);
+}
+
+// ---------------------------------------------------------------------------
+// Outer (block 256) level of the sweep.  Tiles are 64 x 64.
+// ---------------------------------------------------------------------------
+int gj2_tiles(int np, int w) { return (np / 64) * (w / 64); }
+
+template <class T>
+__device__ inline int find_task(const T* __restrict__ tasks, int n_tasks, int b) {
+  int lo = 0, hi = n_tasks - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) / 2;
+    if (tasks[mid].tile_start <= b) lo = mid; else hi = mid - 1;
   }
-  k_gj_finish<<<dim3(1024, ntask), 256, 0, s>>>(d_tasks);
+  return lo;
+}
+
+// B[r, c] = M[r, kb + c] (from the lower triangle), P = B[kb:kb+w, :]
+__global__ __launch_bounds__(256) void k_gj2_gather(const Gj2Task* __restrict__ tasks,
+                                                    int n_tasks) {
+  __shared__ double T[64 * 65];
+  const Gj2Task tk = tasks[find_task(tasks, n_tasks, blockIdx.x)];
+  const int tile = blockIdx.x - tk.tile_start;
+  const int tw = tk.w / 64;
+  const int r0 = (tile / tw) * 64, c0 = (tile % tw) * 64;
+  const int np = tk.np, tid = threadIdx.x;
+  const int col0 = tk.kb + c0;  // global column of the tile
+  const bool lower = r0 >= col0 + 64 || r0 == col0;  // whole tile (or diagonal tile) below
+  if (r0 >= col0 + 64) {
+    for (int e = tid; e < 4096; e += 256) {
+      const int r = e % 64, c = e / 64;
+      T[c * 65 + r] = tk.M[(size_t)(col0 + c) * np + r0 + r];
+    }
+  } else if (r0 + 64 <= col0) {  // strictly above: read the transposed lower tile
+    for (int e = tid; e < 4096; e += 256) {
+      const int c = e % 64, r = e / 64;
+      T[c * 65 + r] = tk.M[(size_t)(r0 + r) * np + col0 + c];
+    }
+  } else {  // diagonal tile
+    for (int e = tid; e < 4096; e += 256) {
+      const int r = e % 64, c = e / 64;
+      const int gr = r0 + r, gc = col0 + c;
+      T[c * 65 + r] = gr >= gc ? tk.M[(size_t)gc * np + gr] : tk.M[(size_t)gr * np + gc];
+    }
+  }
+  (void)lower;
+  __syncthreads();
+  for (int e = tid; e < 4096; e += 256) {
+    const int r = e % 64, c = e / 64;
+    const double v = T[c * 65 + r];
+    tk.B[(size_t)(c0 + c) * np + r0 + r] = v;
+    const int pr = r0 + r - tk.kb;
+    if (pr >= 0 && pr < tk.w) tk.P[(size_t)(c0 + c) * tk.w + pr] = v;
+  }
+}
+
+// Swept block row/column: M[r, kb+c] = U[r, c] (r >= kb + w),
+// M[kb+r, j] = U[j, r] (j < kb), M[kb+r, kb+c] = -P^-1[r, c].
+// Tiles: (np/64) x (w/64) over (row block of U, column c).
+__global__ __launch_bounds__(256) void k_gj2_fix(const Gj2Task* __restrict__ tasks, int n_tasks) {
+  __shared__ double T[64 * 65];
+  const Gj2Task tk = tasks[find_task(tasks, n_tasks, blockIdx.x)];
+  const int tile = blockIdx.x - tk.tile_start;
+  const int tw = tk.w / 64;
+  const int r0 = (tile / tw) * 64, c0 = (tile % tw) * 64;
+  const int np = tk.np, tid = threadIdx.x, kb = tk.kb;
+  if (r0 >= kb + tk.w) {  // below the pivot: column block
+    for (int e = tid; e < 4096; e += 256) {
+      const int r = e % 64, c = e / 64;
+      tk.M[(size_t)(kb + c0 + c) * np + r0 + r] = tk.U[(size_t)(c0 + c) * np + r0 + r];
+    }
+  } else if (r0 < kb) {  // left of the pivot: row block (lower part), transposed
+    for (int e = tid; e < 4096; e += 256) {
+      const int r = e % 64, c = e / 64;
+      T[c * 65 + r] = tk.U[(size_t)(c0 + c) * np + r0 + r];  // U[j = r0+r, c0+c]
+    }
+    __syncthreads();
+    for (int e = tid; e < 4096; e += 256) {
+      const int c = e % 64, r = e / 64;  // M[kb + c0 + c, r0 + r] = U[r0 + r, c0 + c]
+      tk.M[(size_t)(r0 + r) * np + kb + c0 + c] = T[c * 65 + r];
+    }
+  } else {  // pivot block
+    for (int e = tid; e < 4096; e += 256) {
+      const int r = e % 64, c = e / 64;
+      tk.M[(size_t)(kb + c0 + c) * np + r0 + r] = -tk.P[(size_t)(c0 + c) * tk.w + (r0 - kb) + r];
+    }
+  }
+}
+
+void launch_gj2_gather(const Gj2Task* d_tasks, int n_tasks, int total_tiles, hipStream_t s) {
+  if (total_tiles > 0) k_gj2_gather<<<total_tiles, 256, 0, s>>>(d_tasks, n_tasks);
+}
+
+void launch_gj2_fix(const Gj2Task* d_tasks, int n_tasks, int total_tiles, hipStream_t s) {
+  if (total_tiles > 0) k_gj2_fix<<<total_tiles, 256, 0, s>>>(d_tasks, n_tasks);
 }
 
 // ---------------------------------------------------------------------------

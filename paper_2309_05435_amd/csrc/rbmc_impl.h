@@ -129,19 +129,42 @@ struct GemmTask {
   int transA, transB;
   int tiles_n;
   int tile_start;
+  int lower;          // 1: square C, only 128-tiles with row index >= column index
+  int skip0, skip1;   // tiles meeting rows or columns [skip0, skip1) are skipped
 };
+int gemm_task_tiles(int M, int N, int lower);
 void launch_gemm(const GemmTask* d_tasks, int n_tasks, int total_tiles, hipStream_t s);
 
-// Gauss-Jordan sweep inversion of SPD matrices (in place, lower-stored -> full symmetric)
+// Gauss-Jordan sweep inversion of SPD matrices, block 64 (in place; only the
+// lower triangle is kept current; the finish pass negates and symmetrizes).
 struct InvTask {
-  double* M;     // np x np col-major, ld = np; on exit M^-1 (full symmetric)
+  double* M;     // np x np col-major, ld = np
   double* U;     // np x 64 workspace
   double* Bp;    // np x 64 workspace
+  double* Pi;    // 64 x 64 workspace (inverse of the pivot block)
   int np;
   int nb;        // unpadded size (for work accounting)
   int* info;     // set to (block index + 1) on non-SPD pivot
 };
-void launch_spd_inverse(const std::vector<InvTask>& tasks, InvTask* d_tasks, hipStream_t s);
+// one rank-64 sweep step k of every task (tasks with np <= 64 k are skipped)
+void launch_gj_step(const InvTask* d_tasks, int n_tasks, int max_np, int kblk, hipStream_t s);
+void launch_gj_finish(const InvTask* d_tasks, int n_tasks, hipStream_t s);
+
+// Outer level (block 256) of the sweep for large blocks: gather the column
+// block [kb, kb + w) of M (lower-stored) into B (np x w) and the pivot block
+// into P (w x w, ld w); after P <- P^-1 and U = B P, the GEMM updates the
+// lower tiles and the fix pass writes the swept row/column block.
+struct Gj2Task {
+  double* M;
+  double* B;   // np x 256
+  double* U;   // np x 256
+  double* P;   // 256 x 256
+  int np, kb, w;
+  int tile_start;
+};
+void launch_gj2_gather(const Gj2Task* d_tasks, int n_tasks, int total_tiles, hipStream_t s);
+void launch_gj2_fix(const Gj2Task* d_tasks, int n_tasks, int total_tiles, hipStream_t s);
+int gj2_tiles(int np, int w);
 
 // restricted-stencil products on dense column-major matrices (rows = region nodes):
 //   out = alpha * Q_R * op(M) + gamma * Q_R + diag(dv) (+ I on pad) + beta * In

@@ -1,0 +1,66 @@
+"""Parity at the benchmark's full size (64 x 64 grid, T = 32, n = 131,072,
+16 time slabs, 2-hop overlap, 500 samples) in the launch configuration that
+bench.py times.  The oracle cannot run the whole estimator at this size, so
+it checks sampled outputs one by one (conjugate gradients on Q_AA for single
+entries) and properties that hold at any size."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2309_05435_amd.inputs import WORKLOADS, normals
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2309_05435_amd import binding as B  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def setup():
+    wl = WORKLOADS["slab64"]
+    print("fullsize: building models", flush=True)
+    gm = B.Model(wl)
+    M = O.OracleModel.from_workload(wl)
+    lab = O.grid_cores(wl.m, wl.m, wl.T, wl.n_tslabs, 1, 1)
+    yield wl, gm, M, lab
+    gm.close()
+
+
+def test_estimator_sampled_entries_full_size(setup):
+    wl, gm, M, lab = setup
+    x = normals((wl.n_k, gm.n), 77)
+    print("fullsize: estimate_from_samples", flush=True)
+    diag, tr, st, rep = gm.estimate_from_samples(torch.from_numpy(x).cuda(), grad_mask=0b1111)
+    d = diag.cpu().numpy()
+    # entries: first/last time step, slab edges, interior; corner and centre nodes
+    ns = wl.m * wl.m
+    picks = [(0, 0), (1, 2080), (7, 63), (8, 4095), (15, 1000), (16, 2047), (31, 4032),
+             (23, 2)]
+    for t, s in picks:
+        i = t * ns + s
+        p = int(lab[i])
+        det, full = M.entry(lab, p, wl.n_l, i, x, rtol=1e-13)
+        print(f"fullsize: node t={t} s={s} gpu={d[i]:.15e} oracle={full:.15e}", flush=True)
+        assert abs(d[i] - full) <= 1e-9 * full
+    # the log tau / log sigma identities hold exactly at any size
+    D = wl.mask() / wl.sigma ** 2
+    s2 = np.sum(D * d)
+    assert abs(tr[1] + s2 - gm.n) < 1e-9 * gm.n
+    assert abs(tr[3] + 2.0 * s2) < 1e-10 * s2
+
+
+def test_sampler_residuals_full_size(setup):
+    wl, gm, M, lab = setup
+    z = normals((24, gm.n + gm.n_obs), 78)
+    print("fullsize: sample", flush=True)
+    x, st, rep = gm.sample(torch.from_numpy(z).cuda(), rtol=wl.rtol)
+    assert st == B.RBMC_OK
+    x = x.cpu().numpy()
+    b = M.rhs(z)
+    res = np.linalg.norm(M.apply(O.Q, x) - b, axis=1) / np.linalg.norm(b, axis=1)
+    print(f"fullsize: pcg iters max {rep.pcg_it_max} max residual {res.max():.3e}", flush=True)
+    assert res.max() <= 1.05 * wl.rtol
+    assert 50 <= rep.pcg_it_max <= 200

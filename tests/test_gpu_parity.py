@@ -49,6 +49,10 @@ CASES = [
     (10, 8, 4, 1, 0),
     (9, 6, 1, 1, 1),
     (13, 1, 1, 2, 1),
+    # spatial blocks above 256 nodes take the two-level (rank-256) inversion
+    (20, 6, 2, 1, 1),
+    (24, 5, 2, 1, 1),
+    (34, 4, 1, 2, 1),
 ]
 
 
