@@ -76,6 +76,8 @@ def main():
     ap.add_argument("--workload", default="slab64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-m", type=int, default=24)
+    ap.add_argument("--pc", default=None,
+                    help="block-Jacobi blocks 'slabs,tiles_x,tiles_y' (default: the cores)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -90,7 +92,8 @@ def main():
 
     wl = WORKLOADS[args.workload]
     torch.cuda.set_device(0)
-    gm = B.Model(wl)
+    pc = tuple(int(v) for v in args.pc.split(",")) if args.pc else None
+    gm = B.Model(wl, pc=pc)
     z = torch.from_numpy(wl.z()).to("cuda")
     diag = torch.empty(gm.n, dtype=torch.float64, device="cuda")
     grad = 0b111
@@ -152,7 +155,8 @@ def main():
         "config": {"workload": wl.name, "grid": f"{wl.m}x{wl.m}", "T": wl.T, "n": gm.n,
                    "n_obs": gm.n_obs, "n_samples": wl.n_k, "n_tslabs": wl.n_tslabs,
                    "n_tiles": wl.n_tiles, "overlap_hops": wl.n_l, "pcg_rtol": wl.rtol,
-                   "precision": "fp64", "precond": "block-jacobi", "traces": "logkappa,logtau,rho"},
+                   "precision": "fp64", "precond": "block-jacobi",
+                   "pc_blocks": list(pc) if pc else "cores", "traces": "logkappa,logtau,rho"},
         "pcg_iters": {"mean": last["pcg_it_mean"], "max": last["pcg_it_max"]},
         "err_estimate": last["err_estimate"],
         "accuracy_gate_1pct": bool(last["err_estimate"] <= 0.01),

@@ -74,10 +74,15 @@ typedef struct {
  * (len mod parts) pieces get one extra element.  Core p =
  * (slab * n_tiles_y + tile_y) * n_tiles_x + tile_x.  Each core is grown by
  * overlap_hops rounds of graph neighbours of Q to Omega_p* (Alg. 4); the
- * separator is S_p = N(Omega_p*) \ Omega_p*.  The block-Jacobi PCG
- * preconditioner uses the same cores as its blocks. */
+ * separator is S_p = N(Omega_p*) \ Omega_p*.
+ * The blocks of the block-Jacobi PCG preconditioner (Sec. 3.3 names block
+ * Jacobi as the block form of the split preconditioner) are the cores unless
+ * pc_tslabs > 0, in which case they are pc_tslabs time slabs x pc_tiles_x x
+ * pc_tiles_y spatial boxes split by the same rule; the choice changes the
+ * sampler's iteration count, not the samples it converges to. */
 typedef struct {
   int32_t n_tslabs, n_tiles_x, n_tiles_y, overlap_hops;
+  int32_t pc_tslabs, pc_tiles_x, pc_tiles_y; /* 0 = same as the cores */
 } rbmc_decomp_desc;
 
 enum { RBMC_FP64 = 0, RBMC_MIXED = 1 };

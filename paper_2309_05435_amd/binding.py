@@ -43,7 +43,8 @@ class rbmc_model_desc(C.Structure):
 
 class rbmc_decomp_desc(C.Structure):
     _fields_ = [("n_tslabs", C.c_int32), ("n_tiles_x", C.c_int32), ("n_tiles_y", C.c_int32),
-                ("overlap_hops", C.c_int32)]
+                ("overlap_hops", C.c_int32), ("pc_tslabs", C.c_int32), ("pc_tiles_x", C.c_int32),
+                ("pc_tiles_y", C.c_int32)]
 
 
 class rbmc_est_opts(C.Structure):
@@ -208,7 +209,7 @@ def popcount(mask: int) -> int:
 class Model:
     """Owns a context + model; inputs/outputs are torch tensors on the device."""
 
-    def __init__(self, wl, mask=None, theta=None, device: int = 0, decomp=None):
+    def __init__(self, wl, mask=None, theta=None, device: int = 0, decomp=None, pc=None):
         import torch
         self.wl = wl
         self.torch = torch
@@ -220,6 +221,7 @@ class Model:
         self.desc, self._mask = make_desc(wl.m, wl.m, wl.T, wl.h, th, mask)
         if decomp is None:
             decomp = (wl.n_tslabs, wl.n_tiles, wl.n_tiles, wl.n_l)
+        decomp = tuple(decomp) + (tuple(pc) if pc else ())
         self.decomp = rbmc_decomp_desc(*decomp)
         self.m = rbmc_model_create(self.ctx, self.desc, self.decomp)
         self.n = wl.m * wl.m * wl.T

@@ -333,6 +333,13 @@ struct GemmList {
     tiles += gemm_tiles(M, N);
     v.push_back(t);
   }
+  // restrict the last product to the lower 128-tiles of a square result
+  void set_last_lower() {
+    GemmTask& t = v.back();
+    tiles -= gemm_tiles(t.M, t.N);
+    tiles += gemm_task_tiles(t.M, t.N, 1);
+    t.lower = 1;
+  }
   // outer sweep update of the lower tiles: M -= U B^T outside rows/cols [kb, kb + w)
   void add_sweep(double* Mx, int np, const double* U, const double* B, int w, int kb) {
     GemmTask t{};
@@ -365,10 +372,12 @@ struct StencilList {
   std::vector<StencilTask> v;
   int tiles = 0;
   double bytes = 0.0;
+  int max_sparse_np = 0;  // largest block with sparse terms (0: none)
   void add(StencilTask t, int np, int nb) {
     t.tile_start = tiles;
     tiles += (np / 64) * ((t.ncols + 63) / 64);
     bytes += 16.0 * nb * (double)t.ncols;
+    if (t.gamma != 0.0 || t.dv != nullptr || t.pad_identity) max_sparse_np = std::max(max_sparse_np, np);
     v.push_back(t);
   }
 };
@@ -435,6 +444,16 @@ struct Program {
     o.tiles = s.tiles;
     o.family = RBMC_KF_RSTENCIL;
     o.alg_bytes = s.bytes;
+    o.max_np = s.max_sparse_np;
+    ops.push_back(std::move(o));
+  }
+  void mirror(Arena& a, const std::vector<InvTask>& t) {
+    if (t.empty()) return;
+    Op o;
+    o.kind = 12;
+    o.off = a.push(t);
+    o.n = (int)t.size();
+    for (const InvTask& it : t) o.max_np = std::max(o.max_np, it.np);
     ops.push_back(std::move(o));
   }
   // rank-64 sweep of a list of blocks (all steps) followed by the finish pass
@@ -602,8 +621,9 @@ rbmc_status run(rbmc_model* m, const Program& pg, const RunCtx& rc) {
       case 0: launch_gemm(a.at<GemmTask>(o.off), o.n, o.tiles, s); break;
       case 1:
         launch_rstencil(a.at<StencilTask>(o.off), o.n, o.tiles, m->d_regions, m->d_qs,
-                        m->plan.ns, s);
+                        m->plan.ns, o.max_np, s);
         break;
+      case 12: launch_mirror(a.at<InvTask>(o.off), o.n, o.max_np, s); break;
       case 2: launch_gj_step(a.at<InvTask>(o.off), o.n, o.max_np, o.kblk, s); break;
       case 7: launch_gj2_gather(a.at<Gj2Task>(o.off), o.n, o.tiles, s); break;
       case 8: launch_gj2_fix(a.at<Gj2Task>(o.off), o.n, o.tiles, s); break;
@@ -1198,6 +1218,7 @@ static rbmc_status estimate_impl(rbmc_model* m, const rbmc_est_opts* o, const do
     StencilList s1, s2;
     GemmList g1, g2;
     TileList<ExtractTask> e1, e2;
+    std::vector<InvTask> mir;
     for (int c = 0; c < nchains; ++c) {
       const Chain& ch = cs.chains[c];
       if (t > ch.T - 2) continue;
@@ -1253,6 +1274,13 @@ static rbmc_status estimate_impl(rbmc_model* m, const rbmc_est_opts* o, const do
         s2.add(z, np, m->regions[ch.region].nb);
         g2.add(cs.S[c] + blk * t, cs.tmp[c], cs.S[c] + blk * t, cs.sig[c], np, np, np, np, np,
                np, 1.0, 1.0, 1, 0, m->regions[ch.region].nb, m->regions[ch.region].nb);
+        g2.set_last_lower();  // Sigma_tt is symmetric: lower tiles, then mirrored
+        {
+          InvTask mt{};
+          mt.M = cs.sig[c];
+          mt.np = np;
+          mir.push_back(mt);
+        }
         if (is_core(c, t)) {
           ExtractTask e{};
           e.M = cs.sig[c];
@@ -1271,6 +1299,7 @@ static rbmc_status estimate_impl(rbmc_model* m, const rbmc_est_opts* o, const do
     tak.extract(m->arena, e1);
     tak.stencil(m->arena, s2);
     tak.gemm(m->arena, g2);
+    tak.mirror(m->arena, mir);
     tak.extract(m->arena, e2);
   }
   // ---- corrections ----

@@ -224,30 +224,41 @@ constexpr int JLD = JB + 1;
 
 // In-LDS sweep of a 64x64 SPD block P (ld JLD): P <- P^-1.  Returns false on
 // a non-positive pivot.
+// Thread tid owns column c = tid % 64 and rows r = tid / 64 + 4 j (j < 16); the
+// 16 owned entries live in registers for the whole sweep, so a pivot step is
+// one broadcast of row/column p through LDS and 16 independent updates.
 __device__ bool lds_spd_inverse(double* P, double* rowp, double* colp, int tid) {
+  const int c = tid & 63, r0 = tid >> 6;
+  double v[16];
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 16; ++j) v[j] = P[(r0 + 4 * j) * JLD + c];
   bool ok = true;
   for (int p = 0; p < JB; ++p) {
+    // publish row p and column p of the current matrix
+    if ((p & 3) == r0) rowp[c] = v[p >> 2];
+    if (c == p) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) colp[r0 + 4 * j] = v[j];
+    }
     __syncthreads();
-    const double piv = P[p * JLD + p];
+    const double piv = rowp[p];
     if (!(piv > 0.0)) ok = false;
-    if (tid < JB) {
-      rowp[tid] = P[p * JLD + tid];
-      colp[tid] = P[tid * JLD + p];
+    const double ip = 1.0 / piv;
+    const double rc = rowp[c] * ip;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int r = r0 + 4 * j;
+      const double cr = colp[r];
+      double nv = v[j] - cr * rc;
+      if (c == p) nv = cr * ip;
+      if (r == p) nv = (c == p) ? -ip : rc;
+      v[j] = nv;
     }
     __syncthreads();
-    const double ip = 1.0 / piv;
-    for (int e = tid; e < JB * JB; e += 256) {
-      const int r = e / JB, c = e % JB;
-      double v;
-      if (r == p && c == p) v = -ip;
-      else if (r == p) v = rowp[c] * ip;
-      else if (c == p) v = colp[r] * ip;
-      else v = P[r * JLD + c] - colp[r] * rowp[c] * ip;
-      P[r * JLD + c] = v;
-    }
   }
-  __syncthreads();
-  for (int e = tid; e < JB * JB; e += 256) P[(e / JB) * JLD + e % JB] = -P[(e / JB) * JLD + e % JB];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) P[(r0 + 4 * j) * JLD + c] = -v[j];
   __syncthreads();
   return ok;
 }
@@ -530,18 +541,9 @@ __global__ __launch_bounds__(256) void k_rstencil(const StencilTask* __restrict_
   const int tid = threadIdx.x;
   const bool square = (tk.dv != nullptr) || tk.pad_identity || tk.gamma != 0.0;
 
+  // the sparse terms (gamma Q_R, diag(dv), padded identity) are added by
+  // k_sparse_add after this pass
   auto extra = [&](int a, int c, double v) {
-    if (a < rg.nb) {
-      if (tk.gamma != 0.0 && c < rg.nb) {
-        const int node = rg.nodes[a];
-#pragma unroll
-        for (int q = 0; q < kNS; ++q)
-          if (rg.nbr[a * kNS + q] == c) v += tk.gamma * qs[(size_t)q * ns + node];
-      }
-      if (tk.dv && a == c) v += tk.dv[rg.nodes[a]];
-    } else if (tk.pad_identity && a == c) {
-      v += 1.0;
-    }
     if (tk.beta != 0.0) v += tk.beta * tk.In[(size_t)c * tk.ldin + a];
     return v;
   };
@@ -601,10 +603,66 @@ __global__ __launch_bounds__(256) void k_rstencil(const StencilTask* __restrict_
   }
 }
 
+// out += gamma Q_R + diag(dv) + I on the padded diagonal: one thread per row,
+// touching only the stencil positions.  Grid (row blocks of 256, tasks).
+__global__ __launch_bounds__(256) void k_sparse_add(const StencilTask* __restrict__ tasks,
+                                                    const RegionDev* __restrict__ regs,
+                                                    const double* __restrict__ qs, int ns) {
+  const StencilTask tk = tasks[blockIdx.y];
+  if (tk.gamma == 0.0 && tk.dv == nullptr && !tk.pad_identity) return;
+  const RegionDev rg = regs[tk.region];
+  const int a = blockIdx.x * 256 + threadIdx.x;
+  if (a >= rg.np) return;
+  if (a < rg.nb) {
+    const int node = rg.nodes[a];
+    if (tk.gamma != 0.0)
+      for (int q = 0; q < kNS; ++q) {
+        const int c = rg.nbr[a * kNS + q];
+        if (c >= 0) tk.out[(size_t)c * tk.ldout + a] += tk.gamma * qs[(size_t)q * ns + node];
+      }
+    if (tk.dv) tk.out[(size_t)a * tk.ldout + a] += tk.dv[node];
+  } else if (tk.pad_identity) {
+    tk.out[(size_t)a * tk.ldout + a] += 1.0;
+  }
+}
+
 void launch_rstencil(const StencilTask* d_tasks, int n_tasks, int total_tiles,
-                     const RegionDev* d_regions, const double* qs, int ns, hipStream_t s) {
+                     const RegionDev* d_regions, const double* qs, int ns, int max_np,
+                     hipStream_t s) {
   if (total_tiles <= 0) return;
   k_rstencil<<<total_tiles, 256, 0, s>>>(d_tasks, n_tasks, d_regions, qs, ns);
+  if (max_np > 0)
+    k_sparse_add<<<dim3((max_np + 255) / 256, n_tasks), 256, 0, s>>>(d_tasks, d_regions, qs, ns);
+}
+
+// Lower triangle -> upper triangle (full symmetric), 64 x 64 tiles through LDS.
+// Grid (lower tiles of the largest block, tasks).
+__global__ __launch_bounds__(256) void k_mirror(const InvTask* __restrict__ tasks) {
+  __shared__ double T[64 * 65];
+  const InvTask tk = tasks[blockIdx.y];
+  const int np = tk.np, nt = np / 64;
+  const int t = blockIdx.x;
+  if (t >= nt * (nt + 1) / 2) return;
+  int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((I + 1) * (I + 2) / 2 <= t) ++I;
+  while (I * (I + 1) / 2 > t) --I;
+  const int J = t - I * (I + 1) / 2;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 4096; e += 256) {  // lower tile (rows I, cols J)
+    const int r = e % 64, c = e / 64;
+    T[c * 65 + r] = tk.M[(size_t)(J * 64 + c) * np + I * 64 + r];
+  }
+  __syncthreads();
+  for (int e = tid; e < 4096; e += 256) {  // upper tile (rows J, cols I): M[J+c, I+r] = T[c][r]
+    const int c = e % 64, r = e / 64;
+    if (I == J && c <= r) continue;  // diagonal tile: only its strict upper part
+    tk.M[(size_t)(I * 64 + r) * np + J * 64 + c] = T[c * 65 + r];
+  }
+}
+
+void launch_mirror(const InvTask* d_tasks, int n_tasks, int max_np, hipStream_t s) {
+  const int nt = max_np / 64;
+  if (n_tasks > 0 && nt > 0) k_mirror<<<dim3(nt * (nt + 1) / 2, n_tasks), 256, 0, s>>>(d_tasks);
 }
 
 }  // namespace rbmc

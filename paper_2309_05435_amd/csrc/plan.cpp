@@ -104,23 +104,45 @@ std::string make_plan(const rbmc_model_desc& d, const rbmc_decomp_desc& dc, Plan
         c.cT = cT;
         c.core_id = p;
         plan.sub.push_back(c);
-        Chain b;
-        b.region = find_region(plan, x0, x1, y0, y1, 0);
-        b.t0 = ct0;
-        b.T = cT;
-        b.ct0 = ct0;
-        b.cT = cT;
-        b.core_id = p;
-        plan.bj.push_back(b);
+        if (dc.pc_tslabs <= 0) {
+          Chain b;
+          b.region = find_region(plan, x0, x1, y0, y1, 0);
+          b.t0 = ct0;
+          b.T = cT;
+          b.ct0 = ct0;
+          b.cT = cT;
+          b.core_id = p;
+          plan.bj.push_back(b);
+        }
       }
+  if (dc.pc_tslabs > 0) {
+    const int pt = dc.pc_tslabs, px = dc.pc_tiles_x, py = dc.pc_tiles_y;
+    if (pt > d.T || px < 1 || px > d.mx || py < 1 || py > d.my)
+      return "preconditioner blocks: pc_tslabs in [1, T], pc_tiles_x in [1, mx], pc_tiles_y in [1, my]";
+    for (int sl = 0; sl < pt; ++sl)
+      for (int ty = 0; ty < py; ++ty)
+        for (int tx = 0; tx < px; ++tx) {
+          Chain b;
+          const int x0 = piece_start(tx, d.mx, px), y0 = piece_start(ty, d.my, py);
+          b.region = find_region(plan, x0, x0 + piece_len(tx, d.mx, px) - 1, y0,
+                                 y0 + piece_len(ty, d.my, py) - 1, 0);
+          b.t0 = piece_start(sl, d.T, pt);
+          b.T = piece_len(sl, d.T, pt);
+          b.ct0 = b.t0;
+          b.cT = b.T;
+          b.core_id = -1;
+          plan.bj.push_back(b);
+        }
+  }
   return "";
 }
 
 void plan_labels(const Plan& plan, int32_t* label) {
-  for (const Chain& c : plan.bj) {
+  for (const Chain& c : plan.sub) {
     const Region& g = plan.regions[c.region];
-    for (int t = c.t0; t < c.t0 + c.T; ++t)
-      for (int s : g.nodes) label[(size_t)t * plan.ns + s] = c.core_id;
+    for (int t = c.ct0; t < c.ct0 + c.cT; ++t)
+      for (int a = 0; a < g.nb(); ++a)
+        if (g.in_box[a]) label[(size_t)t * plan.ns + g.nodes[a]] = c.core_id;
   }
 }
 

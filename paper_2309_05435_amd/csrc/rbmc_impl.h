@@ -181,8 +181,12 @@ struct StencilTask {
   int region;          // index into region table
   int tile_start;
 };
+// max_np > 0: also add the sparse terms (gamma Q_R, diag(dv), pad identity)
 void launch_rstencil(const StencilTask* d_tasks, int n_tasks, int total_tiles,
-                     const RegionDev* d_regions, const double* qs, int ns, hipStream_t s);
+                     const RegionDev* d_regions, const double* qs, int ns, int max_np,
+                     hipStream_t s);
+// copy the lower triangle of each task's M (np x np) onto its upper triangle
+void launch_mirror(const InvTask* d_tasks, int n_tasks, int max_np, hipStream_t s);
 
 // Panel transfers between global multi-vectors (n x n_k) and chain panels
 // (np x n_k, ld np): mode 0 gather (pad rows zeroed), 1 scatter, 2 correction

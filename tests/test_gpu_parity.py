@@ -130,6 +130,23 @@ def test_sampler_matches_exact_solve(case):
     gm.close()
 
 
+@pytest.mark.parametrize("pc", [(1, 2, 2), (2, 3, 1), (8, 1, 1)])
+def test_sampler_with_other_block_jacobi_blocks(pc):
+    """Preconditioner blocks other than the cores change the iteration count,
+    not the solution the sampler converges to."""
+    wl = wl_of(14, 8, 2, 1, 1)
+    say("sampler pc", pc)
+    M = oracle_model(wl)
+    z = normals((9, M.n + M.n_obs), 32)
+    x_ref = M.sample(z)
+    gm = B.Model(wl, pc=pc)
+    x, st, rep = gm.sample(dev(z), rtol=1e-13, maxit=5000)
+    assert st == B.RBMC_OK
+    err = np.linalg.norm(x.cpu().numpy() - x_ref, axis=1) / np.linalg.norm(x_ref, axis=1)
+    assert err.max() < 1e-9
+    gm.close()
+
+
 def test_full_estimate_matches_oracle_pipeline():
     wl = wl_of(12, 8, 3, 1, 1)
     say("estimate")
