@@ -76,8 +76,13 @@ def main():
     ap.add_argument("--workload", default="slab64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-m", type=int, default=24)
-    ap.add_argument("--pc", default=None,
-                    help="block-Jacobi blocks 'slabs,tiles_x,tiles_y' (default: the cores)")
+    ap.add_argument("--pc", default="workload",
+                    help="block-Jacobi blocks 'slabs,tiles_x,tiles_y', 'cores', or 'workload' "
+                         "(the workload's tuned shape)")
+    ap.add_argument("--no-gate", action="store_true",
+                    help="skip the run at the sample count that reaches <= 1%% error")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the run with block-Jacobi blocks equal to the cores")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -92,7 +97,12 @@ def main():
 
     wl = WORKLOADS[args.workload]
     torch.cuda.set_device(0)
-    pc = tuple(int(v) for v in args.pc.split(",")) if args.pc else None
+    if args.pc == "workload":
+        pc = wl.pc
+    elif args.pc == "cores":
+        pc = None
+    else:
+        pc = tuple(int(v) for v in args.pc.split(","))
     gm = B.Model(wl, pc=pc)
     z = torch.from_numpy(wl.z()).to("cuda")
     diag = torch.empty(gm.n, dtype=torch.float64, device="cuda")
@@ -104,6 +114,20 @@ def main():
         # rebuilding Q(theta) invalidates every factor: each step factors again
         B.rbmc_model_set_theta(gm.m, *theta)
         return B.rbmc_estimate(gm.m, opts, z, 0, diag, B.popcount(grad))
+
+    def timed_once(model, n_k, zz, reps=1):
+        """warm-up call, then `reps` timed calls; returns (seconds per call, report)."""
+        o = B.make_opts(n_k, pcg_maxit=5000, pcg_rtol=wl.rtol, grad_mask=grad)
+        d = torch.empty(model.n, dtype=torch.float64, device="cuda")
+        B.rbmc_model_set_theta(model.m, *theta)
+        B.rbmc_estimate(model.m, o, zz, 0, d, B.popcount(grad))
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            B.rbmc_model_set_theta(model.m, *theta)
+            _, _, rp = B.rbmc_estimate(model.m, o, zz, 0, d, B.popcount(grad))
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps, rp.as_dict()
 
     for _ in range(args.warmup):
         step()
@@ -166,9 +190,36 @@ def main():
         "roofline": roof,
         "cpu_baseline": None,
     }
+    gm.close()
+    del z
+    torch.cuda.empty_cache()
+    if not args.no_gate:
+        # the plug-in error falls as 1/sqrt(n_k): the sample count for <= 1% (with margin)
+        err = last["err_estimate"]
+        if err <= 0.0095:
+            out["accuracy_gate"] = {"n_samples": wl.n_k, "value": value, "err_estimate": err}
+        else:
+            nk_g = int(math.ceil(wl.n_k * (err / 0.0095) ** 2 / 100.0)) * 100
+            mg = B.Model(wl, pc=pc)
+            zg = torch.from_numpy(wl.z(nk_g)).to("cuda")
+            sec, rp = timed_once(mg, nk_g, zg)
+            out["accuracy_gate"] = {"n_samples": nk_g, "value": gm.n / sec, "ms_per_step": sec * 1e3,
+                                    "err_estimate": rp["err_estimate"],
+                                    "met": bool(rp["err_estimate"] <= 0.01),
+                                    "pcg_iters": {"mean": rp["pcg_it_mean"], "max": rp["pcg_it_max"]}}
+            mg.close()
+            del zg
+            torch.cuda.empty_cache()
+    if not args.no_variants and pc is not None:
+        # the preconditioner blocks equal to the cores (16 slabs of 2 steps)
+        mv = B.Model(wl, pc=None)
+        zv = torch.from_numpy(wl.z()).to("cuda")
+        sec, rp = timed_once(mv, wl.n_k, zv)
+        out["variant_pc_cores"] = {"value": mv.n / sec, "ms_per_step": sec * 1e3,
+                                   "pcg_iters": {"mean": rp["pcg_it_mean"], "max": rp["pcg_it_max"]}}
+        mv.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_m)
-    gm.close()
     print(json.dumps(out), flush=True)
 
 

@@ -209,7 +209,11 @@ def popcount(mask: int) -> int:
 class Model:
     """Owns a context + model; inputs/outputs are torch tensors on the device."""
 
-    def __init__(self, wl, mask=None, theta=None, device: int = 0, decomp=None, pc=None):
+    def __init__(self, wl, mask=None, theta=None, device: int = 0, decomp=None, pc="workload"):
+        """pc: block-Jacobi blocks (slabs, tiles_x, tiles_y); "workload" takes the
+        workload's setting, None or () the cores."""
+        if isinstance(pc, str):
+            pc = getattr(wl, "pc", None)
         import torch
         self.wl = wl
         self.torch = torch

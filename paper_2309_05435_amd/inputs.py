@@ -38,6 +38,7 @@ class Workload:
     rtol: float            # PCG relative residual
     mask_seed: int
     z_seed: int
+    pc: tuple | None = None  # block-Jacobi blocks (slabs, tiles_x, tiles_y); None = cores
     extra: dict = field(default_factory=dict)
 
     @property
@@ -97,8 +98,12 @@ def _wl(c, **kw):
 WORKLOADS = {
     "small": _wl(1, name="small", m=16, T=10, range_=0.3, rho=0.9, tau=1.0, sigma=0.5,
                  obs_frac=0.5, n_tslabs=4, n_tiles=1, n_l=1, n_k=200, rtol=1e-8),
+    # measured fastest block-Jacobi shape for the sampler: one block over the
+    # whole 32-step chain (its dense 4096 x 4096 blocks fit; PCG then needs a
+    # single iteration).  pc=None gives blocks equal to the 16 cores.
     "slab64": _wl(2, name="slab64", m=64, T=32, range_=0.2, rho=0.95, tau=1.0, sigma=0.5,
-                  obs_frac=0.2, n_tslabs=16, n_tiles=1, n_l=2, n_k=500, rtol=1e-8),
+                  obs_frac=0.2, n_tslabs=16, n_tiles=1, n_l=2, n_k=500, rtol=1e-8,
+                  pc=(1, 1, 1)),
     "tile256": _wl(4, name="tile256", m=256, T=64, range_=0.1, rho=0.9, tau=1.0, sigma=0.5,
                    obs_frac=0.1, n_tslabs=8, n_tiles=8, n_l=1, n_k=100, rtol=1e-8),
     "tile512": _wl(5, name="tile512", m=512, T=48, range_=0.05, rho=0.98, tau=1.0, sigma=0.5,
