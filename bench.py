@@ -68,6 +68,58 @@ def cpu_baseline(wl, m_sample: int):
                        f"(n={sub.n}, {sub.n_k} samples), {dt:.1f} s")}
 
 
+def batched_leg(n_models: int):
+    """The uneven-model workload (grids 16^2-48^2, T 8-24, 2-8 slabs, 1-step
+    overlap, 100 samples): all models in one rbmc_estimate_batched call against
+    the same models estimated one call each.  Each timing follows a warm-up."""
+    import torch
+
+    from paper_2309_05435_amd import binding as B
+    from paper_2309_05435_amd.inputs import batched_models
+
+    wls = batched_models(n_models)
+    ms = B.ModelSet(wls)
+    zs = [torch.from_numpy(wl.z()).to("cuda") for wl in wls]
+    n_tot = sum(ms.n)
+    res = {"workload": f"{n_models} uneven models, sum n = {n_tot}", "n_models": n_models,
+           "n_samples": wls[0].n_k}
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, r
+
+    def reset_theta():
+        for m, wl in zip(ms.models, wls):
+            B.rbmc_model_set_theta(m, *wl.theta)
+
+    def run_batched():
+        reset_theta()
+        return ms.estimate(zs, rtol=wls[0].rtol)
+
+    def run_each():
+        reset_theta()
+        return ms.estimate_each(zs, rtol=wls[0].rtol)
+
+    sec_b, (db, tb, st, rep) = timed(run_batched)
+    sec_e, (de, te, sts, reps) = timed(run_each)
+    dev = max(float(((a - b).abs() / b.abs()).max()) for a, b in zip(db, de))
+    res.update({"value": n_tot / sec_b, "unit": "entries/s", "ms_per_step": sec_b * 1e3,
+                "per_model_calls": {"value": n_tot / sec_e, "ms_per_step": sec_e * 1e3},
+                "speedup": sec_e / sec_b, "max_rel_diff_vs_per_model": dev,
+                "err_estimate": rep.err_estimate, "pcg_iters_max": rep.pcg_it_max,
+                "phase_s": {k: getattr(rep, k) for k in ("t_sample", "t_factor", "t_takahashi",
+                                                         "t_correct", "t_total")},
+                "device_bytes": rep.peak_bytes})
+    ms.close()
+    del zs
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +135,9 @@ def main():
                     help="skip the run at the sample count that reaches <= 1%% error")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the run with block-Jacobi blocks equal to the cores")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 256-model batched workload")
+    ap.add_argument("--batched-models", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -218,6 +273,8 @@ def main():
         out["variant_pc_cores"] = {"value": mv.n / sec, "ms_per_step": sec * 1e3,
                                    "pcg_iters": {"mean": rp["pcg_it_mean"], "max": rp["pcg_it_max"]}}
         mv.close()
+    if not args.no_batched:
+        out["batched"] = batched_leg(args.batched_models)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_m)
     print(json.dumps(out), flush=True)

@@ -90,7 +90,8 @@ enum { RBMC_PC_BJ = 0, RBMC_PC_BJ_LEARNED = 1 };
 enum { RBMC_GRAD_LOGKAPPA = 1, RBMC_GRAD_LOGTAU = 2, RBMC_GRAD_RHO = 4, RBMC_GRAD_LOGSIGMA = 8 };
 
 typedef struct {
-  int32_t n_samples;  /* n_k >= 0 (0: deterministic part only) */
+  int32_t n_samples;  /* n_k >= 0 (0: deterministic part only); calls that sample
+                         take at most 65535 columns (n_models x n_k when batched) */
   int32_t pcg_maxit;  /* > 0 */
   double pcg_rtol;    /* per-sample ||b - Q x||_2 / ||b||_2 target, > 0 */
   int32_t precision;  /* RBMC_FP64 | RBMC_MIXED */
@@ -129,7 +130,7 @@ rbmc_status rbmc_model_set_theta(rbmc_model* m, double log_kappa, double log_tau
 /* Operators for y = Op x (device x, y; n_rhs columns):
  *   RBMC_OP_Q: Q (n -> n); RBMC_OP_F: the perturbation map F with F F^T = Q,
  *   input [z1 (n) ; z2 (n_obs, ascending observed index)] (n + n_obs -> n);
- *   RBMC_OP_DQ_*: dQ/dtheta_j (n -> n). */
+ *   RBMC_OP_DQ_*: dQ/dtheta_j (n -> n).  n_rhs <= 65535. */
 enum {
   RBMC_OP_Q = 0,
   RBMC_OP_DQ_LOGKAPPA = 1,
@@ -164,6 +165,24 @@ rbmc_status rbmc_estimate_from_samples(rbmc_model* m, const rbmc_est_opts* opts,
  * reserved).  Workspace for x is held by the model. */
 rbmc_status rbmc_estimate(rbmc_model* m, const rbmc_est_opts* opts, const double* z, uint64_t seed,
                           double* diag_out, double* trace_out, rbmc_report* rep);
+
+/* rbmc_estimate for n_models independent models of one context at once
+ * (the estimator of Alg. 3/4 applied to each model; models may differ in
+ * grid, time length, decomposition and theta).  Every kernel launch covers
+ * the chains and sample columns of all models, so many small problems fill
+ * the device together.  Results equal n_models separate rbmc_estimate calls
+ * up to floating-point summation order of the sampler's dot products
+ * (they are per column, so in practice identical).
+ * z[j]: device (n_j + n_obs_j) x n_samples; diag_out[j]: device, n_j;
+ * trace_out[j]: host, popcount(grad_mask) (the array may be NULL if
+ * grad_mask = 0).  The report aggregates all models (timings, the largest
+ * PCG iteration count and residual, the node-averaged error estimate).
+ * Errors: RBMC_E_ARG for NULL entries, a model listed twice, or models of
+ * another context. */
+rbmc_status rbmc_estimate_batched(rbmc_ctx* ctx, int32_t n_models, rbmc_model* const* models,
+                                  const rbmc_est_opts* opts, const double* const* z,
+                                  double* const* diag_out, double* const* trace_out,
+                                  rbmc_report* rep);
 
 /* Planner query, host only (no device needed): core label of every node
  * (label_out, length n) and, for core p, the node state (state_out, length

@@ -23,8 +23,8 @@ RBMC_GRAD_LOGKAPPA, RBMC_GRAD_LOGTAU, RBMC_GRAD_RHO, RBMC_GRAD_LOGSIGMA = 1, 2, 
 # every symbol include/rbmc.h declares
 EXPORTS = ["rbmc_ctx_create", "rbmc_ctx_destroy", "rbmc_model_create", "rbmc_model_destroy",
            "rbmc_model_set_theta", "rbmc_apply_op", "rbmc_sample", "rbmc_estimate_from_samples",
-           "rbmc_estimate", "rbmc_plan_query", "rbmc_ctx_profile", "rbmc_ctx_profile_read",
-           "rbmc_last_error"]
+           "rbmc_estimate", "rbmc_estimate_batched", "rbmc_plan_query", "rbmc_ctx_profile",
+           "rbmc_ctx_profile_read", "rbmc_last_error"]
 (RBMC_KF_GEMM, RBMC_KF_SPD_INVERSE, RBMC_KF_SPMM, RBMC_KF_RSTENCIL, RBMC_KF_PANELS,
  RBMC_KF_COUNT) = range(6)
 KF_NAMES = ["gemm", "spd_inverse", "spmm", "rstencil", "panels"]
@@ -89,6 +89,10 @@ def lib():
                                                  C.POINTER(C.c_double), C.POINTER(rbmc_report)]
         L.rbmc_estimate.argtypes = [vp, C.POINTER(rbmc_est_opts), vp, C.c_uint64, vp,
                                     C.POINTER(C.c_double), C.POINTER(rbmc_report)]
+        L.rbmc_estimate_batched.argtypes = [vp, C.c_int32, C.POINTER(vp),
+                                            C.POINTER(rbmc_est_opts), C.POINTER(vp),
+                                            C.POINTER(vp), C.POINTER(C.POINTER(C.c_double)),
+                                            C.POINTER(rbmc_report)]
         L.rbmc_plan_query.argtypes = [C.POINTER(rbmc_model_desc), C.POINTER(rbmc_decomp_desc),
                                       C.c_int32, vp, vp]
         L.rbmc_ctx_profile.argtypes = [vp, C.c_int]
@@ -167,6 +171,22 @@ def rbmc_estimate(m, opts, z, seed, diag_out, n_trace):
     st = check(lib().rbmc_estimate(m, C.byref(opts), _ptr(z), seed, _ptr(diag_out),
                                    tr if n_trace else None, C.byref(rep)))
     return st, list(tr)[:n_trace], rep
+
+
+def rbmc_estimate_batched(ctx, models, opts, zs, diag_outs, n_trace):
+    """models: model handles of one context; zs, diag_outs: device tensors per model."""
+    nm = len(models)
+    vp = C.c_void_p
+    mh = (vp * max(nm, 1))(*[m.value for m in models])
+    zp = (vp * max(nm, 1))(*[None if z is None else z.data_ptr() for z in zs])
+    dp = (vp * max(nm, 1))(*[d.data_ptr() for d in diag_outs])
+    trs = [(C.c_double * max(n_trace, 1))() for _ in range(nm)]
+    tp = (C.POINTER(C.c_double) * max(nm, 1))(
+        *[C.cast(t, C.POINTER(C.c_double)) for t in trs])
+    rep = rbmc_report()
+    st = check(lib().rbmc_estimate_batched(ctx, nm, mh, C.byref(opts), zp, dp,
+                                           tp if n_trace else None, C.byref(rep)))
+    return st, [list(t)[:n_trace] for t in trs], rep
 
 
 def rbmc_plan_query(desc, decomp, p, label_out=None, state_out=None):
@@ -268,3 +288,59 @@ class Model:
         st, tr, rep = rbmc_estimate(self.m, make_opts(z.shape[0], maxit, rtol, grad_mask),
                                     z.contiguous(), 0, diag, popcount(grad_mask))
         return diag, tr, st, rep
+
+
+class ModelSet:
+    """Many models in one context, estimated together by rbmc_estimate_batched
+    (or one by one with rbmc_estimate, for comparison)."""
+
+    def __init__(self, wls, device: int = 0, pc="workload"):
+        import torch
+        self.torch = torch
+        self.wls = list(wls)
+        self.dev = torch.device("cuda", device)
+        stream = torch.cuda.current_stream(self.dev).cuda_stream
+        self.ctx = rbmc_ctx_create(device, C.c_void_p(stream))
+        self.models, self._keep, self.n, self.n_obs = [], [], [], []
+        for wl in self.wls:
+            p = getattr(wl, "pc", None) if isinstance(pc, str) else pc
+            desc, mask = make_desc(wl.m, wl.m, wl.T, wl.h, wl.theta, wl.mask())
+            dc = rbmc_decomp_desc(*((wl.n_tslabs, wl.n_tiles, wl.n_tiles, wl.n_l) +
+                                    (tuple(p) if p else ())))
+            self.models.append(rbmc_model_create(self.ctx, desc, dc))
+            self._keep.append((desc, mask, dc))
+            self.n.append(wl.m * wl.m * wl.T)
+            self.n_obs.append(int(mask.sum()))
+
+    def close(self):
+        for m in getattr(self, "models", []):
+            rbmc_model_destroy(m)
+        self.models = []
+        if getattr(self, "ctx", None):
+            rbmc_ctx_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        self.close()
+
+    def _diags(self):
+        return [self.torch.empty(n, dtype=self.torch.float64, device=self.dev) for n in self.n]
+
+    def estimate(self, zs, grad_mask=0b111, rtol=1e-8, maxit=5000):
+        """zs: per model (n_k, n + n_obs) device tensors (same n_k)."""
+        zs = [z.contiguous() for z in zs]
+        diags = self._diags()
+        st, trs, rep = rbmc_estimate_batched(
+            self.ctx, self.models, make_opts(zs[0].shape[0], maxit, rtol, grad_mask), zs, diags,
+            popcount(grad_mask))
+        return diags, trs, st, rep
+
+    def estimate_each(self, zs, grad_mask=0b111, rtol=1e-8, maxit=5000):
+        diags, trs, sts, reps = self._diags(), [], [], []
+        for m, z, d in zip(self.models, zs, diags):
+            st, tr, rep = rbmc_estimate(m, make_opts(z.shape[0], maxit, rtol, grad_mask),
+                                        z.contiguous(), 0, d, popcount(grad_mask))
+            trs.append(tr)
+            sts.append(st)
+            reps.append(rep)
+        return diags, trs, sts, reps

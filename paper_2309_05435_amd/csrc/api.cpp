@@ -1,14 +1,18 @@
 // C ABI of the RBMC library and the host-side runtime that sequences the
-// kernels: block-tridiagonal factorization of every chain (block-Jacobi cores
+// kernels: block-tridiagonal factorization of every chain (block-Jacobi blocks
 // and RBMC subdomains), the Takahashi sweep, the correction solves and the
 // preconditioned conjugate-gradient sampler.
 //
-// Every launch works on all chains at once (grouped task lists), so a step
-// of the recursion is one launch per kernel, not one per subdomain.
+// Everything runs on *sets* of models: one model for the single-model calls,
+// many uneven models for rbmc_estimate_batched.  Every launch covers all
+// chains (and all sample columns) of the set, so a step of a recursion is one
+// launch per kernel, not one per subdomain or per model.
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -31,56 +35,9 @@ static rbmc_status fail(rbmc_status st, const std::string& msg) {
                   std::string(#expr) + ": " + hipGetErrorString(e_));                      \
   } while (0)
 
-struct ProfRec {
-  int family;
-  hipEvent_t a, b;
-  double flops, bytes;
-};
-
-struct rbmc_ctx {
-  int device;
-  hipStream_t stream;
-  bool prof = false;
-  std::vector<ProfRec> recs;
-  std::vector<hipEvent_t> spare;
-
-  hipEvent_t ev() {
-    hipEvent_t e = nullptr;
-    if (!spare.empty()) {
-      e = spare.back();
-      spare.pop_back();
-    } else {
-      (void)hipEventCreate(&e);
-    }
-    return e;
-  }
-  // bracket a launch sequence of one kernel family
-  int begin(int family, double flops, double bytes) {
-    if (!prof) return -1;
-    ProfRec r{family, ev(), ev(), flops, bytes};
-    (void)hipEventRecord(r.a, stream);
-    recs.push_back(r);
-    return (int)recs.size() - 1;
-  }
-  void end(int id) {
-    if (id >= 0) (void)hipEventRecord(recs[id].b, stream);
-  }
-  void clear() {
-    for (ProfRec& r : recs) {
-      spare.push_back(r.a);
-      spare.push_back(r.b);
-    }
-    recs.clear();
-  }
-  ~rbmc_ctx() {
-    clear();
-    for (hipEvent_t e : spare) (void)hipEventDestroy(e);
-  }
-};
-
 namespace {
 
-// Device allocations owned by a model.
+// Device allocations with a byte count.
 struct Pool {
   std::vector<void*> ptrs;
   int64_t bytes = 0;
@@ -119,7 +76,7 @@ struct Arena {
     if (host.size() > cap) {
       if (dev) (void)hipFree(dev);
       dev = nullptr;
-      cap = std::max(host.size(), (size_t)1 << 20);
+      cap = std::max(host.size() * 5 / 4, (size_t)1 << 20);
       hipError_t e = hipMalloc(&dev, cap);
       if (e != hipSuccess) {
         cap = 0;
@@ -137,23 +94,123 @@ struct Arena {
   }
 };
 
-template <class T>
-struct Launch {  // a grouped launch: task offset, count, tiles
-  size_t off = 0;
-  int n = 0;
-  int tiles = 0;
+struct ProfRec {
+  int family;
+  hipEvent_t a, b;
+  double flops, bytes;
 };
 
+}  // namespace
+
+struct rbmc_ctx {
+  int device;
+  hipStream_t stream;         // the caller's stream: all results are ordered on it
+  hipStream_t side = nullptr; // library stream for work that overlaps the sampler
+  hipEvent_t join[4] = {nullptr, nullptr, nullptr, nullptr};
+  Arena arenaA, arenaB;       // task lists of work on the caller's / side stream
+  // concatenated sample-column workspace of the sampler (sized per call)
+  Pool ws;
+  size_t ws_len = 0, ws_zlen = 0;
+  int ws_cols = 0, ws_models = 0;
+  double *r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr, *x = nullptr, *zcat = nullptr;
+  double* scal = nullptr;      // 8 x columns
+  double* part = nullptr;      // column partial sums
+  size_t part_len = 0;
+  uint8_t* active = nullptr;
+  int* iters = nullptr;        // columns + 1
+  int64_t *d_off = nullptr, *d_in_off = nullptr;
+  int *d_len = nullptr, *d_model = nullptr;
+  DevModel* d_dms = nullptr;
+  double* epart = nullptr;     // estimator partial sums
+  size_t epart_len = 0;
+  Pool epool;
+  // instrumentation
+  bool prof = false;
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> spare;
+
+  hipEvent_t ev() {
+    hipEvent_t e = nullptr;
+    if (!spare.empty()) {
+      e = spare.back();
+      spare.pop_back();
+    } else {
+      (void)hipEventCreate(&e);
+    }
+    return e;
+  }
+  // bracket a launch sequence of one kernel family on stream s
+  int begin(int family, double flops, double bytes, hipStream_t s) {
+    if (!prof) return -1;
+    ProfRec r{family, ev(), ev(), flops, bytes};
+    (void)hipEventRecord(r.a, s);
+    recs.push_back(r);
+    return (int)recs.size() - 1;
+  }
+  void end(int id, hipStream_t s) {
+    if (id >= 0) (void)hipEventRecord(recs[id].b, s);
+  }
+  void clear() {
+    for (ProfRec& r : recs) {
+      spare.push_back(r.a);
+      spare.push_back(r.b);
+    }
+    recs.clear();
+  }
+  ~rbmc_ctx() {
+    clear();
+    for (hipEvent_t e : spare) (void)hipEventDestroy(e);
+    for (hipEvent_t e : join)
+      if (e) (void)hipEventDestroy(e);
+    if (side) (void)hipStreamDestroy(side);
+    ws.release();
+    epool.release();
+  }
+};
+
+namespace {
+
+// A set of block-tridiagonal chains with their dense blocks and workspaces.
+// For one model the owner of every chain is that model; a batched call
+// concatenates the sets of many models.
 struct ChainSet {
   std::vector<Chain> chains;
-  std::vector<int> np;             // padded block size per chain
-  std::vector<double*> S;          // T x np^2, S_t^-1 after factorization
-  std::vector<double*> tmp;        // np^2 (Schur / Takahashi temporaries)
-  std::vector<double*> sig, xb;    // np^2 (Takahashi Sigma and X), subdomains only
-  std::vector<double*> gjU, gjB;   // np x 256 Gauss-Jordan panels
-  std::vector<double*> gjP, gjPi;  // 256 x 256 outer pivot block, 64 x 64 inner pivot inverse
-  std::vector<double*> gjUi, gjBi; // 256 x 64 inner panels
+  std::vector<rbmc_model*> owner;
+  std::vector<int> np, nb;
+  std::vector<const RegionDev*> rg;  // device pointers
+  std::vector<int*> info;            // device flag per chain
+  std::vector<double*> S;            // T x np^2, S_t^-1 after factorization
+  std::vector<double*> tmp;          // np^2
+  std::vector<double*> sig, xb;      // np^2 (Takahashi Sigma and X), subdomains only
+  std::vector<double*> gjU, gjB;     // np x 256 Gauss-Jordan panels
+  std::vector<double*> gjP, gjPi;    // 256 x 256 outer pivot block, 64 x 64 inner pivot inverse
+  std::vector<double*> gjUi, gjBi;   // 256 x 64 inner panels
+  std::vector<std::vector<double*>> pan;  // per chain: T panels np x n_k
+  std::vector<double*> ytmp;              // per chain: one panel
   int maxT = 0;
+  void append(const ChainSet& o) {
+    auto cat = [](auto& a, const auto& b) { a.insert(a.end(), b.begin(), b.end()); };
+    cat(chains, o.chains);
+    cat(owner, o.owner);
+    cat(np, o.np);
+    cat(nb, o.nb);
+    cat(rg, o.rg);
+    cat(info, o.info);
+    cat(S, o.S);
+    cat(tmp, o.tmp);
+    cat(sig, o.sig);
+    cat(xb, o.xb);
+    cat(gjU, o.gjU);
+    cat(gjB, o.gjB);
+    cat(gjP, o.gjP);
+    cat(gjPi, o.gjPi);
+    cat(gjUi, o.gjUi);
+    cat(gjBi, o.gjBi);
+    cat(pan, o.pan);
+    cat(ytmp, o.ytmp);
+    maxT = std::max(maxT, o.maxT);
+  }
+  size_t size() const { return chains.size(); }
 };
 
 }  // namespace
@@ -167,29 +224,18 @@ struct rbmc_model {
   Coefs co;
   int n_obs = 0;
   Pool pool;      // model-lifetime allocations
-  Pool work;      // sample-count dependent workspace
+  Pool work;      // panels (sample-count dependent)
   int work_nk = -1;
   DevModel dm{};
+  DevModel* d_dm = nullptr;
   double *d_qs = nullptr, *d_kk = nullptr, *d_fs = nullptr, *d_qd = nullptr, *d_dqd = nullptr,
          *d_ld = nullptr, *d_dvec = nullptr;
   int* d_obs_rank = nullptr;
   std::vector<RegionDev> regions;
   RegionDev* d_regions = nullptr;
-  uint8_t** d_inbox = nullptr;
   ChainSet bj, sub;
   int* d_info = nullptr;  // one per chain: bj then sub
   bool bj_ready = false, sub_ready = false;
-  // workspace (n_k dependent)
-  double *w_r = nullptr, *w_p = nullptr, *w_q = nullptr, *w_z = nullptr, *w_x = nullptr;
-  double* w_scal = nullptr;  // 8 x n_k per-column scalars
-  double* w_part = nullptr;  // partial sums
-  uint8_t* w_active = nullptr;
-  int* w_iters = nullptr;    // n_k + 1
-  std::vector<std::vector<double*>> bj_pan, sub_pan;  // per chain: T panels np x n_k
-  std::vector<double*> bj_y, sub_y;                  // per chain temp panel
-  double* w_diag_part = nullptr;
-  size_t diag_part_len = 0;
-  Arena arena;
 };
 
 // ---------------------------------------------------------------------------
@@ -210,10 +256,11 @@ rbmc_status upload_coefs(rbmc_model* m) {
   std::vector<double> dv(P.n);
   for (int i = 0; i < P.n; ++i) dv[i] = m->mask[i] ? c.dobs : 0.0;
   HIPCHK(hipMemcpyAsync(m->d_dvec, dv.data(), dv.size() * 8, hipMemcpyHostToDevice, s));
-  HIPCHK(hipStreamSynchronize(s));
   m->dm.qo = c.qo;
   m->dm.dqo = c.dqo;
   m->dm.lo = c.lo;
+  HIPCHK(hipMemcpyAsync(m->d_dm, &m->dm, sizeof(DevModel), hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
   m->bj_ready = m->sub_ready = false;
   return RBMC_OK;
 }
@@ -224,12 +271,18 @@ bool theta_ok(double lk, double lt, double rho, double ls) {
 }
 
 rbmc_status alloc_chainset(rbmc_model* m, ChainSet& cs, const std::vector<Chain>& chains,
-                           bool subdomains) {
-  cs.chains = chains;
-  cs.maxT = 0;
-  for (const Chain& c : chains) {
-    const int np = pad_to(m->plan.regions[c.region].nb());
+                           bool subdomains, int info_base) {
+  cs = ChainSet();
+  for (size_t i = 0; i < chains.size(); ++i) {
+    const Chain& c = chains[i];
+    const int nb = m->plan.regions[c.region].nb();
+    const int np = pad_to(nb);
+    cs.chains.push_back(c);
+    cs.owner.push_back(m);
     cs.np.push_back(np);
+    cs.nb.push_back(nb);
+    cs.rg.push_back(m->d_regions + c.region);
+    cs.info.push_back(m->d_info + info_base + (int)i);
     const size_t blk = (size_t)np * np;
     double* p = nullptr;
     HIPCHK(m->pool.alloc((void**)&p, blk * c.T * 8));
@@ -241,6 +294,9 @@ rbmc_status alloc_chainset(rbmc_model* m, ChainSet& cs, const std::vector<Chain>
       cs.sig.push_back(p);
       HIPCHK(m->pool.alloc((void**)&p, blk * 8));
       cs.xb.push_back(p);
+    } else {
+      cs.sig.push_back(nullptr);
+      cs.xb.push_back(nullptr);
     }
     HIPCHK(m->pool.alloc((void**)&p, (size_t)np * 256 * 8));
     cs.gjU.push_back(p);
@@ -254,55 +310,37 @@ rbmc_status alloc_chainset(rbmc_model* m, ChainSet& cs, const std::vector<Chain>
     cs.gjUi.push_back(p);
     HIPCHK(m->pool.alloc((void**)&p, (size_t)256 * 64 * 8));
     cs.gjBi.push_back(p);
+    cs.pan.push_back({});
+    cs.ytmp.push_back(nullptr);
     cs.maxT = std::max(cs.maxT, c.T);
   }
   return RBMC_OK;
 }
 
-rbmc_status ensure_work(rbmc_model* m, int n_k) {
-  if (m->work_nk >= n_k && m->work_nk >= 1) return RBMC_OK;
+// correction / preconditioner panels of a model for n_k samples
+rbmc_status ensure_panels(rbmc_model* m, int n_k) {
+  const int nk = std::max(n_k, 1);
+  if (m->work_nk >= nk) return RBMC_OK;
   m->work.release();
   m->work_nk = -1;
-  m->w_diag_part = nullptr;
-  m->diag_part_len = 0;
-  const int nk = std::max(n_k, 1);
-  const size_t vec = (size_t)m->plan.n * nk * 8;
-  HIPCHK(m->work.alloc((void**)&m->w_r, vec));
-  HIPCHK(m->work.alloc((void**)&m->w_p, vec));
-  HIPCHK(m->work.alloc((void**)&m->w_q, vec));
-  HIPCHK(m->work.alloc((void**)&m->w_z, vec));
-  HIPCHK(m->work.alloc((void**)&m->w_x, vec));
-  HIPCHK(m->work.alloc((void**)&m->w_scal, (size_t)8 * nk * 8));
-  const int nch = std::max(spmm_chunks(m->dm), dot_chunks(m->plan.n));
-  HIPCHK(m->work.alloc((void**)&m->w_part, (size_t)nch * nk * 8));
-  HIPCHK(m->work.alloc((void**)&m->w_active, (size_t)nk));
-  HIPCHK(m->work.alloc((void**)&m->w_iters, (size_t)(nk + 1) * 4));
-  auto panels = [&](ChainSet& cs, std::vector<std::vector<double*>>& pan,
-                    std::vector<double*>& ytmp) -> rbmc_status {
-    pan.assign(cs.chains.size(), {});
-    ytmp.assign(cs.chains.size(), nullptr);
-    for (size_t c = 0; c < cs.chains.size(); ++c) {
-      const size_t psz = (size_t)cs.np[c] * nk * 8;
-      for (int t = 0; t < cs.chains[c].T; ++t) {
+  for (ChainSet* cs : {&m->bj, &m->sub})
+    for (size_t c = 0; c < cs->size(); ++c) {
+      const size_t psz = (size_t)cs->np[c] * nk * 8;
+      cs->pan[c].clear();
+      for (int t = 0; t < cs->chains[c].T; ++t) {
         double* p = nullptr;
         HIPCHK(m->work.alloc((void**)&p, psz));
-        pan[c].push_back(p);
+        cs->pan[c].push_back(p);
       }
-      HIPCHK(m->work.alloc((void**)&ytmp[c], psz));
+      HIPCHK(m->work.alloc((void**)&cs->ytmp[c], psz));
     }
-    return RBMC_OK;
-  };
-  rbmc_status st = panels(m->bj, m->bj_pan, m->bj_y);
-  if (st != RBMC_OK) return st;
-  st = panels(m->sub, m->sub_pan, m->sub_y);
-  if (st != RBMC_OK) return st;
   m->work_nk = nk;
   return RBMC_OK;
 }
 
 // ---- task builders ----------------------------------------------------------
 
-int gemm_tiles(int M, int N) { return ((M + 127) / 128) * ((N + 127) / 128); }
+int gemm_tiles(int M, int N) { return gemm_task_tiles(M, N, 0); }
 
 struct GemmList {
   std::vector<GemmTask> v;
@@ -377,7 +415,8 @@ struct StencilList {
     t.tile_start = tiles;
     tiles += (np / 64) * ((t.ncols + 63) / 64);
     bytes += 16.0 * nb * (double)t.ncols;
-    if (t.gamma != 0.0 || t.dv != nullptr || t.pad_identity) max_sparse_np = std::max(max_sparse_np, np);
+    if (t.gamma != 0.0 || t.dv != nullptr || t.pad_identity)
+      max_sparse_np = std::max(max_sparse_np, np);
     v.push_back(t);
   }
 };
@@ -395,7 +434,6 @@ struct TileList {
   }
 };
 
-// Recorded program: a sequence of grouped launches over the arena.
 struct InvJob {  // one SPD block to invert in place, with its workspace
   double* M;
   int np, nb;
@@ -405,19 +443,14 @@ struct InvJob {  // one SPD block to invert in place, with its workspace
 
 struct Op {
   // 0 gemm, 1 stencil, 2 sweep step (rank 64), 3 panels, 4 extract, 5 mc, 6 copy,
-  // 7 outer gather, 8 outer fix, 9 sweep finish, 10 profile begin, 11 profile end
+  // 7 outer gather, 8 outer fix, 9 sweep finish, 10 profile begin, 11 profile end, 12 mirror
   int kind;
-  size_t off;
-  int n, tiles;
+  size_t off = 0;
+  int n = 0, tiles = 0;
   int max_np = 0, kblk = 0;
-  const double* X = nullptr;
-  double* Xout = nullptr;
-  int n_k = 0;
-  // copy
   void* dst = nullptr;
   const void* src = nullptr;
   size_t bytes = 0;
-  // instrumentation: kernel family and algorithmic work of the launch
   int family = -1;
   double alg_flops = 0.0, alg_bytes = 0.0;
 };
@@ -433,7 +466,7 @@ struct Program {
     o.tiles = g.tiles;
     o.family = profiled ? RBMC_KF_GEMM : -1;
     o.alg_flops = g.flops;
-    ops.push_back(std::move(o));
+    ops.push_back(o);
   }
   void stencil(Arena& a, StencilList& s) {
     if (s.v.empty()) return;
@@ -445,7 +478,7 @@ struct Program {
     o.family = RBMC_KF_RSTENCIL;
     o.alg_bytes = s.bytes;
     o.max_np = s.max_sparse_np;
-    ops.push_back(std::move(o));
+    ops.push_back(o);
   }
   void mirror(Arena& a, const std::vector<InvTask>& t) {
     if (t.empty()) return;
@@ -454,7 +487,7 @@ struct Program {
     o.off = a.push(t);
     o.n = (int)t.size();
     for (const InvTask& it : t) o.max_np = std::max(o.max_np, it.np);
-    ops.push_back(std::move(o));
+    ops.push_back(o);
   }
   // rank-64 sweep of a list of blocks (all steps) followed by the finish pass
   void sweep64(Arena& a, const std::vector<InvTask>& t) {
@@ -469,13 +502,13 @@ struct Program {
       o.n = (int)t.size();
       o.max_np = max_np;
       o.kblk = k;
-      ops.push_back(std::move(o));
+      ops.push_back(o);
     }
     Op f;
     f.kind = 9;
     f.off = off;
     f.n = (int)t.size();
-    ops.push_back(std::move(f));
+    ops.push_back(f);
   }
   // In-place inversion of SPD blocks: blocks up to 256 by the rank-64 sweep;
   // larger ones by rank-256 outer sweeps (GEMM updates) whose 256 x 256 pivot
@@ -530,9 +563,7 @@ struct Program {
         t.Bp = j.Bi;
         t.Pi = j.Pi;
         inner.push_back(t);
-        // U = B P^-1
         gu.add(j.B, j.P, nullptr, j.U, j.np, w, w, j.np, w, j.np, 1.0, 0.0, 0, 0, j.np, w);
-        // M_lower -= U B^T outside the swept block row/column
         gm.add_sweep(j.M, j.np, j.U, j.B, w, kb);
       }
       Op og;
@@ -540,29 +571,26 @@ struct Program {
       og.off = a.push(gl.v);
       og.n = (int)gl.v.size();
       og.tiles = gl.tiles;
-      ops.push_back(std::move(og));
+      ops.push_back(og);
       sweep64(a, inner);
       gemm(a, gu, false);
       gemm(a, gm, false);
-      Op of;
+      Op of = og;
       of.kind = 8;
-      of.off = og.off;
-      of.n = og.n;
-      of.tiles = og.tiles;
-      ops.push_back(std::move(of));
+      ops.push_back(of);
     }
     if (!big.empty()) {
       Op f;
       f.kind = 9;
       f.off = a.push(big);
       f.n = (int)big.size();
-      ops.push_back(std::move(f));
+      ops.push_back(f);
     }
     Op pe;
     pe.kind = 11;
     ops.push_back(pe);
   }
-  void panels(Arena& a, TileList<PanelTask>& p, const double* X, double* Xout, int n_k) {
+  void panels(Arena& a, TileList<PanelTask>& p) {
     if (p.v.empty()) return;
     Op o;
     o.kind = 3;
@@ -571,10 +599,7 @@ struct Program {
     o.tiles = p.tiles;
     o.family = RBMC_KF_PANELS;
     o.alg_bytes = p.bytes;
-    o.X = X;
-    o.Xout = Xout;
-    o.n_k = n_k;
-    ops.push_back(std::move(o));
+    ops.push_back(o);
   }
   void extract(Arena& a, TileList<ExtractTask>& e) {
     if (e.v.empty()) return;
@@ -583,17 +608,16 @@ struct Program {
     o.off = a.push(e.v);
     o.n = (int)e.v.size();
     o.tiles = e.tiles;
-    ops.push_back(std::move(o));
+    ops.push_back(o);
   }
-  void mc(Arena& a, TileList<McTask>& e, int n_k) {
+  void mc(Arena& a, TileList<McTask>& e) {
     if (e.v.empty()) return;
     Op o;
     o.kind = 5;
     o.off = a.push(e.v);
     o.n = (int)e.v.size();
     o.tiles = e.tiles;
-    o.n_k = n_k;
-    ops.push_back(std::move(o));
+    ops.push_back(o);
   }
   void copy(void* dst, const void* src, size_t bytes) {
     Op o;
@@ -601,86 +625,73 @@ struct Program {
     o.dst = dst;
     o.src = src;
     o.bytes = bytes;
-    ops.push_back(std::move(o));
+    ops.push_back(o);
   }
 };
 
-struct RunCtx {
-  double* diag_out = nullptr;
-  double* partial = nullptr;
-  int nchunk_max = 0;
-};
-
-rbmc_status run(rbmc_model* m, const Program& pg, const RunCtx& rc) {
-  hipStream_t s = m->ctx->stream;
-  Arena& a = m->arena;
+rbmc_status run(rbmc_ctx* cx, const Program& pg, hipStream_t s, Arena& a) {
   std::vector<int> open_prof;  // records opened by profile-begin ops
   for (const Op& o : pg.ops) {
-    const int pid = (o.family >= 0) ? m->ctx->begin(o.family, o.alg_flops, o.alg_bytes) : -1;
+    const int pid = (o.family >= 0) ? cx->begin(o.family, o.alg_flops, o.alg_bytes, s) : -1;
     switch (o.kind) {
       case 0: launch_gemm(a.at<GemmTask>(o.off), o.n, o.tiles, s); break;
-      case 1:
-        launch_rstencil(a.at<StencilTask>(o.off), o.n, o.tiles, m->d_regions, m->d_qs,
-                        m->plan.ns, o.max_np, s);
-        break;
-      case 12: launch_mirror(a.at<InvTask>(o.off), o.n, o.max_np, s); break;
+      case 1: launch_rstencil(a.at<StencilTask>(o.off), o.n, o.tiles, o.max_np, s); break;
       case 2: launch_gj_step(a.at<InvTask>(o.off), o.n, o.max_np, o.kblk, s); break;
+      case 3: launch_panels(a.at<PanelTask>(o.off), o.n, o.tiles, s); break;
+      case 4: launch_extract(a.at<ExtractTask>(o.off), o.n, o.tiles, s); break;
+      case 5: launch_mc(a.at<McTask>(o.off), o.n, o.tiles, s); break;
+      case 6: HIPCHK(hipMemcpyAsync(o.dst, o.src, o.bytes, hipMemcpyDeviceToDevice, s)); break;
       case 7: launch_gj2_gather(a.at<Gj2Task>(o.off), o.n, o.tiles, s); break;
       case 8: launch_gj2_fix(a.at<Gj2Task>(o.off), o.n, o.tiles, s); break;
       case 9: launch_gj_finish(a.at<InvTask>(o.off), o.n, s); break;
       case 10: open_prof.push_back(pid); break;
       case 11:
         if (!open_prof.empty()) {
-          m->ctx->end(open_prof.back());
+          cx->end(open_prof.back(), s);
           open_prof.pop_back();
         }
         break;
-      case 3:
-        launch_panels(a.at<PanelTask>(o.off), o.n, o.tiles, m->d_regions, m->dm, o.X, o.Xout,
-                      o.n_k, s);
-        break;
-      case 4:
-        launch_extract(a.at<ExtractTask>(o.off), o.n, o.tiles, m->d_regions, m->d_inbox, m->dm,
-                       rc.diag_out, rc.partial, rc.nchunk_max, s);
-        break;
-      case 5:
-        launch_mc(a.at<McTask>(o.off), o.n, o.tiles, m->d_regions, m->d_inbox, m->dm, o.n_k,
-                  rc.diag_out, rc.partial, rc.nchunk_max, s);
-        break;
-      case 6: HIPCHK(hipMemcpyAsync(o.dst, o.src, o.bytes, hipMemcpyDeviceToDevice, s)); break;
+      case 12: launch_mirror(a.at<InvTask>(o.off), o.n, o.max_np, s); break;
     }
-    if (o.kind != 10) m->ctx->end(pid);
+    if (o.kind != 10) cx->end(pid, s);
   }
   HIPCHK(hipGetLastError());
   return RBMC_OK;
 }
 
+StencilTask stask(const ChainSet& cs, size_t c) {
+  StencilTask t{};
+  t.rg = cs.rg[c];
+  t.qs = cs.owner[c]->d_qs;
+  t.ns = cs.owner[c]->plan.ns;
+  return t;
+}
+
 // Factorization program: S_t^-1 of every chain of the set.
 //   S_0 = B_0,  S_t = B_t - q_o^2 Q_R S_{t-1}^-1 Q_R,  B_t = q_d(t) Q_R + D_t
-void build_factor(rbmc_model* m, ChainSet& cs, int info_base, Program& pg) {
-  Arena& a = m->arena;
+void build_factor(ChainSet& cs, Program& pg, Arena& a) {
   for (int t = 0; t < cs.maxT; ++t) {
     StencilList v1, v2;
     std::vector<InvJob> inv;
-    for (size_t c = 0; c < cs.chains.size(); ++c) {
+    for (size_t c = 0; c < cs.size(); ++c) {
       const Chain& ch = cs.chains[c];
       if (t >= ch.T) continue;
-      const int np = cs.np[c];
+      const rbmc_model* m = cs.owner[c];
+      const int np = cs.np[c], nb = cs.nb[c];
       const size_t blk = (size_t)np * np;
       const int tg = ch.t0 + t;
       double* St = cs.S[c] + blk * t;
       if (t > 0) {
-        StencilTask s1{};
+        StencilTask s1 = stask(cs, c);
         s1.M = cs.S[c] + blk * (t - 1);
         s1.ldm = np;
         s1.out = cs.tmp[c];
         s1.ldout = np;
         s1.ncols = np;
         s1.alpha = 1.0;
-        s1.region = ch.region;
-        v1.add(s1, np, m->regions[ch.region].nb);
+        v1.add(s1, np, nb);
       }
-      StencilTask s2{};
+      StencilTask s2 = stask(cs, c);
       s2.M = (t > 0) ? cs.tmp[c] : nullptr;
       s2.ldm = np;
       s2.trans = 1;
@@ -691,13 +702,12 @@ void build_factor(rbmc_model* m, ChainSet& cs, int info_base, Program& pg) {
       s2.out = St;
       s2.ldout = np;
       s2.ncols = np;
-      s2.region = ch.region;
-      v2.add(s2, np, m->regions[ch.region].nb);
+      v2.add(s2, np, nb);
       InvJob it{};
       it.M = St;
       it.np = np;
-      it.nb = m->regions[ch.region].nb;
-      it.info = m->d_info + info_base + (int)c;
+      it.nb = nb;
+      it.info = cs.info[c];
       it.B = cs.gjB[c];
       it.U = cs.gjU[c];
       it.P = cs.gjP[c];
@@ -715,35 +725,33 @@ void build_factor(rbmc_model* m, ChainSet& cs, int info_base, Program& pg) {
 // Block-tridiagonal solve with the chain factors, in place on the panels:
 // forward u_0 = S_0^-1 r_0, u_t = S_t^-1 (r_t - q_o Q_R u_{t-1});
 // backward z_t = u_t - S_t^-1 (q_o Q_R z_{t+1}) down to local step stop[c].
-// r_0 must be in ytmp[c], r_t (t >= 1) in pan[c][t].
-void build_solve(rbmc_model* m, ChainSet& cs, std::vector<std::vector<double*>>& pan,
-                 std::vector<double*>& ytmp, int n_k, const std::vector<int>& stop,
-                 Program& pg) {
-  Arena& a = m->arena;
-  const double qo = m->co.qo;
+// r_0 must be in ytmp[c], r_t (t >= 1) in pan[c][t].  S_t^-1 is symmetric, so
+// it is read through the transposed (contiguous) operand path.
+void build_solve(ChainSet& cs, int n_k, const std::vector<int>& stop, Program& pg, Arena& a) {
   for (int t = 0; t < cs.maxT; ++t) {
     StencilList sl;
     GemmList gl;
-    for (size_t c = 0; c < cs.chains.size(); ++c) {
+    for (size_t c = 0; c < cs.size(); ++c) {
       const Chain& ch = cs.chains[c];
       if (t >= ch.T) continue;
-      const int np = cs.np[c];
+      const double qo = cs.owner[c]->co.qo;
+      const int np = cs.np[c], nb = cs.nb[c];
       const size_t blk = (size_t)np * np;
       if (t > 0) {
-        StencilTask s{};
-        s.M = pan[c][t - 1];
+        StencilTask s = stask(cs, c);
+        s.M = cs.pan[c][t - 1];
         s.ldm = np;
-        s.In = pan[c][t];
+        s.In = cs.pan[c][t];
         s.ldin = np;
         s.beta = 1.0;
         s.alpha = -qo;
-        s.out = ytmp[c];
+        s.out = cs.ytmp[c];
         s.ldout = np;
         s.ncols = n_k;
-        s.region = ch.region;
-        sl.add(s, np, m->regions[ch.region].nb);
+        sl.add(s, np, nb);
       }
-      gl.add(cs.S[c] + blk * t, ytmp[c], nullptr, pan[c][t], np, n_k, np, np, np, np, 1.0, 0.0, 1, 0, m->regions[ch.region].nb, m->regions[ch.region].nb);
+      gl.add(cs.S[c] + blk * t, cs.ytmp[c], nullptr, cs.pan[c][t], np, n_k, np, np, np, np, 1.0,
+             0.0, 1, 0, nb, nb);
     }
     pg.stencil(a, sl);
     pg.gemm(a, gl);
@@ -751,56 +759,47 @@ void build_solve(rbmc_model* m, ChainSet& cs, std::vector<std::vector<double*>>&
   for (int t = cs.maxT - 2; t >= 0; --t) {
     StencilList sl;
     GemmList gl;
-    for (size_t c = 0; c < cs.chains.size(); ++c) {
+    for (size_t c = 0; c < cs.size(); ++c) {
       const Chain& ch = cs.chains[c];
       if (t > ch.T - 2 || t < stop[c]) continue;
-      const int np = cs.np[c];
+      const double qo = cs.owner[c]->co.qo;
+      const int np = cs.np[c], nb = cs.nb[c];
       const size_t blk = (size_t)np * np;
-      StencilTask s{};
-      s.M = pan[c][t + 1];
+      StencilTask s = stask(cs, c);
+      s.M = cs.pan[c][t + 1];
       s.ldm = np;
       s.alpha = qo;
-      s.out = ytmp[c];
+      s.out = cs.ytmp[c];
       s.ldout = np;
       s.ncols = n_k;
-      s.region = ch.region;
-      sl.add(s, np, m->regions[ch.region].nb);
-      gl.add(cs.S[c] + blk * t, ytmp[c], pan[c][t], pan[c][t], np, n_k, np, np, np, np, -1.0,
-             1.0, 1, 0, m->regions[ch.region].nb, m->regions[ch.region].nb);
+      sl.add(s, np, nb);
+      gl.add(cs.S[c] + blk * t, cs.ytmp[c], cs.pan[c][t], cs.pan[c][t], np, n_k, np, np, np, np,
+             -1.0, 1.0, 1, 0, nb, nb);
     }
     pg.stencil(a, sl);
     pg.gemm(a, gl);
   }
 }
 
-rbmc_status check_info(rbmc_model* m, int base, int count, rbmc_report* rep, const char* what) {
-  std::vector<int> info(count);
-  if (count == 0) return RBMC_OK;
-  HIPCHK(hipMemcpy(info.data(), m->d_info + base, count * 4, hipMemcpyDeviceToHost));
-  for (int c = 0; c < count; ++c)
-    if (info[c] != 0) {
+rbmc_status check_info(const ChainSet& cs, rbmc_report* rep, const char* what) {
+  for (size_t c = 0; c < cs.size(); ++c) {
+    int v = 0;
+    HIPCHK(hipMemcpy(&v, cs.info[c], 4, hipMemcpyDeviceToHost));
+    if (v != 0) {
       if (rep) {
-        rep->fail_subdomain = c;
-        rep->fail_block = info[c] - 1;
+        rep->fail_subdomain = (int)c;
+        rep->fail_block = v - 1;
       }
       return fail(RBMC_E_NOT_SPD, std::string(what) + " chain " + std::to_string(c) +
                                       " lost positive definiteness");
     }
+  }
   return RBMC_OK;
 }
 
-rbmc_status factor_set(rbmc_model* m, ChainSet& cs, int info_base, rbmc_report* rep,
-                       const char* what) {
-  hipStream_t s = m->ctx->stream;
-  HIPCHK(hipMemsetAsync(m->d_info + info_base, 0, cs.chains.size() * 4, s));
-  m->arena.clear();
-  Program pg;
-  build_factor(m, cs, info_base, pg);
-  HIPCHK(m->arena.upload(s));
-  rbmc_status st = run(m, pg, RunCtx{});
-  if (st != RBMC_OK) return st;
-  HIPCHK(hipStreamSynchronize(s));
-  return check_info(m, info_base, (int)cs.chains.size(), rep, what);
+rbmc_status zero_info(const ChainSet& cs, hipStream_t s) {
+  for (size_t c = 0; c < cs.size(); ++c) HIPCHK(hipMemsetAsync(cs.info[c], 0, 4, s));
+  return RBMC_OK;
 }
 
 double now_s() {
@@ -826,6 +825,627 @@ rbmc_status check_opts(const rbmc_est_opts* o, bool need_pcg) {
   return RBMC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Column sets of the sampler: columns (model j, sample k), model-major.
+// Column (j, k) of a multi-vector starts at base_j + k n_j with base_j the
+// sum of n_i n_k over earlier models; the F input column at
+// zbase_j + k (n_j + n_obs_j).
+// ---------------------------------------------------------------------------
+struct HostCols {
+  std::vector<int64_t> off, in_off;
+  std::vector<int> len, model;
+  std::vector<size_t> base, zbase;  // per model
+  size_t total = 0, ztotal = 0;
+  int max_len = 0, max_tiles = 0;
+};
+
+// kernels over columns put the column index in grid.y
+constexpr int64_t kMaxCols = 65535;
+
+bool cols_fit(size_t n_models, int nk) { return (int64_t)n_models * nk <= kMaxCols; }
+
+HostCols make_cols(const std::vector<rbmc_model*>& ms, int nk) {
+  HostCols h;
+  for (size_t j = 0; j < ms.size(); ++j) {
+    const rbmc_model* m = ms[j];
+    h.base.push_back(h.total);
+    h.zbase.push_back(h.ztotal);
+    for (int k = 0; k < nk; ++k) {
+      h.off.push_back((int64_t)(h.total + (size_t)k * m->plan.n));
+      h.in_off.push_back((int64_t)(h.ztotal + (size_t)k * (m->plan.n + m->n_obs)));
+      h.len.push_back(m->plan.n);
+      h.model.push_back((int)j);
+    }
+    h.total += (size_t)m->plan.n * nk;
+    h.ztotal += (size_t)(m->plan.n + m->n_obs) * nk;
+    h.max_len = std::max(h.max_len, m->plan.n);
+    h.max_tiles = std::max(h.max_tiles, stencil_tiles(m->plan.mx, m->plan.my));
+  }
+  return h;
+}
+
+// Sampler workspace of the context for a column set (grown on demand).
+rbmc_status ensure_ws(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const HostCols& h,
+                      bool need_zcat) {
+  const int ncols = (int)h.len.size();
+  const size_t part = (size_t)std::max(1, ncols) *
+                      (size_t)std::max(h.max_tiles, dot_chunks(std::max(h.max_len, 1)));
+  const bool fits = cx->ws_len >= h.total && cx->ws_cols >= ncols && cx->part_len >= part &&
+                    cx->ws_models >= (int)ms.size() && (!need_zcat || cx->ws_zlen >= h.ztotal);
+  if (!fits) {
+    cx->ws.release();
+    cx->ws_len = cx->ws_zlen = 0;
+    cx->ws_cols = cx->ws_models = 0;
+    cx->zcat = nullptr;
+    const size_t len = std::max<size_t>(h.total, 1);
+    HIPCHK(cx->ws.alloc((void**)&cx->r, len * 8));
+    HIPCHK(cx->ws.alloc((void**)&cx->p, len * 8));
+    HIPCHK(cx->ws.alloc((void**)&cx->q, len * 8));
+    HIPCHK(cx->ws.alloc((void**)&cx->z, len * 8));
+    HIPCHK(cx->ws.alloc((void**)&cx->x, len * 8));
+    if (need_zcat) {
+      HIPCHK(cx->ws.alloc((void**)&cx->zcat, std::max<size_t>(h.ztotal, 1) * 8));
+      cx->ws_zlen = h.ztotal;
+    }
+    const int nc = std::max(ncols, 1);
+    HIPCHK(cx->ws.alloc((void**)&cx->scal, (size_t)8 * nc * 8));
+    HIPCHK(cx->ws.alloc((void**)&cx->part, part * 8));
+    HIPCHK(cx->ws.alloc((void**)&cx->active, (size_t)nc));
+    HIPCHK(cx->ws.alloc((void**)&cx->iters, (size_t)(nc + 1) * 4));
+    HIPCHK(cx->ws.alloc((void**)&cx->d_off, (size_t)nc * 8));
+    HIPCHK(cx->ws.alloc((void**)&cx->d_in_off, (size_t)nc * 8));
+    HIPCHK(cx->ws.alloc((void**)&cx->d_len, (size_t)nc * 4));
+    HIPCHK(cx->ws.alloc((void**)&cx->d_model, (size_t)nc * 4));
+    HIPCHK(cx->ws.alloc((void**)&cx->d_dms, std::max<size_t>(ms.size(), 1) * sizeof(DevModel)));
+    cx->ws_len = h.total;
+    cx->ws_cols = ncols;
+    cx->part_len = part;
+    cx->ws_models = (int)ms.size();
+  }
+  hipStream_t s = cx->stream;
+  const int nc = ncols;
+  if (nc > 0) {
+    HIPCHK(hipMemcpyAsync(cx->d_off, h.off.data(), (size_t)nc * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(cx->d_in_off, h.in_off.data(), (size_t)nc * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(cx->d_len, h.len.data(), (size_t)nc * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(cx->d_model, h.model.data(), (size_t)nc * 4, hipMemcpyHostToDevice, s));
+  }
+  std::vector<DevModel> dms;
+  for (rbmc_model* m : ms) dms.push_back(m->dm);
+  if (!dms.empty())
+    HIPCHK(hipMemcpyAsync(cx->d_dms, dms.data(), dms.size() * sizeof(DevModel),
+                          hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return RBMC_OK;
+}
+
+ColSet colset(rbmc_ctx* cx, const HostCols& h) {
+  ColSet c{};
+  c.ncols = (int)h.len.size();
+  c.max_len = h.max_len;
+  c.max_tiles = h.max_tiles;
+  c.off = cx->d_off;
+  c.in_off = cx->d_in_off;
+  c.len = cx->d_len;
+  c.model = cx->d_model;
+  c.dms = cx->d_dms;
+  return c;
+}
+
+// Factor the block-Jacobi chains of every model that needs it (one program).
+rbmc_status factor_bj(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, rbmc_report* rep) {
+  ChainSet cs;
+  for (rbmc_model* m : ms)
+    if (!m->bj_ready) cs.append(m->bj);
+  if (cs.size() == 0) return RBMC_OK;
+  hipStream_t s = cx->stream;
+  rbmc_status st = zero_info(cs, s);
+  if (st != RBMC_OK) return st;
+  cx->arenaA.clear();
+  Program pg;
+  build_factor(cs, pg, cx->arenaA);
+  HIPCHK(cx->arenaA.upload(s));
+  st = run(cx, pg, s, cx->arenaA);
+  if (st != RBMC_OK) return st;
+  HIPCHK(hipStreamSynchronize(s));
+  st = check_info(cs, rep, "block-Jacobi");
+  if (st != RBMC_OK) return st;
+  for (rbmc_model* m : ms) m->bj_ready = true;
+  return RBMC_OK;
+}
+
+// Block-Jacobi PCG on Q x = F z for every column of the set (caller's stream).
+// z, x: multi-vectors in the column layout h (z with n + n_obs per column).
+rbmc_status sample_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const HostCols& h,
+                       const rbmc_est_opts* o, const double* z, double* x, rbmc_report* rep) {
+  const int nk = o->n_samples;
+  hipStream_t s = cx->stream;
+  double t0 = now_s();
+  rbmc_status st = factor_bj(cx, ms, rep);
+  if (st != RBMC_OK) return st;
+  const ColSet cols = colset(cx, h);
+  const int nc = cols.ncols;
+  double* r = cx->r;
+  double* p = cx->p;
+  double* q = cx->q;
+  double* zz = cx->z;
+  double* bb = cx->scal;
+  double* rz = cx->scal + nc;
+  double* rzn = cx->scal + 2 * nc;
+  double* pq = cx->scal + 3 * nc;
+  double* rr = cx->scal + 4 * nc;
+  const int nch = dot_chunks(std::max(h.max_len, 1)), nsp = h.max_tiles;
+  // preconditioner program: gather r -> panels, solve, scatter -> z
+  ChainSet cs;
+  std::vector<double*> xbase_r, xbase_z;
+  for (size_t j = 0; j < ms.size(); ++j) cs.append(ms[j]->bj);
+  Arena& ar = cx->arenaA;
+  ar.clear();
+  Program pre, gat, sca;
+  TileList<PanelTask> g, sc;
+  {
+    size_t c0 = 0;
+    for (size_t j = 0; j < ms.size(); ++j) {
+      rbmc_model* m = ms[j];
+      for (size_t c = 0; c < m->bj.size(); ++c) {
+        const size_t cc = c0 + c;
+        const Chain& ch = cs.chains[cc];
+        const int np = cs.np[cc], nb = cs.nb[cc];
+        for (int t = 0; t < ch.T; ++t) {
+          PanelTask pt{};
+          pt.P = (t == 0) ? cs.ytmp[cc] : cs.pan[cc][t];
+          pt.rg = cs.rg[cc];
+          pt.dm = m->d_dm;
+          pt.X = r + h.base[j];
+          pt.n_k = nk;
+          pt.t = ch.t0 + t;
+          pt.mode = 0;
+          g.add(pt, panel_tiles(np, nk), 16.0 * nb * nk);
+          PanelTask ps = pt;
+          ps.P = cs.pan[cc][t];
+          ps.X = nullptr;
+          ps.Xout = zz + h.base[j];
+          ps.mode = 1;
+          sc.add(ps, panel_tiles(np, nk), 16.0 * nb * nk);
+        }
+      }
+      c0 += m->bj.size();
+    }
+  }
+  gat.panels(ar, g);
+  std::vector<int> stop(cs.size(), 0);
+  build_solve(cs, nk, stop, pre, ar);
+  sca.panels(ar, sc);
+  HIPCHK(ar.upload(s));
+  auto precond = [&]() -> rbmc_status {
+    rbmc_status e = run(cx, gat, s, ar);
+    if (e != RBMC_OK) return e;
+    e = run(cx, pre, s, ar);
+    if (e != RBMC_OK) return e;
+    return run(cx, sca, s, ar);
+  };
+  // b = F z -> r; x = 0
+  launch_apply_op(cols, RBMC_OP_F, z, r, s);
+  HIPCHK(hipMemsetAsync(x, 0, h.total * 8, s));
+  launch_dot_partials(cols, r, r, cx->part, s);
+  launch_reduce_partials(cx->part, nch, nc, bb, s);
+  std::vector<double> hbb(nc);
+  HIPCHK(hipMemcpyAsync(hbb.data(), bb, (size_t)nc * 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  std::vector<uint8_t> act(nc);
+  for (int k = 0; k < nc; ++k) act[k] = hbb[k] > 0.0;
+  HIPCHK(hipMemcpyAsync(cx->active, act.data(), nc, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemsetAsync(cx->iters, 0, (size_t)(nc + 1) * 4, s));
+  st = precond();
+  if (st != RBMC_OK) return st;
+  launch_dot_partials(cols, r, zz, cx->part, s);
+  launch_reduce_partials(cx->part, nch, nc, rz, s);
+  launch_pcg_p(cols, zz, p, rz, rz, cx->active, 1, s);
+  int n_active = 0;
+  for (int k = 0; k < nc; ++k) n_active += act[k];
+  int it = 0;
+  while (n_active > 0 && it < o->pcg_maxit) {
+    const int pid = cx->begin(RBMC_KF_SPMM, 0.0, 16.0 * (double)h.total, s);
+    launch_spmm_dot(cols, p, q, cx->part, s);
+    cx->end(pid, s);
+    launch_reduce_partials(cx->part, nsp, nc, pq, s);
+    launch_pcg_xr(cols, p, q, x, r, rz, pq, cx->active, cx->part, s);
+    launch_reduce_partials(cx->part, nch, nc, rr, s);
+    launch_pcg_check(rr, bb, o->pcg_rtol, cx->active, cx->iters + 1, cx->iters, nc, s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(&n_active, cx->iters, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    ++it;
+    if (n_active == 0) break;
+    st = precond();
+    if (st != RBMC_OK) return st;
+    launch_dot_partials(cols, r, zz, cx->part, s);
+    launch_reduce_partials(cx->part, nch, nc, rzn, s);
+    launch_pcg_p(cols, zz, p, rzn, rz, cx->active, 0, s);
+  }
+  HIPCHK(hipGetLastError());
+  std::vector<int> iters(nc + 1);
+  std::vector<double> hrr(nc);
+  HIPCHK(hipMemcpyAsync(iters.data(), cx->iters, (size_t)(nc + 1) * 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(hrr.data(), rr, (size_t)nc * 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (rep) {
+    int itmax = 0;
+    double itsum = 0.0, maxres = 0.0;
+    for (int k = 0; k < nc; ++k) {
+      itmax = std::max(itmax, iters[k + 1]);
+      itsum += iters[k + 1];
+      if (hbb[k] > 0.0) maxres = std::max(maxres, std::sqrt(hrr[k] / hbb[k]));
+    }
+    rep->pcg_it_max = itmax;
+    rep->pcg_it_mean = nc ? itsum / nc : 0.0;
+    rep->max_rel_residual = maxres;
+    rep->t_sample = now_s() - t0;
+  }
+  return n_active > 0 ? RBMC_W_NOT_CONVERGED : RBMC_OK;
+}
+
+// The estimator from samples for a set of models.  x_base: the samples in the
+// column layout h (ignored when n_k = 0).  The subdomain factorization and the
+// Takahashi sweep do not need the samples: when `sampler` is given they run on
+// the side stream while sampler() produces x on the caller's stream, and the
+// two streams join before the correction solves.
+rbmc_status estimate_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const HostCols& h,
+                         const rbmc_est_opts* o, const double* x_base,
+                         const std::vector<double*>& diag_out,
+                         const std::vector<double*>& trace_out, rbmc_report* rep,
+                         const std::function<rbmc_status()>& sampler) {
+  const int nk = o->n_samples;
+  hipStream_t sA = cx->stream;
+  if (sampler && !cx->side) {
+    HIPCHK(hipStreamCreateWithFlags(&cx->side, hipStreamNonBlocking));
+    for (hipEvent_t& e : cx->join) HIPCHK(hipEventCreate(&e));
+  }
+  hipStream_t s = sampler ? cx->side : sA;  // stream of factorization + Takahashi
+  double t0 = now_s();
+  // combined subdomain chain set and per-chain model index
+  ChainSet cs;
+  std::vector<int> cmodel;
+  for (size_t j = 0; j < ms.size(); ++j) {
+    cs.append(ms[j]->sub);
+    cmodel.insert(cmodel.end(), ms[j]->sub.size(), (int)j);
+  }
+  ChainSet cf;  // chains that need factoring now
+  for (rbmc_model* m : ms)
+    if (!m->sub_ready) cf.append(m->sub);
+  const int nchains = (int)cs.size();
+  Arena& ar = cx->arenaB;
+  ar.clear();
+  Program fac;
+  if (cf.size()) build_factor(cf, fac, ar);
+  // partial-sum slots: per chain and local step: det (diag block, off t->t+1,
+  // off t+1->t) in chunks of 256 rows, mc in chunks of 64 rows
+  std::vector<size_t> det_base(nchains + 1, 0), mc_base(nchains + 1, 0);
+  for (int c = 0; c < nchains; ++c) {
+    const int T = cs.chains[c].T;
+    det_base[c + 1] = det_base[c] + (size_t)T * 3 * ((cs.np[c] + 255) / 256);
+    mc_base[c + 1] = mc_base[c] + (size_t)T * (cs.np[c] / 64);
+  }
+  const size_t det_len = det_base[nchains] * 3, mc_len = mc_base[nchains] * 8;
+  const size_t need = std::max<size_t>(det_len + mc_len, 1);
+  if (cx->epart_len < need) {
+    cx->epool.release();
+    HIPCHK(cx->epool.alloc((void**)&cx->epart, need * 8));
+    cx->epart_len = need;
+  }
+  double* det_part = cx->epart;
+  double* mc_part = cx->epart + det_len;
+  auto det_index = [&](int c, int t, int sl) {
+    const size_t nchk = (cs.np[c] + 255) / 256;
+    return det_base[c] + ((size_t)t * 3 + sl) * nchk;
+  };
+  auto mc_index = [&](int c, int t) { return mc_base[c] + (size_t)t * (cs.np[c] / 64); };
+  auto lc0 = [&](int c) { return cs.chains[c].ct0 - cs.chains[c].t0; };
+  auto lc1 = [&](int c) { return lc0(c) + cs.chains[c].cT - 1; };
+  auto is_core = [&](int c, int t) { return t >= lc0(c) && t <= lc1(c); };
+  auto etask = [&](int c, const double* M, int t, int kind, int trans, double sign, int sl) {
+    ExtractTask e{};
+    e.M = M;
+    e.ld = cs.np[c];
+    e.rg = cs.rg[c];
+    e.dm = cs.owner[c]->d_dm;
+    e.diag_out = diag_out[cmodel[c]];
+    e.partial = det_part;
+    e.out_index = (int)det_index(c, t, sl);
+    e.t = cs.chains[c].t0 + t;
+    e.kind = kind;
+    e.trans = trans;
+    e.sign = sign;
+    return e;
+  };
+
+  // ---- Takahashi sweep ----
+  Program tak;
+  {
+    TileList<ExtractTask> ex;
+    for (int c = 0; c < nchains; ++c) {
+      const Chain& ch = cs.chains[c];
+      const int np = cs.np[c];
+      const size_t blk = (size_t)np * np;
+      tak.copy(cs.sig[c], cs.S[c] + blk * (ch.T - 1), blk * 8);
+      if (is_core(c, ch.T - 1))
+        ex.add(etask(c, cs.sig[c], ch.T - 1, 0, 0, 1.0, 0), (np + 255) / 256);
+    }
+    tak.extract(ar, ex);
+  }
+  for (int t = cs.maxT - 2; t >= 0; --t) {
+    StencilList s1, s2;
+    GemmList g1, g2;
+    TileList<ExtractTask> e1, e2;
+    std::vector<InvTask> mir;
+    for (int c = 0; c < nchains; ++c) {
+      const Chain& ch = cs.chains[c];
+      if (t > ch.T - 2) continue;
+      const int stop_x = std::max(lc0(c) - 1, 0);
+      if (t < stop_x) continue;
+      const double qo = cs.owner[c]->co.qo;
+      const int np = cs.np[c], nb = cs.nb[c];
+      const size_t blk = (size_t)np * np;
+      StencilTask v = stask(cs, c);
+      v.M = cs.sig[c];
+      v.ldm = np;
+      v.alpha = 1.0;
+      v.out = cs.tmp[c];
+      v.ldout = np;
+      v.ncols = np;
+      s1.add(v, np, nb);
+      // X = q_o V^T S_t^-1  (Sigma_{t+1,t} = -X)
+      g1.add(cs.tmp[c], cs.S[c] + blk * t, nullptr, cs.xb[c], np, np, np, np, np, np, qo, 0.0, 1,
+             0, nb, nb);
+      if (is_core(c, t))  // rows at t, columns at t+1: Sigma_{t,t+1} = -X^T
+        e1.add(etask(c, cs.xb[c], t, 1, 1, -1.0, 1), (np + 255) / 256);
+      if (is_core(c, t + 1))  // rows at t+1, columns at t: Sigma_{t+1,t} = -X
+        e1.add(etask(c, cs.xb[c], t + 1, 1, 0, -1.0, 2), (np + 255) / 256);
+      if (t >= lc0(c)) {
+        StencilTask z = stask(cs, c);
+        z.M = cs.xb[c];
+        z.ldm = np;
+        z.alpha = qo;
+        z.out = cs.tmp[c];
+        z.ldout = np;
+        z.ncols = np;
+        s2.add(z, np, nb);
+        g2.add(cs.S[c] + blk * t, cs.tmp[c], cs.S[c] + blk * t, cs.sig[c], np, np, np, np, np,
+               np, 1.0, 1.0, 1, 0, nb, nb);
+        g2.set_last_lower();  // Sigma_tt is symmetric: lower tiles, then mirrored
+        InvTask mt{};
+        mt.M = cs.sig[c];
+        mt.np = np;
+        mir.push_back(mt);
+        if (is_core(c, t)) e2.add(etask(c, cs.sig[c], t, 0, 0, 1.0, 0), (np + 255) / 256);
+      }
+    }
+    tak.stencil(ar, s1);
+    tak.gemm(ar, g1);
+    tak.extract(ar, e1);
+    tak.stencil(ar, s2);
+    tak.gemm(ar, g2);
+    tak.mirror(ar, mir);
+    tak.extract(ar, e2);
+  }
+  // ---- corrections ----
+  Program cor;
+  if (nk > 0) {
+    TileList<PanelTask> rt;
+    for (int c = 0; c < nchains; ++c) {
+      const Chain& ch = cs.chains[c];
+      const int np = cs.np[c];
+      for (int t = 0; t < ch.T; ++t) {
+        PanelTask pt{};
+        pt.P = (t == 0) ? cs.ytmp[c] : cs.pan[c][t];
+        pt.rg = cs.rg[c];
+        pt.dm = cs.owner[c]->d_dm;
+        pt.X = x_base + h.base[cmodel[c]];
+        pt.n_k = nk;
+        pt.t = ch.t0 + t;
+        pt.t0 = ch.t0;
+        pt.T = ch.T;
+        pt.mode = 2;
+        rt.add(pt, panel_tiles(np, nk), 16.0 * cs.nb[c] * nk);
+      }
+    }
+    cor.panels(ar, rt);
+    std::vector<int> stop(nchains);
+    for (int c = 0; c < nchains; ++c) stop[c] = std::max(lc0(c) - 1, 0);
+    build_solve(cs, nk, stop, cor, ar);
+    TileList<McTask> mt;
+    for (int c = 0; c < nchains; ++c) {
+      const Chain& ch = cs.chains[c];
+      for (int t = lc0(c); t <= lc1(c); ++t) {
+        McTask k{};
+        k.mu[0] = (t - 1 >= 0) ? cs.pan[c][t - 1] : nullptr;
+        k.mu[1] = cs.pan[c][t];
+        k.mu[2] = (t + 1 < ch.T) ? cs.pan[c][t + 1] : nullptr;
+        k.np = cs.np[c];
+        k.rg = cs.rg[c];
+        k.dm = cs.owner[c]->d_dm;
+        k.diag_out = diag_out[cmodel[c]];
+        k.partial = mc_part;
+        k.out_index = (int)mc_index(c, t);
+        k.n_k = nk;
+        k.t = ch.t0 + t;
+        mt.add(k, cs.np[c] / 64);
+      }
+    }
+    cor.mc(ar, mt);
+  }
+  // the side stream starts after everything already queued on the caller's stream
+  if (s != sA) {
+    HIPCHK(hipEventRecord(cx->join[0], sA));
+    HIPCHK(hipStreamWaitEvent(s, cx->join[0], 0));
+  }
+  HIPCHK(ar.upload(s));
+  HIPCHK(hipMemsetAsync(cx->epart, 0, need * 8, s));
+  if (cf.size()) {
+    rbmc_status st0 = zero_info(cf, s);
+    if (st0 != RBMC_OK) return st0;
+  }
+  hipEvent_t e_fac = nullptr, e_tak = nullptr, e_beg = nullptr;
+  if (cx->join[1]) {
+    e_beg = cx->join[1];
+    e_fac = cx->join[2];
+    e_tak = cx->join[3];
+    HIPCHK(hipEventRecord(e_beg, s));
+  }
+  rbmc_status st = run(cx, fac, s, ar);
+  if (st != RBMC_OK) return st;
+  if (e_fac) HIPCHK(hipEventRecord(e_fac, s));
+  st = run(cx, tak, s, ar);
+  if (st != RBMC_OK) return st;
+  if (e_tak) HIPCHK(hipEventRecord(e_tak, s));
+  rbmc_status st_samp = RBMC_OK;
+  if (sampler) {
+    st_samp = sampler();  // on the caller's stream, concurrently with the side stream
+    if (st_samp < 0) {
+      (void)hipStreamSynchronize(s);
+      return st_samp;
+    }
+    HIPCHK(hipEventRecord(cx->join[0], s));
+    HIPCHK(hipStreamWaitEvent(sA, cx->join[0], 0));
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  if (cf.size()) {
+    st = check_info(cf, rep, "subdomain");
+    if (st != RBMC_OK) return st;
+    for (rbmc_model* m : ms) m->sub_ready = true;
+  }
+  double t2 = now_s();
+  st = run(cx, cor, sA, ar);
+  if (st != RBMC_OK) return st;
+  HIPCHK(hipStreamSynchronize(sA));
+  double t3 = now_s();
+  float ms_fac = 0.f, ms_tak = 0.f;
+  if (e_beg) {
+    HIPCHK(hipEventElapsedTime(&ms_fac, e_beg, e_fac));
+    HIPCHK(hipEventElapsedTime(&ms_tak, e_fac, e_tak));
+  }
+  // ---- traces: combine partial sums with the temporal weights ----
+  std::vector<double> hpart(det_len + mc_len);
+  HIPCHK(hipMemcpy(hpart.data(), cx->epart, (det_len + mc_len) * 8, hipMemcpyDeviceToHost));
+  const double* hdet = hpart.data();
+  const double* hmc = hpart.data() + det_len;
+  std::vector<std::array<double, 4>> tr(ms.size(), {0.0, 0.0, 0.0, 0.0});
+  double ratio_sum = 0.0;  // sum over nodes of (MC part) / (estimate)
+  size_t n_total = 0;
+  for (rbmc_model* m : ms) n_total += m->plan.n;
+  for (int c = 0; c < nchains; ++c) {
+    const Chain& ch = cs.chains[c];
+    const Coefs& co = cs.owner[c]->co;
+    const int nchk = (cs.np[c] + 255) / 256, mchk = cs.np[c] / 64;
+    for (int t = lc0(c); t <= lc1(c); ++t) {
+      const int tg = ch.t0 + t;
+      // deterministic: slot 0 (t,t), slot 1 (t,t+1), slot 2 (t,t-1)
+      double Fd = 0, Fq[3] = {0, 0, 0}, Fk[3] = {0, 0, 0};
+      for (int sl = 0; sl < 3; ++sl)
+        for (int k = 0; k < nchk; ++k) {
+          const double* pp = &hdet[(det_index(c, t, sl) + k) * 3];
+          if (sl == 0) Fd += pp[0];
+          Fq[sl] += pp[1];
+          Fk[sl] += pp[2];
+        }
+      // Monte Carlo: components [t-1, t, t+1] for Q_s and K, then D, then m/s2
+      double G[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      if (nk > 0)
+        for (int k = 0; k < mchk; ++k)
+          for (int j = 0; j < 8; ++j) G[j] += hmc[(mc_index(c, t) + k) * 8 + j];
+      ratio_sum += G[7];
+      const double wq0 = co.qd[tg], wqo = co.qo, wd0 = co.dqd[tg], wdo = co.dqo;
+      const bool hm = (t - 1 >= 0), hp = (t + 1 < ch.T);
+      const double q_tt = Fq[0] + G[1];
+      const double q_tp = hp ? Fq[1] + G[2] : 0.0;
+      const double q_tm = hm ? Fq[2] + G[0] : 0.0;
+      const double k_tt = Fk[0] + G[4];
+      const double k_tp = hp ? Fk[1] + G[5] : 0.0;
+      const double k_tm = hm ? Fk[2] + G[3] : 0.0;
+      std::array<double, 4>& T = tr[cmodel[c]];
+      T[0] += wq0 * k_tt + wqo * (k_tp + k_tm);
+      T[1] += wq0 * q_tt + wqo * (q_tp + q_tm);
+      T[2] += wd0 * q_tt + wdo * (q_tp + q_tm);
+      T[3] += -2.0 * (Fd + G[6]);
+    }
+  }
+  for (size_t j = 0; j < ms.size(); ++j)
+    if (trace_out[j]) {
+      int k = 0;
+      for (int b = 0; b < 4; ++b)
+        if (o->grad_mask & (1u << b)) trace_out[j][k++] = tr[j][b];
+    }
+  if (rep) {
+    // plug-in MC error: m_i ~ E[mu_i^2] chi2_{n_k} / n_k, so the mean absolute relative
+    // error of the estimate is about sqrt(2/pi) sqrt(2/n_k) m_i / s2_i on average
+    rep->err_estimate =
+        nk > 0 ? std::sqrt(2.0 / M_PI) * std::sqrt(2.0 / nk) * ratio_sum / (double)n_total : 0.0;
+    rep->t_factor = ms_fac * 1e-3;
+    rep->t_takahashi = ms_tak * 1e-3;
+    rep->t_correct = t3 - t2;
+    int64_t bytes = cx->ws.bytes + cx->epool.bytes;
+    for (rbmc_model* m : ms) bytes += m->pool.bytes + m->work.bytes;
+    rep->peak_bytes = bytes;
+  }
+  (void)t0;
+  return st_samp;
+}
+
+// Validate a set of models for one call.
+rbmc_status check_models(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms) {
+  for (rbmc_model* m : ms) {
+    if (!m) return fail(RBMC_E_ARG, "model is NULL");
+    if (m->ctx != cx) return fail(RBMC_E_ARG, "models must belong to the same context");
+  }
+  // a model's panels and factors are per model: it may appear only once
+  std::vector<rbmc_model*> sorted(ms);
+  std::sort(sorted.begin(), sorted.end());
+  if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+    return fail(RBMC_E_ARG, "a model appears twice in one batched call");
+  return RBMC_OK;
+}
+
+// Full path over a set: sample (caller's stream) || factor + Takahashi (side
+// stream), then corrections.  z_ptrs: per model (n + n_obs) x n_k.
+rbmc_status estimate_full(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms,
+                          const rbmc_est_opts* opts, const std::vector<const double*>& z_ptrs,
+                          const std::vector<double*>& diag_out,
+                          const std::vector<double*>& trace_out, rbmc_report* rep) {
+  const int nk = opts->n_samples;
+  if (!cols_fit(ms.size(), nk))
+    return fail(RBMC_E_ARG, "n_models * n_samples exceeds 65535 columns per call");
+  const HostCols h = make_cols(ms, nk);
+  const bool single = ms.size() == 1;
+  rbmc_status st = ensure_ws(cx, ms, h, !single && nk > 0);
+  if (st != RBMC_OK) return st;
+  for (rbmc_model* m : ms) {
+    st = ensure_panels(m, nk);
+    if (st != RBMC_OK) return st;
+  }
+  const double* zb = nullptr;
+  if (nk > 0) {
+    if (single) {
+      zb = z_ptrs[0];
+    } else {
+      for (size_t j = 0; j < ms.size(); ++j)
+        HIPCHK(hipMemcpyAsync(cx->zcat + h.zbase[j], z_ptrs[j],
+                              (size_t)(ms[j]->plan.n + ms[j]->n_obs) * nk * 8,
+                              hipMemcpyDeviceToDevice, cx->stream));
+      zb = cx->zcat;
+    }
+  }
+  rbmc_status st1 = RBMC_OK;
+  std::function<rbmc_status()> sampler;
+  if (nk > 0)
+    sampler = [&]() -> rbmc_status {
+      st1 = sample_set(cx, ms, h, opts, zb, cx->x, rep);
+      return st1;
+    };
+  st = estimate_set(cx, ms, h, opts, cx->x, diag_out, trace_out, rep, sampler);
+  if (st < 0) return st;
+  return st1;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -847,6 +1467,7 @@ rbmc_status rbmc_ctx_profile_read(rbmc_ctx* ctx, int family, rbmc_kernel_stats* 
   if (!ctx || !out) return fail(RBMC_E_ARG, "NULL argument");
   if (family < 0 || family >= RBMC_KF_COUNT) return fail(RBMC_E_ARG, "unknown kernel family");
   HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (ctx->side) HIPCHK(hipStreamSynchronize(ctx->side));
   std::memset(out, 0, sizeof(*out));
   for (const ProfRec& r : ctx->recs) {
     if (r.family != family) continue;
@@ -874,7 +1495,11 @@ rbmc_status rbmc_ctx_create(int device, void* hip_stream, rbmc_ctx** out) {
   return RBMC_OK;
 }
 
-void rbmc_ctx_destroy(rbmc_ctx* ctx) { delete ctx; }
+void rbmc_ctx_destroy(rbmc_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  delete ctx;
+}
 
 rbmc_status rbmc_plan_query(const rbmc_model_desc* desc, const rbmc_decomp_desc* decomp,
                             int32_t p, int32_t* label_out, uint8_t* state_out) {
@@ -934,6 +1559,7 @@ rbmc_status rbmc_model_create(rbmc_ctx* ctx, const rbmc_model_desc* desc,
   MCHK(m->pool.alloc((void**)&m->d_ld, (size_t)P.T * 8));
   MCHK(m->pool.alloc((void**)&m->d_dvec, (size_t)P.n * 8));
   MCHK(m->pool.alloc((void**)&m->d_obs_rank, (size_t)P.n * 4));
+  MCHK(m->pool.alloc((void**)&m->d_dm, sizeof(DevModel)));
   {
     std::vector<int> rank(P.n, -1);
     int r = 0;
@@ -957,7 +1583,6 @@ rbmc_status rbmc_model_create(rbmc_ctx* ctx, const rbmc_model_desc* desc,
   dm.dvec = m->d_dvec;
   dm.obs_rank = m->d_obs_rank;
   // regions
-  std::vector<uint8_t*> inbox_ptrs;
   for (const Region& g : P.regions) {
     RegionDev rd{};
     rd.nb = g.nb();
@@ -972,20 +1597,17 @@ rbmc_status rbmc_model_create(rbmc_ctx* ctx, const rbmc_model_desc* desc,
     MCHK(hipMemcpy(ib, g.in_box.data(), g.in_box.size(), hipMemcpyHostToDevice));
     rd.nodes = nodes;
     rd.nbr = nbr;
+    rd.in_box = ib;
     m->regions.push_back(rd);
-    inbox_ptrs.push_back(ib);
   }
   MCHK(m->pool.alloc((void**)&m->d_regions, m->regions.size() * sizeof(RegionDev)));
   MCHK(hipMemcpy(m->d_regions, m->regions.data(), m->regions.size() * sizeof(RegionDev),
                  hipMemcpyHostToDevice));
-  MCHK(m->pool.alloc((void**)&m->d_inbox, inbox_ptrs.size() * sizeof(uint8_t*)));
-  MCHK(hipMemcpy(m->d_inbox, inbox_ptrs.data(), inbox_ptrs.size() * sizeof(uint8_t*),
-                 hipMemcpyHostToDevice));
   MCHK(m->pool.alloc((void**)&m->d_info, (P.bj.size() + P.sub.size()) * 4));
   {
-    rbmc_status st = alloc_chainset(m, m->bj, P.bj, false);
+    rbmc_status st = alloc_chainset(m, m->bj, P.bj, false, 0);
     if (st != RBMC_OK) return cleanup(st);
-    st = alloc_chainset(m, m->sub, P.sub, true);
+    st = alloc_chainset(m, m->sub, P.sub, true, (int)P.bj.size());
     if (st != RBMC_OK) return cleanup(st);
     st = upload_coefs(m);
     if (st != RBMC_OK) return cleanup(st);
@@ -998,6 +1620,8 @@ rbmc_status rbmc_model_create(rbmc_ctx* ctx, const rbmc_model_desc* desc,
 void rbmc_model_destroy(rbmc_model* m) {
   if (!m) return;
   (void)hipSetDevice(m->ctx->device);
+  (void)hipStreamSynchronize(m->ctx->stream);
+  if (m->ctx->side) (void)hipStreamSynchronize(m->ctx->side);
   m->work.release();
   m->pool.release();
   delete m;
@@ -1022,400 +1646,15 @@ rbmc_status rbmc_apply_op(rbmc_model* m, int op, const double* x, double* y, int
   if (op < RBMC_OP_Q || op > RBMC_OP_F) return fail(RBMC_E_ARG, "unknown operator");
   if (n_rhs < 0) return fail(RBMC_E_ARG, "n_rhs must be >= 0");
   if (n_rhs == 0) return RBMC_OK;
+  if (!cols_fit(1, n_rhs)) return fail(RBMC_E_ARG, "n_rhs exceeds 65535");
   HIPCHK(hipSetDevice(m->ctx->device));
-  launch_apply_op(m->dm, op, x, y, n_rhs, m->ctx->stream);
+  std::vector<rbmc_model*> ms{m};
+  const HostCols h = make_cols(ms, n_rhs);
+  rbmc_status st = ensure_ws(m->ctx, ms, h, false);
+  if (st != RBMC_OK) return st;
+  launch_apply_op(colset(m->ctx, h), op, x, y, m->ctx->stream);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(m->ctx->stream));
-  return RBMC_OK;
-}
-
-// Block-Jacobi PCG on Q x = F z for all samples at once.
-static rbmc_status sample_impl(rbmc_model* m, const rbmc_est_opts* o, const double* z, double* x,
-                               rbmc_report* rep) {
-  const int n = m->plan.n, nk = o->n_samples;
-  hipStream_t s = m->ctx->stream;
-  double t0 = now_s();
-  if (!m->bj_ready) {
-    rbmc_status st = factor_set(m, m->bj, 0, rep, "block-Jacobi");
-    if (st != RBMC_OK) return st;
-    m->bj_ready = true;
-  }
-  rbmc_status st = ensure_work(m, nk);
-  if (st != RBMC_OK) return st;
-  double* r = m->w_r;
-  double* p = m->w_p;
-  double* q = m->w_q;
-  double* zz = m->w_z;
-  double* bb = m->w_scal;
-  double* rz = m->w_scal + nk;
-  double* rzn = m->w_scal + 2 * nk;
-  double* pq = m->w_scal + 3 * nk;
-  double* rr = m->w_scal + 4 * nk;
-  const int nch = dot_chunks(n), nsp = spmm_chunks(m->dm);
-  // preconditioner program: gather r -> panels, solve, scatter -> z
-  m->arena.clear();
-  Program pre, gat, sca;
-  TileList<PanelTask> g, sc;
-  for (size_t c = 0; c < m->bj.chains.size(); ++c) {
-    const Chain& ch = m->bj.chains[c];
-    const int np = m->bj.np[c];
-    for (int t = 0; t < ch.T; ++t) {
-      PanelTask pt{};
-      pt.P = (t == 0) ? m->bj_y[c] : m->bj_pan[c][t];
-      pt.region = ch.region;
-      pt.t = ch.t0 + t;
-      pt.mode = 0;
-      g.add(pt, panel_tiles(np, nk), 16.0 * m->regions[ch.region].nb * nk);
-      PanelTask ps = pt;
-      ps.P = m->bj_pan[c][t];
-      ps.mode = 1;
-      sc.add(ps, panel_tiles(np, nk), 16.0 * m->regions[ch.region].nb * nk);
-    }
-  }
-  gat.panels(m->arena, g, r, nullptr, nk);
-  std::vector<int> stop(m->bj.chains.size(), 0);
-  build_solve(m, m->bj, m->bj_pan, m->bj_y, nk, stop, pre);
-  sca.panels(m->arena, sc, nullptr, zz, nk);
-  HIPCHK(m->arena.upload(s));
-  auto precond = [&]() -> rbmc_status {
-    rbmc_status e = run(m, gat, RunCtx{});
-    if (e != RBMC_OK) return e;
-    e = run(m, pre, RunCtx{});
-    if (e != RBMC_OK) return e;
-    return run(m, sca, RunCtx{});
-  };
-  // b = F z -> r; x = 0
-  launch_apply_op(m->dm, RBMC_OP_F, z, r, nk, s);
-  HIPCHK(hipMemsetAsync(x, 0, (size_t)n * nk * 8, s));
-  launch_dot_partials(r, r, n, nk, m->w_part, nch, s);
-  launch_reduce_partials(m->w_part, nch, nk, bb, s);
-  std::vector<double> hbb(nk);
-  HIPCHK(hipMemcpyAsync(hbb.data(), bb, (size_t)nk * 8, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  std::vector<uint8_t> act(nk);
-  for (int k = 0; k < nk; ++k) act[k] = hbb[k] > 0.0;
-  HIPCHK(hipMemcpyAsync(m->w_active, act.data(), nk, hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemsetAsync(m->w_iters, 0, (size_t)(nk + 1) * 4, s));
-  st = precond();
-  if (st != RBMC_OK) return st;
-  launch_dot_partials(r, zz, n, nk, m->w_part, nch, s);
-  launch_reduce_partials(m->w_part, nch, nk, rz, s);
-  launch_pcg_p(zz, p, rz, rz, m->w_active, n, nk, 1, s);
-  int n_active = 0;
-  for (int k = 0; k < nk; ++k) n_active += act[k];
-  int it = 0;
-  while (n_active > 0 && it < o->pcg_maxit) {
-    const int pid = m->ctx->begin(RBMC_KF_SPMM, 0.0, 16.0 * n * (double)nk);
-    launch_spmm_dot(m->dm, p, q, m->w_part, nk, s);
-    m->ctx->end(pid);
-    launch_reduce_partials(m->w_part, nsp, nk, pq, s);
-    launch_pcg_xr(p, q, x, r, rz, pq, m->w_active, n, nk, m->w_part, nch, s);
-    launch_reduce_partials(m->w_part, nch, nk, rr, s);
-    launch_pcg_check(rr, bb, o->pcg_rtol, m->w_active, m->w_iters + 1, m->w_iters, nk, s);
-    HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(&n_active, m->w_iters, 4, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    ++it;
-    if (n_active == 0) break;
-    st = precond();
-    if (st != RBMC_OK) return st;
-    launch_dot_partials(r, zz, n, nk, m->w_part, nch, s);
-    launch_reduce_partials(m->w_part, nch, nk, rzn, s);
-    launch_pcg_p(zz, p, rzn, rz, m->w_active, n, nk, 0, s);
-  }
-  HIPCHK(hipGetLastError());
-  std::vector<int> iters(nk + 1);
-  std::vector<double> hrr(nk);
-  HIPCHK(hipMemcpyAsync(iters.data(), m->w_iters, (size_t)(nk + 1) * 4, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(hrr.data(), rr, (size_t)nk * 8, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  if (rep) {
-    int itmax = 0;
-    double itsum = 0.0, maxres = 0.0;
-    for (int k = 0; k < nk; ++k) {
-      itmax = std::max(itmax, iters[k + 1]);
-      itsum += iters[k + 1];
-      if (hbb[k] > 0.0) maxres = std::max(maxres, std::sqrt(hrr[k] / hbb[k]));
-    }
-    rep->pcg_it_max = itmax;
-    rep->pcg_it_mean = nk ? itsum / nk : 0.0;
-    rep->max_rel_residual = maxres;
-    rep->t_sample = now_s() - t0;
-    rep->peak_bytes = m->pool.bytes + m->work.bytes;
-  }
-  return n_active > 0 ? RBMC_W_NOT_CONVERGED : RBMC_OK;
-}
-
-// Estimator from samples x (n x n_k, device).
-static rbmc_status estimate_impl(rbmc_model* m, const rbmc_est_opts* o, const double* x,
-                                 double* diag_out, double* trace_out, rbmc_report* rep) {
-  const int nk = o->n_samples;
-  hipStream_t s = m->ctx->stream;
-  const Plan& P = m->plan;
-  double t0 = now_s();
-  if (!m->sub_ready) {
-    rbmc_status st = factor_set(m, m->sub, (int)m->bj.chains.size(), rep, "subdomain");
-    if (st != RBMC_OK) return st;
-    m->sub_ready = true;
-  }
-  double t1 = now_s();
-  rbmc_status st = ensure_work(m, nk);
-  if (st != RBMC_OK) return st;
-  ChainSet& cs = m->sub;
-  const int nchains = (int)cs.chains.size();
-  // trace slots: per chain, per local step: det (diag block, off t->t+1, off t+1->t) and mc
-  int nchunk_max = 1;
-  for (int c = 0; c < nchains; ++c) nchunk_max = std::max(nchunk_max, (cs.np[c] + 255) / 256);
-  std::vector<int> slot_base(nchains + 1, 0);
-  for (int c = 0; c < nchains; ++c) slot_base[c + 1] = slot_base[c] + cs.chains[c].T * 4;
-  const int nslots = slot_base[nchains];
-  const int mc_chunks = [&] {
-    int v = 1;
-    for (int c = 0; c < nchains; ++c) v = std::max(v, cs.np[c] / 64);
-    return v;
-  }();
-  const size_t det_len = (size_t)nslots * nchunk_max * 3;
-  const size_t mc_len = (size_t)nslots * mc_chunks * 8;
-  const size_t need = det_len + mc_len;
-  if (m->diag_part_len < need) {
-    double* p = nullptr;
-    HIPCHK(m->work.alloc((void**)&p, need * 8));
-    m->w_diag_part = p;
-    m->diag_part_len = need;
-  }
-  double* det_part = m->w_diag_part;
-  double* mc_part = m->w_diag_part + det_len;
-  HIPCHK(hipMemsetAsync(m->w_diag_part, 0, need * 8, s));
-
-  // ---- Takahashi sweep ----
-  m->arena.clear();
-  Program tak;
-  auto lc0 = [&](int c) { return cs.chains[c].ct0 - cs.chains[c].t0; };
-  auto lc1 = [&](int c) { return lc0(c) + cs.chains[c].cT - 1; };
-  auto is_core = [&](int c, int t) { return t >= lc0(c) && t <= lc1(c); };
-  {
-    TileList<ExtractTask> ex;
-    for (int c = 0; c < nchains; ++c) {
-      const Chain& ch = cs.chains[c];
-      const int np = cs.np[c];
-      const size_t blk = (size_t)np * np;
-      tak.copy(cs.sig[c], cs.S[c] + blk * (ch.T - 1), blk * 8);
-      if (is_core(c, ch.T - 1)) {
-        ExtractTask e{};
-        e.M = cs.sig[c];
-        e.ld = np;
-        e.region = ch.region;
-        e.t = ch.t0 + ch.T - 1;
-        e.kind = 0;
-        e.sign = 1.0;
-        e.out_slot = slot_base[c] + (ch.T - 1) * 4 + 0;
-        ex.add(e, (np + 255) / 256);
-      }
-    }
-    tak.extract(m->arena, ex);
-  }
-  for (int t = cs.maxT - 2; t >= 0; --t) {
-    StencilList s1, s2;
-    GemmList g1, g2;
-    TileList<ExtractTask> e1, e2;
-    std::vector<InvTask> mir;
-    for (int c = 0; c < nchains; ++c) {
-      const Chain& ch = cs.chains[c];
-      if (t > ch.T - 2) continue;
-      const int stop_x = std::max(lc0(c) - 1, 0);
-      if (t < stop_x) continue;
-      const int np = cs.np[c];
-      const size_t blk = (size_t)np * np;
-      StencilTask v{};
-      v.M = cs.sig[c];
-      v.ldm = np;
-      v.alpha = 1.0;
-      v.out = cs.tmp[c];
-      v.ldout = np;
-      v.ncols = np;
-      v.region = ch.region;
-      s1.add(v, np, m->regions[ch.region].nb);
-      // X = q_o V^T S_t^-1  (Sigma_{t+1,t} = -X)
-      g1.add(cs.tmp[c], cs.S[c] + blk * t, nullptr, cs.xb[c], np, np, np, np, np, np, m->co.qo,
-             0.0, 1, 0, m->regions[ch.region].nb, m->regions[ch.region].nb);
-      if (is_core(c, t)) {  // rows at t, columns at t+1: Sigma_{t,t+1} = -X^T
-        ExtractTask e{};
-        e.M = cs.xb[c];
-        e.ld = np;
-        e.region = ch.region;
-        e.t = ch.t0 + t;
-        e.kind = 1;
-        e.trans = 1;
-        e.sign = -1.0;
-        e.out_slot = slot_base[c] + t * 4 + 1;
-        e1.add(e, (np + 255) / 256);
-      }
-      if (is_core(c, t + 1)) {  // rows at t+1, columns at t: Sigma_{t+1,t} = -X
-        ExtractTask e{};
-        e.M = cs.xb[c];
-        e.ld = np;
-        e.region = ch.region;
-        e.t = ch.t0 + t + 1;
-        e.kind = 1;
-        e.trans = 0;
-        e.sign = -1.0;
-        e.out_slot = slot_base[c] + (t + 1) * 4 + 2;
-        e1.add(e, (np + 255) / 256);
-      }
-      if (t >= lc0(c)) {
-        StencilTask z{};
-        z.M = cs.xb[c];
-        z.ldm = np;
-        z.alpha = m->co.qo;
-        z.out = cs.tmp[c];
-        z.ldout = np;
-        z.ncols = np;
-        z.region = ch.region;
-        s2.add(z, np, m->regions[ch.region].nb);
-        g2.add(cs.S[c] + blk * t, cs.tmp[c], cs.S[c] + blk * t, cs.sig[c], np, np, np, np, np,
-               np, 1.0, 1.0, 1, 0, m->regions[ch.region].nb, m->regions[ch.region].nb);
-        g2.set_last_lower();  // Sigma_tt is symmetric: lower tiles, then mirrored
-        {
-          InvTask mt{};
-          mt.M = cs.sig[c];
-          mt.np = np;
-          mir.push_back(mt);
-        }
-        if (is_core(c, t)) {
-          ExtractTask e{};
-          e.M = cs.sig[c];
-          e.ld = np;
-          e.region = ch.region;
-          e.t = ch.t0 + t;
-          e.kind = 0;
-          e.sign = 1.0;
-          e.out_slot = slot_base[c] + t * 4 + 0;
-          e2.add(e, (np + 255) / 256);
-        }
-      }
-    }
-    tak.stencil(m->arena, s1);
-    tak.gemm(m->arena, g1);
-    tak.extract(m->arena, e1);
-    tak.stencil(m->arena, s2);
-    tak.gemm(m->arena, g2);
-    tak.mirror(m->arena, mir);
-    tak.extract(m->arena, e2);
-  }
-  // ---- corrections ----
-  Program cor;
-  if (nk > 0) {
-    TileList<PanelTask> rt;
-    for (int c = 0; c < nchains; ++c) {
-      const Chain& ch = cs.chains[c];
-      const int np = cs.np[c];
-      for (int t = 0; t < ch.T; ++t) {
-        PanelTask pt{};
-        pt.P = (t == 0) ? m->sub_y[c] : m->sub_pan[c][t];
-        pt.region = ch.region;
-        pt.t = ch.t0 + t;
-        pt.t0 = ch.t0;
-        pt.T = ch.T;
-        pt.mode = 2;
-        rt.add(pt, panel_tiles(np, nk), 16.0 * m->regions[ch.region].nb * nk);
-      }
-    }
-    cor.panels(m->arena, rt, x, nullptr, nk);
-    std::vector<int> stop(nchains);
-    for (int c = 0; c < nchains; ++c) stop[c] = std::max(lc0(c) - 1, 0);
-    build_solve(m, cs, m->sub_pan, m->sub_y, nk, stop, cor);
-    TileList<McTask> mt;
-    for (int c = 0; c < nchains; ++c) {
-      const Chain& ch = cs.chains[c];
-      for (int t = lc0(c); t <= lc1(c); ++t) {
-        McTask k{};
-        k.mu[0] = (t - 1 >= 0) ? m->sub_pan[c][t - 1] : nullptr;
-        k.mu[1] = m->sub_pan[c][t];
-        k.mu[2] = (t + 1 < ch.T) ? m->sub_pan[c][t + 1] : nullptr;
-        k.np = cs.np[c];
-        k.region = ch.region;
-        k.t = ch.t0 + t;
-        k.out_slot = slot_base[c] + t * 4 + 3;
-        mt.add(k, cs.np[c] / 64);
-      }
-    }
-    cor.mc(m->arena, mt, nk);
-  }
-  HIPCHK(m->arena.upload(s));
-  RunCtx rc;
-  rc.diag_out = diag_out;
-  rc.partial = det_part;
-  rc.nchunk_max = nchunk_max;
-  st = run(m, tak, rc);
-  if (st != RBMC_OK) return st;
-  HIPCHK(hipStreamSynchronize(s));
-  double t2 = now_s();
-  rc.partial = mc_part;
-  rc.nchunk_max = mc_chunks;
-  st = run(m, cor, rc);
-  if (st != RBMC_OK) return st;
-  HIPCHK(hipStreamSynchronize(s));
-  double t3 = now_s();
-  // ---- traces: combine partial sums with the temporal weights ----
-  std::vector<double> hdet(det_len), hmc(mc_len);
-  HIPCHK(hipMemcpy(hdet.data(), det_part, det_len * 8, hipMemcpyDeviceToHost));
-  HIPCHK(hipMemcpy(hmc.data(), mc_part, mc_len * 8, hipMemcpyDeviceToHost));
-  const Coefs& co = m->co;
-  double tr[4] = {0, 0, 0, 0};
-  double ratio_sum = 0.0;  // sum over nodes of (MC part) / (estimate)
-  for (int c = 0; c < nchains; ++c) {
-    const Chain& ch = cs.chains[c];
-    for (int t = lc0(c); t <= lc1(c); ++t) {
-      const int tg = ch.t0 + t;
-      // deterministic: slot 0 (t,t), slot 1 (t,t+1), slot 2 (t,t-1)
-      double Fd = 0, Fq[3] = {0, 0, 0}, Fk[3] = {0, 0, 0};
-      for (int sl = 0; sl < 3; ++sl) {
-        const int slot = slot_base[c] + t * 4 + sl;
-        for (int ch2 = 0; ch2 < nchunk_max; ++ch2) {
-          const double* pp = &hdet[((size_t)slot * nchunk_max + ch2) * 3];
-          if (sl == 0) Fd += pp[0];
-          Fq[sl] += pp[1];
-          Fk[sl] += pp[2];
-        }
-      }
-      // Monte Carlo: slot 3, components [t-1, t, t+1] for Q_s and K, then D
-      double G[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-      if (nk > 0) {
-        const int slot = slot_base[c] + t * 4 + 3;
-        for (int ch2 = 0; ch2 < mc_chunks; ++ch2)
-          for (int j = 0; j < 8; ++j) G[j] += hmc[((size_t)slot * mc_chunks + ch2) * 8 + j];
-      }
-      ratio_sum += G[7];
-      const double wq0 = co.qd[tg], wqo = co.qo, wd0 = co.dqd[tg], wdo = co.dqo;
-      const bool hm = (t - 1 >= 0), hp = (t + 1 < ch.T);
-      // Q_s-weighted sums over (t,t), (t,t+1), (t,t-1)
-      const double q_tt = Fq[0] + G[1];
-      const double q_tp = hp ? Fq[1] + G[2] : 0.0;
-      const double q_tm = hm ? Fq[2] + G[0] : 0.0;
-      const double k_tt = Fk[0] + G[4];
-      const double k_tp = hp ? Fk[1] + G[5] : 0.0;
-      const double k_tm = hm ? Fk[2] + G[3] : 0.0;
-      tr[0] += wq0 * k_tt + wqo * (k_tp + k_tm);
-      tr[1] += wq0 * q_tt + wqo * (q_tp + q_tm);
-      tr[2] += wd0 * q_tt + wdo * (q_tp + q_tm);
-      tr[3] += -2.0 * (Fd + G[6]);
-    }
-  }
-  if (trace_out) {
-    int j = 0;
-    for (int b = 0; b < 4; ++b)
-      if (o->grad_mask & (1u << b)) trace_out[j++] = tr[b];
-  }
-  if (rep) {
-    // plug-in MC error: m_i ~ E[mu_i^2] chi2_{n_k} / n_k, so the mean absolute relative
-    // error of the estimate is about sqrt(2/pi) sqrt(2/n_k) m_i / s2_i on average
-    rep->err_estimate =
-        nk > 0 ? std::sqrt(2.0 / M_PI) * std::sqrt(2.0 / nk) * ratio_sum / P.n : 0.0;
-    rep->t_factor += t1 - t0;
-    rep->t_takahashi = t2 - t1;
-    rep->t_correct = t3 - t2;
-    rep->peak_bytes = m->pool.bytes + m->work.bytes;
-  }
   return RBMC_OK;
 }
 
@@ -1426,10 +1665,20 @@ rbmc_status rbmc_sample(rbmc_model* m, const rbmc_est_opts* opts, const double* 
   rbmc_status st = check_opts(opts, true);
   if (st != RBMC_OK) return st;
   if (opts->n_samples == 0) return RBMC_OK;
+  if (!cols_fit(1, opts->n_samples)) return fail(RBMC_E_ARG, "n_samples exceeds 65535");
   HIPCHK(hipSetDevice(m->ctx->device));
   double t0 = now_s();
-  st = sample_impl(m, opts, z, x, rep);
-  if (rep) rep->t_total = now_s() - t0;
+  std::vector<rbmc_model*> ms{m};
+  const HostCols h = make_cols(ms, opts->n_samples);
+  st = ensure_ws(m->ctx, ms, h, false);
+  if (st != RBMC_OK) return st;
+  st = ensure_panels(m, opts->n_samples);
+  if (st != RBMC_OK) return st;
+  st = sample_set(m->ctx, ms, h, opts, z, x, rep);
+  if (rep) {
+    rep->t_total = now_s() - t0;
+    rep->peak_bytes = m->ctx->ws.bytes + m->pool.bytes + m->work.bytes;
+  }
   return st;
 }
 
@@ -1443,7 +1692,11 @@ rbmc_status rbmc_estimate_from_samples(rbmc_model* m, const rbmc_est_opts* opts,
   if (opts->grad_mask && !trace_out) return fail(RBMC_E_ARG, "trace_out is NULL");
   HIPCHK(hipSetDevice(m->ctx->device));
   double t0 = now_s();
-  st = estimate_impl(m, opts, x, diag_out, trace_out, rep);
+  std::vector<rbmc_model*> ms{m};
+  const HostCols h = make_cols(ms, opts->n_samples);
+  st = ensure_panels(m, opts->n_samples);
+  if (st != RBMC_OK) return st;
+  st = estimate_set(m->ctx, ms, h, opts, x, {diag_out}, {trace_out}, rep, {});
   if (rep) rep->t_total = now_s() - t0;
   return st;
 }
@@ -1460,26 +1713,42 @@ rbmc_status rbmc_estimate(rbmc_model* m, const rbmc_est_opts* opts, const double
   if (opts->grad_mask && !trace_out) return fail(RBMC_E_ARG, "trace_out is NULL");
   HIPCHK(hipSetDevice(m->ctx->device));
   double t0 = now_s();
-  rbmc_status st1 = RBMC_OK;
-  if (opts->n_samples > 0) {
-    st = ensure_work(m, opts->n_samples);
-    if (st != RBMC_OK) return st;
-    st1 = sample_impl(m, opts, z, m->w_x, rep);
-    if (st1 < 0) return st1;
-  }
-  double ts = rep ? rep->t_sample : 0.0;
-  int itmax = rep ? rep->pcg_it_max : 0;
-  double itmean = rep ? rep->pcg_it_mean : 0.0, maxres = rep ? rep->max_rel_residual : 0.0;
-  st = estimate_impl(m, opts, m->w_x, diag_out, trace_out, rep);
-  if (rep) {
-    rep->t_sample = ts;
-    rep->pcg_it_max = itmax;
-    rep->pcg_it_mean = itmean;
-    rep->max_rel_residual = maxres;
-    rep->t_total = now_s() - t0;
-  }
+  st = estimate_full(m->ctx, {m}, opts, {z}, {diag_out}, {trace_out}, rep);
+  if (rep) rep->t_total = now_s() - t0;
+  return st;
+}
+
+rbmc_status rbmc_estimate_batched(rbmc_ctx* ctx, int32_t n_models, rbmc_model* const* models,
+                                  const rbmc_est_opts* opts, const double* const* z,
+                                  double* const* diag_out, double* const* trace_out,
+                                  rbmc_report* rep) {
+  init_report(rep);
+  if (!ctx || n_models < 0 || (n_models > 0 && (!models || !diag_out)))
+    return fail(RBMC_E_ARG, "NULL argument");
+  rbmc_status st = check_opts(opts, true);
   if (st != RBMC_OK) return st;
-  return st1;
+  if (n_models == 0) return RBMC_OK;
+  std::vector<rbmc_model*> ms(models, models + n_models);
+  st = check_models(ctx, ms);
+  if (st != RBMC_OK) return st;
+  std::vector<const double*> zp(n_models, nullptr);
+  std::vector<double*> dp(diag_out, diag_out + n_models), tp(n_models, nullptr);
+  for (int j = 0; j < n_models; ++j) {
+    if (!dp[j]) return fail(RBMC_E_ARG, "diag_out entry is NULL");
+    if (opts->n_samples > 0) {
+      if (!z || !z[j]) return fail(RBMC_E_UNSUPPORTED, "z must be supplied for every model");
+      zp[j] = z[j];
+    }
+    if (opts->grad_mask) {
+      if (!trace_out || !trace_out[j]) return fail(RBMC_E_ARG, "trace_out entry is NULL");
+      tp[j] = trace_out[j];
+    }
+  }
+  HIPCHK(hipSetDevice(ctx->device));
+  double t0 = now_s();
+  st = estimate_full(ctx, ms, opts, zp, dp, tp, rep);
+  if (rep) rep->t_total = now_s() - t0;
+  return st;
 }
 
 }  // extern "C"

@@ -1,7 +1,8 @@
 // Kernels on chain panels: gather/scatter between global multi-vectors and
 // padded region panels, the correction right-hand sides Q_AB x_B, and the
 // reductions that turn dense Q_AA^-1 blocks and correction panels into the
-// estimator's diagonal and trace contributions.
+// estimator's diagonal and trace contributions.  Every task carries its own
+// model and region pointers, so one launch serves chains of many models.
 #include "rbmc_impl.h"
 
 namespace rbmc {
@@ -9,22 +10,26 @@ namespace rbmc {
 namespace {
 constexpr int PT_N = 64;   // nodes per panel tile
 constexpr int PT_K = 64;   // samples per panel tile
-}  // namespace
 
-int panel_tiles(int np, int n_k) { return (np / PT_N) * ((n_k + PT_K - 1) / PT_K); }
-
-__global__ __launch_bounds__(256) void k_panels(const PanelTask* __restrict__ tasks, int n_tasks,
-                                                const RegionDev* __restrict__ regs, DevModel m,
-                                                const double* __restrict__ X,
-                                                double* __restrict__ Xout, int n_k) {
+template <class T>
+__device__ inline int find_task_of(const T* __restrict__ tasks, int n_tasks, int b) {
   int lo = 0, hi = n_tasks - 1;
-  const int b = blockIdx.x;
   while (lo < hi) {
     int mid = (lo + hi + 1) / 2;
     if (tasks[mid].tile_start <= b) lo = mid; else hi = mid - 1;
   }
-  const PanelTask tk = tasks[lo];
-  const RegionDev rg = regs[tk.region];
+  return lo;
+}
+}  // namespace
+
+int panel_tiles(int np, int n_k) { return (np / PT_N) * ((n_k + PT_K - 1) / PT_K); }
+
+__global__ __launch_bounds__(256) void k_panels(const PanelTask* __restrict__ tasks, int n_tasks) {
+  const int b = blockIdx.x;
+  const PanelTask tk = tasks[find_task_of(tasks, n_tasks, b)];
+  const RegionDev rg = *tk.rg;
+  const DevModel m = *tk.dm;
+  const int n_k = tk.n_k;
   const int tile = b - tk.tile_start;
   const int tiles_k = (n_k + PT_K - 1) / PT_K;
   const int a = (tile / tiles_k) * PT_N + (threadIdx.x & 63);
@@ -37,14 +42,14 @@ __global__ __launch_bounds__(256) void k_panels(const PanelTask* __restrict__ ta
     for (int kk = threadIdx.x >> 6; kk < PT_K; kk += 4) {
       const int k = kbase + kk;
       if (k >= n_k) break;
-      tk.P[(size_t)k * rg.np + a] = real ? X[(size_t)k * m.n + base] : 0.0;
+      tk.P[(size_t)k * rg.np + a] = real ? tk.X[(size_t)k * m.n + base] : 0.0;
     }
   } else if (tk.mode == 1) {
     if (!real) return;
     for (int kk = threadIdx.x >> 6; kk < PT_K; kk += 4) {
       const int k = kbase + kk;
       if (k >= n_k) break;
-      Xout[(size_t)k * m.n + base] = tk.P[(size_t)k * rg.np + a];
+      tk.Xout[(size_t)k * m.n + base] = tk.P[(size_t)k * rg.np + a];
     }
   } else {
     // r_a = sum over neighbours j of (t, node) outside A = [t0, t0+T) x R of Q_aj x_j
@@ -73,40 +78,31 @@ __global__ __launch_bounds__(256) void k_panels(const PanelTask* __restrict__ ta
       const int k = kbase + kk;
       if (k >= n_k) break;
       double v = 0.0;
-      for (int c = 0; c < cnt; ++c) v += cf[c] * X[(size_t)k * m.n + idx[c]];
+      for (int c = 0; c < cnt; ++c) v += cf[c] * tk.X[(size_t)k * m.n + idx[c]];
       tk.P[(size_t)k * rg.np + a] = v;
     }
   }
 }
 
-void launch_panels(const PanelTask* d_tasks, int n_tasks, int total_tiles, const RegionDev* regs,
-                   const DevModel& m, const double* X, double* Xout, int n_k, hipStream_t s) {
+void launch_panels(const PanelTask* d_tasks, int n_tasks, int total_tiles, hipStream_t s) {
   if (total_tiles <= 0) return;
-  k_panels<<<total_tiles, 256, 0, s>>>(d_tasks, n_tasks, regs, m, X, Xout, n_k);
+  k_panels<<<total_tiles, 256, 0, s>>>(d_tasks, n_tasks);
 }
 
 // ---------------------------------------------------------------------------
 // Deterministic-part extraction. One workgroup per 256 region rows.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_extract(const ExtractTask* __restrict__ tasks,
-                                                 int n_tasks,
-                                                 const RegionDev* __restrict__ regs,
-                                                 const uint8_t* const* __restrict__ in_box,
-                                                 DevModel m, double* __restrict__ diag_out,
-                                                 double* __restrict__ partial, int nchunk_max) {
+                                                 int n_tasks) {
   __shared__ double red[3][256];
-  int lo = 0, hi = n_tasks - 1;
   const int b = blockIdx.x;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) / 2;
-    if (tasks[mid].tile_start <= b) lo = mid; else hi = mid - 1;
-  }
-  const ExtractTask tk = tasks[lo];
-  const RegionDev rg = regs[tk.region];
+  const ExtractTask tk = tasks[find_task_of(tasks, n_tasks, b)];
+  const RegionDev rg = *tk.rg;
+  const DevModel& m = *tk.dm;
   const int chunk = b - tk.tile_start;
   const int a = chunk * 256 + threadIdx.x;
   double sd = 0.0, sq = 0.0, sk = 0.0;
-  if (a < rg.nb && in_box[tk.region][a]) {
+  if (a < rg.nb && rg.in_box[a]) {
     const int node = rg.nodes[a];
     auto el = [&](int r, int c) {  // Sigma block entry (r, c) in region-local indices
       return tk.trans ? tk.M[(size_t)r * tk.ld + c] : tk.M[(size_t)c * tk.ld + r];
@@ -119,7 +115,7 @@ __global__ __launch_bounds__(256) void k_extract(const ExtractTask* __restrict__
       if (q < kN5) sk += m.kk[(size_t)q * m.ns + node] * v;
       if (q == 0 && tk.kind == 0) {
         const size_t i = (size_t)tk.t * m.ns + node;
-        diag_out[i] = v;
+        tk.diag_out[i] = v;
         sd = m.dvec[i] * v;
       }
     }
@@ -134,44 +130,35 @@ __global__ __launch_bounds__(256) void k_extract(const ExtractTask* __restrict__
     __syncthreads();
   }
   if (threadIdx.x < 3)
-    partial[((size_t)tk.out_slot * nchunk_max + chunk) * 3 + threadIdx.x] = red[threadIdx.x][0];
+    tk.partial[((size_t)tk.out_index + chunk) * 3 + threadIdx.x] = red[threadIdx.x][0];
 }
 
-void launch_extract(const ExtractTask* d_tasks, int n_tasks, int total_tiles,
-                    const RegionDev* regs, const uint8_t* const* in_box, const DevModel& m,
-                    double* diag_out, double* partial, int nchunk_max, hipStream_t s) {
+void launch_extract(const ExtractTask* d_tasks, int n_tasks, int total_tiles, hipStream_t s) {
   if (total_tiles <= 0) return;
-  k_extract<<<total_tiles, 256, 0, s>>>(d_tasks, n_tasks, regs, in_box, m, diag_out, partial,
-                                       nchunk_max);
+  k_extract<<<total_tiles, 256, 0, s>>>(d_tasks, n_tasks);
 }
 
 // ---------------------------------------------------------------------------
 // Monte Carlo part. Workgroup = 64 region rows x all samples (4 sample lanes
-// per row).  Outputs: diag on core rows and 7 partial sums per workgroup:
+// per row).  Outputs: diag on core rows and 8 partial sums per workgroup:
 //   [0..2] mu_t . (Q_s mu_{t-1,t,t+1}), [3..5] mu_t . (K mu_{t-1,t,t+1}),
-//   [6] sum D mu_t^2, all divided by n_k.
+//   [6] sum D mu_t^2 (all divided by n_k), [7] sum of m_a / s2_a.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_mc(const McTask* __restrict__ tasks, int n_tasks,
-                                            const RegionDev* __restrict__ regs,
-                                            const uint8_t* const* __restrict__ in_box,
-                                            DevModel m, int n_k, double* __restrict__ diag_out,
-                                            double* __restrict__ partial, int nchunk_max) {
+__global__ __launch_bounds__(256) void k_mc(const McTask* __restrict__ tasks, int n_tasks) {
   __shared__ double red[8][256];
-  int lo = 0, hi = n_tasks - 1;
   const int b = blockIdx.x;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) / 2;
-    if (tasks[mid].tile_start <= b) lo = mid; else hi = mid - 1;
-  }
-  const McTask tk = tasks[lo];
-  const RegionDev rg = regs[tk.region];
+  const McTask tk = tasks[find_task_of(tasks, n_tasks, b)];
+  const RegionDev rg = *tk.rg;
+  const DevModel& m = *tk.dm;
+  const int n_k = tk.n_k;
   const int chunk = b - tk.tile_start;
   const int a = chunk * 64 + (threadIdx.x & 63);
   const int ks = threadIdx.x >> 6;
+  const bool mine = a < rg.nb && rg.in_box[a];
   double acc[8];
 #pragma unroll
   for (int c = 0; c < 8; ++c) acc[c] = 0.0;
-  if (a < rg.nb && in_box[tk.region][a]) {
+  if (mine) {
     const int node = rg.nodes[a];
     const size_t i = (size_t)tk.t * m.ns + node;
     const double dv = m.dvec[i];
@@ -211,13 +198,13 @@ __global__ __launch_bounds__(256) void k_mc(const McTask* __restrict__ tasks, in
   // diagonal: combine the 4 sample lanes of each row in a fixed order; the
   // ratio m_a / s2_a (MC part over estimate) feeds the plug-in error estimate
   double ratio = 0.0;
-  if (threadIdx.x < 64 && a < rg.nb && in_box[tk.region][a]) {
+  if (threadIdx.x < 64 && mine) {
     const double s = (red[7][threadIdx.x] + red[7][threadIdx.x + 64]) +
                      (red[7][threadIdx.x + 128] + red[7][threadIdx.x + 192]);
     const size_t i = (size_t)tk.t * m.ns + rg.nodes[a];
     const double mhat = s / n_k;
-    const double est = diag_out[i] + mhat;
-    diag_out[i] = est;
+    const double est = tk.diag_out[i] + mhat;
+    tk.diag_out[i] = est;
     ratio = est > 0.0 ? mhat * n_k / est : 0.0;  // scaled back by 1/n_k below
   }
   __syncthreads();
@@ -229,16 +216,12 @@ __global__ __launch_bounds__(256) void k_mc(const McTask* __restrict__ tasks, in
     __syncthreads();
   }
   if (threadIdx.x < 8)
-    partial[((size_t)tk.out_slot * nchunk_max + chunk) * 8 + threadIdx.x] =
-        red[threadIdx.x][0] / n_k;
+    tk.partial[((size_t)tk.out_index + chunk) * 8 + threadIdx.x] = red[threadIdx.x][0] / n_k;
 }
 
-void launch_mc(const McTask* d_tasks, int n_tasks, int total_tiles, const RegionDev* regs,
-               const uint8_t* const* in_box, const DevModel& m, int n_k, double* diag_out,
-               double* partial, int nchunk_max, hipStream_t s) {
+void launch_mc(const McTask* d_tasks, int n_tasks, int total_tiles, hipStream_t s) {
   if (total_tiles <= 0) return;
-  k_mc<<<total_tiles, 256, 0, s>>>(d_tasks, n_tasks, regs, in_box, m, n_k, diag_out, partial,
-                                   nchunk_max);
+  k_mc<<<total_tiles, 256, 0, s>>>(d_tasks, n_tasks);
 }
 
 }  // namespace rbmc

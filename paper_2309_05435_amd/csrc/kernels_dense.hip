@@ -524,8 +524,7 @@ void launch_gj2_fix(const Gj2Task* d_tasks, int n_tasks, int total_tiles, hipStr
 // on 64 x 64 output tiles; rows are region nodes (padded to np).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_rstencil(const StencilTask* __restrict__ tasks,
-                                                  int n_tasks, const RegionDev* __restrict__ regs,
-                                                  const double* __restrict__ qs, int ns) {
+                                                  int n_tasks) {
   __shared__ double tileT[64 * 65];
   int lo = 0, hi = n_tasks - 1;
   const int b = blockIdx.x;
@@ -534,7 +533,9 @@ __global__ __launch_bounds__(256) void k_rstencil(const StencilTask* __restrict_
     if (tasks[mid].tile_start <= b) lo = mid; else hi = mid - 1;
   }
   const StencilTask tk = tasks[lo];
-  const RegionDev rg = regs[tk.region];
+  const RegionDev rg = *tk.rg;
+  const double* __restrict__ qs = tk.qs;
+  const int ns = tk.ns;
   const int tile = b - tk.tile_start;
   const int tiles_c = (tk.ncols + 63) / 64;
   const int a0 = (tile / tiles_c) * 64, c0 = (tile % tiles_c) * 64;
@@ -605,12 +606,12 @@ __global__ __launch_bounds__(256) void k_rstencil(const StencilTask* __restrict_
 
 // out += gamma Q_R + diag(dv) + I on the padded diagonal: one thread per row,
 // touching only the stencil positions.  Grid (row blocks of 256, tasks).
-__global__ __launch_bounds__(256) void k_sparse_add(const StencilTask* __restrict__ tasks,
-                                                    const RegionDev* __restrict__ regs,
-                                                    const double* __restrict__ qs, int ns) {
+__global__ __launch_bounds__(256) void k_sparse_add(const StencilTask* __restrict__ tasks) {
   const StencilTask tk = tasks[blockIdx.y];
   if (tk.gamma == 0.0 && tk.dv == nullptr && !tk.pad_identity) return;
-  const RegionDev rg = regs[tk.region];
+  const RegionDev rg = *tk.rg;
+  const double* __restrict__ qs = tk.qs;
+  const int ns = tk.ns;
   const int a = blockIdx.x * 256 + threadIdx.x;
   if (a >= rg.np) return;
   if (a < rg.nb) {
@@ -626,13 +627,11 @@ __global__ __launch_bounds__(256) void k_sparse_add(const StencilTask* __restric
   }
 }
 
-void launch_rstencil(const StencilTask* d_tasks, int n_tasks, int total_tiles,
-                     const RegionDev* d_regions, const double* qs, int ns, int max_np,
+void launch_rstencil(const StencilTask* d_tasks, int n_tasks, int total_tiles, int max_np,
                      hipStream_t s) {
   if (total_tiles <= 0) return;
-  k_rstencil<<<total_tiles, 256, 0, s>>>(d_tasks, n_tasks, d_regions, qs, ns);
-  if (max_np > 0)
-    k_sparse_add<<<dim3((max_np + 255) / 256, n_tasks), 256, 0, s>>>(d_tasks, d_regions, qs, ns);
+  k_rstencil<<<total_tiles, 256, 0, s>>>(d_tasks, n_tasks);
+  if (max_np > 0) k_sparse_add<<<dim3((max_np + 255) / 256, n_tasks), 256, 0, s>>>(d_tasks);
 }
 
 // Lower triangle -> upper triangle (full symmetric), 64 x 64 tiles through LDS.

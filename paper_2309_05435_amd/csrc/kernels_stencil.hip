@@ -3,9 +3,12 @@
 // Q = Q_t (x) Q_s + D is applied as a 3-point time combination followed by
 // the 13-point spatial stencil of Q_s:
 //   (Q x)_t = Q_s (q_{t,t-1} x_{t-1} + q_{t,t} x_t + q_{t,t+1} x_{t+1}) + D_t x_t.
-// A workgroup owns a 32 x 16 spatial tile of one right-hand side and walks
-// through time, keeping the three time layers of the tile (with a halo of 2)
-// in LDS, so each x value is read from HBM once per application.
+// A workgroup owns a 32 x 16 spatial tile of one column (model, sample) and
+// walks through time, keeping the three time layers of the tile (with a halo
+// of 2) in LDS, so each x value is read from HBM once per application.
+//
+// All kernels work on column sets: a column is one sample of one model, with
+// its own length and offset, so one launch serves many uneven models.
 #include "rbmc_impl.h"
 
 namespace rbmc {
@@ -14,10 +17,6 @@ namespace {
 
 constexpr int TX = 32, TY = 16, HX = TX + 4, HY = TY + 4;
 constexpr int NTHR = 256;
-
-struct OpW {
-  int kind;  // 0: Q, 1: dlogkappa, 2: dlogtau, 3: drho, 4: dlogsigma, 5: F
-};
 
 // Weights of the time combination for output step t.
 __device__ inline void time_weights(const DevModel& m, int kind, int t, double& wm, double& w0,
@@ -43,21 +42,28 @@ __device__ inline void time_weights(const DevModel& m, int kind, int t, double& 
   if (t == m.T - 1) wp = 0.0;
 }
 
+// KIND: 0 Q, 1 dQ/dlog kappa, 2 dQ/dlog tau, 3 dQ/drho, 4 dQ/dlog sigma, 5 F.
+// Grid (max tiles, columns); DOT: partial sums of x.y per (column, tile).
 template <int KIND, bool DOT>
-__global__ __launch_bounds__(NTHR) void k_space_time_op(DevModel m, const double* __restrict__ x,
-                                                        double* __restrict__ y, int ldx,
-                                                        double* __restrict__ partial,
-                                                        int nchunk) {
+__global__ __launch_bounds__(NTHR) void k_space_time_op(ColSet cs, const double* __restrict__ x,
+                                                        double* __restrict__ y,
+                                                        double* __restrict__ partial) {
   __shared__ double slot[3][HY][HX];
   __shared__ double w[HY][HX];
   __shared__ double red[NTHR];
+  const int col = blockIdx.y;
+  const DevModel& m = cs.dms[cs.model[col]];
   const int ntx = (m.mx + TX - 1) / TX;
   const int tile = blockIdx.x;
-  const int bx = (tile % ntx) * TX, by = (tile / ntx) * TY;
-  const int k = blockIdx.y;
-  const double* xk = x + (size_t)k * ldx;
-  double* yk = y + (size_t)k * m.n;
   const int tid = threadIdx.x;
+  const bool live = tile < ntx * ((m.my + TY - 1) / TY);
+  if (!live) {
+    if (DOT && tid == 0) partial[(size_t)col * cs.max_tiles + tile] = 0.0;
+    return;
+  }
+  const int bx = (tile % ntx) * TX, by = (tile / ntx) * TY;
+  const double* xk = x + (KIND == 5 ? cs.in_off[col] : cs.off[col]);
+  double* yk = y + cs.off[col];
   const int lx = tid % TX, ly = tid / TX;  // ly in [0, 8): rows ly and ly + 8
 
   auto load_layer = [&](int buf, int t) {
@@ -125,35 +131,33 @@ __global__ __launch_bounds__(NTHR) void k_space_time_op(DevModel m, const double
       if (tid < st) red[tid] += red[tid + st];
       __syncthreads();
     }
-    if (tid == 0) partial[(size_t)k * nchunk + tile] = red[0];
+    if (tid == 0) partial[(size_t)col * cs.max_tiles + tile] = red[0];
   }
 }
 
-int n_tiles(const DevModel& m) { return ((m.mx + TX - 1) / TX) * ((m.my + TY - 1) / TY); }
-
 }  // namespace
 
-void launch_apply_op(const DevModel& m, int op, const double* x, double* y, int n_rhs,
-                     hipStream_t s) {
-  dim3 grid(n_tiles(m), n_rhs);
-  int ldx = (op == RBMC_OP_F) ? m.n + m.n_obs : m.n;
+int stencil_tiles(int mx, int my) { return ((mx + TX - 1) / TX) * ((my + TY - 1) / TY); }
+
+void launch_apply_op(const ColSet& cs, int op, const double* x, double* y, hipStream_t s) {
+  if (cs.ncols <= 0) return;
+  dim3 grid(cs.max_tiles, cs.ncols);
   switch (op) {
-    case RBMC_OP_Q: k_space_time_op<0, false><<<grid, NTHR, 0, s>>>(m, x, y, ldx, nullptr, 0); break;
-    case RBMC_OP_DQ_LOGKAPPA: k_space_time_op<1, false><<<grid, NTHR, 0, s>>>(m, x, y, ldx, nullptr, 0); break;
-    case RBMC_OP_DQ_LOGTAU: k_space_time_op<2, false><<<grid, NTHR, 0, s>>>(m, x, y, ldx, nullptr, 0); break;
-    case RBMC_OP_DQ_RHO: k_space_time_op<3, false><<<grid, NTHR, 0, s>>>(m, x, y, ldx, nullptr, 0); break;
-    case RBMC_OP_DQ_LOGSIGMA: k_space_time_op<4, false><<<grid, NTHR, 0, s>>>(m, x, y, ldx, nullptr, 0); break;
-    case RBMC_OP_F: k_space_time_op<5, false><<<grid, NTHR, 0, s>>>(m, x, y, ldx, nullptr, 0); break;
+    case RBMC_OP_Q: k_space_time_op<0, false><<<grid, NTHR, 0, s>>>(cs, x, y, nullptr); break;
+    case RBMC_OP_DQ_LOGKAPPA: k_space_time_op<1, false><<<grid, NTHR, 0, s>>>(cs, x, y, nullptr); break;
+    case RBMC_OP_DQ_LOGTAU: k_space_time_op<2, false><<<grid, NTHR, 0, s>>>(cs, x, y, nullptr); break;
+    case RBMC_OP_DQ_RHO: k_space_time_op<3, false><<<grid, NTHR, 0, s>>>(cs, x, y, nullptr); break;
+    case RBMC_OP_DQ_LOGSIGMA: k_space_time_op<4, false><<<grid, NTHR, 0, s>>>(cs, x, y, nullptr); break;
+    case RBMC_OP_F: k_space_time_op<5, false><<<grid, NTHR, 0, s>>>(cs, x, y, nullptr); break;
     default: break;
   }
 }
 
-int spmm_chunks(const DevModel& m) { return n_tiles(m); }
-
-void launch_spmm_dot(const DevModel& m, const double* p, double* q, double* partial, int n_rhs,
+void launch_spmm_dot(const ColSet& cs, const double* p, double* q, double* partial,
                      hipStream_t s) {
-  dim3 grid(n_tiles(m), n_rhs);
-  k_space_time_op<0, true><<<grid, NTHR, 0, s>>>(m, p, q, m.n, partial, n_tiles(m));
+  if (cs.ncols <= 0) return;
+  dim3 grid(cs.max_tiles, cs.ncols);
+  k_space_time_op<0, true><<<grid, NTHR, 0, s>>>(cs, p, q, partial);
 }
 
 // ---------------------------------------------------------------------------
@@ -177,18 +181,21 @@ __global__ void k_reduce_partials(const double* __restrict__ partial, int nchunk
 
 void launch_reduce_partials(const double* partial, int nchunk, int n_rhs, double* out,
                             hipStream_t s) {
-  k_reduce_partials<<<n_rhs, 256, 0, s>>>(partial, nchunk, out);
+  if (n_rhs > 0) k_reduce_partials<<<n_rhs, 256, 0, s>>>(partial, nchunk, out);
 }
 
 constexpr int kDotBlock = 256, kDotPer = 8;
 int dot_chunks(int n) { return (n + kDotBlock * kDotPer - 1) / (kDotBlock * kDotPer); }
 
-__global__ void k_dot_partials(const double* __restrict__ a, const double* __restrict__ b, int n,
-                               double* __restrict__ partial, int nchunk) {
+// grid (dot_chunks(max_len), ncols); partial[col * nchunk + chunk]
+__global__ void k_dot_partials(ColSet cs, const double* __restrict__ a,
+                               const double* __restrict__ b, double* __restrict__ partial,
+                               int nchunk) {
   __shared__ double red[kDotBlock];
-  const int k = blockIdx.y, c = blockIdx.x, tid = threadIdx.x;
-  const double* ak = a + (size_t)k * n;
-  const double* bk = b + (size_t)k * n;
+  const int col = blockIdx.y, c = blockIdx.x, tid = threadIdx.x;
+  const int n = cs.len[col];
+  const double* ak = a + cs.off[col];
+  const double* bk = b + cs.off[col];
   double acc = 0.0;
   const int base = c * kDotBlock * kDotPer;
 #pragma unroll
@@ -202,25 +209,27 @@ __global__ void k_dot_partials(const double* __restrict__ a, const double* __res
     if (tid < st) red[tid] += red[tid + st];
     __syncthreads();
   }
-  if (tid == 0) partial[(size_t)k * nchunk + c] = red[0];
+  if (tid == 0) partial[(size_t)col * nchunk + c] = red[0];
 }
 
-void launch_dot_partials(const double* a, const double* b, int n, int n_rhs, double* partial,
-                         int nchunk, hipStream_t s) {
-  dim3 grid(nchunk, n_rhs);
-  k_dot_partials<<<grid, kDotBlock, 0, s>>>(a, b, n, partial, nchunk);
+void launch_dot_partials(const ColSet& cs, const double* a, const double* b, double* partial,
+                         hipStream_t s) {
+  if (cs.ncols <= 0) return;
+  const int nch = dot_chunks(cs.max_len);
+  k_dot_partials<<<dim3(nch, cs.ncols), kDotBlock, 0, s>>>(cs, a, b, partial, nch);
 }
 
 // x += alpha p ; r -= alpha q ; partial sums of r.r   (alpha = rz / pq, 0 if inactive)
-__global__ void k_pcg_xr(const double* __restrict__ p, const double* __restrict__ q,
+__global__ void k_pcg_xr(ColSet cs, const double* __restrict__ p, const double* __restrict__ q,
                          double* __restrict__ x, double* __restrict__ r,
                          const double* __restrict__ rz, const double* __restrict__ pq,
-                         const uint8_t* __restrict__ active, int n, double* __restrict__ partial,
+                         const uint8_t* __restrict__ active, double* __restrict__ partial,
                          int nchunk) {
   __shared__ double red[kDotBlock];
   const int k = blockIdx.y, c = blockIdx.x, tid = threadIdx.x;
   const double alpha = active[k] ? rz[k] / pq[k] : 0.0;
-  const size_t off = (size_t)k * n;
+  const size_t off = cs.off[k];
+  const int n = cs.len[k];
   double acc = 0.0;
   const int base = c * kDotBlock * kDotPer;
 #pragma unroll
@@ -245,21 +254,24 @@ __global__ void k_pcg_xr(const double* __restrict__ p, const double* __restrict_
   if (tid == 0) partial[(size_t)k * nchunk + c] = red[0];
 }
 
-void launch_pcg_xr(const double* p, const double* q, double* x, double* r, const double* rz,
-                   const double* pq, const uint8_t* active, int n, int n_rhs, double* rr_partial,
-                   int nchunk, hipStream_t s) {
-  dim3 grid(nchunk, n_rhs);
-  k_pcg_xr<<<grid, kDotBlock, 0, s>>>(p, q, x, r, rz, pq, active, n, rr_partial, nchunk);
+void launch_pcg_xr(const ColSet& cs, const double* p, const double* q, double* x, double* r,
+                   const double* rz, const double* pq, const uint8_t* active,
+                   double* rr_partial, hipStream_t s) {
+  if (cs.ncols <= 0) return;
+  const int nch = dot_chunks(cs.max_len);
+  k_pcg_xr<<<dim3(nch, cs.ncols), kDotBlock, 0, s>>>(cs, p, q, x, r, rz, pq, active, rr_partial,
+                                                     nch);
 }
 
 // p = z + beta p (first iteration: p = z); beta = rz_new / rz_old; active columns only
-__global__ void k_pcg_p(const double* __restrict__ z, double* __restrict__ p,
+__global__ void k_pcg_p(ColSet cs, const double* __restrict__ z, double* __restrict__ p,
                         const double* __restrict__ rz_new, const uint8_t* __restrict__ active,
-                        const double* __restrict__ rz_old, int n, int first) {
+                        const double* __restrict__ rz_old, int first) {
   const int k = blockIdx.y;
   if (!active[k]) return;
   const double beta = first ? 0.0 : rz_new[k] / rz_old[k];
-  const size_t off = (size_t)k * n;
+  const size_t off = cs.off[k];
+  const int n = cs.len[k];
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
     p[off + i] = z[off + i] + beta * p[off + i];
 }
@@ -270,12 +282,12 @@ __global__ void k_copy_scalars(const double* __restrict__ src, double* __restric
   if (k < n_rhs && active[k]) dst[k] = src[k];
 }
 
-void launch_pcg_p(const double* z, double* p, const double* rz_new, double* rz_old,
-                  const uint8_t* active, int n, int n_rhs, int first, hipStream_t s) {
-  int bx = std::min((n + 255) / 256, 1024);
-  dim3 grid(bx, n_rhs);
-  k_pcg_p<<<grid, 256, 0, s>>>(z, p, rz_new, active, rz_old, n, first);
-  k_copy_scalars<<<(n_rhs + 255) / 256, 256, 0, s>>>(rz_new, rz_old, active, n_rhs);
+void launch_pcg_p(const ColSet& cs, const double* z, double* p, const double* rz_new,
+                  double* rz_old, const uint8_t* active, int first, hipStream_t s) {
+  if (cs.ncols <= 0) return;
+  const int bx = std::min((cs.max_len + 255) / 256, 1024);
+  k_pcg_p<<<dim3(bx, cs.ncols), 256, 0, s>>>(cs, z, p, rz_new, active, rz_old, first);
+  k_copy_scalars<<<(cs.ncols + 255) / 256, 256, 0, s>>>(rz_new, rz_old, active, cs.ncols);
 }
 
 // convergence test per column: active <- active && ||r|| > rtol ||b||; count iterations

@@ -88,33 +88,49 @@ struct DevModel {  // device views used by the stencil kernels
   const int* obs_rank;    // n: rank among observed (or -1)
 };
 
-// y = Op x for n_rhs columns (op = RBMC_OP_*); x ld = n (or n + n_obs for F)
-void launch_apply_op(const DevModel& m, int op, const double* x, double* y, int n_rhs,
-                     hipStream_t s);
-// q = Q p and partial sums of p.q per column: partial[k*nchunk + c]
-int spmm_chunks(const DevModel& m);
-void launch_spmm_dot(const DevModel& m, const double* p, double* q, double* partial, int n_rhs,
+// Column sets: the sampler works on the columns (model, sample) of one or
+// many models at once.  Column c has length len[c] (the model's n), starts at
+// off[c] in the concatenated multi-vectors, reads its operator input at
+// in_off[c] (for F the input column has n + n_obs entries) and belongs to
+// model[c] (index into the device array of DevModel).
+struct ColSet {
+  int ncols;
+  int max_len;
+  int max_tiles;             // stencil tiles of the largest model
+  const int64_t* off;
+  const int64_t* in_off;
+  const int* len;
+  const int* model;
+  const DevModel* dms;
+};
+
+int stencil_tiles(int mx, int my);
+// y = Op x per column (op = RBMC_OP_*), x at in_off, y at off
+void launch_apply_op(const ColSet& cs, int op, const double* x, double* y, hipStream_t s);
+// q = Q p per column and partial sums of p.q: partial[c * max_tiles + tile]
+void launch_spmm_dot(const ColSet& cs, const double* p, double* q, double* partial,
                      hipStream_t s);
 
 // PCG helpers (per-column scalars on the device)
 void launch_reduce_partials(const double* partial, int nchunk, int n_rhs, double* out,
                             hipStream_t s);
-void launch_dot_partials(const double* a, const double* b, int n, int n_rhs, double* partial,
-                         int nchunk, hipStream_t s);
 int dot_chunks(int n);
-void launch_pcg_xr(const double* p, const double* q, double* x, double* r, const double* rz,
-                   const double* pq, const uint8_t* active, int n, int n_rhs, double* rr_partial,
-                   int nchunk, hipStream_t s);
-void launch_pcg_p(const double* z, double* p, const double* rz_new, double* rz_old,
-                  const uint8_t* active, int n, int n_rhs, int first, hipStream_t s);
+void launch_dot_partials(const ColSet& cs, const double* a, const double* b, double* partial,
+                         hipStream_t s);
+void launch_pcg_xr(const ColSet& cs, const double* p, const double* q, double* x, double* r,
+                   const double* rz, const double* pq, const uint8_t* active,
+                   double* rr_partial, hipStream_t s);
+void launch_pcg_p(const ColSet& cs, const double* z, double* p, const double* rz_new,
+                  double* rz_old, const uint8_t* active, int first, hipStream_t s);
 void launch_pcg_check(const double* rr, const double* bb, double rtol, uint8_t* active,
                       int* it_count, int* n_active, int n_rhs, hipStream_t s);
 
 // Chain-panel kernels (dense blocks padded to np = pad_to(nb), identity pad)
 struct RegionDev {
   int nb, np;
-  const int* nodes;  // nb
-  const int* nbr;    // nb x kNS
+  const int* nodes;      // nb
+  const int* nbr;        // nb x kNS
+  const uint8_t* in_box; // nb: node lies in the core box
 };
 
 // grouped GEMM: C = alpha * op(A) * op(B) + beta * Cin  (FP64 MFMA)
@@ -176,69 +192,77 @@ struct StencilTask {
   int ncols;           // number of columns of the result (np for square, n_k for panels)
   int trans;           // op(M) = M^T
   double alpha, beta, gamma;
-  const double* dv;    // optional diagonal (length nb), added on the diagonal (square only)
+  const double* dv;    // optional diagonal (indexed by spatial node), square only
   int pad_identity;    // add 1 on padded diagonal (square only)
-  int region;          // index into region table
+  const RegionDev* rg; // device pointer
+  const double* qs;    // the model's Q_s stencil (kNS x ns)
+  int ns;
   int tile_start;
 };
 // max_np > 0: also add the sparse terms (gamma Q_R, diag(dv), pad identity)
-void launch_rstencil(const StencilTask* d_tasks, int n_tasks, int total_tiles,
-                     const RegionDev* d_regions, const double* qs, int ns, int max_np,
+void launch_rstencil(const StencilTask* d_tasks, int n_tasks, int total_tiles, int max_np,
                      hipStream_t s);
 // copy the lower triangle of each task's M (np x np) onto its upper triangle
 void launch_mirror(const InvTask* d_tasks, int n_tasks, int max_np, hipStream_t s);
 
-// Panel transfers between global multi-vectors (n x n_k) and chain panels
-// (np x n_k, ld np): mode 0 gather (pad rows zeroed), 1 scatter, 2 correction
-// right-hand side r = Q_AB x_B for the block at global time t of a chain whose
-// time range is [t0, t0 + T).
+// Panel transfers between global multi-vectors (column k of the model at
+// X + k n) and chain panels (np x n_k, ld np): mode 0 gather (pad rows
+// zeroed), 1 scatter, 2 correction right-hand side r = Q_AB x_B for the block
+// at global time t of a chain whose time range is [t0, t0 + T).
 struct PanelTask {
   double* P;
-  int region;
+  const RegionDev* rg;
+  const DevModel* dm;
+  const double* X;   // source multi-vector (modes 0, 2)
+  double* Xout;      // destination multi-vector (mode 1)
+  int n_k;
   int t;        // global time step of the block
   int t0, T;    // chain time range (mode 2)
   int mode;
   int tile_start;
 };
-void launch_panels(const PanelTask* d_tasks, int n_tasks, int total_tiles, const RegionDev* regs,
-                   const DevModel& m, const double* X, double* Xout, int n_k, hipStream_t s);
+void launch_panels(const PanelTask* d_tasks, int n_tasks, int total_tiles, hipStream_t s);
 int panel_tiles(int np, int n_k);
 
 // Deterministic part of the outputs from dense blocks of Q_AA^-1:
 //   kind 0 (diagonal block Sigma_tt): diag_out[t*ns + node] = Sigma_aa on core
-//     nodes; out[0] = sum D_a Sigma_aa, out[1] = <Sigma, Q_s>_F, out[2] = <Sigma, K>_F
-//     over core rows;
+//     nodes; sums D_a Sigma_aa, <Sigma, Q_s>_F, <Sigma, K>_F over core rows;
 //   kind 1 (off-diagonal block given as X with Sigma_off = sign * op(X)):
-//     out[1], out[2] as above.
+//     the two Frobenius products.
+// Partial sums of chunk c go to partial[(out_index + c) * 3 + j].
 struct ExtractTask {
   const double* M;
   int ld;
-  int region;
+  const RegionDev* rg;
+  const DevModel* dm;
+  double* diag_out;
+  double* partial;
+  int out_index;
   int t;          // global time of the rows
   int kind;
   int trans;
   double sign;
-  int out_slot;   // partial sums at out[(out_slot * nchunk_max + chunk) * 3 + c]
   int tile_start;
 };
-void launch_extract(const ExtractTask* d_tasks, int n_tasks, int total_tiles,
-                    const RegionDev* regs, const uint8_t* const* in_box, const DevModel& m,
-                    double* diag_out, double* partial, int nchunk_max, hipStream_t s);
+void launch_extract(const ExtractTask* d_tasks, int n_tasks, int total_tiles, hipStream_t s);
 
 // Monte Carlo part from the correction panels mu_t (np x n_k) of a chain:
 //   diag_out[t*ns + node] += (1/n_k) sum_k mu_t[a,k]^2 on core nodes;
 //   partial sums of (1/n_k) sum_k mu_t[a,k] (S mu_t')[a,k] for t' = t-1, t, t+1,
-//   S in {Q_s, K}, and of (1/n_k) sum_k D_a mu_t[a,k]^2.
+//   S in {Q_s, K}, of (1/n_k) sum_k D_a mu_t[a,k]^2 and of m_a / s2_a.
+// Partial sums of chunk c go to partial[(out_index + c) * 8 + j].
 struct McTask {
   const double* mu[3];  // panels for t-1, t, t+1 (null if outside the chain)
   int np;
-  int region;
+  const RegionDev* rg;
+  const DevModel* dm;
+  double* diag_out;
+  double* partial;
+  int out_index;
+  int n_k;
   int t;
-  int out_slot;         // out[(out_slot * nchunk_max + chunk) * 7 + c]
   int tile_start;
 };
-void launch_mc(const McTask* d_tasks, int n_tasks, int total_tiles, const RegionDev* regs,
-               const uint8_t* const* in_box, const DevModel& m, int n_k, double* diag_out,
-               double* partial, int nchunk_max, hipStream_t s);
+void launch_mc(const McTask* d_tasks, int n_tasks, int total_tiles, hipStream_t s);
 
 }  // namespace rbmc

@@ -52,15 +52,22 @@ def test_estimator_sampled_entries_full_size(setup):
     assert abs(tr[3] + 2.0 * s2) < 1e-10 * s2
 
 
-def test_sampler_residuals_full_size(setup):
+@pytest.mark.parametrize("pc,it_lo,it_hi", [("workload", 1, 3), (None, 50, 200)])
+def test_sampler_residuals_full_size(setup, pc, it_lo, it_hi):
+    """The timed configuration uses one block-Jacobi block per time chain (an
+    exact preconditioner: one or two iterations); the core-shaped blocks take
+    tens of iterations.  Both must reach the tolerance."""
     wl, gm, M, lab = setup
+    sm = gm if pc == "workload" else B.Model(wl, pc=pc)
     z = normals((24, gm.n + gm.n_obs), 78)
-    print("fullsize: sample", flush=True)
-    x, st, rep = gm.sample(torch.from_numpy(z).cuda(), rtol=wl.rtol)
+    print(f"fullsize: sample pc={pc}", flush=True)
+    x, st, rep = sm.sample(torch.from_numpy(z).cuda(), rtol=wl.rtol)
+    if sm is not gm:
+        sm.close()
     assert st == B.RBMC_OK
     x = x.cpu().numpy()
     b = M.rhs(z)
     res = np.linalg.norm(M.apply(O.Q, x) - b, axis=1) / np.linalg.norm(b, axis=1)
     print(f"fullsize: pcg iters max {rep.pcg_it_max} max residual {res.max():.3e}", flush=True)
     assert res.max() <= 1.05 * wl.rtol
-    assert 50 <= rep.pcg_it_max <= 200
+    assert it_lo <= rep.pcg_it_max <= it_hi
