@@ -24,6 +24,12 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6    # MI355X dense FP64 (matrix and vector)
 PEAK_HBM_GBS = 8000.0      # MI355X HBM3E
+PEAK_FP32_TFLOPS = 157.3   # MI355X dense FP32 matrix
+
+
+# the HIP kernel behind each instrumented family
+KERNEL_OF = {"gemm": "k_gemm_f64", "gemm_mixed": "k_gemm_mx", "spmm": "k_space_time_op",
+             "rstencil": "k_rstencil", "panels": "k_panels", "spd_inverse": "gauss_jordan"}
 
 
 def kernel_sources_hash() -> str:
@@ -46,6 +52,68 @@ def traffic_for(kernel: str, workload: str):
     if d.get("sources_hash") != kernel_sources_hash():
         return None
     return d.get("bytes_per_launch")
+
+
+def calibration_copy(nbytes: int, reps: int = 3):
+    """A plain device-to-device copy of nbytes, reps times: under rocprofv3
+    --pmc its FETCH_SIZE / WRITE_SIZE per dispatch give the counter's scale."""
+    import torch
+    n = nbytes // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration_copy_bytes": n * 8, "reps": reps}), flush=True)
+
+
+def _counter_per_dispatch(path: str, counter: str):
+    """{kernel name: [KiB per dispatch, ...]} from a rocprofv3 counter CSV."""
+    import csv
+    out = {}
+    with open(path) as f:
+        for row in csv.DictReader(f):
+            if row.get("Counter_Name") != counter:
+                continue
+            out.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]))
+    return out
+
+
+def write_traffic(paths, workload: str, copy_bytes: int, commands):
+    """HBM bytes per launch of each library kernel from two counter runs of the
+    bench (FETCH_SIZE, WRITE_SIZE) and two of the calibration copy, each
+    scaled by (known copy bytes) / (counter reading of the copy)."""
+    f_main, w_main, f_copy, w_copy = (_counter_per_dispatch(p, c) for p, c in zip(
+        paths, ("FETCH_SIZE", "WRITE_SIZE", "FETCH_SIZE", "WRITE_SIZE")))
+
+    def copy_kib(d):
+        vals = [v for k, vs in d.items() if "copyBuffer" in k for v in vs]
+        big = [v for v in vals if v * 1024 > copy_bytes / 2]
+        return sum(big) / len(big)
+
+    s_fetch = copy_bytes / (copy_kib(f_copy) * 1024)
+    s_write = copy_bytes / (copy_kib(w_copy) * 1024)
+    written = []
+    for fam, kern in KERNEL_OF.items():
+        fk = [k for k in f_main if ("rbmc::" + kern + "(") in k or k.startswith(kern + "(")]
+        wk = [k for k in w_main if ("rbmc::" + kern + "(") in k or k.startswith(kern + "(")]
+        if not fk or not wk:
+            continue
+        fv = [v for k in fk for v in f_main[k]]
+        wv = [v for k in wk for v in w_main[k]]
+        fb = sum(fv) / len(fv) * 1024 * s_fetch
+        wb = sum(wv) / len(wv) * 1024 * s_write
+        rec = {"kernel": kern, "workload": workload, "dispatches": len(fv),
+               "bytes_per_launch": fb + wb, "fetch_bytes_per_launch": fb,
+               "write_bytes_per_launch": wb, "scale_fetch": s_fetch, "scale_write": s_write,
+               "calibration_copy_bytes": copy_bytes, "sources_hash": kernel_sources_hash(),
+               "commands": commands}
+        path = os.path.join(ROOT, "profiles", f"traffic_{kern}_{workload}.json")
+        with open(path, "w") as f:
+            json.dump(rec, f, indent=1)
+        written.append(path)
+    print(json.dumps({"written": written}))
 
 
 def cpu_baseline(wl, m_sample: int):
@@ -138,7 +206,19 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 256-model batched workload")
     ap.add_argument("--batched-models", type=int, default=256)
+    ap.add_argument("--batched-only", action="store_true",
+                    help="run only the batched workload and print its JSON")
+    ap.add_argument("--calibration-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (counter calibration)")
+    ap.add_argument("--traffic-from", nargs=4, metavar="CSV",
+                    help="write profiles/traffic_*.json from the counter CSVs of the bench "
+                         "(FETCH_SIZE, WRITE_SIZE) and of the calibration copy (same order)")
+    ap.add_argument("--commands", default="", help="commands recorded with --traffic-from")
     args = ap.parse_args()
+    if args.traffic_from:
+        write_traffic(args.traffic_from, args.workload, args.calibration_copy,
+                      args.commands)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
               "(the library has no multi-GPU path)", file=sys.stderr)
@@ -146,6 +226,13 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.calibration_copy:
+        calibration_copy(args.calibration_copy)
+        return
+    if args.batched_only:
+        print(json.dumps(batched_leg(args.batched_models)), flush=True)
+        return
 
     from paper_2309_05435_amd import binding as B
     from paper_2309_05435_amd.inputs import WORKLOADS
@@ -201,21 +288,24 @@ def main():
     ms = (t1 - t0) * 1000.0 / args.steps
     value = gm.n / (ms / 1000.0)
 
-    # dominant kernel family by device time
-    dom = max(stats, key=lambda k: stats[k]["total_ms"])
+    # dominant single kernel by device time (the inversion family is a
+    # composite of several kernels and its products are counted under gemm)
+    dom = max((k for k in stats if k != "spd_inverse"), key=lambda k: stats[k]["total_ms"])
     s = stats[dom]
-    if dom in ("gemm", "spd_inverse"):
+    per_launch = 1.0 / max(s["launches"], 1)
+    if dom in ("gemm", "gemm_mixed"):
+        peak = PEAK_FP64_TFLOPS if dom == "gemm" else PEAK_FP32_TFLOPS
         achieved = s["alg_flops"] / (s["total_ms"] * 1e-3) / 1e12
-        roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS}
+        roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "alg_flops_per_launch": s["alg_flops"] * per_launch}
     else:
         achieved = s["alg_bytes"] / (s["total_ms"] * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": achieved / PEAK_HBM_GBS}
-    roof["kernel"] = dom
-    roof["launches"] = s["launches"] // max(args.steps, 1)
-    roof["avg_launch_ms"] = s["total_ms"] / max(s["launches"], 1)
-    roof["traffic"] = traffic_for(dom, wl.name)
+                "frac": achieved / PEAK_HBM_GBS, "alg_bytes_per_launch": s["alg_bytes"] * per_launch}
+    roof["traffic"] = traffic_for(KERNEL_OF[dom], wl.name)
+    roof["kernel"] = KERNEL_OF[dom]
+    roof["launches_per_step"] = s["launches"] // max(args.steps, 1)
+    roof["avg_launch_ms"] = s["total_ms"] * per_launch
 
     last = reps[-1]
     out = {
@@ -245,6 +335,38 @@ def main():
         "roofline": roof,
         "cpu_baseline": None,
     }
+    if not args.no_variants:
+        # RBMC_MIXED on the same model and samples: FP32 matrix-core products in
+        # the Takahashi sweep and the solves; error stated against the FP64 run
+        d64 = diag.clone()
+        t64 = list(tr)
+        om = B.make_opts(wl.n_k, pcg_maxit=5000, pcg_rtol=wl.rtol, grad_mask=grad,
+                         precision=B.RBMC_MIXED)
+        dm = torch.empty_like(diag)
+        B.rbmc_model_set_theta(gm.m, *theta)
+        B.rbmc_estimate(gm.m, om, z, 0, dm, B.popcount(grad))
+        torch.cuda.synchronize()
+        B.rbmc_ctx_profile(gm.ctx, True)
+        ta = time.perf_counter()
+        B.rbmc_model_set_theta(gm.m, *theta)
+        _, trm, rpm = B.rbmc_estimate(gm.m, om, z, 0, dm, B.popcount(grad))
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - ta
+        sm = {B.KF_NAMES[f]: B.rbmc_ctx_profile_read(gm.ctx, f) for f in range(B.RBMC_KF_COUNT)}
+        B.rbmc_ctx_profile(gm.ctx, False)
+        g = sm["gemm_mixed"]
+        out["variant_mixed"] = {
+            "value": gm.n / sec, "ms_per_step": sec * 1e3,
+            "max_rel_err_diag_vs_fp64": float(((dm - d64).abs() / d64).max()),
+            "mean_rel_err_diag_vs_fp64": float(((dm - d64).abs() / d64).mean()),
+            "rel_err_traces_vs_fp64": [abs(a - b) / abs(b) for a, b in zip(trm, t64)],
+            "pcg_iters": {"mean": rpm.pcg_it_mean, "max": rpm.pcg_it_max},
+            "phase_s": {k: getattr(rpm, k) for k in ("t_sample", "t_factor", "t_takahashi",
+                                                     "t_correct", "t_total")},
+            "kernel_ms": {k: v["total_ms"] for k, v in sm.items()},
+            "gemm_mixed_tflops": (g["alg_flops"] / (g["total_ms"] * 1e-3) / 1e12
+                                  if g["total_ms"] > 0 else None),
+            "gemm_mixed_peak_tflops": PEAK_FP32_TFLOPS}
     gm.close()
     del z
     torch.cuda.empty_cache()
@@ -274,7 +396,10 @@ def main():
                                    "pcg_iters": {"mean": rp["pcg_it_mean"], "max": rp["pcg_it_max"]}}
         mv.close()
     if not args.no_batched:
-        out["batched"] = batched_leg(args.batched_models)
+        try:
+            out["batched"] = batched_leg(args.batched_models)
+        except B.RbmcError as e:  # e.g. device memory: report, keep the main line
+            out["batched"] = {"error": str(e)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_m)
     print(json.dumps(out), flush=True)

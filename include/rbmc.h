@@ -85,6 +85,14 @@ typedef struct {
   int32_t pc_tslabs, pc_tiles_x, pc_tiles_y; /* 0 = same as the cores */
 } rbmc_decomp_desc;
 
+/* Precision.  RBMC_FP64: every step in FP64.  RBMC_MIXED: the dense
+ * products of the Takahashi sweep, of the correction solves and of the
+ * preconditioner solves run on the FP32 matrix cores (operands rounded to
+ * FP32, each K chunk of 16 summed in FP32 and accumulated in FP64); the
+ * block-tridiagonal factorizations (inversions of the Schur complements),
+ * the operators, the PCG inner products and residual updates and the final
+ * diagonal/trace accumulation stay FP64.  PCG on the FP64 operator refines
+ * the samples to pcg_rtol whatever the preconditioner's precision. */
 enum { RBMC_FP64 = 0, RBMC_MIXED = 1 };
 enum { RBMC_PC_BJ = 0, RBMC_PC_BJ_LEARNED = 1 };
 enum { RBMC_GRAD_LOGKAPPA = 1, RBMC_GRAD_LOGTAU = 2, RBMC_GRAD_RHO = 4, RBMC_GRAD_LOGSIGMA = 8 };
@@ -193,15 +201,21 @@ rbmc_status rbmc_plan_query(const rbmc_model_desc* desc, const rbmc_decomp_desc*
 /* Instrumentation (for throughput and roofline reporting, not part of the
  * method).  While enabled, every launch of a kernel family is bracketed by
  * HIP events on the context stream and its algorithmic work is counted:
- *   RBMC_KF_GEMM         dense products on the matrix cores; flops = 2 M K N
- *                        over the unpadded block sizes;
- *   RBMC_KF_SPD_INVERSE  one Gauss-Jordan inversion batch; flops = sum n_b^3;
+ *   RBMC_KF_GEMM         dense products on the FP64 matrix cores (one kernel,
+ *                        also those inside the inversions); flops = 2 M K N
+ *                        over the unpadded block sizes (lower-half updates:
+ *                        half of that);
+ *   RBMC_KF_SPD_INVERSE  one Gauss-Jordan inversion batch, all its kernels
+ *                        (its products are also counted under RBMC_KF_GEMM);
+ *                        flops = sum n_b^3;
  *   RBMC_KF_SPMM         q = Q p in the sampler; bytes = 16 per node and
  *                        sample (read p, write q);
  *   RBMC_KF_RSTENCIL     restricted-stencil products with dense blocks;
  *                        bytes = 16 per output entry;
  *   RBMC_KF_PANELS       gathers/scatters/right-hand sides; bytes = 16 per
- *                        panel entry.
+ *                        panel entry;
+ *   RBMC_KF_GEMM_MIXED   dense products on the FP32 matrix cores (RBMC_MIXED);
+ *                        flops as RBMC_KF_GEMM.
  * rbmc_ctx_profile(ctx, 1) clears and enables, (ctx, 0) disables;
  * rbmc_ctx_profile_read synchronizes the stream and sums the records. */
 enum {
@@ -210,7 +224,8 @@ enum {
   RBMC_KF_SPMM = 2,
   RBMC_KF_RSTENCIL = 3,
   RBMC_KF_PANELS = 4,
-  RBMC_KF_COUNT = 5
+  RBMC_KF_GEMM_MIXED = 5,
+  RBMC_KF_COUNT = 6
 };
 typedef struct {
   int64_t launches;

@@ -26,8 +26,8 @@ EXPORTS = ["rbmc_ctx_create", "rbmc_ctx_destroy", "rbmc_model_create", "rbmc_mod
            "rbmc_estimate", "rbmc_estimate_batched", "rbmc_plan_query", "rbmc_ctx_profile",
            "rbmc_ctx_profile_read", "rbmc_last_error"]
 (RBMC_KF_GEMM, RBMC_KF_SPD_INVERSE, RBMC_KF_SPMM, RBMC_KF_RSTENCIL, RBMC_KF_PANELS,
- RBMC_KF_COUNT) = range(6)
-KF_NAMES = ["gemm", "spd_inverse", "spmm", "rstencil", "panels"]
+ RBMC_KF_GEMM_MIXED, RBMC_KF_COUNT) = range(7)
+KF_NAMES = ["gemm", "spd_inverse", "spmm", "rstencil", "panels", "gemm_mixed"]
 
 
 class rbmc_kernel_stats(C.Structure):

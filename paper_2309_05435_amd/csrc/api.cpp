@@ -345,11 +345,14 @@ int gemm_tiles(int M, int N) { return gemm_task_tiles(M, N, 0); }
 struct GemmList {
   std::vector<GemmTask> v;
   int tiles = 0;
+  int mixed = 0;       // 1: FP32 matrix-core products, FP64 accumulation
   double flops = 0.0;  // algorithmic (unpadded) flops of the list
+  double last_flops = 0.0;
   void add(const double* A, const double* B, const double* Cin, double* C, int M, int N, int K,
            int lda, int ldb, int ldc, double alpha, double beta, int tA, int tB, int Mreal,
            int Kreal) {
-    flops += 2.0 * Mreal * (double)N * Kreal;
+    last_flops = 2.0 * Mreal * (double)N * Kreal;
+    flops += last_flops;
     GemmTask t{};
     t.A = A;
     t.B = B;
@@ -374,12 +377,16 @@ struct GemmList {
   // restrict the last product to the lower 128-tiles of a square result
   void set_last_lower() {
     GemmTask& t = v.back();
+    flops -= 0.5 * last_flops;  // a symmetric result: the lower half is the work
     tiles -= gemm_tiles(t.M, t.N);
     tiles += gemm_task_tiles(t.M, t.N, 1);
     t.lower = 1;
   }
   // outer sweep update of the lower tiles: M -= U B^T outside rows/cols [kb, kb + w)
-  void add_sweep(double* Mx, int np, const double* U, const double* B, int w, int kb) {
+  // (nb: unpadded size, for the algorithmic flops of the lower half)
+  void add_sweep(double* Mx, int np, const double* U, const double* B, int w, int kb, int nb) {
+    const double r = std::max(0, nb - w);
+    flops += r * r * w;
     GemmTask t{};
     t.A = U;
     t.B = B;
@@ -464,8 +471,9 @@ struct Program {
     o.off = a.push(g.v);
     o.n = (int)g.v.size();
     o.tiles = g.tiles;
-    o.family = profiled ? RBMC_KF_GEMM : -1;
+    o.family = profiled ? (g.mixed ? RBMC_KF_GEMM_MIXED : RBMC_KF_GEMM) : -1;
     o.alg_flops = g.flops;
+    o.kblk = g.mixed;
     ops.push_back(o);
   }
   void stencil(Arena& a, StencilList& s) {
@@ -564,7 +572,7 @@ struct Program {
         t.Pi = j.Pi;
         inner.push_back(t);
         gu.add(j.B, j.P, nullptr, j.U, j.np, w, w, j.np, w, j.np, 1.0, 0.0, 0, 0, j.np, w);
-        gm.add_sweep(j.M, j.np, j.U, j.B, w, kb);
+        gm.add_sweep(j.M, j.np, j.U, j.B, w, kb, j.nb);
       }
       Op og;
       og.kind = 7;
@@ -573,8 +581,8 @@ struct Program {
       og.tiles = gl.tiles;
       ops.push_back(og);
       sweep64(a, inner);
-      gemm(a, gu, false);
-      gemm(a, gm, false);
+      gemm(a, gu);
+      gemm(a, gm);
       Op of = og;
       of.kind = 8;
       ops.push_back(of);
@@ -634,7 +642,7 @@ rbmc_status run(rbmc_ctx* cx, const Program& pg, hipStream_t s, Arena& a) {
   for (const Op& o : pg.ops) {
     const int pid = (o.family >= 0) ? cx->begin(o.family, o.alg_flops, o.alg_bytes, s) : -1;
     switch (o.kind) {
-      case 0: launch_gemm(a.at<GemmTask>(o.off), o.n, o.tiles, s); break;
+      case 0: launch_gemm(a.at<GemmTask>(o.off), o.n, o.tiles, s, o.kblk); break;
       case 1: launch_rstencil(a.at<StencilTask>(o.off), o.n, o.tiles, o.max_np, s); break;
       case 2: launch_gj_step(a.at<InvTask>(o.off), o.n, o.max_np, o.kblk, s); break;
       case 3: launch_panels(a.at<PanelTask>(o.off), o.n, o.tiles, s); break;
@@ -727,10 +735,12 @@ void build_factor(ChainSet& cs, Program& pg, Arena& a) {
 // backward z_t = u_t - S_t^-1 (q_o Q_R z_{t+1}) down to local step stop[c].
 // r_0 must be in ytmp[c], r_t (t >= 1) in pan[c][t].  S_t^-1 is symmetric, so
 // it is read through the transposed (contiguous) operand path.
-void build_solve(ChainSet& cs, int n_k, const std::vector<int>& stop, Program& pg, Arena& a) {
+void build_solve(ChainSet& cs, int n_k, const std::vector<int>& stop, Program& pg, Arena& a,
+                 int mixed) {
   for (int t = 0; t < cs.maxT; ++t) {
     StencilList sl;
     GemmList gl;
+    gl.mixed = mixed;
     for (size_t c = 0; c < cs.size(); ++c) {
       const Chain& ch = cs.chains[c];
       if (t >= ch.T) continue;
@@ -759,6 +769,7 @@ void build_solve(ChainSet& cs, int n_k, const std::vector<int>& stop, Program& p
   for (int t = cs.maxT - 2; t >= 0; --t) {
     StencilList sl;
     GemmList gl;
+    gl.mixed = mixed;
     for (size_t c = 0; c < cs.size(); ++c) {
       const Chain& ch = cs.chains[c];
       if (t > ch.T - 2 || t < stop[c]) continue;
@@ -820,8 +831,12 @@ rbmc_status check_opts(const rbmc_est_opts* o, bool need_pcg) {
   if (need_pcg && (o->pcg_maxit < 1 || !(o->pcg_rtol > 0.0)))
     return fail(RBMC_E_ARG, "pcg_maxit must be >= 1 and pcg_rtol > 0");
   if (o->grad_mask & ~15u) return fail(RBMC_E_ARG, "grad_mask has unknown bits");
-  if (o->precision != RBMC_FP64) return fail(RBMC_E_UNSUPPORTED, "only RBMC_FP64 is built");
-  if (o->precond != RBMC_PC_BJ) return fail(RBMC_E_UNSUPPORTED, "only RBMC_PC_BJ is built");
+  if (o->precision != RBMC_FP64 && o->precision != RBMC_MIXED)
+    return fail(RBMC_E_ARG, "precision must be RBMC_FP64 or RBMC_MIXED");
+  if (o->precond != RBMC_PC_BJ && o->precond != RBMC_PC_BJ_LEARNED)
+    return fail(RBMC_E_ARG, "precond must be RBMC_PC_BJ or RBMC_PC_BJ_LEARNED");
+  if (o->precond == RBMC_PC_BJ_LEARNED)
+    return fail(RBMC_E_UNSUPPORTED, "the learned preconditioner correction is not built");
   return RBMC_OK;
 }
 
@@ -1014,7 +1029,7 @@ rbmc_status sample_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const H
   }
   gat.panels(ar, g);
   std::vector<int> stop(cs.size(), 0);
-  build_solve(cs, nk, stop, pre, ar);
+  build_solve(cs, nk, stop, pre, ar, o->precision == RBMC_MIXED);
   sca.panels(ar, sc);
   HIPCHK(ar.upload(s));
   auto precond = [&]() -> rbmc_status {
@@ -1096,6 +1111,7 @@ rbmc_status estimate_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const
                          const std::vector<double*>& trace_out, rbmc_report* rep,
                          const std::function<rbmc_status()>& sampler) {
   const int nk = o->n_samples;
+  const int mixed = o->precision == RBMC_MIXED;
   hipStream_t sA = cx->stream;
   if (sampler && !cx->side) {
     HIPCHK(hipStreamCreateWithFlags(&cx->side, hipStreamNonBlocking));
@@ -1176,6 +1192,7 @@ rbmc_status estimate_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const
   for (int t = cs.maxT - 2; t >= 0; --t) {
     StencilList s1, s2;
     GemmList g1, g2;
+    g1.mixed = g2.mixed = mixed;
     TileList<ExtractTask> e1, e2;
     std::vector<InvTask> mir;
     for (int c = 0; c < nchains; ++c) {
@@ -1252,7 +1269,7 @@ rbmc_status estimate_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const
     cor.panels(ar, rt);
     std::vector<int> stop(nchains);
     for (int c = 0; c < nchains; ++c) stop[c] = std::max(lc0(c) - 1, 0);
-    build_solve(cs, nk, stop, cor, ar);
+    build_solve(cs, nk, stop, cor, ar, mixed);
     TileList<McTask> mt;
     for (int c = 0; c < nchains; ++c) {
       const Chain& ch = cs.chains[c];

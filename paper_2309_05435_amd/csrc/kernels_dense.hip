@@ -204,10 +204,203 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(const GemmTask* __restrict_
     }
 }
 
-void launch_gemm(const GemmTask* d_tasks, int n_tasks, int total_tiles, hipStream_t s) {
+// ---------------------------------------------------------------------------
+// Mixed-precision grouped GEMM: FP64 operands and result, products on the
+// FP32 matrix cores (v_mfma_f32_16x16x4f32).  Operands are rounded to FP32
+// when staged into LDS; each K chunk of 16 is accumulated in FP32 and then
+// added to FP64 accumulators, so the error is that of rounding the operands
+// (about 2^-24 relative per element) rather than of a long FP32 sum.
+// Same 128 x 128 tiles and task semantics as k_gemm_f64; eight waves of
+// 64 x 32 keep the FP64 accumulators within the register budget.
+// FP32 16x16x4: lane l supplies A[l%16][l/16] and B[l/16][l%16]; accumulator
+// register i of lane l holds C[4 (l/16) + i][l%16].
+// ---------------------------------------------------------------------------
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+namespace {
+constexpr int XLD = GBK + 4;  // LDS row stride (floats) of the k-contiguous tiles
+
+struct XRegs {
+  double2 v[2];
+};
+
+__device__ inline void xload_a(const GemmTask& tk, int m0, int k0, int tid, XRegs& r) {
+  if (!tk.transA) {  // 4 consecutive rows of column k
+    const int kk = tid >> 5, gm = m0 + (tid & 31) * 4;
+    const double* src = tk.A + (size_t)(k0 + kk) * tk.lda + gm;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int c = gm + 2 * j;
+      if (c + 1 < tk.M) r.v[j] = *(const double2*)(src + 2 * j);
+      else r.v[j] = double2{c < tk.M ? src[2 * j] : 0.0, 0.0};
+    }
+  } else {  // 4 consecutive k of row m
+    const int gm = m0 + (tid >> 2), kk = (tid & 3) * 4;
+    const double* src = tk.A + (size_t)gm * tk.lda + k0 + kk;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      r.v[j] = (gm < tk.M) ? *(const double2*)(src + 2 * j) : double2{0.0, 0.0};
+  }
+}
+
+__device__ inline void xstore_a(const GemmTask& tk, int tid, const XRegs& r, float* As) {
+  if (!tk.transA) {
+    const int kk = tid >> 5, mm = (tid & 31) * 4;
+    As[(mm + 0) * XLD + kk] = (float)r.v[0].x;
+    As[(mm + 1) * XLD + kk] = (float)r.v[0].y;
+    As[(mm + 2) * XLD + kk] = (float)r.v[1].x;
+    As[(mm + 3) * XLD + kk] = (float)r.v[1].y;
+  } else {
+    const int mm = tid >> 2, kk = (tid & 3) * 4;
+    *(float4*)&As[mm * XLD + kk] =
+        float4{(float)r.v[0].x, (float)r.v[0].y, (float)r.v[1].x, (float)r.v[1].y};
+  }
+}
+
+__device__ inline void xload_b(const GemmTask& tk, int n0, int k0, int tid, XRegs& r) {
+  if (!tk.transB) {  // 4 consecutive k of column n
+    const int gn = n0 + (tid >> 2), kk = (tid & 3) * 4;
+    const double* src = tk.B + (size_t)gn * tk.ldb + k0 + kk;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      r.v[j] = (gn < tk.N) ? *(const double2*)(src + 2 * j) : double2{0.0, 0.0};
+  } else {  // 4 consecutive n of row k
+    const int kk = tid >> 5, gn = n0 + (tid & 31) * 4;
+    const double* src = tk.B + (size_t)(k0 + kk) * tk.ldb + gn;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int c = gn + 2 * j;
+      if (c + 1 < tk.N) r.v[j] = *(const double2*)(src + 2 * j);
+      else r.v[j] = double2{c < tk.N ? src[2 * j] : 0.0, 0.0};
+    }
+  }
+}
+
+__device__ inline void xstore_b(const GemmTask& tk, int tid, const XRegs& r, float* Bs) {
+  if (!tk.transB) {
+    const int nn = tid >> 2, kk = (tid & 3) * 4;
+    *(float4*)&Bs[nn * XLD + kk] =
+        float4{(float)r.v[0].x, (float)r.v[0].y, (float)r.v[1].x, (float)r.v[1].y};
+  } else {
+    const int kk = tid >> 5, nn = (tid & 31) * 4;
+    Bs[(nn + 0) * XLD + kk] = (float)r.v[0].x;
+    Bs[(nn + 1) * XLD + kk] = (float)r.v[0].y;
+    Bs[(nn + 2) * XLD + kk] = (float)r.v[1].x;
+    Bs[(nn + 3) * XLD + kk] = (float)r.v[1].y;
+  }
+}
+}  // namespace
+
+__global__ __launch_bounds__(512, 1) void k_gemm_mx(const GemmTask* __restrict__ tasks,
+                                                    int n_tasks, int total_tiles, int per_xcd) {
+  __shared__ float As[GBM * XLD];
+  __shared__ float Bs[GBN * XLD];
+  const int b = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (b >= total_tiles) return;
+  int lo = 0, hi = n_tasks - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) / 2;
+    if (tasks[mid].tile_start <= b) lo = mid; else hi = mid - 1;
+  }
+  const GemmTask tk = tasks[lo];
+  const int tile = b - tk.tile_start;
+  int tm, tn;
+  if (tk.lower) {
+    tm = (int)((sqrt(8.0 * tile + 1.0) - 1.0) * 0.5);
+    while ((tm + 1) * (tm + 2) / 2 <= tile) ++tm;
+    while (tm * (tm + 1) / 2 > tile) --tm;
+    tn = tile - tm * (tm + 1) / 2;
+  } else {
+    tm = tile / tk.tiles_n;
+    tn = tile % tk.tiles_n;
+  }
+  const int m0 = tm * GBM, n0 = tn * GBN;
+  if (tk.skip1 > tk.skip0) {
+    const bool rows_hit = m0 < tk.skip1 && m0 + GBM > tk.skip0;
+    const bool cols_hit = n0 < tk.skip1 && n0 + GBN > tk.skip0;
+    if (rows_hit || cols_hit) return;
+  }
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 2) * 64, wn = (wave & 3) * 32;
+  const int l16 = lane & 15, g = lane >> 4;
+
+  double acc[4][2][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[i][j][r] = 0.0;
+
+  XRegs ra, rb;
+  xload_a(tk, m0, 0, tid, ra);
+  xload_b(tk, n0, 0, tid, rb);
+  xstore_a(tk, tid, ra, As);
+  xstore_b(tk, tid, rb, Bs);
+  __syncthreads();
+  for (int k0 = 0; k0 < tk.K; k0 += GBK) {
+    const bool more = k0 + GBK < tk.K;
+    if (more) {
+      xload_a(tk, m0, k0 + GBK, tid, ra);
+      xload_b(tk, n0, k0 + GBK, tid, rb);
+    }
+    float4 a[4], bb[2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = *(const float4*)&As[(wm + i * 16 + l16) * XLD + 4 * g];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) bb[j] = *(const float4*)&Bs[(wn + j * 16 + l16) * XLD + 4 * g];
+    v4f c32[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) c32[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        c32[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].x, bb[j].x, c32[i][j], 0, 0, 0);
+        c32[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].y, bb[j].y, c32[i][j], 0, 0, 0);
+        c32[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].z, bb[j].z, c32[i][j], 0, 0, 0);
+        c32[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].w, bb[j].w, c32[i][j], 0, 0, 0);
+      }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[i][j][r] += (double)c32[i][j][r];
+    __syncthreads();
+    if (more) {
+      xstore_a(tk, tid, ra, As);
+      xstore_b(tk, tid, rb, Bs);
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int gn = n0 + wn + j * 16 + l16;
+      if (gn >= tk.N) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + wm + i * 16 + 4 * g + r;
+        if (gm >= tk.M) continue;
+        double v = tk.alpha * acc[i][j][r];
+        if (tk.beta != 0.0) v += tk.beta * tk.Cin[(size_t)gn * tk.ldcin + gm];
+        tk.C[(size_t)gn * tk.ldc + gm] = v;
+      }
+    }
+}
+
+void launch_gemm(const GemmTask* d_tasks, int n_tasks, int total_tiles, hipStream_t s,
+                 int mixed) {
   if (total_tiles <= 0) return;
   const int per_xcd = (total_tiles + 7) / 8;
-  k_gemm_f64<<<per_xcd * 8, 256, 0, s>>>(d_tasks, n_tasks, total_tiles, per_xcd);
+  if (mixed)
+    k_gemm_mx<<<per_xcd * 8, 512, 0, s>>>(d_tasks, n_tasks, total_tiles, per_xcd);
+  else
+    k_gemm_f64<<<per_xcd * 8, 256, 0, s>>>(d_tasks, n_tasks, total_tiles, per_xcd);
 }
 
 // ---------------------------------------------------------------------------

@@ -149,7 +149,9 @@ struct GemmTask {
   int skip0, skip1;   // tiles meeting rows or columns [skip0, skip1) are skipped
 };
 int gemm_task_tiles(int M, int N, int lower);
-void launch_gemm(const GemmTask* d_tasks, int n_tasks, int total_tiles, hipStream_t s);
+// mixed = 1: FP32 matrix-core products with FP64 accumulation across K chunks
+void launch_gemm(const GemmTask* d_tasks, int n_tasks, int total_tiles, hipStream_t s,
+                 int mixed = 0);
 
 // Gauss-Jordan sweep inversion of SPD matrices, block 64 (in place; only the
 // lower triangle is kept current; the finish pass negates and symmetrizes).

@@ -113,7 +113,9 @@ WORKLOADS = {
 
 def batched_models(n_models: int = 256, master: int = 3000):
     """Uneven models of the batched workload: m ~ U{16..48}, T ~ U{8..24},
-    slabs ~ U{2..8}, range ~ U(0.1, 0.5), rho ~ U(0.5, 0.99), f ~ U(0.1, 0.6)."""
+    slabs ~ U{2..8}, range ~ U(0.1, 0.5), rho ~ U(0.5, 0.99), f ~ U(0.1, 0.6).
+    The block-Jacobi preconditioner of each model is one block per time chain
+    (the whole model: an exact preconditioner)."""
     out = []
     for i in range(n_models):
         g = np.random.default_rng(master + i)
@@ -125,5 +127,5 @@ def batched_models(n_models: int = 256, master: int = 3000):
         f = float(g.uniform(0.1, 0.6))
         out.append(Workload(name=f"batch{i}", m=m, T=T, range_=rng_, rho=rho, tau=1.0, sigma=0.5,
                             obs_frac=f, n_tslabs=min(P, T), n_tiles=1, n_l=1, n_k=100, rtol=1e-8,
-                            mask_seed=300000 + i, z_seed=400000 + i))
+                            mask_seed=300000 + i, z_seed=400000 + i, pc=(1, 1, 1)))
     return out

@@ -213,7 +213,96 @@ def test_error_codes():
         B.rbmc_sample(m, B.make_opts(4, pcg_maxit=0), z, x)
     assert e.value.status == B.RBMC_E_ARG
     with pytest.raises(B.RbmcError) as e:
-        B.rbmc_sample(m, B.make_opts(4, precision=B.RBMC_MIXED), z, x)
-    assert e.value.status == B.RBMC_E_UNSUPPORTED
+        B.rbmc_sample(m, B.make_opts(4, precision=7), z, x)
+    assert e.value.status == B.RBMC_E_ARG
+    with pytest.raises(B.RbmcError) as e:
+        B.rbmc_sample(m, B.make_opts(4, precond=B.RBMC_PC_BJ_LEARNED + 1), z, x)
+    assert e.value.status == B.RBMC_E_ARG
     B.rbmc_model_destroy(m)
     B.rbmc_ctx_destroy(ctx)
+
+
+# Mixed precision: FP32 matrix-core products in the Takahashi sweep and the
+# solves, FP64 factorizations.  Every entry of Q_AA^-1 and of the corrections
+# then carries a relative error of about 1e-6 (operand rounding to FP32), so
+# the bar is 1e-5 relative per diagonal entry and, for a trace
+# sum_ik S_ik (dQ_j)_ik, 1e-5 times its condition number
+# c_j = sum_ik |S_ik (dQ_j)_ik| / |sum_ik S_ik (dQ_j)_ik| (the traces of
+# dQ/dlog kappa and dQ/drho cancel strongly).  The measured errors are printed.
+MIXED_TOL = 1e-5
+GRADS = (O.DQ_LOGKAPPA, O.DQ_LOGTAU, O.DQ_RHO, O.DQ_LOGSIGMA)
+
+
+def trace_condition(M):
+    S = np.linalg.inv(M.csr(O.Q).dense())
+    out = []
+    for sel in GRADS:
+        P = S * M.csr(sel).dense()
+        out.append(np.abs(P).sum() / abs(P.sum()))
+    return np.array(out)
+
+
+def check_mixed(tag, d, tr, ref, cond):
+    e_d = np.max(np.abs(d - ref["diag"]) / ref["diag"])
+    e_t = np.abs(np.array(tr) - ref["trace"]) / np.abs(ref["trace"])
+    say(f"{tag}: max rel err diag {e_d:.2e}; traces {np.array2string(e_t, precision=2)}"
+        f" (condition {np.array2string(cond, precision=1)})")
+    assert e_d < MIXED_TOL
+    assert np.all(e_t < MIXED_TOL * cond)
+
+
+@pytest.mark.parametrize("case", [(12, 8, 3, 1, 1), (20, 6, 2, 1, 1), (34, 4, 1, 2, 1)])
+def test_mixed_precision_from_samples_error(case):
+    m, T, P, tiles, n_l = case
+    wl = wl_of(m, T, P, tiles, n_l)
+    say("mixed from_samples", case)
+    M = oracle_model(wl)
+    lab = O.grid_cores(m, m, T, P, tiles, tiles)
+    x = normals((67, M.n), 21)
+    ref = M.rbmc(lab, P * tiles * tiles, n_l, x, 0b1111)
+    gm = B.Model(wl)
+    diag = torch.empty(gm.n, dtype=torch.float64, device="cuda")
+    st, tr, rep = B.rbmc_estimate_from_samples(
+        gm.m, B.make_opts(67, grad_mask=0b1111, precision=B.RBMC_MIXED), dev(x), diag, 4)
+    check_mixed(f"mixed {case}", diag.cpu().numpy(), tr, ref, trace_condition(M))
+    gm.close()
+
+
+def test_mixed_precision_full_estimate():
+    wl = wl_of(16, 8, 2, 1, 1)
+    say("mixed estimate")
+    M = oracle_model(wl)
+    lab = O.grid_cores(16, 16, 8, 2, 1, 1)
+    z = normals((70, M.n + M.n_obs), 43)
+    ref = M.rbmc(lab, 2, 1, M.sample(z), 0b1111)
+    cond = trace_condition(M)
+    for pc in [None, (1, 1, 1)]:
+        gm = B.Model(wl, pc=pc)
+        diag = torch.empty(gm.n, dtype=torch.float64, device="cuda")
+        st, tr, rep = B.rbmc_estimate(
+            gm.m, B.make_opts(70, 5000, 1e-12, 0b1111, precision=B.RBMC_MIXED), dev(z), 0,
+            diag, 4)
+        assert st == B.RBMC_OK
+        check_mixed(f"mixed estimate pc={pc} iters {rep.pcg_it_max}", diag.cpu().numpy(), tr,
+                    ref, cond)
+        gm.close()
+
+
+def test_mixed_gemm_ragged_shapes():
+    """The mixed product path on ragged sample counts (n_k not a multiple of the
+    tile): the sampler with mixed preconditioner solves still reaches the FP64
+    tolerance, and matches the exact sample."""
+    wl = wl_of(14, 9, 3, 2, 1)
+    say("mixed sampler")
+    M = oracle_model(wl)
+    z = normals((37, M.n + M.n_obs), 31)
+    x_ref = M.sample(z)
+    gm = B.Model(wl, pc=(1, 1, 1))
+    x = torch.empty((37, gm.n), dtype=torch.float64, device="cuda")
+    st, rep = B.rbmc_sample(gm.m, B.make_opts(37, 5000, 1e-13, precision=B.RBMC_MIXED),
+                            dev(z), x)
+    assert st == B.RBMC_OK
+    err = np.linalg.norm(x.cpu().numpy() - x_ref, axis=1) / np.linalg.norm(x_ref, axis=1)
+    say(f"mixed sampler: iters {rep.pcg_it_max} max err {err.max():.2e}")
+    assert err.max() < 1e-9
+    gm.close()
