@@ -13,7 +13,9 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "rbmc_impl.h"
@@ -124,12 +126,13 @@ struct rbmc_ctx {
   double* epart = nullptr;     // estimator partial sums
   size_t epart_len = 0;
   Pool epool;
-  // instrumentation
+  // instrumentation (records may be added from two host threads)
   bool prof = false;
+  std::mutex prof_mu;
   std::vector<ProfRec> recs;
   std::vector<hipEvent_t> spare;
 
-  hipEvent_t ev() {
+  hipEvent_t ev() {  // prof_mu held
     hipEvent_t e = nullptr;
     if (!spare.empty()) {
       e = spare.back();
@@ -142,13 +145,16 @@ struct rbmc_ctx {
   // bracket a launch sequence of one kernel family on stream s
   int begin(int family, double flops, double bytes, hipStream_t s) {
     if (!prof) return -1;
+    std::lock_guard<std::mutex> lk(prof_mu);
     ProfRec r{family, ev(), ev(), flops, bytes};
     (void)hipEventRecord(r.a, s);
     recs.push_back(r);
     return (int)recs.size() - 1;
   }
   void end(int id, hipStream_t s) {
-    if (id >= 0) (void)hipEventRecord(recs[id].b, s);
+    if (id < 0) return;
+    std::lock_guard<std::mutex> lk(prof_mu);
+    (void)hipEventRecord(recs[id].b, s);
   }
   void clear() {
     for (ProfRec& r : recs) {
@@ -183,8 +189,9 @@ struct ChainSet {
   std::vector<double*> tmp;          // np^2
   std::vector<double*> sig, xb;      // np^2 (Takahashi Sigma and X), subdomains only
   std::vector<double*> gjU, gjB;     // np x 256 Gauss-Jordan panels
-  std::vector<double*> gjP, gjPi;    // 256 x 256 outer pivot block, 64 x 64 inner pivot inverse
-  std::vector<double*> gjUi, gjBi;   // 256 x 64 inner panels
+  std::vector<double*> gjP;          // 256 x 256 pivot block
+  std::vector<double*> gjU2, gjB2;   // 256 x 128 panels of the pivot block's sweep
+  std::vector<double*> gjP2;         // 128 x 128
   std::vector<std::vector<double*>> pan;  // per chain: T panels np x n_k
   std::vector<double*> ytmp;              // per chain: one panel
   int maxT = 0;
@@ -203,9 +210,9 @@ struct ChainSet {
     cat(gjU, o.gjU);
     cat(gjB, o.gjB);
     cat(gjP, o.gjP);
-    cat(gjPi, o.gjPi);
-    cat(gjUi, o.gjUi);
-    cat(gjBi, o.gjBi);
+    cat(gjU2, o.gjU2);
+    cat(gjB2, o.gjB2);
+    cat(gjP2, o.gjP2);
     cat(pan, o.pan);
     cat(ytmp, o.ytmp);
     maxT = std::max(maxT, o.maxT);
@@ -304,12 +311,12 @@ rbmc_status alloc_chainset(rbmc_model* m, ChainSet& cs, const std::vector<Chain>
     cs.gjB.push_back(p);
     HIPCHK(m->pool.alloc((void**)&p, (size_t)256 * 256 * 8));
     cs.gjP.push_back(p);
-    HIPCHK(m->pool.alloc((void**)&p, (size_t)64 * 64 * 8));
-    cs.gjPi.push_back(p);
-    HIPCHK(m->pool.alloc((void**)&p, (size_t)256 * 64 * 8));
-    cs.gjUi.push_back(p);
-    HIPCHK(m->pool.alloc((void**)&p, (size_t)256 * 64 * 8));
-    cs.gjBi.push_back(p);
+    HIPCHK(m->pool.alloc((void**)&p, (size_t)256 * 128 * 8));
+    cs.gjU2.push_back(p);
+    HIPCHK(m->pool.alloc((void**)&p, (size_t)256 * 128 * 8));
+    cs.gjB2.push_back(p);
+    HIPCHK(m->pool.alloc((void**)&p, (size_t)128 * 128 * 8));
+    cs.gjP2.push_back(p);
     cs.pan.push_back({});
     cs.ytmp.push_back(nullptr);
     cs.maxT = std::max(cs.maxT, c.T);
@@ -340,11 +347,13 @@ rbmc_status ensure_panels(rbmc_model* m, int n_k) {
 
 // ---- task builders ----------------------------------------------------------
 
-int gemm_tiles(int M, int N) { return gemm_task_tiles(M, N, 0); }
+// A launch with fewer 128-tiles than this runs the 64 x 64-tile FP64 kernel
+// (two workgroups per CU on 128-tiles would leave most of the device idle or
+// latency-bound).
+constexpr int kSmallGemmTiles = 768;
 
 struct GemmList {
-  std::vector<GemmTask> v;
-  int tiles = 0;
+  std::vector<GemmTask> v;  // tile_start / tiles_n are set when the list is launched
   int mixed = 0;       // 1: FP32 matrix-core products, FP64 accumulation
   double flops = 0.0;  // algorithmic (unpadded) flops of the list
   double last_flops = 0.0;
@@ -369,18 +378,27 @@ struct GemmList {
     t.beta = beta;
     t.transA = tA;
     t.transB = tB;
-    t.tiles_n = (N + 127) / 128;
-    t.tile_start = tiles;
-    tiles += gemm_tiles(M, N);
     v.push_back(t);
   }
-  // restrict the last product to the lower 128-tiles of a square result
+  // restrict the last product to the lower tiles of a square result
   void set_last_lower() {
     GemmTask& t = v.back();
     flops -= 0.5 * last_flops;  // a symmetric result: the lower half is the work
-    tiles -= gemm_tiles(t.M, t.N);
-    tiles += gemm_task_tiles(t.M, t.N, 1);
     t.lower = 1;
+  }
+  // choose the kernel and number the tiles; returns the total tile count
+  int finalize(int* kind) {
+    int t128 = 0;
+    for (const GemmTask& t : v) t128 += gemm_task_tiles(t.M, t.N, t.lower, 128);
+    *kind = mixed ? kGemmMixed : (t128 < kSmallGemmTiles ? kGemmSmall : kGemmF64);
+    const int ts = (*kind == kGemmSmall) ? 64 : 128;
+    int tiles = 0;
+    for (GemmTask& t : v) {
+      t.tiles_n = (t.N + ts - 1) / ts;
+      t.tile_start = tiles;
+      tiles += gemm_task_tiles(t.M, t.N, t.lower, ts);
+    }
+    return tiles;
   }
   // outer sweep update of the lower tiles: M -= U B^T outside rows/cols [kb, kb + w)
   // (nb: unpadded size, for the algorithmic flops of the lower half)
@@ -403,12 +421,9 @@ struct GemmList {
     t.beta = 1.0;
     t.transA = 0;
     t.transB = 1;
-    t.tiles_n = (np + 127) / 128;
     t.lower = 1;
     t.skip0 = kb;
     t.skip1 = kb + w;
-    t.tile_start = tiles;
-    tiles += gemm_task_tiles(np, np, 1);
     v.push_back(t);
   }
 };
@@ -445,11 +460,13 @@ struct InvJob {  // one SPD block to invert in place, with its workspace
   double* M;
   int np, nb;
   int* info;
-  double *B, *U, *P, *Pi, *Ui, *Bi;
+  int base;            // row offset of M in the outermost block (for info)
+  double *B, *U, *P;   // np x 256, np x 256, 256 x 256: outer sweep panels and pivot block
+  double *B2, *U2, *P2; // 256 x 128, 256 x 128, 128 x 128: the same one level down
 };
 
 struct Op {
-  // 0 gemm, 1 stencil, 2 sweep step (rank 64), 3 panels, 4 extract, 5 mc, 6 copy,
+  // 0 gemm, 1 stencil, 2 register inversion, 3 panels, 4 extract, 5 mc, 6 copy,
   // 7 outer gather, 8 outer fix, 9 sweep finish, 10 profile begin, 11 profile end, 12 mirror
   int kind;
   size_t off = 0;
@@ -468,12 +485,11 @@ struct Program {
     if (g.v.empty()) return;
     Op o;
     o.kind = 0;
+    o.tiles = g.finalize(&o.kblk);
     o.off = a.push(g.v);
     o.n = (int)g.v.size();
-    o.tiles = g.tiles;
     o.family = profiled ? (g.mixed ? RBMC_KF_GEMM_MIXED : RBMC_KF_GEMM) : -1;
     o.alg_flops = g.flops;
-    o.kblk = g.mixed;
     ops.push_back(o);
   }
   void stencil(Arena& a, StencilList& s) {
@@ -497,30 +513,21 @@ struct Program {
     for (const InvTask& it : t) o.max_np = std::max(o.max_np, it.np);
     ops.push_back(o);
   }
-  // rank-64 sweep of a list of blocks (all steps) followed by the finish pass
-  void sweep64(Arena& a, const std::vector<InvTask>& t) {
+  // register-resident inversion of blocks of order <= 128
+  void inv128(Arena& a, const std::vector<SmallInvTask>& t) {
     if (t.empty()) return;
-    const size_t off = a.push(t);
-    int max_np = 0;
-    for (const InvTask& it : t) max_np = std::max(max_np, it.np);
-    for (int k = 0; k < max_np / 64; ++k) {
-      Op o;
-      o.kind = 2;
-      o.off = off;
-      o.n = (int)t.size();
-      o.max_np = max_np;
-      o.kblk = k;
-      ops.push_back(o);
-    }
-    Op f;
-    f.kind = 9;
-    f.off = off;
-    f.n = (int)t.size();
-    ops.push_back(f);
+    Op o;
+    o.kind = 2;
+    o.off = a.push(t);
+    o.n = (int)t.size();
+    ops.push_back(o);
   }
-  // In-place inversion of SPD blocks: blocks up to 256 by the rank-64 sweep;
-  // larger ones by rank-256 outer sweeps (GEMM updates) whose 256 x 256 pivot
-  // blocks are inverted by the rank-64 sweep.
+  // In-place inversion of SPD blocks: blocks up to 128 in registers; larger
+  // ones by outer sweeps of width w (GEMM updates of the lower tiles) whose
+  // pivot blocks are inverted the same way one level down, then the finish
+  // pass (negate and mirror).  Few blocks (a latency-bound chain) take w = 128
+  // and a register inversion per step; many blocks take w = 256, halving the
+  // passes of the rank-w updates over the blocks.
   void inverse(Arena& a, const std::vector<InvJob>& jobs) {
     if (jobs.empty()) return;
     Op pb;
@@ -528,31 +535,31 @@ struct Program {
     pb.family = RBMC_KF_SPD_INVERSE;
     for (const InvJob& j : jobs) pb.alg_flops += (double)j.nb * j.nb * j.nb;
     ops.push_back(pb);
-    std::vector<InvTask> small, big;
+    sweep(a, jobs, jobs.size() >= 4 ? 256 : 128);
+    Op pe;
+    pe.kind = 11;
+    ops.push_back(pe);
+  }
+  void sweep(Arena& a, const std::vector<InvJob>& jobs, int wo) {
+    std::vector<SmallInvTask> small;
+    std::vector<InvTask> big;
     int max_big = 0;
     for (const InvJob& j : jobs) {
-      InvTask t{};
-      t.M = j.M;
-      t.np = j.np;
-      t.nb = j.nb;
-      t.info = j.info;
-      t.U = j.U;
-      t.Bp = j.B;
-      t.Pi = j.Pi;
-      if (j.np <= 256) small.push_back(t);
-      else {
-        big.push_back(t);
+      if (j.np <= 128) {
+        small.push_back(SmallInvTask{j.M, j.np, j.np, j.info, j.base});
+      } else {
+        big.push_back(InvTask{j.M, j.np, j.nb, j.info});
         max_big = std::max(max_big, j.np);
       }
     }
-    sweep64(a, small);
-    for (int kb = 0; kb < max_big; kb += 256) {
+    inv128(a, small);
+    for (int kb = 0; kb < max_big; kb += wo) {
       TileList<Gj2Task> gl;
-      std::vector<InvTask> inner;
+      std::vector<InvJob> inner;
       GemmList gu, gm;
       for (const InvJob& j : jobs) {
-        if (j.np <= 256 || kb >= j.np) continue;
-        const int w = std::min(256, j.np - kb);
+        if (j.np <= 128 || kb >= j.np) continue;
+        const int w = std::min(wo, j.np - kb);
         Gj2Task g{};
         g.M = j.M;
         g.B = j.B;
@@ -562,15 +569,17 @@ struct Program {
         g.kb = kb;
         g.w = w;
         gl.add(g, gj2_tiles(j.np, w));
-        InvTask t{};
-        t.M = j.P;
-        t.np = w;
-        t.nb = w;
-        t.info = j.info;
-        t.U = j.Ui;
-        t.Bp = j.Bi;
-        t.Pi = j.Pi;
-        inner.push_back(t);
+        // the pivot block, inverted one level down with the inner workspace
+        InvJob in{};
+        in.M = j.P;
+        in.np = w;
+        in.nb = w;
+        in.info = j.info;
+        in.base = j.base + kb;
+        in.B = j.B2;
+        in.U = j.U2;
+        in.P = j.P2;
+        inner.push_back(in);
         gu.add(j.B, j.P, nullptr, j.U, j.np, w, w, j.np, w, j.np, 1.0, 0.0, 0, 0, j.np, w);
         gm.add_sweep(j.M, j.np, j.U, j.B, w, kb, j.nb);
       }
@@ -580,7 +589,7 @@ struct Program {
       og.n = (int)gl.v.size();
       og.tiles = gl.tiles;
       ops.push_back(og);
-      sweep64(a, inner);
+      sweep(a, inner, 128);
       gemm(a, gu);
       gemm(a, gm);
       Op of = og;
@@ -592,11 +601,9 @@ struct Program {
       f.kind = 9;
       f.off = a.push(big);
       f.n = (int)big.size();
+      f.max_np = max_big;
       ops.push_back(f);
     }
-    Op pe;
-    pe.kind = 11;
-    ops.push_back(pe);
   }
   void panels(Arena& a, TileList<PanelTask>& p) {
     if (p.v.empty()) return;
@@ -644,14 +651,14 @@ rbmc_status run(rbmc_ctx* cx, const Program& pg, hipStream_t s, Arena& a) {
     switch (o.kind) {
       case 0: launch_gemm(a.at<GemmTask>(o.off), o.n, o.tiles, s, o.kblk); break;
       case 1: launch_rstencil(a.at<StencilTask>(o.off), o.n, o.tiles, o.max_np, s); break;
-      case 2: launch_gj_step(a.at<InvTask>(o.off), o.n, o.max_np, o.kblk, s); break;
+      case 2: launch_inv128(a.at<SmallInvTask>(o.off), o.n, s); break;
       case 3: launch_panels(a.at<PanelTask>(o.off), o.n, o.tiles, s); break;
       case 4: launch_extract(a.at<ExtractTask>(o.off), o.n, o.tiles, s); break;
       case 5: launch_mc(a.at<McTask>(o.off), o.n, o.tiles, s); break;
       case 6: HIPCHK(hipMemcpyAsync(o.dst, o.src, o.bytes, hipMemcpyDeviceToDevice, s)); break;
       case 7: launch_gj2_gather(a.at<Gj2Task>(o.off), o.n, o.tiles, s); break;
       case 8: launch_gj2_fix(a.at<Gj2Task>(o.off), o.n, o.tiles, s); break;
-      case 9: launch_gj_finish(a.at<InvTask>(o.off), o.n, s); break;
+      case 9: launch_gj_finish(a.at<InvTask>(o.off), o.n, o.max_np, s); break;
       case 10: open_prof.push_back(pid); break;
       case 11:
         if (!open_prof.empty()) {
@@ -719,9 +726,10 @@ void build_factor(ChainSet& cs, Program& pg, Arena& a) {
       it.B = cs.gjB[c];
       it.U = cs.gjU[c];
       it.P = cs.gjP[c];
-      it.Pi = cs.gjPi[c];
-      it.Ui = cs.gjUi[c];
-      it.Bi = cs.gjBi[c];
+      it.B2 = cs.gjB2[c];
+      it.U2 = cs.gjU2[c];
+      it.P2 = cs.gjP2[c];
+      it.base = 0;
       inv.push_back(it);
     }
     pg.stencil(a, v1);
@@ -1309,22 +1317,45 @@ rbmc_status estimate_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const
     e_tak = cx->join[3];
     HIPCHK(hipEventRecord(e_beg, s));
   }
-  rbmc_status st = run(cx, fac, s, ar);
-  if (st != RBMC_OK) return st;
-  if (e_fac) HIPCHK(hipEventRecord(e_fac, s));
-  st = run(cx, tak, s, ar);
-  if (st != RBMC_OK) return st;
-  if (e_tak) HIPCHK(hipEventRecord(e_tak, s));
+  // factorization + Takahashi on stream s; with a sampler they are enqueued
+  // by a second host thread, so neither stream waits for the host to finish
+  // enqueuing the other's launches (a stream's queue fills up long before
+  // thousands of launches are placed, and placing then blocks).
+  rbmc_status st_b = RBMC_OK;
+  std::string err_b;
+  auto side_work = [&]() {
+    if (sampler && hipSetDevice(cx->device) != hipSuccess) {
+      st_b = fail(RBMC_E_DEVICE, "hipSetDevice failed on the launch thread");
+    }
+    if (st_b == RBMC_OK) st_b = run(cx, fac, s, ar);
+    if (st_b == RBMC_OK && e_fac && hipEventRecord(e_fac, s) != hipSuccess)
+      st_b = fail(RBMC_E_DEVICE, "hipEventRecord failed");
+    if (st_b == RBMC_OK) st_b = run(cx, tak, s, ar);
+    if (st_b == RBMC_OK && e_tak && hipEventRecord(e_tak, s) != hipSuccess)
+      st_b = fail(RBMC_E_DEVICE, "hipEventRecord failed");
+    if (st_b != RBMC_OK) err_b = g_err;
+  };
   rbmc_status st_samp = RBMC_OK;
   if (sampler) {
+    std::thread tb(side_work);
     st_samp = sampler();  // on the caller's stream, concurrently with the side stream
+    tb.join();
+    if (st_b != RBMC_OK) {
+      (void)hipStreamSynchronize(sA);
+      (void)hipStreamSynchronize(s);
+      return fail(st_b, err_b);
+    }
     if (st_samp < 0) {
       (void)hipStreamSynchronize(s);
       return st_samp;
     }
     HIPCHK(hipEventRecord(cx->join[0], s));
     HIPCHK(hipStreamWaitEvent(sA, cx->join[0], 0));
+  } else {
+    side_work();
+    if (st_b != RBMC_OK) return st_b;
   }
+  rbmc_status st = RBMC_OK;
   HIPCHK(hipStreamSynchronize(s));
   if (cf.size()) {
     st = check_info(cf, rep, "subdomain");

@@ -1,7 +1,8 @@
 // Dense FP64 kernels for the spatial blocks of the block-tridiagonal chains:
 //   - grouped GEMM on the FP64 matrix cores (v_mfma_f64_16x16x4f64);
-//   - in-place inversion of SPD blocks by the block Gauss-Jordan sweep,
-//     whose rank-64 updates also run on the matrix cores;
+//   - in-place inversion of SPD blocks by the block Gauss-Jordan sweep:
+//     register-resident for order <= 128, rank-128 outer steps on the
+//     matrix cores above;
 //   - products of the restricted 13-point stencil Q_R with dense blocks.
 // Dense blocks are column-major, padded to multiples of 64 with identity on
 // the padded diagonal.
@@ -102,8 +103,8 @@ __device__ inline void store_b(const GemmTask& tk, int tid, const TileRegs& r, d
   }
 }
 
-int gemm_task_tiles(int M, int N, int lower) {
-  const int tm = (M + GBM - 1) / GBM, tn = (N + GBN - 1) / GBN;
+int gemm_task_tiles(int M, int N, int lower, int ts) {
+  const int tm = (M + ts - 1) / ts, tn = (N + ts - 1) / ts;
   return lower ? tm * (tm + 1) / 2 : tm * tn;
 }
 
@@ -111,11 +112,12 @@ int gemm_task_tiles(int M, int N, int lower) {
 // a workgroup is chosen so that each XCD walks a contiguous range of tiles
 // (neighbouring tiles share A row panels in its L2).  The K loop prefetches
 // the next A/B tiles into registers while the matrix cores consume the
-// current LDS tiles.
+// current LDS tiles; the LDS tiles are double-buffered, so one barrier per
+// K step separates the stores of step k + 1 from the reads of step k.
 __global__ __launch_bounds__(256, 2) void k_gemm_f64(const GemmTask* __restrict__ tasks,
                                                      int n_tasks, int total_tiles, int per_xcd) {
-  __shared__ double As[GBM * GLDS];
-  __shared__ double Bs[GBN * GLDS];
+  __shared__ double As[2][GBM * GLDS];
+  __shared__ double Bs[2][GBN * GLDS];
   const int b = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
   if (b >= total_tiles) return;
   int lo = 0, hi = n_tasks - 1;
@@ -154,9 +156,10 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(const GemmTask* __restrict_
   TileRegs ra, rb;
   load_a(tk, m0, 0, tid, ra);
   load_b(tk, n0, 0, tid, rb);
-  store_a(tk, tid, ra, As);
-  store_b(tk, tid, rb, Bs);
+  store_a(tk, tid, ra, As[0]);
+  store_b(tk, tid, rb, Bs[0]);
   __syncthreads();
+  int buf = 0;
   for (int k0 = 0; k0 < tk.K; k0 += GBK) {
     const bool more = k0 + GBK < tk.K;
     if (more) {
@@ -166,10 +169,10 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(const GemmTask* __restrict_
     double a[4][4], bb[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const double* pa = &As[(wm + i * 16 + l16) * GLDS + 4 * g];
+      const double* pa = &As[buf][(wm + i * 16 + l16) * GLDS + 4 * g];
       double2 x0 = *(const double2*)pa, x1 = *(const double2*)(pa + 2);
       a[i][0] = x0.x; a[i][1] = x0.y; a[i][2] = x1.x; a[i][3] = x1.y;
-      const double* pb = &Bs[(wn + i * 16 + l16) * GLDS + 4 * g];
+      const double* pb = &Bs[buf][(wn + i * 16 + l16) * GLDS + 4 * g];
       double2 y0 = *(const double2*)pb, y1 = *(const double2*)(pb + 2);
       bb[i][0] = y0.x; bb[i][1] = y0.y; bb[i][2] = y1.x; bb[i][3] = y1.y;
     }
@@ -178,30 +181,32 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(const GemmTask* __restrict_
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = mfma64(a[i][s], bb[j][s], acc[i][j]);
-    __syncthreads();
-    if (more) {
-      store_a(tk, tid, ra, As);
-      store_b(tk, tid, rb, Bs);
-      __syncthreads();
+        for (int j = 0; j < 4; ++j) acc[i][j] = mfma64(bb[j][s], a[i][s], acc[i][j]);
+    if (more) {  // the other buffer was last read before the previous barrier
+      store_a(tk, tid, ra, As[buf ^ 1]);
+      store_b(tk, tid, rb, Bs[buf ^ 1]);
     }
+    __syncthreads();
+    buf ^= 1;
   }
-  // ---- epilogue: C = alpha acc + beta Cin
+  // ---- epilogue: C = alpha acc + beta Cin.  The products were formed as
+  // (B^T A^T) tiles, so register r of lane l holds C[16 i + l%16][16 j + l/16
+  // + 4 r]: 16 consecutive rows of a column per lane group (128-byte segments).
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 4; ++i) {
+    const int gm = m0 + wm + i * 16 + l16;
+    if (gm >= tk.M) continue;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int gn = n0 + wn + j * 16 + l16;
-      if (gn >= tk.N) continue;
+    for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int gm = m0 + wm + i * 16 + g + 4 * r;
-        if (gm >= tk.M) continue;
+        const int gn = n0 + wn + j * 16 + g + 4 * r;
+        if (gn >= tk.N) continue;
         double v = tk.alpha * acc[i][j][r];
         if (tk.beta != 0.0) v += tk.beta * tk.Cin[(size_t)gn * tk.ldcin + gm];
         tk.C[(size_t)gn * tk.ldc + gm] = v;
       }
-    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -213,7 +218,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(const GemmTask* __restrict_
 // Same 128 x 128 tiles and task semantics as k_gemm_f64; eight waves of
 // 64 x 32 keep the FP64 accumulators within the register budget.
 // FP32 16x16x4: lane l supplies A[l%16][l/16] and B[l/16][l%16]; accumulator
-// register i of lane l holds C[4 (l/16) + i][l%16].
+// register i of lane l holds C[4 (l/16) + i][l%16].  As in the FP64 kernels
+// the tile is formed transposed (B^T A^T), so the stores run down columns.
 // ---------------------------------------------------------------------------
 typedef float v4f __attribute__((ext_vector_type(4)));
 
@@ -293,8 +299,8 @@ __device__ inline void xstore_b(const GemmTask& tk, int tid, const XRegs& r, flo
 
 __global__ __launch_bounds__(512, 1) void k_gemm_mx(const GemmTask* __restrict__ tasks,
                                                     int n_tasks, int total_tiles, int per_xcd) {
-  __shared__ float As[GBM * XLD];
-  __shared__ float Bs[GBN * XLD];
+  __shared__ float As[2][GBM * XLD];
+  __shared__ float Bs[2][GBN * XLD];
   const int b = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
   if (b >= total_tiles) return;
   int lo = 0, hi = n_tasks - 1;
@@ -335,9 +341,10 @@ __global__ __launch_bounds__(512, 1) void k_gemm_mx(const GemmTask* __restrict__
   XRegs ra, rb;
   xload_a(tk, m0, 0, tid, ra);
   xload_b(tk, n0, 0, tid, rb);
-  xstore_a(tk, tid, ra, As);
-  xstore_b(tk, tid, rb, Bs);
+  xstore_a(tk, tid, ra, As[0]);
+  xstore_b(tk, tid, rb, Bs[0]);
   __syncthreads();
+  int buf = 0;
   for (int k0 = 0; k0 < tk.K; k0 += GBK) {
     const bool more = k0 + GBK < tk.K;
     if (more) {
@@ -346,9 +353,9 @@ __global__ __launch_bounds__(512, 1) void k_gemm_mx(const GemmTask* __restrict__
     }
     float4 a[4], bb[2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) a[i] = *(const float4*)&As[(wm + i * 16 + l16) * XLD + 4 * g];
+    for (int i = 0; i < 4; ++i) a[i] = *(const float4*)&As[buf][(wm + i * 16 + l16) * XLD + 4 * g];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) bb[j] = *(const float4*)&Bs[(wn + j * 16 + l16) * XLD + 4 * g];
+    for (int j = 0; j < 2; ++j) bb[j] = *(const float4*)&Bs[buf][(wn + j * 16 + l16) * XLD + 4 * g];
     v4f c32[4][2];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -358,10 +365,10 @@ __global__ __launch_bounds__(512, 1) void k_gemm_mx(const GemmTask* __restrict__
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        c32[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].x, bb[j].x, c32[i][j], 0, 0, 0);
-        c32[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].y, bb[j].y, c32[i][j], 0, 0, 0);
-        c32[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].z, bb[j].z, c32[i][j], 0, 0, 0);
-        c32[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].w, bb[j].w, c32[i][j], 0, 0, 0);
+        c32[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(bb[j].x, a[i].x, c32[i][j], 0, 0, 0);
+        c32[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(bb[j].y, a[i].y, c32[i][j], 0, 0, 0);
+        c32[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(bb[j].z, a[i].z, c32[i][j], 0, 0, 0);
+        c32[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(bb[j].w, a[i].w, c32[i][j], 0, 0, 0);
       }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -369,255 +376,342 @@ __global__ __launch_bounds__(512, 1) void k_gemm_mx(const GemmTask* __restrict__
       for (int j = 0; j < 2; ++j)
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[i][j][r] += (double)c32[i][j][r];
-    __syncthreads();
-    if (more) {
-      xstore_a(tk, tid, ra, As);
-      xstore_b(tk, tid, rb, Bs);
-      __syncthreads();
+    if (more) {  // the other buffer was last read before the previous barrier
+      xstore_a(tk, tid, ra, As[buf ^ 1]);
+      xstore_b(tk, tid, rb, Bs[buf ^ 1]);
     }
+    __syncthreads();
+    buf ^= 1;
   }
+  // transposed tile products: register r of lane l holds C[16 i + l%16][16 j + 4 (l/16) + r]
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 4; ++i) {
+    const int gm = m0 + wm + i * 16 + l16;
+    if (gm >= tk.M) continue;
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int gn = n0 + wn + j * 16 + l16;
-      if (gn >= tk.N) continue;
+    for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int gm = m0 + wm + i * 16 + 4 * g + r;
-        if (gm >= tk.M) continue;
+        const int gn = n0 + wn + j * 16 + 4 * g + r;
+        if (gn >= tk.N) continue;
         double v = tk.alpha * acc[i][j][r];
         if (tk.beta != 0.0) v += tk.beta * tk.Cin[(size_t)gn * tk.ldcin + gm];
         tk.C[(size_t)gn * tk.ldc + gm] = v;
       }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Grouped FP64 GEMM with 64 x 64 tiles (four waves of 32 x 32), for launches
+// with too few 128 x 128 tiles to fill the device: a small working set per
+// workgroup lets several workgroups share a CU and hide memory latency.
+// Same task semantics (lower mode and skip ranges on 64-tiles).
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int SB = 64;
+
+__device__ inline void sload_a(const GemmTask& tk, int m0, int k0, int tid, XRegs& r) {
+  if (!tk.transA) {  // 4 consecutive rows of column k
+    const int kk = tid >> 4, gm = m0 + (tid & 15) * 4;
+    const double* src = tk.A + (size_t)(k0 + kk) * tk.lda + gm;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int c = gm + 2 * j;
+      if (c + 1 < tk.M) r.v[j] = *(const double2*)(src + 2 * j);
+      else r.v[j] = double2{c < tk.M ? src[2 * j] : 0.0, 0.0};
     }
+  } else {  // 4 consecutive k of row m
+    const int gm = m0 + (tid >> 2), kk = (tid & 3) * 4;
+    const double* src = tk.A + (size_t)gm * tk.lda + k0 + kk;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      r.v[j] = (gm < tk.M) ? *(const double2*)(src + 2 * j) : double2{0.0, 0.0};
+  }
+}
+
+__device__ inline void sstore_a(const GemmTask& tk, int tid, const XRegs& r, double* As) {
+  if (!tk.transA) {
+    const int kk = tid >> 4, mm = (tid & 15) * 4;
+    As[(mm + 0) * GLDS + kk] = r.v[0].x;
+    As[(mm + 1) * GLDS + kk] = r.v[0].y;
+    As[(mm + 2) * GLDS + kk] = r.v[1].x;
+    As[(mm + 3) * GLDS + kk] = r.v[1].y;
+  } else {
+    const int mm = tid >> 2, kk = (tid & 3) * 4;
+    *(double2*)&As[mm * GLDS + kk] = r.v[0];
+    *(double2*)&As[mm * GLDS + kk + 2] = r.v[1];
+  }
+}
+
+__device__ inline void sload_b(const GemmTask& tk, int n0, int k0, int tid, XRegs& r) {
+  if (!tk.transB) {  // 4 consecutive k of column n
+    const int gn = n0 + (tid >> 2), kk = (tid & 3) * 4;
+    const double* src = tk.B + (size_t)gn * tk.ldb + k0 + kk;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      r.v[j] = (gn < tk.N) ? *(const double2*)(src + 2 * j) : double2{0.0, 0.0};
+  } else {  // 4 consecutive n of row k
+    const int kk = tid >> 4, gn = n0 + (tid & 15) * 4;
+    const double* src = tk.B + (size_t)(k0 + kk) * tk.ldb + gn;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int c = gn + 2 * j;
+      if (c + 1 < tk.N) r.v[j] = *(const double2*)(src + 2 * j);
+      else r.v[j] = double2{c < tk.N ? src[2 * j] : 0.0, 0.0};
+    }
+  }
+}
+
+__device__ inline void sstore_b(const GemmTask& tk, int tid, const XRegs& r, double* Bs) {
+  if (!tk.transB) {
+    const int nn = tid >> 2, kk = (tid & 3) * 4;
+    *(double2*)&Bs[nn * GLDS + kk] = r.v[0];
+    *(double2*)&Bs[nn * GLDS + kk + 2] = r.v[1];
+  } else {
+    const int kk = tid >> 4, nn = (tid & 15) * 4;
+    Bs[(nn + 0) * GLDS + kk] = r.v[0].x;
+    Bs[(nn + 1) * GLDS + kk] = r.v[0].y;
+    Bs[(nn + 2) * GLDS + kk] = r.v[1].x;
+    Bs[(nn + 3) * GLDS + kk] = r.v[1].y;
+  }
+}
+}  // namespace
+
+__global__ __launch_bounds__(256) void k_gemm_f64s(const GemmTask* __restrict__ tasks,
+                                                   int n_tasks, int total_tiles, int per_xcd) {
+  __shared__ double As[2][SB * GLDS];
+  __shared__ double Bs[2][SB * GLDS];
+  const int b = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (b >= total_tiles) return;
+  int lo = 0, hi = n_tasks - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) / 2;
+    if (tasks[mid].tile_start <= b) lo = mid; else hi = mid - 1;
+  }
+  const GemmTask tk = tasks[lo];
+  const int tile = b - tk.tile_start;
+  int tm, tn;
+  if (tk.lower) {
+    tm = (int)((sqrt(8.0 * tile + 1.0) - 1.0) * 0.5);
+    while ((tm + 1) * (tm + 2) / 2 <= tile) ++tm;
+    while (tm * (tm + 1) / 2 > tile) --tm;
+    tn = tile - tm * (tm + 1) / 2;
+  } else {
+    tm = tile / tk.tiles_n;
+    tn = tile % tk.tiles_n;
+  }
+  const int m0 = tm * SB, n0 = tn * SB;
+  if (tk.skip1 > tk.skip0) {
+    const bool rows_hit = m0 < tk.skip1 && m0 + SB > tk.skip0;
+    const bool cols_hit = n0 < tk.skip1 && n0 + SB > tk.skip0;
+    if (rows_hit || cols_hit) return;
+  }
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int l16 = lane & 15, g = lane >> 4;
+
+  v4d acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+
+  XRegs ra, rb;
+  sload_a(tk, m0, 0, tid, ra);
+  sload_b(tk, n0, 0, tid, rb);
+  sstore_a(tk, tid, ra, As[0]);
+  sstore_b(tk, tid, rb, Bs[0]);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = 0; k0 < tk.K; k0 += GBK) {
+    const bool more = k0 + GBK < tk.K;
+    if (more) {
+      sload_a(tk, m0, k0 + GBK, tid, ra);
+      sload_b(tk, n0, k0 + GBK, tid, rb);
+    }
+    double a[2][4], bb[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const double* pa = &As[buf][(wm + i * 16 + l16) * GLDS + 4 * g];
+      double2 x0 = *(const double2*)pa, x1 = *(const double2*)(pa + 2);
+      a[i][0] = x0.x; a[i][1] = x0.y; a[i][2] = x1.x; a[i][3] = x1.y;
+      const double* pb = &Bs[buf][(wn + i * 16 + l16) * GLDS + 4 * g];
+      double2 y0 = *(const double2*)pb, y1 = *(const double2*)(pb + 2);
+      bb[i][0] = y0.x; bb[i][1] = y0.y; bb[i][2] = y1.x; bb[i][3] = y1.y;
+    }
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = mfma64(bb[j][s2], a[i][s2], acc[i][j]);
+    if (more) {  // the other buffer was last read before the previous barrier
+      sstore_a(tk, tid, ra, As[buf ^ 1]);
+      sstore_b(tk, tid, rb, Bs[buf ^ 1]);
+    }
+    __syncthreads();
+    buf ^= 1;
+  }
+  // transposed tile products: register r of lane l holds C[16 i + l%16][16 j + l/16 + 4 r]
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int gm = m0 + wm + i * 16 + l16;
+    if (gm >= tk.M) continue;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gn = n0 + wn + j * 16 + g + 4 * r;
+        if (gn >= tk.N) continue;
+        double v = tk.alpha * acc[i][j][r];
+        if (tk.beta != 0.0) v += tk.beta * tk.Cin[(size_t)gn * tk.ldcin + gm];
+        tk.C[(size_t)gn * tk.ldc + gm] = v;
+      }
+  }
 }
 
 void launch_gemm(const GemmTask* d_tasks, int n_tasks, int total_tiles, hipStream_t s,
-                 int mixed) {
+                 int kind) {
   if (total_tiles <= 0) return;
   const int per_xcd = (total_tiles + 7) / 8;
-  if (mixed)
+  if (kind == kGemmMixed)
     k_gemm_mx<<<per_xcd * 8, 512, 0, s>>>(d_tasks, n_tasks, total_tiles, per_xcd);
+  else if (kind == kGemmSmall)
+    k_gemm_f64s<<<per_xcd * 8, 256, 0, s>>>(d_tasks, n_tasks, total_tiles, per_xcd);
   else
     k_gemm_f64<<<per_xcd * 8, 256, 0, s>>>(d_tasks, n_tasks, total_tiles, per_xcd);
 }
 
 // ---------------------------------------------------------------------------
-// SPD inversion by the block Gauss-Jordan sweep (block size 64).
-// Sweeping pivot block k of a symmetric M:
-//   M_kk <- -M_kk^-1, M_ik <- M_ik M_kk^-1, M_kj <- M_kk^-1 M_kj,
-//   M_ij <- M_ij - M_ik M_kk^-1 M_kj   (i, j != k);
-// after all pivots M holds -A^-1.  Pivot blocks are Schur complements of an
-// SPD matrix, hence SPD.  Only the lower block triangle is kept current.
+// SPD inversion by the block Gauss-Jordan sweep.  Sweeping pivot k of a
+// symmetric M:
+//   M_kk <- -1/M_kk,  M_ik <- M_ik / M_kk,  M_kj <- M_kj / M_kk,
+//   M_ij <- M_ij - M_ik M_kj / M_kk   (i, j != k);
+// after all pivots M holds -A^-1.  Pivots are Schur complements of an SPD
+// matrix, hence positive.  Blocks of order <= 128 are swept entirely in
+// registers by one workgroup; larger blocks take outer rank-128 steps whose
+// updates run on the matrix cores (k_gj2_* and the grouped GEMM).
 // ---------------------------------------------------------------------------
 namespace {
-constexpr int JB = 64;
-constexpr int JLD = JB + 1;
-
-// In-LDS sweep of a 64x64 SPD block P (ld JLD): P <- P^-1.  Returns false on
-// a non-positive pivot.
-// Thread tid owns column c = tid % 64 and rows r = tid / 64 + 4 j (j < 16); the
-// 16 owned entries live in registers for the whole sweep, so a pivot step is
-// one broadcast of row/column p through LDS and 16 independent updates.
-__device__ bool lds_spd_inverse(double* P, double* rowp, double* colp, int tid) {
-  const int c = tid & 63, r0 = tid >> 6;
-  double v[16];
-  __syncthreads();
-#pragma unroll
-  for (int j = 0; j < 16; ++j) v[j] = P[(r0 + 4 * j) * JLD + c];
-  bool ok = true;
-  for (int p = 0; p < JB; ++p) {
-    // publish row p and column p of the current matrix
-    if ((p & 3) == r0) rowp[c] = v[p >> 2];
-    if (c == p) {
-#pragma unroll
-      for (int j = 0; j < 16; ++j) colp[r0 + 4 * j] = v[j];
-    }
-    __syncthreads();
-    const double piv = rowp[p];
-    if (!(piv > 0.0)) ok = false;
-    const double ip = 1.0 / piv;
-    const double rc = rowp[c] * ip;
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const int r = r0 + 4 * j;
-      const double cr = colp[r];
-      double nv = v[j] - cr * rc;
-      if (c == p) nv = cr * ip;
-      if (r == p) nv = (c == p) ? -ip : rc;
-      v[j] = nv;
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int j = 0; j < 16; ++j) P[(r0 + 4 * j) * JLD + c] = -v[j];
-  __syncthreads();
-  return ok;
-}
+constexpr int IB = 128;  // order of the register-resident sweep
+constexpr int IT = 1024; // threads, 32 x 32, each owning a 4 x 4 block
 }  // namespace
 
-// Pivot kernel: one workgroup per task inverts the 64 x 64 pivot block k
-// (symmetrized from the lower triangle) into Pi.
-__global__ __launch_bounds__(256) void k_gj_pivot(const InvTask* __restrict__ tasks, int kblk) {
-  __shared__ double P[JB * JLD];
-  __shared__ double rowp[JB], colp[JB];
-  const InvTask tk = tasks[blockIdx.x];
-  if (kblk >= tk.np / JB) return;
-  const int tid = threadIdx.x, kb = kblk * JB, np = tk.np;
-  for (int e = tid; e < JB * JB; e += 256) {
-    const int r = e % JB, c = e / JB;
-    const int rr = r > c ? r : c, cc = r > c ? c : r;
-    P[r * JLD + c] = tk.M[(size_t)(kb + cc) * np + kb + rr];
+// One workgroup per task inverts P (order w <= 128, column-major, ld, full
+// symmetric) in place.  Rows/columns w..127 are identity.  Thread
+// (tr, tc) = (tid / 32, tid % 32) keeps rows 4 tr .. 4 tr + 3 x columns
+// 4 tc .. 4 tc + 3 in registers.  Pivot p: the owners of row p and of column
+// p publish them (and the pivot's owner 1/M_pp) to LDS, double-buffered so
+// one barrier per pivot suffices; every thread then reads 4 column and 4 row
+// values (128-bit loads) and updates its 16 entries with one FMA each; only
+// the pivot row and column are fixed up.  Iterating p as 4 q + s with s
+// unrolled keeps every register index static.  P is symmetric, so entry
+// (r, c) is read from and written to P[r * ld + c] (coalesced along c).
+__global__ __launch_bounds__(IT) void k_inv128(const SmallInvTask* __restrict__ tasks) {
+  __shared__ __align__(16) double rowp[2][IB];
+  __shared__ __align__(16) double colp[2][IB];
+  __shared__ double ipv[2];
+  const SmallInvTask tk = tasks[blockIdx.x];
+  const int tid = threadIdx.x, tr = tid >> 5, tc = tid & 31, w = tk.w;
+  double v[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = 4 * tr + i, c = 4 * tc + j;
+      v[i][j] = (r < w && c < w) ? tk.P[(size_t)r * tk.ld + c] : (r == c ? 1.0 : 0.0);
+    }
+  int bad = -1;
+  for (int q = 0; q < IB / 4; ++q) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int p = 4 * q + s, buf = s & 1;
+      if (tr == q) {
+        *(double2*)&rowp[buf][4 * tc] = double2{v[s][0], v[s][1]};
+        *(double2*)&rowp[buf][4 * tc + 2] = double2{v[s][2], v[s][3]};
+        if (tc == q) ipv[buf] = 1.0 / v[s][s];
+      }
+      if (tc == q) {
+        *(double2*)&colp[buf][4 * tr] = double2{v[0][s], v[1][s]};
+        *(double2*)&colp[buf][4 * tr + 2] = double2{v[2][s], v[3][s]};
+      }
+      __syncthreads();
+      const double piv = rowp[buf][p];
+      const double ip = ipv[buf];
+      if (!(piv > 0.0) && bad < 0) bad = p;
+      const double2 c01 = *(const double2*)&colp[buf][4 * tr];
+      const double2 c23 = *(const double2*)&colp[buf][4 * tr + 2];
+      const double2 r01 = *(const double2*)&rowp[buf][4 * tc];
+      const double2 r23 = *(const double2*)&rowp[buf][4 * tc + 2];
+      const double col[4] = {c01.x, c01.y, c23.x, c23.y};
+      const double rc[4] = {r01.x * ip, r01.y * ip, r23.x * ip, r23.y * ip};
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[i][j] = fma(-col[i], rc[j], v[i][j]);
+      if (tc == q) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i][s] = col[i] * ip;
+      }
+      if (tr == q) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[s][j] = rc[j];
+        if (tc == q) v[s][s] = -ip;
+      }
+    }
   }
-  const bool ok = lds_spd_inverse(P, rowp, colp, tid);
-  if (!ok && tid == 0) atomicCAS(tk.info, 0, kblk + 1);
-  for (int e = tid; e < JB * JB; e += 256) tk.Pi[e] = P[(e % JB) * JLD + e / JB];
+  if (bad >= 0 && tid == 0) atomicCAS(tk.info, 0, tk.base + bad + 1);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = 4 * tr + i, c = 4 * tc + j;
+      if (r < w && c < w) tk.P[(size_t)r * tk.ld + c] = -v[i][j];
+    }
 }
 
-// Panel kernel: grid (np/64 row blocks, tasks).  B_i = M_ik (lower-stored: i > k
-// from M, i < k from M_ki^T, i = k the pivot block), U_i = B_i Pi (U_k = Pi),
-// on the matrix cores; B_i and U_i go to the task's panels.
-__global__ __launch_bounds__(256) void k_gj_panel(const InvTask* __restrict__ tasks, int kblk) {
-  __shared__ double Bt[JB * JLD];
-  __shared__ double Ps[JB * JLD];
-  const InvTask tk = tasks[blockIdx.y];
-  const int nblk = tk.np / JB;
-  const int i = blockIdx.x;
-  if (kblk >= nblk || i >= nblk) return;
-  const int tid = threadIdx.x;
-  const int kb = kblk * JB, ib = i * JB, np = tk.np;
-  for (int e = tid; e < JB * JB; e += 256) {
-    const int r = e % JB, c = e / JB;
-    double v;
-    if (i > kblk) v = tk.M[(size_t)(kb + c) * np + ib + r];
-    else if (i < kblk) v = tk.M[(size_t)(ib + r) * np + kb + c];
-    else {
-      const int rr = r > c ? r : c, cc = r > c ? c : r;
-      v = tk.M[(size_t)(kb + cc) * np + kb + rr];
-    }
-    Bt[r * JLD + c] = v;
-    Ps[c * JLD + r] = tk.Pi[(size_t)c * JB + r];  // Ps[col][row] : k contiguous per column
-  }
-  __syncthreads();
-  const int lane = tid & 63, w = tid >> 6, l16 = lane & 15, g = lane >> 4;
-  if (i == kblk) {
-    for (int e = tid; e < JB * JB; e += 256) {
-      const int r = e % JB, c = e / JB;
-      tk.U[(size_t)c * np + ib + r] = tk.Pi[(size_t)c * JB + r];
-      tk.Bp[(size_t)c * np + ib + r] = Bt[r * JLD + c];
-    }
-    return;
-  }
-  // wave w: rows 16w..16w+15 of U_i = B_i Pi
-  v4d acc[4];
-#pragma unroll
-  for (int c = 0; c < 4; ++c) acc[c] = v4d{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < JB; k0 += 4) {
-    const double a = Bt[(w * 16 + l16) * JLD + k0 + g];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) acc[c] = mfma64(a, Ps[(c * 16 + l16) * JLD + k0 + g], acc[c]);
-  }
-#pragma unroll
-  for (int c = 0; c < 4; ++c)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = w * 16 + g + 4 * r, col = c * 16 + l16;
-      tk.U[(size_t)col * np + ib + row] = acc[c][r];
-    }
-  for (int e = tid; e < JB * JB; e += 256) {
-    const int r = e % JB, c = e / JB;
-    tk.Bp[(size_t)c * np + ib + r] = Bt[r * JLD + c];
-  }
+void launch_inv128(const SmallInvTask* d_tasks, int n_tasks, hipStream_t s) {
+  if (n_tasks > 0) k_inv128<<<n_tasks, IT, 0, s>>>(d_tasks);
 }
 
-// Rank-64 update of the lower block triangle: grid (lower tiles, tasks).
-//   tile (i, j), i >= j:
-//     i, j != k : M_ij -= U_i B_j^T
-//     i > k = j : M_ik  = U_i
-//     i = k > j : M_kj  = U_j^T
-//     i = j = k : M_kk  = -U_k
-__global__ __launch_bounds__(256) void k_gj_update(const InvTask* __restrict__ tasks, int kblk) {
-  __shared__ double Us[JB * JLD];
-  __shared__ double Bs[JB * JLD];
+// M (holding -A^-1 in its lower triangle) -> A^-1, full symmetric; 64 x 64
+// tiles through LDS so both the lower and the mirrored upper writes coalesce.
+// Grid (lower tiles of the largest block, tasks).
+__global__ __launch_bounds__(256) void k_gj_finish(const InvTask* __restrict__ tasks) {
+  __shared__ double T[64 * 65];
   const InvTask tk = tasks[blockIdx.y];
-  const int nblk = tk.np / JB;
-  if (kblk >= nblk) return;
+  const int np = tk.np, nt = np / 64;
   const int t = blockIdx.x;
-  if (t >= nblk * (nblk + 1) / 2) return;
-  int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-  while ((i + 1) * (i + 2) / 2 <= t) ++i;
-  while (i * (i + 1) / 2 > t) --i;
-  const int j = t - i * (i + 1) / 2;
-  const int np = tk.np, ib = i * JB, jb = j * JB;
+  if (t >= nt * (nt + 1) / 2) return;
+  int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((I + 1) * (I + 2) / 2 <= t) ++I;
+  while (I * (I + 1) / 2 > t) --I;
+  const int J = t - I * (I + 1) / 2;
   const int tid = threadIdx.x;
-  double* Mt = tk.M;
-  if (i == kblk || j == kblk) {
-    for (int e = tid; e < JB * JB; e += 256) {
-      const int r = e % JB, c = e / JB;
-      double v;
-      if (i == kblk && j == kblk) v = -tk.U[(size_t)c * np + kblk * JB + r];
-      else if (j == kblk) v = tk.U[(size_t)c * np + ib + r];
-      else v = tk.U[(size_t)r * np + jb + c];
-      Mt[(size_t)(jb + c) * np + ib + r] = v;
-    }
-    return;
-  }
-  for (int e = tid; e < JB * JB; e += 256) {
-    const int r = e % JB, q = e / JB;
-    Us[r * JLD + q] = tk.U[(size_t)q * np + ib + r];
-    Bs[r * JLD + q] = tk.Bp[(size_t)q * np + jb + r];
+  for (int e = tid; e < 4096; e += 256) {  // lower tile (rows I, cols J), negated in place
+    const int r = e % 64, c = e / 64;
+    const size_t at = (size_t)(J * 64 + c) * np + I * 64 + r;
+    if (I == J && r < c) continue;
+    const double v = -tk.M[at];
+    tk.M[at] = v;
+    T[c * 65 + r] = v;
   }
   __syncthreads();
-  const int lane = tid & 63, w = tid >> 6, l16 = lane & 15, g = lane >> 4;
-  v4d acc[4];
-#pragma unroll
-  for (int c = 0; c < 4; ++c) acc[c] = v4d{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < JB; k0 += 4) {
-    const double a = Us[(w * 16 + l16) * JLD + k0 + g];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) acc[c] = mfma64(a, Bs[(c * 16 + l16) * JLD + k0 + g], acc[c]);
-  }
-#pragma unroll
-  for (int c = 0; c < 4; ++c)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = ib + w * 16 + g + 4 * r, col = jb + c * 16 + l16;
-      Mt[(size_t)col * np + row] -= acc[c][r];
-    }
-}
-
-// M (holding -A^-1 in its lower triangle) -> A^-1, full symmetric
-__global__ void k_gj_finish(const InvTask* __restrict__ tasks) {
-  const InvTask tk = tasks[blockIdx.y];
-  const int np = tk.np;
-  const size_t tot = (size_t)np * np;
-  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
-       e += (size_t)gridDim.x * blockDim.x) {
-    const int r = (int)(e % np), c = (int)(e / np);
-    if (r >= c) {
-      const double v = -tk.M[(size_t)c * np + r];
-      tk.M[(size_t)c * np + r] = v;
-      if (r != c) tk.M[(size_t)r * np + c] = v;
-    }
+  for (int e = tid; e < 4096; e += 256) {  // upper tile (rows J, cols I): (J+c, I+r) = (I+r, J+c)
+    const int c = e % 64, r = e / 64;
+    if (I == J && c >= r) continue;  // diagonal tile: only its strict upper part
+    tk.M[(size_t)(I * 64 + r) * np + J * 64 + c] = T[c * 65 + r];
   }
 }
 
-void launch_gj_step(const InvTask* d_tasks, int n_tasks, int max_np, int kblk, hipStream_t s) {
-  const int maxblk = max_np / JB;
-  if (n_tasks <= 0 || kblk >= maxblk) return;
-  k_gj_pivot<<<n_tasks, 256, 0, s>>>(d_tasks, kblk);
-  k_gj_panel<<<dim3(maxblk, n_tasks), 256, 0, s>>>(d_tasks, kblk);
-  k_gj_update<<<dim3(maxblk * (maxblk + 1) / 2, n_tasks), 256, 0, s>>>(d_tasks, kblk);
-}
-
-void launch_gj_finish(const InvTask* d_tasks, int n_tasks, hipStream_t s) {
-  if (n_tasks <= 0) return;
-  k_gj_finish<<<dim3(1024, n_tasks), 256, 0, s>>>(d_tasks);
+void launch_gj_finish(const InvTask* d_tasks, int n_tasks, int max_np, hipStream_t s) {
+  const int nt = max_np / 64;
+  if (n_tasks > 0 && nt > 0)
+    k_gj_finish<<<dim3(nt * (nt + 1) / 2, n_tasks), 256, 0, s>>>(d_tasks);
 }
 
 // ---------------------------------------------------------------------------
-// Outer (block 256) level of the sweep.  Tiles are 64 x 64.
+// Outer (block 128) level of the sweep.  Tiles are 64 x 64.
 // ---------------------------------------------------------------------------
 int gj2_tiles(int np, int w) { return (np / 64) * (w / 64); }
 
@@ -847,7 +941,7 @@ __global__ __launch_bounds__(256) void k_mirror(const InvTask* __restrict__ task
   __syncthreads();
   for (int e = tid; e < 4096; e += 256) {  // upper tile (rows J, cols I): M[J+c, I+r] = T[c][r]
     const int c = e % 64, r = e / 64;
-    if (I == J && c <= r) continue;  // diagonal tile: only its strict upper part
+    if (I == J && c >= r) continue;  // diagonal tile: only its strict upper part
     tk.M[(size_t)(I * 64 + r) * np + J * 64 + c] = T[c * 65 + r];
   }
 }

@@ -148,35 +148,45 @@ struct GemmTask {
   int lower;          // 1: square C, only 128-tiles with row index >= column index
   int skip0, skip1;   // tiles meeting rows or columns [skip0, skip1) are skipped
 };
-int gemm_task_tiles(int M, int N, int lower);
-// mixed = 1: FP32 matrix-core products with FP64 accumulation across K chunks
+// tiles of ts x ts (lower: only tiles with row index >= column index)
+int gemm_task_tiles(int M, int N, int lower, int ts);
+// kernels: FP64 128 x 128 tiles; FP64 64 x 64 tiles (for launches with few
+// tiles); FP32 matrix-core products with FP64 accumulation across K chunks
+// (128 x 128 tiles)
+enum { kGemmF64 = 0, kGemmSmall = 1, kGemmMixed = 2 };
 void launch_gemm(const GemmTask* d_tasks, int n_tasks, int total_tiles, hipStream_t s,
-                 int mixed = 0);
+                 int kind);
 
-// Gauss-Jordan sweep inversion of SPD matrices, block 64 (in place; only the
-// lower triangle is kept current; the finish pass negates and symmetrizes).
+// Gauss-Jordan sweep inversion of SPD matrices (in place).
 struct InvTask {
   double* M;     // np x np col-major, ld = np
-  double* U;     // np x 64 workspace
-  double* Bp;    // np x 64 workspace
-  double* Pi;    // 64 x 64 workspace (inverse of the pivot block)
   int np;
   int nb;        // unpadded size (for work accounting)
-  int* info;     // set to (block index + 1) on non-SPD pivot
+  int* info;
 };
-// one rank-64 sweep step k of every task (tasks with np <= 64 k are skipped)
-void launch_gj_step(const InvTask* d_tasks, int n_tasks, int max_np, int kblk, hipStream_t s);
-void launch_gj_finish(const InvTask* d_tasks, int n_tasks, hipStream_t s);
+// M (holding -A^-1 in its lower triangle) -> A^-1, full symmetric
+void launch_gj_finish(const InvTask* d_tasks, int n_tasks, int max_np, hipStream_t s);
 
-// Outer level (block 256) of the sweep for large blocks: gather the column
+// Register-resident sweep of a block of order w <= 128 (full symmetric,
+// column-major, leading dimension ld): P <- P^-1.  A non-positive pivot p
+// sets *info = base + p + 1 (if still 0).
+struct SmallInvTask {
+  double* P;
+  int w, ld;
+  int* info;
+  int base;
+};
+void launch_inv128(const SmallInvTask* d_tasks, int n_tasks, hipStream_t s);
+
+// Outer level (block w = 128 or 256) of the sweep for large blocks: gather the column
 // block [kb, kb + w) of M (lower-stored) into B (np x w) and the pivot block
 // into P (w x w, ld w); after P <- P^-1 and U = B P, the GEMM updates the
 // lower tiles and the fix pass writes the swept row/column block.
 struct Gj2Task {
   double* M;
-  double* B;   // np x 256
-  double* U;   // np x 256
-  double* P;   // 256 x 256
+  double* B;   // np x w
+  double* U;   // np x w
+  double* P;   // w x w
   int np, kb, w;
   int tile_start;
 };
