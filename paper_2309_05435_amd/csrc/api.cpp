@@ -388,9 +388,15 @@ struct GemmList {
   }
   // choose the kernel and number the tiles; returns the total tile count
   int finalize(int* kind) {
-    int t128 = 0;
-    for (const GemmTask& t : v) t128 += gemm_task_tiles(t.M, t.N, t.lower, 128);
-    *kind = mixed ? kGemmMixed : (t128 < kSmallGemmTiles ? kGemmSmall : kGemmF64);
+    int t128 = 0, kmax = 0;
+    for (const GemmTask& t : v) {
+      t128 += gemm_task_tiles(t.M, t.N, t.lower, 128);
+      kmax = std::max(kmax, t.K);
+    }
+    // measured on MI355X: the 64-tile kernel is faster for short K (<= 256)
+    // at any tile count, and whenever the 128-tiles would not fill the device
+    *kind = mixed ? kGemmMixed
+                  : ((t128 < kSmallGemmTiles || kmax <= 256) ? kGemmSmall : kGemmF64);
     const int ts = (*kind == kGemmSmall) ? 64 : 128;
     int tiles = 0;
     for (GemmTask& t : v) {
@@ -400,27 +406,28 @@ struct GemmList {
     }
     return tiles;
   }
-  // outer sweep update of the lower tiles: M -= U B^T outside rows/cols [kb, kb + w)
+  // outer sweep update of the lower tiles: M -= Ut^T Bt outside rows/cols
+  // [kb, kb + w), with the transposed panels Ut, Bt (w x np, ld w)
   // (nb: unpadded size, for the algorithmic flops of the lower half)
-  void add_sweep(double* Mx, int np, const double* U, const double* B, int w, int kb, int nb) {
+  void add_sweep(double* Mx, int np, const double* Ut, const double* Bt, int w, int kb, int nb) {
     const double r = std::max(0, nb - w);
     flops += r * r * w;
     GemmTask t{};
-    t.A = U;
-    t.B = B;
+    t.A = Ut;
+    t.B = Bt;
     t.Cin = Mx;
     t.C = Mx;
     t.M = np;
     t.N = np;
     t.K = w;
-    t.lda = np;
-    t.ldb = np;
+    t.lda = w;
+    t.ldb = w;
     t.ldc = np;
     t.ldcin = np;
     t.alpha = -1.0;
     t.beta = 1.0;
-    t.transA = 0;
-    t.transB = 1;
+    t.transA = 1;
+    t.transB = 0;
     t.lower = 1;
     t.skip0 = kb;
     t.skip1 = kb + w;
@@ -461,8 +468,8 @@ struct InvJob {  // one SPD block to invert in place, with its workspace
   int np, nb;
   int* info;
   int base;            // row offset of M in the outermost block (for info)
-  double *B, *U, *P;   // np x 256, np x 256, 256 x 256: outer sweep panels and pivot block
-  double *B2, *U2, *P2; // 256 x 128, 256 x 128, 128 x 128: the same one level down
+  double *B, *U, *P;   // 256 x np, 256 x np, 256 x 256: transposed sweep panels, pivot block
+  double *B2, *U2, *P2; // 128 x 256, 128 x 256, 128 x 128: the same one level down
 };
 
 struct Op {
@@ -580,7 +587,8 @@ struct Program {
         in.U = j.U2;
         in.P = j.P2;
         inner.push_back(in);
-        gu.add(j.B, j.P, nullptr, j.U, j.np, w, w, j.np, w, j.np, 1.0, 0.0, 0, 0, j.np, w);
+        // Ut = P^-1 Bt (P^-1 symmetric, read through the transposed path)
+        gu.add(j.P, j.B, nullptr, j.U, w, j.np, w, w, w, w, 1.0, 0.0, 1, 0, w, w);
         gm.add_sweep(j.M, j.np, j.U, j.B, w, kb, j.nb);
       }
       Op og;

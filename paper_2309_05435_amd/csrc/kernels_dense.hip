@@ -725,7 +725,9 @@ __device__ inline int find_task(const T* __restrict__ tasks, int n_tasks, int b)
   return lo;
 }
 
-// B[r, c] = M[r, kb + c] (from the lower triangle), P = B[kb:kb+w, :]
+// Bt[c, r] = M[r, kb + c] (from the lower triangle; Bt is w x np, ld w, the
+// transposed column block), P[c, r'] = M[kb + r', kb + c] (w x w, ld w).
+// Tiles: (np/64) x (w/64) over (row block r0 of M, column c0 of the block).
 __global__ __launch_bounds__(256) void k_gj2_gather(const Gj2Task* __restrict__ tasks,
                                                     int n_tasks) {
   __shared__ double T[64 * 65];
@@ -735,7 +737,6 @@ __global__ __launch_bounds__(256) void k_gj2_gather(const Gj2Task* __restrict__ 
   const int r0 = (tile / tw) * 64, c0 = (tile % tw) * 64;
   const int np = tk.np, tid = threadIdx.x;
   const int col0 = tk.kb + c0;  // global column of the tile
-  const bool lower = r0 >= col0 + 64 || r0 == col0;  // whole tile (or diagonal tile) below
   if (r0 >= col0 + 64) {
     for (int e = tid; e < 4096; e += 256) {
       const int r = e % 64, c = e / 64;
@@ -753,46 +754,50 @@ __global__ __launch_bounds__(256) void k_gj2_gather(const Gj2Task* __restrict__ 
       T[c * 65 + r] = gr >= gc ? tk.M[(size_t)gc * np + gr] : tk.M[(size_t)gr * np + gc];
     }
   }
-  (void)lower;
   __syncthreads();
-  for (int e = tid; e < 4096; e += 256) {
-    const int r = e % 64, c = e / 64;
-    const double v = T[c * 65 + r];
-    tk.B[(size_t)(c0 + c) * np + r0 + r] = v;
-    const int pr = r0 + r - tk.kb;
-    if (pr >= 0 && pr < tk.w) tk.P[(size_t)(c0 + c) * tk.w + pr] = v;
+  for (int e = tid; e < 4096; e += 256) {  // Bt column r0 + r holds row r0 + r of B
+    const int c = e % 64, r = e / 64;
+    tk.B[(size_t)(r0 + r) * tk.w + c0 + c] = T[c * 65 + r];
+  }
+  if (r0 + 64 > tk.kb && r0 < tk.kb + tk.w) {  // the pivot rows: P is symmetric
+    for (int e = tid; e < 4096; e += 256) {
+      const int c = e % 64, r = e / 64;
+      tk.P[(size_t)(r0 - tk.kb + r) * tk.w + c0 + c] = T[c * 65 + r];
+    }
   }
 }
 
-// Swept block row/column: M[r, kb+c] = U[r, c] (r >= kb + w),
-// M[kb+r, j] = U[j, r] (j < kb), M[kb+r, kb+c] = -P^-1[r, c].
-// Tiles: (np/64) x (w/64) over (row block of U, column c).
+// Swept row/column block from Ut = P^-1 Bt (w x np, ld w):
+//   M[r, kb + c] = Ut[c, r] for r >= kb + w (below the pivot, lower storage),
+//   M[kb + c, j] = Ut[c, j] for j < kb (stored at column j, row kb + c),
+//   M[kb + r, kb + c] = -P^-1[r, c].
+// Tiles: (np/64) x (w/64) over (row block r0, column c0 of the block).
 __global__ __launch_bounds__(256) void k_gj2_fix(const Gj2Task* __restrict__ tasks, int n_tasks) {
   __shared__ double T[64 * 65];
   const Gj2Task tk = tasks[find_task(tasks, n_tasks, blockIdx.x)];
   const int tile = blockIdx.x - tk.tile_start;
   const int tw = tk.w / 64;
   const int r0 = (tile / tw) * 64, c0 = (tile % tw) * 64;
-  const int np = tk.np, tid = threadIdx.x, kb = tk.kb;
-  if (r0 >= kb + tk.w) {  // below the pivot: column block
+  const int np = tk.np, tid = threadIdx.x, kb = tk.kb, w = tk.w;
+  if (r0 >= kb + w) {  // below the pivot: transpose through LDS so both sides coalesce
     for (int e = tid; e < 4096; e += 256) {
-      const int r = e % 64, c = e / 64;
-      tk.M[(size_t)(kb + c0 + c) * np + r0 + r] = tk.U[(size_t)(c0 + c) * np + r0 + r];
-    }
-  } else if (r0 < kb) {  // left of the pivot: row block (lower part), transposed
-    for (int e = tid; e < 4096; e += 256) {
-      const int r = e % 64, c = e / 64;
-      T[c * 65 + r] = tk.U[(size_t)(c0 + c) * np + r0 + r];  // U[j = r0+r, c0+c]
+      const int c = e % 64, r = e / 64;
+      T[c * 65 + r] = tk.U[(size_t)(r0 + r) * w + c0 + c];
     }
     __syncthreads();
     for (int e = tid; e < 4096; e += 256) {
-      const int c = e % 64, r = e / 64;  // M[kb + c0 + c, r0 + r] = U[r0 + r, c0 + c]
-      tk.M[(size_t)(r0 + r) * np + kb + c0 + c] = T[c * 65 + r];
+      const int r = e % 64, c = e / 64;
+      tk.M[(size_t)(kb + c0 + c) * np + r0 + r] = T[c * 65 + r];
+    }
+  } else if (r0 < kb) {  // left of the pivot: row block kb.., columns r0..
+    for (int e = tid; e < 4096; e += 256) {
+      const int c = e % 64, r = e / 64;
+      tk.M[(size_t)(r0 + r) * np + kb + c0 + c] = tk.U[(size_t)(r0 + r) * w + c0 + c];
     }
   } else {  // pivot block
     for (int e = tid; e < 4096; e += 256) {
       const int r = e % 64, c = e / 64;
-      tk.M[(size_t)(kb + c0 + c) * np + r0 + r] = -tk.P[(size_t)(c0 + c) * tk.w + (r0 - kb) + r];
+      tk.M[(size_t)(kb + c0 + c) * np + r0 + r] = -tk.P[(size_t)(c0 + c) * w + (r0 - kb) + r];
     }
   }
 }

@@ -178,14 +178,17 @@ struct SmallInvTask {
 };
 void launch_inv128(const SmallInvTask* d_tasks, int n_tasks, hipStream_t s);
 
-// Outer level (block w = 128 or 256) of the sweep for large blocks: gather the column
-// block [kb, kb + w) of M (lower-stored) into B (np x w) and the pivot block
-// into P (w x w, ld w); after P <- P^-1 and U = B P, the GEMM updates the
-// lower tiles and the fix pass writes the swept row/column block.
+// Outer level (block w = 128 or 256) of the sweep for large blocks: gather
+// the column block [kb, kb + w) of M (lower-stored) transposed into B (w x np,
+// ld w) and the pivot block into P (w x w, ld w); after P <- P^-1 and
+// U = P B (w x np: the transposed panel P^-1 B^T), the GEMM updates the lower
+// tiles (M -= U^T B) and the fix pass writes the swept row/column block.
+// Both panels are kept transposed so every product reads its operands in
+// the GEMM's fast orientation.
 struct Gj2Task {
   double* M;
-  double* B;   // np x w
-  double* U;   // np x w
+  double* B;   // w x np
+  double* U;   // w x np
   double* P;   // w x w
   int np, kb, w;
   int tile_start;
