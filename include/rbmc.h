@@ -119,7 +119,16 @@ typedef struct {
 } rbmc_report;
 
 /* Create a context on HIP device `device`; hip_stream is a hipStream_t (NULL
- * = the default stream).  The stream is not owned. */
+ * = the default stream).  The stream is not owned.
+ * Scheduling of rbmc_estimate / rbmc_estimate_batched (environment, read
+ * here): by default the sampler and the corrections run on one library
+ * stream, the subdomain factorization on a second one (which can be kept
+ * off RBMC_RESERVE_CUS compute units, default 0), and the Takahashi sweep on
+ * a third; the factorization and
+ * sweep are enqueued by their own host thread, and the given stream waits
+ * for all of it.  RBMC_OVERLAP=0 runs everything one step after the other on
+ * the given stream; RBMC_LAUNCH_THREADS=1 enqueues all streams from the
+ * calling thread. */
 rbmc_status rbmc_ctx_create(int device, void* hip_stream, rbmc_ctx** out);
 void rbmc_ctx_destroy(rbmc_ctx* ctx);
 
@@ -192,6 +201,49 @@ rbmc_status rbmc_estimate_batched(rbmc_ctx* ctx, int32_t n_models, rbmc_model* c
                                   double* const* diag_out, double* const* trace_out,
                                   rbmc_report* rep);
 
+/* Learned correction of the block-Jacobi preconditioner (used when
+ * opts->precond = RBMC_PC_BJ_LEARNED; not part of the paper's method).  The
+ * preconditioned residual becomes z = M_BJ^-1 r + N_w(r), with N_w four 3-D
+ * convolutions 3x3x3 over the (t, y, x) grid of a sample (channels
+ * 1 -> 16 -> 16 -> 16 -> 1, ReLU between, no bias, zero outside the grid),
+ * BF16 weights and FP32 accumulation, applied to r / ||r|| and scaled back;
+ * PCG then uses the flexible (Polak-Ribiere) update.  A model whose trained
+ * correction did not reduce the held-out error falls back to plain block
+ * Jacobi.  Weight vector (RBMC_PC_NWEIGHTS floats): layer l's W[co][ci][tap]
+ * after layer l-1's, tap = (dt+1)*9 + (dy+1)*3 + (dx+1). */
+#define RBMC_PC_NWEIGHTS 14688
+typedef struct {
+  int32_t n_pairs;  /* training pairs (>= 2), e.g. 2000 */
+  int32_t epochs;   /* passes over the pairs (>= 0) */
+  int32_t batch;    /* pairs per Adam step (0: 8) */
+  float lr;         /* Adam step size (0: 1e-3) */
+  uint64_t seed;    /* crop positions, pair order, initial weights */
+  int32_t crop_t, crop_xy; /* crop interior: time steps, grid side (0: 16, 64) */
+} rbmc_train_opts;
+
+/* Train N_w on pairs the sampler generates: a block-Jacobi PCG run on the
+ * right-hand sides F z gives x*; an identical second run stops at evenly
+ * spaced iterations k, where the preconditioner's remaining error is
+ * t_k = (x* - x_k) - M_BJ^-1 r_k; random crops of (r_k, t_k) / ||r_k|| (with
+ * the network's 4-voxel halo) are the pairs; Adam minimizes the mean of
+ * ||N_w(r) - t||^2 / ||t||^2 over crop interiors.  The last tenth of the
+ * pairs is held out: its relative error sqrt(sum ||N_w(r)-t||^2 / sum ||t||^2)
+ * goes to loss_out[epochs] (and the report's err_estimate); loss_out[e] is the
+ * training loss of epoch e (host, epochs + 1 floats, may be NULL).  The
+ * correction is used only if the held-out error is below 1.
+ * z: device (n + n_obs) x n_train standard normals; pcg_opts: pcg_maxit and
+ * pcg_rtol of the pair-generating runs. */
+rbmc_status rbmc_precond_train(rbmc_model* m, const rbmc_est_opts* pcg_opts,
+                               const rbmc_train_opts* train_opts, const double* z,
+                               int32_t n_train, float* loss_out, rbmc_report* rep);
+/* y = N_w(r) for n_rhs device vectors (no normalization); for testing. */
+rbmc_status rbmc_precond_apply(rbmc_model* m, const double* r, double* y, int32_t n_rhs);
+/* Weights (host, RBMC_PC_NWEIGHTS floats), whether they are used, and the
+ * held-out error of the last training (-1 if set directly). */
+rbmc_status rbmc_precond_get_weights(rbmc_model* m, float* w, int32_t* usable,
+                                     double* val_rel_err);
+rbmc_status rbmc_precond_set_weights(rbmc_model* m, const float* w);
+
 /* Planner query, host only (no device needed): core label of every node
  * (label_out, length n) and, for core p, the node state (state_out, length
  * n: 1 core, 2 overlap, 3 separator, 0 outside). Either output may be NULL. */
@@ -201,8 +253,8 @@ rbmc_status rbmc_plan_query(const rbmc_model_desc* desc, const rbmc_decomp_desc*
 /* Instrumentation (for throughput and roofline reporting, not part of the
  * method).  While enabled, every launch of a kernel family is bracketed by
  * HIP events on the context stream and its algorithmic work is counted:
- *   RBMC_KF_GEMM         dense products on the FP64 matrix cores (one kernel,
- *                        also those inside the inversions); flops = 2 M K N
+ *   RBMC_KF_GEMM         dense products on the FP64 matrix cores, 128 x 128
+ *                        tiles (also those inside the inversions); flops = 2 M K N
  *                        over the unpadded block sizes (lower-half updates:
  *                        half of that);
  *   RBMC_KF_SPD_INVERSE  one Gauss-Jordan inversion batch, all its kernels
@@ -215,7 +267,11 @@ rbmc_status rbmc_plan_query(const rbmc_model_desc* desc, const rbmc_decomp_desc*
  *   RBMC_KF_PANELS       gathers/scatters/right-hand sides; bytes = 16 per
  *                        panel entry;
  *   RBMC_KF_GEMM_MIXED   dense products on the FP32 matrix cores (RBMC_MIXED);
- *                        flops as RBMC_KF_GEMM.
+ *                        flops as RBMC_KF_GEMM;
+ *   RBMC_KF_GEMM_SMALL   FP64 matrix-core products with 64 x 64 tiles (short
+ *                        K or few tiles); flops as RBMC_KF_GEMM;
+ *   RBMC_KF_INV_SMALL    register-resident inversions of blocks of order
+ *                        w <= 128 (one workgroup each); flops = sum w^3.
  * rbmc_ctx_profile(ctx, 1) clears and enables, (ctx, 0) disables;
  * rbmc_ctx_profile_read synchronizes the stream and sums the records. */
 enum {
@@ -225,7 +281,9 @@ enum {
   RBMC_KF_RSTENCIL = 3,
   RBMC_KF_PANELS = 4,
   RBMC_KF_GEMM_MIXED = 5,
-  RBMC_KF_COUNT = 6
+  RBMC_KF_GEMM_SMALL = 6,
+  RBMC_KF_INV_SMALL = 7,
+  RBMC_KF_COUNT = 8
 };
 typedef struct {
   int64_t launches;

@@ -24,10 +24,15 @@ RBMC_GRAD_LOGKAPPA, RBMC_GRAD_LOGTAU, RBMC_GRAD_RHO, RBMC_GRAD_LOGSIGMA = 1, 2, 
 EXPORTS = ["rbmc_ctx_create", "rbmc_ctx_destroy", "rbmc_model_create", "rbmc_model_destroy",
            "rbmc_model_set_theta", "rbmc_apply_op", "rbmc_sample", "rbmc_estimate_from_samples",
            "rbmc_estimate", "rbmc_estimate_batched", "rbmc_plan_query", "rbmc_ctx_profile",
-           "rbmc_ctx_profile_read", "rbmc_last_error"]
+           "rbmc_ctx_profile_read", "rbmc_precond_train", "rbmc_precond_apply",
+           "rbmc_precond_get_weights", "rbmc_precond_set_weights", "rbmc_last_error"]
+RBMC_PC_NWEIGHTS = 14688
+# (cin, cout) of the learned correction's four convolutions, in weight order
+PC_LAYERS = [(1, 16), (16, 16), (16, 16), (16, 1)]
 (RBMC_KF_GEMM, RBMC_KF_SPD_INVERSE, RBMC_KF_SPMM, RBMC_KF_RSTENCIL, RBMC_KF_PANELS,
- RBMC_KF_GEMM_MIXED, RBMC_KF_COUNT) = range(7)
-KF_NAMES = ["gemm", "spd_inverse", "spmm", "rstencil", "panels", "gemm_mixed"]
+ RBMC_KF_GEMM_MIXED, RBMC_KF_GEMM_SMALL, RBMC_KF_INV_SMALL, RBMC_KF_COUNT) = range(9)
+KF_NAMES = ["gemm", "spd_inverse", "spmm", "rstencil", "panels", "gemm_mixed", "gemm_small",
+            "inv_small"]
 
 
 class rbmc_kernel_stats(C.Structure):
@@ -51,6 +56,12 @@ class rbmc_est_opts(C.Structure):
     _fields_ = [("n_samples", C.c_int32), ("pcg_maxit", C.c_int32), ("pcg_rtol", C.c_double),
                 ("precision", C.c_int32), ("precond", C.c_int32), ("grad_mask", C.c_uint32),
                 ("sample_chunk", C.c_int32)]
+
+
+class rbmc_train_opts(C.Structure):
+    _fields_ = [("n_pairs", C.c_int32), ("epochs", C.c_int32), ("batch", C.c_int32),
+                ("lr", C.c_float), ("seed", C.c_uint64), ("crop_t", C.c_int32),
+                ("crop_xy", C.c_int32)]
 
 
 class rbmc_report(C.Structure):
@@ -97,6 +108,13 @@ def lib():
                                       C.c_int32, vp, vp]
         L.rbmc_ctx_profile.argtypes = [vp, C.c_int]
         L.rbmc_ctx_profile_read.argtypes = [vp, C.c_int, C.POINTER(rbmc_kernel_stats)]
+        L.rbmc_precond_train.argtypes = [vp, C.POINTER(rbmc_est_opts), C.POINTER(rbmc_train_opts),
+                                         vp, C.c_int32, C.POINTER(C.c_float),
+                                         C.POINTER(rbmc_report)]
+        L.rbmc_precond_apply.argtypes = [vp, vp, vp, C.c_int32]
+        L.rbmc_precond_get_weights.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(C.c_int32),
+                                               C.POINTER(C.c_double)]
+        L.rbmc_precond_set_weights.argtypes = [vp, C.POINTER(C.c_float)]
         L.rbmc_last_error.restype = C.c_char_p
         for name in EXPORTS:
             if name not in ("rbmc_ctx_destroy", "rbmc_model_destroy", "rbmc_last_error"):
@@ -189,6 +207,35 @@ def rbmc_estimate_batched(ctx, models, opts, zs, diag_outs, n_trace):
     return st, [list(t)[:n_trace] for t in trs], rep
 
 
+def rbmc_precond_train(m, pcg_opts, train_opts, z, n_train):
+    loss = (C.c_float * (train_opts.epochs + 1))()
+    rep = rbmc_report()
+    st = check(lib().rbmc_precond_train(m, C.byref(pcg_opts), C.byref(train_opts), _ptr(z),
+                                        n_train, loss, C.byref(rep)))
+    return st, list(loss), rep
+
+
+def rbmc_precond_apply(m, r, y, n_rhs):
+    return check(lib().rbmc_precond_apply(m, _ptr(r), _ptr(y), n_rhs))
+
+
+def rbmc_precond_get_weights(m):
+    import numpy as np
+    w = np.zeros(RBMC_PC_NWEIGHTS, np.float32)
+    usable = C.c_int32()
+    err = C.c_double()
+    check(lib().rbmc_precond_get_weights(m, w.ctypes.data_as(C.POINTER(C.c_float)),
+                                         C.byref(usable), C.byref(err)))
+    return w, bool(usable.value), err.value
+
+
+def rbmc_precond_set_weights(m, w):
+    import numpy as np
+    w = np.ascontiguousarray(w, np.float32)
+    assert w.shape == (RBMC_PC_NWEIGHTS,)
+    return check(lib().rbmc_precond_set_weights(m, w.ctypes.data_as(C.POINTER(C.c_float))))
+
+
 def rbmc_plan_query(desc, decomp, p, label_out=None, state_out=None):
     """label_out / state_out: numpy int32 / uint8 arrays of length n (host)."""
     lp = None if label_out is None else label_out.ctypes.data_as(C.c_void_p)
@@ -220,6 +267,10 @@ def make_desc(mx, my, T, h, theta, mask):
 def make_opts(n_samples, pcg_maxit=2000, pcg_rtol=1e-8, grad_mask=0b111,
               precision=RBMC_FP64, precond=RBMC_PC_BJ):
     return rbmc_est_opts(n_samples, pcg_maxit, pcg_rtol, precision, precond, grad_mask, 0)
+
+
+def make_train_opts(n_pairs=2000, epochs=5, batch=8, lr=1e-3, seed=1, crop_t=0, crop_xy=0):
+    return rbmc_train_opts(n_pairs, epochs, batch, lr, seed, crop_t, crop_xy)
 
 
 def popcount(mask: int) -> int:

@@ -9,11 +9,13 @@
 // launch per kernel, not one per subdomain or per model.
 #include <algorithm>
 #include <array>
+#include <cstdlib>
 #include <chrono>
 #include <cmath>
 #include <cstring>
 #include <functional>
 #include <mutex>
+#include <random>
 #include <string>
 #include <thread>
 #include <vector>
@@ -107,14 +109,20 @@ struct ProfRec {
 struct rbmc_ctx {
   int device;
   hipStream_t stream;         // the caller's stream: all results are ordered on it
-  hipStream_t side = nullptr; // library stream for work that overlaps the sampler
-  hipEvent_t join[4] = {nullptr, nullptr, nullptr, nullptr};
+  // library streams of the overlapped estimate: the sampler and the
+  // corrections (work), the subdomain factorization (side, kept off
+  // `reserve_cus` compute units so the sampler's serial chain always finds a
+  // free CU) and the Takahashi sweep (side2, all CUs)
+  hipStream_t work = nullptr, side = nullptr, side2 = nullptr;
+  int reserve_cus = 0;  // measured on MI355X: no gain from reserving CUs (0/32/64 equal, 16 worse)
+  hipEvent_t join[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   Arena arenaA, arenaB;       // task lists of work on the caller's / side stream
   // concatenated sample-column workspace of the sampler (sized per call)
   Pool ws;
   size_t ws_len = 0, ws_zlen = 0;
   int ws_cols = 0, ws_models = 0;
   double *r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr, *x = nullptr, *zcat = nullptr;
+  double* zp = nullptr;        // previous preconditioned residual (flexible PCG)
   double* scal = nullptr;      // 8 x columns
   double* part = nullptr;      // column partial sums
   size_t part_len = 0;
@@ -126,6 +134,12 @@ struct rbmc_ctx {
   double* epart = nullptr;     // estimator partial sums
   size_t epart_len = 0;
   Pool epool;
+  // scheduling of rbmc_estimate*: overlap the sampler with the subdomain
+  // factorization + Takahashi sweep on a second stream (else one after the
+  // other on the context stream), and enqueue the two streams from two host
+  // threads (else from one)
+  bool overlap = true;
+  bool launch_threads = true;
   // instrumentation (records may be added from two host threads)
   bool prof = false;
   std::mutex prof_mu;
@@ -169,6 +183,8 @@ struct rbmc_ctx {
     for (hipEvent_t e : join)
       if (e) (void)hipEventDestroy(e);
     if (side) (void)hipStreamDestroy(side);
+    if (side2) (void)hipStreamDestroy(side2);
+    if (work) (void)hipStreamDestroy(work);
     ws.release();
     epool.release();
   }
@@ -243,6 +259,18 @@ struct rbmc_model {
   ChainSet bj, sub;
   int* d_info = nullptr;  // one per chain: bj then sub
   bool bj_ready = false, sub_ready = false;
+  // learned correction to the block-Jacobi preconditioner
+  struct Learned {
+    bool ready = false;          // weights present
+    bool usable = false;         // validated: reduces the preconditioner error
+    double val_rel_err = -1.0;   // held-out ||N(r) - t|| / ||t|| after training
+    float* w = nullptr;          // FP32 weights (device)
+    uint16_t* wb = nullptr;      // BF16 weights used by the kernels
+    uint16_t* wf = nullptr;      // BF16 flipped/transposed weights (input gradients)
+    float *am = nullptr, *av = nullptr, *g = nullptr;  // Adam moments, gradient
+  } lrn;
+  Pool lwork;                    // inference activations
+  size_t lwork_cols = 0;
 };
 
 // ---------------------------------------------------------------------------
@@ -495,7 +523,9 @@ struct Program {
     o.tiles = g.finalize(&o.kblk);
     o.off = a.push(g.v);
     o.n = (int)g.v.size();
-    o.family = profiled ? (g.mixed ? RBMC_KF_GEMM_MIXED : RBMC_KF_GEMM) : -1;
+    o.family = !profiled ? -1
+               : o.kblk == kGemmMixed ? RBMC_KF_GEMM_MIXED
+               : o.kblk == kGemmSmall ? RBMC_KF_GEMM_SMALL : RBMC_KF_GEMM;
     o.alg_flops = g.flops;
     ops.push_back(o);
   }
@@ -527,6 +557,8 @@ struct Program {
     o.kind = 2;
     o.off = a.push(t);
     o.n = (int)t.size();
+    o.family = RBMC_KF_INV_SMALL;
+    for (const SmallInvTask& k : t) o.alg_flops += (double)k.w * k.w * k.w;
     ops.push_back(o);
   }
   // In-place inversion of SPD blocks: blocks up to 128 in registers; larger
@@ -808,10 +840,11 @@ void build_solve(ChainSet& cs, int n_k, const std::vector<int>& stop, Program& p
   }
 }
 
-rbmc_status check_info(const ChainSet& cs, rbmc_report* rep, const char* what) {
+rbmc_status check_info(const ChainSet& cs, rbmc_report* rep, const char* what, hipStream_t s) {
   for (size_t c = 0; c < cs.size(); ++c) {
     int v = 0;
-    HIPCHK(hipMemcpy(&v, cs.info[c], 4, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpyAsync(&v, cs.info[c], 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
     if (v != 0) {
       if (rep) {
         rep->fail_subdomain = (int)c;
@@ -851,8 +884,6 @@ rbmc_status check_opts(const rbmc_est_opts* o, bool need_pcg) {
     return fail(RBMC_E_ARG, "precision must be RBMC_FP64 or RBMC_MIXED");
   if (o->precond != RBMC_PC_BJ && o->precond != RBMC_PC_BJ_LEARNED)
     return fail(RBMC_E_ARG, "precond must be RBMC_PC_BJ or RBMC_PC_BJ_LEARNED");
-  if (o->precond == RBMC_PC_BJ_LEARNED)
-    return fail(RBMC_E_UNSUPPORTED, "the learned preconditioner correction is not built");
   return RBMC_OK;
 }
 
@@ -914,6 +945,7 @@ rbmc_status ensure_ws(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const Ho
     HIPCHK(cx->ws.alloc((void**)&cx->q, len * 8));
     HIPCHK(cx->ws.alloc((void**)&cx->z, len * 8));
     HIPCHK(cx->ws.alloc((void**)&cx->x, len * 8));
+    HIPCHK(cx->ws.alloc((void**)&cx->zp, len * 8));
     if (need_zcat) {
       HIPCHK(cx->ws.alloc((void**)&cx->zcat, std::max<size_t>(h.ztotal, 1) * 8));
       cx->ws_zlen = h.ztotal;
@@ -964,12 +996,12 @@ ColSet colset(rbmc_ctx* cx, const HostCols& h) {
 }
 
 // Factor the block-Jacobi chains of every model that needs it (one program).
-rbmc_status factor_bj(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, rbmc_report* rep) {
+rbmc_status factor_bj(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, rbmc_report* rep,
+                      hipStream_t s) {
   ChainSet cs;
   for (rbmc_model* m : ms)
     if (!m->bj_ready) cs.append(m->bj);
   if (cs.size() == 0) return RBMC_OK;
-  hipStream_t s = cx->stream;
   rbmc_status st = zero_info(cs, s);
   if (st != RBMC_OK) return st;
   cx->arenaA.clear();
@@ -979,7 +1011,7 @@ rbmc_status factor_bj(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, rbmc_rep
   st = run(cx, pg, s, cx->arenaA);
   if (st != RBMC_OK) return st;
   HIPCHK(hipStreamSynchronize(s));
-  st = check_info(cs, rep, "block-Jacobi");
+  st = check_info(cs, rep, "block-Jacobi", s);
   if (st != RBMC_OK) return st;
   for (rbmc_model* m : ms) m->bj_ready = true;
   return RBMC_OK;
@@ -987,12 +1019,26 @@ rbmc_status factor_bj(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, rbmc_rep
 
 // Block-Jacobi PCG on Q x = F z for every column of the set (caller's stream).
 // z, x: multi-vectors in the column layout h (z with n + n_obs per column).
+// Learned correction y += N_w(r) for the columns of one model (defined below).
+rbmc_status learned_apply(rbmc_ctx* cx, rbmc_model* m, const double* r, const double* rr,
+                          const uint8_t* active, double* y, int ncols, int accumulate,
+                          hipStream_t s);
+bool learned_usable(const rbmc_model* m);
+
+// Per-iteration observer of the sampler (pair generation for training): called
+// after the preconditioner of iteration it, with x = x_it, r = r_it, z = M^-1 r_it.
+using SampleHook = std::function<rbmc_status(int it, const double* x, const double* r,
+                                             const double* z, const double* rr)>;
+
 rbmc_status sample_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const HostCols& h,
-                       const rbmc_est_opts* o, const double* z, double* x, rbmc_report* rep) {
+                       const rbmc_est_opts* o, const double* z, double* x, rbmc_report* rep,
+                       hipStream_t s, const SampleHook& hook = {}) {
   const int nk = o->n_samples;
-  hipStream_t s = cx->stream;
   double t0 = now_s();
-  rbmc_status st = factor_bj(cx, ms, rep);
+  // the learned correction makes the preconditioner vary between iterations:
+  // flexible (Polak-Ribiere) PCG, z_prev kept in zp
+  const bool learned = o->precond == RBMC_PC_BJ_LEARNED;
+  rbmc_status st = factor_bj(cx, ms, rep, s);
   if (st != RBMC_OK) return st;
   const ColSet cols = colset(cx, h);
   const int nc = cols.ncols;
@@ -1048,13 +1094,26 @@ rbmc_status sample_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const H
   build_solve(cs, nk, stop, pre, ar, o->precision == RBMC_MIXED);
   sca.panels(ar, sc);
   HIPCHK(ar.upload(s));
-  auto precond = [&]() -> rbmc_status {
+  // z = M^-1 r (+ N_w(r) per model); rrv: the current squared residual norms
+  auto precond = [&](const double* rrv) -> rbmc_status {
     rbmc_status e = run(cx, gat, s, ar);
     if (e != RBMC_OK) return e;
     e = run(cx, pre, s, ar);
     if (e != RBMC_OK) return e;
-    return run(cx, sca, s, ar);
+    e = run(cx, sca, s, ar);
+    if (e != RBMC_OK || !learned) return e;
+    int col0 = 0;
+    for (size_t j = 0; j < ms.size(); ++j) {
+      if (learned_usable(ms[j])) {
+        e = learned_apply(cx, ms[j], r + h.base[j], rrv + col0, cx->active + col0,
+                          zz + h.base[j], nk, 1, s);
+        if (e != RBMC_OK) return e;
+      }
+      col0 += nk;
+    }
+    return RBMC_OK;
   };
+  double* rzp = cx->scal + 5 * nc;
   // b = F z -> r; x = 0
   launch_apply_op(cols, RBMC_OP_F, z, r, s);
   HIPCHK(hipMemsetAsync(x, 0, h.total * 8, s));
@@ -1067,8 +1126,12 @@ rbmc_status sample_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const H
   for (int k = 0; k < nc; ++k) act[k] = hbb[k] > 0.0;
   HIPCHK(hipMemcpyAsync(cx->active, act.data(), nc, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemsetAsync(cx->iters, 0, (size_t)(nc + 1) * 4, s));
-  st = precond();
+  st = precond(bb);
   if (st != RBMC_OK) return st;
+  if (hook) {
+    st = hook(0, x, r, zz, bb);
+    if (st != RBMC_OK) return st;
+  }
   launch_dot_partials(cols, r, zz, cx->part, s);
   launch_reduce_partials(cx->part, nch, nc, rz, s);
   launch_pcg_p(cols, zz, p, rz, rz, cx->active, 1, s);
@@ -1088,11 +1151,20 @@ rbmc_status sample_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const H
     HIPCHK(hipStreamSynchronize(s));
     ++it;
     if (n_active == 0) break;
-    st = precond();
+    if (learned) HIPCHK(hipMemcpyAsync(cx->zp, zz, h.total * 8, hipMemcpyDeviceToDevice, s));
+    st = precond(rr);
     if (st != RBMC_OK) return st;
+    if (hook) {
+      st = hook(it, x, r, zz, rr);
+      if (st != RBMC_OK) return st;
+    }
     launch_dot_partials(cols, r, zz, cx->part, s);
     launch_reduce_partials(cx->part, nch, nc, rzn, s);
-    launch_pcg_p(cols, zz, p, rzn, rz, cx->active, 0, s);
+    if (learned) {
+      launch_dot_partials(cols, r, cx->zp, cx->part, s);
+      launch_reduce_partials(cx->part, nch, nc, rzp, s);
+    }
+    launch_pcg_p(cols, zz, p, rzn, rz, cx->active, 0, s, learned ? rzp : nullptr);
   }
   HIPCHK(hipGetLastError());
   std::vector<int> iters(nc + 1);
@@ -1116,6 +1188,34 @@ rbmc_status sample_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const H
   return n_active > 0 ? RBMC_W_NOT_CONVERGED : RBMC_OK;
 }
 
+// Library streams of the overlapped estimate (created once per context).
+// The factorization stream excludes `reserve_cus` compute units, spread
+// evenly over the device, so that the sampler's chain of small serial
+// kernels always finds a free CU; the other two use every CU.
+rbmc_status ensure_streams(rbmc_ctx* cx) {
+  if (cx->work) return RBMC_OK;
+  HIPCHK(hipStreamCreateWithFlags(&cx->work, hipStreamNonBlocking));
+  HIPCHK(hipStreamCreateWithFlags(&cx->side2, hipStreamNonBlocking));
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, cx->device));
+  const int ncu = prop.multiProcessorCount;
+  const int r = cx->reserve_cus;
+  if (r > 0 && r < ncu) {
+    const int stride = ncu / r;
+    std::vector<uint32_t> mask((ncu + 31) / 32, 0u);
+    for (int i = 0; i < ncu; ++i)
+      if (i % stride != stride - 1 || i / stride >= r) mask[i / 32] |= 1u << (i % 32);
+    if (hipExtStreamCreateWithCUMask(&cx->side, (uint32_t)mask.size(), mask.data()) !=
+        hipSuccess) {
+      (void)hipGetLastError();
+      cx->side = nullptr;
+    }
+  }
+  if (!cx->side) HIPCHK(hipStreamCreateWithFlags(&cx->side, hipStreamNonBlocking));
+  for (hipEvent_t& e : cx->join) HIPCHK(hipEventCreate(&e));
+  return RBMC_OK;
+}
+
 // The estimator from samples for a set of models.  x_base: the samples in the
 // column layout h (ignored when n_k = 0).  The subdomain factorization and the
 // Takahashi sweep do not need the samples: when `sampler` is given they run on
@@ -1128,12 +1228,15 @@ rbmc_status estimate_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const
                          const std::function<rbmc_status()>& sampler) {
   const int nk = o->n_samples;
   const int mixed = o->precision == RBMC_MIXED;
-  hipStream_t sA = cx->stream;
-  if (sampler && !cx->side) {
-    HIPCHK(hipStreamCreateWithFlags(&cx->side, hipStreamNonBlocking));
-    for (hipEvent_t& e : cx->join) HIPCHK(hipEventCreate(&e));
+  if (sampler) {
+    rbmc_status e = ensure_streams(cx);
+    if (e != RBMC_OK) return e;
   }
-  hipStream_t s = sampler ? cx->side : sA;  // stream of factorization + Takahashi
+  // sA: sampler (when overlapped) and corrections; s: factorization;
+  // sT: Takahashi sweep
+  hipStream_t sA = sampler ? cx->work : cx->stream;
+  hipStream_t s = sampler ? cx->side : sA;
+  hipStream_t sT = sampler ? cx->side2 : sA;
   double t0 = now_s();
   // combined subdomain chain set and per-chain model index
   ChainSet cs;
@@ -1307,10 +1410,11 @@ rbmc_status estimate_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const
     }
     cor.mc(ar, mt);
   }
-  // the side stream starts after everything already queued on the caller's stream
-  if (s != sA) {
-    HIPCHK(hipEventRecord(cx->join[0], sA));
+  // the library streams start after everything already queued on the caller's stream
+  if (sampler) {
+    HIPCHK(hipEventRecord(cx->join[0], cx->stream));
     HIPCHK(hipStreamWaitEvent(s, cx->join[0], 0));
+    HIPCHK(hipStreamWaitEvent(sA, cx->join[0], 0));
   }
   HIPCHK(ar.upload(s));
   HIPCHK(hipMemsetAsync(cx->epart, 0, need * 8, s));
@@ -1338,41 +1442,54 @@ rbmc_status estimate_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const
     if (st_b == RBMC_OK) st_b = run(cx, fac, s, ar);
     if (st_b == RBMC_OK && e_fac && hipEventRecord(e_fac, s) != hipSuccess)
       st_b = fail(RBMC_E_DEVICE, "hipEventRecord failed");
-    if (st_b == RBMC_OK) st_b = run(cx, tak, s, ar);
-    if (st_b == RBMC_OK && e_tak && hipEventRecord(e_tak, s) != hipSuccess)
+    if (st_b == RBMC_OK && sT != s && hipStreamWaitEvent(sT, e_fac, 0) != hipSuccess)
+      st_b = fail(RBMC_E_DEVICE, "hipStreamWaitEvent failed");
+    if (st_b == RBMC_OK) st_b = run(cx, tak, sT, ar);
+    if (st_b == RBMC_OK && e_tak && hipEventRecord(e_tak, sT) != hipSuccess)
       st_b = fail(RBMC_E_DEVICE, "hipEventRecord failed");
     if (st_b != RBMC_OK) err_b = g_err;
   };
   rbmc_status st_samp = RBMC_OK;
   if (sampler) {
-    std::thread tb(side_work);
-    st_samp = sampler();  // on the caller's stream, concurrently with the side stream
-    tb.join();
+    if (cx->launch_threads) {
+      std::thread tb(side_work);
+      st_samp = sampler();  // on the caller's stream, concurrently with the side stream
+      tb.join();
+    } else {
+      side_work();
+      st_samp = sampler();
+    }
     if (st_b != RBMC_OK) {
       (void)hipStreamSynchronize(sA);
       (void)hipStreamSynchronize(s);
+      (void)hipStreamSynchronize(sT);
       return fail(st_b, err_b);
     }
     if (st_samp < 0) {
       (void)hipStreamSynchronize(s);
+      (void)hipStreamSynchronize(sT);
       return st_samp;
     }
-    HIPCHK(hipEventRecord(cx->join[0], s));
-    HIPCHK(hipStreamWaitEvent(sA, cx->join[0], 0));
+    HIPCHK(hipStreamWaitEvent(sA, e_tak, 0));
   } else {
     side_work();
     if (st_b != RBMC_OK) return st_b;
   }
   rbmc_status st = RBMC_OK;
   HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipStreamSynchronize(sT));
   if (cf.size()) {
-    st = check_info(cf, rep, "subdomain");
+    st = check_info(cf, rep, "subdomain", sA);
     if (st != RBMC_OK) return st;
     for (rbmc_model* m : ms) m->sub_ready = true;
   }
   double t2 = now_s();
   st = run(cx, cor, sA, ar);
   if (st != RBMC_OK) return st;
+  if (sA != cx->stream) {
+    HIPCHK(hipEventRecord(cx->join[4], sA));
+    HIPCHK(hipStreamWaitEvent(cx->stream, cx->join[4], 0));
+  }
   HIPCHK(hipStreamSynchronize(sA));
   double t3 = now_s();
   float ms_fac = 0.f, ms_tak = 0.f;
@@ -1447,6 +1564,351 @@ rbmc_status estimate_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const
   return st_samp;
 }
 
+
+// ---------------------------------------------------------------------------
+// Learned correction N_w: 4 convolutions 3^3 (1 -> 16 -> 16 -> 16 -> 1), ReLU
+// between them, no bias (so N_w(a r) = a N_w(r) for a > 0), on the space-time
+// grid of each sample.  Weights: layer l occupies [kWOff[l], kWOff[l+1]).
+// ---------------------------------------------------------------------------
+constexpr int kNL = 4;
+constexpr int kCin[kNL] = {1, 16, 16, 16};
+constexpr int kCout[kNL] = {16, 16, 16, 1};
+constexpr int kWOff[kNL + 1] = {0, 432, 432 + 6912, 432 + 2 * 6912, 2 * 432 + 2 * 6912};
+constexpr int kNW = kWOff[kNL];
+static_assert(kNW == RBMC_PC_NWEIGHTS, "weight count");
+constexpr int kHalo = kNL;  // receptive-field radius of the network
+
+bool learned_usable(const rbmc_model* m) { return m->lrn.ready && m->lrn.usable; }
+
+rbmc_status ensure_learned(rbmc_model* m) {
+  if (m->lrn.w) return RBMC_OK;
+  HIPCHK(m->pool.alloc((void**)&m->lrn.w, kNW * 4));
+  HIPCHK(m->pool.alloc((void**)&m->lrn.wb, kNW * 2));
+  HIPCHK(m->pool.alloc((void**)&m->lrn.wf, kNW * 2));
+  HIPCHK(m->pool.alloc((void**)&m->lrn.am, kNW * 4));
+  HIPCHK(m->pool.alloc((void**)&m->lrn.av, kNW * 4));
+  HIPCHK(m->pool.alloc((void**)&m->lrn.g, kNW * 4));
+  return RBMC_OK;
+}
+
+// BF16 copy and flipped/transposed copy of the FP32 weights
+void learned_derive(rbmc_model* m, hipStream_t s) {
+  launch_to_bf16(m->lrn.w, m->lrn.wb, kNW, s);
+  for (int l = 0; l < kNL; ++l)
+    launch_conv_wflip(m->lrn.wb + kWOff[l], kCin[l], kCout[l], m->lrn.wf + kWOff[l], s);
+}
+
+ConvGeom model_geom(const rbmc_model* m) { return ConvGeom{m->plan.T, m->plan.my, m->plan.mx}; }
+
+// Forward pass over `batch` volumes: in (B x 1 x V) -> out (B x 1 x V);
+// h[0..2]: B x 16 x V pre-activations (h[2] may alias h[0]).
+void learned_forward(const rbmc_model* m, ConvGeom g, const ConvBox* boxes, int batch,
+                     const float* in, float* const h[3], float* out, hipStream_t s) {
+  const float* src = in;
+  for (int l = 0; l < kNL; ++l) {
+    ConvArgs a{};
+    a.in = src;
+    a.out = (l == kNL - 1) ? out : h[l];
+    a.w = m->lrn.wb + kWOff[l];
+    a.boxes = boxes;
+    a.geom = g;
+    a.relu_in = l > 0;
+    a.scale = 1.f;
+    launch_conv3d(a, kCin[l], kCout[l], batch, s);
+    src = a.out;
+  }
+}
+
+rbmc_status learned_apply(rbmc_ctx* cx, rbmc_model* m, const double* r, const double* rr,
+                          const uint8_t* active, double* y, int ncols, int accumulate,
+                          hipStream_t s) {
+  (void)cx;
+  const ConvGeom g = model_geom(m);
+  const size_t V = (size_t)m->plan.n;
+  // columns per chunk: in, out and two 16-channel buffers within ~4 GB
+  const size_t per_col = V * 4 * (1 + 1 + 16 + 16);
+  const int cb = (int)std::max<size_t>(1, std::min<size_t>(ncols, ((size_t)4 << 30) / per_col));
+  if (m->lwork_cols < (size_t)cb) {
+    m->lwork.release();
+    m->lwork_cols = 0;
+    float* p = nullptr;
+    HIPCHK(m->lwork.alloc((void**)&p, per_col * cb));
+    m->lwork_cols = cb;
+  }
+  float* base = (float*)m->lwork.ptrs[0];
+  float* vin = base;
+  float* vout = vin + V * cb;
+  float* ha = vout + V * cb;
+  float* hb = ha + 16 * V * cb;
+  float* const hs[3] = {ha, hb, ha};
+  for (int c0 = 0; c0 < ncols; c0 += cb) {
+    const int nc = std::min(cb, ncols - c0);
+    launch_cols_to_vol(r + (size_t)c0 * V, V, rr ? rr + c0 : nullptr, vin, nc, s);
+    learned_forward(m, g, nullptr, nc, vin, hs, vout, s);
+    launch_vol_to_cols(vout, V, rr ? rr + c0 : nullptr, active ? active + c0 : nullptr,
+                       y + (size_t)c0 * V, nc, accumulate, s);
+  }
+  HIPCHK(hipGetLastError());
+  return RBMC_OK;
+}
+
+// Training of N_w on pairs generated by the sampler itself.  A first
+// block-Jacobi PCG run on the given right-hand sides gives x*; a second,
+// identical run stops at n_sel evenly spaced iterations k, where the error
+// left by the block-Jacobi preconditioner is t_k = (x* - x_k) - M^-1 r_k
+// (Q e_k = r_k for the error e_k = x* - x_k); random crops of r_k / |r_k|
+// (with a halo of the network's receptive field) and of t_k / |r_k| form the
+// pairs.  Adam on the mean over a batch of ||N_w(r) - t||^2 / ||t||^2 over
+// the crop interiors; the last tenth of the pairs is held out.
+rbmc_status precond_train(rbmc_model* m, const rbmc_est_opts* po, const rbmc_train_opts* to,
+                          const double* z, int n_train, float* loss_out, rbmc_report* rep) {
+  rbmc_ctx* cx = m->ctx;
+  hipStream_t s = cx->stream;
+  rbmc_status st = ensure_learned(m);
+  if (st != RBMC_OK) return st;
+  const ConvGeom g = model_geom(m);
+  const size_t n = (size_t)m->plan.n;
+  const int ct = std::min(to->crop_t > 0 ? to->crop_t : 16, g.T);
+  const int cxy = to->crop_xy > 0 ? to->crop_xy : 64;
+  const int cy = std::min(cxy, g.MY), cxx = std::min(cxy, g.MX);
+  const ConvGeom cg{ct + 2 * kHalo, cy + 2 * kHalo, cxx + 2 * kHalo};
+  const size_t cv = (size_t)cg.T * cg.MY * cg.MX;
+  const int npairs = std::max(to->n_pairs, 2);
+  std::mt19937_64 rng(to->seed);
+  // initial weights: He-scaled normals (last layer 10x smaller)
+  if (!m->lrn.ready) {
+    std::vector<float> w(kNW);
+    for (int l = 0; l < kNL; ++l) {
+      std::normal_distribution<float> nd(0.f, std::sqrt(2.f / (kCin[l] * 27.f)) *
+                                                   (l == kNL - 1 ? 0.1f : 1.f));
+      for (int i = kWOff[l]; i < kWOff[l + 1]; ++i) w[i] = nd(rng);
+    }
+    HIPCHK(hipMemcpyAsync(m->lrn.w, w.data(), kNW * 4, hipMemcpyHostToDevice, s));
+    learned_derive(m, s);
+    m->lrn.ready = true;
+  }
+  HIPCHK(hipMemsetAsync(m->lrn.am, 0, kNW * 4, s));
+  HIPCHK(hipMemsetAsync(m->lrn.av, 0, kNW * 4, s));
+  // ---- pairs from the sampler ----
+  rbmc_est_opts o = *po;
+  o.n_samples = n_train;
+  o.precond = RBMC_PC_BJ;
+  std::vector<rbmc_model*> ms{m};
+  const HostCols h = make_cols(ms, n_train);
+  st = ensure_ws(cx, ms, h, false);
+  if (st != RBMC_OK) return st;
+  st = ensure_panels(m, n_train);
+  if (st != RBMC_OK) return st;
+  Pool tp;  // training data, released on return
+  struct Release {
+    Pool& p;
+    ~Release() { p.release(); }
+  } rel{tp};
+  double *xs = nullptr, *tv = nullptr;
+  float *pin = nullptr, *ptg = nullptr, *ptn = nullptr;
+  ConvBox* pbox = nullptr;
+  CropSpec* dspec = nullptr;
+  HIPCHK(tp.alloc((void**)&xs, n * n_train * 8));
+  HIPCHK(tp.alloc((void**)&tv, n * n_train * 8));
+  HIPCHK(tp.alloc((void**)&pin, cv * npairs * 4));
+  HIPCHK(tp.alloc((void**)&ptg, cv * npairs * 4));
+  HIPCHK(tp.alloc((void**)&ptn, (size_t)npairs * 4));
+  HIPCHK(tp.alloc((void**)&pbox, (size_t)npairs * sizeof(ConvBox)));
+  HIPCHK(tp.alloc((void**)&dspec, (size_t)npairs * 2 * sizeof(CropSpec)));
+  {
+    std::vector<float> ones(npairs, 1.f);
+    HIPCHK(hipMemcpyAsync(ptn, ones.data(), npairs * 4, hipMemcpyHostToDevice, s));
+  }
+  rbmc_report r1{};
+  st = sample_set(cx, ms, h, &o, z, xs, &r1, s);
+  if (st < 0) return st;
+  const int nit = std::max(r1.pcg_it_max, 1);
+  const int per_it = std::max(1, (npairs + nit * n_train - 1) / (nit * n_train));
+  const int n_sel = std::min(nit, (npairs + per_it * n_train - 1) / (per_it * n_train));
+  std::vector<int> sel_it(n_sel);
+  for (int i = 0; i < n_sel; ++i) sel_it[i] = (int)((long long)i * nit / n_sel);
+  std::vector<int> slot(npairs);  // random slot order so batches are random
+  for (int i = 0; i < npairs; ++i) slot[i] = i;
+  std::shuffle(slot.begin(), slot.end(), rng);
+  std::vector<ConvBox> boxes(npairs);
+  int made = 0, next_sel = 0;
+  std::vector<double> hrr(n_train);
+  SampleHook hook = [&](int it, const double* x, const double* r, const double* zk,
+                        const double* rrv) -> rbmc_status {
+    if (next_sel >= n_sel || it != sel_it[next_sel] || made >= npairs) return RBMC_OK;
+    ++next_sel;
+    HIPCHK(hipMemcpyAsync(hrr.data(), rrv, n_train * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    launch_sub3(xs, x, zk, tv, n * n_train, s);  // t = x* - x_k - M^-1 r_k
+    std::vector<CropSpec> sp;
+    for (int c = 0; c < n_train && made < npairs; ++c) {
+      if (!(hrr[c] > 0.0)) continue;
+      for (int k = 0; k < per_it && made < npairs; ++k, ++made) {
+        const int it0 = std::uniform_int_distribution<int>(0, g.T - ct)(rng);
+        const int iy0 = std::uniform_int_distribution<int>(0, g.MY - cy)(rng);
+        const int ix0 = std::uniform_int_distribution<int>(0, g.MX - cxx)(rng);
+        CropSpec c1{c, slot[made], it0 - kHalo, iy0 - kHalo, ix0 - kHalo, 1.0 / std::sqrt(hrr[c])};
+        sp.push_back(c1);
+        ConvBox b{std::max(0, -c1.ot), std::min(cg.T, g.T - c1.ot), std::max(0, -c1.oy),
+                  std::min(cg.MY, g.MY - c1.oy), std::max(0, -c1.ox), std::min(cg.MX, g.MX - c1.ox)};
+        boxes[slot[made]] = b;
+      }
+    }
+    if (sp.empty()) return RBMC_OK;
+    HIPCHK(hipMemcpyAsync(dspec, sp.data(), sp.size() * sizeof(CropSpec), hipMemcpyHostToDevice, s));
+    launch_crop(r, g, dspec, (int)sp.size(), cg, pin, s);
+    launch_crop(tv, g, dspec, (int)sp.size(), cg, ptg, s);
+    HIPCHK(hipStreamSynchronize(s));  // dspec is reused by the next stop
+    return RBMC_OK;
+  };
+  rbmc_report r2{};
+  st = sample_set(cx, ms, h, &o, z, cx->x, &r2, s, hook);
+  if (st < 0) return st;
+  if (made < 2) return fail(RBMC_E_ARG, "too few training pairs (the sampler converged at once)");
+  const int np_used = made;
+  std::vector<int> used_slots(slot.begin(), slot.begin() + np_used);
+  std::sort(used_slots.begin(), used_slots.end());
+  // slots are a permutation of [0, npairs); compact the used ones to [0, np_used)
+  // by training only on the slots that were filled
+  std::vector<int> order = used_slots;
+  HIPCHK(hipMemcpyAsync(pbox, boxes.data(), npairs * sizeof(ConvBox), hipMemcpyHostToDevice, s));
+  // interior norms ||t||^2 per pair
+  const int lblk = 32;
+  float* lpart = nullptr;
+  HIPCHK(tp.alloc((void**)&lpart, (size_t)npairs * lblk * 2 * 4));
+  for (int slot_i : order) {
+    launch_crop_loss(ptg + (size_t)slot_i * cv, ptg + (size_t)slot_i * cv, pbox + slot_i,
+                     ptn + slot_i, cg, kHalo, 1, nullptr, lpart + (size_t)slot_i * lblk * 2, lblk,
+                     s);
+  }
+  std::vector<float> hpart((size_t)npairs * lblk * 2);
+  HIPCHK(hipMemcpyAsync(hpart.data(), lpart, hpart.size() * 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  std::vector<float> tn(npairs, 1.f);
+  for (int slot_i : order) {
+    double a = 0.0;
+    for (int k = 0; k < lblk; ++k) a += hpart[((size_t)slot_i * lblk + k) * 2 + 1];
+    tn[slot_i] = (float)std::max(a, 1e-30);
+  }
+  HIPCHK(hipMemcpyAsync(ptn, tn.data(), npairs * 4, hipMemcpyHostToDevice, s));
+  // ---- training ----
+  const int B = std::max(1, std::min(to->batch > 0 ? to->batch : 8, np_used));
+  const int n_val = std::max(1, np_used / 10);
+  const int n_fit = np_used - n_val;
+  std::vector<int> fit(order.begin(), order.begin() + n_fit), val(order.begin() + n_fit, order.end());
+  // batches must be contiguous slots: train on runs of B consecutive used slots
+  float *bin = nullptr, *btg = nullptr, *bdy = nullptr, *hbuf = nullptr, *gbuf = nullptr,
+        *wpart = nullptr;
+  ConvBox* bbox = nullptr;
+  float* btn = nullptr;
+  HIPCHK(tp.alloc((void**)&bin, cv * B * 4));
+  HIPCHK(tp.alloc((void**)&btg, cv * B * 4));
+  HIPCHK(tp.alloc((void**)&bdy, cv * B * 4));
+  HIPCHK(tp.alloc((void**)&hbuf, cv * B * 16 * 3 * 4));
+  HIPCHK(tp.alloc((void**)&gbuf, cv * B * 16 * 2 * 4));
+  HIPCHK(tp.alloc((void**)&bbox, (size_t)B * sizeof(ConvBox)));
+  HIPCHK(tp.alloc((void**)&btn, (size_t)B * 4));
+  const int wt_tiles = conv_wgrad_tiles(cg);
+  HIPCHK(tp.alloc((void**)&wpart, (size_t)wt_tiles * B * 16 * 16 * 27 * 4));
+  float* const hs[3] = {hbuf, hbuf + cv * B * 16, hbuf + cv * B * 32};
+  float* yout = bdy;  // forward output, then overwritten by dL/dy
+  float* ga = gbuf;
+  float* gb = gbuf + cv * B * 16;
+  auto load_batch = [&](const std::vector<int>& ids, int i0, int nb) -> rbmc_status {
+    for (int k = 0; k < nb; ++k) {
+      const int sl = ids[i0 + k];
+      HIPCHK(hipMemcpyAsync(bin + cv * k, pin + cv * sl, cv * 4, hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipMemcpyAsync(btg + cv * k, ptg + cv * sl, cv * 4, hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipMemcpyAsync(bbox + k, pbox + sl, sizeof(ConvBox), hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipMemcpyAsync(btn + k, ptn + sl, 4, hipMemcpyDeviceToDevice, s));
+    }
+    return RBMC_OK;
+  };
+  auto batch_loss = [&](int nb, bool grad, double* err, double* ref) -> rbmc_status {
+    learned_forward(m, cg, bbox, nb, bin, hs, yout, s);
+    launch_crop_loss(yout, btg, bbox, btn, cg, kHalo, nb, grad ? bdy : nullptr, lpart, lblk, s);
+    std::vector<float> lp((size_t)nb * lblk * 2);
+    HIPCHK(hipMemcpyAsync(lp.data(), lpart, lp.size() * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    *err = *ref = 0.0;
+    for (size_t k = 0; k < lp.size(); k += 2) {
+      *err += lp[k];
+      *ref += lp[k + 1];
+    }
+    return RBMC_OK;
+  };
+  const int epochs = std::max(to->epochs, 0);
+  const float lr = to->lr > 0.f ? to->lr : 1e-3f;
+  int step = 0;
+  for (int ep = 0; ep < epochs; ++ep) {
+    std::shuffle(fit.begin(), fit.end(), rng);
+    double ep_err = 0.0, ep_ref = 0.0;
+    for (int i0 = 0; i0 + B <= n_fit; i0 += B) {
+      st = load_batch(fit, i0, B);
+      if (st != RBMC_OK) return st;
+      double e = 0.0, rf = 0.0;
+      st = batch_loss(B, true, &e, &rf);
+      if (st != RBMC_OK) return st;
+      ep_err += e;
+      ep_ref += rf;
+      // backward: layer l consumes a_{l-1} = relu(h_{l-1}) (the input for l = 0)
+      const float* gout = bdy;  // dL/d(output of layer l)
+      for (int l = kNL - 1; l >= 0; --l) {
+        const float* ain = (l == 0) ? bin : hs[l - 1];
+        ConvWArgs wa{};
+        wa.gout = gout;
+        wa.ain = ain;
+        wa.partial = wpart;
+        wa.boxes = bbox;
+        wa.geom = cg;
+        wa.relu_in = l > 0;
+        launch_conv3d_wgrad(wa, kCin[l], kCout[l], B, s);
+        launch_sum_rows(wpart, wt_tiles * B, kCout[l] * kCin[l] * 27, m->lrn.g + kWOff[l], s);
+        if (l > 0) {  // dL/dh_{l-1} = conv(gout, flipped W_l) * [h_{l-1} > 0]
+          ConvArgs a{};
+          a.in = gout;
+          a.out = (gout == ga) ? gb : ga;
+          a.w = m->lrn.wf + kWOff[l];
+          a.mask = hs[l - 1];
+          a.boxes = bbox;
+          a.geom = cg;
+          a.scale = 1.f;
+          launch_conv3d(a, kCout[l], kCin[l], B, s);
+          gout = a.out;
+        }
+      }
+      ++step;
+      launch_adam(m->lrn.w, m->lrn.g, m->lrn.am, m->lrn.av, m->lrn.wb, kNW, lr, 0.9f, 0.999f,
+                  1e-8f, step, s);
+      for (int l = 0; l < kNL; ++l)
+        launch_conv_wflip(m->lrn.wb + kWOff[l], kCin[l], kCout[l], m->lrn.wf + kWOff[l], s);
+      HIPCHK(hipGetLastError());
+    }
+    if (loss_out) loss_out[ep] = (float)(ep_ref > 0 ? ep_err / ep_ref : 0.0);
+  }
+  // held-out relative error of the correction (1 = no better than no correction)
+  double verr = 0.0, vref = 0.0;
+  for (int i0 = 0; i0 < n_val; i0 += B) {
+    const int nb = std::min(B, n_val - i0);
+    st = load_batch(val, i0, nb);
+    if (st != RBMC_OK) return st;
+    double e = 0.0, rf = 0.0;
+    st = batch_loss(nb, false, &e, &rf);
+    if (st != RBMC_OK) return st;
+    verr += e;
+    vref += rf;
+  }
+  m->lrn.val_rel_err = vref > 0.0 ? std::sqrt(verr / vref) : 1.0;
+  m->lrn.usable = m->lrn.val_rel_err < 1.0;
+  if (loss_out) loss_out[epochs] = (float)m->lrn.val_rel_err;
+  HIPCHK(hipStreamSynchronize(s));
+  if (rep) {
+    *rep = r1;
+    rep->err_estimate = m->lrn.val_rel_err;
+  }
+  return RBMC_OK;
+}
+
 // Validate a set of models for one call.
 rbmc_status check_models(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms) {
   for (rbmc_model* m : ms) {
@@ -1492,11 +1954,15 @@ rbmc_status estimate_full(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms,
   }
   rbmc_status st1 = RBMC_OK;
   std::function<rbmc_status()> sampler;
-  if (nk > 0)
+  if (nk > 0 && cx->overlap)
     sampler = [&]() -> rbmc_status {
-      st1 = sample_set(cx, ms, h, opts, zb, cx->x, rep);
+      st1 = sample_set(cx, ms, h, opts, zb, cx->x, rep, cx->work);
       return st1;
     };
+  if (nk > 0 && !cx->overlap) {  // sample first, then everything else, on one stream
+    st1 = sample_set(cx, ms, h, opts, zb, cx->x, rep, cx->stream);
+    if (st1 < 0) return st1;
+  }
   st = estimate_set(cx, ms, h, opts, cx->x, diag_out, trace_out, rep, sampler);
   if (st < 0) return st;
   return st1;
@@ -1523,7 +1989,8 @@ rbmc_status rbmc_ctx_profile_read(rbmc_ctx* ctx, int family, rbmc_kernel_stats* 
   if (!ctx || !out) return fail(RBMC_E_ARG, "NULL argument");
   if (family < 0 || family >= RBMC_KF_COUNT) return fail(RBMC_E_ARG, "unknown kernel family");
   HIPCHK(hipStreamSynchronize(ctx->stream));
-  if (ctx->side) HIPCHK(hipStreamSynchronize(ctx->side));
+  for (hipStream_t q : {ctx->side, ctx->side2, ctx->work})
+    if (q) HIPCHK(hipStreamSynchronize(q));
   std::memset(out, 0, sizeof(*out));
   for (const ProfRec& r : ctx->recs) {
     if (r.family != family) continue;
@@ -1547,6 +2014,9 @@ rbmc_status rbmc_ctx_create(int device, void* hip_stream, rbmc_ctx** out) {
   rbmc_ctx* c = new rbmc_ctx;
   c->device = device;
   c->stream = (hipStream_t)hip_stream;
+  if (const char* e = std::getenv("RBMC_OVERLAP")) c->overlap = std::atoi(e) != 0;
+  if (const char* e = std::getenv("RBMC_LAUNCH_THREADS")) c->launch_threads = std::atoi(e) > 1;
+  if (const char* e = std::getenv("RBMC_RESERVE_CUS")) c->reserve_cus = std::atoi(e);
   *out = c;
   return RBMC_OK;
 }
@@ -1677,8 +2147,10 @@ void rbmc_model_destroy(rbmc_model* m) {
   if (!m) return;
   (void)hipSetDevice(m->ctx->device);
   (void)hipStreamSynchronize(m->ctx->stream);
-  if (m->ctx->side) (void)hipStreamSynchronize(m->ctx->side);
+  for (hipStream_t q : {m->ctx->side, m->ctx->side2, m->ctx->work})
+    if (q) (void)hipStreamSynchronize(q);
   m->work.release();
+  m->lwork.release();
   m->pool.release();
   delete m;
 }
@@ -1730,7 +2202,7 @@ rbmc_status rbmc_sample(rbmc_model* m, const rbmc_est_opts* opts, const double* 
   if (st != RBMC_OK) return st;
   st = ensure_panels(m, opts->n_samples);
   if (st != RBMC_OK) return st;
-  st = sample_set(m->ctx, ms, h, opts, z, x, rep);
+  st = sample_set(m->ctx, ms, h, opts, z, x, rep, m->ctx->stream);
   if (rep) {
     rep->t_total = now_s() - t0;
     rep->peak_bytes = m->ctx->ws.bytes + m->pool.bytes + m->work.bytes;
@@ -1805,6 +2277,63 @@ rbmc_status rbmc_estimate_batched(rbmc_ctx* ctx, int32_t n_models, rbmc_model* c
   st = estimate_full(ctx, ms, opts, zp, dp, tp, rep);
   if (rep) rep->t_total = now_s() - t0;
   return st;
+}
+
+rbmc_status rbmc_precond_train(rbmc_model* m, const rbmc_est_opts* pcg_opts,
+                               const rbmc_train_opts* train_opts, const double* z,
+                               int32_t n_train, float* loss_out, rbmc_report* rep) {
+  init_report(rep);
+  if (!m || !pcg_opts || !train_opts || !z) return fail(RBMC_E_ARG, "NULL argument");
+  if (n_train < 1) return fail(RBMC_E_ARG, "n_train must be >= 1");
+  if (pcg_opts->pcg_maxit < 1 || !(pcg_opts->pcg_rtol > 0.0))
+    return fail(RBMC_E_ARG, "pcg_maxit must be >= 1 and pcg_rtol > 0");
+  if (train_opts->n_pairs < 2 || train_opts->epochs < 0 || train_opts->batch < 0)
+    return fail(RBMC_E_ARG, "n_pairs must be >= 2, epochs and batch >= 0");
+  if (train_opts->crop_t < 0 || train_opts->crop_xy < 0)
+    return fail(RBMC_E_ARG, "crop sizes must be >= 0 (0 = default)");
+  HIPCHK(hipSetDevice(m->ctx->device));
+  double t0 = now_s();
+  rbmc_status st = precond_train(m, pcg_opts, train_opts, z, n_train, loss_out, rep);
+  if (rep) rep->t_total = now_s() - t0;
+  return st;
+}
+
+rbmc_status rbmc_precond_apply(rbmc_model* m, const double* r, double* y, int32_t n_rhs) {
+  if (!m || !r || !y) return fail(RBMC_E_ARG, "NULL argument");
+  if (n_rhs < 0) return fail(RBMC_E_ARG, "n_rhs must be >= 0");
+  if (!m->lrn.ready) return fail(RBMC_E_ARG, "the learned correction has no weights");
+  if (n_rhs == 0) return RBMC_OK;
+  HIPCHK(hipSetDevice(m->ctx->device));
+  rbmc_status st = learned_apply(m->ctx, m, r, nullptr, nullptr, y, n_rhs, 0, m->ctx->stream);
+  if (st != RBMC_OK) return st;
+  HIPCHK(hipStreamSynchronize(m->ctx->stream));
+  return RBMC_OK;
+}
+
+rbmc_status rbmc_precond_get_weights(rbmc_model* m, float* w, int32_t* usable,
+                                     double* val_rel_err) {
+  if (!m || !w) return fail(RBMC_E_ARG, "NULL argument");
+  if (!m->lrn.ready) return fail(RBMC_E_ARG, "the learned correction has no weights");
+  HIPCHK(hipMemcpy(w, m->lrn.w, kNW * 4, hipMemcpyDeviceToHost));
+  if (usable) *usable = m->lrn.usable ? 1 : 0;
+  if (val_rel_err) *val_rel_err = m->lrn.val_rel_err;
+  return RBMC_OK;
+}
+
+rbmc_status rbmc_precond_set_weights(rbmc_model* m, const float* w) {
+  if (!m || !w) return fail(RBMC_E_ARG, "NULL argument");
+  for (int i = 0; i < kNW; ++i)
+    if (!std::isfinite(w[i])) return fail(RBMC_E_ARG, "weights must be finite");
+  HIPCHK(hipSetDevice(m->ctx->device));
+  rbmc_status st = ensure_learned(m);
+  if (st != RBMC_OK) return st;
+  HIPCHK(hipMemcpyAsync(m->lrn.w, w, kNW * 4, hipMemcpyHostToDevice, m->ctx->stream));
+  learned_derive(m, m->ctx->stream);
+  HIPCHK(hipStreamSynchronize(m->ctx->stream));
+  m->lrn.ready = true;
+  m->lrn.usable = true;  // weights given by the caller are taken as they are
+  m->lrn.val_rel_err = -1.0;
+  return RBMC_OK;
 }
 
 }  // extern "C"

@@ -263,13 +263,17 @@ void launch_pcg_xr(const ColSet& cs, const double* p, const double* q, double* x
                                                      nch);
 }
 
-// p = z + beta p (first iteration: p = z); beta = rz_new / rz_old; active columns only
+// p = z + beta p (first iteration: p = z); active columns only.
+// beta = rz_new / rz_old, or (rz_new - rz_sub) / rz_old (flexible form, with
+// rz_sub = r_new . z_old, for a preconditioner that varies between iterations)
 __global__ void k_pcg_p(ColSet cs, const double* __restrict__ z, double* __restrict__ p,
                         const double* __restrict__ rz_new, const uint8_t* __restrict__ active,
-                        const double* __restrict__ rz_old, int first) {
+                        const double* __restrict__ rz_old, const double* __restrict__ rz_sub,
+                        int first) {
   const int k = blockIdx.y;
   if (!active[k]) return;
-  const double beta = first ? 0.0 : rz_new[k] / rz_old[k];
+  const double beta =
+      first ? 0.0 : (rz_sub ? rz_new[k] - rz_sub[k] : rz_new[k]) / rz_old[k];
   const size_t off = cs.off[k];
   const int n = cs.len[k];
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
@@ -283,10 +287,11 @@ __global__ void k_copy_scalars(const double* __restrict__ src, double* __restric
 }
 
 void launch_pcg_p(const ColSet& cs, const double* z, double* p, const double* rz_new,
-                  double* rz_old, const uint8_t* active, int first, hipStream_t s) {
+                  double* rz_old, const uint8_t* active, int first, hipStream_t s,
+                  const double* rz_sub) {
   if (cs.ncols <= 0) return;
   const int bx = std::min((cs.max_len + 255) / 256, 1024);
-  k_pcg_p<<<dim3(bx, cs.ncols), 256, 0, s>>>(cs, z, p, rz_new, active, rz_old, first);
+  k_pcg_p<<<dim3(bx, cs.ncols), 256, 0, s>>>(cs, z, p, rz_new, active, rz_old, rz_sub, first);
   k_copy_scalars<<<(cs.ncols + 255) / 256, 256, 0, s>>>(rz_new, rz_old, active, cs.ncols);
 }
 

@@ -120,8 +120,10 @@ void launch_dot_partials(const ColSet& cs, const double* a, const double* b, dou
 void launch_pcg_xr(const ColSet& cs, const double* p, const double* q, double* x, double* r,
                    const double* rz, const double* pq, const uint8_t* active,
                    double* rr_partial, hipStream_t s);
+// beta = (rz_new - rz_sub) / rz_old when rz_sub is given (flexible PCG)
 void launch_pcg_p(const ColSet& cs, const double* z, double* p, const double* rz_new,
-                  double* rz_old, const uint8_t* active, int first, hipStream_t s);
+                  double* rz_old, const uint8_t* active, int first, hipStream_t s,
+                  const double* rz_sub = nullptr);
 void launch_pcg_check(const double* rr, const double* bb, double rtol, uint8_t* active,
                       int* it_count, int* n_active, int n_rhs, hipStream_t s);
 
@@ -279,5 +281,59 @@ struct McTask {
   int tile_start;
 };
 void launch_mc(const McTask* d_tasks, int n_tasks, int total_tiles, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Learned correction to the preconditioner: 3-D convolutions (kernels_conv.hip)
+// ---------------------------------------------------------------------------
+struct ConvGeom {  // volume of T x MY x MX voxels
+  int T, MY, MX;
+};
+struct ConvBox {  // valid voxels [t0, t1) x [y0, y1) x [x0, x1) of one volume
+  int t0, t1, y0, y1, x0, x1;
+};
+struct ConvArgs {
+  const float* in;        // B x Cin x V
+  float* out;             // B x Cout x V
+  const uint16_t* w;      // Cout x Cin x 27, BF16
+  const float* mask;      // optional, B x Cout x V: outputs where mask <= 0 are zeroed
+  const ConvBox* boxes;   // optional (device), one per volume; null = whole volume
+  ConvGeom geom;
+  int relu_in;            // apply max(0, .) to the input on load
+  int accumulate;         // out += result
+  float scale;
+};
+int conv_tiles(const ConvGeom& g);
+void launch_conv3d(const ConvArgs& a, int cin, int cout, int batch, hipStream_t s);
+struct ConvWArgs {
+  const float* gout;      // B x Cout x V
+  const float* ain;       // B x Cin x V
+  float* partial;         // (tiles * B) x Cout x Cin x 27
+  const ConvBox* boxes;
+  ConvGeom geom;
+  int relu_in;
+};
+int conv_wgrad_tiles(const ConvGeom& g);
+void launch_conv3d_wgrad(const ConvWArgs& a, int cin, int cout, int batch, hipStream_t s);
+void launch_sum_rows(const float* part, int nwg, int len, float* out, hipStream_t s);
+void launch_conv_wflip(const uint16_t* w, int cin, int cout, uint16_t* wt, hipStream_t s);
+void launch_adam(float* p, const float* g, float* m, float* v, uint16_t* pb, int n, float lr,
+                 float b1, float b2, float eps, int step, hipStream_t s);
+void launch_to_bf16(const float* p, uint16_t* pb, int n, hipStream_t s);
+// columns (c * n, FP64) <-> volumes (FP32), normalized by sqrt(rr[c])
+void launch_cols_to_vol(const double* x, size_t n, const double* rr, float* vol, int ncols,
+                        hipStream_t s);
+void launch_vol_to_cols(const float* vol, size_t n, const double* rr, const uint8_t* active,
+                        double* y, int ncols, int accumulate, hipStream_t s);
+struct CropSpec {  // crop of column `col` with its voxel (0,0,0) at grid (ot, oy, ox)
+  int col, slot, ot, oy, ox;
+  double scale;
+};
+void launch_crop(const double* src, ConvGeom g, const CropSpec* d_specs, int n_specs, ConvGeom cg,
+                 float* out, hipStream_t s);
+void launch_crop_loss(const float* y, const float* t, const ConvBox* boxes, const float* tn,
+                      ConvGeom cg, int h, int batch, float* dy, float* part, int nblk,
+                      hipStream_t s);
+void launch_sub3(const double* a, const double* b, const double* c, double* d, size_t n,
+                 hipStream_t s);
 
 }  // namespace rbmc
