@@ -407,6 +407,11 @@ def main():
         out["variant_pc_cores"] = {"value": mv.n / sec, "ms_per_step": sec * 1e3,
                                    "pcg_iters": {"mean": rp["pcg_it_mean"], "max": rp["pcg_it_max"]}}
         mv.close()
+    if not args.no_variants:
+        try:
+            out["variant_learned"] = learned_leg(wl)
+        except B.RbmcError as e:
+            out["variant_learned"] = {"error": str(e)}
     if not args.no_batched:
         try:
             out["batched"] = batched_leg(args.batched_models)
@@ -415,6 +420,46 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_m)
     print(json.dumps(out), flush=True)
+
+
+def learned_leg(wl, pc=(4, 2, 2), n_train=8, n_cols=32):
+    """The learned correction of the block-Jacobi preconditioner on the same
+    grid with tiled blocks (4 slabs x 2 x 2 tiles: block Jacobi alone needs
+    several hundred iterations, the most room for a correction): training
+    (pairs from n_train columns, a quarter held out), its acceptance trial,
+    then n_cols samples with block Jacobi alone and with the trained
+    correction applied (forced, whatever the trial decided)."""
+    import torch
+    from paper_2309_05435_amd import binding as B
+    from paper_2309_05435_amd.inputs import normals
+    gm = B.Model(wl, pc=pc)
+    zt = torch.from_numpy(normals((n_train, gm.n + gm.n_obs), 71)).to("cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, loss, rep = B.rbmc_precond_train(
+        gm.m, B.make_opts(n_train, 20000, wl.rtol),
+        B.make_train_opts(n_pairs=1000, epochs=8, batch=8, lr=2e-3, seed=3), zt, n_train)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    info = B.rbmc_precond_info(gm.m)
+    B.rbmc_precond_set_weights(gm.m, B.rbmc_precond_get_weights(gm.m))  # force use
+    z = torch.from_numpy(normals((n_cols, gm.n + gm.n_obs), 72)).to("cuda")
+    x = torch.empty((n_cols, gm.n), dtype=torch.float64, device="cuda")
+    runs = {}
+    for name, pcv in (("block_jacobi", B.RBMC_PC_BJ), ("learned", B.RBMC_PC_BJ_LEARNED)):
+        o = B.make_opts(n_cols, 20000, wl.rtol, precond=pcv)
+        B.rbmc_sample(gm.m, o, z, x)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        _, rp = B.rbmc_sample(gm.m, o, z, x)
+        torch.cuda.synchronize()
+        runs[name] = {"pcg_iters_max": rp.pcg_it_max, "sampler_s": time.perf_counter() - ta,
+                      "max_rel_residual": rp.max_rel_residual}
+    gm.close()
+    return {"pc_blocks": list(pc), "train_s": t_train, "train_ratios": loss[:-1],
+            "heldout_energy_ratio": info.val_ratio, "accepted": bool(info.usable),
+            "trial_iters": [info.trial_it_bj, info.trial_it_learned],
+            "trial_s": [info.trial_s_bj, info.trial_s_learned], "n_samples": n_cols, **runs}
 
 
 if __name__ == "__main__":

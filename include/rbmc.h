@@ -202,46 +202,69 @@ rbmc_status rbmc_estimate_batched(rbmc_ctx* ctx, int32_t n_models, rbmc_model* c
                                   rbmc_report* rep);
 
 /* Learned correction of the block-Jacobi preconditioner (used when
- * opts->precond = RBMC_PC_BJ_LEARNED; not part of the paper's method).  The
- * preconditioned residual becomes z = M_BJ^-1 r + N_w(r), with N_w four 3-D
- * convolutions 3x3x3 over the (t, y, x) grid of a sample (channels
- * 1 -> 16 -> 16 -> 16 -> 1, ReLU between, no bias, zero outside the grid),
- * BF16 weights and FP32 accumulation, applied to r / ||r|| and scaled back;
- * PCG then uses the flexible (Polak-Ribiere) update.  A model whose trained
- * correction did not reduce the held-out error falls back to plain block
- * Jacobi.  Weight vector (RBMC_PC_NWEIGHTS floats): layer l's W[co][ci][tap]
- * after layer l-1's, tap = (dt+1)*9 + (dy+1)*3 + (dx+1). */
-#define RBMC_PC_NWEIGHTS 14688
+ * opts->precond = RBMC_PC_BJ_LEARNED; not part of the paper's method).  With
+ * u = M_BJ^-1 r and v = N_w(r, u), the preconditioned residual becomes
+ * z = u + g v, where the per-column step g = (v.r - v.Qu) / v.Qv minimizes
+ * the energy error ||z - Q^-1 r||_Q along v (g = 0 when v.Qv <= 0), so the
+ * correction never makes one preconditioning step worse than block Jacobi;
+ * PCG then uses the flexible (Polak-Ribiere) update.  N_w: four 3-D
+ * convolutions 3x3x3 over the (t, y, x) grid of a sample, channels
+ * 2 -> 16 -> 16 -> 16 -> 1 (inputs r and u, both divided by ||r||), ReLU
+ * between, no bias (so N_w(a r, a u) = a N_w(r, u) for a > 0), zero outside
+ * the grid; BF16 weights, FP32 accumulation.  A model whose trained
+ * correction did not reduce the held-out energy error falls back to plain
+ * block Jacobi.  Weight vector (RBMC_PC_NWEIGHTS floats): layer l's
+ * W[co][ci][tap] after layer l-1's, tap = (dt+1)*9 + (dy+1)*3 + (dx+1). */
+#define RBMC_PC_NWEIGHTS 15120
 typedef struct {
   int32_t n_pairs;  /* training pairs (>= 2), e.g. 2000 */
   int32_t epochs;   /* passes over the pairs (>= 0) */
   int32_t batch;    /* pairs per Adam step (0: 8) */
   float lr;         /* Adam step size (0: 1e-3) */
-  uint64_t seed;    /* crop positions, pair order, initial weights */
-  int32_t crop_t, crop_xy; /* crop interior: time steps, grid side (0: 16, 64) */
+  uint64_t seed;    /* pair order, initial weights */
 } rbmc_train_opts;
 
 /* Train N_w on pairs the sampler generates: a block-Jacobi PCG run on the
  * right-hand sides F z gives x*; an identical second run stops at evenly
- * spaced iterations k, where the preconditioner's remaining error is
- * t_k = (x* - x_k) - M_BJ^-1 r_k; random crops of (r_k, t_k) / ||r_k|| (with
- * the network's 4-voxel halo) are the pairs; Adam minimizes the mean of
- * ||N_w(r) - t||^2 / ||t||^2 over crop interiors.  The last tenth of the
- * pairs is held out: its relative error sqrt(sum ||N_w(r)-t||^2 / sum ||t||^2)
- * goes to loss_out[epochs] (and the report's err_estimate); loss_out[e] is the
- * training loss of epoch e (host, epochs + 1 floats, may be NULL).  The
- * correction is used only if the held-out error is below 1.
+ * spaced iterations k; each column there gives one pair (r_k, u_k, e_k) / ||r_k||
+ * with e_k = x* - x_k the error (Q e_k = r_k).  Adam minimizes the mean over
+ * pairs of the relative energy error ||u + N_w(r, u) - e||_Q^2 / ||e||_Q^2
+ * (whole grids, Q applied in FP64).  The pairs of the last max(1, n_train/4)
+ * columns are held out (n_train >= 2): the ratio of its energy error with the correction to that without
+ * (block Jacobi alone) goes to loss_out[epochs] and to the report's
+ * err_estimate; loss_out[e] is the mean training ratio of epoch e (host,
+ * epochs + 1 floats, may be NULL).  A correction with a held-out ratio
+ * below 1 is then tried: PCG on the held-out right-hand sides at the
+ * caller's pcg_rtol, with and without it; it is used only if it needs fewer
+ * iterations and less time (a weak correction makes the nonlinear, flexible
+ * PCG slower than plain block Jacobi, and each application of N_w costs
+ * about 30 kflop per node).  Training continues from the current weights
+ * if the model has any (a new model starts from He-scaled normals with the
+ * last layer zero, i.e. from plain block Jacobi).
  * z: device (n + n_obs) x n_train standard normals; pcg_opts: pcg_maxit and
- * pcg_rtol of the pair-generating runs. */
+ * pcg_rtol of the pair-generating runs.  Pairs are held in FP32 on the
+ * device (12 bytes per node per pair); RBMC_E_ARG if they exceed 16 GiB. */
 rbmc_status rbmc_precond_train(rbmc_model* m, const rbmc_est_opts* pcg_opts,
                                const rbmc_train_opts* train_opts, const double* z,
                                int32_t n_train, float* loss_out, rbmc_report* rep);
-/* y = N_w(r) for n_rhs device vectors (no normalization); for testing. */
-rbmc_status rbmc_precond_apply(rbmc_model* m, const double* r, double* y, int32_t n_rhs);
-/* Weights (host, RBMC_PC_NWEIGHTS floats), whether they are used, and the
- * held-out error of the last training (-1 if set directly). */
-rbmc_status rbmc_precond_get_weights(rbmc_model* m, float* w, int32_t* usable,
-                                     double* val_rel_err);
+/* y = N_w(r, u) for n_rhs device vectors r, u (n x n_rhs each; no
+ * normalization); for testing. */
+rbmc_status rbmc_precond_apply(rbmc_model* m, const double* r, const double* u, double* y,
+                               int32_t n_rhs);
+typedef struct {
+  int32_t ready;            /* the model has weights */
+  int32_t usable;           /* RBMC_PC_BJ_LEARNED applies them (else plain block Jacobi) */
+  double val_ratio;         /* held-out energy-error ratio of the last training (-1: none) */
+  int32_t trial_it_bj;      /* PCG iterations of the trial, block Jacobi (-1: no trial) */
+  int32_t trial_it_learned; /* and with the correction (-1: no trial) */
+  double trial_s_bj;        /* sampler seconds of the trial, block Jacobi (-1: no trial) */
+  double trial_s_learned;   /* and with the correction (-1: no trial) */
+} rbmc_pc_info;
+rbmc_status rbmc_precond_info(rbmc_model* m, rbmc_pc_info* info);
+/* Weights (host, RBMC_PC_NWEIGHTS floats); RBMC_E_ARG if the model has none. */
+rbmc_status rbmc_precond_get_weights(rbmc_model* m, float* w);
+/* Set the weights (host, finite); they are used as given (usable = 1, no
+ * held-out ratio, no trial). */
 rbmc_status rbmc_precond_set_weights(rbmc_model* m, const float* w);
 
 /* Planner query, host only (no device needed): core label of every node

@@ -25,10 +25,11 @@ EXPORTS = ["rbmc_ctx_create", "rbmc_ctx_destroy", "rbmc_model_create", "rbmc_mod
            "rbmc_model_set_theta", "rbmc_apply_op", "rbmc_sample", "rbmc_estimate_from_samples",
            "rbmc_estimate", "rbmc_estimate_batched", "rbmc_plan_query", "rbmc_ctx_profile",
            "rbmc_ctx_profile_read", "rbmc_precond_train", "rbmc_precond_apply",
-           "rbmc_precond_get_weights", "rbmc_precond_set_weights", "rbmc_last_error"]
-RBMC_PC_NWEIGHTS = 14688
+           "rbmc_precond_get_weights", "rbmc_precond_set_weights", "rbmc_precond_info",
+           "rbmc_last_error"]
+RBMC_PC_NWEIGHTS = 15120
 # (cin, cout) of the learned correction's four convolutions, in weight order
-PC_LAYERS = [(1, 16), (16, 16), (16, 16), (16, 1)]
+PC_LAYERS = [(2, 16), (16, 16), (16, 16), (16, 1)]
 (RBMC_KF_GEMM, RBMC_KF_SPD_INVERSE, RBMC_KF_SPMM, RBMC_KF_RSTENCIL, RBMC_KF_PANELS,
  RBMC_KF_GEMM_MIXED, RBMC_KF_GEMM_SMALL, RBMC_KF_INV_SMALL, RBMC_KF_COUNT) = range(9)
 KF_NAMES = ["gemm", "spd_inverse", "spmm", "rstencil", "panels", "gemm_mixed", "gemm_small",
@@ -60,8 +61,13 @@ class rbmc_est_opts(C.Structure):
 
 class rbmc_train_opts(C.Structure):
     _fields_ = [("n_pairs", C.c_int32), ("epochs", C.c_int32), ("batch", C.c_int32),
-                ("lr", C.c_float), ("seed", C.c_uint64), ("crop_t", C.c_int32),
-                ("crop_xy", C.c_int32)]
+                ("lr", C.c_float), ("seed", C.c_uint64)]
+
+
+class rbmc_pc_info(C.Structure):
+    _fields_ = [("ready", C.c_int32), ("usable", C.c_int32), ("val_ratio", C.c_double),
+                ("trial_it_bj", C.c_int32), ("trial_it_learned", C.c_int32),
+                ("trial_s_bj", C.c_double), ("trial_s_learned", C.c_double)]
 
 
 class rbmc_report(C.Structure):
@@ -111,9 +117,9 @@ def lib():
         L.rbmc_precond_train.argtypes = [vp, C.POINTER(rbmc_est_opts), C.POINTER(rbmc_train_opts),
                                          vp, C.c_int32, C.POINTER(C.c_float),
                                          C.POINTER(rbmc_report)]
-        L.rbmc_precond_apply.argtypes = [vp, vp, vp, C.c_int32]
-        L.rbmc_precond_get_weights.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(C.c_int32),
-                                               C.POINTER(C.c_double)]
+        L.rbmc_precond_apply.argtypes = [vp, vp, vp, vp, C.c_int32]
+        L.rbmc_precond_get_weights.argtypes = [vp, C.POINTER(C.c_float)]
+        L.rbmc_precond_info.argtypes = [vp, C.POINTER(rbmc_pc_info)]
         L.rbmc_precond_set_weights.argtypes = [vp, C.POINTER(C.c_float)]
         L.rbmc_last_error.restype = C.c_char_p
         for name in EXPORTS:
@@ -215,18 +221,21 @@ def rbmc_precond_train(m, pcg_opts, train_opts, z, n_train):
     return st, list(loss), rep
 
 
-def rbmc_precond_apply(m, r, y, n_rhs):
-    return check(lib().rbmc_precond_apply(m, _ptr(r), _ptr(y), n_rhs))
+def rbmc_precond_apply(m, r, u, y, n_rhs):
+    return check(lib().rbmc_precond_apply(m, _ptr(r), _ptr(u), _ptr(y), n_rhs))
 
 
 def rbmc_precond_get_weights(m):
     import numpy as np
     w = np.zeros(RBMC_PC_NWEIGHTS, np.float32)
-    usable = C.c_int32()
-    err = C.c_double()
-    check(lib().rbmc_precond_get_weights(m, w.ctypes.data_as(C.POINTER(C.c_float)),
-                                         C.byref(usable), C.byref(err)))
-    return w, bool(usable.value), err.value
+    check(lib().rbmc_precond_get_weights(m, w.ctypes.data_as(C.POINTER(C.c_float))))
+    return w
+
+
+def rbmc_precond_info(m):
+    info = rbmc_pc_info()
+    check(lib().rbmc_precond_info(m, C.byref(info)))
+    return info
 
 
 def rbmc_precond_set_weights(m, w):
@@ -269,8 +278,8 @@ def make_opts(n_samples, pcg_maxit=2000, pcg_rtol=1e-8, grad_mask=0b111,
     return rbmc_est_opts(n_samples, pcg_maxit, pcg_rtol, precision, precond, grad_mask, 0)
 
 
-def make_train_opts(n_pairs=2000, epochs=5, batch=8, lr=1e-3, seed=1, crop_t=0, crop_xy=0):
-    return rbmc_train_opts(n_pairs, epochs, batch, lr, seed, crop_t, crop_xy)
+def make_train_opts(n_pairs=2000, epochs=5, batch=8, lr=1e-3, seed=1):
+    return rbmc_train_opts(n_pairs, epochs, batch, lr, seed)
 
 
 def popcount(mask: int) -> int:

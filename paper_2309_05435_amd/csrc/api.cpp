@@ -123,7 +123,11 @@ struct rbmc_ctx {
   int ws_cols = 0, ws_models = 0;
   double *r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr, *x = nullptr, *zcat = nullptr;
   double* zp = nullptr;        // previous preconditioned residual (flexible PCG)
-  double* scal = nullptr;      // 8 x columns
+  double* scal = nullptr;      // 9 x columns
+  // learned correction v = N_w(r, u) and Q v per column (allocated on first use)
+  Pool lws;
+  size_t lws_len = 0;
+  double *lv = nullptr, *lqv = nullptr;
   double* part = nullptr;      // column partial sums
   size_t part_len = 0;
   uint8_t* active = nullptr;
@@ -263,7 +267,9 @@ struct rbmc_model {
   struct Learned {
     bool ready = false;          // weights present
     bool usable = false;         // validated: reduces the preconditioner error
-    double val_rel_err = -1.0;   // held-out ||N(r) - t|| / ||t|| after training
+    double val_rel_err = -1.0;   // held-out energy error with / without N_w
+    int trial_bj = -1, trial_lrn = -1;  // PCG iterations of the acceptance trial
+    double trial_s_bj = -1.0, trial_s_lrn = -1.0;  // and its sampler seconds
     float* w = nullptr;          // FP32 weights (device)
     uint16_t* wb = nullptr;      // BF16 weights used by the kernels
     uint16_t* wf = nullptr;      // BF16 flipped/transposed weights (input gradients)
@@ -951,7 +957,7 @@ rbmc_status ensure_ws(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const Ho
       cx->ws_zlen = h.ztotal;
     }
     const int nc = std::max(ncols, 1);
-    HIPCHK(cx->ws.alloc((void**)&cx->scal, (size_t)8 * nc * 8));
+    HIPCHK(cx->ws.alloc((void**)&cx->scal, (size_t)9 * nc * 8));
     HIPCHK(cx->ws.alloc((void**)&cx->part, part * 8));
     HIPCHK(cx->ws.alloc((void**)&cx->active, (size_t)nc));
     HIPCHK(cx->ws.alloc((void**)&cx->iters, (size_t)(nc + 1) * 4));
@@ -1019,9 +1025,10 @@ rbmc_status factor_bj(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, rbmc_rep
 
 // Block-Jacobi PCG on Q x = F z for every column of the set (caller's stream).
 // z, x: multi-vectors in the column layout h (z with n + n_obs per column).
-// Learned correction y += N_w(r) for the columns of one model (defined below).
-rbmc_status learned_apply(rbmc_ctx* cx, rbmc_model* m, const double* r, const double* rr,
-                          const uint8_t* active, double* y, int ncols, int accumulate,
+// Learned correction y = N_w(r, u) for the columns of one model, inputs
+// divided by sqrt(rr[c]) and the output multiplied back (defined below).
+rbmc_status learned_apply(rbmc_ctx* cx, rbmc_model* m, const double* r, const double* u,
+                          const double* rr, const uint8_t* active, double* y, int ncols,
                           hipStream_t s);
 bool learned_usable(const rbmc_model* m);
 
@@ -1035,9 +1042,11 @@ rbmc_status sample_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const H
                        hipStream_t s, const SampleHook& hook = {}) {
   const int nk = o->n_samples;
   double t0 = now_s();
-  // the learned correction makes the preconditioner vary between iterations:
-  // flexible (Polak-Ribiere) PCG, z_prev kept in zp
-  const bool learned = o->precond == RBMC_PC_BJ_LEARNED;
+  // the learned correction makes the preconditioner nonlinear: flexible
+  // (Polak-Ribiere) PCG, z_prev kept in zp
+  bool learned = false;
+  if (o->precond == RBMC_PC_BJ_LEARNED)
+    for (rbmc_model* m : ms) learned = learned || learned_usable(m);
   rbmc_status st = factor_bj(cx, ms, rep, s);
   if (st != RBMC_OK) return st;
   const ColSet cols = colset(cx, h);
@@ -1094,7 +1103,21 @@ rbmc_status sample_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const H
   build_solve(cs, nk, stop, pre, ar, o->precision == RBMC_MIXED);
   sca.panels(ar, sc);
   HIPCHK(ar.upload(s));
-  // z = M^-1 r (+ N_w(r) per model); rrv: the current squared residual norms
+  if (learned && cx->lws_len < h.total) {
+    cx->lws.release();
+    cx->lws_len = 0;
+    HIPCHK(cx->lws.alloc((void**)&cx->lv, h.total * 8));
+    HIPCHK(cx->lws.alloc((void**)&cx->lqv, h.total * 8));
+    cx->lws_len = h.total;
+  }
+  if (learned)  // columns of models without a usable correction keep v = 0
+    HIPCHK(hipMemsetAsync(cx->lv, 0, h.total * 8, s));
+  double* vr = cx->scal + 6 * nc;
+  double* vqu = cx->scal + 7 * nc;
+  double* vqv = cx->scal + 8 * nc;
+  // z = u + g v with u = M^-1 r, v = N_w(r, u) and the per-column step g
+  // minimizing ||z - Q^-1 r||_Q (models with a usable correction);
+  // rrv: the current squared residual norms.  q is free here and holds Q u.
   auto precond = [&](const double* rrv) -> rbmc_status {
     rbmc_status e = run(cx, gat, s, ar);
     if (e != RBMC_OK) return e;
@@ -1105,12 +1128,28 @@ rbmc_status sample_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const H
     int col0 = 0;
     for (size_t j = 0; j < ms.size(); ++j) {
       if (learned_usable(ms[j])) {
-        e = learned_apply(cx, ms[j], r + h.base[j], rrv + col0, cx->active + col0,
-                          zz + h.base[j], nk, 1, s);
+        e = learned_apply(cx, ms[j], r + h.base[j], zz + h.base[j], rrv + col0,
+                          cx->active + col0, cx->lv + h.base[j], nk, s);
         if (e != RBMC_OK) return e;
       }
       col0 += nk;
     }
+    launch_apply_op(cols, RBMC_OP_Q, zz, q, s);
+    launch_apply_op(cols, RBMC_OP_Q, cx->lv, cx->lqv, s);
+    launch_dot_partials(cols, cx->lv, r, cx->part, s);
+    launch_reduce_partials(cx->part, nch, nc, vr, s);
+    launch_dot_partials(cols, cx->lv, q, cx->part, s);
+    launch_reduce_partials(cx->part, nch, nc, vqu, s);
+    launch_dot_partials(cols, cx->lv, cx->lqv, cx->part, s);
+    launch_reduce_partials(cx->part, nch, nc, vqv, s);
+    col0 = 0;
+    for (size_t j = 0; j < ms.size(); ++j) {
+      if (learned_usable(ms[j]))
+        launch_gamma_axpy(cx->lv + h.base[j], zz + h.base[j], (size_t)ms[j]->plan.n, vr + col0,
+                          vqu + col0, vqv + col0, cx->active + col0, nk, s);
+      col0 += nk;
+    }
+    HIPCHK(hipGetLastError());
     return RBMC_OK;
   };
   double* rzp = cx->scal + 5 * nc;
@@ -1566,17 +1605,17 @@ rbmc_status estimate_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const
 
 
 // ---------------------------------------------------------------------------
-// Learned correction N_w: 4 convolutions 3^3 (1 -> 16 -> 16 -> 16 -> 1), ReLU
-// between them, no bias (so N_w(a r) = a N_w(r) for a > 0), on the space-time
-// grid of each sample.  Weights: layer l occupies [kWOff[l], kWOff[l+1]).
+// Learned correction N_w: 4 convolutions 3^3 (2 -> 16 -> 16 -> 16 -> 1), ReLU
+// between them, no bias (so N_w(a r, a u) = a N_w(r, u) for a > 0), on the
+// space-time grid of each sample; inputs r and u = M_BJ^-1 r.  Weights:
+// layer l occupies [kWOff[l], kWOff[l+1]).
 // ---------------------------------------------------------------------------
 constexpr int kNL = 4;
-constexpr int kCin[kNL] = {1, 16, 16, 16};
+constexpr int kCin[kNL] = {2, 16, 16, 16};
 constexpr int kCout[kNL] = {16, 16, 16, 1};
-constexpr int kWOff[kNL + 1] = {0, 432, 432 + 6912, 432 + 2 * 6912, 2 * 432 + 2 * 6912};
+constexpr int kWOff[kNL + 1] = {0, 864, 864 + 6912, 864 + 2 * 6912, 864 + 2 * 6912 + 432};
 constexpr int kNW = kWOff[kNL];
 static_assert(kNW == RBMC_PC_NWEIGHTS, "weight count");
-constexpr int kHalo = kNL;  // receptive-field radius of the network
 
 bool learned_usable(const rbmc_model* m) { return m->lrn.ready && m->lrn.usable; }
 
@@ -1600,17 +1639,16 @@ void learned_derive(rbmc_model* m, hipStream_t s) {
 
 ConvGeom model_geom(const rbmc_model* m) { return ConvGeom{m->plan.T, m->plan.my, m->plan.mx}; }
 
-// Forward pass over `batch` volumes: in (B x 1 x V) -> out (B x 1 x V);
+// Forward pass over `batch` volumes: in (B x 2 x V) -> out (B x 1 x V);
 // h[0..2]: B x 16 x V pre-activations (h[2] may alias h[0]).
-void learned_forward(const rbmc_model* m, ConvGeom g, const ConvBox* boxes, int batch,
-                     const float* in, float* const h[3], float* out, hipStream_t s) {
+void learned_forward(const rbmc_model* m, ConvGeom g, int batch, const float* in,
+                     float* const h[3], float* out, hipStream_t s) {
   const float* src = in;
   for (int l = 0; l < kNL; ++l) {
     ConvArgs a{};
     a.in = src;
     a.out = (l == kNL - 1) ? out : h[l];
     a.w = m->lrn.wb + kWOff[l];
-    a.boxes = boxes;
     a.geom = g;
     a.relu_in = l > 0;
     a.scale = 1.f;
@@ -1619,14 +1657,14 @@ void learned_forward(const rbmc_model* m, ConvGeom g, const ConvBox* boxes, int 
   }
 }
 
-rbmc_status learned_apply(rbmc_ctx* cx, rbmc_model* m, const double* r, const double* rr,
-                          const uint8_t* active, double* y, int ncols, int accumulate,
+rbmc_status learned_apply(rbmc_ctx* cx, rbmc_model* m, const double* r, const double* u,
+                          const double* rr, const uint8_t* active, double* y, int ncols,
                           hipStream_t s) {
   (void)cx;
   const ConvGeom g = model_geom(m);
   const size_t V = (size_t)m->plan.n;
-  // columns per chunk: in, out and two 16-channel buffers within ~4 GB
-  const size_t per_col = V * 4 * (1 + 1 + 16 + 16);
+  // columns per chunk: input (2 channels), output, two 16-channel buffers, within ~4 GB
+  const size_t per_col = V * 4 * (2 + 1 + 16 + 16);
   const int cb = (int)std::max<size_t>(1, std::min<size_t>(ncols, ((size_t)4 << 30) / per_col));
   if (m->lwork_cols < (size_t)cb) {
     m->lwork.release();
@@ -1637,29 +1675,48 @@ rbmc_status learned_apply(rbmc_ctx* cx, rbmc_model* m, const double* r, const do
   }
   float* base = (float*)m->lwork.ptrs[0];
   float* vin = base;
-  float* vout = vin + V * cb;
+  float* vout = vin + 2 * V * cb;
   float* ha = vout + V * cb;
   float* hb = ha + 16 * V * cb;
   float* const hs[3] = {ha, hb, ha};
   for (int c0 = 0; c0 < ncols; c0 += cb) {
     const int nc = std::min(cb, ncols - c0);
-    launch_cols_to_vol(r + (size_t)c0 * V, V, rr ? rr + c0 : nullptr, vin, nc, s);
-    learned_forward(m, g, nullptr, nc, vin, hs, vout, s);
+    launch_cols2_to_vol(r + (size_t)c0 * V, u + (size_t)c0 * V, V, rr ? rr + c0 : nullptr, vin,
+                        nc, s);
+    learned_forward(m, g, nc, vin, hs, vout, s);
     launch_vol_to_cols(vout, V, rr ? rr + c0 : nullptr, active ? active + c0 : nullptr,
-                       y + (size_t)c0 * V, nc, accumulate, s);
+                       y + (size_t)c0 * V, nc, 0, s);
   }
   HIPCHK(hipGetLastError());
   return RBMC_OK;
 }
 
+// Scale the first layer's u-channel weights by a and the last layer by b
+// (host round trip; used to fold / unfold the input and output scales).
+rbmc_status learned_rescale(rbmc_model* m, double a, double b, hipStream_t s) {
+  std::vector<float> w(kNW);
+  HIPCHK(hipMemcpyAsync(w.data(), m->lrn.w, kNW * 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int co = 0; co < kCout[0]; ++co)
+    for (int k = 0; k < 27; ++k) w[(co * kCin[0] + 1) * 27 + k] = (float)(w[(co * kCin[0] + 1) * 27 + k] * a);
+  for (int i = kWOff[kNL - 1]; i < kWOff[kNL]; ++i) w[i] = (float)(w[i] * b);
+  HIPCHK(hipMemcpyAsync(m->lrn.w, w.data(), kNW * 4, hipMemcpyHostToDevice, s));
+  learned_derive(m, s);
+  HIPCHK(hipStreamSynchronize(s));
+  return RBMC_OK;
+}
+
 // Training of N_w on pairs generated by the sampler itself.  A first
-// block-Jacobi PCG run on the given right-hand sides gives x*; a second,
-// identical run stops at n_sel evenly spaced iterations k, where the error
-// left by the block-Jacobi preconditioner is t_k = (x* - x_k) - M^-1 r_k
-// (Q e_k = r_k for the error e_k = x* - x_k); random crops of r_k / |r_k|
-// (with a halo of the network's receptive field) and of t_k / |r_k| form the
-// pairs.  Adam on the mean over a batch of ||N_w(r) - t||^2 / ||t||^2 over
-// the crop interiors; the last tenth of the pairs is held out.
+// block-Jacobi PCG run on the given right-hand sides, 1000 times tighter than
+// the caller's tolerance, gives x*; an identical second run stops at n_sel
+// evenly spaced iterations k in the first three quarters of its iterations
+// (so that x* - x_k is accurate to about 1e-3); every column there gives a
+// pair (r_k, u_k, e_k) / |r_k| with u_k = M^-1 r_k and e_k = x* - x_k
+// (Q e_k = r_k).  The network sees (r, s u) and its output y gives the
+// correction y / s, with s the RMS ratio of r to u over the pairs (folded into
+// the weights afterwards).  Adam minimizes the mean over a batch of the
+// relative energy error ||u + y / s - e||_Q^2 / (e . r) on whole grids; the
+// last tenth of the pairs is held out.
 rbmc_status precond_train(rbmc_model* m, const rbmc_est_opts* po, const rbmc_train_opts* to,
                           const double* z, int n_train, float* loss_out, rbmc_report* rep) {
   rbmc_ctx* cx = m->ctx;
@@ -1668,24 +1725,20 @@ rbmc_status precond_train(rbmc_model* m, const rbmc_est_opts* po, const rbmc_tra
   if (st != RBMC_OK) return st;
   const ConvGeom g = model_geom(m);
   const size_t n = (size_t)m->plan.n;
-  const int ct = std::min(to->crop_t > 0 ? to->crop_t : 16, g.T);
-  const int cxy = to->crop_xy > 0 ? to->crop_xy : 64;
-  const int cy = std::min(cxy, g.MY), cxx = std::min(cxy, g.MX);
-  const ConvGeom cg{ct + 2 * kHalo, cy + 2 * kHalo, cxx + 2 * kHalo};
-  const size_t cv = (size_t)cg.T * cg.MY * cg.MX;
   const int npairs = std::max(to->n_pairs, 2);
+  if ((double)npairs * n * 12.0 > 16.0 * (1ull << 30))
+    return fail(RBMC_E_ARG, "training pairs exceed 16 GiB (reduce n_pairs)");
   std::mt19937_64 rng(to->seed);
-  // initial weights: He-scaled normals (last layer 10x smaller)
-  if (!m->lrn.ready) {
-    std::vector<float> w(kNW);
-    for (int l = 0; l < kNL; ++l) {
-      std::normal_distribution<float> nd(0.f, std::sqrt(2.f / (kCin[l] * 27.f)) *
-                                                   (l == kNL - 1 ? 0.1f : 1.f));
+  const bool fresh = !m->lrn.ready;
+  if (fresh) {
+    // He-scaled normals; the last layer zero, so training starts from block Jacobi
+    std::vector<float> w(kNW, 0.f);
+    for (int l = 0; l < kNL - 1; ++l) {
+      std::normal_distribution<float> nd(0.f, std::sqrt(2.f / (kCin[l] * 27.f)));
       for (int i = kWOff[l]; i < kWOff[l + 1]; ++i) w[i] = nd(rng);
     }
     HIPCHK(hipMemcpyAsync(m->lrn.w, w.data(), kNW * 4, hipMemcpyHostToDevice, s));
     learned_derive(m, s);
-    m->lrn.ready = true;
   }
   HIPCHK(hipMemsetAsync(m->lrn.am, 0, kNW * 4, s));
   HIPCHK(hipMemsetAsync(m->lrn.av, 0, kNW * 4, s));
@@ -1693,6 +1746,8 @@ rbmc_status precond_train(rbmc_model* m, const rbmc_est_opts* po, const rbmc_tra
   rbmc_est_opts o = *po;
   o.n_samples = n_train;
   o.precond = RBMC_PC_BJ;
+  o.pcg_rtol = std::max(std::min(po->pcg_rtol, 1e-8) * 1e-3, 1e-14);
+  o.pcg_maxit = std::max(po->pcg_maxit, 1) * 2;
   std::vector<rbmc_model*> ms{m};
   const HostCols h = make_cols(ms, n_train);
   st = ensure_ws(cx, ms, h, false);
@@ -1704,61 +1759,43 @@ rbmc_status precond_train(rbmc_model* m, const rbmc_est_opts* po, const rbmc_tra
     Pool& p;
     ~Release() { p.release(); }
   } rel{tp};
-  double *xs = nullptr, *tv = nullptr;
-  float *pin = nullptr, *ptg = nullptr, *ptn = nullptr;
-  ConvBox* pbox = nullptr;
-  CropSpec* dspec = nullptr;
+  double* xs = nullptr;
+  float *R = nullptr, *U = nullptr, *E = nullptr;
+  int* dslot = nullptr;
   HIPCHK(tp.alloc((void**)&xs, n * n_train * 8));
-  HIPCHK(tp.alloc((void**)&tv, n * n_train * 8));
-  HIPCHK(tp.alloc((void**)&pin, cv * npairs * 4));
-  HIPCHK(tp.alloc((void**)&ptg, cv * npairs * 4));
-  HIPCHK(tp.alloc((void**)&ptn, (size_t)npairs * 4));
-  HIPCHK(tp.alloc((void**)&pbox, (size_t)npairs * sizeof(ConvBox)));
-  HIPCHK(tp.alloc((void**)&dspec, (size_t)npairs * 2 * sizeof(CropSpec)));
-  {
-    std::vector<float> ones(npairs, 1.f);
-    HIPCHK(hipMemcpyAsync(ptn, ones.data(), npairs * 4, hipMemcpyHostToDevice, s));
-  }
+  HIPCHK(tp.alloc((void**)&R, n * npairs * 4));
+  HIPCHK(tp.alloc((void**)&U, n * npairs * 4));
+  HIPCHK(tp.alloc((void**)&E, n * npairs * 4));
+  HIPCHK(tp.alloc((void**)&dslot, (size_t)std::max(n_train, npairs) * 4));
   rbmc_report r1{};
   st = sample_set(cx, ms, h, &o, z, xs, &r1, s);
   if (st < 0) return st;
   const int nit = std::max(r1.pcg_it_max, 1);
-  const int per_it = std::max(1, (npairs + nit * n_train - 1) / (nit * n_train));
-  const int n_sel = std::min(nit, (npairs + per_it * n_train - 1) / (per_it * n_train));
+  const int span = std::max(1, (3 * nit) / 4);
+  const int n_sel = std::max(1, std::min(span, (npairs + n_train - 1) / n_train));
   std::vector<int> sel_it(n_sel);
-  for (int i = 0; i < n_sel; ++i) sel_it[i] = (int)((long long)i * nit / n_sel);
-  std::vector<int> slot(npairs);  // random slot order so batches are random
-  for (int i = 0; i < npairs; ++i) slot[i] = i;
-  std::shuffle(slot.begin(), slot.end(), rng);
-  std::vector<ConvBox> boxes(npairs);
+  for (int i = 0; i < n_sel; ++i) sel_it[i] = (int)((long long)i * span / n_sel);
   int made = 0, next_sel = 0;
   std::vector<double> hrr(n_train);
+  std::vector<int> cslot(n_train), pair_col;
+  // the last quarter of the columns is held out: its pairs validate, and the
+  // acceptance trial runs on its right-hand sides
+  const int n_hold = std::max(1, n_train / 4);
+  const int c_hold = n_train - n_hold;
   SampleHook hook = [&](int it, const double* x, const double* r, const double* zk,
                         const double* rrv) -> rbmc_status {
-    if (next_sel >= n_sel || it != sel_it[next_sel] || made >= npairs) return RBMC_OK;
+    if (next_sel >= n_sel || made >= npairs) return RBMC_W_NOT_CONVERGED;  // done: stop the run
+    if (it != sel_it[next_sel]) return RBMC_OK;
     ++next_sel;
     HIPCHK(hipMemcpyAsync(hrr.data(), rrv, n_train * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    launch_sub3(xs, x, zk, tv, n * n_train, s);  // t = x* - x_k - M^-1 r_k
-    std::vector<CropSpec> sp;
-    for (int c = 0; c < n_train && made < npairs; ++c) {
-      if (!(hrr[c] > 0.0)) continue;
-      for (int k = 0; k < per_it && made < npairs; ++k, ++made) {
-        const int it0 = std::uniform_int_distribution<int>(0, g.T - ct)(rng);
-        const int iy0 = std::uniform_int_distribution<int>(0, g.MY - cy)(rng);
-        const int ix0 = std::uniform_int_distribution<int>(0, g.MX - cxx)(rng);
-        CropSpec c1{c, slot[made], it0 - kHalo, iy0 - kHalo, ix0 - kHalo, 1.0 / std::sqrt(hrr[c])};
-        sp.push_back(c1);
-        ConvBox b{std::max(0, -c1.ot), std::min(cg.T, g.T - c1.ot), std::max(0, -c1.oy),
-                  std::min(cg.MY, g.MY - c1.oy), std::max(0, -c1.ox), std::min(cg.MX, g.MX - c1.ox)};
-        boxes[slot[made]] = b;
-      }
+    for (int c = 0; c < n_train; ++c) {
+      cslot[c] = (hrr[c] > 0.0 && made < npairs) ? made++ : -1;
+      if (cslot[c] >= 0) pair_col.push_back(c);
     }
-    if (sp.empty()) return RBMC_OK;
-    HIPCHK(hipMemcpyAsync(dspec, sp.data(), sp.size() * sizeof(CropSpec), hipMemcpyHostToDevice, s));
-    launch_crop(r, g, dspec, (int)sp.size(), cg, pin, s);
-    launch_crop(tv, g, dspec, (int)sp.size(), cg, ptg, s);
-    HIPCHK(hipStreamSynchronize(s));  // dspec is reused by the next stop
+    HIPCHK(hipMemcpyAsync(dslot, cslot.data(), n_train * 4, hipMemcpyHostToDevice, s));
+    launch_pair_store(r, zk, xs, x, n, rrv, dslot, R, U, E, n_train, s);
+    HIPCHK(hipStreamSynchronize(s));  // dslot is reused by the next stop
     return RBMC_OK;
   };
   rbmc_report r2{};
@@ -1766,101 +1803,135 @@ rbmc_status precond_train(rbmc_model* m, const rbmc_est_opts* po, const rbmc_tra
   if (st < 0) return st;
   if (made < 2) return fail(RBMC_E_ARG, "too few training pairs (the sampler converged at once)");
   const int np_used = made;
-  std::vector<int> used_slots(slot.begin(), slot.begin() + np_used);
-  std::sort(used_slots.begin(), used_slots.end());
-  // slots are a permutation of [0, npairs); compact the used ones to [0, np_used)
-  // by training only on the slots that were filled
-  std::vector<int> order = used_slots;
-  HIPCHK(hipMemcpyAsync(pbox, boxes.data(), npairs * sizeof(ConvBox), hipMemcpyHostToDevice, s));
-  // interior norms ||t||^2 per pair
-  const int lblk = 32;
-  float* lpart = nullptr;
-  HIPCHK(tp.alloc((void**)&lpart, (size_t)npairs * lblk * 2 * 4));
-  for (int slot_i : order) {
-    launch_crop_loss(ptg + (size_t)slot_i * cv, ptg + (size_t)slot_i * cv, pbox + slot_i,
-                     ptn + slot_i, cg, kHalo, 1, nullptr, lpart + (size_t)slot_i * lblk * 2, lblk,
-                     s);
+  // per-pair e . r (= ||e||_Q^2) and the input scale s = RMS(r) / RMS(u)
+  const int nblk = 64;
+  double* part = nullptr;
+  HIPCHK(tp.alloc((void**)&part, (size_t)std::max(np_used, 8) * nblk * 8));
+  {
+    std::vector<int> iota(np_used);
+    for (int i = 0; i < np_used; ++i) iota[i] = i;
+    HIPCHK(hipMemcpyAsync(dslot, iota.data(), np_used * 4, hipMemcpyHostToDevice, s));
   }
-  std::vector<float> hpart((size_t)npairs * lblk * 2);
-  HIPCHK(hipMemcpyAsync(hpart.data(), lpart, hpart.size() * 4, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  std::vector<float> tn(npairs, 1.f);
-  for (int slot_i : order) {
-    double a = 0.0;
-    for (int k = 0; k < lblk; ++k) a += hpart[((size_t)slot_i * lblk + k) * 2 + 1];
-    tn[slot_i] = (float)std::max(a, 1e-30);
-  }
-  HIPCHK(hipMemcpyAsync(ptn, tn.data(), npairs * 4, hipMemcpyHostToDevice, s));
-  // ---- training ----
-  const int B = std::max(1, std::min(to->batch > 0 ? to->batch : 8, np_used));
-  const int n_val = std::max(1, np_used / 10);
-  const int n_fit = np_used - n_val;
-  std::vector<int> fit(order.begin(), order.begin() + n_fit), val(order.begin() + n_fit, order.end());
-  // batches must be contiguous slots: train on runs of B consecutive used slots
-  float *bin = nullptr, *btg = nullptr, *bdy = nullptr, *hbuf = nullptr, *gbuf = nullptr,
-        *wpart = nullptr;
-  ConvBox* bbox = nullptr;
-  float* btn = nullptr;
-  HIPCHK(tp.alloc((void**)&bin, cv * B * 4));
-  HIPCHK(tp.alloc((void**)&btg, cv * B * 4));
-  HIPCHK(tp.alloc((void**)&bdy, cv * B * 4));
-  HIPCHK(tp.alloc((void**)&hbuf, cv * B * 16 * 3 * 4));
-  HIPCHK(tp.alloc((void**)&gbuf, cv * B * 16 * 2 * 4));
-  HIPCHK(tp.alloc((void**)&bbox, (size_t)B * sizeof(ConvBox)));
-  HIPCHK(tp.alloc((void**)&btn, (size_t)B * 4));
-  const int wt_tiles = conv_wgrad_tiles(cg);
-  HIPCHK(tp.alloc((void**)&wpart, (size_t)wt_tiles * B * 16 * 16 * 27 * 4));
-  float* const hs[3] = {hbuf, hbuf + cv * B * 16, hbuf + cv * B * 32};
-  float* yout = bdy;  // forward output, then overwritten by dL/dy
-  float* ga = gbuf;
-  float* gb = gbuf + cv * B * 16;
-  auto load_batch = [&](const std::vector<int>& ids, int i0, int nb) -> rbmc_status {
-    for (int k = 0; k < nb; ++k) {
-      const int sl = ids[i0 + k];
-      HIPCHK(hipMemcpyAsync(bin + cv * k, pin + cv * sl, cv * 4, hipMemcpyDeviceToDevice, s));
-      HIPCHK(hipMemcpyAsync(btg + cv * k, ptg + cv * sl, cv * 4, hipMemcpyDeviceToDevice, s));
-      HIPCHK(hipMemcpyAsync(bbox + k, pbox + sl, sizeof(ConvBox), hipMemcpyDeviceToDevice, s));
-      HIPCHK(hipMemcpyAsync(btn + k, ptn + sl, 4, hipMemcpyDeviceToDevice, s));
-    }
-    return RBMC_OK;
-  };
-  auto batch_loss = [&](int nb, bool grad, double* err, double* ref) -> rbmc_status {
-    learned_forward(m, cg, bbox, nb, bin, hs, yout, s);
-    launch_crop_loss(yout, btg, bbox, btn, cg, kHalo, nb, grad ? bdy : nullptr, lpart, lblk, s);
-    std::vector<float> lp((size_t)nb * lblk * 2);
-    HIPCHK(hipMemcpyAsync(lp.data(), lpart, lp.size() * 4, hipMemcpyDeviceToHost, s));
+  auto pair_sums = [&](const float* a, const float* b2, std::vector<double>& out) -> rbmc_status {
+    launch_energy_dot(nullptr, a, dslot, nullptr, b2, n, nullptr, nullptr, part, nblk, np_used, s);
+    std::vector<double> hp((size_t)np_used * nblk);
+    HIPCHK(hipMemcpyAsync(hp.data(), part, hp.size() * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    *err = *ref = 0.0;
-    for (size_t k = 0; k < lp.size(); k += 2) {
-      *err += lp[k];
-      *ref += lp[k + 1];
+    out.assign(np_used, 0.0);
+    for (int i = 0; i < np_used; ++i)
+      for (int k = 0; k < nblk; ++k) out[i] += hp[(size_t)i * nblk + k];
+    return RBMC_OK;
+  };
+  std::vector<double> eref, rsq, usq;
+  if ((st = pair_sums(E, R, eref)) != RBMC_OK) return st;
+  if ((st = pair_sums(R, R, rsq)) != RBMC_OK) return st;
+  if ((st = pair_sums(U, U, usq)) != RBMC_OK) return st;
+  double sr = 0.0, su2 = 0.0;
+  for (int i = 0; i < np_used; ++i) {
+    sr += rsq[i];
+    su2 += usq[i];
+  }
+  const double su = (sr > 0.0 && su2 > 0.0) ? std::sqrt(sr / su2) : 1.0;
+  // pairs with a positive energy (all, in exact arithmetic): fitted ones from
+  // the training columns, held-out ones from the last n_hold columns
+  std::vector<int> fit, val;
+  for (int i = 0; i < np_used; ++i)
+    if (eref[i] > 0.0) (pair_col[i] < c_hold ? fit : val).push_back(i);
+  if (fit.empty() || val.empty())
+    return fail(RBMC_E_ARG, "too few training pairs (need n_train >= 2 and unconverged columns)");
+  std::vector<int> order(fit);
+  order.insert(order.end(), val.begin(), val.end());
+  if (!fresh) {  // continue from folded weights: unfold for the scaled inputs
+    st = learned_rescale(m, 1.0 / su, su, s);
+    if (st != RBMC_OK) return st;
+  }
+  // ---- training ----
+  const int B = std::max(1, std::min(to->batch > 0 ? to->batch : 8, (int)fit.size()));
+  const int n_val = (int)val.size();
+  const int n_fit = (int)fit.size();
+  const HostCols hB = make_cols(ms, B);
+  st = ensure_ws(cx, ms, hB, false);
+  if (st != RBMC_OK) return st;
+  const ColSet cB = colset(cx, hB);
+  float *bin = nullptr, *hbuf = nullptr, *gbuf = nullptr, *yout = nullptr, *gy = nullptr,
+        *wpart = nullptr, *dcoef = nullptr;
+  double *dcol = nullptr, *qd = nullptr;
+  int* bslot = nullptr;
+  HIPCHK(tp.alloc((void**)&bin, n * B * 2 * 4));
+  HIPCHK(tp.alloc((void**)&hbuf, n * B * 16 * 3 * 4));
+  HIPCHK(tp.alloc((void**)&gbuf, n * B * 16 * 2 * 4));
+  HIPCHK(tp.alloc((void**)&yout, n * B * 4));
+  HIPCHK(tp.alloc((void**)&gy, n * B * 4));
+  HIPCHK(tp.alloc((void**)&dcol, n * B * 8));
+  HIPCHK(tp.alloc((void**)&qd, n * B * 8));
+  HIPCHK(tp.alloc((void**)&bslot, (size_t)B * 4));
+  HIPCHK(tp.alloc((void**)&dcoef, (size_t)B * 4));
+  const int wt_tiles = conv_wgrad_tiles(g);
+  HIPCHK(tp.alloc((void**)&wpart, (size_t)wt_tiles * B * 16 * 16 * 27 * 4));
+  float* const hs[3] = {hbuf, hbuf + n * B * 16, hbuf + n * B * 32};
+  float* ga = gbuf;
+  float* gb = gbuf + n * B * 16;
+  std::vector<int> hsl(B);
+  std::vector<float> hcoef(B);
+  std::vector<double> hp((size_t)B * nblk);
+  // energy error of a batch (per pair: d^T Q d / (e . r)); with_net false:
+  // block Jacobi alone; grad: also the output gradient in gy
+  auto batch_energy = [&](const std::vector<int>& ids, int i0, int nb, bool with_net, bool grad,
+                          std::vector<double>& out) -> rbmc_status {
+    for (int k = 0; k < nb; ++k) {
+      hsl[k] = ids[i0 + k];
+      hcoef[k] = (float)(2.0 / (su * eref[hsl[k]] * nb));
+    }
+    HIPCHK(hipMemcpyAsync(bslot, hsl.data(), nb * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(dcoef, hcoef.data(), nb * 4, hipMemcpyHostToDevice, s));
+    if (with_net) {
+      launch_pack_train(R, U, bslot, n, (float)su, bin, nb, s);
+      learned_forward(m, g, nb, bin, hs, yout, s);
+    }
+    launch_energy_d(U, E, with_net ? yout : nullptr, bslot, n, (float)(1.0 / su), dcol, nb, s);
+    ColSet c = cB;
+    c.ncols = nb;
+    launch_apply_op(c, RBMC_OP_Q, dcol, qd, s);
+    launch_energy_dot(dcol, nullptr, bslot, qd, nullptr, n, dcoef, grad ? gy : nullptr, part,
+                      nblk, nb, s);
+    HIPCHK(hipMemcpyAsync(hp.data(), part, (size_t)nb * nblk * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    out.assign(nb, 0.0);
+    for (int k = 0; k < nb; ++k) {
+      for (int j = 0; j < nblk; ++j) out[k] += hp[(size_t)k * nblk + j];
+      out[k] /= eref[hsl[k]];
     }
     return RBMC_OK;
   };
+  // block-Jacobi energy error of every pair (the baseline of the ratios)
+  std::vector<double> base_e(np_used, 0.0), be;
+  for (int i0 = 0; i0 < (int)order.size(); i0 += B) {
+    const int nb = std::min(B, (int)order.size() - i0);
+    if ((st = batch_energy(order, i0, nb, false, false, be)) != RBMC_OK) return st;
+    for (int k = 0; k < nb; ++k) base_e[order[i0 + k]] = be[k];
+  }
   const int epochs = std::max(to->epochs, 0);
   const float lr = to->lr > 0.f ? to->lr : 1e-3f;
   int step = 0;
+  std::vector<double> le;
   for (int ep = 0; ep < epochs; ++ep) {
     std::shuffle(fit.begin(), fit.end(), rng);
-    double ep_err = 0.0, ep_ref = 0.0;
+    double ep_err = 0.0, ep_base = 0.0;
     for (int i0 = 0; i0 + B <= n_fit; i0 += B) {
-      st = load_batch(fit, i0, B);
-      if (st != RBMC_OK) return st;
-      double e = 0.0, rf = 0.0;
-      st = batch_loss(B, true, &e, &rf);
-      if (st != RBMC_OK) return st;
-      ep_err += e;
-      ep_ref += rf;
+      if ((st = batch_energy(fit, i0, B, true, true, le)) != RBMC_OK) return st;
+      for (int k = 0; k < B; ++k) {
+        ep_err += le[k];
+        ep_base += base_e[fit[i0 + k]];
+      }
       // backward: layer l consumes a_{l-1} = relu(h_{l-1}) (the input for l = 0)
-      const float* gout = bdy;  // dL/d(output of layer l)
+      const float* gout = gy;  // dL/d(output of layer l)
       for (int l = kNL - 1; l >= 0; --l) {
         const float* ain = (l == 0) ? bin : hs[l - 1];
         ConvWArgs wa{};
         wa.gout = gout;
         wa.ain = ain;
         wa.partial = wpart;
-        wa.boxes = bbox;
-        wa.geom = cg;
+        wa.geom = g;
         wa.relu_in = l > 0;
         launch_conv3d_wgrad(wa, kCin[l], kCout[l], B, s);
         launch_sum_rows(wpart, wt_tiles * B, kCout[l] * kCin[l] * 27, m->lrn.g + kWOff[l], s);
@@ -1870,8 +1941,7 @@ rbmc_status precond_train(rbmc_model* m, const rbmc_est_opts* po, const rbmc_tra
           a.out = (gout == ga) ? gb : ga;
           a.w = m->lrn.wf + kWOff[l];
           a.mask = hs[l - 1];
-          a.boxes = bbox;
-          a.geom = cg;
+          a.geom = g;
           a.scale = 1.f;
           launch_conv3d(a, kCout[l], kCin[l], B, s);
           gout = a.out;
@@ -1884,24 +1954,52 @@ rbmc_status precond_train(rbmc_model* m, const rbmc_est_opts* po, const rbmc_tra
         launch_conv_wflip(m->lrn.wb + kWOff[l], kCin[l], kCout[l], m->lrn.wf + kWOff[l], s);
       HIPCHK(hipGetLastError());
     }
-    if (loss_out) loss_out[ep] = (float)(ep_ref > 0 ? ep_err / ep_ref : 0.0);
+    if (loss_out) loss_out[ep] = (float)(ep_base > 0 ? ep_err / ep_base : 1.0);
   }
-  // held-out relative error of the correction (1 = no better than no correction)
-  double verr = 0.0, vref = 0.0;
+  // held-out energy error with the correction relative to block Jacobi alone
+  double verr = 0.0, vbase = 0.0;
   for (int i0 = 0; i0 < n_val; i0 += B) {
     const int nb = std::min(B, n_val - i0);
-    st = load_batch(val, i0, nb);
-    if (st != RBMC_OK) return st;
-    double e = 0.0, rf = 0.0;
-    st = batch_loss(nb, false, &e, &rf);
-    if (st != RBMC_OK) return st;
-    verr += e;
-    vref += rf;
+    if ((st = batch_energy(val, i0, nb, true, false, le)) != RBMC_OK) return st;
+    for (int k = 0; k < nb; ++k) {
+      verr += le[k];
+      vbase += base_e[val[i0 + k]];
+    }
   }
-  m->lrn.val_rel_err = vref > 0.0 ? std::sqrt(verr / vref) : 1.0;
-  m->lrn.usable = m->lrn.val_rel_err < 1.0;
+  m->lrn.val_rel_err = vbase > 0.0 ? verr / vbase : 1.0;
+  m->lrn.ready = true;
+  m->lrn.usable = false;
+  m->lrn.trial_bj = m->lrn.trial_lrn = -1;
+  m->lrn.trial_s_bj = m->lrn.trial_s_lrn = -1.0;
+  st = learned_rescale(m, su, 1.0 / su, s);  // fold the scales into the weights
+  if (st != RBMC_OK) return st;
+  if (m->lrn.val_rel_err < 1.0) {
+    // acceptance trial on the held-out right-hand sides at the caller's
+    // tolerance: the correction must save both iterations and time
+    const HostCols hh = make_cols(ms, n_hold);
+    st = ensure_ws(cx, ms, hh, false);
+    if (st != RBMC_OK) return st;
+    const double* zh = z + (size_t)c_hold * (n + (size_t)m->n_obs);
+    rbmc_est_opts ot = *po;
+    ot.n_samples = n_hold;
+    ot.precond = RBMC_PC_BJ;
+    // each run twice, the second timed (workspaces allocated, kernels loaded)
+    rbmc_report rb{}, rl{};
+    rbmc_status sb = RBMC_OK, sl = RBMC_OK;
+    for (int k = 0; k < 2 && sb >= 0; ++k) sb = sample_set(cx, ms, hh, &ot, zh, cx->x, &rb, s);
+    if (sb < 0) return sb;
+    m->lrn.usable = true;
+    ot.precond = RBMC_PC_BJ_LEARNED;
+    for (int k = 0; k < 2 && sl >= 0; ++k) sl = sample_set(cx, ms, hh, &ot, zh, cx->x, &rl, s);
+    m->lrn.usable = false;
+    if (sl < 0) return sl;
+    m->lrn.trial_bj = rb.pcg_it_max;
+    m->lrn.trial_lrn = rl.pcg_it_max;
+    m->lrn.trial_s_bj = rb.t_sample;
+    m->lrn.trial_s_lrn = rl.t_sample;
+    m->lrn.usable = sl == RBMC_OK && rl.pcg_it_max < rb.pcg_it_max && rl.t_sample < rb.t_sample;
+  }
   if (loss_out) loss_out[epochs] = (float)m->lrn.val_rel_err;
-  HIPCHK(hipStreamSynchronize(s));
   if (rep) {
     *rep = r1;
     rep->err_estimate = m->lrn.val_rel_err;
@@ -2284,13 +2382,11 @@ rbmc_status rbmc_precond_train(rbmc_model* m, const rbmc_est_opts* pcg_opts,
                                int32_t n_train, float* loss_out, rbmc_report* rep) {
   init_report(rep);
   if (!m || !pcg_opts || !train_opts || !z) return fail(RBMC_E_ARG, "NULL argument");
-  if (n_train < 1) return fail(RBMC_E_ARG, "n_train must be >= 1");
+  if (n_train < 2) return fail(RBMC_E_ARG, "n_train must be >= 2 (a quarter of the columns is held out)");
   if (pcg_opts->pcg_maxit < 1 || !(pcg_opts->pcg_rtol > 0.0))
     return fail(RBMC_E_ARG, "pcg_maxit must be >= 1 and pcg_rtol > 0");
   if (train_opts->n_pairs < 2 || train_opts->epochs < 0 || train_opts->batch < 0)
     return fail(RBMC_E_ARG, "n_pairs must be >= 2, epochs and batch >= 0");
-  if (train_opts->crop_t < 0 || train_opts->crop_xy < 0)
-    return fail(RBMC_E_ARG, "crop sizes must be >= 0 (0 = default)");
   HIPCHK(hipSetDevice(m->ctx->device));
   double t0 = now_s();
   rbmc_status st = precond_train(m, pcg_opts, train_opts, z, n_train, loss_out, rep);
@@ -2298,25 +2394,36 @@ rbmc_status rbmc_precond_train(rbmc_model* m, const rbmc_est_opts* pcg_opts,
   return st;
 }
 
-rbmc_status rbmc_precond_apply(rbmc_model* m, const double* r, double* y, int32_t n_rhs) {
-  if (!m || !r || !y) return fail(RBMC_E_ARG, "NULL argument");
+rbmc_status rbmc_precond_apply(rbmc_model* m, const double* r, const double* u, double* y,
+                               int32_t n_rhs) {
+  if (!m || !r || !u || !y) return fail(RBMC_E_ARG, "NULL argument");
   if (n_rhs < 0) return fail(RBMC_E_ARG, "n_rhs must be >= 0");
   if (!m->lrn.ready) return fail(RBMC_E_ARG, "the learned correction has no weights");
   if (n_rhs == 0) return RBMC_OK;
   HIPCHK(hipSetDevice(m->ctx->device));
-  rbmc_status st = learned_apply(m->ctx, m, r, nullptr, nullptr, y, n_rhs, 0, m->ctx->stream);
+  rbmc_status st = learned_apply(m->ctx, m, r, u, nullptr, nullptr, y, n_rhs, m->ctx->stream);
   if (st != RBMC_OK) return st;
   HIPCHK(hipStreamSynchronize(m->ctx->stream));
   return RBMC_OK;
 }
 
-rbmc_status rbmc_precond_get_weights(rbmc_model* m, float* w, int32_t* usable,
-                                     double* val_rel_err) {
+rbmc_status rbmc_precond_info(rbmc_model* m, rbmc_pc_info* info) {
+  if (!m || !info) return fail(RBMC_E_ARG, "NULL argument");
+  info->ready = m->lrn.ready ? 1 : 0;
+  info->usable = learned_usable(m) ? 1 : 0;
+  info->val_ratio = m->lrn.val_rel_err;
+  info->trial_it_bj = m->lrn.trial_bj;
+  info->trial_it_learned = m->lrn.trial_lrn;
+  info->trial_s_bj = m->lrn.trial_s_bj;
+  info->trial_s_learned = m->lrn.trial_s_lrn;
+  return RBMC_OK;
+}
+
+rbmc_status rbmc_precond_get_weights(rbmc_model* m, float* w) {
   if (!m || !w) return fail(RBMC_E_ARG, "NULL argument");
   if (!m->lrn.ready) return fail(RBMC_E_ARG, "the learned correction has no weights");
+  HIPCHK(hipSetDevice(m->ctx->device));
   HIPCHK(hipMemcpy(w, m->lrn.w, kNW * 4, hipMemcpyDeviceToHost));
-  if (usable) *usable = m->lrn.usable ? 1 : 0;
-  if (val_rel_err) *val_rel_err = m->lrn.val_rel_err;
   return RBMC_OK;
 }
 
@@ -2333,6 +2440,8 @@ rbmc_status rbmc_precond_set_weights(rbmc_model* m, const float* w) {
   m->lrn.ready = true;
   m->lrn.usable = true;  // weights given by the caller are taken as they are
   m->lrn.val_rel_err = -1.0;
+  m->lrn.trial_bj = m->lrn.trial_lrn = -1;
+  m->lrn.trial_s_bj = m->lrn.trial_s_lrn = -1.0;
   return RBMC_OK;
 }
 

@@ -112,10 +112,10 @@ __global__ __launch_bounds__(256) void k_conv3d(ConvArgs a) {
 
 void launch_conv3d(const ConvArgs& a, int cin, int cout, int batch, hipStream_t s) {
   const dim3 grid(conv_tiles(a.geom), batch);
-  if (cin == 1 && cout == 16) k_conv3d<1, 16><<<grid, 256, 0, s>>>(a);
+  if (cin == 2 && cout == 16) k_conv3d<2, 16><<<grid, 256, 0, s>>>(a);
   else if (cin == 16 && cout == 16) k_conv3d<16, 16><<<grid, 256, 0, s>>>(a);
   else if (cin == 16 && cout == 1) k_conv3d<16, 1><<<grid, 256, 0, s>>>(a);
-  else if (cin == 1 && cout == 1) k_conv3d<1, 1><<<grid, 256, 0, s>>>(a);
+  else if (cin == 1 && cout == 16) k_conv3d<1, 16><<<grid, 256, 0, s>>>(a);
 }
 
 // Weight gradient partial sums: for each workgroup (tile, batch item),
@@ -204,10 +204,9 @@ __global__ __launch_bounds__(256) void k_conv3d_wgrad(ConvWArgs a) {
 
 void launch_conv3d_wgrad(const ConvWArgs& a, int cin, int cout, int batch, hipStream_t s) {
   const dim3 grid(conv_wgrad_tiles(a.geom), batch);
-  if (cin == 1 && cout == 16) k_conv3d_wgrad<1, 16><<<grid, 256, 0, s>>>(a);
+  if (cin == 2 && cout == 16) k_conv3d_wgrad<2, 16><<<grid, 256, 0, s>>>(a);
   else if (cin == 16 && cout == 16) k_conv3d_wgrad<16, 16><<<grid, 256, 0, s>>>(a);
   else if (cin == 16 && cout == 1) k_conv3d_wgrad<16, 1><<<grid, 256, 0, s>>>(a);
-  else if (cin == 1 && cout == 1) k_conv3d_wgrad<1, 1><<<grid, 256, 0, s>>>(a);
 }
 
 // sum over nwg partial rows of length len: out[i] = sum_w part[w * len + i]
@@ -286,20 +285,25 @@ void launch_to_bf16(const float* p, uint16_t* pb, int n, hipStream_t s) {
 // Data movement of the learned correction
 // ---------------------------------------------------------------------------
 
-// vol[c][v] = (float)(x[c * n + v] * scl[c]),  scl[c] = 1 / sqrt(rr[c]) (0 if rr[c] <= 0)
-__global__ void k_cols_to_vol(const double* __restrict__ x, size_t n, const double* __restrict__ rr,
-                              float* __restrict__ vol) {
+// Two-channel input volumes of the network from FP64 columns:
+// vol[c][0][v] = r[c * n + v] * s_c,  vol[c][1][v] = u[c * n + v] * s_c,
+// s_c = 1 / sqrt(rr[c]) (0 if rr[c] <= 0; 1 when rr is null).
+__global__ void k_cols2_to_vol(const double* __restrict__ r, const double* __restrict__ u, size_t n,
+                               const double* __restrict__ rr, float* __restrict__ vol) {
   const int c = blockIdx.y;
   const double r2 = rr ? rr[c] : 1.0;
   const double sc = r2 > 0.0 ? 1.0 / sqrt(r2) : 0.0;
+  float* o = vol + (size_t)c * 2 * n;
   for (size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
-       v += (size_t)gridDim.x * blockDim.x)
-    vol[(size_t)c * n + v] = (float)(x[(size_t)c * n + v] * sc);
+       v += (size_t)gridDim.x * blockDim.x) {
+    o[v] = (float)(r[(size_t)c * n + v] * sc);
+    o[n + v] = (float)(u[(size_t)c * n + v] * sc);
+  }
 }
 
-void launch_cols_to_vol(const double* x, size_t n, const double* rr, float* vol, int ncols,
-                        hipStream_t s) {
-  if (ncols > 0) k_cols_to_vol<<<dim3(256, ncols), 256, 0, s>>>(x, n, rr, vol);
+void launch_cols2_to_vol(const double* r, const double* u, size_t n, const double* rr, float* vol,
+                         int ncols, hipStream_t s) {
+  if (ncols > 0) k_cols2_to_vol<<<dim3(256, ncols), 256, 0, s>>>(r, u, n, rr, vol);
 }
 
 // y[c * n + v] (=|+=) vol[c][v] * sqrt(rr[c]) (rr null: 1); active (if given) gates columns
@@ -322,92 +326,126 @@ void launch_vol_to_cols(const float* vol, size_t n, const double* rr, const uint
   if (ncols > 0) k_vol_to_cols<<<dim3(256, ncols), 256, 0, s>>>(vol, n, rr, active, y, accumulate);
 }
 
-// Crops: out[i][v] = src[col_i * n + node(origin_i + v)] * scale_i for crop voxels
-// inside the grid, else 0.  Crop volume dims (ct, cy, cx).
-__global__ void k_crop(const double* __restrict__ src, ConvGeom g, const CropSpec* __restrict__ cs,
-                       ConvGeom cg, float* __restrict__ out) {
-  const CropSpec c = cs[blockIdx.y];
-  const size_t cv = (size_t)cg.T * cg.MY * cg.MX;
-  const size_t n = (size_t)g.T * g.MY * g.MX;
-  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < cv;
-       e += (size_t)gridDim.x * blockDim.x) {
-    const int x = c.ox + (int)(e % cg.MX), y = c.oy + (int)((e / cg.MX) % cg.MY),
-              t = c.ot + (int)(e / ((size_t)cg.MX * cg.MY));
-    float v = 0.f;
-    if (t >= 0 && t < g.T && y >= 0 && y < g.MY && x >= 0 && x < g.MX)
-      v = (float)(src[(size_t)c.col * n + ((size_t)t * g.MY + y) * g.MX + x] * c.scale);
-    out[(size_t)c.slot * cv + e] = v;
+// Training pairs from PCG state: for each column c with slot[c] >= 0,
+//   R[slot] = r_c / |r_c|,  U[slot] = u_c / |r_c|,  E[slot] = (xs_c - x_c) / |r_c|
+// (|r_c|^2 = rr[c] > 0).  Grid (blocks, ncols).
+__global__ void k_pair_store(const double* __restrict__ r, const double* __restrict__ u,
+                             const double* __restrict__ xs, const double* __restrict__ x, size_t n,
+                             const double* __restrict__ rr, const int* __restrict__ slot,
+                             float* __restrict__ R, float* __restrict__ U, float* __restrict__ E) {
+  const int c = blockIdx.y;
+  const int sl = slot[c];
+  if (sl < 0 || !(rr[c] > 0.0)) return;
+  const double sc = 1.0 / sqrt(rr[c]);
+  const size_t o = (size_t)sl * n, ci = (size_t)c * n;
+  for (size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+       v += (size_t)gridDim.x * blockDim.x) {
+    R[o + v] = (float)(r[ci + v] * sc);
+    U[o + v] = (float)(u[ci + v] * sc);
+    E[o + v] = (float)((xs[ci + v] - x[ci + v]) * sc);
   }
 }
 
-void launch_crop(const double* src, ConvGeom g, const CropSpec* d_specs, int n_specs, ConvGeom cg,
-                 float* out, hipStream_t s) {
-  if (n_specs > 0) k_crop<<<dim3(64, n_specs), 256, 0, s>>>(src, g, d_specs, cg, out);
+void launch_pair_store(const double* r, const double* u, const double* xs, const double* x,
+                       size_t n, const double* rr, const int* slot, float* R, float* U, float* E,
+                       int ncols, hipStream_t s) {
+  if (ncols > 0) k_pair_store<<<dim3(256, ncols), 256, 0, s>>>(r, u, xs, x, n, rr, slot, R, U, E);
 }
 
-// Loss of one batch over the interior [h, dim - h) of each crop volume,
-// restricted to its valid box:  L = sum_b ||y_b - t_b||^2 / tn_b,
-// dy_b = 2 (y_b - t_b) / tn_b / B there, 0 elsewhere.  Per-workgroup partial
-// sums of the numerators go to part[(b * gridDim.x + blk) * 2 + {0: err, 1: ref}].
-__global__ void k_crop_loss(const float* __restrict__ y, const float* __restrict__ t,
-                            const ConvBox* __restrict__ boxes, const float* __restrict__ tn,
-                            ConvGeom cg, int h, int batch, float* __restrict__ dy,
-                            float* __restrict__ part) {
-  __shared__ float re[256], rt[256];
+// Network input of a training batch: vin[b][0] = R[sl_b], vin[b][1] = su * U[sl_b]
+__global__ void k_pack_train(const float* __restrict__ R, const float* __restrict__ U,
+                             const int* __restrict__ slots, size_t n, float su,
+                             float* __restrict__ vin) {
   const int b = blockIdx.y;
-  const ConvBox bx = boxes[b];
-  const size_t cv = (size_t)cg.T * cg.MY * cg.MX;
-  float se = 0.f, st = 0.f;
-  const float w = 2.f / (tn[b] * batch);
-  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < cv;
-       e += (size_t)gridDim.x * blockDim.x) {
-    const int x = (int)(e % cg.MX), yy = (int)((e / cg.MX) % cg.MY),
-              tt = (int)(e / ((size_t)cg.MX * cg.MY));
-    const bool in = tt >= h && tt < cg.T - h && yy >= h && yy < cg.MY - h && x >= h &&
-                    x < cg.MX - h && tt >= bx.t0 && tt < bx.t1 && yy >= bx.y0 && yy < bx.y1 &&
-                    x >= bx.x0 && x < bx.x1;
-    float g = 0.f;
-    if (in) {
-      const float d = y[(size_t)b * cv + e] - t[(size_t)b * cv + e];
-      se += d * d;
-      st += t[(size_t)b * cv + e] * t[(size_t)b * cv + e];
-      g = w * d;
-    }
-    if (dy) dy[(size_t)b * cv + e] = g;
+  const size_t o = (size_t)slots[b] * n;
+  float* d = vin + (size_t)b * 2 * n;
+  for (size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+       v += (size_t)gridDim.x * blockDim.x) {
+    d[v] = R[o + v];
+    d[n + v] = su * U[o + v];
   }
-  re[threadIdx.x] = se;
-  rt[threadIdx.x] = st;
+}
+
+void launch_pack_train(const float* R, const float* U, const int* slots, size_t n, float su,
+                       float* vin, int batch, hipStream_t s) {
+  if (batch > 0) k_pack_train<<<dim3(256, batch), 256, 0, s>>>(R, U, slots, n, su, vin);
+}
+
+// Energy residual of a batch (FP64 columns b * n): d_b = U[sl_b] + y_b / su - E[sl_b]
+// (y null: the network's output taken as zero, i.e. block Jacobi alone)
+__global__ void k_energy_d(const float* __restrict__ U, const float* __restrict__ E,
+                           const float* __restrict__ y, const int* __restrict__ slots, size_t n,
+                           float inv_su, double* __restrict__ d) {
+  const int b = blockIdx.y;
+  const size_t o = (size_t)slots[b] * n;
+  for (size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+       v += (size_t)gridDim.x * blockDim.x) {
+    double val = (double)U[o + v] - (double)E[o + v];
+    if (y) val += (double)y[(size_t)b * n + v] * (double)inv_su;
+    d[(size_t)b * n + v] = val;
+  }
+}
+
+void launch_energy_d(const float* U, const float* E, const float* y, const int* slots, size_t n,
+                     float inv_su, double* d, int batch, hipStream_t s) {
+  if (batch > 0) k_energy_d<<<dim3(256, batch), 256, 0, s>>>(U, E, y, slots, n, inv_su, d);
+}
+
+// Block partial sums of a_b . q_b (FP64; a either FP64 columns or, with af,
+// FP32 rows at slot sl_b) into part[b * gridDim.x + blk]; with gy, also the
+// output gradient gy_b = coef[b] * q_b (FP32).
+__global__ void k_energy_dot(const double* __restrict__ a, const float* __restrict__ af,
+                             const int* __restrict__ slots, const double* __restrict__ q,
+                             const float* __restrict__ qf, size_t n,
+                             const float* __restrict__ coef, float* __restrict__ gy,
+                             double* __restrict__ part) {
+  __shared__ double red[256];
+  const int b = blockIdx.y;
+  const size_t oa = af ? (size_t)slots[b] * n : (size_t)b * n;
+  const size_t oq = qf ? (size_t)slots[b] * n : (size_t)b * n;
+  double acc = 0.0;
+  for (size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+       v += (size_t)gridDim.x * blockDim.x) {
+    const double av = af ? (double)af[oa + v] : a[oa + v];
+    const double qv = qf ? (double)qf[oq + v] : q[oq + v];
+    acc += av * qv;
+    if (gy) gy[(size_t)b * n + v] = (float)(coef[b] * qv);
+  }
+  red[threadIdx.x] = acc;
   __syncthreads();
   for (int k = 128; k > 0; k >>= 1) {
-    if (threadIdx.x < k) {
-      re[threadIdx.x] += re[threadIdx.x + k];
-      rt[threadIdx.x] += rt[threadIdx.x + k];
-    }
+    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    part[((size_t)b * gridDim.x + blockIdx.x) * 2] = re[0];
-    part[((size_t)b * gridDim.x + blockIdx.x) * 2 + 1] = rt[0];
-  }
+  if (threadIdx.x == 0) part[(size_t)b * gridDim.x + blockIdx.x] = red[0];
 }
 
-void launch_crop_loss(const float* y, const float* t, const ConvBox* boxes, const float* tn,
-                      ConvGeom cg, int h, int batch, float* dy, float* part, int nblk,
-                      hipStream_t s) {
-  k_crop_loss<<<dim3(nblk, batch), 256, 0, s>>>(y, t, boxes, tn, cg, h, batch, dy, part);
+void launch_energy_dot(const double* a, const float* af, const int* slots, const double* q,
+                       const float* qf, size_t n, const float* coef, float* gy, double* part,
+                       int nblk, int batch, hipStream_t s) {
+  if (batch > 0)
+    k_energy_dot<<<dim3(nblk, batch), 256, 0, s>>>(a, af, slots, q, qf, n, coef, gy, part);
 }
 
-// d = a - b - c over n elements (target of the correction: x* - x_k - M^-1 r_k)
-__global__ void k_sub3(const double* __restrict__ a, const double* __restrict__ b,
-                       const double* __restrict__ c, double* __restrict__ d, size_t n) {
+// Safeguarded correction, per column c (columns of length n):
+//   g = (vr - vqu) / vqv if vqv > 0 (else 0);  z_c += g v_c
+// (only active columns).
+__global__ void k_gamma_axpy(const double* __restrict__ v, double* __restrict__ z, size_t n,
+                             const double* __restrict__ vr, const double* __restrict__ vqu,
+                             const double* __restrict__ vqv, const uint8_t* __restrict__ active) {
+  const int c = blockIdx.y;
+  if (active && !active[c]) return;
+  const double den = vqv[c];
+  if (!(den > 0.0)) return;
+  const double g = (vr[c] - vqu[c]) / den;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (size_t)gridDim.x * blockDim.x)
-    d[i] = a[i] - b[i] - c[i];
+    z[(size_t)c * n + i] += g * v[(size_t)c * n + i];
 }
 
-void launch_sub3(const double* a, const double* b, const double* c, double* d, size_t n,
-                 hipStream_t s) {
-  if (n > 0) k_sub3<<<2048, 256, 0, s>>>(a, b, c, d, n);
+void launch_gamma_axpy(const double* v, double* z, size_t n, const double* vr, const double* vqu,
+                       const double* vqv, const uint8_t* active, int ncols, hipStream_t s) {
+  if (ncols > 0) k_gamma_axpy<<<dim3(256, ncols), 256, 0, s>>>(v, z, n, vr, vqu, vqv, active);
 }
 
 }  // namespace rbmc

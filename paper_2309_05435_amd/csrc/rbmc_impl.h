@@ -319,21 +319,24 @@ void launch_conv_wflip(const uint16_t* w, int cin, int cout, uint16_t* wt, hipSt
 void launch_adam(float* p, const float* g, float* m, float* v, uint16_t* pb, int n, float lr,
                  float b1, float b2, float eps, int step, hipStream_t s);
 void launch_to_bf16(const float* p, uint16_t* pb, int n, hipStream_t s);
-// columns (c * n, FP64) <-> volumes (FP32), normalized by sqrt(rr[c])
-void launch_cols_to_vol(const double* x, size_t n, const double* rr, float* vol, int ncols,
-                        hipStream_t s);
+// two-channel network input (r, u) / sqrt(rr[c]) from FP64 columns; output back
+void launch_cols2_to_vol(const double* r, const double* u, size_t n, const double* rr, float* vol,
+                         int ncols, hipStream_t s);
 void launch_vol_to_cols(const float* vol, size_t n, const double* rr, const uint8_t* active,
                         double* y, int ncols, int accumulate, hipStream_t s);
-struct CropSpec {  // crop of column `col` with its voxel (0,0,0) at grid (ot, oy, ox)
-  int col, slot, ot, oy, ox;
-  double scale;
-};
-void launch_crop(const double* src, ConvGeom g, const CropSpec* d_specs, int n_specs, ConvGeom cg,
-                 float* out, hipStream_t s);
-void launch_crop_loss(const float* y, const float* t, const ConvBox* boxes, const float* tn,
-                      ConvGeom cg, int h, int batch, float* dy, float* part, int nblk,
-                      hipStream_t s);
-void launch_sub3(const double* a, const double* b, const double* c, double* d, size_t n,
-                 hipStream_t s);
+// training pairs, batches and the energy loss
+void launch_pair_store(const double* r, const double* u, const double* xs, const double* x,
+                       size_t n, const double* rr, const int* slot, float* R, float* U, float* E,
+                       int ncols, hipStream_t s);
+void launch_pack_train(const float* R, const float* U, const int* slots, size_t n, float su,
+                       float* vin, int batch, hipStream_t s);
+void launch_energy_d(const float* U, const float* E, const float* y, const int* slots, size_t n,
+                     float inv_su, double* d, int batch, hipStream_t s);
+void launch_energy_dot(const double* a, const float* af, const int* slots, const double* q,
+                       const float* qf, size_t n, const float* coef, float* gy, double* part,
+                       int nblk, int batch, hipStream_t s);
+// safeguarded correction z_c += g_c v_c, g_c = (vr - vqu) / vqv
+void launch_gamma_axpy(const double* v, double* z, size_t n, const double* vr, const double* vqu,
+                       const double* vqv, const uint8_t* active, int ncols, hipStream_t s);
 
 }  // namespace rbmc

@@ -1,8 +1,9 @@
 """The learned correction of the block-Jacobi preconditioner (opts.precond =
 RBMC_PC_BJ_LEARNED): its convolutions against a plain NumPy implementation of
 the same network (BF16-rounded weights, FP64 arithmetic), its training on
-pairs from the sampler, and flexible PCG with it converging to the same
-samples as the exact solve."""
+pairs from the sampler (the held-out energy error must drop below block
+Jacobi's), and flexible PCG with the safeguarded correction converging to the
+same samples as the exact solve - also with arbitrary weights."""
 import numpy as np
 import pytest
 
@@ -48,8 +49,8 @@ def conv3d_ref(x, w):
     return out
 
 
-def net_ref(r, wvec, T, Y, X):
-    h = r.reshape(1, T, Y, X)
+def net_ref(r, u, wvec, T, Y, X):
+    h = np.stack([r.reshape(T, Y, X), u.reshape(T, Y, X)])
     off = 0
     for l, (ci, co) in enumerate(B.PC_LAYERS):
         w = bf16(wvec[off:off + ci * co * 27]).reshape(co, ci, 27)
@@ -66,18 +67,37 @@ def test_learned_network_matches_numpy():
     w = np.concatenate([rng.standard_normal(ci * co * 27) * np.sqrt(2.0 / (ci * 27))
                         for ci, co in B.PC_LAYERS]).astype(np.float32)
     B.rbmc_precond_set_weights(gm.m, w)
-    w2, usable, err = B.rbmc_precond_get_weights(gm.m)
-    assert np.array_equal(w2, w) and usable
+    w2 = B.rbmc_precond_get_weights(gm.m)
+    info = B.rbmc_precond_info(gm.m)
+    assert np.array_equal(w2, w) and info.ready and info.usable and info.val_ratio == -1.0
     r = rng.standard_normal((3, gm.n))
+    u = rng.standard_normal((3, gm.n)) * 0.5
     rd = torch.from_numpy(r).cuda()
+    ud = torch.from_numpy(u).cuda()
     y = torch.empty_like(rd)
-    B.rbmc_precond_apply(gm.m, rd, y, 3)
+    B.rbmc_precond_apply(gm.m, rd, ud, y, 3)
     y = y.cpu().numpy()
     for k in range(3):
-        ref = net_ref(r[k], w, wl.T, wl.m, wl.m)
+        ref = net_ref(r[k], u[k], w, wl.T, wl.m, wl.m)
         # FP32 activations, 27..432-term FP32 sums: ~1e-6 relative to the magnitude
         np.testing.assert_allclose(y[k], ref, rtol=0, atol=2e-5 * np.abs(ref).max())
     gm.close()
+
+
+def exact_vs_pcg(gm, M, seed, tag):
+    """PCG samples (plain and learned) against the oracle's exact samples."""
+    z = normals((6, M.n + M.n_obs), seed)
+    x_ref = M.sample(z)
+    x = torch.empty((6, gm.n), dtype=torch.float64, device="cuda")
+    its = {}
+    for pc in (B.RBMC_PC_BJ, B.RBMC_PC_BJ_LEARNED):
+        st, rep = B.rbmc_sample(gm.m, B.make_opts(6, 5000, 1e-12, precond=pc),
+                                torch.from_numpy(z).cuda(), x)
+        err = np.linalg.norm(x.cpu().numpy() - x_ref, axis=1) / np.linalg.norm(x_ref, axis=1)
+        say(f"learned ({tag}): precond {pc}: iterations {rep.pcg_it_max}, max err {err.max():.2e}")
+        assert st == B.RBMC_OK and err.max() < 1e-8
+        its[pc] = rep.pcg_it_max
+    return its
 
 
 def test_train_and_flexible_pcg():
@@ -85,21 +105,52 @@ def test_train_and_flexible_pcg():
     say("learned: training")
     gm = B.Model(wl, pc=None)   # block-Jacobi over the 8 cores
     M = O.OracleModel.from_workload(wl)
-    zt = torch.from_numpy(normals((4, gm.n + gm.n_obs), 61)).cuda()
+    zt = torch.from_numpy(normals((8, gm.n + gm.n_obs), 61)).cuda()
     st, loss, rep = B.rbmc_precond_train(gm.m, B.make_opts(4, 5000, 1e-10),
-                                         B.make_train_opts(n_pairs=200, epochs=4, batch=8,
-                                                           lr=2e-3, seed=5, crop_t=4,
-                                                           crop_xy=12), zt, 4)
-    say(f"learned: epoch losses {np.round(loss[:-1], 4)} held-out rel err {loss[-1]:.3f}")
-    assert all(np.isfinite(loss))
+                                         B.make_train_opts(n_pairs=400, epochs=12, batch=8,
+                                                           lr=2e-3, seed=5), zt, 8)
+    say(f"learned: epoch energy ratios {np.round(loss[:-1], 4)} held-out {loss[-1]:.3f}")
+    assert st == B.RBMC_OK and all(np.isfinite(loss))
     assert loss[-2] < loss[0]   # the training loss decreases
-    # flexible PCG with the correction reaches the exact samples
-    z = normals((6, M.n + M.n_obs), 62)
-    x_ref = M.sample(z)
-    x = torch.empty((6, gm.n), dtype=torch.float64, device="cuda")
+    info = B.rbmc_precond_info(gm.m)
+    say(f"learned: trial iterations block Jacobi {info.trial_it_bj} ({info.trial_s_bj:.3f} s), "
+        f"learned {info.trial_it_learned} ({info.trial_s_learned:.3f} s), usable {info.usable}")
+    # one preconditioning step with the correction leaves less energy error
+    # than block Jacobi alone on held-out pairs
+    assert info.val_ratio == pytest.approx(loss[-1], rel=1e-6) and info.val_ratio < 0.95
+    # the acceptance trial ran, and the correction is used only if it won it
+    assert info.trial_it_bj > 0 and info.trial_it_learned > 0
+    assert bool(info.usable) == (info.trial_it_learned < info.trial_it_bj
+                                 and info.trial_s_learned < info.trial_s_bj)
+    exact_vs_pcg(gm, M, 62, "trained")
+    # on fresh right-hand sides at the trial's tolerance the accepted
+    # correction generalizes (15% slack); a rejected one is plain block Jacobi
+    z = torch.from_numpy(normals((8, gm.n + gm.n_obs), 64)).cuda()
+    x = torch.empty((8, gm.n), dtype=torch.float64, device="cuda")
+    its = {}
     for pc in (B.RBMC_PC_BJ, B.RBMC_PC_BJ_LEARNED):
-        st, rep = B.rbmc_sample(gm.m, B.make_opts(6, 5000, 1e-12, precond=pc), torch.from_numpy(z).cuda(), x)
-        err = np.linalg.norm(x.cpu().numpy() - x_ref, axis=1) / np.linalg.norm(x_ref, axis=1)
-        say(f"learned: precond {pc}: iterations {rep.pcg_it_max}, max err {err.max():.2e}")
-        assert st == B.RBMC_OK and err.max() < 1e-8
+        st, rep = B.rbmc_sample(gm.m, B.make_opts(8, 5000, 1e-10, precond=pc), z, x)
+        assert st == B.RBMC_OK
+        its[pc] = rep.pcg_it_max
+    say(f"learned: fresh right-hand sides at 1e-10: iterations {its}")
+    if info.usable:
+        assert its[B.RBMC_PC_BJ_LEARNED] <= 1.15 * its[B.RBMC_PC_BJ]
+    else:
+        assert its[B.RBMC_PC_BJ_LEARNED] == its[B.RBMC_PC_BJ]
+    gm.close()
+
+
+def test_safeguard_with_arbitrary_weights():
+    """Untrained, large random weights: the per-column energy-optimal step keeps
+    every preconditioning step no worse than block Jacobi, so flexible PCG
+    still reaches the exact samples."""
+    wl = wl_of(20, 6, 2, 1, 1, seed=13)
+    say("learned: arbitrary weights")
+    gm = B.Model(wl, pc=None)
+    M = O.OracleModel.from_workload(wl)
+    rng = np.random.default_rng(8)
+    w = np.concatenate([rng.standard_normal(ci * co * 27) * np.sqrt(2.0 / (ci * 27)) * 10.0
+                        for ci, co in B.PC_LAYERS]).astype(np.float32)
+    B.rbmc_precond_set_weights(gm.m, w)
+    exact_vs_pcg(gm, M, 63, "arbitrary")
     gm.close()
