@@ -16,6 +16,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -97,8 +98,11 @@ def write_traffic(paths, workload: str, copy_bytes: int, commands):
     s_write = copy_bytes / (copy_kib(w_copy) * 1024)
     written = []
     for fam, kern in KERNEL_OF.items():
-        fk = [k for k in f_main if ("rbmc::" + kern + "(") in k or k.startswith(kern + "(")]
-        wk = [k for k in w_main if ("rbmc::" + kern + "(") in k or k.startswith(kern + "(")]
+        # the stencil family times Q p with the fused dot: k_space_time_op<0, true>
+        tail = r"<0, true>\(" if kern == "k_space_time_op" else r"[<(]"
+        pat = re.compile(r"(^|[\s:])" + re.escape(kern) + tail)
+        fk = [k for k in f_main if pat.search(k)]
+        wk = [k for k in w_main if pat.search(k)]
         if not fk or not wk:
             continue
         fv = [v for k in fk for v in f_main[k]]

@@ -476,7 +476,7 @@ struct StencilList {
   int max_sparse_np = 0;  // largest block with sparse terms (0: none)
   void add(StencilTask t, int np, int nb) {
     t.tile_start = tiles;
-    tiles += (np / 64) * ((t.ncols + 63) / 64);
+    tiles += rstencil_tiles(np, t.ncols);
     bytes += 16.0 * nb * (double)t.ncols;
     if (t.gamma != 0.0 || t.dv != nullptr || t.pad_identity)
       max_sparse_np = std::max(max_sparse_np, np);
@@ -730,6 +730,8 @@ StencilTask stask(const ChainSet& cs, size_t c) {
 
 // Factorization program: S_t^-1 of every chain of the set.
 //   S_0 = B_0,  S_t = B_t - q_o^2 Q_R S_{t-1}^-1 Q_R,  B_t = q_d(t) Q_R + D_t
+// The product is two stencil passes over columns: tmp = (Q_R S^-1)^T, stored
+// transposed, equals S^-1 Q_R (S^-1 is exactly symmetric), then Q_R tmp.
 void build_factor(ChainSet& cs, Program& pg, Arena& a) {
   for (int t = 0; t < cs.maxT; ++t) {
     StencilList v1, v2;
@@ -750,12 +752,12 @@ void build_factor(ChainSet& cs, Program& pg, Arena& a) {
         s1.ldout = np;
         s1.ncols = np;
         s1.alpha = 1.0;
+        s1.tstore = 1;
         v1.add(s1, np, nb);
       }
       StencilTask s2 = stask(cs, c);
       s2.M = (t > 0) ? cs.tmp[c] : nullptr;
       s2.ldm = np;
-      s2.trans = 1;
       s2.alpha = (t > 0) ? -m->co.qo * m->co.qo : 0.0;
       s2.gamma = m->co.qd[tg];
       s2.dv = m->d_dvec + (size_t)tg * m->plan.ns;

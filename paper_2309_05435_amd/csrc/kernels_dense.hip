@@ -6,6 +6,8 @@
 //   - products of the restricted 13-point stencil Q_R with dense blocks.
 // Dense blocks are column-major, padded to multiples of 64 with identity on
 // the padded diagonal.
+#include <climits>
+
 #include "rbmc_impl.h"
 
 namespace rbmc {
@@ -811,89 +813,145 @@ void launch_gj2_fix(const Gj2Task* d_tasks, int n_tasks, int total_tiles, hipStr
 }
 
 // ---------------------------------------------------------------------------
-// Restricted-stencil products: out = alpha Q_R op(M) + gamma Q_R + diag(dv)
-//                                    (+ I on the padded diagonal) + beta In
-// on 64 x 64 output tiles; rows are region nodes (padded to np).
+// Restricted-stencil products: out = alpha Q_R M + beta In (+ the sparse terms
+// gamma Q_R + diag(dv) + I on the padded diagonal, added by k_sparse_add);
+// rows are region nodes (padded to np).  Column c of the result is the
+// 13-point stencil applied to column c of M, a field over the region.
+//
+// Workgroup = 256 output rows (one per thread) x up to 4 groups of 16
+// columns.  The rows of M those outputs reach form one contiguous span
+// [lo, hi] of region indices (the region is ordered by grid rows; a stencil
+// reaches two grid rows up and down).  Per group, the span of its 16 columns
+// is staged in LDS and the 13 taps are read from there; the loads of the next
+// group are in flight (in registers) while the current one is computed.  The
+// stencil rows (neighbours, coefficients) are loaded once per workgroup.  A
+// tile whose span exceeds kRsSpan (a region more than 68 nodes wide) reads its
+// taps from global memory.  tstore: write the result transposed
+// (out[a * ldout + c], 16-byte stores; requires beta = 0).
 // ---------------------------------------------------------------------------
+namespace {
+constexpr int kRsRows = 256, kRsCols = 16, kRsGroups = 4, kRsSpan = 528;
+}
+
 __global__ __launch_bounds__(256) void k_rstencil(const StencilTask* __restrict__ tasks,
                                                   int n_tasks) {
-  __shared__ double tileT[64 * 65];
-  int lo = 0, hi = n_tasks - 1;
+  __shared__ double src[kRsCols * kRsSpan];
+  __shared__ int span_lo, span_hi;
+  int lo_t = 0, hi_t = n_tasks - 1;
   const int b = blockIdx.x;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) / 2;
-    if (tasks[mid].tile_start <= b) lo = mid; else hi = mid - 1;
+  while (lo_t < hi_t) {
+    int mid = (lo_t + hi_t + 1) / 2;
+    if (tasks[mid].tile_start <= b) lo_t = mid; else hi_t = mid - 1;
   }
-  const StencilTask tk = tasks[lo];
+  const StencilTask tk = tasks[lo_t];
   const RegionDev rg = *tk.rg;
-  const double* __restrict__ qs = tk.qs;
-  const int ns = tk.ns;
   const int tile = b - tk.tile_start;
-  const int tiles_c = (tk.ncols + 63) / 64;
-  const int a0 = (tile / tiles_c) * 64, c0 = (tile % tiles_c) * 64;
+  constexpr int kWide = kRsCols * kRsGroups;
+  const int tiles_c = (tk.ncols + kWide - 1) / kWide;
+  const int a0 = (tile / tiles_c) * kRsRows, cw = (tile % tiles_c) * kWide;
+  const int ngrp = min(kRsGroups, (tk.ncols - cw + kRsCols - 1) / kRsCols);
   const int tid = threadIdx.x;
-  const bool square = (tk.dv != nullptr) || tk.pad_identity || tk.gamma != 0.0;
-
-  // the sparse terms (gamma Q_R, diag(dv), padded identity) are added by
-  // k_sparse_add after this pass
-  auto extra = [&](int a, int c, double v) {
-    if (tk.beta != 0.0) v += tk.beta * tk.In[(size_t)c * tk.ldin + a];
-    return v;
-  };
-  (void)square;
-
-  if (!tk.trans) {
-    // thread -> row a (fast), 16 columns
-    const int a = a0 + (tid & 63);
-    int nbr[kNS];
-    double cf[kNS];
-    const bool real = a < rg.nb;
-    if (real) {
-      const int node = rg.nodes[a];
+  const int a = a0 + tid;
+  const bool use = tk.alpha != 0.0;
+  const bool real = use && a < rg.nb;
+  int nbr[kNS];
+  double cf[kNS];
+  int lo = INT_MAX, hi = -1;
+  if (real) {
+    const int node = rg.nodes[a];
 #pragma unroll
-      for (int q = 0; q < kNS; ++q) {
-        nbr[q] = rg.nbr[a * kNS + q];
-        cf[q] = qs[(size_t)q * ns + node];
+    for (int q = 0; q < kNS; ++q) {
+      nbr[q] = rg.nbr[a * kNS + q];
+      cf[q] = tk.qs[(size_t)q * tk.ns + node];
+      if (nbr[q] >= 0) {
+        lo = min(lo, nbr[q]);
+        hi = max(hi, nbr[q]);
       }
-    }
-    for (int cc = (tid >> 6); cc < 64; cc += 4) {
-      const int c = c0 + cc;
-      if (c >= tk.ncols) break;
-      double v = 0.0;
-      if (real && tk.alpha != 0.0) {
-        const double* mc = tk.M + (size_t)c * tk.ldm;
-#pragma unroll
-        for (int q = 0; q < kNS; ++q)
-          if (nbr[q] >= 0) v += cf[q] * mc[nbr[q]];
-        v *= tk.alpha;
-      }
-      tk.out[(size_t)c * tk.ldout + a] = extra(a, c, v);
-    }
-  } else {
-    // thread -> column c (fast), 16 rows; transpose through LDS for the store
-    const int cl = tid & 63, c = c0 + cl;
-    for (int ar = (tid >> 6); ar < 64; ar += 4) {
-      const int a = a0 + ar;
-      double v = 0.0;
-      if (a < rg.nb && c < tk.ncols && tk.alpha != 0.0) {
-        const int node = rg.nodes[a];
-#pragma unroll
-        for (int q = 0; q < kNS; ++q) {
-          const int nb = rg.nbr[a * kNS + q];
-          if (nb >= 0) v += qs[(size_t)q * ns + node] * tk.M[(size_t)nb * tk.ldm + c];
-        }
-        v *= tk.alpha;
-      }
-      tileT[ar * 65 + cl] = v;
-    }
-    __syncthreads();
-    const int al = tid & 63, a = a0 + al;
-    for (int cc = (tid >> 6); cc < 64; cc += 4) {
-      const int c2 = c0 + cc;
-      if (c2 >= tk.ncols) break;
-      tk.out[(size_t)c2 * tk.ldout + a] = extra(a, c2, tileT[al * 65 + cc]);
     }
   }
+  if (tid == 0) {
+    span_lo = INT_MAX;
+    span_hi = -1;
+  }
+  __syncthreads();
+  if (real) {
+    atomicMin(&span_lo, lo);
+    atomicMax(&span_hi, hi);
+  }
+  __syncthreads();
+  const int slo = span_lo, span = span_hi - span_lo + 1;  // span <= 0: no taps
+  const bool staged = span > 0 && span <= kRsSpan;
+  const bool row_ok = a < rg.np;
+  double ld[2 * kRsCols];
+  // loads of group g: rows tid and tid + 256 of the span, 16 columns
+  auto issue = [&](int g) {
+    const int c0 = cw + g * kRsCols, ncc = min(kRsCols, tk.ncols - c0);
+#pragma unroll
+    for (int cc = 0; cc < kRsCols; ++cc) {
+      const double* mc = tk.M + (size_t)(c0 + cc) * tk.ldm + slo;
+      ld[2 * cc] = (cc < ncc && tid < span) ? mc[tid] : 0.0;
+      ld[2 * cc + 1] = (cc < ncc && tid + 256 < span) ? mc[tid + 256] : 0.0;
+    }
+  };
+  if (staged) issue(0);
+  for (int g = 0; g < ngrp; ++g) {
+    const int c0 = cw + g * kRsCols, ncc = min(kRsCols, tk.ncols - c0);
+    if (staged) {
+      __syncthreads();  // the previous group is no longer read from src
+#pragma unroll
+      for (int cc = 0; cc < kRsCols; ++cc) {
+        src[cc * kRsSpan + tid] = ld[2 * cc];
+        src[cc * kRsSpan + tid + 256] = ld[2 * cc + 1];
+      }
+      for (int e = tid; e < ncc * (span - 512); e += 256) {  // rows 512.. of a long span
+        const int w = span - 512, cc = e / w, r = 512 + (e - cc * w);
+        src[cc * kRsSpan + r] = tk.M[(size_t)(c0 + cc) * tk.ldm + slo + r];
+      }
+      __syncthreads();
+      if (g + 1 < ngrp) issue(g + 1);
+    }
+    double v[kRsCols];
+#pragma unroll
+    for (int cc = 0; cc < kRsCols; ++cc) {
+      double acc = 0.0;
+      if (real && cc < ncc) {
+        if (staged) {
+#pragma unroll
+          for (int q = 0; q < kNS; ++q)
+            if (nbr[q] >= 0) acc += cf[q] * src[cc * kRsSpan + nbr[q] - slo];
+        } else {
+          const double* mc = tk.M + (size_t)(c0 + cc) * tk.ldm;
+#pragma unroll
+          for (int q = 0; q < kNS; ++q)
+            if (nbr[q] >= 0) acc += cf[q] * mc[nbr[q]];
+        }
+        acc *= tk.alpha;
+      }
+      v[cc] = acc;
+    }
+    if (!row_ok) continue;
+    if (!tk.tstore) {
+#pragma unroll
+      for (int cc = 0; cc < kRsCols; ++cc) {
+        if (cc >= ncc) break;
+        double r = v[cc];
+        if (tk.beta != 0.0) r += tk.beta * tk.In[(size_t)(c0 + cc) * tk.ldin + a];
+        tk.out[(size_t)(c0 + cc) * tk.ldout + a] = r;
+      }
+    } else if (ncc == kRsCols) {  // 16 contiguous doubles of row a (c0, ldout even)
+      double2* o = reinterpret_cast<double2*>(tk.out + (size_t)a * tk.ldout + c0);
+#pragma unroll
+      for (int k = 0; k < kRsCols / 2; ++k) o[k] = make_double2(v[2 * k], v[2 * k + 1]);
+    } else {
+#pragma unroll
+      for (int cc = 0; cc < kRsCols; ++cc)
+        if (cc < ncc) tk.out[(size_t)a * tk.ldout + c0 + cc] = v[cc];
+    }
+  }
+}
+
+int rstencil_tiles(int np, int ncols) {
+  return ((np + kRsRows - 1) / kRsRows) * ((ncols + kRsCols * kRsGroups - 1) / (kRsCols * kRsGroups));
 }
 
 // out += gamma Q_R + diag(dv) + I on the padded diagonal: one thread per row,

@@ -202,12 +202,12 @@ int gj2_tiles(int np, int w);
 // restricted-stencil products on dense column-major matrices (rows = region nodes):
 //   out = alpha * Q_R * op(M) + gamma * Q_R + diag(dv) (+ I on pad) + beta * In
 struct StencilTask {
-  const double* M;     // np x ncols (op N) or ncols x np (op T); may be null (alpha = 0)
+  const double* M;     // np x ncols, column-major (ldm); may be null (alpha = 0)
   const double* In;    // optional (beta)
   double* out;
   int ldm, ldin, ldout;
   int ncols;           // number of columns of the result (np for square, n_k for panels)
-  int trans;           // op(M) = M^T
+  int tstore;          // store the result transposed: out[a * ldout + c] (beta = 0)
   double alpha, beta, gamma;
   const double* dv;    // optional diagonal (indexed by spatial node), square only
   int pad_identity;    // add 1 on padded diagonal (square only)
@@ -216,6 +216,8 @@ struct StencilTask {
   int ns;
   int tile_start;
 };
+// output tiles of one task (np rows x ncols)
+int rstencil_tiles(int np, int ncols);
 // max_np > 0: also add the sparse terms (gamma Q_R, diag(dv), pad identity)
 void launch_rstencil(const StencilTask* d_tasks, int n_tasks, int total_tiles, int max_np,
                      hipStream_t s);
