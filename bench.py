@@ -31,7 +31,7 @@ PEAK_FP32_TFLOPS = 157.3   # MI355X dense FP32 matrix
 # the HIP kernel behind each instrumented family
 KERNEL_OF = {"gemm": "k_gemm_f64", "gemm_small": "k_gemm_f64s", "gemm_mixed": "k_gemm_mx",
              "inv_small": "k_inv128", "spmm": "k_space_time_op", "rstencil": "k_rstencil",
-             "panels": "k_panels", "spd_inverse": "gauss_jordan"}
+             "panels": "k_panels", "spd_inverse": "gauss_jordan", "offdiag": "k_offdiag"}
 
 
 def kernel_sources_hash() -> str:
@@ -313,14 +313,26 @@ def main():
         r["avg_launch_ms"] = s["total_ms"] * per_launch
         return r
 
-    # dominant single kernel by device time (the inversion family is a
-    # composite of several kernels and its products are counted under gemm);
-    # times on the two streams overlap, so a kernel's time includes waiting
-    # for compute units held by the other stream
+    # dominant single kernel: the largest speed-of-light time per step
+    # (algorithmic flops / peak, or bytes / HBM peak).  Event times do not rank
+    # kernels here: three streams overlap, and a kernel's event time includes
+    # waiting for compute units held by the other streams (the 128-order
+    # register inversion takes 70 us alone, 4-5 times that in the overlapped
+    # step).  The inversion family is a composite of several kernels whose
+    # products are counted under the GEMM families.
+    def ideal_ms(fam):
+        s = stats[fam]
+        if fam in ("gemm", "gemm_small", "gemm_mixed", "inv_small"):
+            peak = PEAK_FP32_TFLOPS if fam == "gemm_mixed" else PEAK_FP64_TFLOPS
+            return s["alg_flops"] / (peak * 1e12) * 1e3
+        return s["alg_bytes"] / (PEAK_HBM_GBS * 1e9) * 1e3
+
     singles = [k for k in stats if k != "spd_inverse" and stats[k]["launches"] > 0]
-    dom = max(singles, key=lambda k: stats[k]["total_ms"])
+    dom = max(singles, key=ideal_ms)
     roof = roofline(dom)
-    others = {KERNEL_OF[k]: roofline(k) for k in singles if k != dom}
+    roof["ideal_ms_per_step"] = ideal_ms(dom) / max(args.steps, 1)
+    others = {KERNEL_OF[k]: dict(roofline(k), ideal_ms_per_step=ideal_ms(k) / max(args.steps, 1))
+              for k in singles if k != dom}
 
     last = reps[-1]
     out = {

@@ -294,7 +294,10 @@ rbmc_status rbmc_plan_query(const rbmc_model_desc* desc, const rbmc_decomp_desc*
  *   RBMC_KF_GEMM_SMALL   FP64 matrix-core products with 64 x 64 tiles (short
  *                        K or few tiles); flops as RBMC_KF_GEMM;
  *   RBMC_KF_INV_SMALL    register-resident inversions of blocks of order
- *                        w <= 128 (one workgroup each); flops = sum w^3.
+ *                        w <= 128 (one workgroup each); flops = sum w^3;
+ *   RBMC_KF_OFFDIAG      off-diagonal time-block entries on the stencil
+ *                        pattern of the core rows (13 dot products per row);
+ *                        bytes = 16 n_b^2 per block pair (each read once).
  * rbmc_ctx_profile(ctx, 1) clears and enables, (ctx, 0) disables;
  * rbmc_ctx_profile_read synchronizes the stream and sums the records. */
 enum {
@@ -306,7 +309,8 @@ enum {
   RBMC_KF_GEMM_MIXED = 5,
   RBMC_KF_GEMM_SMALL = 6,
   RBMC_KF_INV_SMALL = 7,
-  RBMC_KF_COUNT = 8
+  RBMC_KF_OFFDIAG = 8,
+  RBMC_KF_COUNT = 9
 };
 typedef struct {
   int64_t launches;

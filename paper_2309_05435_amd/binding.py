@@ -31,9 +31,10 @@ RBMC_PC_NWEIGHTS = 15120
 # (cin, cout) of the learned correction's four convolutions, in weight order
 PC_LAYERS = [(2, 16), (16, 16), (16, 16), (16, 1)]
 (RBMC_KF_GEMM, RBMC_KF_SPD_INVERSE, RBMC_KF_SPMM, RBMC_KF_RSTENCIL, RBMC_KF_PANELS,
- RBMC_KF_GEMM_MIXED, RBMC_KF_GEMM_SMALL, RBMC_KF_INV_SMALL, RBMC_KF_COUNT) = range(9)
+ RBMC_KF_GEMM_MIXED, RBMC_KF_GEMM_SMALL, RBMC_KF_INV_SMALL, RBMC_KF_OFFDIAG,
+ RBMC_KF_COUNT) = range(10)
 KF_NAMES = ["gemm", "spd_inverse", "spmm", "rstencil", "panels", "gemm_mixed", "gemm_small",
-            "inv_small"]
+            "inv_small", "offdiag"]
 
 
 class rbmc_kernel_stats(C.Structure):

@@ -205,9 +205,15 @@ struct ChainSet {
   std::vector<int> np, nb;
   std::vector<const RegionDev*> rg;  // device pointers
   std::vector<int*> info;            // device flag per chain
-  std::vector<double*> S;            // T x np^2, S_t^-1 after factorization
+  // block-Jacobi chains: S holds S_t^-1 for all T steps.  Subdomains: S holds
+  // the forward inverses F_t = (S^f_t)^-1 for t < the last core step, G the
+  // backward inverses G_t = (S^b_t)^-1 for t > the first core step (block
+  // t - first core - 1), sig Sigma_tt of the first core step, sig2 that of the
+  // core step in hand.
+  std::vector<double*> S;
+  std::vector<double*> G;
   std::vector<double*> tmp;          // np^2
-  std::vector<double*> sig, xb;      // np^2 (Takahashi Sigma and X), subdomains only
+  std::vector<double*> sig, sig2;    // np^2, subdomains only
   std::vector<double*> gjU, gjB;     // np x 256 Gauss-Jordan panels
   std::vector<double*> gjP;          // 256 x 256 pivot block
   std::vector<double*> gjU2, gjB2;   // 256 x 128 panels of the pivot block's sweep
@@ -225,8 +231,9 @@ struct ChainSet {
     cat(info, o.info);
     cat(S, o.S);
     cat(tmp, o.tmp);
+    cat(G, o.G);
     cat(sig, o.sig);
-    cat(xb, o.xb);
+    cat(sig2, o.sig2);
     cat(gjU, o.gjU);
     cat(gjB, o.gjB);
     cat(gjP, o.gjP);
@@ -326,18 +333,24 @@ rbmc_status alloc_chainset(rbmc_model* m, ChainSet& cs, const std::vector<Chain>
     cs.info.push_back(m->d_info + info_base + (int)i);
     const size_t blk = (size_t)np * np;
     double* p = nullptr;
-    HIPCHK(m->pool.alloc((void**)&p, blk * c.T * 8));
+    const int lc0 = c.ct0 - c.t0, lc1 = lc0 + c.cT - 1;
+    const int nF = subdomains ? lc1 : c.T, nG = subdomains ? c.T - 1 - lc0 : 0;
+    p = nullptr;
+    if (nF > 0) HIPCHK(m->pool.alloc((void**)&p, blk * nF * 8));
     cs.S.push_back(p);
+    p = nullptr;
+    if (nG > 0) HIPCHK(m->pool.alloc((void**)&p, blk * nG * 8));
+    cs.G.push_back(p);
     HIPCHK(m->pool.alloc((void**)&p, blk * 8));
     cs.tmp.push_back(p);
     if (subdomains) {
       HIPCHK(m->pool.alloc((void**)&p, blk * 8));
       cs.sig.push_back(p);
       HIPCHK(m->pool.alloc((void**)&p, blk * 8));
-      cs.xb.push_back(p);
+      cs.sig2.push_back(p);
     } else {
       cs.sig.push_back(nullptr);
-      cs.xb.push_back(nullptr);
+      cs.sig2.push_back(nullptr);
     }
     HIPCHK(m->pool.alloc((void**)&p, (size_t)np * 256 * 8));
     cs.gjU.push_back(p);
@@ -508,7 +521,8 @@ struct InvJob {  // one SPD block to invert in place, with its workspace
 
 struct Op {
   // 0 gemm, 1 stencil, 2 register inversion, 3 panels, 4 extract, 5 mc, 6 copy,
-  // 7 outer gather, 8 outer fix, 9 sweep finish, 10 profile begin, 11 profile end, 12 mirror
+  // 7 outer gather, 8 outer fix, 9 sweep finish, 10 profile begin, 11 profile end, 12 mirror,
+  // 13 off-diagonal pattern entries
   int kind;
   size_t off = 0;
   int n = 0, tiles = 0;
@@ -680,6 +694,17 @@ struct Program {
     o.tiles = e.tiles;
     ops.push_back(o);
   }
+  void offdiag(Arena& a, TileList<OffdiagTask>& t) {
+    if (t.v.empty()) return;
+    Op o;
+    o.kind = 13;
+    o.off = a.push(t.v);
+    o.n = (int)t.v.size();
+    o.tiles = t.tiles;
+    o.family = RBMC_KF_OFFDIAG;
+    o.alg_bytes = t.bytes;
+    ops.push_back(o);
+  }
   void copy(void* dst, const void* src, size_t bytes) {
     Op o;
     o.kind = 6;
@@ -713,6 +738,7 @@ rbmc_status run(rbmc_ctx* cx, const Program& pg, hipStream_t s, Arena& a) {
         }
         break;
       case 12: launch_mirror(a.at<InvTask>(o.off), o.n, o.max_np, s); break;
+      case 13: launch_offdiag(a.at<OffdiagTask>(o.off), o.n, o.tiles, s); break;
     }
     if (o.kind != 10) cx->end(pid, s);
   }
@@ -783,6 +809,221 @@ void build_factor(ChainSet& cs, Program& pg, Arena& a) {
     pg.stencil(a, v1);
     pg.stencil(a, v2);
     pg.inverse(a, inv);
+  }
+}
+
+// Local core range [lc0, lc1] of a chain and its two-sided factor blocks.
+inline int chain_lc0(const Chain& ch) { return ch.ct0 - ch.t0; }
+inline int chain_lc1(const Chain& ch) { return ch.ct0 - ch.t0 + ch.cT - 1; }
+inline double* fblock(const ChainSet& cs, size_t c, int t) {
+  return cs.S[c] + (size_t)cs.np[c] * cs.np[c] * t;
+}
+inline double* gblock(const ChainSet& cs, size_t c, int t) {
+  return cs.G[c] + (size_t)cs.np[c] * cs.np[c] * (t - chain_lc0(cs.chains[c]) - 1);
+}
+
+// Stencil tasks forming  out = B_t - q_o^2 Q_R (X + Y) Q_R  (X, Y inverse
+// blocks, either may be null; B_t = q_d(t) Q_R + D_t, identity on the padded
+// diagonal) in three passes through cs.tmp[c]: tmp = (Q_R X)^T, tmp +=
+// (Q_R Y)^T (both stored transposed, i.e. X Q_R and Y Q_R), out = -q_o^2 Q_R
+// tmp + B_t.
+void add_schur(const ChainSet& cs, size_t c, int t, const double* X, const double* Y,
+               double* out, StencilList& v1, StencilList& v1b, StencilList& v2) {
+  const Chain& ch = cs.chains[c];
+  const rbmc_model* m = cs.owner[c];
+  const int np = cs.np[c], nb = cs.nb[c];
+  const int tg = ch.t0 + t;
+  const double* first = X ? X : Y;
+  const double* second = X ? Y : nullptr;
+  if (first) {
+    StencilTask s1 = stask(cs, c);
+    s1.M = first;
+    s1.ldm = np;
+    s1.out = cs.tmp[c];
+    s1.ldout = np;
+    s1.ncols = np;
+    s1.alpha = 1.0;
+    s1.tstore = 1;
+    v1.add(s1, np, nb);
+  }
+  if (second) {
+    StencilTask s1 = stask(cs, c);
+    s1.M = second;
+    s1.ldm = np;
+    s1.In = cs.tmp[c];
+    s1.ldin = np;
+    s1.beta = 1.0;
+    s1.out = cs.tmp[c];
+    s1.ldout = np;
+    s1.ncols = np;
+    s1.alpha = 1.0;
+    s1.tstore = 1;
+    v1b.add(s1, np, nb);
+  }
+  StencilTask s2 = stask(cs, c);
+  s2.M = first ? cs.tmp[c] : nullptr;
+  s2.ldm = np;
+  s2.alpha = first ? -m->co.qo * m->co.qo : 0.0;
+  s2.gamma = m->co.qd[tg];
+  s2.dv = m->d_dvec + (size_t)tg * m->plan.ns;
+  s2.pad_identity = 1;
+  s2.out = out;
+  s2.ldout = np;
+  s2.ncols = np;
+  v2.add(s2, np, nb);
+}
+
+InvJob inv_job(const ChainSet& cs, size_t c, double* M) {
+  InvJob it{};
+  it.M = M;
+  it.np = cs.np[c];
+  it.nb = cs.nb[c];
+  it.info = cs.info[c];
+  it.B = cs.gjB[c];
+  it.U = cs.gjU[c];
+  it.P = cs.gjP[c];
+  it.B2 = cs.gjB2[c];
+  it.U2 = cs.gjU2[c];
+  it.P2 = cs.gjP2[c];
+  it.base = 0;
+  return it;
+}
+
+// Two-sided factorization of the subdomain chains (block-tridiagonal Q_AA
+// with diagonal blocks B_t and off-diagonal blocks q_o Q_R):
+//   forward  F_0 = B_0^-1,      F_t = (B_t - q_o^2 Q_R F_{t-1} Q_R)^-1,  t < lc1;
+//   backward G_{T-1} = B_{T-1}^-1, G_t = (B_t - q_o^2 Q_R G_{t+1} Q_R)^-1, t > lc0.
+// Round r takes forward step r and backward step T-1-r of every chain (the
+// two use the chain's workspace one after the other).
+void build_twosided(ChainSet& cs, Program& pg, Arena& a) {
+  int rounds = 0;
+  for (size_t c = 0; c < cs.size(); ++c) {
+    const Chain& ch = cs.chains[c];
+    rounds = std::max(rounds, std::max(chain_lc1(ch), ch.T - 1 - chain_lc0(ch)));
+  }
+  for (int r = 0; r < rounds; ++r) {
+    for (int dir = 0; dir < 2; ++dir) {
+      StencilList v1, v1b, v2;
+      std::vector<InvJob> inv;
+      for (size_t c = 0; c < cs.size(); ++c) {
+        const Chain& ch = cs.chains[c];
+        if (dir == 0) {
+          if (r >= chain_lc1(ch)) continue;
+          double* out = fblock(cs, c, r);
+          add_schur(cs, c, r, r > 0 ? fblock(cs, c, r - 1) : nullptr, nullptr, out, v1, v1b, v2);
+          inv.push_back(inv_job(cs, c, out));
+        } else {
+          const int t = ch.T - 1 - r;
+          if (t <= chain_lc0(ch)) continue;
+          double* out = gblock(cs, c, t);
+          add_schur(cs, c, t, t < ch.T - 1 ? gblock(cs, c, t + 1) : nullptr, nullptr, out, v1,
+                    v1b, v2);
+          inv.push_back(inv_job(cs, c, out));
+        }
+      }
+      pg.stencil(a, v1);
+      pg.stencil(a, v2);
+      pg.inverse(a, inv);
+    }
+  }
+}
+
+// Twisted block solve Q_AA mu = r with the two-sided factors, meeting at the
+// first core step k = lc0 (r_t in pan[c][t] for every t; cs.ytmp[c] is the
+// work panel):
+//   forward  u_t = F_t (r_t - q_o Q_R u_{t-1}),             t < k;
+//   backward v_t = G_t (r_t - q_o Q_R v_{t+1}),             t > k;
+//   twist    mu_k = Sigma_kk (r_k - q_o Q_R u_{k-1} - q_o Q_R v_{k+1});
+//   then     mu_{k-1} = u_{k-1} - F_{k-1} q_o Q_R mu_k,
+//            mu_t = v_t - G_t q_o Q_R mu_{t-1}   for k < t <= lc1 + 1,
+// i.e. mu on every step the Monte Carlo terms of the core rows read.
+void build_twisted_solve(ChainSet& cs, int n_k, Program& pg, Arena& a, int mixed) {
+  auto stencil_into_ytmp = [&](size_t c, const double* M, double alpha, const double* In,
+                               StencilList& sl) {
+    StencilTask st = stask(cs, c);
+    st.M = M;
+    st.ldm = cs.np[c];
+    st.alpha = M ? alpha : 0.0;
+    st.In = In;
+    st.ldin = cs.np[c];
+    st.beta = In ? 1.0 : 0.0;
+    st.out = cs.ytmp[c];
+    st.ldout = cs.np[c];
+    st.ncols = n_k;
+    sl.add(st, cs.np[c], cs.nb[c]);
+  };
+  auto gemm = [&](size_t c, const double* Sinv, const double* Cin, double* C, double alpha,
+                  double beta, GemmList& gl) {
+    const int np = cs.np[c], nb = cs.nb[c];
+    gl.add(Sinv, cs.ytmp[c], Cin, C, np, n_k, np, np, np, np, alpha, beta, 1, 0, nb, nb);
+  };
+  for (int t = 0; t < cs.maxT; ++t) {  // forward and backward partial solutions
+    for (int dir = 0; dir < 2; ++dir) {
+      StencilList sl;
+      GemmList gl;
+      gl.mixed = mixed;
+      for (size_t c = 0; c < cs.size(); ++c) {
+        const Chain& ch = cs.chains[c];
+        const double qo = cs.owner[c]->co.qo;
+        const int k = chain_lc0(ch);
+        if (dir == 0) {
+          if (t >= k) continue;
+          stencil_into_ytmp(c, t > 0 ? cs.pan[c][t - 1] : nullptr, -qo, cs.pan[c][t], sl);
+          gemm(c, fblock(cs, c, t), nullptr, cs.pan[c][t], 1.0, 0.0, gl);
+        } else {
+          const int tt = ch.T - 1 - t;
+          if (tt <= k) continue;
+          stencil_into_ytmp(c, tt < ch.T - 1 ? cs.pan[c][tt + 1] : nullptr, -qo, cs.pan[c][tt], sl);
+          gemm(c, gblock(cs, c, tt), nullptr, cs.pan[c][tt], 1.0, 0.0, gl);
+        }
+      }
+      pg.stencil(a, sl);
+      pg.gemm(a, gl);
+    }
+  }
+  {  // twist
+    StencilList s1, s2;
+    GemmList gl;
+    gl.mixed = mixed;
+    for (size_t c = 0; c < cs.size(); ++c) {
+      const Chain& ch = cs.chains[c];
+      const double qo = cs.owner[c]->co.qo;
+      const int k = chain_lc0(ch);
+      stencil_into_ytmp(c, k > 0 ? cs.pan[c][k - 1] : nullptr, -qo, cs.pan[c][k], s1);
+      if (k + 1 < ch.T) stencil_into_ytmp(c, cs.pan[c][k + 1], -qo, cs.ytmp[c], s2);
+      gemm(c, cs.sig[c], nullptr, cs.pan[c][k], 1.0, 0.0, gl);
+    }
+    pg.stencil(a, s1);
+    pg.stencil(a, s2);
+    pg.gemm(a, gl);
+  }
+  {  // one step down
+    StencilList sl;
+    GemmList gl;
+    gl.mixed = mixed;
+    for (size_t c = 0; c < cs.size(); ++c) {
+      const Chain& ch = cs.chains[c];
+      const int k = chain_lc0(ch);
+      if (k < 1) continue;
+      stencil_into_ytmp(c, cs.pan[c][k], cs.owner[c]->co.qo, nullptr, sl);
+      gemm(c, fblock(cs, c, k - 1), cs.pan[c][k - 1], cs.pan[c][k - 1], -1.0, 1.0, gl);
+    }
+    pg.stencil(a, sl);
+    pg.gemm(a, gl);
+  }
+  for (int d = 1; d < cs.maxT; ++d) {  // up to one step above the core
+    StencilList sl;
+    GemmList gl;
+    gl.mixed = mixed;
+    for (size_t c = 0; c < cs.size(); ++c) {
+      const Chain& ch = cs.chains[c];
+      const int t = chain_lc0(ch) + d;
+      if (t > chain_lc1(ch) + 1 || t >= ch.T) continue;
+      stencil_into_ytmp(c, cs.pan[c][t - 1], cs.owner[c]->co.qo, nullptr, sl);
+      gemm(c, gblock(cs, c, t), cs.pan[c][t], cs.pan[c][t], -1.0, 1.0, gl);
+    }
+    pg.stencil(a, sl);
+    pg.gemm(a, gl);
   }
 }
 
@@ -1273,8 +1514,8 @@ rbmc_status estimate_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const
     rbmc_status e = ensure_streams(cx);
     if (e != RBMC_OK) return e;
   }
-  // sA: sampler (when overlapped) and corrections; s: factorization;
-  // sT: Takahashi sweep
+  // sA: sampler (when overlapped) and corrections; s: two-sided
+  // factorization; sT: core steps
   hipStream_t sA = sampler ? cx->work : cx->stream;
   hipStream_t s = sampler ? cx->side : sA;
   hipStream_t sT = sampler ? cx->side2 : sA;
@@ -1293,7 +1534,7 @@ rbmc_status estimate_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const
   Arena& ar = cx->arenaB;
   ar.clear();
   Program fac;
-  if (cf.size()) build_factor(cf, fac, ar);
+  if (cf.size()) build_twosided(cf, fac, ar);
   // partial-sum slots: per chain and local step: det (diag block, off t->t+1,
   // off t+1->t) in chunks of 256 rows, mc in chunks of 64 rows
   std::vector<size_t> det_base(nchains + 1, 0), mc_base(nchains + 1, 0);
@@ -1335,75 +1576,65 @@ rbmc_status estimate_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const
     return e;
   };
 
-  // ---- Takahashi sweep ----
+  // ---- core steps: Sigma_tt = (B_t - q_o^2 Q_R (F_{t-1} + G_{t+1}) Q_R)^-1,
+  // its diagonal and stencil entries, and the stencil entries of the
+  // off-diagonal blocks Sigma_{t,t+1} = -q_o (G_{t+1} Q_R Sigma_tt)^T and
+  // Sigma_{t,t-1} = -q_o (F_{t-1} Q_R Sigma_tt)^T.  Core step k of every
+  // chain per round (sig holds the first core step for the solves).
   Program tak;
   {
-    TileList<ExtractTask> ex;
-    for (int c = 0; c < nchains; ++c) {
-      const Chain& ch = cs.chains[c];
-      const int np = cs.np[c];
-      const size_t blk = (size_t)np * np;
-      tak.copy(cs.sig[c], cs.S[c] + blk * (ch.T - 1), blk * 8);
-      if (is_core(c, ch.T - 1))
-        ex.add(etask(c, cs.sig[c], ch.T - 1, 0, 0, 1.0, 0), (np + 255) / 256);
-    }
-    tak.extract(ar, ex);
-  }
-  for (int t = cs.maxT - 2; t >= 0; --t) {
-    StencilList s1, s2;
-    GemmList g1, g2;
-    g1.mixed = g2.mixed = mixed;
-    TileList<ExtractTask> e1, e2;
-    std::vector<InvTask> mir;
-    for (int c = 0; c < nchains; ++c) {
-      const Chain& ch = cs.chains[c];
-      if (t > ch.T - 2) continue;
-      const int stop_x = std::max(lc0(c) - 1, 0);
-      if (t < stop_x) continue;
-      const double qo = cs.owner[c]->co.qo;
-      const int np = cs.np[c], nb = cs.nb[c];
-      const size_t blk = (size_t)np * np;
-      StencilTask v = stask(cs, c);
-      v.M = cs.sig[c];
-      v.ldm = np;
-      v.alpha = 1.0;
-      v.out = cs.tmp[c];
-      v.ldout = np;
-      v.ncols = np;
-      s1.add(v, np, nb);
-      // X = q_o V^T S_t^-1  (Sigma_{t+1,t} = -X)
-      g1.add(cs.tmp[c], cs.S[c] + blk * t, nullptr, cs.xb[c], np, np, np, np, np, np, qo, 0.0, 1,
-             0, nb, nb);
-      if (is_core(c, t))  // rows at t, columns at t+1: Sigma_{t,t+1} = -X^T
-        e1.add(etask(c, cs.xb[c], t, 1, 1, -1.0, 1), (np + 255) / 256);
-      if (is_core(c, t + 1))  // rows at t+1, columns at t: Sigma_{t+1,t} = -X
-        e1.add(etask(c, cs.xb[c], t + 1, 1, 0, -1.0, 2), (np + 255) / 256);
-      if (t >= lc0(c)) {
-        StencilTask z = stask(cs, c);
-        z.M = cs.xb[c];
-        z.ldm = np;
-        z.alpha = qo;
-        z.out = cs.tmp[c];
-        z.ldout = np;
-        z.ncols = np;
-        s2.add(z, np, nb);
-        g2.add(cs.S[c] + blk * t, cs.tmp[c], cs.S[c] + blk * t, cs.sig[c], np, np, np, np, np,
-               np, 1.0, 1.0, 1, 0, nb, nb);
-        g2.set_last_lower();  // Sigma_tt is symmetric: lower tiles, then mirrored
-        InvTask mt{};
-        mt.M = cs.sig[c];
-        mt.np = np;
-        mir.push_back(mt);
-        if (is_core(c, t)) e2.add(etask(c, cs.sig[c], t, 0, 0, 1.0, 0), (np + 255) / 256);
+    int max_ct = 0;
+    for (int c = 0; c < nchains; ++c) max_ct = std::max(max_ct, cs.chains[c].cT);
+    for (int k = 0; k < max_ct; ++k) {
+      StencilList v1, v1b, v2, wp, wm;
+      std::vector<InvJob> inv;
+      TileList<ExtractTask> ex;
+      TileList<OffdiagTask> op, om;
+      for (int c = 0; c < nchains; ++c) {
+        const Chain& ch = cs.chains[c];
+        if (k >= ch.cT) continue;
+        const int t = lc0(c) + k;
+        const int np = cs.np[c], nb = cs.nb[c];
+        const double qo = cs.owner[c]->co.qo;
+        double* sg = (k == 0) ? cs.sig[c] : cs.sig2[c];
+        const double* Fm = (t >= 1) ? fblock(cs, c, t - 1) : nullptr;
+        const double* Gp = (t + 1 < ch.T) ? gblock(cs, c, t + 1) : nullptr;
+        add_schur(cs, c, t, Fm, Gp, sg, v1, v1b, v2);
+        inv.push_back(inv_job(cs, c, sg));
+        ex.add(etask(c, sg, t, 0, 0, 1.0, 0), (np + 255) / 256);
+        for (int side = 0; side < 2; ++side) {
+          const double* far = side == 0 ? Gp : Fm;
+          if (!far) continue;
+          StencilTask w = stask(cs, c);  // W = Q_R (far inverse), column-major
+          w.M = far;
+          w.ldm = np;
+          w.alpha = 1.0;
+          w.out = cs.tmp[c];
+          w.ldout = np;
+          w.ncols = np;
+          (side == 0 ? wp : wm).add(w, np, nb);
+          OffdiagTask o{};
+          o.W = cs.tmp[c];
+          o.Sig = sg;
+          o.ld = np;
+          o.rg = cs.rg[c];
+          o.dm = cs.owner[c]->d_dm;
+          o.partial = det_part;
+          o.out_index = (int)det_index(c, t, side == 0 ? 1 : 2);
+          o.scale = -qo;
+          (side == 0 ? op : om).add(o, (np + 255) / 256, 16.0 * nb * (double)nb);
+        }
       }
+      tak.stencil(ar, v1);
+      tak.stencil(ar, v1b);
+      tak.stencil(ar, v2);
+      tak.inverse(ar, inv);
+      tak.extract(ar, ex);
+      tak.stencil(ar, wp);
+      tak.offdiag(ar, op);
+      tak.stencil(ar, wm);
+      tak.offdiag(ar, om);
     }
-    tak.stencil(ar, s1);
-    tak.gemm(ar, g1);
-    tak.extract(ar, e1);
-    tak.stencil(ar, s2);
-    tak.gemm(ar, g2);
-    tak.mirror(ar, mir);
-    tak.extract(ar, e2);
   }
   // ---- corrections ----
   Program cor;
@@ -1414,7 +1645,7 @@ rbmc_status estimate_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const
       const int np = cs.np[c];
       for (int t = 0; t < ch.T; ++t) {
         PanelTask pt{};
-        pt.P = (t == 0) ? cs.ytmp[c] : cs.pan[c][t];
+        pt.P = cs.pan[c][t];
         pt.rg = cs.rg[c];
         pt.dm = cs.owner[c]->d_dm;
         pt.X = x_base + h.base[cmodel[c]];
@@ -1427,9 +1658,7 @@ rbmc_status estimate_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const
       }
     }
     cor.panels(ar, rt);
-    std::vector<int> stop(nchains);
-    for (int c = 0; c < nchains; ++c) stop[c] = std::max(lc0(c) - 1, 0);
-    build_solve(cs, nk, stop, cor, ar, mixed);
+    build_twisted_solve(cs, nk, cor, ar, mixed);
     TileList<McTask> mt;
     for (int c = 0; c < nchains; ++c) {
       const Chain& ch = cs.chains[c];
@@ -1459,8 +1688,8 @@ rbmc_status estimate_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const
   }
   HIPCHK(ar.upload(s));
   HIPCHK(hipMemsetAsync(cx->epart, 0, need * 8, s));
-  if (cf.size()) {
-    rbmc_status st0 = zero_info(cf, s);
+  {  // the core-step inversions run on every call
+    rbmc_status st0 = zero_info(cs, s);
     if (st0 != RBMC_OK) return st0;
   }
   hipEvent_t e_fac = nullptr, e_tak = nullptr, e_beg = nullptr;
@@ -1519,11 +1748,9 @@ rbmc_status estimate_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const
   rbmc_status st = RBMC_OK;
   HIPCHK(hipStreamSynchronize(s));
   HIPCHK(hipStreamSynchronize(sT));
-  if (cf.size()) {
-    st = check_info(cf, rep, "subdomain", sA);
-    if (st != RBMC_OK) return st;
-    for (rbmc_model* m : ms) m->sub_ready = true;
-  }
+  st = check_info(cs, rep, "subdomain", sA);
+  if (st != RBMC_OK) return st;
+  for (rbmc_model* m : ms) m->sub_ready = true;
   double t2 = now_s();
   st = run(cx, cor, sA, ar);
   if (st != RBMC_OK) return st;

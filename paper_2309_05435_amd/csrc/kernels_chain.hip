@@ -139,6 +139,76 @@ void launch_extract(const ExtractTask* d_tasks, int n_tasks, int total_tiles, hi
 }
 
 // ---------------------------------------------------------------------------
+// Off-diagonal time blocks on the stencil pattern only.  For a core step t
+// and a neighbouring step t' = t +- 1 of the chain,
+//   Sigma_{t,t'}[a, c] = scale * sum_k W[k, c] Sigma_tt[k, a],
+// with W = Q_R S'^-1 (S' the Schur complement inverse on the far side of t,
+// one stencil pass) and scale = -q_o; only the 13 stencil neighbours c of
+// each core row a are formed.  They enter the traces exactly as k_extract's
+// off-diagonal slots do (sum over c of Q_s / K coefficient x entry).
+// One workgroup (16 waves) per 256 region rows; each wave forms the 13 dot
+// products of one row at a time, its lanes striding the shared index k.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_offdiag(const OffdiagTask* __restrict__ tasks,
+                                                  int n_tasks) {
+  __shared__ double red[2][16];
+  const int b = blockIdx.x;
+  const OffdiagTask tk = tasks[find_task_of(tasks, n_tasks, b)];
+  const RegionDev rg = *tk.rg;
+  const DevModel& m = *tk.dm;
+  const int chunk = b - tk.tile_start;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double sq = 0.0, sk = 0.0;  // lane 0 of each wave
+  for (int r = wave; r < 256; r += 16) {
+    const int a = chunk * 256 + r;
+    if (a >= rg.nb || !rg.in_box[a]) continue;
+    int nbr[kNS];
+#pragma unroll
+    for (int q = 0; q < kNS; ++q) nbr[q] = rg.nbr[a * kNS + q];
+    double acc[kNS];
+#pragma unroll
+    for (int q = 0; q < kNS; ++q) acc[q] = 0.0;
+    const double* sg = tk.Sig + (size_t)a * tk.ld;
+    for (int k = lane; k < rg.nb; k += 64) {
+      const double sv = sg[k];
+#pragma unroll
+      for (int q = 0; q < kNS; ++q)
+        if (nbr[q] >= 0) acc[q] = fma(tk.W[(size_t)nbr[q] * tk.ld + k], sv, acc[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < kNS; ++q)
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) acc[q] += __shfl_xor(acc[q], off, 64);
+    if (lane == 0) {
+      const int node = rg.nodes[a];
+#pragma unroll
+      for (int q = 0; q < kNS; ++q) {
+        if (nbr[q] < 0) continue;
+        const double v = tk.scale * acc[q];
+        sq += m.qs[(size_t)q * m.ns + node] * v;
+        if (q < kN5) sk += m.kk[(size_t)q * m.ns + node] * v;
+      }
+    }
+  }
+  if (lane == 0) {
+    red[0][wave] = sq;
+    red[1][wave] = sk;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double v = 0.0;
+    if (threadIdx.x > 0)
+      for (int w = 0; w < 16; ++w) v += red[threadIdx.x - 1][w];
+    tk.partial[((size_t)tk.out_index + chunk) * 3 + threadIdx.x] = v;
+  }
+}
+
+void launch_offdiag(const OffdiagTask* d_tasks, int n_tasks, int total_tiles, hipStream_t s) {
+  if (total_tiles <= 0) return;
+  k_offdiag<<<total_tiles, 1024, 0, s>>>(d_tasks, n_tasks);
+}
+
+// ---------------------------------------------------------------------------
 // Monte Carlo part. Workgroup = 64 region rows x all samples (4 sample lanes
 // per row).  Outputs: diag on core rows and 8 partial sums per workgroup:
 //   [0..2] mu_t . (Q_s mu_{t-1,t,t+1}), [3..5] mu_t . (K mu_{t-1,t,t+1}),

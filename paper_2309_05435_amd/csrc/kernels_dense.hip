@@ -827,7 +827,7 @@ void launch_gj2_fix(const Gj2Task* d_tasks, int n_tasks, int total_tiles, hipStr
 // stencil rows (neighbours, coefficients) are loaded once per workgroup.  A
 // tile whose span exceeds kRsSpan (a region more than 68 nodes wide) reads its
 // taps from global memory.  tstore: write the result transposed
-// (out[a * ldout + c], 16-byte stores; requires beta = 0).
+// (out[a * ldout + c], In read the same way; 16-byte stores when beta = 0).
 // ---------------------------------------------------------------------------
 namespace {
 constexpr int kRsRows = 256, kRsCols = 16, kRsGroups = 4, kRsSpan = 528;
@@ -938,14 +938,18 @@ __global__ __launch_bounds__(256) void k_rstencil(const StencilTask* __restrict_
         if (tk.beta != 0.0) r += tk.beta * tk.In[(size_t)(c0 + cc) * tk.ldin + a];
         tk.out[(size_t)(c0 + cc) * tk.ldout + a] = r;
       }
-    } else if (ncc == kRsCols) {  // 16 contiguous doubles of row a (c0, ldout even)
+    } else if (ncc == kRsCols && tk.beta == 0.0) {  // 16 contiguous doubles of row a
       double2* o = reinterpret_cast<double2*>(tk.out + (size_t)a * tk.ldout + c0);
 #pragma unroll
       for (int k = 0; k < kRsCols / 2; ++k) o[k] = make_double2(v[2 * k], v[2 * k + 1]);
     } else {
 #pragma unroll
-      for (int cc = 0; cc < kRsCols; ++cc)
-        if (cc < ncc) tk.out[(size_t)a * tk.ldout + c0 + cc] = v[cc];
+      for (int cc = 0; cc < kRsCols; ++cc) {
+        if (cc >= ncc) break;
+        double r = v[cc];
+        if (tk.beta != 0.0) r += tk.beta * tk.In[(size_t)a * tk.ldin + c0 + cc];
+        tk.out[(size_t)a * tk.ldout + c0 + cc] = r;
+      }
     }
   }
 }

@@ -207,7 +207,7 @@ struct StencilTask {
   double* out;
   int ldm, ldin, ldout;
   int ncols;           // number of columns of the result (np for square, n_k for panels)
-  int tstore;          // store the result transposed: out[a * ldout + c] (beta = 0)
+  int tstore;          // store the result transposed: out[a * ldout + c] (In read the same way)
   double alpha, beta, gamma;
   const double* dv;    // optional diagonal (indexed by spatial node), square only
   int pad_identity;    // add 1 on padded diagonal (square only)
@@ -264,6 +264,22 @@ struct ExtractTask {
   int tile_start;
 };
 void launch_extract(const ExtractTask* d_tasks, int n_tasks, int total_tiles, hipStream_t s);
+// Off-diagonal time-block entries on the stencil pattern of the core rows:
+// Sigma_{t,t'}[a, c] = scale * W[:, c] . Sigma_tt[:, a] (both column-major,
+// ld), accumulated like k_extract's off-diagonal slots (partial chunk layout
+// identical).  One tile = 256 region rows.
+struct OffdiagTask {
+  const double* W;
+  const double* Sig;
+  int ld;
+  const RegionDev* rg;
+  const DevModel* dm;
+  double* partial;
+  int out_index;
+  double scale;
+  int tile_start;
+};
+void launch_offdiag(const OffdiagTask* d_tasks, int n_tasks, int total_tiles, hipStream_t s);
 
 // Monte Carlo part from the correction panels mu_t (np x n_k) of a chain:
 //   diag_out[t*ns + node] += (1/n_k) sum_k mu_t[a,k]^2 on core nodes;
