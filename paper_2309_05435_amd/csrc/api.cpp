@@ -199,6 +199,9 @@ namespace {
 // A set of block-tridiagonal chains with their dense blocks and workspaces.
 // For one model the owner of every chain is that model; a batched call
 // concatenates the sets of many models.
+// widest outer Gauss-Jordan step (the sweep workspaces are sized for it)
+constexpr int kSweepMax = 512;
+
 struct ChainSet {
   std::vector<Chain> chains;
   std::vector<rbmc_model*> owner;
@@ -214,10 +217,12 @@ struct ChainSet {
   std::vector<double*> G;
   std::vector<double*> tmp;          // np^2
   std::vector<double*> sig, sig2;    // np^2, subdomains only
-  std::vector<double*> gjU, gjB;     // np x 256 Gauss-Jordan panels
-  std::vector<double*> gjP;          // 256 x 256 pivot block
-  std::vector<double*> gjU2, gjB2;   // 256 x 128 panels of the pivot block's sweep
+  std::vector<double*> gjU, gjB;     // np x kSweepMax Gauss-Jordan panels
+  std::vector<double*> gjP;          // kSweepMax^2 pivot block
+  std::vector<double*> gjU2, gjB2;   // kSweepMax x 128 panels of the pivot block's sweep
   std::vector<double*> gjP2;         // 128 x 128
+  // a second workspace set, for the backward inversion of the same round
+  std::vector<double*> gjUb, gjBb, gjPb, gjU2b, gjB2b, gjP2b;
   std::vector<std::vector<double*>> pan;  // per chain: T panels np x n_k
   std::vector<double*> ytmp;              // per chain: one panel
   int maxT = 0;
@@ -239,6 +244,12 @@ struct ChainSet {
     cat(gjP, o.gjP);
     cat(gjU2, o.gjU2);
     cat(gjB2, o.gjB2);
+    cat(gjUb, o.gjUb);
+    cat(gjBb, o.gjBb);
+    cat(gjPb, o.gjPb);
+    cat(gjU2b, o.gjU2b);
+    cat(gjB2b, o.gjB2b);
+    cat(gjP2b, o.gjP2b);
     cat(gjP2, o.gjP2);
     cat(pan, o.pan);
     cat(ytmp, o.ytmp);
@@ -352,18 +363,31 @@ rbmc_status alloc_chainset(rbmc_model* m, ChainSet& cs, const std::vector<Chain>
       cs.sig.push_back(nullptr);
       cs.sig2.push_back(nullptr);
     }
-    HIPCHK(m->pool.alloc((void**)&p, (size_t)np * 256 * 8));
+    const size_t wmax = kSweepMax;
+    HIPCHK(m->pool.alloc((void**)&p, (size_t)np * wmax * 8));
     cs.gjU.push_back(p);
-    HIPCHK(m->pool.alloc((void**)&p, (size_t)np * 256 * 8));
+    HIPCHK(m->pool.alloc((void**)&p, (size_t)np * wmax * 8));
     cs.gjB.push_back(p);
-    HIPCHK(m->pool.alloc((void**)&p, (size_t)256 * 256 * 8));
+    HIPCHK(m->pool.alloc((void**)&p, wmax * wmax * 8));
     cs.gjP.push_back(p);
-    HIPCHK(m->pool.alloc((void**)&p, (size_t)256 * 128 * 8));
+    HIPCHK(m->pool.alloc((void**)&p, wmax * 128 * 8));
     cs.gjU2.push_back(p);
-    HIPCHK(m->pool.alloc((void**)&p, (size_t)256 * 128 * 8));
+    HIPCHK(m->pool.alloc((void**)&p, wmax * 128 * 8));
     cs.gjB2.push_back(p);
     HIPCHK(m->pool.alloc((void**)&p, (size_t)128 * 128 * 8));
     cs.gjP2.push_back(p);
+    HIPCHK(m->pool.alloc((void**)&p, (size_t)np * wmax * 8));
+    cs.gjUb.push_back(p);
+    HIPCHK(m->pool.alloc((void**)&p, (size_t)np * wmax * 8));
+    cs.gjBb.push_back(p);
+    HIPCHK(m->pool.alloc((void**)&p, wmax * wmax * 8));
+    cs.gjPb.push_back(p);
+    HIPCHK(m->pool.alloc((void**)&p, wmax * 128 * 8));
+    cs.gjU2b.push_back(p);
+    HIPCHK(m->pool.alloc((void**)&p, wmax * 128 * 8));
+    cs.gjB2b.push_back(p);
+    HIPCHK(m->pool.alloc((void**)&p, (size_t)128 * 128 * 8));
+    cs.gjP2b.push_back(p);
     cs.pan.push_back({});
     cs.ytmp.push_back(nullptr);
     cs.maxT = std::max(cs.maxT, c.T);
@@ -594,7 +618,10 @@ struct Program {
     pb.family = RBMC_KF_SPD_INVERSE;
     for (const InvJob& j : jobs) pb.alg_flops += (double)j.nb * j.nb * j.nb;
     ops.push_back(pb);
-    sweep(a, jobs, jobs.size() >= 4 ? 256 : 128);
+    // batches: rank-512 outer steps (longer products, half the trailing
+    // re-reads; measured faster than 256); few blocks: 128 (shorter chain of
+    // dependent launches)
+    sweep(a, jobs, jobs.size() >= 4 ? kSweepMax : 128);
     Op pe;
     pe.kind = 11;
     ops.push_back(pe);
@@ -754,72 +781,25 @@ StencilTask stask(const ChainSet& cs, size_t c) {
   return t;
 }
 
-// Factorization program: S_t^-1 of every chain of the set.
-//   S_0 = B_0,  S_t = B_t - q_o^2 Q_R S_{t-1}^-1 Q_R,  B_t = q_d(t) Q_R + D_t
-// The product is two stencil passes over columns: tmp = (Q_R S^-1)^T, stored
-// transposed, equals S^-1 Q_R (S^-1 is exactly symmetric), then Q_R tmp.
-void build_factor(ChainSet& cs, Program& pg, Arena& a) {
-  for (int t = 0; t < cs.maxT; ++t) {
-    StencilList v1, v2;
-    std::vector<InvJob> inv;
-    for (size_t c = 0; c < cs.size(); ++c) {
-      const Chain& ch = cs.chains[c];
-      if (t >= ch.T) continue;
-      const rbmc_model* m = cs.owner[c];
-      const int np = cs.np[c], nb = cs.nb[c];
-      const size_t blk = (size_t)np * np;
-      const int tg = ch.t0 + t;
-      double* St = cs.S[c] + blk * t;
-      if (t > 0) {
-        StencilTask s1 = stask(cs, c);
-        s1.M = cs.S[c] + blk * (t - 1);
-        s1.ldm = np;
-        s1.out = cs.tmp[c];
-        s1.ldout = np;
-        s1.ncols = np;
-        s1.alpha = 1.0;
-        s1.tstore = 1;
-        v1.add(s1, np, nb);
-      }
-      StencilTask s2 = stask(cs, c);
-      s2.M = (t > 0) ? cs.tmp[c] : nullptr;
-      s2.ldm = np;
-      s2.alpha = (t > 0) ? -m->co.qo * m->co.qo : 0.0;
-      s2.gamma = m->co.qd[tg];
-      s2.dv = m->d_dvec + (size_t)tg * m->plan.ns;
-      s2.pad_identity = 1;
-      s2.out = St;
-      s2.ldout = np;
-      s2.ncols = np;
-      v2.add(s2, np, nb);
-      InvJob it{};
-      it.M = St;
-      it.np = np;
-      it.nb = nb;
-      it.info = cs.info[c];
-      it.B = cs.gjB[c];
-      it.U = cs.gjU[c];
-      it.P = cs.gjP[c];
-      it.B2 = cs.gjB2[c];
-      it.U2 = cs.gjU2[c];
-      it.P2 = cs.gjP2[c];
-      it.base = 0;
-      inv.push_back(it);
-    }
-    pg.stencil(a, v1);
-    pg.stencil(a, v2);
-    pg.inverse(a, inv);
-  }
-}
 
 // Local core range [lc0, lc1] of a chain and its two-sided factor blocks.
+// Subdomain chains: forward inverses F_t for t < lc1 in S, backward G_t for
+// t > lc0 in G, Sigma at the first core step in sig.  Block-Jacobi chains
+// (bj): twist k = T/2, F_t (t < k), Sigma_k and G_t (t > k) all in S at their
+// step index.
 inline int chain_lc0(const Chain& ch) { return ch.ct0 - ch.t0; }
 inline int chain_lc1(const Chain& ch) { return ch.ct0 - ch.t0 + ch.cT - 1; }
+inline int twist_of(const Chain& ch, bool bj) { return bj ? ch.T / 2 : chain_lc0(ch); }
+inline int fwd_count(const Chain& ch, bool bj) { return bj ? ch.T / 2 : chain_lc1(ch); }
 inline double* fblock(const ChainSet& cs, size_t c, int t) {
   return cs.S[c] + (size_t)cs.np[c] * cs.np[c] * t;
 }
-inline double* gblock(const ChainSet& cs, size_t c, int t) {
+inline double* gblock(const ChainSet& cs, size_t c, int t, bool bj = false) {
+  if (bj) return cs.S[c] + (size_t)cs.np[c] * cs.np[c] * t;
   return cs.G[c] + (size_t)cs.np[c] * cs.np[c] * (t - chain_lc0(cs.chains[c]) - 1);
+}
+inline double* sigblock(const ChainSet& cs, size_t c, bool bj) {
+  return bj ? cs.S[c] + (size_t)cs.np[c] * cs.np[c] * (cs.chains[c].T / 2) : cs.sig[c];
 }
 
 // Stencil tasks forming  out = B_t - q_o^2 Q_R (X + Y) Q_R  (X, Y inverse
@@ -873,58 +853,81 @@ void add_schur(const ChainSet& cs, size_t c, int t, const double* X, const doubl
   v2.add(s2, np, nb);
 }
 
-InvJob inv_job(const ChainSet& cs, size_t c, double* M) {
+// ws: workspace set 0 or 1 (two inversions of one chain may share a batch)
+InvJob inv_job(const ChainSet& cs, size_t c, double* M, int ws = 0) {
   InvJob it{};
   it.M = M;
   it.np = cs.np[c];
   it.nb = cs.nb[c];
   it.info = cs.info[c];
-  it.B = cs.gjB[c];
-  it.U = cs.gjU[c];
-  it.P = cs.gjP[c];
-  it.B2 = cs.gjB2[c];
-  it.U2 = cs.gjU2[c];
-  it.P2 = cs.gjP2[c];
+  it.B = ws ? cs.gjBb[c] : cs.gjB[c];
+  it.U = ws ? cs.gjUb[c] : cs.gjU[c];
+  it.P = ws ? cs.gjPb[c] : cs.gjP[c];
+  it.B2 = ws ? cs.gjB2b[c] : cs.gjB2[c];
+  it.U2 = ws ? cs.gjU2b[c] : cs.gjU2[c];
+  it.P2 = ws ? cs.gjP2b[c] : cs.gjP2[c];
   it.base = 0;
   return it;
 }
 
-// Two-sided factorization of the subdomain chains (block-tridiagonal Q_AA
-// with diagonal blocks B_t and off-diagonal blocks q_o Q_R):
-//   forward  F_0 = B_0^-1,      F_t = (B_t - q_o^2 Q_R F_{t-1} Q_R)^-1,  t < lc1;
-//   backward G_{T-1} = B_{T-1}^-1, G_t = (B_t - q_o^2 Q_R G_{t+1} Q_R)^-1, t > lc0.
-// Round r takes forward step r and backward step T-1-r of every chain (the
-// two use the chain's workspace one after the other).
-void build_twosided(ChainSet& cs, Program& pg, Arena& a) {
+// Two-sided factorization of block-tridiagonal chains (diagonal blocks B_t,
+// off-diagonal blocks q_o Q_R):
+//   forward  F_0 = B_0^-1,      F_t = (B_t - q_o^2 Q_R F_{t-1} Q_R)^-1;
+//   backward G_{T-1} = B_{T-1}^-1, G_t = (B_t - q_o^2 Q_R G_{t+1} Q_R)^-1.
+// Subdomains: F for t < lc1, G for t > lc0 (their Sigma_tt are formed per
+// call by the core-step program).  Block-Jacobi chains (bj): F for t < k,
+// G for t > k and Sigma_k = (B_k - q_o^2 Q_R (F_{k-1} + G_{k+1}) Q_R)^-1 at the
+// twist k = T/2, so the dependent chain of inversions is about half as long.
+// Round r takes forward step r and backward step T-1-r of every chain: their
+// stencil passes one after the other (they share cs.tmp), their inversions
+// in one batch (each with its own workspace set).
+void build_twosided(ChainSet& cs, Program& pg, Arena& a, bool bj = false) {
   int rounds = 0;
   for (size_t c = 0; c < cs.size(); ++c) {
     const Chain& ch = cs.chains[c];
-    rounds = std::max(rounds, std::max(chain_lc1(ch), ch.T - 1 - chain_lc0(ch)));
+    const int k0 = bj ? ch.T / 2 : chain_lc0(ch);
+    rounds = std::max(rounds, std::max(fwd_count(ch, bj), ch.T - 1 - k0));
   }
   for (int r = 0; r < rounds; ++r) {
+    std::vector<InvJob> inv;
     for (int dir = 0; dir < 2; ++dir) {
       StencilList v1, v1b, v2;
-      std::vector<InvJob> inv;
       for (size_t c = 0; c < cs.size(); ++c) {
         const Chain& ch = cs.chains[c];
         if (dir == 0) {
-          if (r >= chain_lc1(ch)) continue;
+          if (r >= fwd_count(ch, bj)) continue;
           double* out = fblock(cs, c, r);
           add_schur(cs, c, r, r > 0 ? fblock(cs, c, r - 1) : nullptr, nullptr, out, v1, v1b, v2);
           inv.push_back(inv_job(cs, c, out));
         } else {
           const int t = ch.T - 1 - r;
-          if (t <= chain_lc0(ch)) continue;
-          double* out = gblock(cs, c, t);
-          add_schur(cs, c, t, t < ch.T - 1 ? gblock(cs, c, t + 1) : nullptr, nullptr, out, v1,
-                    v1b, v2);
-          inv.push_back(inv_job(cs, c, out));
+          if (t <= (bj ? ch.T / 2 : chain_lc0(ch))) continue;
+          double* out = gblock(cs, c, t, bj);
+          add_schur(cs, c, t, t < ch.T - 1 ? gblock(cs, c, t + 1, bj) : nullptr, nullptr, out,
+                    v1, v1b, v2);
+          inv.push_back(inv_job(cs, c, out, 1));
         }
       }
       pg.stencil(a, v1);
       pg.stencil(a, v2);
-      pg.inverse(a, inv);
     }
+    pg.inverse(a, inv);
+  }
+  if (bj) {  // Sigma at the twist
+    StencilList v1, v1b, v2;
+    std::vector<InvJob> inv;
+    for (size_t c = 0; c < cs.size(); ++c) {
+      const Chain& ch = cs.chains[c];
+      const int k = ch.T / 2;
+      double* out = sigblock(cs, c, true);
+      add_schur(cs, c, k, k >= 1 ? fblock(cs, c, k - 1) : nullptr,
+                k + 1 < ch.T ? gblock(cs, c, k + 1, true) : nullptr, out, v1, v1b, v2);
+      inv.push_back(inv_job(cs, c, out));
+    }
+    pg.stencil(a, v1);
+    pg.stencil(a, v1b);
+    pg.stencil(a, v2);
+    pg.inverse(a, inv);
   }
 }
 
@@ -936,8 +939,11 @@ void build_twosided(ChainSet& cs, Program& pg, Arena& a) {
 //   twist    mu_k = Sigma_kk (r_k - q_o Q_R u_{k-1} - q_o Q_R v_{k+1});
 //   then     mu_{k-1} = u_{k-1} - F_{k-1} q_o Q_R mu_k,
 //            mu_t = v_t - G_t q_o Q_R mu_{t-1}   for k < t <= lc1 + 1,
-// i.e. mu on every step the Monte Carlo terms of the core rows read.
-void build_twisted_solve(ChainSet& cs, int n_k, Program& pg, Arena& a, int mixed) {
+// i.e. mu on every step the Monte Carlo terms of the core rows read.  Block-
+// Jacobi chains (bj): twist k = T/2 and the back substitution runs over the
+// whole chain (the preconditioned residual).
+void build_twisted_solve(ChainSet& cs, int n_k, Program& pg, Arena& a, int mixed,
+                         bool bj = false) {
   auto stencil_into_ytmp = [&](size_t c, const double* M, double alpha, const double* In,
                                StencilList& sl) {
     StencilTask st = stask(cs, c);
@@ -965,7 +971,7 @@ void build_twisted_solve(ChainSet& cs, int n_k, Program& pg, Arena& a, int mixed
       for (size_t c = 0; c < cs.size(); ++c) {
         const Chain& ch = cs.chains[c];
         const double qo = cs.owner[c]->co.qo;
-        const int k = chain_lc0(ch);
+        const int k = twist_of(ch, bj);
         if (dir == 0) {
           if (t >= k) continue;
           stencil_into_ytmp(c, t > 0 ? cs.pan[c][t - 1] : nullptr, -qo, cs.pan[c][t], sl);
@@ -974,7 +980,7 @@ void build_twisted_solve(ChainSet& cs, int n_k, Program& pg, Arena& a, int mixed
           const int tt = ch.T - 1 - t;
           if (tt <= k) continue;
           stencil_into_ytmp(c, tt < ch.T - 1 ? cs.pan[c][tt + 1] : nullptr, -qo, cs.pan[c][tt], sl);
-          gemm(c, gblock(cs, c, tt), nullptr, cs.pan[c][tt], 1.0, 0.0, gl);
+          gemm(c, gblock(cs, c, tt, bj), nullptr, cs.pan[c][tt], 1.0, 0.0, gl);
         }
       }
       pg.stencil(a, sl);
@@ -988,106 +994,45 @@ void build_twisted_solve(ChainSet& cs, int n_k, Program& pg, Arena& a, int mixed
     for (size_t c = 0; c < cs.size(); ++c) {
       const Chain& ch = cs.chains[c];
       const double qo = cs.owner[c]->co.qo;
-      const int k = chain_lc0(ch);
+      const int k = twist_of(ch, bj);
       stencil_into_ytmp(c, k > 0 ? cs.pan[c][k - 1] : nullptr, -qo, cs.pan[c][k], s1);
       if (k + 1 < ch.T) stencil_into_ytmp(c, cs.pan[c][k + 1], -qo, cs.ytmp[c], s2);
-      gemm(c, cs.sig[c], nullptr, cs.pan[c][k], 1.0, 0.0, gl);
+      gemm(c, sigblock(cs, c, bj), nullptr, cs.pan[c][k], 1.0, 0.0, gl);
     }
     pg.stencil(a, s1);
     pg.stencil(a, s2);
     pg.gemm(a, gl);
   }
-  {  // one step down
-    StencilList sl;
-    GemmList gl;
-    gl.mixed = mixed;
-    for (size_t c = 0; c < cs.size(); ++c) {
-      const Chain& ch = cs.chains[c];
-      const int k = chain_lc0(ch);
-      if (k < 1) continue;
-      stencil_into_ytmp(c, cs.pan[c][k], cs.owner[c]->co.qo, nullptr, sl);
-      gemm(c, fblock(cs, c, k - 1), cs.pan[c][k - 1], cs.pan[c][k - 1], -1.0, 1.0, gl);
+  // outward: subdomains one step below the core and up to one above it;
+  // block-Jacobi chains down to step 0 and up to T-1 (down and up steps of
+  // the same distance share the launches; they use the work panel in turn)
+  for (int d = 1; d < cs.maxT; ++d) {
+    for (int dir = 0; dir < 2; ++dir) {
+      StencilList sl;
+      GemmList gl;
+      gl.mixed = mixed;
+      for (size_t c = 0; c < cs.size(); ++c) {
+        const Chain& ch = cs.chains[c];
+        const int k = twist_of(ch, bj);
+        const double qo = cs.owner[c]->co.qo;
+        if (dir == 0) {
+          const int t = k - d;
+          if (t < 0 || (!bj && d > 1)) continue;
+          stencil_into_ytmp(c, cs.pan[c][t + 1], qo, nullptr, sl);
+          gemm(c, fblock(cs, c, t), cs.pan[c][t], cs.pan[c][t], -1.0, 1.0, gl);
+        } else {
+          const int t = k + d;
+          if (t >= ch.T || (!bj && t > chain_lc1(ch) + 1)) continue;
+          stencil_into_ytmp(c, cs.pan[c][t - 1], qo, nullptr, sl);
+          gemm(c, gblock(cs, c, t, bj), cs.pan[c][t], cs.pan[c][t], -1.0, 1.0, gl);
+        }
+      }
+      pg.stencil(a, sl);
+      pg.gemm(a, gl);
     }
-    pg.stencil(a, sl);
-    pg.gemm(a, gl);
-  }
-  for (int d = 1; d < cs.maxT; ++d) {  // up to one step above the core
-    StencilList sl;
-    GemmList gl;
-    gl.mixed = mixed;
-    for (size_t c = 0; c < cs.size(); ++c) {
-      const Chain& ch = cs.chains[c];
-      const int t = chain_lc0(ch) + d;
-      if (t > chain_lc1(ch) + 1 || t >= ch.T) continue;
-      stencil_into_ytmp(c, cs.pan[c][t - 1], cs.owner[c]->co.qo, nullptr, sl);
-      gemm(c, gblock(cs, c, t), cs.pan[c][t], cs.pan[c][t], -1.0, 1.0, gl);
-    }
-    pg.stencil(a, sl);
-    pg.gemm(a, gl);
   }
 }
 
-// Block-tridiagonal solve with the chain factors, in place on the panels:
-// forward u_0 = S_0^-1 r_0, u_t = S_t^-1 (r_t - q_o Q_R u_{t-1});
-// backward z_t = u_t - S_t^-1 (q_o Q_R z_{t+1}) down to local step stop[c].
-// r_0 must be in ytmp[c], r_t (t >= 1) in pan[c][t].  S_t^-1 is symmetric, so
-// it is read through the transposed (contiguous) operand path.
-void build_solve(ChainSet& cs, int n_k, const std::vector<int>& stop, Program& pg, Arena& a,
-                 int mixed) {
-  for (int t = 0; t < cs.maxT; ++t) {
-    StencilList sl;
-    GemmList gl;
-    gl.mixed = mixed;
-    for (size_t c = 0; c < cs.size(); ++c) {
-      const Chain& ch = cs.chains[c];
-      if (t >= ch.T) continue;
-      const double qo = cs.owner[c]->co.qo;
-      const int np = cs.np[c], nb = cs.nb[c];
-      const size_t blk = (size_t)np * np;
-      if (t > 0) {
-        StencilTask s = stask(cs, c);
-        s.M = cs.pan[c][t - 1];
-        s.ldm = np;
-        s.In = cs.pan[c][t];
-        s.ldin = np;
-        s.beta = 1.0;
-        s.alpha = -qo;
-        s.out = cs.ytmp[c];
-        s.ldout = np;
-        s.ncols = n_k;
-        sl.add(s, np, nb);
-      }
-      gl.add(cs.S[c] + blk * t, cs.ytmp[c], nullptr, cs.pan[c][t], np, n_k, np, np, np, np, 1.0,
-             0.0, 1, 0, nb, nb);
-    }
-    pg.stencil(a, sl);
-    pg.gemm(a, gl);
-  }
-  for (int t = cs.maxT - 2; t >= 0; --t) {
-    StencilList sl;
-    GemmList gl;
-    gl.mixed = mixed;
-    for (size_t c = 0; c < cs.size(); ++c) {
-      const Chain& ch = cs.chains[c];
-      if (t > ch.T - 2 || t < stop[c]) continue;
-      const double qo = cs.owner[c]->co.qo;
-      const int np = cs.np[c], nb = cs.nb[c];
-      const size_t blk = (size_t)np * np;
-      StencilTask s = stask(cs, c);
-      s.M = cs.pan[c][t + 1];
-      s.ldm = np;
-      s.alpha = qo;
-      s.out = cs.ytmp[c];
-      s.ldout = np;
-      s.ncols = n_k;
-      sl.add(s, np, nb);
-      gl.add(cs.S[c] + blk * t, cs.ytmp[c], cs.pan[c][t], cs.pan[c][t], np, n_k, np, np, np, np,
-             -1.0, 1.0, 1, 0, nb, nb);
-    }
-    pg.stencil(a, sl);
-    pg.gemm(a, gl);
-  }
-}
 
 rbmc_status check_info(const ChainSet& cs, rbmc_report* rep, const char* what, hipStream_t s) {
   for (size_t c = 0; c < cs.size(); ++c) {
@@ -1255,7 +1200,7 @@ rbmc_status factor_bj(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, rbmc_rep
   if (st != RBMC_OK) return st;
   cx->arenaA.clear();
   Program pg;
-  build_factor(cs, pg, cx->arenaA);
+  build_twosided(cs, pg, cx->arenaA, true);
   HIPCHK(cx->arenaA.upload(s));
   st = run(cx, pg, s, cx->arenaA);
   if (st != RBMC_OK) return st;
@@ -1322,7 +1267,7 @@ rbmc_status sample_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const H
         const int np = cs.np[cc], nb = cs.nb[cc];
         for (int t = 0; t < ch.T; ++t) {
           PanelTask pt{};
-          pt.P = (t == 0) ? cs.ytmp[cc] : cs.pan[cc][t];
+          pt.P = cs.pan[cc][t];
           pt.rg = cs.rg[cc];
           pt.dm = m->d_dm;
           pt.X = r + h.base[j];
@@ -1342,8 +1287,7 @@ rbmc_status sample_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const H
     }
   }
   gat.panels(ar, g);
-  std::vector<int> stop(cs.size(), 0);
-  build_solve(cs, nk, stop, pre, ar, o->precision == RBMC_MIXED);
+  build_twisted_solve(cs, nk, pre, ar, o->precision == RBMC_MIXED, true);
   sca.panels(ar, sc);
   HIPCHK(ar.upload(s));
   if (learned && cx->lws_len < h.total) {
