@@ -150,6 +150,7 @@ def batched_leg(n_models: int):
     from paper_2309_05435_amd import binding as B
     from paper_2309_05435_amd.inputs import batched_models
 
+    torch.cuda.empty_cache()  # the library allocates beside torch's cache
     wls = batched_models(n_models)
     ms = B.ModelSet(wls)
     zs = [torch.from_numpy(wl.z()).to("cuda") for wl in wls]

@@ -86,13 +86,13 @@ typedef struct {
 } rbmc_decomp_desc;
 
 /* Precision.  RBMC_FP64: every step in FP64.  RBMC_MIXED: the dense
- * products of the Takahashi sweep, of the correction solves and of the
- * preconditioner solves run on the FP32 matrix cores (operands rounded to
- * FP32, each K chunk of 16 summed in FP32 and accumulated in FP64); the
- * block-tridiagonal factorizations (inversions of the Schur complements),
- * the operators, the PCG inner products and residual updates and the final
- * diagonal/trace accumulation stay FP64.  PCG on the FP64 operator refines
- * the samples to pcg_rtol whatever the preconditioner's precision. */
+ * products of the correction solves run on the FP32 matrix cores (operands
+ * rounded to FP32, each K chunk of 16 summed in FP32 and accumulated in
+ * FP64); the block-tridiagonal factorizations (inversions of the Schur
+ * complements), the selected entries, the sampler (its preconditioner
+ * included: FP32-rounded solves would cost the exact chain preconditioner
+ * extra PCG iterations), the operators and the diagonal/trace accumulation
+ * stay FP64. */
 enum { RBMC_FP64 = 0, RBMC_MIXED = 1 };
 enum { RBMC_PC_BJ = 0, RBMC_PC_BJ_LEARNED = 1 };
 enum { RBMC_GRAD_LOGKAPPA = 1, RBMC_GRAD_LOGTAU = 2, RBMC_GRAD_RHO = 4, RBMC_GRAD_LOGSIGMA = 8 };

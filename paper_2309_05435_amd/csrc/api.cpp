@@ -110,11 +110,13 @@ struct rbmc_ctx {
   int device;
   hipStream_t stream;         // the caller's stream: all results are ordered on it
   // library streams of the overlapped estimate: the sampler and the
-  // corrections (work), the subdomain factorization (side, kept off
-  // `reserve_cus` compute units so the sampler's serial chain always finds a
-  // free CU) and the Takahashi sweep (side2, all CUs)
+  // corrections (work), the subdomain factorization (side) and the core
+  // steps (side2); the two side streams can be kept off `reserve_cus`
+  // compute units so the sampler's chain of dependent launches always finds
+  // free ones
   hipStream_t work = nullptr, side = nullptr, side2 = nullptr;
-  int reserve_cus = 0;  // measured on MI355X: no gain from reserving CUs (0/32/64 equal, 16 worse)
+  int reserve_cus = 0;
+  bool cu_masked = false;  // the side streams were created with a CU mask
   hipEvent_t join[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   Arena arenaA, arenaB;       // task lists of work on the caller's / side stream
   // concatenated sample-column workspace of the sampler (sized per call)
@@ -199,8 +201,16 @@ namespace {
 // A set of block-tridiagonal chains with their dense blocks and workspaces.
 // For one model the owner of every chain is that model; a batched call
 // concatenates the sets of many models.
-// widest outer Gauss-Jordan step (the sweep workspaces are sized for it)
+// Outer Gauss-Jordan step widths: rank-512 steps for batches of large blocks
+// (longer products, half the re-reads of the updated matrix; measured faster
+// than 256 on order-4096 blocks), 256 for batches of smaller blocks, 128 for
+// one to three blocks (a shorter chain of dependent launches).  A chain's
+// sweep workspaces are sized for the widest step its blocks take.
 constexpr int kSweepMax = 512;
+constexpr int kSweepWideFrom = 2048;  // smallest block order of a rank-512 batch
+inline int sweep_width_of(int np) {
+  return np >= kSweepWideFrom ? kSweepMax : std::min(256, np);
+}
 
 struct ChainSet {
   std::vector<Chain> chains;
@@ -363,7 +373,7 @@ rbmc_status alloc_chainset(rbmc_model* m, ChainSet& cs, const std::vector<Chain>
       cs.sig.push_back(nullptr);
       cs.sig2.push_back(nullptr);
     }
-    const size_t wmax = kSweepMax;
+    const size_t wmax = sweep_width_of(np);  // widest step on this block
     HIPCHK(m->pool.alloc((void**)&p, (size_t)np * wmax * 8));
     cs.gjU.push_back(p);
     HIPCHK(m->pool.alloc((void**)&p, (size_t)np * wmax * 8));
@@ -618,10 +628,12 @@ struct Program {
     pb.family = RBMC_KF_SPD_INVERSE;
     for (const InvJob& j : jobs) pb.alg_flops += (double)j.nb * j.nb * j.nb;
     ops.push_back(pb);
-    // batches: rank-512 outer steps (longer products, half the trailing
-    // re-reads; measured faster than 256); few blocks: 128 (shorter chain of
-    // dependent launches)
-    sweep(a, jobs, jobs.size() >= 4 ? kSweepMax : 128);
+    int w = 128;
+    if (jobs.size() >= 4) {
+      w = kSweepMax;
+      for (const InvJob& j : jobs) w = std::min(w, j.np >= kSweepWideFrom ? kSweepMax : 256);
+    }
+    sweep(a, jobs, w);
     Op pe;
     pe.kind = 11;
     ops.push_back(pe);
@@ -1287,7 +1299,9 @@ rbmc_status sample_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const H
     }
   }
   gat.panels(ar, g);
-  build_twisted_solve(cs, nk, pre, ar, o->precision == RBMC_MIXED, true);
+  // FP64 even under RBMC_MIXED: FP32-rounded solves cost the one-iteration
+  // exact chain preconditioner two more iterations
+  build_twisted_solve(cs, nk, pre, ar, 0, true);
   sca.panels(ar, sc);
   HIPCHK(ar.upload(s));
   if (learned && cx->lws_len < h.total) {
@@ -1421,7 +1435,6 @@ rbmc_status sample_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const H
 rbmc_status ensure_streams(rbmc_ctx* cx) {
   if (cx->work) return RBMC_OK;
   HIPCHK(hipStreamCreateWithFlags(&cx->work, hipStreamNonBlocking));
-  HIPCHK(hipStreamCreateWithFlags(&cx->side2, hipStreamNonBlocking));
   hipDeviceProp_t prop;
   HIPCHK(hipGetDeviceProperties(&prop, cx->device));
   const int ncu = prop.multiProcessorCount;
@@ -1431,13 +1444,16 @@ rbmc_status ensure_streams(rbmc_ctx* cx) {
     std::vector<uint32_t> mask((ncu + 31) / 32, 0u);
     for (int i = 0; i < ncu; ++i)
       if (i % stride != stride - 1 || i / stride >= r) mask[i / 32] |= 1u << (i % 32);
-    if (hipExtStreamCreateWithCUMask(&cx->side, (uint32_t)mask.size(), mask.data()) !=
-        hipSuccess) {
-      (void)hipGetLastError();
-      cx->side = nullptr;
-    }
+    for (hipStream_t* st : {&cx->side, &cx->side2})
+      if (hipExtStreamCreateWithCUMask(st, (uint32_t)mask.size(), mask.data()) != hipSuccess) {
+        (void)hipGetLastError();
+        *st = nullptr;
+      } else {
+        cx->cu_masked = true;
+      }
   }
   if (!cx->side) HIPCHK(hipStreamCreateWithFlags(&cx->side, hipStreamNonBlocking));
+  if (!cx->side2) HIPCHK(hipStreamCreateWithFlags(&cx->side2, hipStreamNonBlocking));
   for (hipEvent_t& e : cx->join) HIPCHK(hipEventCreate(&e));
   return RBMC_OK;
 }

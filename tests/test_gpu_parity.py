@@ -289,20 +289,31 @@ def test_mixed_precision_full_estimate():
 
 
 def test_mixed_gemm_ragged_shapes():
-    """The mixed product path on ragged sample counts (n_k not a multiple of the
-    tile): the sampler with mixed preconditioner solves still reaches the FP64
-    tolerance, and matches the exact sample."""
+    """The mixed product path on a ragged sample count (n_k = 37, not a
+    multiple of the tile), through the correction solves: the estimate agrees
+    with the FP64 one to the mixed-precision bar.  The sampler stays FP64 under
+    RBMC_MIXED: its samples equal the FP64 ones bit for bit."""
     wl = wl_of(14, 9, 3, 2, 1)
-    say("mixed sampler")
+    say("mixed ragged")
     M = oracle_model(wl)
     z = normals((37, M.n + M.n_obs), 31)
-    x_ref = M.sample(z)
     gm = B.Model(wl, pc=(1, 1, 1))
-    x = torch.empty((37, gm.n), dtype=torch.float64, device="cuda")
-    st, rep = B.rbmc_sample(gm.m, B.make_opts(37, 5000, 1e-13, precision=B.RBMC_MIXED),
-                            dev(z), x)
-    assert st == B.RBMC_OK
-    err = np.linalg.norm(x.cpu().numpy() - x_ref, axis=1) / np.linalg.norm(x_ref, axis=1)
-    say(f"mixed sampler: iters {rep.pcg_it_max} max err {err.max():.2e}")
+    xs = []
+    for prec in (B.RBMC_FP64, B.RBMC_MIXED):
+        x = torch.empty((37, gm.n), dtype=torch.float64, device="cuda")
+        st, rep = B.rbmc_sample(gm.m, B.make_opts(37, 5000, 1e-13, precision=prec), dev(z), x)
+        assert st == B.RBMC_OK
+        xs.append(x)
+    assert torch.equal(xs[0], xs[1])
+    x_ref = M.sample(z)
+    err = np.linalg.norm(xs[0].cpu().numpy() - x_ref, axis=1) / np.linalg.norm(x_ref, axis=1)
     assert err.max() < 1e-9
+    d64, tr64, st, _ = gm.estimate_from_samples(xs[0], grad_mask=0b1111)
+    assert st == B.RBMC_OK
+    ref = {"diag": d64.cpu().numpy(), "trace": np.array(tr64)}
+    o = B.make_opts(37, grad_mask=0b1111, precision=B.RBMC_MIXED)
+    dm = torch.empty_like(d64)
+    st, trm, rep = B.rbmc_estimate_from_samples(gm.m, o, xs[0], dm, 4)
+    assert st == B.RBMC_OK
+    check_mixed("mixed ragged", dm.cpu().numpy(), trm, ref, trace_condition(M))
     gm.close()
