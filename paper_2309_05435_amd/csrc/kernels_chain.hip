@@ -3,6 +3,8 @@
 // reductions that turn dense Q_AA^-1 blocks and correction panels into the
 // estimator's diagonal and trace contributions.  Every task carries its own
 // model and region pointers, so one launch serves chains of many models.
+#include <climits>
+
 #include "rbmc_impl.h"
 
 namespace rbmc {
@@ -146,66 +148,156 @@ void launch_extract(const ExtractTask* d_tasks, int n_tasks, int total_tiles, hi
 // one stencil pass) and scale = -q_o; only the 13 stencil neighbours c of
 // each core row a are formed.  They enter the traces exactly as k_extract's
 // off-diagonal slots do (sum over c of Q_s / K coefficient x entry).
-// One workgroup (16 waves) per 256 region rows; each wave forms the 13 dot
-// products of one row at a time, its lanes striding the shared index k.
+//
+// Workgroup = 256 region rows, one per thread.  The neighbour columns of the
+// 256 rows form one contiguous span [lo, hi] of W's columns (the region is
+// ordered by grid rows; a stencil reaches two grid rows up and down).  The
+// shared index k is walked in chunks of kOdK: the chunk of Sigma's 256
+// columns and of W's span is staged in LDS (coalesced 64-byte column pieces),
+// then each thread adds kOdK terms to its 13 dot products from LDS.  A tile
+// whose span exceeds kOdSpan streams its columns from global memory instead,
+// one wave per row.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_offdiag(const OffdiagTask* __restrict__ tasks,
-                                                  int n_tasks) {
-  __shared__ double red[2][16];
+namespace {
+constexpr int kOdK = 8, kOdLd = kOdK + 1, kOdSpan = 528;
+}
+
+__global__ __launch_bounds__(256) void k_offdiag(const OffdiagTask* __restrict__ tasks,
+                                                 int n_tasks) {
+  __shared__ double sg_s[256 * kOdLd];
+  __shared__ double w_s[kOdSpan * kOdLd];
+  __shared__ double red[2][256];
+  __shared__ int span_lo, span_hi;
   const int b = blockIdx.x;
   const OffdiagTask tk = tasks[find_task_of(tasks, n_tasks, b)];
   const RegionDev rg = *tk.rg;
   const DevModel& m = *tk.dm;
   const int chunk = b - tk.tile_start;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  double sq = 0.0, sk = 0.0;  // lane 0 of each wave
-  for (int r = wave; r < 256; r += 16) {
-    const int a = chunk * 256 + r;
-    if (a >= rg.nb || !rg.in_box[a]) continue;
-    int nbr[kNS];
+  const int tid = threadIdx.x;
+  const int a0 = chunk * 256, a = a0 + tid;
+  const bool row = a < rg.nb && rg.in_box[a];
+  int nbr[kNS];
+  int lo = INT_MAX, hi = -1;
 #pragma unroll
-    for (int q = 0; q < kNS; ++q) nbr[q] = rg.nbr[a * kNS + q];
-    double acc[kNS];
-#pragma unroll
-    for (int q = 0; q < kNS; ++q) acc[q] = 0.0;
-    const double* sg = tk.Sig + (size_t)a * tk.ld;
-    for (int k = lane; k < rg.nb; k += 64) {
-      const double sv = sg[k];
-#pragma unroll
-      for (int q = 0; q < kNS; ++q)
-        if (nbr[q] >= 0) acc[q] = fma(tk.W[(size_t)nbr[q] * tk.ld + k], sv, acc[q]);
-    }
-#pragma unroll
-    for (int q = 0; q < kNS; ++q)
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) acc[q] += __shfl_xor(acc[q], off, 64);
-    if (lane == 0) {
-      const int node = rg.nodes[a];
-#pragma unroll
-      for (int q = 0; q < kNS; ++q) {
-        if (nbr[q] < 0) continue;
-        const double v = tk.scale * acc[q];
-        sq += m.qs[(size_t)q * m.ns + node] * v;
-        if (q < kN5) sk += m.kk[(size_t)q * m.ns + node] * v;
-      }
+  for (int q = 0; q < kNS; ++q) {
+    nbr[q] = row ? rg.nbr[a * kNS + q] : -1;
+    if (nbr[q] >= 0) {
+      lo = min(lo, nbr[q]);
+      hi = max(hi, nbr[q]);
     }
   }
-  if (lane == 0) {
-    red[0][wave] = sq;
-    red[1][wave] = sk;
+  if (tid == 0) {
+    span_lo = INT_MAX;
+    span_hi = -1;
   }
   __syncthreads();
-  if (threadIdx.x < 3) {
-    double v = 0.0;
-    if (threadIdx.x > 0)
-      for (int w = 0; w < 16; ++w) v += red[threadIdx.x - 1][w];
-    tk.partial[((size_t)tk.out_index + chunk) * 3 + threadIdx.x] = v;
+  if (row) {
+    atomicMin(&span_lo, lo);
+    atomicMax(&span_hi, hi);
   }
+  __syncthreads();
+  const int slo = span_lo, span = span_hi - span_lo + 1;
+  double acc[kNS];
+#pragma unroll
+  for (int q = 0; q < kNS; ++q) acc[q] = 0.0;
+  const int nrows = min(256, rg.nb - a0);  // Sigma columns of this tile
+  if (span > 0 && span <= kOdSpan) {
+    for (int k0 = 0; k0 < rg.nb; k0 += kOdK) {
+      const int kc = min(kOdK, rg.nb - k0);
+      // all loads of a thread in flight at once: column tid / 8 + 32 i, k = tid % 8
+      constexpr int kSg = 256 * kOdK / 256, kW = (kOdSpan * kOdK + 255) / 256;
+      const int kk = tid % kOdK, c0 = tid / kOdK;
+      const bool kin = kk < kc;
+      double ls[kSg], lw[kW];
+#pragma unroll
+      for (int i = 0; i < kSg; ++i) {
+        const int col = c0 + 32 * i;
+        ls[i] = (kin && col < nrows) ? tk.Sig[(size_t)(a0 + col) * tk.ld + k0 + kk] : 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < kW; ++i) {
+        const int col = c0 + 32 * i;
+        lw[i] = (kin && col < span) ? tk.W[(size_t)(slo + col) * tk.ld + k0 + kk] : 0.0;
+      }
+      __syncthreads();  // the previous chunk is no longer read
+#pragma unroll
+      for (int i = 0; i < kSg; ++i) sg_s[(c0 + 32 * i) * kOdLd + kk] = ls[i];
+#pragma unroll
+      for (int i = 0; i < kW; ++i)
+        if (c0 + 32 * i < kOdSpan) w_s[(c0 + 32 * i) * kOdLd + kk] = lw[i];
+      __syncthreads();
+      if (row) {
+#pragma unroll
+        for (int kk = 0; kk < kOdK; ++kk) {
+          const double sv = sg_s[tid * kOdLd + kk];
+#pragma unroll
+          for (int q = 0; q < kNS; ++q)
+            if (nbr[q] >= 0) acc[q] = fma(w_s[(nbr[q] - slo) * kOdLd + kk], sv, acc[q]);
+        }
+      }
+    }
+  } else if (span > 0) {  // wide regions: one wave per row, columns from global memory
+    const int lane = tid & 63, wave = tid >> 6;
+    double accw[kNS];
+    for (int r = wave; r < nrows; r += 4) {
+      const int ar = a0 + r;
+      if (!rg.in_box[ar]) continue;
+      int nb2[kNS];
+#pragma unroll
+      for (int q = 0; q < kNS; ++q) {
+        nb2[q] = rg.nbr[ar * kNS + q];
+        accw[q] = 0.0;
+      }
+      const double* sg = tk.Sig + (size_t)ar * tk.ld;
+      for (int k = lane; k < rg.nb; k += 64) {
+        const double sv = sg[k];
+#pragma unroll
+        for (int q = 0; q < kNS; ++q)
+          if (nb2[q] >= 0) accw[q] = fma(tk.W[(size_t)nb2[q] * tk.ld + k], sv, accw[q]);
+      }
+#pragma unroll
+      for (int q = 0; q < kNS; ++q) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) accw[q] += __shfl_xor(accw[q], off, 64);
+      }
+      // row ar's sums go to its own thread (tid = r) through LDS
+      if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < kNS; ++q) w_s[r * kNS + q] = accw[q];
+    }
+    __syncthreads();
+    if (row)
+#pragma unroll
+      for (int q = 0; q < kNS; ++q) acc[q] = w_s[tid * kNS + q];
+  }
+  double sq = 0.0, sk = 0.0;
+  if (row) {
+    const int node = rg.nodes[a];
+#pragma unroll
+    for (int q = 0; q < kNS; ++q) {
+      if (nbr[q] < 0) continue;
+      const double v = tk.scale * acc[q];
+      sq += m.qs[(size_t)q * m.ns + node] * v;
+      if (q < kN5) sk += m.kk[(size_t)q * m.ns + node] * v;
+    }
+  }
+  red[0][tid] = sq;
+  red[1][tid] = sk;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (tid < st) {
+      red[0][tid] += red[0][tid + st];
+      red[1][tid] += red[1][tid + st];
+    }
+    __syncthreads();
+  }
+  if (tid < 3)
+    tk.partial[((size_t)tk.out_index + chunk) * 3 + tid] = tid == 0 ? 0.0 : red[tid - 1][0];
 }
 
 void launch_offdiag(const OffdiagTask* d_tasks, int n_tasks, int total_tiles, hipStream_t s) {
   if (total_tiles <= 0) return;
-  k_offdiag<<<total_tiles, 1024, 0, s>>>(d_tasks, n_tasks);
+  k_offdiag<<<total_tiles, 256, 0, s>>>(d_tasks, n_tasks);
 }
 
 // ---------------------------------------------------------------------------
