@@ -3,7 +3,7 @@
 A step is one full estimate on the 64 x 64 x 32 space-time workload
 (n = 131,072, 500 samples, 16 time slabs, 2-hop overlap, PCG to 1e-8):
 rebuild Q(theta), sample x = Q^-1 F z by block-Jacobi PCG, factor every
-overlapping subdomain, run the Takahashi sweep, the correction solves and
+overlapping subdomain, form the selected inverse entries, the correction solves and
 the trace/diagonal accumulation.  Inputs (z) are resident in HBM before the
 timed region.  Prints one JSON line.
 
@@ -185,7 +185,7 @@ def batched_leg(n_models: int):
                 "per_model_calls": {"value": n_tot / sec_e, "ms_per_step": sec_e * 1e3},
                 "speedup": sec_e / sec_b, "max_rel_diff_vs_per_model": dev,
                 "err_estimate": rep.err_estimate, "pcg_iters_max": rep.pcg_it_max,
-                "phase_s": {k: getattr(rep, k) for k in ("t_sample", "t_factor", "t_takahashi",
+                "phase_s": {k: getattr(rep, k) for k in ("t_sample", "t_factor", "t_select",
                                                          "t_correct", "t_total")},
                 "device_bytes": rep.peak_bytes})
     ms.close()
@@ -357,7 +357,7 @@ def main():
         "pcg_iters": {"mean": last["pcg_it_mean"], "max": last["pcg_it_max"]},
         "err_estimate": last["err_estimate"],
         "accuracy_gate_1pct": bool(last["err_estimate"] <= 0.01),
-        "phase_s": {k: last[k] for k in ("t_sample", "t_factor", "t_takahashi", "t_correct",
+        "phase_s": {k: last[k] for k in ("t_sample", "t_factor", "t_select", "t_correct",
                                          "t_total")},
         "kernel_ms_per_step": {k: v["total_ms"] / args.steps for k, v in stats.items()},
         "roofline": roof,
@@ -366,7 +366,7 @@ def main():
     }
     if not args.no_variants:
         # RBMC_MIXED on the same model and samples: FP32 matrix-core products in
-        # the Takahashi sweep and the solves; error stated against the FP64 run
+        # the correction solves; error stated against the FP64 run
         d64 = diag.clone()
         t64 = list(tr)
         om = B.make_opts(wl.n_k, pcg_maxit=5000, pcg_rtol=wl.rtol, grad_mask=grad,
@@ -390,7 +390,7 @@ def main():
             "mean_rel_err_diag_vs_fp64": float(((dm - d64).abs() / d64).mean()),
             "rel_err_traces_vs_fp64": [abs(a - b) / abs(b) for a, b in zip(trm, t64)],
             "pcg_iters": {"mean": rpm.pcg_it_mean, "max": rpm.pcg_it_max},
-            "phase_s": {k: getattr(rpm, k) for k in ("t_sample", "t_factor", "t_takahashi",
+            "phase_s": {k: getattr(rpm, k) for k in ("t_sample", "t_factor", "t_select",
                                                      "t_correct", "t_total")},
             "kernel_ms": {k: v["total_ms"] for k, v in sm.items()},
             "gemm_mixed_tflops": (g["alg_flops"] / (g["total_ms"] * 1e-3) / 1e12

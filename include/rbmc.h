@@ -109,7 +109,7 @@ typedef struct {
 } rbmc_est_opts;
 
 typedef struct {
-  double t_sample, t_factor, t_takahashi, t_correct, t_total; /* seconds */
+  double t_sample, t_factor, t_select, t_correct, t_total; /* seconds; t_select: core steps */
   int32_t pcg_it_max;      /* iterations of the slowest sample */
   double pcg_it_mean;      /* mean iterations over samples */
   double max_rel_residual; /* max_k ||b_k - Q x_k|| / ||b_k|| (recurrence) */
@@ -122,11 +122,11 @@ typedef struct {
  * = the default stream).  The stream is not owned.
  * Scheduling of rbmc_estimate / rbmc_estimate_batched (environment, read
  * here): by default the sampler and the corrections run on one library
- * stream, the subdomain factorization on a second one (which can be kept
- * off RBMC_RESERVE_CUS compute units, default 0), and the Takahashi sweep on
- * a third; the factorization and
- * sweep are enqueued by their own host thread, and the given stream waits
- * for all of it.  RBMC_OVERLAP=0 runs everything one step after the other on
+ * stream, the subdomain factorization on a second and the core steps
+ * (selected inverse entries) on a third (both can be kept off
+ * RBMC_RESERVE_CUS compute units, default 0); the factorization and the
+ * core steps are enqueued by their own host thread, and the given stream
+ * waits for all of it.  RBMC_OVERLAP=0 runs everything one step after the other on
  * the given stream; RBMC_LAUNCH_THREADS=1 enqueues all streams from the
  * calling thread. */
 rbmc_status rbmc_ctx_create(int device, void* hip_stream, rbmc_ctx** out);

@@ -72,7 +72,7 @@ class rbmc_pc_info(C.Structure):
 
 
 class rbmc_report(C.Structure):
-    _fields_ = [("t_sample", C.c_double), ("t_factor", C.c_double), ("t_takahashi", C.c_double),
+    _fields_ = [("t_sample", C.c_double), ("t_factor", C.c_double), ("t_select", C.c_double),
                 ("t_correct", C.c_double), ("t_total", C.c_double), ("pcg_it_max", C.c_int32),
                 ("pcg_it_mean", C.c_double), ("max_rel_residual", C.c_double),
                 ("err_estimate", C.c_double), ("peak_bytes", C.c_int64),

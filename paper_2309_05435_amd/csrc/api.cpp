@@ -1,6 +1,6 @@
 // C ABI of the RBMC library and the host-side runtime that sequences the
 // kernels: block-tridiagonal factorization of every chain (block-Jacobi blocks
-// and RBMC subdomains), the Takahashi sweep, the correction solves and the
+// and RBMC subdomains), the selected inverse entries, the correction solves and the
 // preconditioned conjugate-gradient sampler.
 //
 // Everything runs on *sets* of models: one model for the single-model calls,
@@ -141,7 +141,7 @@ struct rbmc_ctx {
   size_t epart_len = 0;
   Pool epool;
   // scheduling of rbmc_estimate*: overlap the sampler with the subdomain
-  // factorization + Takahashi sweep on a second stream (else one after the
+  // factorization + core steps on further streams (else one after the
   // other on the context stream), and enqueue the two streams from two host
   // threads (else from one)
   bool overlap = true;
@@ -1460,7 +1460,7 @@ rbmc_status ensure_streams(rbmc_ctx* cx) {
 
 // The estimator from samples for a set of models.  x_base: the samples in the
 // column layout h (ignored when n_k = 0).  The subdomain factorization and the
-// Takahashi sweep do not need the samples: when `sampler` is given they run on
+// core steps do not need the samples: when `sampler` is given they run on
 // the side stream while sampler() produces x on the caller's stream, and the
 // two streams join before the correction solves.
 rbmc_status estimate_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const HostCols& h,
@@ -1659,7 +1659,7 @@ rbmc_status estimate_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const
     e_tak = cx->join[3];
     HIPCHK(hipEventRecord(e_beg, s));
   }
-  // factorization + Takahashi on stream s; with a sampler they are enqueued
+  // factorization on stream s and the core steps on sT; with a sampler they are enqueued
   // by a second host thread, so neither stream waits for the host to finish
   // enqueuing the other's launches (a stream's queue fills up long before
   // thousands of launches are placed, and placing then blocks).
@@ -1782,7 +1782,7 @@ rbmc_status estimate_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const
     rep->err_estimate =
         nk > 0 ? std::sqrt(2.0 / M_PI) * std::sqrt(2.0 / nk) * ratio_sum / (double)n_total : 0.0;
     rep->t_factor = ms_fac * 1e-3;
-    rep->t_takahashi = ms_tak * 1e-3;
+    rep->t_select = ms_tak * 1e-3;
     rep->t_correct = t3 - t2;
     int64_t bytes = cx->ws.bytes + cx->epool.bytes;
     for (rbmc_model* m : ms) bytes += m->pool.bytes + m->work.bytes;
@@ -2210,7 +2210,7 @@ rbmc_status check_models(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms) {
   return RBMC_OK;
 }
 
-// Full path over a set: sample (caller's stream) || factor + Takahashi (side
+// Full path over a set: sample (caller's stream) || factor + core steps (side
 // stream), then corrections.  z_ptrs: per model (n + n_obs) x n_k.
 rbmc_status estimate_full(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms,
                           const rbmc_est_opts* opts, const std::vector<const double*>& z_ptrs,

@@ -222,8 +222,8 @@ def test_error_codes():
     B.rbmc_ctx_destroy(ctx)
 
 
-# Mixed precision: FP32 matrix-core products in the Takahashi sweep and the
-# solves, FP64 factorizations.  Every entry of Q_AA^-1 and of the corrections
+# Mixed precision: FP32 matrix-core products in the correction solves, FP64
+# factorizations.  Every entry of Q_AA^-1 and of the corrections
 # then carries a relative error of about 1e-6 (operand rounding to FP32), so
 # the bar is 1e-5 relative per diagonal entry and, for a trace
 # sum_ik S_ik (dQ_j)_ik, 1e-5 times its condition number
