@@ -141,7 +141,14 @@ def cpu_baseline(wl, m_sample: int):
                        f"(n={sub.n}, {sub.n_k} samples), {dt:.1f} s")}
 
 
-def batched_leg(n_models: int):
+def tune_dict(r):
+    return {"small_k": r.best.small_k, "small_tiles": r.best.small_tiles,
+            "wide_from": r.best.wide_from, "ms": r.best_ms,
+            "default_ms": r.default_ms if not r.from_cache else None,
+            "from_cache": bool(r.from_cache), "candidates": r.n_candidates}
+
+
+def batched_leg(n_models: int, tune_cache=None):
     """The uneven-model workload (grids 16^2-48^2, T 8-24, 2-8 slabs, 1-step
     overlap, 100 samples): all models in one rbmc_estimate_batched call against
     the same models estimated one call each.  Each timing follows a warm-up."""
@@ -154,9 +161,15 @@ def batched_leg(n_models: int):
     wls = batched_models(n_models)
     ms = B.ModelSet(wls)
     zs = [torch.from_numpy(wl.z()).to("cuda") for wl in wls]
+    tune = None
+    if tune_cache is not None:
+        tr_ = B.rbmc_autotune(ms.ctx, ms.models,
+                              B.make_opts(wls[0].n_k, pcg_maxit=5000, pcg_rtol=wls[0].rtol),
+                              zs, tune_cache)
+        tune = tune_dict(tr_)
     n_tot = sum(ms.n)
     res = {"workload": f"{n_models} uneven models, sum n = {n_tot}", "n_models": n_models,
-           "n_samples": wls[0].n_k}
+           "n_samples": wls[0].n_k, "tune": tune}
 
     def timed(fn):
         fn()
@@ -216,6 +229,11 @@ def main():
                     help="run only the batched workload and print its JSON")
     ap.add_argument("--calibration-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter calibration)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch shapes (no rbmc_autotune before timing)")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2309_05435_amd",
+                                                          "tune_cache.txt"),
+                    help="autotuner cache file (read, and appended to when a workload is new)")
     ap.add_argument("--traffic-from", nargs=4, metavar="CSV",
                     help="write profiles/traffic_*.json from the counter CSVs of the bench "
                          "(FETCH_SIZE, WRITE_SIZE) and of the calibration copy (same order)")
@@ -237,7 +255,8 @@ def main():
         calibration_copy(args.calibration_copy)
         return
     if args.batched_only:
-        print(json.dumps(batched_leg(args.batched_models)), flush=True)
+        print(json.dumps(batched_leg(args.batched_models,
+                                     None if args.no_autotune else args.tune_cache)), flush=True)
         return
 
     from paper_2309_05435_amd import binding as B
@@ -277,6 +296,12 @@ def main():
         torch.cuda.synchronize()
         return (time.perf_counter() - t) / reps, rp.as_dict()
 
+    tune = None
+    if not args.no_autotune:
+        # launch shapes chosen by the autotuner (end-to-end timing of this
+        # workload, or its cached choice), outside the timed steps
+        tr_ = B.rbmc_autotune(gm.ctx, [gm.m], opts, [z], args.tune_cache)
+        tune = tune_dict(tr_)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -363,6 +388,7 @@ def main():
         "roofline": roof,
         "rooflines_other_kernels": others,
         "cpu_baseline": None,
+        "tune": tune,
     }
     if not args.no_variants:
         # RBMC_MIXED on the same model and samples: FP32 matrix-core products in
@@ -431,7 +457,8 @@ def main():
             out["variant_learned"] = {"error": str(e)}
     if not args.no_batched:
         try:
-            out["batched"] = batched_leg(args.batched_models)
+            out["batched"] = batched_leg(args.batched_models,
+                                         None if args.no_autotune else args.tune_cache)
         except B.RbmcError as e:  # e.g. device memory: report, keep the main line
             out["batched"] = {"error": str(e)}
     if not args.no_cpu_baseline:

@@ -201,6 +201,44 @@ rbmc_status rbmc_estimate_batched(rbmc_ctx* ctx, int32_t n_models, rbmc_model* c
                                   double* const* diag_out, double* const* trace_out,
                                   rbmc_report* rep);
 
+/* Launch-shape choices of a context (not part of the method; results differ
+ * only by rounding).  Products with K <= small_k, or launches with fewer
+ * than small_tiles 128 x 128 tiles, use the 64 x 64-tile FP64 GEMM; batches
+ * of at least four blocks, all of order >= wide_from, take rank-512
+ * Gauss-Jordan steps (else 256; one to three blocks: 128).  Defaults 256,
+ * 768, 2048.  RBMC_E_ARG if small_k or small_tiles < 0 or wide_from < 2048
+ * (the sweep workspaces are sized for rank 512 from order 2048). */
+typedef struct {
+  int32_t small_k, small_tiles, wide_from;
+} rbmc_tune;
+rbmc_status rbmc_ctx_get_tune(rbmc_ctx* ctx, rbmc_tune* t);
+rbmc_status rbmc_ctx_set_tune(rbmc_ctx* ctx, const rbmc_tune* t);
+
+typedef struct {
+  rbmc_tune best;        /* the choice now in force on the context */
+  double best_ms;        /* its time for one estimate (ms) */
+  double default_ms;     /* the defaults' time (ms; -1 when read from the cache) */
+  int32_t from_cache;    /* 1: read from the cache, no runs */
+  int32_t n_candidates;  /* configurations timed */
+  int32_t cache_written; /* 1: a line was appended to the cache */
+} rbmc_tune_report;
+
+/* Autotuner: times rbmc_estimate_batched(ctx, n_models, models, opts, z, ...)
+ * end to end (factorizations included: every model's factors are redone)
+ * for each candidate (small_k in {256, 512} x small_tiles in {768, 1536} x
+ * wide_from in {2048, never}), one warm-up and one timed run each, and keeps
+ * the fastest on the context.  The end-to-end time is what counts: a faster
+ * factorization can slow the overlapped step.  cache_path (may be NULL): a
+ * text file with one line per tuned workload (key, small_k, small_tiles,
+ * wide_from, ms, signature), the key a hash of the device architecture, the
+ * options and every model's grid and decomposition; a matching line is used
+ * without any run, a new result is appended.  The models' outputs are left
+ * undefined (the runs write to scratch buffers); z as for
+ * rbmc_estimate_batched. */
+rbmc_status rbmc_autotune(rbmc_ctx* ctx, int32_t n_models, rbmc_model* const* models,
+                          const rbmc_est_opts* opts, const double* const* z, const char* cache_path,
+                          rbmc_tune_report* out);
+
 /* Learned correction of the block-Jacobi preconditioner (used when
  * opts->precond = RBMC_PC_BJ_LEARNED; not part of the paper's method).  With
  * u = M_BJ^-1 r and v = N_w(r, u), the preconditioned residual becomes

@@ -26,7 +26,7 @@ EXPORTS = ["rbmc_ctx_create", "rbmc_ctx_destroy", "rbmc_model_create", "rbmc_mod
            "rbmc_estimate", "rbmc_estimate_batched", "rbmc_plan_query", "rbmc_ctx_profile",
            "rbmc_ctx_profile_read", "rbmc_precond_train", "rbmc_precond_apply",
            "rbmc_precond_get_weights", "rbmc_precond_set_weights", "rbmc_precond_info",
-           "rbmc_last_error"]
+           "rbmc_ctx_get_tune", "rbmc_ctx_set_tune", "rbmc_autotune", "rbmc_last_error"]
 RBMC_PC_NWEIGHTS = 15120
 # (cin, cout) of the learned correction's four convolutions, in weight order
 PC_LAYERS = [(2, 16), (16, 16), (16, 16), (16, 1)]
@@ -63,6 +63,16 @@ class rbmc_est_opts(C.Structure):
 class rbmc_train_opts(C.Structure):
     _fields_ = [("n_pairs", C.c_int32), ("epochs", C.c_int32), ("batch", C.c_int32),
                 ("lr", C.c_float), ("seed", C.c_uint64)]
+
+
+class rbmc_tune(C.Structure):
+    _fields_ = [("small_k", C.c_int32), ("small_tiles", C.c_int32), ("wide_from", C.c_int32)]
+
+
+class rbmc_tune_report(C.Structure):
+    _fields_ = [("best", rbmc_tune), ("best_ms", C.c_double), ("default_ms", C.c_double),
+                ("from_cache", C.c_int32), ("n_candidates", C.c_int32),
+                ("cache_written", C.c_int32)]
 
 
 class rbmc_pc_info(C.Structure):
@@ -121,6 +131,10 @@ def lib():
         L.rbmc_precond_apply.argtypes = [vp, vp, vp, vp, C.c_int32]
         L.rbmc_precond_get_weights.argtypes = [vp, C.POINTER(C.c_float)]
         L.rbmc_precond_info.argtypes = [vp, C.POINTER(rbmc_pc_info)]
+        L.rbmc_ctx_get_tune.argtypes = [vp, C.POINTER(rbmc_tune)]
+        L.rbmc_ctx_set_tune.argtypes = [vp, C.POINTER(rbmc_tune)]
+        L.rbmc_autotune.argtypes = [vp, C.c_int32, C.POINTER(vp), C.POINTER(rbmc_est_opts),
+                                    C.POINTER(vp), C.c_char_p, C.POINTER(rbmc_tune_report)]
         L.rbmc_precond_set_weights.argtypes = [vp, C.POINTER(C.c_float)]
         L.rbmc_last_error.restype = C.c_char_p
         for name in EXPORTS:
@@ -231,6 +245,29 @@ def rbmc_precond_get_weights(m):
     w = np.zeros(RBMC_PC_NWEIGHTS, np.float32)
     check(lib().rbmc_precond_get_weights(m, w.ctypes.data_as(C.POINTER(C.c_float))))
     return w
+
+
+def rbmc_ctx_get_tune(ctx):
+    t = rbmc_tune()
+    check(lib().rbmc_ctx_get_tune(ctx, C.byref(t)))
+    return t
+
+
+def rbmc_ctx_set_tune(ctx, small_k, small_tiles, wide_from):
+    return check(lib().rbmc_ctx_set_tune(ctx, C.byref(rbmc_tune(small_k, small_tiles, wide_from))))
+
+
+def rbmc_autotune(ctx, models, opts, zs, cache_path=None):
+    """models: model handles of one context; zs: per model (n + n_obs) x n_k device
+    tensors (None entries when n_k = 0).  Returns an rbmc_tune_report."""
+    nm = len(models)
+    vp = C.c_void_p
+    mh = (vp * max(nm, 1))(*[m.value for m in models])
+    zp = (vp * max(nm, 1))(*[None if z is None else z.data_ptr() for z in zs])
+    rep = rbmc_tune_report()
+    check(lib().rbmc_autotune(ctx, nm, mh, C.byref(opts), zp,
+                              cache_path.encode() if cache_path else None, C.byref(rep)))
+    return rep
 
 
 def rbmc_precond_info(m):

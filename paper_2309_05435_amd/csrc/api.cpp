@@ -12,10 +12,13 @@
 #include <cstdlib>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <functional>
+#include <fstream>
 #include <mutex>
 #include <random>
+#include <sstream>
 #include <string>
 #include <thread>
 #include <vector>
@@ -106,6 +109,29 @@ struct ProfRec {
 
 }  // namespace
 
+// Outer Gauss-Jordan step widths: rank-512 steps for batches of large blocks
+// (longer products, half the re-reads of the updated matrix; measured faster
+// than 256 on order-4096 blocks), 256 for batches of smaller blocks, 128 for
+// one to three blocks (a shorter chain of dependent launches).  A chain's
+// sweep workspaces are sized for the widest step its blocks take.
+constexpr int kSweepMax = 512;
+constexpr int kSweepWideFrom = 2048;  // smallest block order with rank-512 workspaces
+inline int sweep_width_of(int np) {
+  return np >= kSweepWideFrom ? kSweepMax : std::min(256, np);
+}
+
+// Launch-shape choices that the autotuner sets per context (rbmc_autotune):
+// products with K <= small_k or fewer than small_tiles 128-tiles use the
+// 64 x 64-tile GEMM; batches whose blocks all have order >= wide_from take
+// rank-512 sweep steps (wide_from >= kSweepWideFrom, the workspace bound).
+struct Tune {
+  int small_k = 256;
+  int small_tiles = 768;
+  int wide_from = kSweepWideFrom;
+};
+// the tuning in force while programs are built on this thread
+thread_local Tune g_tune;
+
 struct rbmc_ctx {
   int device;
   hipStream_t stream;         // the caller's stream: all results are ordered on it
@@ -117,6 +143,7 @@ struct rbmc_ctx {
   hipStream_t work = nullptr, side = nullptr, side2 = nullptr;
   int reserve_cus = 0;
   bool cu_masked = false;  // the side streams were created with a CU mask
+  Tune tune;               // launch-shape choices (rbmc_autotune / rbmc_ctx_set_tune)
   hipEvent_t join[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   Arena arenaA, arenaB;       // task lists of work on the caller's / side stream
   // concatenated sample-column workspace of the sampler (sized per call)
@@ -201,16 +228,6 @@ namespace {
 // A set of block-tridiagonal chains with their dense blocks and workspaces.
 // For one model the owner of every chain is that model; a batched call
 // concatenates the sets of many models.
-// Outer Gauss-Jordan step widths: rank-512 steps for batches of large blocks
-// (longer products, half the re-reads of the updated matrix; measured faster
-// than 256 on order-4096 blocks), 256 for batches of smaller blocks, 128 for
-// one to three blocks (a shorter chain of dependent launches).  A chain's
-// sweep workspaces are sized for the widest step its blocks take.
-constexpr int kSweepMax = 512;
-constexpr int kSweepWideFrom = 2048;  // smallest block order of a rank-512 batch
-inline int sweep_width_of(int np) {
-  return np >= kSweepWideFrom ? kSweepMax : std::min(256, np);
-}
 
 struct ChainSet {
   std::vector<Chain> chains;
@@ -431,7 +448,6 @@ rbmc_status ensure_panels(rbmc_model* m, int n_k) {
 // A launch with fewer 128-tiles than this runs the 64 x 64-tile FP64 kernel
 // (two workgroups per CU on 128-tiles would leave most of the device idle or
 // latency-bound).
-constexpr int kSmallGemmTiles = 768;
 
 struct GemmList {
   std::vector<GemmTask> v;  // tile_start / tiles_n are set when the list is launched
@@ -477,7 +493,7 @@ struct GemmList {
     // measured on MI355X: the 64-tile kernel is faster for short K (<= 256)
     // at any tile count, and whenever the 128-tiles would not fill the device
     *kind = mixed ? kGemmMixed
-                  : ((t128 < kSmallGemmTiles || kmax <= 256) ? kGemmSmall : kGemmF64);
+                  : ((t128 < g_tune.small_tiles || kmax <= g_tune.small_k) ? kGemmSmall : kGemmF64);
     const int ts = (*kind == kGemmSmall) ? 64 : 128;
     int tiles = 0;
     for (GemmTask& t : v) {
@@ -631,7 +647,7 @@ struct Program {
     int w = 128;
     if (jobs.size() >= 4) {
       w = kSweepMax;
-      for (const InvJob& j : jobs) w = std::min(w, j.np >= kSweepWideFrom ? kSweepMax : 256);
+      for (const InvJob& j : jobs) w = std::min(w, j.np >= g_tune.wide_from ? kSweepMax : 256);
     }
     sweep(a, jobs, w);
     Op pe;
@@ -1204,6 +1220,7 @@ ColSet colset(rbmc_ctx* cx, const HostCols& h) {
 // Factor the block-Jacobi chains of every model that needs it (one program).
 rbmc_status factor_bj(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, rbmc_report* rep,
                       hipStream_t s) {
+  g_tune = cx->tune;
   ChainSet cs;
   for (rbmc_model* m : ms)
     if (!m->bj_ready) cs.append(m->bj);
@@ -1240,6 +1257,7 @@ using SampleHook = std::function<rbmc_status(int it, const double* x, const doub
 rbmc_status sample_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const HostCols& h,
                        const rbmc_est_opts* o, const double* z, double* x, rbmc_report* rep,
                        hipStream_t s, const SampleHook& hook = {}) {
+  g_tune = cx->tune;
   const int nk = o->n_samples;
   double t0 = now_s();
   // the learned correction makes the preconditioner nonlinear: flexible
@@ -1468,6 +1486,7 @@ rbmc_status estimate_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const
                          const std::vector<double*>& diag_out,
                          const std::vector<double*>& trace_out, rbmc_report* rep,
                          const std::function<rbmc_status()>& sampler) {
+  g_tune = cx->tune;
   const int nk = o->n_samples;
   const int mixed = o->precision == RBMC_MIXED;
   if (sampler) {
@@ -2260,6 +2279,56 @@ rbmc_status estimate_full(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms,
 // ---------------------------------------------------------------------------
 // ABI
 // ---------------------------------------------------------------------------
+namespace {
+// workload signature of an autotuning: device, options, every model's grid
+// and decomposition
+std::string tune_signature(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms,
+                           const rbmc_est_opts* o) {
+  hipDeviceProp_t prop;
+  std::ostringstream os;
+  if (hipGetDeviceProperties(&prop, cx->device) == hipSuccess) os << prop.gcnArchName;
+  os << "|nk" << o->n_samples << " prec" << o->precision << " pc" << o->precond << " g"
+     << o->grad_mask;
+  for (const rbmc_model* m : ms) {
+    const rbmc_decomp_desc& d = m->dc;
+    os << "|" << m->plan.mx << "x" << m->plan.my << "x" << m->plan.T << " " << d.n_tslabs << ","
+       << d.n_tiles_x << "," << d.n_tiles_y << "," << d.overlap_hops << " " << d.pc_tslabs << ","
+       << d.pc_tiles_x << "," << d.pc_tiles_y;
+  }
+  return os.str();
+}
+
+std::string tune_key(const std::string& sig) {  // FNV-1a, 64 bit
+  uint64_t h = 1469598103934665603ull;
+  for (unsigned char c : sig) {
+    h ^= c;
+    h *= 1099511628211ull;
+  }
+  char buf[17];
+  std::snprintf(buf, sizeof buf, "%016llx", (unsigned long long)h);
+  return buf;
+}
+
+// cache line: <key> <small_k> <small_tiles> <wide_from> <best_ms> <signature>
+bool tune_cache_lookup(const char* path, const std::string& key, Tune* t, double* ms) {
+  if (!path) return false;
+  std::ifstream f(path);
+  std::string line;
+  while (std::getline(f, line)) {
+    std::istringstream is(line);
+    std::string k;
+    Tune v;
+    double b = 0.0;
+    if (!(is >> k >> v.small_k >> v.small_tiles >> v.wide_from >> b) || k != key) continue;
+    if (v.small_k < 0 || v.small_tiles < 0 || v.wide_from < kSweepWideFrom) continue;
+    *t = v;
+    *ms = b;
+    return true;
+  }
+  return false;
+}
+}  // namespace
+
 extern "C" {
 
 const char* rbmc_last_error(void) { return g_err.c_str(); }
@@ -2564,6 +2633,105 @@ rbmc_status rbmc_estimate_batched(rbmc_ctx* ctx, int32_t n_models, rbmc_model* c
   st = estimate_full(ctx, ms, opts, zp, dp, tp, rep);
   if (rep) rep->t_total = now_s() - t0;
   return st;
+}
+
+rbmc_status rbmc_ctx_get_tune(rbmc_ctx* ctx, rbmc_tune* t) {
+  if (!ctx || !t) return fail(RBMC_E_ARG, "NULL argument");
+  t->small_k = ctx->tune.small_k;
+  t->small_tiles = ctx->tune.small_tiles;
+  t->wide_from = ctx->tune.wide_from;
+  return RBMC_OK;
+}
+
+rbmc_status rbmc_ctx_set_tune(rbmc_ctx* ctx, const rbmc_tune* t) {
+  if (!ctx || !t) return fail(RBMC_E_ARG, "NULL argument");
+  if (t->small_k < 0 || t->small_tiles < 0 || t->wide_from < kSweepWideFrom)
+    return fail(RBMC_E_ARG, "small_k and small_tiles must be >= 0, wide_from >= 2048");
+  ctx->tune.small_k = t->small_k;
+  ctx->tune.small_tiles = t->small_tiles;
+  ctx->tune.wide_from = t->wide_from;
+  return RBMC_OK;
+}
+
+
+rbmc_status rbmc_autotune(rbmc_ctx* ctx, int32_t n_models, rbmc_model* const* models,
+                          const rbmc_est_opts* opts, const double* const* z, const char* cache_path,
+                          rbmc_tune_report* out) {
+  if (!ctx || n_models < 1 || !models || !opts) return fail(RBMC_E_ARG, "NULL argument or no model");
+  std::vector<rbmc_model*> ms(models, models + n_models);
+  rbmc_status st = check_models(ctx, ms);
+  if (st != RBMC_OK) return st;
+  st = check_opts(opts, true);
+  if (st != RBMC_OK) return st;
+  HIPCHK(hipSetDevice(ctx->device));
+  rbmc_tune_report rep{};
+  const std::string sig = tune_signature(ctx, ms, opts), key = tune_key(sig);
+  Tune cached;
+  double cached_ms = 0.0;
+  if (tune_cache_lookup(cache_path, key, &cached, &cached_ms)) {
+    ctx->tune = cached;
+    rep.best = rbmc_tune{cached.small_k, cached.small_tiles, cached.wide_from};
+    rep.best_ms = cached_ms;
+    rep.default_ms = -1.0;
+    rep.from_cache = 1;
+    if (out) *out = rep;
+    return RBMC_OK;
+  }
+  // outputs of the timed runs (device diagonals, host traces)
+  std::vector<double*> dp(n_models, nullptr), tp(n_models, nullptr);
+  std::vector<std::vector<double>> th(n_models, std::vector<double>(4));
+  Pool tmp;
+  struct Release {
+    Pool& p;
+    ~Release() { p.release(); }
+  } rel{tmp};
+  for (int j = 0; j < n_models; ++j) {
+    HIPCHK(tmp.alloc((void**)&dp[j], (size_t)ms[j]->plan.n * 8));
+    tp[j] = th[j].data();
+  }
+  std::vector<Tune> cands;
+  for (int wide : {kSweepWideFrom, INT_MAX})
+    for (int sk : {256, 512})
+      for (int stl : {768, 1536}) cands.push_back(Tune{sk, stl, wide});
+  const Tune keep = ctx->tune;
+  double best = 1e300;
+  Tune best_t = cands[0];
+  for (size_t i = 0; i < cands.size(); ++i) {
+    ctx->tune = cands[i];
+    double tmin = 1e300;
+    for (int r = 0; r < 2; ++r) {  // a warm-up run, then a timed one
+      for (rbmc_model* m : ms) m->bj_ready = m->sub_ready = false;
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+      const double t0 = now_s();
+      st = rbmc_estimate_batched(ctx, n_models, models, opts, z, dp.data(),
+                                 opts->grad_mask ? tp.data() : nullptr, nullptr);
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+      if (st < 0) {
+        ctx->tune = keep;
+        return st;
+      }
+      if (r > 0) tmin = std::min(tmin, now_s() - t0);
+    }
+    if (i == 0) rep.default_ms = tmin * 1e3;
+    if (tmin < best) {
+      best = tmin;
+      best_t = cands[i];
+    }
+  }
+  ctx->tune = best_t;
+  rep.best = rbmc_tune{best_t.small_k, best_t.small_tiles, best_t.wide_from};
+  rep.best_ms = best * 1e3;
+  rep.n_candidates = (int)cands.size();
+  if (cache_path) {
+    std::ofstream f(cache_path, std::ios::app);
+    if (f) {
+      f << key << " " << best_t.small_k << " " << best_t.small_tiles << " " << best_t.wide_from
+        << " " << rep.best_ms << " " << sig << "\n";
+      rep.cache_written = f.good() ? 1 : 0;
+    }
+  }
+  if (out) *out = rep;
+  return RBMC_OK;
 }
 
 rbmc_status rbmc_precond_train(rbmc_model* m, const rbmc_est_opts* pcg_opts,
