@@ -37,21 +37,21 @@ __global__ __launch_bounds__(256) void k_panels(const PanelTask* __restrict__ ta
   const int a = (tile / tiles_k) * PT_N + (threadIdx.x & 63);
   const int kbase = (tile % tiles_k) * PT_K;
   const bool real = a < rg.nb;
-  const int node = real ? rg.nodes[a] : 0;
+  const int node = real ? G(rg.nodes)[a] : 0;
   const size_t base = (size_t)tk.t * m.ns + node;
 
   if (tk.mode == 0) {
     for (int kk = threadIdx.x >> 6; kk < PT_K; kk += 4) {
       const int k = kbase + kk;
       if (k >= n_k) break;
-      tk.P[(size_t)k * rg.np + a] = real ? tk.X[(size_t)k * m.n + base] : 0.0;
+      G(tk.P)[(size_t)k * rg.np + a] = real ? G(tk.X)[(size_t)k * m.n + base] : 0.0;
     }
   } else if (tk.mode == 1) {
     if (!real) return;
     for (int kk = threadIdx.x >> 6; kk < PT_K; kk += 4) {
       const int k = kbase + kk;
       if (k >= n_k) break;
-      tk.Xout[(size_t)k * m.n + base] = tk.P[(size_t)k * rg.np + a];
+      G(tk.Xout)[(size_t)k * m.n + base] = G(tk.P)[(size_t)k * rg.np + a];
     }
   } else {
     // r_a = sum over neighbours j of (t, node) outside A = [t0, t0+T) x R of Q_aj x_j
@@ -68,10 +68,10 @@ __global__ __launch_bounds__(256) void k_panels(const PanelTask* __restrict__ ta
         for (int q = 0; q < kNS; ++q) {
           const int jx = ix + kSdx[q], jy = iy + kSdy[q];
           if (jx < 0 || jx >= m.mx || jy < 0 || jy >= m.my) continue;
-          const bool s_in = rg.nbr[a * kNS + q] >= 0;
+          const bool s_in = G(rg.nbr)[a * kNS + q] >= 0;
           if (t_in && s_in) continue;
           idx[cnt] = tt * m.ns + jy * m.mx + jx;
-          cf[cnt] = wt * m.qs[(size_t)q * m.ns + node];
+          cf[cnt] = wt * G(m.qs)[(size_t)q * m.ns + node];
           ++cnt;
         }
       }
@@ -80,8 +80,8 @@ __global__ __launch_bounds__(256) void k_panels(const PanelTask* __restrict__ ta
       const int k = kbase + kk;
       if (k >= n_k) break;
       double v = 0.0;
-      for (int c = 0; c < cnt; ++c) v += cf[c] * tk.X[(size_t)k * m.n + idx[c]];
-      tk.P[(size_t)k * rg.np + a] = v;
+      for (int c = 0; c < cnt; ++c) v += cf[c] * G(tk.X)[(size_t)k * m.n + idx[c]];
+      G(tk.P)[(size_t)k * rg.np + a] = v;
     }
   }
 }
@@ -104,21 +104,21 @@ __global__ __launch_bounds__(256) void k_extract(const ExtractTask* __restrict__
   const int chunk = b - tk.tile_start;
   const int a = chunk * 256 + threadIdx.x;
   double sd = 0.0, sq = 0.0, sk = 0.0;
-  if (a < rg.nb && rg.in_box[a]) {
-    const int node = rg.nodes[a];
+  if (a < rg.nb && G(rg.in_box)[a]) {
+    const int node = G(rg.nodes)[a];
     auto el = [&](int r, int c) {  // Sigma block entry (r, c) in region-local indices
-      return tk.trans ? tk.M[(size_t)r * tk.ld + c] : tk.M[(size_t)c * tk.ld + r];
+      return tk.trans ? G(tk.M)[(size_t)r * tk.ld + c] : G(tk.M)[(size_t)c * tk.ld + r];
     };
     for (int q = 0; q < kNS; ++q) {
-      const int c = rg.nbr[a * kNS + q];
+      const int c = G(rg.nbr)[a * kNS + q];
       if (c < 0) continue;
       const double v = tk.sign * el(a, c);
-      sq += m.qs[(size_t)q * m.ns + node] * v;
-      if (q < kN5) sk += m.kk[(size_t)q * m.ns + node] * v;
+      sq += G(m.qs)[(size_t)q * m.ns + node] * v;
+      if (q < kN5) sk += G(m.kk)[(size_t)q * m.ns + node] * v;
       if (q == 0 && tk.kind == 0) {
         const size_t i = (size_t)tk.t * m.ns + node;
-        tk.diag_out[i] = v;
-        sd = m.dvec[i] * v;
+        G(tk.diag_out)[i] = v;
+        sd = G(m.dvec)[i] * v;
       }
     }
   }
@@ -132,7 +132,7 @@ __global__ __launch_bounds__(256) void k_extract(const ExtractTask* __restrict__
     __syncthreads();
   }
   if (threadIdx.x < 3)
-    tk.partial[((size_t)tk.out_index + chunk) * 3 + threadIdx.x] = red[threadIdx.x][0];
+    G(tk.partial)[((size_t)tk.out_index + chunk) * 3 + threadIdx.x] = red[threadIdx.x][0];
 }
 
 void launch_extract(const ExtractTask* d_tasks, int n_tasks, int total_tiles, hipStream_t s) {
@@ -175,12 +175,12 @@ __global__ __launch_bounds__(256) void k_offdiag(const OffdiagTask* __restrict__
   const int chunk = b - tk.tile_start;
   const int tid = threadIdx.x;
   const int a0 = chunk * 256, a = a0 + tid;
-  const bool row = a < rg.nb && rg.in_box[a];
+  const bool row = a < rg.nb && G(rg.in_box)[a];
   int nbr[kNS];
   int lo = INT_MAX, hi = -1;
 #pragma unroll
   for (int q = 0; q < kNS; ++q) {
-    nbr[q] = row ? rg.nbr[a * kNS + q] : -1;
+    nbr[q] = row ? G(rg.nbr)[a * kNS + q] : -1;
     if (nbr[q] >= 0) {
       lo = min(lo, nbr[q]);
       hi = max(hi, nbr[q]);
@@ -212,12 +212,12 @@ __global__ __launch_bounds__(256) void k_offdiag(const OffdiagTask* __restrict__
 #pragma unroll
       for (int i = 0; i < kSg; ++i) {
         const int col = c0 + 32 * i;
-        ls[i] = (kin && col < nrows) ? tk.Sig[(size_t)(a0 + col) * tk.ld + k0 + kk] : 0.0;
+        ls[i] = (kin && col < nrows) ? G(tk.Sig)[(size_t)(a0 + col) * tk.ld + k0 + kk] : 0.0;
       }
 #pragma unroll
       for (int i = 0; i < kW; ++i) {
         const int col = c0 + 32 * i;
-        lw[i] = (kin && col < span) ? tk.W[(size_t)(slo + col) * tk.ld + k0 + kk] : 0.0;
+        lw[i] = (kin && col < span) ? G(tk.W)[(size_t)(slo + col) * tk.ld + k0 + kk] : 0.0;
       }
       __syncthreads();  // the previous chunk is no longer read
 #pragma unroll
@@ -241,14 +241,14 @@ __global__ __launch_bounds__(256) void k_offdiag(const OffdiagTask* __restrict__
     double accw[kNS];
     for (int r = wave; r < nrows; r += 4) {
       const int ar = a0 + r;
-      if (!rg.in_box[ar]) continue;
+      if (!G(rg.in_box)[ar]) continue;
       int nb2[kNS];
 #pragma unroll
       for (int q = 0; q < kNS; ++q) {
-        nb2[q] = rg.nbr[ar * kNS + q];
+        nb2[q] = G(rg.nbr)[ar * kNS + q];
         accw[q] = 0.0;
       }
-      const double* sg = tk.Sig + (size_t)ar * tk.ld;
+      const gptr<const double> sg = G(tk.Sig) + (size_t)ar * tk.ld;
       for (int k = lane; k < rg.nb; k += 64) {
         const double sv = sg[k];
 #pragma unroll
@@ -272,13 +272,13 @@ __global__ __launch_bounds__(256) void k_offdiag(const OffdiagTask* __restrict__
   }
   double sq = 0.0, sk = 0.0;
   if (row) {
-    const int node = rg.nodes[a];
+    const int node = G(rg.nodes)[a];
 #pragma unroll
     for (int q = 0; q < kNS; ++q) {
       if (nbr[q] < 0) continue;
       const double v = tk.scale * acc[q];
-      sq += m.qs[(size_t)q * m.ns + node] * v;
-      if (q < kN5) sk += m.kk[(size_t)q * m.ns + node] * v;
+      sq += G(m.qs)[(size_t)q * m.ns + node] * v;
+      if (q < kN5) sk += G(m.kk)[(size_t)q * m.ns + node] * v;
     }
   }
   red[0][tid] = sq;
@@ -292,7 +292,7 @@ __global__ __launch_bounds__(256) void k_offdiag(const OffdiagTask* __restrict__
     __syncthreads();
   }
   if (tid < 3)
-    tk.partial[((size_t)tk.out_index + chunk) * 3 + tid] = tid == 0 ? 0.0 : red[tid - 1][0];
+    G(tk.partial)[((size_t)tk.out_index + chunk) * 3 + tid] = tid == 0 ? 0.0 : red[tid - 1][0];
 }
 
 void launch_offdiag(const OffdiagTask* d_tasks, int n_tasks, int total_tiles, hipStream_t s) {
@@ -316,21 +316,21 @@ __global__ __launch_bounds__(256) void k_mc(const McTask* __restrict__ tasks, in
   const int chunk = b - tk.tile_start;
   const int a = chunk * 64 + (threadIdx.x & 63);
   const int ks = threadIdx.x >> 6;
-  const bool mine = a < rg.nb && rg.in_box[a];
+  const bool mine = a < rg.nb && G(rg.in_box)[a];
   double acc[8];
 #pragma unroll
   for (int c = 0; c < 8; ++c) acc[c] = 0.0;
   if (mine) {
-    const int node = rg.nodes[a];
+    const int node = G(rg.nodes)[a];
     const size_t i = (size_t)tk.t * m.ns + node;
-    const double dv = m.dvec[i];
+    const double dv = G(m.dvec)[i];
     int nbr[kNS];
     double cq[kNS], ck[kN5];
 #pragma unroll
     for (int q = 0; q < kNS; ++q) {
-      nbr[q] = rg.nbr[a * kNS + q];
-      cq[q] = m.qs[(size_t)q * m.ns + node];
-      if (q < kN5) ck[q] = m.kk[(size_t)q * m.ns + node];
+      nbr[q] = G(rg.nbr)[a * kNS + q];
+      cq[q] = G(m.qs)[(size_t)q * m.ns + node];
+      if (q < kN5) ck[q] = G(m.kk)[(size_t)q * m.ns + node];
     }
     for (int k = ks; k < n_k; k += 4) {
       const size_t off = (size_t)k * tk.np;
@@ -363,10 +363,10 @@ __global__ __launch_bounds__(256) void k_mc(const McTask* __restrict__ tasks, in
   if (threadIdx.x < 64 && mine) {
     const double s = (red[7][threadIdx.x] + red[7][threadIdx.x + 64]) +
                      (red[7][threadIdx.x + 128] + red[7][threadIdx.x + 192]);
-    const size_t i = (size_t)tk.t * m.ns + rg.nodes[a];
+    const size_t i = (size_t)tk.t * m.ns + G(rg.nodes)[a];
     const double mhat = s / n_k;
-    const double est = tk.diag_out[i] + mhat;
-    tk.diag_out[i] = est;
+    const double est = G(tk.diag_out)[i] + mhat;
+    G(tk.diag_out)[i] = est;
     ratio = est > 0.0 ? mhat * n_k / est : 0.0;  // scaled back by 1/n_k below
   }
   __syncthreads();
@@ -378,7 +378,7 @@ __global__ __launch_bounds__(256) void k_mc(const McTask* __restrict__ tasks, in
     __syncthreads();
   }
   if (threadIdx.x < 8)
-    tk.partial[((size_t)tk.out_index + chunk) * 8 + threadIdx.x] = red[threadIdx.x][0] / n_k;
+    G(tk.partial)[((size_t)tk.out_index + chunk) * 8 + threadIdx.x] = red[threadIdx.x][0] / n_k;
 }
 
 void launch_mc(const McTask* d_tasks, int n_tasks, int total_tiles, hipStream_t s) {

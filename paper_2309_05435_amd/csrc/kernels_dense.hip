@@ -40,19 +40,19 @@ struct TileRegs {
 __device__ inline void load_a(const GemmTask& tk, int m0, int k0, int tid, TileRegs& r) {
   if (!tk.transA) {  // column-major A: 8 consecutive rows of one column k
     const int kk = tid >> 4, mm = (tid & 15) * 8, gm = m0 + mm;
-    const double* src = tk.A + (size_t)(k0 + kk) * tk.lda + gm;
+    const gptr<const double> src = G(tk.A) + (size_t)(k0 + kk) * tk.lda + gm;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int c = gm + 2 * j;
-      if (c + 1 < tk.M) r.v[j] = *(const double2*)(src + 2 * j);
+      if (c + 1 < tk.M) r.v[j] = ldg2(src + 2 * j);
       else r.v[j] = double2{c < tk.M ? src[2 * j] : 0.0, 0.0};
     }
   } else {  // A^T stored column-major: 8 consecutive k of one row m
     const int mm = tid >> 1, kk = (tid & 1) * 8, gm = m0 + mm;
-    const double* src = tk.A + (size_t)gm * tk.lda + k0 + kk;
+    const gptr<const double> src = G(tk.A) + (size_t)gm * tk.lda + k0 + kk;
 #pragma unroll
     for (int j = 0; j < 4; ++j)
-      r.v[j] = (gm < tk.M) ? *(const double2*)(src + 2 * j) : double2{0.0, 0.0};
+      r.v[j] = (gm < tk.M) ? ldg2(src + 2 * j) : double2{0.0, 0.0};
   }
 }
 
@@ -74,17 +74,17 @@ __device__ inline void store_a(const GemmTask& tk, int tid, const TileRegs& r, d
 __device__ inline void load_b(const GemmTask& tk, int n0, int k0, int tid, TileRegs& r) {
   if (!tk.transB) {  // column-major B: 8 consecutive k of one column n
     const int nn = tid >> 1, kk = (tid & 1) * 8, gn = n0 + nn;
-    const double* src = tk.B + (size_t)gn * tk.ldb + k0 + kk;
+    const gptr<const double> src = G(tk.B) + (size_t)gn * tk.ldb + k0 + kk;
 #pragma unroll
     for (int j = 0; j < 4; ++j)
-      r.v[j] = (gn < tk.N) ? *(const double2*)(src + 2 * j) : double2{0.0, 0.0};
+      r.v[j] = (gn < tk.N) ? ldg2(src + 2 * j) : double2{0.0, 0.0};
   } else {  // B^T stored column-major: 8 consecutive n of one row k
     const int kk = tid >> 4, nn = (tid & 15) * 8, gn = n0 + nn;
-    const double* src = tk.B + (size_t)(k0 + kk) * tk.ldb + gn;
+    const gptr<const double> src = G(tk.B) + (size_t)(k0 + kk) * tk.ldb + gn;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int c = gn + 2 * j;
-      if (c + 1 < tk.N) r.v[j] = *(const double2*)(src + 2 * j);
+      if (c + 1 < tk.N) r.v[j] = ldg2(src + 2 * j);
       else r.v[j] = double2{c < tk.N ? src[2 * j] : 0.0, 0.0};
     }
   }
@@ -205,8 +205,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(const GemmTask* __restrict_
         const int gn = n0 + wn + j * 16 + g + 4 * r;
         if (gn >= tk.N) continue;
         double v = tk.alpha * acc[i][j][r];
-        if (tk.beta != 0.0) v += tk.beta * tk.Cin[(size_t)gn * tk.ldcin + gm];
-        tk.C[(size_t)gn * tk.ldc + gm] = v;
+        if (tk.beta != 0.0) v += tk.beta * G(tk.Cin)[(size_t)gn * tk.ldcin + gm];
+        G(tk.C)[(size_t)gn * tk.ldc + gm] = v;
       }
   }
 }
@@ -235,19 +235,19 @@ struct XRegs {
 __device__ inline void xload_a(const GemmTask& tk, int m0, int k0, int tid, XRegs& r) {
   if (!tk.transA) {  // 4 consecutive rows of column k
     const int kk = tid >> 5, gm = m0 + (tid & 31) * 4;
-    const double* src = tk.A + (size_t)(k0 + kk) * tk.lda + gm;
+    const gptr<const double> src = G(tk.A) + (size_t)(k0 + kk) * tk.lda + gm;
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int c = gm + 2 * j;
-      if (c + 1 < tk.M) r.v[j] = *(const double2*)(src + 2 * j);
+      if (c + 1 < tk.M) r.v[j] = ldg2(src + 2 * j);
       else r.v[j] = double2{c < tk.M ? src[2 * j] : 0.0, 0.0};
     }
   } else {  // 4 consecutive k of row m
     const int gm = m0 + (tid >> 2), kk = (tid & 3) * 4;
-    const double* src = tk.A + (size_t)gm * tk.lda + k0 + kk;
+    const gptr<const double> src = G(tk.A) + (size_t)gm * tk.lda + k0 + kk;
 #pragma unroll
     for (int j = 0; j < 2; ++j)
-      r.v[j] = (gm < tk.M) ? *(const double2*)(src + 2 * j) : double2{0.0, 0.0};
+      r.v[j] = (gm < tk.M) ? ldg2(src + 2 * j) : double2{0.0, 0.0};
   }
 }
 
@@ -268,17 +268,17 @@ __device__ inline void xstore_a(const GemmTask& tk, int tid, const XRegs& r, flo
 __device__ inline void xload_b(const GemmTask& tk, int n0, int k0, int tid, XRegs& r) {
   if (!tk.transB) {  // 4 consecutive k of column n
     const int gn = n0 + (tid >> 2), kk = (tid & 3) * 4;
-    const double* src = tk.B + (size_t)gn * tk.ldb + k0 + kk;
+    const gptr<const double> src = G(tk.B) + (size_t)gn * tk.ldb + k0 + kk;
 #pragma unroll
     for (int j = 0; j < 2; ++j)
-      r.v[j] = (gn < tk.N) ? *(const double2*)(src + 2 * j) : double2{0.0, 0.0};
+      r.v[j] = (gn < tk.N) ? ldg2(src + 2 * j) : double2{0.0, 0.0};
   } else {  // 4 consecutive n of row k
     const int kk = tid >> 5, gn = n0 + (tid & 31) * 4;
-    const double* src = tk.B + (size_t)(k0 + kk) * tk.ldb + gn;
+    const gptr<const double> src = G(tk.B) + (size_t)(k0 + kk) * tk.ldb + gn;
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int c = gn + 2 * j;
-      if (c + 1 < tk.N) r.v[j] = *(const double2*)(src + 2 * j);
+      if (c + 1 < tk.N) r.v[j] = ldg2(src + 2 * j);
       else r.v[j] = double2{c < tk.N ? src[2 * j] : 0.0, 0.0};
     }
   }
@@ -397,8 +397,8 @@ __global__ __launch_bounds__(512, 1) void k_gemm_mx(const GemmTask* __restrict__
         const int gn = n0 + wn + j * 16 + 4 * g + r;
         if (gn >= tk.N) continue;
         double v = tk.alpha * acc[i][j][r];
-        if (tk.beta != 0.0) v += tk.beta * tk.Cin[(size_t)gn * tk.ldcin + gm];
-        tk.C[(size_t)gn * tk.ldc + gm] = v;
+        if (tk.beta != 0.0) v += tk.beta * G(tk.Cin)[(size_t)gn * tk.ldcin + gm];
+        G(tk.C)[(size_t)gn * tk.ldc + gm] = v;
       }
   }
 }
@@ -415,19 +415,19 @@ constexpr int SB = 64;
 __device__ inline void sload_a(const GemmTask& tk, int m0, int k0, int tid, XRegs& r) {
   if (!tk.transA) {  // 4 consecutive rows of column k
     const int kk = tid >> 4, gm = m0 + (tid & 15) * 4;
-    const double* src = tk.A + (size_t)(k0 + kk) * tk.lda + gm;
+    const gptr<const double> src = G(tk.A) + (size_t)(k0 + kk) * tk.lda + gm;
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int c = gm + 2 * j;
-      if (c + 1 < tk.M) r.v[j] = *(const double2*)(src + 2 * j);
+      if (c + 1 < tk.M) r.v[j] = ldg2(src + 2 * j);
       else r.v[j] = double2{c < tk.M ? src[2 * j] : 0.0, 0.0};
     }
   } else {  // 4 consecutive k of row m
     const int gm = m0 + (tid >> 2), kk = (tid & 3) * 4;
-    const double* src = tk.A + (size_t)gm * tk.lda + k0 + kk;
+    const gptr<const double> src = G(tk.A) + (size_t)gm * tk.lda + k0 + kk;
 #pragma unroll
     for (int j = 0; j < 2; ++j)
-      r.v[j] = (gm < tk.M) ? *(const double2*)(src + 2 * j) : double2{0.0, 0.0};
+      r.v[j] = (gm < tk.M) ? ldg2(src + 2 * j) : double2{0.0, 0.0};
   }
 }
 
@@ -448,17 +448,17 @@ __device__ inline void sstore_a(const GemmTask& tk, int tid, const XRegs& r, dou
 __device__ inline void sload_b(const GemmTask& tk, int n0, int k0, int tid, XRegs& r) {
   if (!tk.transB) {  // 4 consecutive k of column n
     const int gn = n0 + (tid >> 2), kk = (tid & 3) * 4;
-    const double* src = tk.B + (size_t)gn * tk.ldb + k0 + kk;
+    const gptr<const double> src = G(tk.B) + (size_t)gn * tk.ldb + k0 + kk;
 #pragma unroll
     for (int j = 0; j < 2; ++j)
-      r.v[j] = (gn < tk.N) ? *(const double2*)(src + 2 * j) : double2{0.0, 0.0};
+      r.v[j] = (gn < tk.N) ? ldg2(src + 2 * j) : double2{0.0, 0.0};
   } else {  // 4 consecutive n of row k
     const int kk = tid >> 4, gn = n0 + (tid & 15) * 4;
-    const double* src = tk.B + (size_t)(k0 + kk) * tk.ldb + gn;
+    const gptr<const double> src = G(tk.B) + (size_t)(k0 + kk) * tk.ldb + gn;
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int c = gn + 2 * j;
-      if (c + 1 < tk.N) r.v[j] = *(const double2*)(src + 2 * j);
+      if (c + 1 < tk.N) r.v[j] = ldg2(src + 2 * j);
       else r.v[j] = double2{c < tk.N ? src[2 * j] : 0.0, 0.0};
     }
   }
@@ -566,8 +566,8 @@ __global__ __launch_bounds__(256) void k_gemm_f64s(const GemmTask* __restrict__ 
         const int gn = n0 + wn + j * 16 + g + 4 * r;
         if (gn >= tk.N) continue;
         double v = tk.alpha * acc[i][j][r];
-        if (tk.beta != 0.0) v += tk.beta * tk.Cin[(size_t)gn * tk.ldcin + gm];
-        tk.C[(size_t)gn * tk.ldc + gm] = v;
+        if (tk.beta != 0.0) v += tk.beta * G(tk.Cin)[(size_t)gn * tk.ldcin + gm];
+        G(tk.C)[(size_t)gn * tk.ldc + gm] = v;
       }
   }
 }
@@ -621,7 +621,7 @@ __global__ __launch_bounds__(IT) void k_inv128(const SmallInvTask* __restrict__ 
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int r = 4 * tr + i, c = 4 * tc + j;
-      v[i][j] = (r < w && c < w) ? tk.P[(size_t)r * tk.ld + c] : (r == c ? 1.0 : 0.0);
+      v[i][j] = (r < w && c < w) ? G(tk.P)[(size_t)r * tk.ld + c] : (r == c ? 1.0 : 0.0);
     }
   int bad = -1;
   for (int q = 0; q < IB / 4; ++q) {
@@ -668,7 +668,7 @@ __global__ __launch_bounds__(IT) void k_inv128(const SmallInvTask* __restrict__ 
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int r = 4 * tr + i, c = 4 * tc + j;
-      if (r < w && c < w) tk.P[(size_t)r * tk.ld + c] = -v[i][j];
+      if (r < w && c < w) G(tk.P)[(size_t)r * tk.ld + c] = -v[i][j];
     }
 }
 
@@ -694,15 +694,15 @@ __global__ __launch_bounds__(256) void k_gj_finish(const InvTask* __restrict__ t
     const int r = e % 64, c = e / 64;
     const size_t at = (size_t)(J * 64 + c) * np + I * 64 + r;
     if (I == J && r < c) continue;
-    const double v = -tk.M[at];
-    tk.M[at] = v;
+    const double v = -G(tk.M)[at];
+    G(tk.M)[at] = v;
     T[c * 65 + r] = v;
   }
   __syncthreads();
   for (int e = tid; e < 4096; e += 256) {  // upper tile (rows J, cols I): (J+c, I+r) = (I+r, J+c)
     const int c = e % 64, r = e / 64;
     if (I == J && c >= r) continue;  // diagonal tile: only its strict upper part
-    tk.M[(size_t)(I * 64 + r) * np + J * 64 + c] = T[c * 65 + r];
+    G(tk.M)[(size_t)(I * 64 + r) * np + J * 64 + c] = T[c * 65 + r];
   }
 }
 
@@ -742,29 +742,29 @@ __global__ __launch_bounds__(256) void k_gj2_gather(const Gj2Task* __restrict__ 
   if (r0 >= col0 + 64) {
     for (int e = tid; e < 4096; e += 256) {
       const int r = e % 64, c = e / 64;
-      T[c * 65 + r] = tk.M[(size_t)(col0 + c) * np + r0 + r];
+      T[c * 65 + r] = G(tk.M)[(size_t)(col0 + c) * np + r0 + r];
     }
   } else if (r0 + 64 <= col0) {  // strictly above: read the transposed lower tile
     for (int e = tid; e < 4096; e += 256) {
       const int c = e % 64, r = e / 64;
-      T[c * 65 + r] = tk.M[(size_t)(r0 + r) * np + col0 + c];
+      T[c * 65 + r] = G(tk.M)[(size_t)(r0 + r) * np + col0 + c];
     }
   } else {  // diagonal tile
     for (int e = tid; e < 4096; e += 256) {
       const int r = e % 64, c = e / 64;
       const int gr = r0 + r, gc = col0 + c;
-      T[c * 65 + r] = gr >= gc ? tk.M[(size_t)gc * np + gr] : tk.M[(size_t)gr * np + gc];
+      T[c * 65 + r] = gr >= gc ? G(tk.M)[(size_t)gc * np + gr] : G(tk.M)[(size_t)gr * np + gc];
     }
   }
   __syncthreads();
   for (int e = tid; e < 4096; e += 256) {  // Bt column r0 + r holds row r0 + r of B
     const int c = e % 64, r = e / 64;
-    tk.B[(size_t)(r0 + r) * tk.w + c0 + c] = T[c * 65 + r];
+    G(tk.B)[(size_t)(r0 + r) * tk.w + c0 + c] = T[c * 65 + r];
   }
   if (r0 + 64 > tk.kb && r0 < tk.kb + tk.w) {  // the pivot rows: P is symmetric
     for (int e = tid; e < 4096; e += 256) {
       const int c = e % 64, r = e / 64;
-      tk.P[(size_t)(r0 - tk.kb + r) * tk.w + c0 + c] = T[c * 65 + r];
+      G(tk.P)[(size_t)(r0 - tk.kb + r) * tk.w + c0 + c] = T[c * 65 + r];
     }
   }
 }
@@ -784,22 +784,22 @@ __global__ __launch_bounds__(256) void k_gj2_fix(const Gj2Task* __restrict__ tas
   if (r0 >= kb + w) {  // below the pivot: transpose through LDS so both sides coalesce
     for (int e = tid; e < 4096; e += 256) {
       const int c = e % 64, r = e / 64;
-      T[c * 65 + r] = tk.U[(size_t)(r0 + r) * w + c0 + c];
+      T[c * 65 + r] = G(tk.U)[(size_t)(r0 + r) * w + c0 + c];
     }
     __syncthreads();
     for (int e = tid; e < 4096; e += 256) {
       const int r = e % 64, c = e / 64;
-      tk.M[(size_t)(kb + c0 + c) * np + r0 + r] = T[c * 65 + r];
+      G(tk.M)[(size_t)(kb + c0 + c) * np + r0 + r] = T[c * 65 + r];
     }
   } else if (r0 < kb) {  // left of the pivot: row block kb.., columns r0..
     for (int e = tid; e < 4096; e += 256) {
       const int c = e % 64, r = e / 64;
-      tk.M[(size_t)(r0 + r) * np + kb + c0 + c] = tk.U[(size_t)(r0 + r) * w + c0 + c];
+      G(tk.M)[(size_t)(r0 + r) * np + kb + c0 + c] = G(tk.U)[(size_t)(r0 + r) * w + c0 + c];
     }
   } else {  // pivot block
     for (int e = tid; e < 4096; e += 256) {
       const int r = e % 64, c = e / 64;
-      tk.M[(size_t)(kb + c0 + c) * np + r0 + r] = -tk.P[(size_t)(c0 + c) * w + (r0 - kb) + r];
+      G(tk.M)[(size_t)(kb + c0 + c) * np + r0 + r] = -G(tk.P)[(size_t)(c0 + c) * w + (r0 - kb) + r];
     }
   }
 }
@@ -858,11 +858,11 @@ __global__ __launch_bounds__(256) void k_rstencil(const StencilTask* __restrict_
   double cf[kNS];
   int lo = INT_MAX, hi = -1;
   if (real) {
-    const int node = rg.nodes[a];
+    const int node = G(rg.nodes)[a];
 #pragma unroll
     for (int q = 0; q < kNS; ++q) {
-      nbr[q] = rg.nbr[a * kNS + q];
-      cf[q] = tk.qs[(size_t)q * tk.ns + node];
+      nbr[q] = G(rg.nbr)[a * kNS + q];
+      cf[q] = G(tk.qs)[(size_t)q * tk.ns + node];
       if (nbr[q] >= 0) {
         lo = min(lo, nbr[q]);
         hi = max(hi, nbr[q]);
@@ -888,7 +888,7 @@ __global__ __launch_bounds__(256) void k_rstencil(const StencilTask* __restrict_
     const int c0 = cw + g * kRsCols, ncc = min(kRsCols, tk.ncols - c0);
 #pragma unroll
     for (int cc = 0; cc < kRsCols; ++cc) {
-      const double* mc = tk.M + (size_t)(c0 + cc) * tk.ldm + slo;
+      const gptr<const double> mc = G(tk.M) + (size_t)(c0 + cc) * tk.ldm + slo;
       ld[2 * cc] = (cc < ncc && tid < span) ? mc[tid] : 0.0;
       ld[2 * cc + 1] = (cc < ncc && tid + 256 < span) ? mc[tid + 256] : 0.0;
     }
@@ -905,7 +905,7 @@ __global__ __launch_bounds__(256) void k_rstencil(const StencilTask* __restrict_
       }
       for (int e = tid; e < ncc * (span - 512); e += 256) {  // rows 512.. of a long span
         const int w = span - 512, cc = e / w, r = 512 + (e - cc * w);
-        src[cc * kRsSpan + r] = tk.M[(size_t)(c0 + cc) * tk.ldm + slo + r];
+        src[cc * kRsSpan + r] = G(tk.M)[(size_t)(c0 + cc) * tk.ldm + slo + r];
       }
       __syncthreads();
       if (g + 1 < ngrp) issue(g + 1);
@@ -920,7 +920,7 @@ __global__ __launch_bounds__(256) void k_rstencil(const StencilTask* __restrict_
           for (int q = 0; q < kNS; ++q)
             if (nbr[q] >= 0) acc += cf[q] * src[cc * kRsSpan + nbr[q] - slo];
         } else {
-          const double* mc = tk.M + (size_t)(c0 + cc) * tk.ldm;
+          const gptr<const double> mc = G(tk.M) + (size_t)(c0 + cc) * tk.ldm;
 #pragma unroll
           for (int q = 0; q < kNS; ++q)
             if (nbr[q] >= 0) acc += cf[q] * mc[nbr[q]];
@@ -935,20 +935,20 @@ __global__ __launch_bounds__(256) void k_rstencil(const StencilTask* __restrict_
       for (int cc = 0; cc < kRsCols; ++cc) {
         if (cc >= ncc) break;
         double r = v[cc];
-        if (tk.beta != 0.0) r += tk.beta * tk.In[(size_t)(c0 + cc) * tk.ldin + a];
-        tk.out[(size_t)(c0 + cc) * tk.ldout + a] = r;
+        if (tk.beta != 0.0) r += tk.beta * G(tk.In)[(size_t)(c0 + cc) * tk.ldin + a];
+        G(tk.out)[(size_t)(c0 + cc) * tk.ldout + a] = r;
       }
     } else if (ncc == kRsCols && tk.beta == 0.0) {  // 16 contiguous doubles of row a
-      double2* o = reinterpret_cast<double2*>(tk.out + (size_t)a * tk.ldout + c0);
+      const gptr<double> o = G(tk.out) + (size_t)a * tk.ldout + c0;
 #pragma unroll
-      for (int k = 0; k < kRsCols / 2; ++k) o[k] = make_double2(v[2 * k], v[2 * k + 1]);
+      for (int k = 0; k < kRsCols / 2; ++k) stg2(o + 2 * k, v[2 * k], v[2 * k + 1]);
     } else {
 #pragma unroll
       for (int cc = 0; cc < kRsCols; ++cc) {
         if (cc >= ncc) break;
         double r = v[cc];
-        if (tk.beta != 0.0) r += tk.beta * tk.In[(size_t)a * tk.ldin + c0 + cc];
-        tk.out[(size_t)a * tk.ldout + c0 + cc] = r;
+        if (tk.beta != 0.0) r += tk.beta * G(tk.In)[(size_t)a * tk.ldin + c0 + cc];
+        G(tk.out)[(size_t)a * tk.ldout + c0 + cc] = r;
       }
     }
   }
@@ -969,15 +969,15 @@ __global__ __launch_bounds__(256) void k_sparse_add(const StencilTask* __restric
   const int a = blockIdx.x * 256 + threadIdx.x;
   if (a >= rg.np) return;
   if (a < rg.nb) {
-    const int node = rg.nodes[a];
+    const int node = G(rg.nodes)[a];
     if (tk.gamma != 0.0)
       for (int q = 0; q < kNS; ++q) {
-        const int c = rg.nbr[a * kNS + q];
-        if (c >= 0) tk.out[(size_t)c * tk.ldout + a] += tk.gamma * qs[(size_t)q * ns + node];
+        const int c = G(rg.nbr)[a * kNS + q];
+        if (c >= 0) G(tk.out)[(size_t)c * tk.ldout + a] += tk.gamma * qs[(size_t)q * ns + node];
       }
-    if (tk.dv) tk.out[(size_t)a * tk.ldout + a] += tk.dv[node];
+    if (tk.dv) G(tk.out)[(size_t)a * tk.ldout + a] += G(tk.dv)[node];
   } else if (tk.pad_identity) {
-    tk.out[(size_t)a * tk.ldout + a] += 1.0;
+    G(tk.out)[(size_t)a * tk.ldout + a] += 1.0;
   }
 }
 
@@ -1003,13 +1003,13 @@ __global__ __launch_bounds__(256) void k_mirror(const InvTask* __restrict__ task
   const int tid = threadIdx.x;
   for (int e = tid; e < 4096; e += 256) {  // lower tile (rows I, cols J)
     const int r = e % 64, c = e / 64;
-    T[c * 65 + r] = tk.M[(size_t)(J * 64 + c) * np + I * 64 + r];
+    T[c * 65 + r] = G(tk.M)[(size_t)(J * 64 + c) * np + I * 64 + r];
   }
   __syncthreads();
   for (int e = tid; e < 4096; e += 256) {  // upper tile (rows J, cols I): M[J+c, I+r] = T[c][r]
     const int c = e % 64, r = e / 64;
     if (I == J && c >= r) continue;  // diagonal tile: only its strict upper part
-    tk.M[(size_t)(I * 64 + r) * np + J * 64 + c] = T[c * 65 + r];
+    G(tk.M)[(size_t)(I * 64 + r) * np + J * 64 + c] = T[c * 65 + r];
   }
 }
 

@@ -17,6 +17,27 @@ constexpr int kSdy[kNS] = {0, 0, 0, -1, 1, 0, 0, -2, 2, -1, -1, 1, 1};
 // the first 5 entries form the 5-point stencil of G, K_kappa and F_s
 constexpr int kN5 = 5;
 
+// Global-memory views of device pointers.  Pointers read from task records
+// are generic, so accesses through them compile to flat instructions, which
+// count against the LDS wait counter as well: a wait for LDS reads would then
+// also wait for a global prefetch in flight.  Accesses through these views
+// compile to global instructions.  Only for pointers into device memory.
+template <class T>
+using gptr = T __attribute__((address_space(1)))*;
+template <class T>
+__device__ __forceinline__ gptr<T> G(T* p) {
+  return (gptr<T>)p;
+}
+typedef double gv2d __attribute__((ext_vector_type(2)));
+// 16-byte global load / store of two consecutive doubles
+__device__ __forceinline__ double2 ldg2(gptr<const double> p) {
+  const gv2d v = *(gptr<const gv2d>)p;
+  return double2{v.x, v.y};
+}
+__device__ __forceinline__ void stg2(gptr<double> p, double x, double y) {
+  *(gptr<gv2d>)p = gv2d{x, y};
+}
+
 // Dense blocks are padded to multiples of this (identity on the padded diagonal).
 constexpr int kPad = 64;
 inline int pad_to(int n) { return (n + kPad - 1) / kPad * kPad; }
