@@ -537,8 +537,10 @@ struct StencilList {
   int tiles = 0;
   double bytes = 0.0;
   int max_sparse_np = 0;  // largest block with sparse terms (0: none)
+  int two = 0;            // some task has a second input M2
   void add(StencilTask t, int np, int nb) {
     t.tile_start = tiles;
+    if (t.M2) two = 1;
     tiles += rstencil_tiles(np, t.ncols);
     bytes += 16.0 * nb * (double)t.ncols;
     if (t.gamma != 0.0 || t.dv != nullptr || t.pad_identity)
@@ -609,6 +611,7 @@ struct Program {
     o.family = RBMC_KF_RSTENCIL;
     o.alg_bytes = s.bytes;
     o.max_np = s.max_sparse_np;
+    o.kblk = s.two;
     ops.push_back(o);
   }
   void mirror(Arena& a, const std::vector<InvTask>& t) {
@@ -776,7 +779,7 @@ rbmc_status run(rbmc_ctx* cx, const Program& pg, hipStream_t s, Arena& a) {
     const int pid = (o.family >= 0) ? cx->begin(o.family, o.alg_flops, o.alg_bytes, s) : -1;
     switch (o.kind) {
       case 0: launch_gemm(a.at<GemmTask>(o.off), o.n, o.tiles, s, o.kblk); break;
-      case 1: launch_rstencil(a.at<StencilTask>(o.off), o.n, o.tiles, o.max_np, s); break;
+      case 1: launch_rstencil(a.at<StencilTask>(o.off), o.n, o.tiles, o.max_np, o.kblk, s); break;
       case 2: launch_inv128(a.at<SmallInvTask>(o.off), o.n, s); break;
       case 3: launch_panels(a.at<PanelTask>(o.off), o.n, o.tiles, s); break;
       case 4: launch_extract(a.at<ExtractTask>(o.off), o.n, o.tiles, s); break;
@@ -830,13 +833,13 @@ inline double* sigblock(const ChainSet& cs, size_t c, bool bj) {
   return bj ? cs.S[c] + (size_t)cs.np[c] * cs.np[c] * (cs.chains[c].T / 2) : cs.sig[c];
 }
 
-// Stencil tasks forming  out = B_t - q_o^2 Q_R (X + Y) Q_R  (X, Y inverse
-// blocks, either may be null; B_t = q_d(t) Q_R + D_t, identity on the padded
-// diagonal) in three passes through cs.tmp[c]: tmp = (Q_R X)^T, tmp +=
-// (Q_R Y)^T (both stored transposed, i.e. X Q_R and Y Q_R), out = -q_o^2 Q_R
-// tmp + B_t.
+// Stencil tasks forming  out = B_t - q_o^2 Q_R (X + Y) Q_R  (X, Y symmetric
+// inverse blocks, either may be null; B_t = q_d(t) Q_R + D_t, identity on the
+// padded diagonal) in two passes through cs.tmp[c]: tmp = (Q_R (X + Y))^T
+// (stored transposed, i.e. (X + Y) Q_R; the sum is formed as the inputs are
+// loaded), out = -q_o^2 Q_R tmp + B_t.
 void add_schur(const ChainSet& cs, size_t c, int t, const double* X, const double* Y,
-               double* out, StencilList& v1, StencilList& v1b, StencilList& v2) {
+               double* out, StencilList& v1, StencilList& v2) {
   const Chain& ch = cs.chains[c];
   const rbmc_model* m = cs.owner[c];
   const int np = cs.np[c], nb = cs.nb[c];
@@ -846,6 +849,7 @@ void add_schur(const ChainSet& cs, size_t c, int t, const double* X, const doubl
   if (first) {
     StencilTask s1 = stask(cs, c);
     s1.M = first;
+    s1.M2 = second;
     s1.ldm = np;
     s1.out = cs.tmp[c];
     s1.ldout = np;
@@ -853,20 +857,7 @@ void add_schur(const ChainSet& cs, size_t c, int t, const double* X, const doubl
     s1.alpha = 1.0;
     s1.tstore = 1;
     v1.add(s1, np, nb);
-  }
-  if (second) {
-    StencilTask s1 = stask(cs, c);
-    s1.M = second;
-    s1.ldm = np;
-    s1.In = cs.tmp[c];
-    s1.ldin = np;
-    s1.beta = 1.0;
-    s1.out = cs.tmp[c];
-    s1.ldout = np;
-    s1.ncols = np;
-    s1.alpha = 1.0;
-    s1.tstore = 1;
-    v1b.add(s1, np, nb);
+    if (second) v1.bytes += 8.0 * nb * (double)np;  // the second input's reads
   }
   StencilTask s2 = stask(cs, c);
   s2.M = first ? cs.tmp[c] : nullptr;
@@ -919,20 +910,20 @@ void build_twosided(ChainSet& cs, Program& pg, Arena& a, bool bj = false) {
   for (int r = 0; r < rounds; ++r) {
     std::vector<InvJob> inv;
     for (int dir = 0; dir < 2; ++dir) {
-      StencilList v1, v1b, v2;
+      StencilList v1, v2;
       for (size_t c = 0; c < cs.size(); ++c) {
         const Chain& ch = cs.chains[c];
         if (dir == 0) {
           if (r >= fwd_count(ch, bj)) continue;
           double* out = fblock(cs, c, r);
-          add_schur(cs, c, r, r > 0 ? fblock(cs, c, r - 1) : nullptr, nullptr, out, v1, v1b, v2);
+          add_schur(cs, c, r, r > 0 ? fblock(cs, c, r - 1) : nullptr, nullptr, out, v1, v2);
           inv.push_back(inv_job(cs, c, out));
         } else {
           const int t = ch.T - 1 - r;
           if (t <= (bj ? ch.T / 2 : chain_lc0(ch))) continue;
           double* out = gblock(cs, c, t, bj);
           add_schur(cs, c, t, t < ch.T - 1 ? gblock(cs, c, t + 1, bj) : nullptr, nullptr, out,
-                    v1, v1b, v2);
+                    v1, v2);
           inv.push_back(inv_job(cs, c, out, 1));
         }
       }
@@ -942,18 +933,17 @@ void build_twosided(ChainSet& cs, Program& pg, Arena& a, bool bj = false) {
     pg.inverse(a, inv);
   }
   if (bj) {  // Sigma at the twist
-    StencilList v1, v1b, v2;
+    StencilList v1, v2;
     std::vector<InvJob> inv;
     for (size_t c = 0; c < cs.size(); ++c) {
       const Chain& ch = cs.chains[c];
       const int k = ch.T / 2;
       double* out = sigblock(cs, c, true);
       add_schur(cs, c, k, k >= 1 ? fblock(cs, c, k - 1) : nullptr,
-                k + 1 < ch.T ? gblock(cs, c, k + 1, true) : nullptr, out, v1, v1b, v2);
+                k + 1 < ch.T ? gblock(cs, c, k + 1, true) : nullptr, out, v1, v2);
       inv.push_back(inv_job(cs, c, out));
     }
     pg.stencil(a, v1);
-    pg.stencil(a, v1b);
     pg.stencil(a, v2);
     pg.inverse(a, inv);
   }
@@ -1565,7 +1555,7 @@ rbmc_status estimate_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const
     int max_ct = 0;
     for (int c = 0; c < nchains; ++c) max_ct = std::max(max_ct, cs.chains[c].cT);
     for (int k = 0; k < max_ct; ++k) {
-      StencilList v1, v1b, v2, wp, wm;
+      StencilList v1, v2, wp, wm;
       std::vector<InvJob> inv;
       TileList<ExtractTask> ex;
       TileList<OffdiagTask> op, om;
@@ -1578,7 +1568,7 @@ rbmc_status estimate_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const
         double* sg = (k == 0) ? cs.sig[c] : cs.sig2[c];
         const double* Fm = (t >= 1) ? fblock(cs, c, t - 1) : nullptr;
         const double* Gp = (t + 1 < ch.T) ? gblock(cs, c, t + 1) : nullptr;
-        add_schur(cs, c, t, Fm, Gp, sg, v1, v1b, v2);
+        add_schur(cs, c, t, Fm, Gp, sg, v1, v2);
         inv.push_back(inv_job(cs, c, sg));
         ex.add(etask(c, sg, t, 0, 0, 1.0, 0), (np + 255) / 256);
         for (int side = 0; side < 2; ++side) {
@@ -1605,7 +1595,6 @@ rbmc_status estimate_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const
         }
       }
       tak.stencil(ar, v1);
-      tak.stencil(ar, v1b);
       tak.stencil(ar, v2);
       tak.inverse(ar, inv);
       tak.extract(ar, ex);

@@ -813,7 +813,8 @@ void launch_gj2_fix(const Gj2Task* d_tasks, int n_tasks, int total_tiles, hipStr
 }
 
 // ---------------------------------------------------------------------------
-// Restricted-stencil products: out = alpha Q_R M + beta In (+ the sparse terms
+// Restricted-stencil products: out = alpha Q_R (M + M2) + beta In (M2 optional,
+// summed as M is loaded; + the sparse terms
 // gamma Q_R + diag(dv) + I on the padded diagonal, added by k_sparse_add);
 // rows are region nodes (padded to np).  Column c of the result is the
 // 13-point stencil applied to column c of M, a field over the region.
@@ -833,7 +834,10 @@ namespace {
 constexpr int kRsRows = 256, kRsCols = 16, kRsGroups = 4, kRsSpan = 528;
 }
 
-__global__ __launch_bounds__(256) void k_rstencil(const StencilTask* __restrict__ tasks,
+// kTwo: some task of the launch has a second input M2.  Its loads stay
+// unconditional: a task without M2 reads M a second time with weight 0.
+template <bool kTwo>
+__global__ __launch_bounds__(256, 2) void k_rstencil(const StencilTask* __restrict__ tasks,
                                                   int n_tasks) {
   __shared__ double src[kRsCols * kRsSpan];
   __shared__ int span_lo, span_hi;
@@ -882,15 +886,32 @@ __global__ __launch_bounds__(256) void k_rstencil(const StencilTask* __restrict_
   const int slo = span_lo, span = span_hi - span_lo + 1;  // span <= 0: no taps
   const bool staged = span > 0 && span <= kRsSpan;
   const bool row_ok = a < rg.np;
+  const gptr<const double> m2 = G(tk.M2 ? tk.M2 : tk.M);
+  const double w2 = tk.M2 ? 1.0 : 0.0;
+  // entry (r, c) of the input M (+ M2)
+  auto in_at = [&](size_t off) {
+    return kTwo ? fma(w2, m2[off], G(tk.M)[off]) : G(tk.M)[off];
+  };
   double ld[2 * kRsCols];
-  // loads of group g: rows tid and tid + 256 of the span, 16 columns
+  double ld2[kTwo ? 2 * kRsCols : 1];
+  // loads of group g: rows tid and tid + 256 of the span, 16 columns.  The
+  // loads are unconditional (all in flight at once): a lane outside the span
+  // or the columns reads entry (slo, c0), which exists; LDS entries outside
+  // the span and the columns are never read by the taps.
   auto issue = [&](int g) {
     const int c0 = cw + g * kRsCols, ncc = min(kRsCols, tk.ncols - c0);
+    const size_t safe = (size_t)c0 * tk.ldm + slo;
 #pragma unroll
     for (int cc = 0; cc < kRsCols; ++cc) {
-      const gptr<const double> mc = G(tk.M) + (size_t)(c0 + cc) * tk.ldm + slo;
-      ld[2 * cc] = (cc < ncc && tid < span) ? mc[tid] : 0.0;
-      ld[2 * cc + 1] = (cc < ncc && tid + 256 < span) ? mc[tid + 256] : 0.0;
+      const size_t mc = (size_t)(c0 + cc) * tk.ldm + slo;
+      const size_t o0 = (cc < ncc && tid < span) ? mc + tid : safe;
+      const size_t o1 = (cc < ncc && tid + 256 < span) ? mc + tid + 256 : safe;
+      ld[2 * cc] = G(tk.M)[o0];
+      ld[2 * cc + 1] = G(tk.M)[o1];
+      if constexpr (kTwo) {
+        ld2[2 * cc] = m2[o0];
+        ld2[2 * cc + 1] = m2[o1];
+      }
     }
   };
   if (staged) issue(0);
@@ -900,12 +921,17 @@ __global__ __launch_bounds__(256) void k_rstencil(const StencilTask* __restrict_
       __syncthreads();  // the previous group is no longer read from src
 #pragma unroll
       for (int cc = 0; cc < kRsCols; ++cc) {
-        src[cc * kRsSpan + tid] = ld[2 * cc];
-        src[cc * kRsSpan + tid + 256] = ld[2 * cc + 1];
+        if constexpr (kTwo) {
+          src[cc * kRsSpan + tid] = fma(w2, ld2[2 * cc], ld[2 * cc]);
+          src[cc * kRsSpan + tid + 256] = fma(w2, ld2[2 * cc + 1], ld[2 * cc + 1]);
+        } else {
+          src[cc * kRsSpan + tid] = ld[2 * cc];
+          src[cc * kRsSpan + tid + 256] = ld[2 * cc + 1];
+        }
       }
       for (int e = tid; e < ncc * (span - 512); e += 256) {  // rows 512.. of a long span
         const int w = span - 512, cc = e / w, r = 512 + (e - cc * w);
-        src[cc * kRsSpan + r] = G(tk.M)[(size_t)(c0 + cc) * tk.ldm + slo + r];
+        src[cc * kRsSpan + r] = in_at((size_t)(c0 + cc) * tk.ldm + slo + r);
       }
       __syncthreads();
       if (g + 1 < ngrp) issue(g + 1);
@@ -920,10 +946,10 @@ __global__ __launch_bounds__(256) void k_rstencil(const StencilTask* __restrict_
           for (int q = 0; q < kNS; ++q)
             if (nbr[q] >= 0) acc += cf[q] * src[cc * kRsSpan + nbr[q] - slo];
         } else {
-          const gptr<const double> mc = G(tk.M) + (size_t)(c0 + cc) * tk.ldm;
+          const size_t mc = (size_t)(c0 + cc) * tk.ldm;
 #pragma unroll
           for (int q = 0; q < kNS; ++q)
-            if (nbr[q] >= 0) acc += cf[q] * mc[nbr[q]];
+            if (nbr[q] >= 0) acc += cf[q] * in_at(mc + nbr[q]);
         }
         acc *= tk.alpha;
       }
@@ -982,9 +1008,12 @@ __global__ __launch_bounds__(256) void k_sparse_add(const StencilTask* __restric
 }
 
 void launch_rstencil(const StencilTask* d_tasks, int n_tasks, int total_tiles, int max_np,
-                     hipStream_t s) {
+                     int two, hipStream_t s) {
   if (total_tiles <= 0) return;
-  k_rstencil<<<total_tiles, 256, 0, s>>>(d_tasks, n_tasks);
+  if (two)
+    k_rstencil<true><<<total_tiles, 256, 0, s>>>(d_tasks, n_tasks);
+  else
+    k_rstencil<false><<<total_tiles, 256, 0, s>>>(d_tasks, n_tasks);
   if (max_np > 0) k_sparse_add<<<dim3((max_np + 255) / 256, n_tasks), 256, 0, s>>>(d_tasks);
 }
 

@@ -224,6 +224,7 @@ int gj2_tiles(int np, int w);
 //   out = alpha * Q_R * op(M) + gamma * Q_R + diag(dv) (+ I on pad) + beta * In
 struct StencilTask {
   const double* M;     // np x ncols, column-major (ldm); may be null (alpha = 0)
+  const double* M2;    // optional second input of the same shape: Q_R (M + M2)
   const double* In;    // optional (beta)
   double* out;
   int ldm, ldin, ldout;
@@ -239,9 +240,10 @@ struct StencilTask {
 };
 // output tiles of one task (np rows x ncols)
 int rstencil_tiles(int np, int ncols);
-// max_np > 0: also add the sparse terms (gamma Q_R, diag(dv), pad identity)
+// max_np > 0: also add the sparse terms (gamma Q_R, diag(dv), pad identity);
+// two: some task has a second input M2
 void launch_rstencil(const StencilTask* d_tasks, int n_tasks, int total_tiles, int max_np,
-                     hipStream_t s);
+                     int two, hipStream_t s);
 // copy the lower triangle of each task's M (np x np) onto its upper triangle
 void launch_mirror(const InvTask* d_tasks, int n_tasks, int max_np, hipStream_t s);
 
