@@ -222,6 +222,44 @@ def test_error_codes():
     B.rbmc_ctx_destroy(ctx)
 
 
+def test_empty_inputs_and_column_limit():
+    """Zero columns: the call succeeds and leaves its outputs untouched.  More
+    than 65535 columns: rejected before any work (the buffers passed are far
+    smaller and are never read).  An estimate with no samples is the
+    deterministic part: bit-identical to the estimator run on no samples, and
+    equal to the oracle's."""
+    wl = wl_of(10, 4, 2, 1, 1)
+    say("empty inputs and column limit")
+    gm = B.Model(wl)
+    n, n_obs = gm.n, gm.n_obs
+    x = torch.full((1, n), 7.0, dtype=torch.float64, device="cuda")
+    y = torch.full((1, n), 3.0, dtype=torch.float64, device="cuda")
+    assert B.rbmc_apply_op(gm.m, B.RBMC_OP_Q, x, y, 0) == B.RBMC_OK
+    for bad in (-1, 65536):
+        with pytest.raises(B.RbmcError) as e:
+            B.rbmc_apply_op(gm.m, B.RBMC_OP_Q, x, y, bad)
+        assert e.value.status == B.RBMC_E_ARG
+    z = torch.ones((1, n + n_obs), dtype=torch.float64, device="cuda")
+    xs = torch.full((1, n), 5.0, dtype=torch.float64, device="cuda")
+    st, _rep = B.rbmc_sample(gm.m, B.make_opts(0), z, xs)
+    assert st == B.RBMC_OK
+    with pytest.raises(B.RbmcError) as e:
+        B.rbmc_sample(gm.m, B.make_opts(65536), z, xs)
+    assert e.value.status == B.RBMC_E_ARG
+    torch.cuda.synchronize()
+    assert torch.all(y == 3.0) and torch.all(xs == 5.0)
+    d_est = torch.empty(n, dtype=torch.float64, device="cuda")
+    st, tr_est, _rep = B.rbmc_estimate(gm.m, B.make_opts(0, grad_mask=0b1111), None, 0, d_est, 4)
+    assert st == B.RBMC_OK
+    d_det, tr_det, st, _rep = gm.estimate_from_samples(None, grad_mask=0b1111)
+    assert torch.equal(d_est, d_det) and tr_est == tr_det
+    M = oracle_model(wl)
+    ref = M.rbmc(O.grid_cores(10, 10, 4, 2, 1, 1), 2, 1, None, 0b1111)
+    np.testing.assert_allclose(d_est.cpu().numpy(), ref["diag_det"], rtol=RTOL)
+    np.testing.assert_allclose(tr_est, ref["trace_det"], rtol=RTOL)
+    gm.close()
+
+
 # Mixed precision: FP32 matrix-core products in the correction solves, FP64
 # factorizations.  Every entry of Q_AA^-1 and of the corrections
 # then carries a relative error of about 1e-6 (operand rounding to FP32), so
