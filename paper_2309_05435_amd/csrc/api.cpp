@@ -950,8 +950,8 @@ void build_twosided(ChainSet& cs, Program& pg, Arena& a, bool bj = false) {
 }
 
 // Twisted block solve Q_AA mu = r with the two-sided factors, meeting at the
-// first core step k = lc0 (r_t in pan[c][t] for every t; cs.ytmp[c] is the
-// work panel):
+// first core step k = lc0 (r_t in pan[c][t] for every t; cs.ytmp[c] and
+// cs.tmp[c] are the work panels):
 //   forward  u_t = F_t (r_t - q_o Q_R u_{t-1}),             t < k;
 //   backward v_t = G_t (r_t - q_o Q_R v_{t+1}),             t > k;
 //   twist    mu_k = Sigma_kk (r_k - q_o Q_R u_{k-1} - q_o Q_R v_{k+1});
@@ -962,8 +962,15 @@ void build_twosided(ChainSet& cs, Program& pg, Arena& a, bool bj = false) {
 // whole chain (the preconditioned residual).
 void build_twisted_solve(ChainSet& cs, int n_k, Program& pg, Arena& a, int mixed,
                          bool bj = false) {
-  auto stencil_into_ytmp = [&](size_t c, const double* M, double alpha, const double* In,
-                               StencilList& sl) {
+  // Work panels: ytmp for the forward (downward) direction; for the backward
+  // (upward) one the chain's Schur temporary, idle during the solves, when
+  // n_k <= np, so both directions of a round share one stencil and one GEMM
+  // launch.  Otherwise the directions take turns with ytmp.
+  bool pair = true;
+  for (size_t c = 0; c < cs.size(); ++c) pair = pair && n_k <= cs.np[c];
+  auto work = [&](size_t c, int dir) { return (dir == 1 && pair) ? cs.tmp[c] : cs.ytmp[c]; };
+  auto stencil_into = [&](size_t c, double* y, const double* M, double alpha, const double* In,
+                          StencilList& sl) {
     StencilTask st = stask(cs, c);
     st.M = M;
     st.ldm = cs.np[c];
@@ -971,39 +978,48 @@ void build_twisted_solve(ChainSet& cs, int n_k, Program& pg, Arena& a, int mixed
     st.In = In;
     st.ldin = cs.np[c];
     st.beta = In ? 1.0 : 0.0;
-    st.out = cs.ytmp[c];
+    st.out = y;
     st.ldout = cs.np[c];
     st.ncols = n_k;
     sl.add(st, cs.np[c], cs.nb[c]);
   };
-  auto gemm = [&](size_t c, const double* Sinv, const double* Cin, double* C, double alpha,
-                  double beta, GemmList& gl) {
+  auto gemm = [&](size_t c, const double* y, const double* Sinv, const double* Cin, double* C,
+                  double alpha, double beta, GemmList& gl) {
     const int np = cs.np[c], nb = cs.nb[c];
-    gl.add(Sinv, cs.ytmp[c], Cin, C, np, n_k, np, np, np, np, alpha, beta, 1, 0, nb, nb);
+    gl.add(Sinv, y, Cin, C, np, n_k, np, np, np, np, alpha, beta, 1, 0, nb, nb);
+  };
+  // one round: list 0 holds both directions when paired, else list dir
+  auto emit = [&](StencilList* sl, GemmList* gl) {
+    for (int dir = 0; dir < 2; ++dir) {
+      pg.stencil(a, sl[dir]);
+      pg.gemm(a, gl[dir]);
+    }
   };
   for (int t = 0; t < cs.maxT; ++t) {  // forward and backward partial solutions
+    StencilList sl[2];
+    GemmList gl[2];
+    gl[0].mixed = gl[1].mixed = mixed;
     for (int dir = 0; dir < 2; ++dir) {
-      StencilList sl;
-      GemmList gl;
-      gl.mixed = mixed;
+      const int li = pair ? 0 : dir;
       for (size_t c = 0; c < cs.size(); ++c) {
         const Chain& ch = cs.chains[c];
         const double qo = cs.owner[c]->co.qo;
         const int k = twist_of(ch, bj);
+        double* y = work(c, dir);
         if (dir == 0) {
           if (t >= k) continue;
-          stencil_into_ytmp(c, t > 0 ? cs.pan[c][t - 1] : nullptr, -qo, cs.pan[c][t], sl);
-          gemm(c, fblock(cs, c, t), nullptr, cs.pan[c][t], 1.0, 0.0, gl);
+          stencil_into(c, y, t > 0 ? cs.pan[c][t - 1] : nullptr, -qo, cs.pan[c][t], sl[li]);
+          gemm(c, y, fblock(cs, c, t), nullptr, cs.pan[c][t], 1.0, 0.0, gl[li]);
         } else {
           const int tt = ch.T - 1 - t;
           if (tt <= k) continue;
-          stencil_into_ytmp(c, tt < ch.T - 1 ? cs.pan[c][tt + 1] : nullptr, -qo, cs.pan[c][tt], sl);
-          gemm(c, gblock(cs, c, tt, bj), nullptr, cs.pan[c][tt], 1.0, 0.0, gl);
+          stencil_into(c, y, tt < ch.T - 1 ? cs.pan[c][tt + 1] : nullptr, -qo, cs.pan[c][tt],
+                       sl[li]);
+          gemm(c, y, gblock(cs, c, tt, bj), nullptr, cs.pan[c][tt], 1.0, 0.0, gl[li]);
         }
       }
-      pg.stencil(a, sl);
-      pg.gemm(a, gl);
     }
+    emit(sl, gl);
   }
   {  // twist
     StencilList s1, s2;
@@ -1013,41 +1029,43 @@ void build_twisted_solve(ChainSet& cs, int n_k, Program& pg, Arena& a, int mixed
       const Chain& ch = cs.chains[c];
       const double qo = cs.owner[c]->co.qo;
       const int k = twist_of(ch, bj);
-      stencil_into_ytmp(c, k > 0 ? cs.pan[c][k - 1] : nullptr, -qo, cs.pan[c][k], s1);
-      if (k + 1 < ch.T) stencil_into_ytmp(c, cs.pan[c][k + 1], -qo, cs.ytmp[c], s2);
-      gemm(c, sigblock(cs, c, bj), nullptr, cs.pan[c][k], 1.0, 0.0, gl);
+      double* y = cs.ytmp[c];
+      stencil_into(c, y, k > 0 ? cs.pan[c][k - 1] : nullptr, -qo, cs.pan[c][k], s1);
+      if (k + 1 < ch.T) stencil_into(c, y, cs.pan[c][k + 1], -qo, y, s2);
+      gemm(c, y, sigblock(cs, c, bj), nullptr, cs.pan[c][k], 1.0, 0.0, gl);
     }
     pg.stencil(a, s1);
     pg.stencil(a, s2);
     pg.gemm(a, gl);
   }
   // outward: subdomains one step below the core and up to one above it;
-  // block-Jacobi chains down to step 0 and up to T-1 (down and up steps of
-  // the same distance share the launches; they use the work panel in turn)
+  // block-Jacobi chains down to step 0 and up to T-1 (the down and up steps
+  // of the same distance form one round)
   for (int d = 1; d < cs.maxT; ++d) {
+    StencilList sl[2];
+    GemmList gl[2];
+    gl[0].mixed = gl[1].mixed = mixed;
     for (int dir = 0; dir < 2; ++dir) {
-      StencilList sl;
-      GemmList gl;
-      gl.mixed = mixed;
+      const int li = pair ? 0 : dir;
       for (size_t c = 0; c < cs.size(); ++c) {
         const Chain& ch = cs.chains[c];
         const int k = twist_of(ch, bj);
         const double qo = cs.owner[c]->co.qo;
+        double* y = work(c, dir);
         if (dir == 0) {
           const int t = k - d;
           if (t < 0 || (!bj && d > 1)) continue;
-          stencil_into_ytmp(c, cs.pan[c][t + 1], qo, nullptr, sl);
-          gemm(c, fblock(cs, c, t), cs.pan[c][t], cs.pan[c][t], -1.0, 1.0, gl);
+          stencil_into(c, y, cs.pan[c][t + 1], qo, nullptr, sl[li]);
+          gemm(c, y, fblock(cs, c, t), cs.pan[c][t], cs.pan[c][t], -1.0, 1.0, gl[li]);
         } else {
           const int t = k + d;
           if (t >= ch.T || (!bj && t > chain_lc1(ch) + 1)) continue;
-          stencil_into_ytmp(c, cs.pan[c][t - 1], qo, nullptr, sl);
-          gemm(c, gblock(cs, c, t, bj), cs.pan[c][t], cs.pan[c][t], -1.0, 1.0, gl);
+          stencil_into(c, y, cs.pan[c][t - 1], qo, nullptr, sl[li]);
+          gemm(c, y, gblock(cs, c, t, bj), cs.pan[c][t], cs.pan[c][t], -1.0, 1.0, gl[li]);
         }
       }
-      pg.stencil(a, sl);
-      pg.gemm(a, gl);
     }
+    emit(sl, gl);
   }
 }
 

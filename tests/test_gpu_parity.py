@@ -106,6 +106,22 @@ def test_estimator_from_samples_matches_oracle(case):
     gm.close()
 
 
+def test_more_samples_than_block_order():
+    """n_k > n_p: the two directions of the correction solves take turns with
+    one work panel instead of sharing launches (the block order is 64 here)."""
+    wl = wl_of(8, 6, 2, 1, 1)
+    say("samples > block order")
+    M = oracle_model(wl)
+    lab = O.grid_cores(8, 8, 6, 2, 1, 1)
+    x = normals((150, M.n), 23)
+    ref = M.rbmc(lab, 2, 1, x, 0b1111)
+    gm = B.Model(wl)
+    diag, tr, st, rep = gm.estimate_from_samples(dev(x), grad_mask=0b1111)
+    np.testing.assert_allclose(diag.cpu().numpy(), ref["diag"], rtol=RTOL)
+    np.testing.assert_allclose(tr, ref["trace"], rtol=RTOL)
+    gm.close()
+
+
 @pytest.mark.parametrize("case", [(12, 8, 3, 1, 1), (14, 9, 3, 2, 1), (11, 7, 2, 2, 2)])
 def test_sampler_matches_exact_solve(case):
     """PCG x = Q^-1 F z against the oracle's banded-Cholesky solve; the error bound
