@@ -1,6 +1,6 @@
 """GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
 same seeded inputs.  FP64 throughout; the bar is 1e-10 relative for the
-estimator from given samples (spec FP64 tolerance) and a
+estimator from given samples and a
 residual-derived bound for quantities that pass through PCG."""
 import math
 import sys
@@ -158,6 +158,26 @@ def test_sampler_with_other_block_jacobi_blocks(pc):
     gm = B.Model(wl, pc=pc)
     x, st, rep = gm.sample(dev(z), rtol=1e-13, maxit=5000)
     assert st == B.RBMC_OK
+    err = np.linalg.norm(x.cpu().numpy() - x_ref, axis=1) / np.linalg.norm(x_ref, axis=1)
+    assert err.max() < 1e-9
+    gm.close()
+
+
+@pytest.mark.parametrize("m,T", [(16, 6), (21, 5), (32, 3)])
+def test_single_chain_sampler(m, T):
+    """One block-Jacobi chain over the whole domain (the exact preconditioner):
+    its inversions of order 256, 448 (a half-width last sweep step) and 1024
+    (eight steps) run the two-block twisted factorization with rank-128
+    sweeps.  The samples match the oracle's exact solve and PCG converges at
+    once."""
+    wl = wl_of(m, T, 2, 1, 1)
+    say("single-chain sampler", m, T)
+    M = oracle_model(wl)
+    z = normals((40, M.n + M.n_obs), 33)
+    x_ref = M.sample(z)
+    gm = B.Model(wl, pc=(1, 1, 1))
+    x, st, rep = gm.sample(dev(z), rtol=1e-12, maxit=50)
+    assert st == B.RBMC_OK and rep.pcg_it_max <= 2
     err = np.linalg.norm(x.cpu().numpy() - x_ref, axis=1) / np.linalg.norm(x_ref, axis=1)
     assert err.max() < 1e-9
     gm.close()
