@@ -309,16 +309,18 @@ def main():
         # workload, or its cached choice), outside the timed steps
         tr_ = B.rbmc_autotune(gm.ctx, [gm.m], opts, [z], args.tune_cache)
         tune = tune_dict(tr_)
-    for _ in range(args.warmup):
+    for i in range(args.warmup):
         step()
+        print(f"warm-up step {i + 1} of {args.warmup} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     B.rbmc_ctx_profile(gm.ctx, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     reps = []
-    for _ in range(args.steps):
+    for i in range(args.steps):
         st, tr, rep = step()
         reps.append(rep.as_dict())
+        print(f"step {i + 1} of {args.steps} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     stats = {B.KF_NAMES[f]: B.rbmc_ctx_profile_read(gm.ctx, f) for f in range(B.RBMC_KF_COUNT)}
