@@ -104,12 +104,14 @@ WORKLOADS = {
     "slab64": _wl(2, name="slab64", m=64, T=32, range_=0.2, rho=0.95, tau=1.0, sigma=0.5,
                   obs_frac=0.2, n_tslabs=16, n_tiles=1, n_l=2, n_k=500, rtol=1e-8,
                   pc=(1, 1, 1)),
-    # block-Jacobi measured on MI355X (8 samples): the 512 cores need 1925 PCG
-    # iterations, 2 slabs x 8 x 8 tiles 1324, the whole 64-step chain of each
-    # 32 x 32 tile 412 (4.4x faster sampling)
+    # block-Jacobi measured on MI355X: the 512 cores need 1925 PCG iterations
+    # (8 samples), 2 slabs x 8 x 8 tiles 1324; whole 64-step chains of spatial
+    # tiles (100 samples): 64 x 32 tiles 380 iterations / 40.2 s of sampling,
+    # 32 x 32 412 / 27.8 s, 16 x 16 575 / 22.4 s, 16 x 8 726 / 30.0 s, 8 x 8
+    # 841 / 46.0 s (the cost of an iteration grows with the block order)
     "tile256": _wl(4, name="tile256", m=256, T=64, range_=0.1, rho=0.9, tau=1.0, sigma=0.5,
                    obs_frac=0.1, n_tslabs=8, n_tiles=8, n_l=1, n_k=100, rtol=1e-8,
-                   pc=(1, 8, 8)),
+                   pc=(1, 16, 16)),
     "tile512": _wl(5, name="tile512", m=512, T=48, range_=0.05, rho=0.98, tau=1.0, sigma=0.5,
                    obs_frac=0.05, n_tslabs=3, n_tiles=8, n_l=2, n_k=200, rtol=1e-8),
 }

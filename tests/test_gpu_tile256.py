@@ -35,7 +35,7 @@ def say(*a):
 @pytest.fixture(scope="module")
 def model():
     say("tile256: building the model")
-    gm = B.Model(WL)  # the workload's block-Jacobi shape (whole time chains of 32 x 32 tiles)
+    gm = B.Model(WL)  # the workload's block-Jacobi shape (whole time chains of 16 x 16 tiles)
     yield gm, WL.mask()
     gm.close()
 
