@@ -5,7 +5,9 @@
 //   (Q x)_t = Q_s (q_{t,t-1} x_{t-1} + q_{t,t} x_t + q_{t,t+1} x_{t+1}) + D_t x_t.
 // A workgroup owns a 32 x 16 spatial tile of one column (model, sample) and
 // walks through time, keeping the three time layers of the tile (with a halo
-// of 2) in LDS, so each x value is read from HBM once per application.
+// of 2) in LDS, so each x value is read from HBM once per application.  The
+// spatial stencil coefficients of a thread's two nodes do not depend on time:
+// they are read once, into registers, before the walk.
 //
 // All kernels work on column sets: a column is one sample of one model, with
 // its own length and offset, so one launch serves many uneven models.
@@ -65,28 +67,60 @@ __global__ __launch_bounds__(NTHR) void k_space_time_op(ColSet cs, const double*
   const double* xk = x + (KIND == 5 ? cs.in_off[col] : cs.off[col]);
   double* yk = y + cs.off[col];
   const int lx = tid % TX, ly = tid / TX;  // ly in [0, 8): rows ly and ly + 8
+  // stencil coefficients of the thread's two nodes (13 for Q_s, 5 for K, F_s)
+  constexpr int NC = (KIND == 0 || KIND == 2 || KIND == 3) ? kNS : (KIND == 4 ? 1 : kN5);
+  const double* __restrict__ cf_src = (KIND == 1) ? m.kk : (KIND == 5) ? m.fs : m.qs;
+  double cf[2][NC];
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+    const int gx = bx + lx, gy = by + ly + 8 * half;
+    const bool in = gx < m.mx && gy < m.my;
+    const int s = in ? gy * m.mx + gx : 0;
+#pragma unroll
+    for (int q = 0; q < NC; ++q) cf[half][q] = (KIND != 4 && in) ? cf_src[(size_t)q * m.ns + s] : 0.0;
+  }
 
-  auto load_layer = [&](int buf, int t) {
-    for (int e = tid; e < HX * HY; e += NTHR) {
-      int hx = e % HX, hy = e / HX;
-      int gx = bx + hx - 2, gy = by + hy - 2;
-      double v = 0.0;
-      if (t >= 0 && t < m.T && gx >= 0 && gx < m.mx && gy >= 0 && gy < m.my)
-        v = xk[(size_t)t * m.ns + gy * m.mx + gx];
-      slot[buf][hy][hx] = v;
+  // A layer (the tile with its halo of 2) is fetched into registers one step
+  // ahead of its store to LDS, so its loads are in flight during a step's
+  // arithmetic.  The loads are unconditional: entries outside the grid or
+  // the time range read element 0 and are stored as 0.
+  constexpr int NL = (HX * HY + NTHR - 1) / NTHR;  // entries per thread
+  double pre[NL];
+  bool pre_ok[NL];
+  auto fetch = [&](int t) {
+#pragma unroll
+    for (int j = 0; j < NL; ++j) {
+      const int e = tid + NTHR * j;
+      const int hx = e % HX, hy = e / HX;
+      const int gx = bx + hx - 2, gy = by + hy - 2;
+      const bool ok = e < HX * HY && t >= 0 && t < m.T && gx >= 0 && gx < m.mx && gy >= 0 &&
+                      gy < m.my;
+      pre[j] = xk[ok ? (size_t)t * m.ns + gy * m.mx + gx : 0];
+      pre_ok[j] = ok;
+    }
+  };
+  auto put = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < NL; ++j) {
+      const int e = tid + NTHR * j;
+      if (e < HX * HY) slot[buf][e / HX][e % HX] = pre_ok[j] ? pre[j] : 0.0;
     }
   };
 
   double acc = 0.0;
   // the layer of step t lives in slot t mod 3 (step -1 in slot 2)
   if (KIND != 4) {
-    load_layer(2, -1);
-    load_layer(0, 0);
+    fetch(-1);
+    put(2);
+    fetch(0);
+    put(0);
+    fetch(1);
   }
   for (int t = 0; t < m.T; ++t) {
     const int bm = (t + 2) % 3, b0 = t % 3, bp = (t + 1) % 3;  // t-1, t, t+1
     if (KIND != 4) {
-      load_layer(bp, t + 1);
+      put(bp);     // layer t + 1, fetched during the previous step
+      fetch(t + 2);  // zeros beyond the last step
       __syncthreads();
       double wm, w0, wp;
       time_weights(m, KIND, t, wm, w0, wp);
@@ -106,13 +140,13 @@ __global__ __launch_bounds__(NTHR) void k_space_time_op(ColSet cs, const double*
         double v = 0.0;
         if (KIND == 0 || KIND == 2 || KIND == 3) {
 #pragma unroll
-          for (int q = 0; q < kNS; ++q) v += m.qs[(size_t)q * m.ns + s] * w[hy + kSdy[q]][hx + kSdx[q]];
+          for (int q = 0; q < kNS; ++q) v += cf[half][q] * w[hy + kSdy[q]][hx + kSdx[q]];
         } else if (KIND == 1) {
 #pragma unroll
-          for (int q = 0; q < kN5; ++q) v += m.kk[(size_t)q * m.ns + s] * w[hy + kSdy[q]][hx + kSdx[q]];
+          for (int q = 0; q < kN5; ++q) v += cf[half][q] * w[hy + kSdy[q]][hx + kSdx[q]];
         } else if (KIND == 5) {
 #pragma unroll
-          for (int q = 0; q < kN5; ++q) v += m.fs[(size_t)q * m.ns + s] * w[hy + kSdy[q]][hx + kSdx[q]];
+          for (int q = 0; q < kN5; ++q) v += cf[half][q] * w[hy + kSdy[q]][hx + kSdx[q]];
           int r = m.obs_rank[i];
           if (r >= 0) v += sqrt(m.dvec[i]) * xk[(size_t)m.n + r];
         }
