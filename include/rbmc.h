@@ -94,7 +94,31 @@ typedef struct {
  * extra PCG iterations), the operators and the diagonal/trace accumulation
  * stay FP64. */
 enum { RBMC_FP64 = 0, RBMC_MIXED = 1 };
-enum { RBMC_PC_BJ = 0, RBMC_PC_BJ_LEARNED = 1 };
+/* Preconditioners of the PCG sampler (Sec. 3.3):
+ *   RBMC_PC_BJ          block Jacobi over the blocks of rbmc_decomp_desc (the
+ *                       plain method), each block factored block-tridiagonally;
+ *   RBMC_PC_BJ_LEARNED  block Jacobi with the learned correction below;
+ *   RBMC_PC_SPECTRAL    M = Q_t (x) Q_s + dbar I, dbar = n_obs / (sigma^2 n):
+ *                       the prior precision with the observation term spread
+ *                       evenly, applied exactly in the basis that diagonalizes
+ *                       it (2-D DCT-II in space, which diagonalizes the Neumann
+ *                       grid Laplacian and hence Q_s; one tridiagonal solve in
+ *                       time per spatial frequency).  Not in the paper. */
+enum { RBMC_PC_BJ = 0, RBMC_PC_BJ_LEARNED = 1, RBMC_PC_SPECTRAL = 2 };
+/* How the selected entries of Q_AA^-1 and the correction solves of a
+ * subdomain A = Omega_p* are computed (the estimator's values are the same
+ * up to rounding either way):
+ *   RBMC_SEL_BLOCKTRI  two-sided block-tridiagonal inversion of Q_AA over its
+ *                      time steps (dense spatial blocks; Alg. 4's subdomain
+ *                      solve as a block-tridiagonal factorization);
+ *   RBMC_SEL_KRON      Q_AA = Q_t|A (x) Q_s|R + D_A is a Kronecker product plus
+ *                      a diagonal of rank n_o (the observed nodes of A), so
+ *                      Q_AA^-1 = V (x) S^-1 - Zt Y Zt^T (Woodbury) with S =
+ *                      Q_s|R inverted once per spatial region (shared by all
+ *                      time slabs), V = (Q_t|A)^-1 and Y the inverse of the
+ *                      n_o x n_o capacitance matrix;
+ *   RBMC_SEL_AUTO      the one with fewer dense flops for the call's models. */
+enum { RBMC_SEL_AUTO = 0, RBMC_SEL_BLOCKTRI = 1, RBMC_SEL_KRON = 2 };
 enum { RBMC_GRAD_LOGKAPPA = 1, RBMC_GRAD_LOGTAU = 2, RBMC_GRAD_RHO = 4, RBMC_GRAD_LOGSIGMA = 8 };
 
 typedef struct {
@@ -103,9 +127,14 @@ typedef struct {
   int32_t pcg_maxit;  /* > 0 */
   double pcg_rtol;    /* per-sample ||b - Q x||_2 / ||b||_2 target, > 0 */
   int32_t precision;  /* RBMC_FP64 | RBMC_MIXED */
-  int32_t precond;    /* RBMC_PC_BJ | RBMC_PC_BJ_LEARNED */
+  int32_t precond;    /* RBMC_PC_BJ | RBMC_PC_BJ_LEARNED | RBMC_PC_SPECTRAL */
   uint32_t grad_mask; /* RBMC_GRAD_* bits; traces are written in bit order */
-  int32_t sample_chunk; /* reserved, 0 */
+  int32_t sample_chunk; /* rbmc_estimate with RBMC_SEL_KRON: samples drawn and
+                           corrected per pass (0: all at once); the estimator is
+                           a sum over samples (Alg. 4), so the passes add up to
+                           the same result while the sampler's workspace holds
+                           one pass.  Other calls: must be 0 or >= n_samples */
+  int32_t method;     /* RBMC_SEL_* */
 } rbmc_est_opts;
 
 typedef struct {
@@ -128,7 +157,10 @@ typedef struct {
  * core steps are enqueued by their own host thread, and the given stream
  * waits for all of it.  RBMC_OVERLAP=0 runs everything one step after the other on
  * the given stream; RBMC_LAUNCH_THREADS=1 enqueues all streams from the
- * calling thread. */
+ * calling thread.  The Kronecker method (RBMC_SEL_KRON) runs on the given
+ * stream, one batch of subdomains at a time, each batch as large as the free
+ * device memory allows (at most RBMC_KRON_BATCH_BYTES bytes of workspace when
+ * that variable is set; a single subdomain always forms a batch). */
 rbmc_status rbmc_ctx_create(int device, void* hip_stream, rbmc_ctx** out);
 void rbmc_ctx_destroy(rbmc_ctx* ctx);
 
@@ -178,10 +210,25 @@ rbmc_status rbmc_estimate_from_samples(rbmc_model* m, const rbmc_est_opts* opts,
                                        double* diag_out, double* trace_out, rbmc_report* rep);
 
 /* rbmc_sample followed by rbmc_estimate_from_samples (the full hot path).
- * z: device (n + n_obs) x n_samples standard normals (required; seed is
- * reserved).  Workspace for x is held by the model. */
+ * z: device (n + n_obs) x n_samples standard normals, or NULL: then column k
+ * of z is elements [k (n + n_obs), (k + 1)(n + n_obs)) of the device stream
+ * of `seed` (rbmc_normals), drawn per sample pass without storing all of z
+ * (needs the Kronecker method; RBMC_E_UNSUPPORTED otherwise).  With
+ * opts->sample_chunk = c < n_samples (Kronecker method) the samples are drawn
+ * and corrected in passes of c columns; the result equals the one-pass
+ * estimate up to summation order.  Workspace for x is held by the context. */
 rbmc_status rbmc_estimate(rbmc_model* m, const rbmc_est_opts* opts, const double* z, uint64_t seed,
                           double* diag_out, double* trace_out, rbmc_report* rep);
+
+/* Standard normals of the stream of `seed`: out[i] = element offset + i
+ * (i < count).  Element e is the first (e even) or second (e odd) value of
+ * the Box-Muller transform of pair e / 2, whose two 53-bit uniforms come from
+ * the four words of Philox4x32-10 (Salmon et al., SC11) with key = seed and
+ * counter = (e / 2, 0, 0): any element depends only on (seed, e).
+ * out: device, count doubles; ordered on the context stream (synchronized).
+ * RBMC_E_ARG for count < 0. */
+rbmc_status rbmc_normals(rbmc_ctx* ctx, uint64_t seed, uint64_t offset, int64_t count,
+                         double* out);
 
 /* rbmc_estimate for n_models independent models of one context at once
  * (the estimator of Alg. 3/4 applied to each model; models may differ in
@@ -335,7 +382,14 @@ rbmc_status rbmc_plan_query(const rbmc_model_desc* desc, const rbmc_decomp_desc*
  *                        w <= 128 (one workgroup each); flops = sum w^3;
  *   RBMC_KF_OFFDIAG      off-diagonal time-block entries on the stencil
  *                        pattern of the core rows (13 dot products per row);
- *                        bytes = 16 n_b^2 per block pair (each read once).
+ *                        bytes = 16 n_b^2 per block pair (each read once);
+ *   RBMC_KF_DCT          the 2-D DCT-II transforms of the spectral
+ *                        preconditioner run as matrix-core products;
+ *                        flops = 2 m per entry and axis;
+ *   RBMC_KF_KRON_REDUCE  group sums of the Kronecker form (k_kron_reduce);
+ *                        bytes = 24 per entry of X_g (X_g, Z, K_R Z read once);
+ *   RBMC_KF_SPEC_SOLVE   per-frequency tridiagonal solves of the spectral
+ *                        preconditioner; bytes = 16 per entry (read, write).
  * rbmc_ctx_profile(ctx, 1) clears and enables, (ctx, 0) disables;
  * rbmc_ctx_profile_read synchronizes the stream and sums the records. */
 enum {
@@ -348,7 +402,10 @@ enum {
   RBMC_KF_GEMM_SMALL = 6,
   RBMC_KF_INV_SMALL = 7,
   RBMC_KF_OFFDIAG = 8,
-  RBMC_KF_COUNT = 9
+  RBMC_KF_DCT = 9,
+  RBMC_KF_KRON_REDUCE = 10,
+  RBMC_KF_SPEC_SOLVE = 11,
+  RBMC_KF_COUNT = 12
 };
 typedef struct {
   int64_t launches;

@@ -15,7 +15,8 @@ LIB_PATH = os.path.join(HERE, "librbmc.so")
 RBMC_OK, RBMC_W_NOT_CONVERGED = 0, 1
 RBMC_E_ARG, RBMC_E_NOT_SPD, RBMC_E_OOM, RBMC_E_DEVICE, RBMC_E_UNSUPPORTED = -1, -2, -3, -4, -5
 RBMC_FP64, RBMC_MIXED = 0, 1
-RBMC_PC_BJ, RBMC_PC_BJ_LEARNED = 0, 1
+RBMC_PC_BJ, RBMC_PC_BJ_LEARNED, RBMC_PC_SPECTRAL = 0, 1, 2
+RBMC_SEL_AUTO, RBMC_SEL_BLOCKTRI, RBMC_SEL_KRON = 0, 1, 2
 RBMC_GRAD_LOGKAPPA, RBMC_GRAD_LOGTAU, RBMC_GRAD_RHO, RBMC_GRAD_LOGSIGMA = 1, 2, 4, 8
 (RBMC_OP_Q, RBMC_OP_DQ_LOGKAPPA, RBMC_OP_DQ_LOGTAU, RBMC_OP_DQ_RHO, RBMC_OP_DQ_LOGSIGMA,
  RBMC_OP_F) = range(6)
@@ -26,15 +27,16 @@ EXPORTS = ["rbmc_ctx_create", "rbmc_ctx_destroy", "rbmc_model_create", "rbmc_mod
            "rbmc_estimate", "rbmc_estimate_batched", "rbmc_plan_query", "rbmc_ctx_profile",
            "rbmc_ctx_profile_read", "rbmc_precond_train", "rbmc_precond_apply",
            "rbmc_precond_get_weights", "rbmc_precond_set_weights", "rbmc_precond_info",
-           "rbmc_ctx_get_tune", "rbmc_ctx_set_tune", "rbmc_autotune", "rbmc_last_error"]
+           "rbmc_ctx_get_tune", "rbmc_ctx_set_tune", "rbmc_autotune", "rbmc_last_error",
+           "rbmc_normals"]
 RBMC_PC_NWEIGHTS = 15120
 # (cin, cout) of the learned correction's four convolutions, in weight order
 PC_LAYERS = [(2, 16), (16, 16), (16, 16), (16, 1)]
 (RBMC_KF_GEMM, RBMC_KF_SPD_INVERSE, RBMC_KF_SPMM, RBMC_KF_RSTENCIL, RBMC_KF_PANELS,
- RBMC_KF_GEMM_MIXED, RBMC_KF_GEMM_SMALL, RBMC_KF_INV_SMALL, RBMC_KF_OFFDIAG,
- RBMC_KF_COUNT) = range(10)
+ RBMC_KF_GEMM_MIXED, RBMC_KF_GEMM_SMALL, RBMC_KF_INV_SMALL, RBMC_KF_OFFDIAG, RBMC_KF_DCT,
+ RBMC_KF_KRON_REDUCE, RBMC_KF_SPEC_SOLVE, RBMC_KF_COUNT) = range(13)
 KF_NAMES = ["gemm", "spd_inverse", "spmm", "rstencil", "panels", "gemm_mixed", "gemm_small",
-            "inv_small", "offdiag"]
+            "inv_small", "offdiag", "dct", "kron_reduce", "spec_solve"]
 
 
 class rbmc_kernel_stats(C.Structure):
@@ -57,7 +59,7 @@ class rbmc_decomp_desc(C.Structure):
 class rbmc_est_opts(C.Structure):
     _fields_ = [("n_samples", C.c_int32), ("pcg_maxit", C.c_int32), ("pcg_rtol", C.c_double),
                 ("precision", C.c_int32), ("precond", C.c_int32), ("grad_mask", C.c_uint32),
-                ("sample_chunk", C.c_int32)]
+                ("sample_chunk", C.c_int32), ("method", C.c_int32)]
 
 
 class rbmc_train_opts(C.Structure):
@@ -136,6 +138,7 @@ def lib():
         L.rbmc_autotune.argtypes = [vp, C.c_int32, C.POINTER(vp), C.POINTER(rbmc_est_opts),
                                     C.POINTER(vp), C.c_char_p, C.POINTER(rbmc_tune_report)]
         L.rbmc_precond_set_weights.argtypes = [vp, C.POINTER(C.c_float)]
+        L.rbmc_normals.argtypes = [vp, C.c_uint64, C.c_uint64, C.c_int64, vp]
         L.rbmc_last_error.restype = C.c_char_p
         for name in EXPORTS:
             if name not in ("rbmc_ctx_destroy", "rbmc_model_destroy", "rbmc_last_error"):
@@ -283,6 +286,11 @@ def rbmc_precond_set_weights(m, w):
     return check(lib().rbmc_precond_set_weights(m, w.ctypes.data_as(C.POINTER(C.c_float))))
 
 
+def rbmc_normals(ctx, seed, offset, count, out):
+    """out: device float64 tensor with at least count entries."""
+    return check(lib().rbmc_normals(ctx, seed, offset, count, _ptr(out)))
+
+
 def rbmc_plan_query(desc, decomp, p, label_out=None, state_out=None):
     """label_out / state_out: numpy int32 / uint8 arrays of length n (host)."""
     lp = None if label_out is None else label_out.ctypes.data_as(C.c_void_p)
@@ -312,8 +320,9 @@ def make_desc(mx, my, T, h, theta, mask):
 
 
 def make_opts(n_samples, pcg_maxit=2000, pcg_rtol=1e-8, grad_mask=0b111,
-              precision=RBMC_FP64, precond=RBMC_PC_BJ):
-    return rbmc_est_opts(n_samples, pcg_maxit, pcg_rtol, precision, precond, grad_mask, 0)
+              precision=RBMC_FP64, precond=RBMC_PC_BJ, method=RBMC_SEL_AUTO, sample_chunk=0):
+    return rbmc_est_opts(n_samples, pcg_maxit, pcg_rtol, precision, precond, grad_mask,
+                         sample_chunk, method)
 
 
 def make_train_opts(n_pairs=2000, epochs=5, batch=8, lr=1e-3, seed=1):
@@ -367,24 +376,31 @@ class Model:
         rbmc_apply_op(self.m, op, x, y, n_rhs)
         return y
 
-    def sample(self, z, rtol=1e-8, maxit=5000):
+    def sample(self, z, rtol=1e-8, maxit=5000, precond=RBMC_PC_BJ):
         z = z.contiguous()
         x = self.torch.empty((z.shape[0], self.n), dtype=self.torch.float64, device=self.dev)
-        st, rep = rbmc_sample(self.m, make_opts(z.shape[0], maxit, rtol), z, x)
+        st, rep = rbmc_sample(self.m, make_opts(z.shape[0], maxit, rtol, precond=precond), z, x)
         return x, st, rep
 
-    def estimate_from_samples(self, x, grad_mask=0b111):
+    def estimate_from_samples(self, x, grad_mask=0b111, method=RBMC_SEL_AUTO,
+                              precision=RBMC_FP64):
         n_k = 0 if x is None else x.shape[0]
         diag = self.torch.empty(self.n, dtype=self.torch.float64, device=self.dev)
         st, tr, rep = rbmc_estimate_from_samples(
-            self.m, make_opts(n_k, grad_mask=grad_mask), None if x is None else x.contiguous(),
-            diag, popcount(grad_mask))
+            self.m, make_opts(n_k, grad_mask=grad_mask, method=method, precision=precision),
+            None if x is None else x.contiguous(), diag, popcount(grad_mask))
         return diag, tr, st, rep
 
-    def estimate(self, z, grad_mask=0b111, rtol=1e-8, maxit=5000):
+    def estimate(self, z, grad_mask=0b111, rtol=1e-8, maxit=5000, precond=RBMC_PC_BJ,
+                 method=RBMC_SEL_AUTO, precision=RBMC_FP64, sample_chunk=0, n_samples=None,
+                 seed=0):
+        """z: (n_k, n + n_obs) device tensor, or None for device normals drawn
+        from seed (then n_samples gives n_k)."""
         diag = self.torch.empty(self.n, dtype=self.torch.float64, device=self.dev)
-        st, tr, rep = rbmc_estimate(self.m, make_opts(z.shape[0], maxit, rtol, grad_mask),
-                                    z.contiguous(), 0, diag, popcount(grad_mask))
+        nk = z.shape[0] if z is not None else n_samples
+        opts = make_opts(nk, maxit, rtol, grad_mask, precision, precond, method, sample_chunk)
+        st, tr, rep = rbmc_estimate(self.m, opts, None if z is None else z.contiguous(), seed,
+                                    diag, popcount(grad_mask))
         return diag, tr, st, rep
 
 

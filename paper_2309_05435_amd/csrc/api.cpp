@@ -167,6 +167,12 @@ struct rbmc_ctx {
   double* epart = nullptr;     // estimator partial sums
   size_t epart_len = 0;
   Pool epool;
+  // workspace of the Kronecker method (a batch of subdomains at a time)
+  Pool kws;
+  char* kws_base = nullptr;
+  size_t kws_cap = 0;
+  size_t kron_batch_cap = 0;  // upper bound of a batch's workspace (0: free memory)
+  Pool kbank;  // Y of every subdomain and the deterministic diagonals, kept across sample passes
   // scheduling of rbmc_estimate*: overlap the sampler with the subdomain
   // factorization + core steps on further streams (else one after the
   // other on the context stream), and enqueue the two streams from two host
@@ -220,6 +226,8 @@ struct rbmc_ctx {
     if (work) (void)hipStreamDestroy(work);
     ws.release();
     epool.release();
+    kws.release();
+    kbank.release();
   }
 };
 
@@ -296,8 +304,35 @@ struct rbmc_model {
   Coefs co;
   int n_obs = 0;
   Pool pool;      // model-lifetime allocations
-  Pool work;      // panels (sample-count dependent)
-  int work_nk = -1;
+  // chain sets are allocated on first use: the block-Jacobi chains by the
+  // block-Jacobi preconditioner, the subdomain chains by the block-tridiagonal
+  // method (at 512 x 512 x 48 either would exceed the device memory)
+  bool bj_alloc = false, sub_alloc = false;
+  Pool work_bj, work_sub;  // panels (sample-count dependent)
+  int work_bj_nk = -1, work_sub_nk = -1;
+  // Kronecker method: per subdomain, the observed slots grouped by local time
+  // step (each group padded to a multiple of 16, the total to 64); per region,
+  // S^-1 = (Q_s|R)^-1 and its node quantities
+  struct KronSub {
+    int chain = 0, TA = 0, nc = 0, nobs = 0;
+    std::vector<int> goff, gpad;
+    int *d_obs_a = nullptr, *d_obs_t = nullptr, *d_goff = nullptr, *d_gpad = nullptr;
+  };
+  struct KronReg {
+    int region = 0, nb = 0, np = 0;
+    double *inv = nullptr, *dR = nullptr, *qR = nullptr, *kR = nullptr;
+  };
+  std::vector<KronSub> ksub;
+  std::vector<KronReg> kreg;
+  std::vector<int> kreg_of;  // plan region -> kreg index (-1: none)
+  bool kron_static = false, kron_ready = false;
+  Pool kpool;
+  double* d_kk13 = nullptr;  // K in the 13-point layout (rows 5..12 zero)
+  // spectral preconditioner data (allocated on first use)
+  bool spec_alloc = false, spec_ready = false;
+  double *d_lam = nullptr, *d_dctx = nullptr, *d_dcty = nullptr, *d_spcp = nullptr,
+         *d_spid = nullptr, *d_spoff = nullptr;
+  Pool spool;
   DevModel dm{};
   DevModel* d_dm = nullptr;
   double *d_qs = nullptr, *d_kk = nullptr, *d_fs = nullptr, *d_qd = nullptr, *d_dqd = nullptr,
@@ -348,6 +383,8 @@ rbmc_status upload_coefs(rbmc_model* m) {
   HIPCHK(hipMemcpyAsync(m->d_dm, &m->dm, sizeof(DevModel), hipMemcpyHostToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
   m->bj_ready = m->sub_ready = false;
+  m->kron_ready = false;
+  m->spec_ready = false;
   return RBMC_OK;
 }
 
@@ -422,24 +459,34 @@ rbmc_status alloc_chainset(rbmc_model* m, ChainSet& cs, const std::vector<Chain>
   return RBMC_OK;
 }
 
-// correction / preconditioner panels of a model for n_k samples
-rbmc_status ensure_panels(rbmc_model* m, int n_k) {
+// The block-Jacobi (bj) or subdomain chain set of a model, allocated on first
+// use, with its correction / preconditioner panels for n_k samples.
+rbmc_status ensure_chains(rbmc_model* m, bool bj, int n_k) {
+  bool& done = bj ? m->bj_alloc : m->sub_alloc;
+  ChainSet& cs = bj ? m->bj : m->sub;
+  if (!done) {
+    rbmc_status st = bj ? alloc_chainset(m, m->bj, m->plan.bj, false, 0)
+                        : alloc_chainset(m, m->sub, m->plan.sub, true, (int)m->plan.bj.size());
+    if (st != RBMC_OK) return st;
+    done = true;
+  }
   const int nk = std::max(n_k, 1);
-  if (m->work_nk >= nk) return RBMC_OK;
-  m->work.release();
-  m->work_nk = -1;
-  for (ChainSet* cs : {&m->bj, &m->sub})
-    for (size_t c = 0; c < cs->size(); ++c) {
-      const size_t psz = (size_t)cs->np[c] * nk * 8;
-      cs->pan[c].clear();
-      for (int t = 0; t < cs->chains[c].T; ++t) {
-        double* p = nullptr;
-        HIPCHK(m->work.alloc((void**)&p, psz));
-        cs->pan[c].push_back(p);
-      }
-      HIPCHK(m->work.alloc((void**)&cs->ytmp[c], psz));
+  Pool& work = bj ? m->work_bj : m->work_sub;
+  int& work_nk = bj ? m->work_bj_nk : m->work_sub_nk;
+  if (work_nk >= nk) return RBMC_OK;
+  work.release();
+  work_nk = -1;
+  for (size_t c = 0; c < cs.size(); ++c) {
+    const size_t psz = (size_t)cs.np[c] * nk * 8;
+    cs.pan[c].clear();
+    for (int t = 0; t < cs.chains[c].T; ++t) {
+      double* p = nullptr;
+      HIPCHK(work.alloc((void**)&p, psz));
+      cs.pan[c].push_back(p);
     }
-  m->work_nk = nk;
+    HIPCHK(work.alloc((void**)&cs.ytmp[c], psz));
+  }
+  work_nk = nk;
   return RBMC_OK;
 }
 
@@ -574,7 +621,9 @@ struct InvJob {  // one SPD block to invert in place, with its workspace
 struct Op {
   // 0 gemm, 1 stencil, 2 register inversion, 3 panels, 4 extract, 5 mc, 6 copy,
   // 7 outer gather, 8 outer fix, 9 sweep finish, 10 profile begin, 11 profile end, 12 mirror,
-  // 13 off-diagonal pattern entries
+  // 13 off-diagonal pattern entries, 14-19 Kronecker-form kernels (region, build,
+  // reduce, det, time mix, observed gather), 20 fill with zeros, 21 spectral
+  // tridiagonal solves, 22 direct DCT along one axis
   int kind;
   size_t off = 0;
   int n = 0, tiles = 0;
@@ -584,11 +633,12 @@ struct Op {
   size_t bytes = 0;
   int family = -1;
   double alg_flops = 0.0, alg_bytes = 0.0;
+  ColSet cols{};  // kinds 21, 22
 };
 
 struct Program {
   std::vector<Op> ops;
-  void gemm(Arena& a, GemmList& g, bool profiled = true) {
+  void gemm(Arena& a, GemmList& g, bool profiled = true, int family = -1) {
     if (g.v.empty()) return;
     Op o;
     o.kind = 0;
@@ -596,6 +646,7 @@ struct Program {
     o.off = a.push(g.v);
     o.n = (int)g.v.size();
     o.family = !profiled ? -1
+               : family >= 0 ? family
                : o.kblk == kGemmMixed ? RBMC_KF_GEMM_MIXED
                : o.kblk == kGemmSmall ? RBMC_KF_GEMM_SMALL : RBMC_KF_GEMM;
     o.alg_flops = g.flops;
@@ -763,6 +814,27 @@ struct Program {
     o.alg_bytes = t.bytes;
     ops.push_back(o);
   }
+  // Kronecker-form kernels (kinds 14-19)
+  template <class T>
+  void kron(Arena& a, int kind, TileList<T>& t, int family = -1) {
+    if (t.v.empty()) return;
+    Op o;
+    o.kind = kind;
+    o.off = a.push(t.v);
+    o.n = (int)t.v.size();
+    o.tiles = t.tiles;
+    o.family = family;
+    o.alg_bytes = t.bytes;
+    ops.push_back(o);
+  }
+  void fill(double* p, size_t n) {
+    if (n == 0) return;
+    Op o;
+    o.kind = 20;
+    o.dst = p;
+    o.bytes = n;
+    ops.push_back(o);
+  }
   void copy(void* dst, const void* src, size_t bytes) {
     Op o;
     o.kind = 6;
@@ -797,6 +869,15 @@ rbmc_status run(rbmc_ctx* cx, const Program& pg, hipStream_t s, Arena& a) {
         break;
       case 12: launch_mirror(a.at<InvTask>(o.off), o.n, o.max_np, s); break;
       case 13: launch_offdiag(a.at<OffdiagTask>(o.off), o.n, o.tiles, s); break;
+      case 14: launch_kron_region(a.at<KronRegionTask>(o.off), o.n, o.tiles, s); break;
+      case 15: launch_kron_build(a.at<KronBuildTask>(o.off), o.n, o.tiles, s); break;
+      case 16: launch_kron_reduce(a.at<KronReduceTask>(o.off), o.n, o.tiles, s); break;
+      case 17: launch_kron_det(a.at<KronDetTask>(o.off), o.n, o.tiles, s); break;
+      case 18: launch_kron_tmix(a.at<KronMixTask>(o.off), o.n, o.tiles, s); break;
+      case 19: launch_kron_obs(a.at<KronObsTask>(o.off), o.n, o.tiles, s); break;
+      case 20: launch_fill((double*)o.dst, o.bytes, 0.0, s); break;
+      case 21: launch_spec_solve(o.cols, (double*)o.dst, s); break;
+      case 22: launch_dct_direct(o.cols, (const double*)o.src, (double*)o.dst, o.n, o.kblk, s); break;
     }
     if (o.kind != 10) cx->end(pid, s);
   }
@@ -1112,8 +1193,12 @@ rbmc_status check_opts(const rbmc_est_opts* o, bool need_pcg) {
   if (o->grad_mask & ~15u) return fail(RBMC_E_ARG, "grad_mask has unknown bits");
   if (o->precision != RBMC_FP64 && o->precision != RBMC_MIXED)
     return fail(RBMC_E_ARG, "precision must be RBMC_FP64 or RBMC_MIXED");
-  if (o->precond != RBMC_PC_BJ && o->precond != RBMC_PC_BJ_LEARNED)
-    return fail(RBMC_E_ARG, "precond must be RBMC_PC_BJ or RBMC_PC_BJ_LEARNED");
+  if (o->precond != RBMC_PC_BJ && o->precond != RBMC_PC_BJ_LEARNED &&
+      o->precond != RBMC_PC_SPECTRAL)
+    return fail(RBMC_E_ARG, "precond must be RBMC_PC_BJ, RBMC_PC_BJ_LEARNED or RBMC_PC_SPECTRAL");
+  if (o->method != RBMC_SEL_AUTO && o->method != RBMC_SEL_BLOCKTRI && o->method != RBMC_SEL_KRON)
+    return fail(RBMC_E_ARG, "method must be RBMC_SEL_AUTO, RBMC_SEL_BLOCKTRI or RBMC_SEL_KRON");
+  if (o->sample_chunk < 0) return fail(RBMC_E_ARG, "sample_chunk must be >= 0");
   return RBMC_OK;
 }
 
@@ -1128,7 +1213,7 @@ struct HostCols {
   std::vector<int> len, model;
   std::vector<size_t> base, zbase;  // per model
   size_t total = 0, ztotal = 0;
-  int max_len = 0, max_tiles = 0;
+  int max_len = 0, max_tiles = 0, max_ns = 0;
 };
 
 // kernels over columns put the column index in grid.y
@@ -1151,6 +1236,7 @@ HostCols make_cols(const std::vector<rbmc_model*>& ms, int nk) {
     h.total += (size_t)m->plan.n * nk;
     h.ztotal += (size_t)(m->plan.n + m->n_obs) * nk;
     h.max_len = std::max(h.max_len, m->plan.n);
+    h.max_ns = std::max(h.max_ns, m->plan.ns);
     h.max_tiles = std::max(h.max_tiles, stencil_tiles(m->plan.mx, m->plan.my));
   }
   return h;
@@ -1217,12 +1303,160 @@ ColSet colset(rbmc_ctx* cx, const HostCols& h) {
   c.ncols = (int)h.len.size();
   c.max_len = h.max_len;
   c.max_tiles = h.max_tiles;
+  c.max_ns = h.max_ns;
   c.off = cx->d_off;
   c.in_off = cx->d_in_off;
   c.len = cx->d_len;
   c.model = cx->d_model;
   c.dms = cx->d_dms;
   return c;
+}
+
+// ---------------------------------------------------------------------------
+// Spectral preconditioner M = Q_t (x) Q_s + dbar I.  The orthonormal DCT-II
+// matrix C (C[k, i] = c_k cos(pi k (2 i + 1) / (2 m)), c_0 = m^-1/2, else
+// (2/m)^1/2) diagonalizes the Neumann path Laplacian, C G_1 C^T = diag(2 - 2
+// cos(pi k / m)), so the 2-D transform diagonalizes G = G_x (+) G_y and every
+// polynomial in it: Q_s = tau (kappa^4 h^2 I + 2 kappa^2 G + G^2 / h^2) has
+// eigenvalue lambda_f = tau (kappa^4 h^2 + 2 kappa^2 l + l^2 / h^2) at
+// frequency f = (kx, ky), l = l_x(kx) + l_y(ky).  In that basis M is one
+// tridiagonal system per frequency (lambda_f Q_t + dbar I).
+// ---------------------------------------------------------------------------
+void dct_matrix(int m, std::vector<double>& C) {
+  C.assign((size_t)m * m, 0.0);
+  for (int k = 0; k < m; ++k) {
+    const double ck = k == 0 ? std::sqrt(1.0 / m) : std::sqrt(2.0 / m);
+    for (int i = 0; i < m; ++i) C[(size_t)i * m + k] = ck * std::cos(M_PI * k * (2 * i + 1) / (2.0 * m));
+  }
+}
+
+rbmc_status upload_dm(rbmc_model* m, hipStream_t s) {
+  HIPCHK(hipMemcpyAsync(m->d_dm, &m->dm, sizeof(DevModel), hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return RBMC_OK;
+}
+
+rbmc_status ensure_spectral(rbmc_model* m, hipStream_t s) {
+  const Plan& P = m->plan;
+  if (!m->spec_alloc) {
+    HIPCHK(m->spool.alloc((void**)&m->d_lam, (size_t)P.ns * 8));
+    HIPCHK(m->spool.alloc((void**)&m->d_spoff, (size_t)P.ns * 8));
+    HIPCHK(m->spool.alloc((void**)&m->d_spcp, (size_t)P.n * 8));
+    HIPCHK(m->spool.alloc((void**)&m->d_spid, (size_t)P.n * 8));
+    HIPCHK(m->spool.alloc((void**)&m->d_dctx, (size_t)P.mx * P.mx * 8));
+    HIPCHK(m->spool.alloc((void**)&m->d_dcty, (size_t)P.my * P.my * 8));
+    std::vector<double> C;
+    dct_matrix(P.mx, C);
+    HIPCHK(hipMemcpyAsync(m->d_dctx, C.data(), C.size() * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    dct_matrix(P.my, C);
+    HIPCHK(hipMemcpyAsync(m->d_dcty, C.data(), C.size() * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    m->spec_alloc = true;
+  }
+  if (m->spec_ready) return RBMC_OK;
+  const Coefs& co = m->co;
+  const double k2 = co.kappa * co.kappa, h2 = co.h * co.h;
+  std::vector<double> lx(P.mx), ly(P.my), lam((size_t)P.ns);
+  for (int k = 0; k < P.mx; ++k) lx[k] = 2.0 - 2.0 * std::cos(M_PI * k / P.mx);
+  for (int k = 0; k < P.my; ++k) ly[k] = 2.0 - 2.0 * std::cos(M_PI * k / P.my);
+  for (int ky = 0; ky < P.my; ++ky)
+    for (int kx = 0; kx < P.mx; ++kx) {
+      const double l = lx[kx] + ly[ky];
+      lam[(size_t)ky * P.mx + kx] = co.tau * (k2 * k2 * h2 + 2.0 * k2 * l + l * l / h2);
+    }
+  HIPCHK(hipMemcpyAsync(m->d_lam, lam.data(), lam.size() * 8, hipMemcpyHostToDevice, s));
+  SpecCoefTask t{};
+  t.lam = m->d_lam;
+  t.qd = m->d_qd;
+  t.qo = co.qo;
+  t.dbar = P.n > 0 ? (double)m->n_obs * co.dobs / P.n : 0.0;
+  t.ns = P.ns;
+  t.T = P.T;
+  t.cp = m->d_spcp;
+  t.id = m->d_spid;
+  t.off = m->d_spoff;
+  launch_spec_coef(t, s);
+  HIPCHK(hipGetLastError());
+  m->dm.dct_x = m->d_dctx;
+  m->dm.dct_y = m->d_dcty;
+  m->dm.sp_cp = m->d_spcp;
+  m->dm.sp_id = m->d_spid;
+  m->dm.sp_off = m->d_spoff;
+  m->dm.spec_gemm = (P.mx % 16 == 0 && P.my % 16 == 0 && P.mx >= 64 && P.my >= 64) ? 1 : 0;
+  rbmc_status st = upload_dm(m, s);  // synchronizes: lam is on the host stack
+  if (st != RBMC_OK) return st;
+  m->spec_ready = true;
+  return RBMC_OK;
+}
+
+// One axis of the 2-D transform for every column of the set: models with the
+// GEMM route as matrix-core products (axis 0: C_x X over all rows of x at
+// once; axis 1: X_s C_y^T per (time step, sample) slice), the others by the
+// direct kernel.  inverse: C^T.
+void spectral_axis(const std::vector<rbmc_model*>& ms, const HostCols& h, const ColSet& cols,
+                   int nk, const double* in, double* out, int axis, int inverse, Program& pg,
+                   Arena& a) {
+  GemmList gl;
+  bool direct = false;
+  for (size_t j = 0; j < ms.size(); ++j) {
+    const rbmc_model* m = ms[j];
+    const int mx = m->plan.mx, my = m->plan.my, T = m->plan.T;
+    if (!m->dm.spec_gemm) {
+      direct = true;
+      continue;
+    }
+    const double* src = in + h.base[j];
+    double* dst = out + h.base[j];
+    if (axis == 0) {
+      gl.add(m->d_dctx, src, nullptr, dst, mx, my * T * nk, mx, mx, mx, mx, 1.0, 0.0, inverse, 0,
+             mx, mx);
+    } else {
+      for (int sl = 0; sl < T * nk; ++sl) {
+        const size_t o = (size_t)sl * mx * my;
+        gl.add(src + o, m->d_dcty, nullptr, dst + o, mx, my, my, mx, my, mx, 1.0, 0.0, 0,
+               inverse ? 0 : 1, mx, my);
+      }
+    }
+  }
+  pg.gemm(a, gl, true, RBMC_KF_DCT);
+  if (direct) {
+    Op o;
+    o.kind = 22;
+    o.cols = cols;
+    o.src = in;
+    o.dst = out;
+    o.n = axis;
+    o.kblk = inverse;
+    pg.ops.push_back(o);
+  }
+}
+
+// z = M^-1 r over the columns of the set, tmp a work multi-vector.
+void build_spectral(const std::vector<rbmc_model*>& ms, const HostCols& h, const ColSet& cols,
+                    int nk, const double* r, double* z, double* tmp, Program& pg, Arena& a) {
+  spectral_axis(ms, h, cols, nk, r, tmp, 0, 0, pg, a);
+  spectral_axis(ms, h, cols, nk, tmp, z, 1, 0, pg, a);
+  Op o;
+  o.kind = 21;
+  o.cols = cols;
+  o.dst = z;
+  o.family = RBMC_KF_SPEC_SOLVE;
+  o.alg_bytes = 16.0 * (double)h.total;
+  pg.ops.push_back(o);
+  spectral_axis(ms, h, cols, nk, z, tmp, 1, 1, pg, a);
+  spectral_axis(ms, h, cols, nk, tmp, z, 0, 1, pg, a);
+}
+
+// the per-model device views of a column set, after a model's view changed
+rbmc_status upload_dms(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, hipStream_t s) {
+  std::vector<DevModel> dms;
+  for (rbmc_model* m : ms) dms.push_back(m->dm);
+  if (!dms.empty())
+    HIPCHK(hipMemcpyAsync(cx->d_dms, dms.data(), dms.size() * sizeof(DevModel),
+                          hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return RBMC_OK;
 }
 
 // Factor the block-Jacobi chains of every model that needs it (one program).
@@ -1273,7 +1507,21 @@ rbmc_status sample_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const H
   bool learned = false;
   if (o->precond == RBMC_PC_BJ_LEARNED)
     for (rbmc_model* m : ms) learned = learned || learned_usable(m);
-  rbmc_status st = factor_bj(cx, ms, rep, s);
+  const bool spectral = o->precond == RBMC_PC_SPECTRAL;
+  rbmc_status st = RBMC_OK;
+  if (spectral) {
+    for (rbmc_model* m : ms) {
+      st = ensure_spectral(m, s);
+      if (st != RBMC_OK) return st;
+    }
+    st = upload_dms(cx, ms, s);
+  } else {
+    for (rbmc_model* m : ms) {
+      st = ensure_chains(m, true, nk);
+      if (st != RBMC_OK) return st;
+    }
+    st = factor_bj(cx, ms, rep, s);
+  }
   if (st != RBMC_OK) return st;
   const ColSet cols = colset(cx, h);
   const int nc = cols.ncols;
@@ -1287,15 +1535,18 @@ rbmc_status sample_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const H
   double* pq = cx->scal + 3 * nc;
   double* rr = cx->scal + 4 * nc;
   const int nch = dot_chunks(std::max(h.max_len, 1)), nsp = h.max_tiles;
-  // preconditioner program: gather r -> panels, solve, scatter -> z
+  // preconditioner program: gather r -> panels, solve, scatter -> z (block
+  // Jacobi), or the spectral transforms and solves
   ChainSet cs;
-  std::vector<double*> xbase_r, xbase_z;
-  for (size_t j = 0; j < ms.size(); ++j) cs.append(ms[j]->bj);
+  if (!spectral)
+    for (size_t j = 0; j < ms.size(); ++j) cs.append(ms[j]->bj);
   Arena& ar = cx->arenaA;
   ar.clear();
   Program pre, gat, sca;
   TileList<PanelTask> g, sc;
-  {
+  if (spectral) {
+    build_spectral(ms, h, cols, nk, r, zz, cx->zp, pre, ar);
+  } else {
     size_t c0 = 0;
     for (size_t j = 0; j < ms.size(); ++j) {
       rbmc_model* m = ms[j];
@@ -1324,11 +1575,13 @@ rbmc_status sample_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const H
       c0 += m->bj.size();
     }
   }
-  gat.panels(ar, g);
-  // FP64 even under RBMC_MIXED: FP32-rounded solves cost the one-iteration
-  // exact chain preconditioner two more iterations
-  build_twisted_solve(cs, nk, pre, ar, 0, true);
-  sca.panels(ar, sc);
+  if (!spectral) {
+    gat.panels(ar, g);
+    // FP64 even under RBMC_MIXED: FP32-rounded solves cost the one-iteration
+    // exact chain preconditioner two more iterations
+    build_twisted_solve(cs, nk, pre, ar, 0, true);
+    sca.panels(ar, sc);
+  }
   HIPCHK(ar.upload(s));
   if (learned && cx->lws_len < h.total) {
     cx->lws.release();
@@ -1484,6 +1737,118 @@ rbmc_status ensure_streams(rbmc_ctx* cx) {
   return RBMC_OK;
 }
 
+// Partial-sum layout of the estimator over a list of subdomain chains: per
+// chain and local step, the deterministic slots (diagonal block, off-diagonal
+// t -> t+1, t+1 -> t) in chunks of 256 rows with 3 sums each, and the Monte
+// Carlo sums in chunks of 64 rows with 8 sums each.
+struct EstLayout {
+  std::vector<Chain> ch;
+  std::vector<const rbmc_model*> owner;
+  std::vector<int> np, cmodel;
+  std::vector<size_t> det_base, mc_base;
+  size_t det_len = 0, mc_len = 0;
+  void add(const Chain& c, const rbmc_model* m, int np_, int model) {
+    ch.push_back(c);
+    owner.push_back(m);
+    np.push_back(np_);
+    cmodel.push_back(model);
+  }
+  void finish() {
+    const size_t n = ch.size();
+    det_base.assign(n + 1, 0);
+    mc_base.assign(n + 1, 0);
+    for (size_t c = 0; c < n; ++c) {
+      det_base[c + 1] = det_base[c] + (size_t)ch[c].T * 3 * nchk(c);
+      mc_base[c + 1] = mc_base[c] + (size_t)ch[c].T * (np[c] / 64);
+    }
+    det_len = det_base[n] * 3;
+    mc_len = mc_base[n] * 8;
+  }
+  size_t nchk(size_t c) const { return (np[c] + 255) / 256; }
+  size_t det_index(size_t c, int t, int sl) const {
+    return det_base[c] + ((size_t)t * 3 + sl) * nchk(c);
+  }
+  size_t mc_index(size_t c, int t) const { return mc_base[c] + (size_t)t * (np[c] / 64); }
+};
+
+// Device partial sums of a layout (the context's estimator buffer).
+rbmc_status ensure_epart(rbmc_ctx* cx, const EstLayout& L) {
+  const size_t need = std::max<size_t>(L.det_len + L.mc_len, 1);
+  if (cx->epart_len < need) {
+    cx->epool.release();
+    cx->epart_len = 0;
+    HIPCHK(cx->epool.alloc((void**)&cx->epart, need * 8));
+    cx->epart_len = need;
+  }
+  return RBMC_OK;
+}
+
+// Traces and the plug-in error from the partial sums (host, fixed order):
+// the deterministic and Monte Carlo Frobenius products of each core step
+// weighted by the time coefficients of dQ_j (eq:hyperpar:4).
+rbmc_status combine_traces(rbmc_ctx* cx, const EstLayout& L, const std::vector<rbmc_model*>& ms,
+                           int nk, const rbmc_est_opts* o,
+                           const std::vector<double*>& trace_out, rbmc_report* rep) {
+  std::vector<double> hpart(L.det_len + L.mc_len);
+  HIPCHK(hipMemcpy(hpart.data(), cx->epart, (L.det_len + L.mc_len) * 8, hipMemcpyDeviceToHost));
+  const double* hdet = hpart.data();
+  const double* hmc = hpart.data() + L.det_len;
+  std::vector<std::array<double, 4>> tr(ms.size(), {0.0, 0.0, 0.0, 0.0});
+  double ratio_sum = 0.0;  // sum over nodes of (MC part) / (estimate)
+  size_t n_total = 0;
+  for (rbmc_model* m : ms) n_total += m->plan.n;
+  for (size_t c = 0; c < L.ch.size(); ++c) {
+    const Chain& ch = L.ch[c];
+    const Coefs& co = L.owner[c]->co;
+    const size_t nchk = L.nchk(c), mchk = L.np[c] / 64;
+    const int lc0 = ch.ct0 - ch.t0, lc1 = lc0 + ch.cT - 1;
+    for (int t = lc0; t <= lc1; ++t) {
+      const int tg = ch.t0 + t;
+      // deterministic: slot 0 (t,t), slot 1 (t,t+1), slot 2 (t,t-1)
+      double Fd = 0, Fq[3] = {0, 0, 0}, Fk[3] = {0, 0, 0};
+      for (int sl = 0; sl < 3; ++sl)
+        for (size_t k = 0; k < nchk; ++k) {
+          const double* pp = &hdet[(L.det_index(c, t, sl) + k) * 3];
+          if (sl == 0) Fd += pp[0];
+          Fq[sl] += pp[1];
+          Fk[sl] += pp[2];
+        }
+      // Monte Carlo: components [t-1, t, t+1] for Q_s and K, then D, then m/s2
+      double G[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      if (nk > 0)
+        for (size_t k = 0; k < mchk; ++k)
+          for (int j = 0; j < 8; ++j) G[j] += hmc[(L.mc_index(c, t) + k) * 8 + j];
+      ratio_sum += G[7];
+      const double wq0 = co.qd[tg], wqo = co.qo, wd0 = co.dqd[tg], wdo = co.dqo;
+      const bool hm = (t - 1 >= 0), hp = (t + 1 < ch.T);
+      const double q_tt = Fq[0] + G[1];
+      const double q_tp = hp ? Fq[1] + G[2] : 0.0;
+      const double q_tm = hm ? Fq[2] + G[0] : 0.0;
+      const double k_tt = Fk[0] + G[4];
+      const double k_tp = hp ? Fk[1] + G[5] : 0.0;
+      const double k_tm = hm ? Fk[2] + G[3] : 0.0;
+      std::array<double, 4>& T = tr[L.cmodel[c]];
+      T[0] += wq0 * k_tt + wqo * (k_tp + k_tm);
+      T[1] += wq0 * q_tt + wqo * (q_tp + q_tm);
+      T[2] += wd0 * q_tt + wdo * (q_tp + q_tm);
+      T[3] += -2.0 * (Fd + G[6]);
+    }
+  }
+  for (size_t j = 0; j < ms.size(); ++j)
+    if (trace_out[j]) {
+      int k = 0;
+      for (int b = 0; b < 4; ++b)
+        if (o->grad_mask & (1u << b)) trace_out[j][k++] = tr[j][b];
+    }
+  if (rep) {
+    // plug-in MC error: m_i ~ E[mu_i^2] chi2_{n_k} / n_k, so the mean absolute relative
+    // error of the estimate is about sqrt(2/pi) sqrt(2/n_k) m_i / s2_i on average
+    rep->err_estimate =
+        nk > 0 ? std::sqrt(2.0 / M_PI) * std::sqrt(2.0 / nk) * ratio_sum / (double)n_total : 0.0;
+  }
+  return RBMC_OK;
+}
+
 // The estimator from samples for a set of models.  x_base: the samples in the
 // column layout h (ignored when n_k = 0).  The subdomain factorization and the
 // core steps do not need the samples: when `sampler` is given they run on
@@ -1507,6 +1872,24 @@ rbmc_status estimate_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const
   hipStream_t s = sampler ? cx->side : sA;
   hipStream_t sT = sampler ? cx->side2 : sA;
   double t0 = now_s();
+  for (rbmc_model* m : ms) {
+    rbmc_status e = ensure_chains(m, false, nk);
+    if (e != RBMC_OK) return e;
+  }
+  EstLayout L;
+  for (size_t j = 0; j < ms.size(); ++j)
+    for (size_t c = 0; c < ms[j]->sub.size(); ++c)
+      L.add(ms[j]->sub.chains[c], ms[j], ms[j]->sub.np[c], (int)j);
+  L.finish();
+  {
+    rbmc_status e = ensure_epart(cx, L);
+    if (e != RBMC_OK) return e;
+  }
+  const size_t need = std::max<size_t>(L.det_len + L.mc_len, 1);
+  double* det_part = cx->epart;
+  double* mc_part = cx->epart + L.det_len;
+  auto det_index = [&](int c, int t, int sl) { return L.det_index(c, t, sl); };
+  auto mc_index = [&](int c, int t) { return L.mc_index(c, t); };
   // combined subdomain chain set and per-chain model index
   ChainSet cs;
   std::vector<int> cmodel;
@@ -1522,28 +1905,6 @@ rbmc_status estimate_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const
   ar.clear();
   Program fac;
   if (cf.size()) build_twosided(cf, fac, ar);
-  // partial-sum slots: per chain and local step: det (diag block, off t->t+1,
-  // off t+1->t) in chunks of 256 rows, mc in chunks of 64 rows
-  std::vector<size_t> det_base(nchains + 1, 0), mc_base(nchains + 1, 0);
-  for (int c = 0; c < nchains; ++c) {
-    const int T = cs.chains[c].T;
-    det_base[c + 1] = det_base[c] + (size_t)T * 3 * ((cs.np[c] + 255) / 256);
-    mc_base[c + 1] = mc_base[c] + (size_t)T * (cs.np[c] / 64);
-  }
-  const size_t det_len = det_base[nchains] * 3, mc_len = mc_base[nchains] * 8;
-  const size_t need = std::max<size_t>(det_len + mc_len, 1);
-  if (cx->epart_len < need) {
-    cx->epool.release();
-    HIPCHK(cx->epool.alloc((void**)&cx->epart, need * 8));
-    cx->epart_len = need;
-  }
-  double* det_part = cx->epart;
-  double* mc_part = cx->epart + det_len;
-  auto det_index = [&](int c, int t, int sl) {
-    const size_t nchk = (cs.np[c] + 255) / 256;
-    return det_base[c] + ((size_t)t * 3 + sl) * nchk;
-  };
-  auto mc_index = [&](int c, int t) { return mc_base[c] + (size_t)t * (cs.np[c] / 64); };
   auto lc0 = [&](int c) { return cs.chains[c].ct0 - cs.chains[c].t0; };
   auto lc1 = [&](int c) { return lc0(c) + cs.chains[c].cT - 1; };
   auto is_core = [&](int c, int t) { return t >= lc0(c) && t <= lc1(c); };
@@ -1660,6 +2021,8 @@ rbmc_status estimate_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const
         k.partial = mc_part;
         k.out_index = (int)mc_index(c, t);
         k.n_k = nk;
+        k.scale = 1.0 / nk;
+        k.accum = 0;
         k.t = ch.t0 + t;
         mt.add(k, cs.np[c] / 64);
       }
@@ -1752,66 +2115,16 @@ rbmc_status estimate_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const
     HIPCHK(hipEventElapsedTime(&ms_tak, e_fac, e_tak));
   }
   // ---- traces: combine partial sums with the temporal weights ----
-  std::vector<double> hpart(det_len + mc_len);
-  HIPCHK(hipMemcpy(hpart.data(), cx->epart, (det_len + mc_len) * 8, hipMemcpyDeviceToHost));
-  const double* hdet = hpart.data();
-  const double* hmc = hpart.data() + det_len;
-  std::vector<std::array<double, 4>> tr(ms.size(), {0.0, 0.0, 0.0, 0.0});
-  double ratio_sum = 0.0;  // sum over nodes of (MC part) / (estimate)
-  size_t n_total = 0;
-  for (rbmc_model* m : ms) n_total += m->plan.n;
-  for (int c = 0; c < nchains; ++c) {
-    const Chain& ch = cs.chains[c];
-    const Coefs& co = cs.owner[c]->co;
-    const int nchk = (cs.np[c] + 255) / 256, mchk = cs.np[c] / 64;
-    for (int t = lc0(c); t <= lc1(c); ++t) {
-      const int tg = ch.t0 + t;
-      // deterministic: slot 0 (t,t), slot 1 (t,t+1), slot 2 (t,t-1)
-      double Fd = 0, Fq[3] = {0, 0, 0}, Fk[3] = {0, 0, 0};
-      for (int sl = 0; sl < 3; ++sl)
-        for (int k = 0; k < nchk; ++k) {
-          const double* pp = &hdet[(det_index(c, t, sl) + k) * 3];
-          if (sl == 0) Fd += pp[0];
-          Fq[sl] += pp[1];
-          Fk[sl] += pp[2];
-        }
-      // Monte Carlo: components [t-1, t, t+1] for Q_s and K, then D, then m/s2
-      double G[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-      if (nk > 0)
-        for (int k = 0; k < mchk; ++k)
-          for (int j = 0; j < 8; ++j) G[j] += hmc[(mc_index(c, t) + k) * 8 + j];
-      ratio_sum += G[7];
-      const double wq0 = co.qd[tg], wqo = co.qo, wd0 = co.dqd[tg], wdo = co.dqo;
-      const bool hm = (t - 1 >= 0), hp = (t + 1 < ch.T);
-      const double q_tt = Fq[0] + G[1];
-      const double q_tp = hp ? Fq[1] + G[2] : 0.0;
-      const double q_tm = hm ? Fq[2] + G[0] : 0.0;
-      const double k_tt = Fk[0] + G[4];
-      const double k_tp = hp ? Fk[1] + G[5] : 0.0;
-      const double k_tm = hm ? Fk[2] + G[3] : 0.0;
-      std::array<double, 4>& T = tr[cmodel[c]];
-      T[0] += wq0 * k_tt + wqo * (k_tp + k_tm);
-      T[1] += wq0 * q_tt + wqo * (q_tp + q_tm);
-      T[2] += wd0 * q_tt + wdo * (q_tp + q_tm);
-      T[3] += -2.0 * (Fd + G[6]);
-    }
-  }
-  for (size_t j = 0; j < ms.size(); ++j)
-    if (trace_out[j]) {
-      int k = 0;
-      for (int b = 0; b < 4; ++b)
-        if (o->grad_mask & (1u << b)) trace_out[j][k++] = tr[j][b];
-    }
+  st = combine_traces(cx, L, ms, nk, o, trace_out, rep);
+  if (st != RBMC_OK) return st;
   if (rep) {
-    // plug-in MC error: m_i ~ E[mu_i^2] chi2_{n_k} / n_k, so the mean absolute relative
-    // error of the estimate is about sqrt(2/pi) sqrt(2/n_k) m_i / s2_i on average
-    rep->err_estimate =
-        nk > 0 ? std::sqrt(2.0 / M_PI) * std::sqrt(2.0 / nk) * ratio_sum / (double)n_total : 0.0;
     rep->t_factor = ms_fac * 1e-3;
     rep->t_select = ms_tak * 1e-3;
     rep->t_correct = t3 - t2;
     int64_t bytes = cx->ws.bytes + cx->epool.bytes;
-    for (rbmc_model* m : ms) bytes += m->pool.bytes + m->work.bytes;
+    for (rbmc_model* m : ms)
+      bytes += m->pool.bytes + m->work_bj.bytes + m->work_sub.bytes + m->kpool.bytes +
+               m->spool.bytes;
     rep->peak_bytes = bytes;
   }
   (void)t0;
@@ -1967,7 +2280,7 @@ rbmc_status precond_train(rbmc_model* m, const rbmc_est_opts* po, const rbmc_tra
   const HostCols h = make_cols(ms, n_train);
   st = ensure_ws(cx, ms, h, false);
   if (st != RBMC_OK) return st;
-  st = ensure_panels(m, n_train);
+  st = ensure_chains(m, true, n_train);
   if (st != RBMC_OK) return st;
   Pool tp;  // training data, released on return
   struct Release {
@@ -2222,6 +2535,801 @@ rbmc_status precond_train(rbmc_model* m, const rbmc_est_opts* po, const rbmc_tra
   return RBMC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Kronecker method for the subdomains (RBMC_SEL_KRON).  For A = [t0, t0 + T_A)
+// x R the prior part of Q_AA is Q_t|A (x) Q_s|R, and the observations add a
+// diagonal of rank n_o, so by the Woodbury identity
+//   Q_AA^-1 = V (x) S^-1 - (V (x) S^-1) P Y P^T (V (x) S^-1),
+//   S = Q_s|R,  V = (Q_t|A)^-1,  Y = (sigma^2 I + P^T (V (x) S^-1) P)^-1.
+// S^-1 is formed once per spatial region (all time slabs of a tile share it),
+// Y once per subdomain; the kernels in kernels_kron.hip turn them into the
+// diagonal and stencil entries the estimator reads (Alg. 4, eq:hyperpar:4)
+// and into the correction solves mu = Q_AA^-1 Q_AB x_B.
+// ---------------------------------------------------------------------------
+struct Carve {  // bump allocation inside one device block (256-byte aligned)
+  char* base = nullptr;
+  size_t off = 0;
+  double* d(size_t n) {
+    off = (off + 255) / 256 * 256;
+    double* p = (double*)(base + off);
+    off += n * 8;
+    return p;
+  }
+};
+
+// Sweep workspaces of a Gauss-Jordan inversion of order np (see InvJob).
+void carve_gj(Carve& cv, int np, InvJob& j) {
+  const size_t w = sweep_width_of(np);
+  j.B = cv.d((size_t)np * w);
+  j.U = cv.d((size_t)np * w);
+  j.P = cv.d(w * w);
+  j.B2 = cv.d(w * 128);
+  j.U2 = cv.d(w * 128);
+  j.P2 = cv.d((size_t)128 * 128);
+}
+
+rbmc_status ensure_kws(rbmc_ctx* cx, size_t bytes) {
+  if (cx->kws_cap >= bytes) return RBMC_OK;
+  cx->kws.release();
+  cx->kws_base = nullptr;
+  cx->kws_cap = 0;
+  HIPCHK(cx->kws.alloc((void**)&cx->kws_base, bytes));
+  cx->kws_cap = bytes;
+  return RBMC_OK;
+}
+
+// Observed slots of every subdomain (plan and mask only), the regions'
+// S^-1 storage and K in the 13-point coefficient layout.
+rbmc_status kron_static(rbmc_model* m) {
+  if (m->kron_static) return RBMC_OK;
+  const Plan& P = m->plan;
+  hipStream_t s = m->ctx->stream;
+  m->kreg_of.assign(P.regions.size(), -1);
+  m->ksub.clear();
+  m->kreg.clear();
+  std::vector<int> idx;  // all index tables of the model, one upload
+  std::vector<size_t> at;
+  for (size_t c = 0; c < P.sub.size(); ++c) {
+    const Chain& ch = P.sub[c];
+    const Region& g = P.regions[ch.region];
+    if (m->kreg_of[ch.region] < 0) {
+      rbmc_model::KronReg r;
+      r.region = ch.region;
+      r.nb = g.nb();
+      r.np = pad_to(r.nb);
+      HIPCHK(m->kpool.alloc((void**)&r.inv, (size_t)r.np * r.np * 8));
+      HIPCHK(m->kpool.alloc((void**)&r.dR, (size_t)r.np * 8));
+      HIPCHK(m->kpool.alloc((void**)&r.qR, (size_t)r.np * 8));
+      HIPCHK(m->kpool.alloc((void**)&r.kR, (size_t)r.np * 8));
+      m->kreg_of[ch.region] = (int)m->kreg.size();
+      m->kreg.push_back(r);
+    }
+    rbmc_model::KronSub k;
+    k.chain = (int)c;
+    k.TA = ch.T;
+    std::vector<int> oa, ot;
+    for (int t = 0; t < ch.T; ++t) {
+      k.goff.push_back((int)oa.size());
+      int cnt = 0;
+      for (int a = 0; a < g.nb(); ++a)
+        if (m->mask[(size_t)(ch.t0 + t) * P.ns + g.nodes[a]]) {
+          oa.push_back(a);
+          ot.push_back(t);
+          ++cnt;
+        }
+      const int pad = (cnt + 15) / 16 * 16;
+      for (int i = cnt; i < pad; ++i) {
+        oa.push_back(-1);
+        ot.push_back(t);
+      }
+      k.gpad.push_back(pad);
+      k.nobs += cnt;
+    }
+    k.nc = std::max(kPad, pad_to((int)oa.size()));
+    while ((int)oa.size() < k.nc) {  // trailing unused slots (in no group)
+      oa.push_back(-1);
+      ot.push_back(0);
+    }
+    at.push_back(idx.size());
+    idx.insert(idx.end(), oa.begin(), oa.end());
+    idx.insert(idx.end(), ot.begin(), ot.end());
+    idx.insert(idx.end(), k.goff.begin(), k.goff.end());
+    idx.insert(idx.end(), k.gpad.begin(), k.gpad.end());
+    m->ksub.push_back(std::move(k));
+  }
+  int* d_idx = nullptr;
+  HIPCHK(m->kpool.alloc((void**)&d_idx, std::max<size_t>(idx.size(), 1) * 4));
+  HIPCHK(hipMemcpyAsync(d_idx, idx.data(), idx.size() * 4, hipMemcpyHostToDevice, s));
+  for (size_t c = 0; c < m->ksub.size(); ++c) {
+    rbmc_model::KronSub& k = m->ksub[c];
+    k.d_obs_a = d_idx + at[c];
+    k.d_obs_t = k.d_obs_a + k.nc;
+    k.d_goff = k.d_obs_t + k.nc;
+    k.d_gpad = k.d_goff + k.TA;
+  }
+  std::vector<double> kk13((size_t)kNS * P.ns, 0.0);
+  std::copy(m->co.kk.begin(), m->co.kk.end(), kk13.begin());
+  HIPCHK(m->kpool.alloc((void**)&m->d_kk13, kk13.size() * 8));
+  HIPCHK(hipMemcpyAsync(m->d_kk13, kk13.data(), kk13.size() * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  m->kron_static = true;
+  return RBMC_OK;
+}
+
+// (Q_t restricted to steps [t0, t0 + TA))^-1, TA x TA, symmetric: each column
+// by a tridiagonal elimination, then the two triangles averaged.
+std::vector<double> time_inverse(const Coefs& co, int t0, int TA) {
+  std::vector<double> V((size_t)TA * TA, 0.0), cp(TA), dp(TA);
+  const double a = co.qo;
+  for (int j = 0; j < TA; ++j) {
+    for (int t = 0; t < TA; ++t) {
+      const double b = co.qd[t0 + t];
+      const double den = t == 0 ? b : b - a * cp[t - 1];
+      cp[t] = a / den;
+      const double rhs = (t == j) ? 1.0 : 0.0;
+      dp[t] = (t == 0 ? rhs : rhs - a * dp[t - 1]) / den;
+    }
+    double y = dp[TA - 1];
+    V[(size_t)(TA - 1) * TA + j] = y;
+    for (int t = TA - 2; t >= 0; --t) {
+      y = dp[t] - cp[t] * y;
+      V[(size_t)t * TA + j] = y;
+    }
+  }
+  for (int i = 0; i < TA; ++i)
+    for (int j = 0; j < i; ++j) {
+      const double v = 0.5 * (V[(size_t)i * TA + j] + V[(size_t)j * TA + i]);
+      V[(size_t)i * TA + j] = V[(size_t)j * TA + i] = v;
+    }
+  return V;
+}
+
+// S^-1 = (Q_s|R)^-1 of every region of the models that need it (after a
+// change of theta), with the node quantities dR, qR, kR.
+rbmc_status kron_regions(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, hipStream_t s,
+                         rbmc_report* rep) {
+  std::vector<std::pair<rbmc_model*, int>> todo;
+  for (rbmc_model* m : ms)
+    if (!m->kron_ready)
+      for (size_t r = 0; r < m->kreg.size(); ++r) todo.push_back({m, (int)r});
+  if (todo.empty()) return RBMC_OK;
+  size_t bytes = 4096;
+  for (auto& tr : todo) {
+    const int np = tr.first->kreg[tr.second].np;
+    const size_t w = sweep_width_of(np);
+    bytes += (2 * (size_t)np * w + w * w + 2 * w * 128 + 128 * 128) * 8 + 6 * 256;
+  }
+  // one info flag per region job, at the start of the workspace
+  bytes += todo.size() * 4 + 256;
+  rbmc_status st = ensure_kws(cx, bytes);
+  if (st != RBMC_OK) return st;
+  Carve cv{cx->kws_base, 0};
+  int* info = (int*)cv.d((todo.size() + 1) / 2);
+  HIPCHK(hipMemsetAsync(info, 0, todo.size() * 4, s));
+  Arena& ar = cx->arenaB;
+  ar.clear();
+  Program pg;
+  StencilList sl;
+  std::vector<InvJob> jobs;
+  TileList<KronRegionTask> rt;
+  for (size_t i = 0; i < todo.size(); ++i) {
+    rbmc_model* m = todo[i].first;
+    const rbmc_model::KronReg& R = m->kreg[todo[i].second];
+    StencilTask t{};
+    t.rg = m->d_regions + R.region;
+    t.qs = m->d_qs;
+    t.ns = m->plan.ns;
+    t.M = nullptr;
+    t.alpha = 0.0;
+    t.gamma = 1.0;
+    t.pad_identity = 1;
+    t.out = R.inv;
+    t.ldout = R.np;
+    t.ldm = R.np;
+    t.ncols = R.np;
+    sl.add(t, R.np, R.nb);
+    InvJob j{};
+    j.M = R.inv;
+    j.np = R.np;
+    j.nb = R.nb;
+    j.info = info + i;
+    j.base = 0;
+    carve_gj(cv, R.np, j);
+    jobs.push_back(j);
+    KronRegionTask k{};
+    k.inv = R.inv;
+    k.rg = t.rg;
+    k.dm = m->d_dm;
+    k.dR = R.dR;
+    k.qR = R.qR;
+    k.kR = R.kR;
+    rt.add(k, (R.np + 255) / 256);
+  }
+  pg.stencil(ar, sl);
+  pg.inverse(ar, jobs);
+  pg.kron(ar, 14, rt);
+  HIPCHK(ar.upload(s));
+  st = run(cx, pg, s, ar);
+  if (st != RBMC_OK) return st;
+  std::vector<int> hinfo(todo.size());
+  HIPCHK(hipMemcpyAsync(hinfo.data(), info, todo.size() * 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (size_t i = 0; i < todo.size(); ++i)
+    if (hinfo[i] != 0) {
+      if (rep) rep->fail_block = hinfo[i] - 1;
+      return fail(RBMC_E_NOT_SPD, "spatial block Q_s|R of region " +
+                                      std::to_string(todo[i].second) + " lost positive definiteness");
+    }
+  for (rbmc_model* m : ms) m->kron_ready = true;
+  return RBMC_OK;
+}
+
+// Device workspace of one subdomain in a batch (bytes, with alignment slack).
+size_t kron_sub_bytes(const rbmc_model* m, const rbmc_model::KronSub& k, int nk) {
+  const rbmc_model::KronReg& R = m->kreg[m->kreg_of[m->plan.sub[k.chain].region]];
+  const size_t np = R.np, nc = k.nc, TA = k.TA, w = sweep_width_of(k.nc);
+  size_t d = 3 * np * nc + nc * nc + TA * TA * 3 * np + TA * TA;  // Z, KZ, X, C, part, V
+  d += 2 * nc * w + w * w + 2 * w * 128 + 128 * 128;              // inversion of C
+  if (nk > 0) d += 2 * np * TA * nk + 2 * nc * nk;                // Rb, Ub, v, w
+  return d * 8 + 20 * 256;
+}
+
+struct KronBuf {
+  double *Z, *KZ, *X, *C, *part, *V, *Rb, *Ub, *v, *w;
+  InvJob inv;
+};
+
+// The subdomains of a set, in order: (model index, subdomain index).
+std::vector<std::pair<int, int>> kron_refs(const std::vector<rbmc_model*>& ms) {
+  std::vector<std::pair<int, int>> r;
+  for (size_t j = 0; j < ms.size(); ++j)
+    for (size_t c = 0; c < ms[j]->ksub.size(); ++c) r.push_back({(int)j, (int)c});
+  return r;
+}
+
+// Selected entries of one batch of subdomains [i0, i1) of refs.
+rbmc_status kron_det_batch(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms,
+                           const std::vector<std::pair<int, int>>& refs, size_t i0, size_t i1,
+                           const std::vector<KronBuf>& kb, const EstLayout& L,
+                           const std::vector<size_t>& lidx,
+                           const std::vector<double*>& diag_out, hipStream_t s,
+                           rbmc_report* rep) {
+  Arena& ar = cx->arenaB;
+  ar.clear();
+  Program pg;
+  TileList<KronBuildTask> zt, ct;
+  StencilList kz;
+  std::vector<InvJob> jobs;
+  int maxTA = 0;
+  for (size_t i = i0; i < i1; ++i) {
+    rbmc_model* m = ms[refs[i].first];
+    const rbmc_model::KronSub& k = m->ksub[refs[i].second];
+    const Chain& ch = m->plan.sub[k.chain];
+    const rbmc_model::KronReg& R = m->kreg[m->kreg_of[ch.region]];
+    const KronBuf& b = kb[i - i0];
+    maxTA = std::max(maxTA, k.TA);
+    pg.fill(b.part, (size_t)k.TA * k.TA * 3 * R.np);
+    KronBuildTask t{};
+    t.mode = 0;
+    t.inv = R.inv;
+    t.Z = b.Z;
+    t.V = b.V;
+    t.obs_a = k.d_obs_a;
+    t.obs_t = k.d_obs_t;
+    t.np = R.np;
+    t.nc = k.nc;
+    t.TA = k.TA;
+    t.noise = 1.0 / m->co.dobs;
+    t.out = b.Z;
+    zt.add(t, kron_cols_tiles(R.np, k.nc), 16.0 * R.np * k.nc);
+    t.mode = 1;
+    t.out = b.C;
+    ct.add(t, kron_cols_tiles(k.nc, k.nc), 16.0 * k.nc * k.nc);
+    StencilTask st{};
+    st.rg = m->d_regions + ch.region;
+    st.qs = m->d_kk13;
+    st.ns = m->plan.ns;
+    st.M = b.Z;
+    st.ldm = R.np;
+    st.alpha = 1.0;
+    st.out = b.KZ;
+    st.ldout = R.np;
+    st.ncols = k.nc;
+    kz.add(st, R.np, R.nb);
+    InvJob j = b.inv;
+    j.M = b.C;
+    j.np = k.nc;
+    j.nb = k.nobs;
+    j.info = m->d_info + m->plan.bj.size() + k.chain;
+    j.base = 0;
+    jobs.push_back(j);
+  }
+  pg.kron(ar, 15, zt);
+  pg.stencil(ar, kz);
+  pg.kron(ar, 15, ct);
+  pg.inverse(ar, jobs);
+  for (int g = 0; g < maxTA; ++g) {
+    GemmList gx;
+    TileList<KronReduceTask> rl;
+    for (size_t i = i0; i < i1; ++i) {
+      rbmc_model* m = ms[refs[i].first];
+      const rbmc_model::KronSub& k = m->ksub[refs[i].second];
+      if (g >= k.TA || k.gpad[g] == 0) continue;
+      const rbmc_model::KronReg& R = m->kreg[m->kreg_of[m->plan.sub[k.chain].region]];
+      const KronBuf& b = kb[i - i0];
+      // X_g = Z_g Y_{g,:}  (np x nc, K = the group's slots)
+      gx.add(b.Z + (size_t)k.goff[g] * R.np, b.C + k.goff[g], nullptr, b.X, R.np, k.nc, k.gpad[g],
+             R.np, k.nc, R.np, 1.0, 0.0, 0, 0, R.nb, k.gpad[g]);
+      KronReduceTask rt{};
+      rt.X = b.X;
+      rt.Z = b.Z;
+      rt.KZ = b.KZ;
+      rt.obs_a = k.d_obs_a;
+      rt.goff = k.d_goff;
+      rt.gpad = k.d_gpad;
+      rt.part = b.part;
+      rt.np = R.np;
+      rt.TA = k.TA;
+      rt.g = g;
+      rl.add(rt, (R.np + 63) / 64, 24.0 * R.np * k.nc);
+    }
+    pg.gemm(ar, gx);
+    pg.kron(ar, 16, rl, RBMC_KF_KRON_REDUCE);
+  }
+  TileList<KronDetTask> dt;
+  for (size_t i = i0; i < i1; ++i) {
+    rbmc_model* m = ms[refs[i].first];
+    const rbmc_model::KronSub& k = m->ksub[refs[i].second];
+    const Chain& ch = m->plan.sub[k.chain];
+    const rbmc_model::KronReg& R = m->kreg[m->kreg_of[ch.region]];
+    const KronBuf& b = kb[i - i0];
+    const size_t c = lidx[i];
+    for (int t = ch.ct0 - ch.t0; t < ch.ct0 - ch.t0 + ch.cT; ++t) {
+      KronDetTask d{};
+      d.V = b.V;
+      d.part = b.part;
+      d.dR = R.dR;
+      d.qR = R.qR;
+      d.kR = R.kR;
+      d.rg = m->d_regions + ch.region;
+      d.dm = m->d_dm;
+      d.diag_out = diag_out[refs[i].first];
+      d.partial = cx->epart;
+      d.out_index = (int)L.det_index(c, t, 0);
+      d.nchk = (int)L.nchk(c);
+      d.TA = k.TA;
+      d.t = t;
+      d.t0 = ch.t0;
+      dt.add(d, (int)L.nchk(c));
+    }
+  }
+  pg.kron(ar, 17, dt);
+  // info flags of the batch's capacitance inversions start at zero
+  for (size_t i = i0; i < i1; ++i) {
+    rbmc_model* m = ms[refs[i].first];
+    HIPCHK(hipMemsetAsync(m->d_info + m->plan.bj.size() + m->ksub[refs[i].second].chain, 0, 4, s));
+  }
+  HIPCHK(ar.upload(s));
+  rbmc_status st = run(cx, pg, s, ar);
+  if (st != RBMC_OK) return st;
+  HIPCHK(hipStreamSynchronize(s));
+  for (size_t i = i0; i < i1; ++i) {
+    rbmc_model* m = ms[refs[i].first];
+    const int c = m->ksub[refs[i].second].chain;
+    int v = 0;
+    HIPCHK(hipMemcpy(&v, m->d_info + m->plan.bj.size() + c, 4, hipMemcpyDeviceToHost));
+    if (v != 0) {
+      if (rep) {
+        rep->fail_subdomain = c;
+        rep->fail_block = v - 1;
+      }
+      return fail(RBMC_E_NOT_SPD, "capacitance matrix of subdomain " + std::to_string(c) +
+                                      " lost positive definiteness");
+    }
+  }
+  return RBMC_OK;
+}
+
+// Correction solves and Monte Carlo sums of one batch (samples x at x_base in
+// the column layout h, nk of them).
+// gather_z: form Z = S^-1[:, a_o] first (a pass after the first, whose Z
+// went with the batch's deterministic part); scale = 1 / (total samples),
+// accum: add to the Monte Carlo sums of earlier passes.
+rbmc_status kron_corr_batch(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const HostCols& h,
+                            int nk, const double* x_base,
+                            const std::vector<std::pair<int, int>>& refs, size_t i0, size_t i1,
+                            const std::vector<KronBuf>& kb, const EstLayout& L,
+                            const std::vector<size_t>& lidx,
+                            const std::vector<double*>& diag_out, int mixed, bool gather_z,
+                            double scale, int accum, hipStream_t s) {
+  Arena& ar = cx->arenaB;
+  ar.clear();
+  Program pg;
+  if (gather_z) {
+    TileList<KronBuildTask> zt;
+    for (size_t i = i0; i < i1; ++i) {
+      rbmc_model* m = ms[refs[i].first];
+      const rbmc_model::KronSub& k = m->ksub[refs[i].second];
+      const rbmc_model::KronReg& R = m->kreg[m->kreg_of[m->plan.sub[k.chain].region]];
+      KronBuildTask t{};
+      t.mode = 0;
+      t.inv = R.inv;
+      t.obs_a = k.d_obs_a;
+      t.obs_t = k.d_obs_t;
+      t.np = R.np;
+      t.nc = k.nc;
+      t.TA = k.TA;
+      t.out = kb[i - i0].Z;
+      zt.add(t, kron_cols_tiles(R.np, k.nc), 16.0 * R.np * k.nc);
+    }
+    pg.kron(ar, 15, zt);
+  }
+  TileList<PanelTask> rt;
+  GemmList gu, gw, gz;
+  gu.mixed = gw.mixed = gz.mixed = mixed;
+  TileList<KronMixTask> m1, m2;
+  TileList<KronObsTask> ob;
+  TileList<McTask> mt;
+  for (size_t i = i0; i < i1; ++i) {
+    const int j = refs[i].first;
+    rbmc_model* m = ms[j];
+    const rbmc_model::KronSub& k = m->ksub[refs[i].second];
+    const Chain& ch = m->plan.sub[k.chain];
+    const rbmc_model::KronReg& R = m->kreg[m->kreg_of[ch.region]];
+    const KronBuf& b = kb[i - i0];
+    const size_t panel = (size_t)R.np * nk;
+    for (int t = 0; t < k.TA; ++t) {  // r = Q_AB x_B, one panel per step
+      PanelTask pt{};
+      pt.P = b.Rb + (size_t)t * panel;
+      pt.rg = m->d_regions + ch.region;
+      pt.dm = m->d_dm;
+      pt.X = x_base + h.base[j];
+      pt.n_k = nk;
+      pt.t = ch.t0 + t;
+      pt.t0 = ch.t0;
+      pt.T = ch.T;
+      pt.mode = 2;
+      rt.add(pt, panel_tiles(R.np, nk), 16.0 * R.nb * nk);
+    }
+    // U = S^-1 R over all steps at once (panels are stacked columns)
+    gu.add(R.inv, b.Rb, nullptr, b.Ub, R.np, k.TA * nk, R.np, R.np, R.np, R.np, 1.0, 0.0, 0, 0,
+           R.nb, R.nb);
+    KronMixTask mx{};
+    mx.V = b.V;
+    mx.U = b.Ub;
+    mx.In = nullptr;
+    mx.out = b.Rb;
+    mx.np = R.np;
+    mx.n_k = nk;
+    mx.TA = k.TA;
+    mx.alpha = 1.0;
+    mx.beta = 0.0;
+    m1.add(mx, kron_mix_tiles(R.np, nk));
+    KronObsTask ot{};
+    ot.U = b.Rb;
+    ot.v = b.v;
+    ot.obs_a = k.d_obs_a;
+    ot.obs_t = k.d_obs_t;
+    ot.np = R.np;
+    ot.nc = k.nc;
+    ot.n_k = nk;
+    ob.add(ot, kron_cols_tiles(k.nc, nk));
+    gw.add(b.C, b.v, nullptr, b.w, k.nc, nk, k.nc, k.nc, k.nc, k.nc, 1.0, 0.0, 0, 0, k.nobs,
+           k.nobs);
+    for (int g = 0; g < k.TA; ++g)
+      if (k.gpad[g] > 0)
+        gz.add(b.Z + (size_t)k.goff[g] * R.np, b.w + k.goff[g], nullptr, b.Ub + (size_t)g * panel,
+               R.np, nk, k.gpad[g], R.np, k.nc, R.np, 1.0, 0.0, 0, 0, R.nb, k.gpad[g]);
+    mx.U = b.Ub;
+    mx.In = b.Rb;
+    mx.out = b.Rb;
+    mx.alpha = -1.0;
+    mx.beta = 1.0;
+    m2.add(mx, kron_mix_tiles(R.np, nk));
+    const size_t c = lidx[i];
+    for (int t = ch.ct0 - ch.t0; t < ch.ct0 - ch.t0 + ch.cT; ++t) {
+      McTask q{};
+      q.mu[0] = t - 1 >= 0 ? b.Rb + (size_t)(t - 1) * panel : nullptr;
+      q.mu[1] = b.Rb + (size_t)t * panel;
+      q.mu[2] = t + 1 < k.TA ? b.Rb + (size_t)(t + 1) * panel : nullptr;
+      q.np = R.np;
+      q.rg = m->d_regions + ch.region;
+      q.dm = m->d_dm;
+      q.diag_out = diag_out[j];
+      q.partial = cx->epart + L.det_len;
+      q.out_index = (int)L.mc_index(c, t);
+      q.n_k = nk;
+      q.scale = scale;
+      q.accum = accum;
+      q.t = ch.t0 + t;
+      mt.add(q, R.np / 64);
+    }
+  }
+  pg.panels(ar, rt);
+  pg.gemm(ar, gu);
+  pg.kron(ar, 18, m1);
+  pg.kron(ar, 19, ob);
+  pg.gemm(ar, gw);
+  for (size_t i = i0; i < i1; ++i) {
+    rbmc_model* m = ms[refs[i].first];
+    const rbmc_model::KronSub& k = m->ksub[refs[i].second];
+    const rbmc_model::KronReg& R = m->kreg[m->kreg_of[m->plan.sub[k.chain].region]];
+    pg.fill(kb[i - i0].Ub, (size_t)R.np * k.TA * nk);
+  }
+  pg.gemm(ar, gz);
+  pg.kron(ar, 18, m2);
+  pg.mc(ar, mt);
+  HIPCHK(ar.upload(s));
+  rbmc_status st = run(cx, pg, s, ar);
+  if (st != RBMC_OK) return st;
+  HIPCHK(hipStreamSynchronize(s));
+  return RBMC_OK;
+}
+
+// Samples of pass c of a chunked estimate: columns [k0, k0 + kn) of every
+// model in the column layout *h, at *x.
+using KronSampler =
+    std::function<rbmc_status(int k0, int kn, const double** x, HostCols* h, rbmc_report* r)>;
+
+// Device workspace of one subdomain in a pass after the first (Z, V and the
+// correction buffers; Y is in the bank).
+size_t kron_corr_bytes(const rbmc_model* m, const rbmc_model::KronSub& k, int nk) {
+  const rbmc_model::KronReg& R = m->kreg[m->kreg_of[m->plan.sub[k.chain].region]];
+  const size_t np = R.np, nc = k.nc, TA = k.TA;
+  return (np * nc + TA * TA + 2 * np * TA * nk + 2 * nc * nk) * 8 + 10 * 256;
+}
+
+// The estimator by the Kronecker method, over batches of subdomains sized to
+// the free device memory.  Samples: x_given (layout *h_given, nk_total
+// columns) or, when sampler is set, passes of `chunk` columns drawn by it.
+// With one pass every batch forms its selected entries and corrects its
+// subdomains in turn; with several, the selected entries come first (Y of
+// every subdomain kept in the bank), then each pass draws its samples and
+// corrects all batches, adding to the Monte Carlo sums.
+rbmc_status estimate_set_kron(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms,
+                              const rbmc_est_opts* o, int nk_total, int chunk,
+                              const KronSampler& sampler, const double* x_given,
+                              const HostCols* h_given, const std::vector<double*>& diag_out,
+                              const std::vector<double*>& trace_out, rbmc_report* rep) {
+  g_tune = cx->tune;
+  const int mixed = o->precision == RBMC_MIXED;
+  hipStream_t s = cx->stream;
+  const int npass = nk_total > 0 ? (nk_total + chunk - 1) / chunk : 0;
+  double t_fac = 0.0, t_cor = 0.0, t_smp = 0.0, ta = now_s();
+  rbmc_status st = RBMC_OK, st_s = RBMC_OK;
+  for (rbmc_model* m : ms) {
+    st = kron_static(m);
+    if (st != RBMC_OK) return st;
+  }
+  const std::vector<std::pair<int, int>> refs = kron_refs(ms);
+  EstLayout L;
+  std::vector<size_t> lidx;
+  for (const auto& r : refs) {
+    rbmc_model* m = ms[r.first];
+    const Chain& ch = m->plan.sub[m->ksub[r.second].chain];
+    lidx.push_back(L.ch.size());
+    L.add(ch, m, m->kreg[m->kreg_of[ch.region]].np, r.first);
+  }
+  L.finish();
+  st = ensure_epart(cx, L);
+  if (st != RBMC_OK) return st;
+  launch_fill(cx->epart, L.det_len + L.mc_len, 0.0, s);
+  // sampler report, summed over passes
+  int it_max = 0;
+  double it_sum = 0.0, res_max = 0.0;
+  auto draw = [&](int k0, int kn, const double** x, HostCols* hc) -> rbmc_status {
+    rbmc_report r{};
+    const double t = now_s();
+    rbmc_status e = sampler(k0, kn, x, hc, &r);
+    t_smp += now_s() - t;
+    if (e < 0) return e;
+    if (e != RBMC_OK) st_s = e;
+    it_max = std::max(it_max, r.pcg_it_max);
+    it_sum += r.pcg_it_mean * kn;
+    res_max = std::max(res_max, r.max_rel_residual);
+    return RBMC_OK;
+  };
+  // one pass: samples first, corrected batch by batch with the selected entries
+  const double* x1 = x_given;
+  HostCols h1;
+  if (npass == 1 && sampler) {
+    st = draw(0, nk_total, &x1, &h1);
+    if (st != RBMC_OK) return st;
+  } else if (x_given) {
+    h1 = *h_given;
+  }
+  ta = now_s();
+  st = kron_regions(cx, ms, s, rep);
+  if (st != RBMC_OK) return st;
+  // several passes: Y of every subdomain and the deterministic diagonals in the bank
+  std::vector<double*> ybank(refs.size(), nullptr), ddet(ms.size(), nullptr);
+  if (npass > 1) {
+    size_t need = 0;
+    for (const auto& r : refs) {
+      const size_t nc = ms[r.first]->ksub[r.second].nc;
+      need += nc * nc * 8 + 256;
+    }
+    for (rbmc_model* m : ms) need += (size_t)m->plan.n * 8 + 256;
+    cx->kbank.release();
+    char* base = nullptr;
+    HIPCHK(cx->kbank.alloc((void**)&base, need));
+    Carve cb{base, 0};
+    for (size_t i = 0; i < refs.size(); ++i) {
+      const size_t nc = ms[refs[i].first]->ksub[refs[i].second].nc;
+      ybank[i] = cb.d(nc * nc);
+    }
+    for (size_t j = 0; j < ms.size(); ++j) ddet[j] = cb.d((size_t)ms[j]->plan.n);
+  }
+  size_t free_b = 0, total_b = 0;
+  HIPCHK(hipMemGetInfo(&free_b, &total_b));
+  const size_t reserve = ((size_t)1 << 30) + total_b / 64;
+  size_t avail = free_b + cx->kws_cap > reserve ? free_b + cx->kws_cap - reserve : 0;
+  if (cx->kron_batch_cap > 0) avail = std::min(avail, cx->kron_batch_cap);
+  t_fac += now_s() - ta;
+  // batches [i0, i1) of refs whose workspace fits
+  auto next_batch = [&](size_t i0, bool corr_only, int nk) {
+    size_t i1 = i0, bytes = 0;
+    while (i1 < refs.size()) {
+      const rbmc_model* m = ms[refs[i1].first];
+      const rbmc_model::KronSub& k = m->ksub[refs[i1].second];
+      const size_t b = corr_only ? kron_corr_bytes(m, k, nk) : kron_sub_bytes(m, k, nk);
+      if (i1 > i0 && bytes + b > avail) break;
+      bytes += b;
+      ++i1;
+    }
+    return std::make_pair(i1, bytes);
+  };
+  // carve a batch; V of each subdomain uploaded
+  auto carve_batch = [&](size_t i0, size_t i1, bool corr_only, int nk,
+                         std::vector<KronBuf>& kb) -> rbmc_status {
+    Carve cv{cx->kws_base, 0};
+    kb.assign(i1 - i0, KronBuf{});
+    std::vector<double> hV;
+    std::vector<size_t> vat;
+    for (size_t i = i0; i < i1; ++i) {
+      rbmc_model* m = ms[refs[i].first];
+      const rbmc_model::KronSub& k = m->ksub[refs[i].second];
+      const Chain& ch = m->plan.sub[k.chain];
+      const int np = m->kreg[m->kreg_of[ch.region]].np;
+      KronBuf& b = kb[i - i0];
+      b.Z = cv.d((size_t)np * k.nc);
+      b.V = cv.d((size_t)k.TA * k.TA);
+      if (!corr_only) {
+        b.KZ = cv.d((size_t)np * k.nc);
+        b.X = cv.d((size_t)np * k.nc);
+        b.part = cv.d((size_t)k.TA * k.TA * 3 * np);
+        b.C = npass > 1 ? ybank[i] : cv.d((size_t)k.nc * k.nc);
+        carve_gj(cv, k.nc, b.inv);
+      } else {
+        b.C = ybank[i];
+      }
+      if (nk > 0 && (corr_only || npass == 1)) {
+        b.Rb = cv.d((size_t)np * k.TA * nk);
+        b.Ub = cv.d((size_t)np * k.TA * nk);
+        b.v = cv.d((size_t)k.nc * nk);
+        b.w = cv.d((size_t)k.nc * nk);
+      }
+      const std::vector<double> V = time_inverse(m->co, ch.t0, k.TA);
+      vat.push_back(hV.size());
+      hV.insert(hV.end(), V.begin(), V.end());
+    }
+    for (size_t i = i0; i < i1; ++i) {
+      const size_t len = (i + 1 < i1 ? vat[i + 1 - i0] : hV.size()) - vat[i - i0];
+      HIPCHK(hipMemcpyAsync(kb[i - i0].V, hV.data() + vat[i - i0], len * 8,
+                            hipMemcpyHostToDevice, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));  // hV is host memory of this scope
+    return RBMC_OK;
+  };
+  const int nk1 = npass == 1 ? nk_total : 0;  // samples corrected with the selected entries
+  std::vector<KronBuf> kb;
+  for (size_t i0 = 0; i0 < refs.size();) {
+    const auto nb = next_batch(i0, false, nk1);
+    const size_t i1 = nb.first;
+    st = ensure_kws(cx, nb.second);
+    if (st != RBMC_OK) return st;
+    st = carve_batch(i0, i1, false, nk1, kb);
+    if (st != RBMC_OK) return st;
+    double tb = now_s();
+    st = kron_det_batch(cx, ms, refs, i0, i1, kb, L, lidx, diag_out, s, rep);
+    if (st != RBMC_OK) return st;
+    t_fac += now_s() - tb;
+    if (nk1 > 0) {
+      tb = now_s();
+      st = kron_corr_batch(cx, ms, h1, nk1, x1, refs, i0, i1, kb, L, lidx, diag_out, mixed,
+                           false, 1.0 / nk1, 0, s);
+      if (st != RBMC_OK) return st;
+      t_cor += now_s() - tb;
+    }
+    i0 = i1;
+  }
+  if (npass > 1) {
+    for (size_t j = 0; j < ms.size(); ++j)
+      HIPCHK(hipMemcpyAsync(ddet[j], diag_out[j], (size_t)ms[j]->plan.n * 8,
+                            hipMemcpyDeviceToDevice, s));
+    for (int c = 0; c < npass; ++c) {
+      const int k0 = c * chunk, kn = std::min(chunk, nk_total - k0);
+      const double* xc = nullptr;
+      HostCols hc;
+      st = draw(k0, kn, &xc, &hc);
+      if (st != RBMC_OK) return st;
+      const double tb = now_s();
+      for (size_t i0 = 0; i0 < refs.size();) {
+        const auto nb = next_batch(i0, true, kn);
+        const size_t i1 = nb.first;
+        st = ensure_kws(cx, nb.second);
+        if (st != RBMC_OK) return st;
+        st = carve_batch(i0, i1, true, kn, kb);
+        if (st != RBMC_OK) return st;
+        st = kron_corr_batch(cx, ms, hc, kn, xc, refs, i0, i1, kb, L, lidx, diag_out, mixed,
+                             true, 1.0 / nk_total, c > 0 ? 1 : 0, s);
+        if (st != RBMC_OK) return st;
+        i0 = i1;
+      }
+      t_cor += now_s() - tb;
+    }
+  }
+  st = combine_traces(cx, L, ms, nk_total, o, trace_out, rep);
+  if (st != RBMC_OK) return st;
+  if (rep && npass > 1) {  // plug-in error from the Monte Carlo share of each node
+    size_t n_total = 0;
+    double share = 0.0;
+    for (size_t j = 0; j < ms.size(); ++j) {
+      const size_t n = ms[j]->plan.n;
+      n_total += n;
+      const int nbk = mc_share_blocks(n);
+      launch_mc_share(diag_out[j], ddet[j], n, cx->epart, s);
+      std::vector<double> hp(nbk);
+      HIPCHK(hipMemcpyAsync(hp.data(), cx->epart, nbk * 8, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      for (double v : hp) share += v;
+    }
+    rep->err_estimate = std::sqrt(2.0 / M_PI) * std::sqrt(2.0 / nk_total) * share / n_total;
+  }
+  if (rep) {
+    rep->t_sample = t_smp;
+    rep->t_factor = t_fac;
+    rep->t_select = 0.0;
+    rep->t_correct = t_cor;
+    rep->pcg_it_max = it_max;
+    rep->pcg_it_mean = nk_total > 0 && sampler ? it_sum / nk_total : 0.0;
+    rep->max_rel_residual = res_max;
+    int64_t bytes = cx->ws.bytes + cx->epool.bytes + cx->kws.bytes + cx->kbank.bytes;
+    for (rbmc_model* m : ms)
+      bytes += m->pool.bytes + m->work_bj.bytes + m->work_sub.bytes + m->kpool.bytes +
+               m->spool.bytes;
+    rep->peak_bytes = bytes;
+  }
+  return st_s;
+}
+
+// RBMC_SEL_AUTO: the method with fewer dense flops for the set (Gauss-Jordan
+// inversions of order n cost ~n^3; the block-tridiagonal method inverts one
+// block per step of the two sweeps and per core step, the Kronecker method one
+// spatial block per region and the capacitance matrix per subdomain, plus the
+// product Z Y).
+int resolve_method(const rbmc_est_opts* o, const std::vector<rbmc_model*>& ms) {
+  if (o->method == RBMC_SEL_BLOCKTRI || o->method == RBMC_SEL_KRON) return o->method;
+  double fb = 0.0, fk = 0.0;
+  for (const rbmc_model* m : ms) {
+    const Plan& P = m->plan;
+    const double frac = P.n > 0 ? (double)m->n_obs / P.n : 0.0;
+    std::vector<char> seen(P.regions.size(), 0);
+    for (const Chain& c : P.sub) {
+      const double nb = P.regions[c.region].nb();
+      const int lc0 = c.ct0 - c.t0, lc1 = lc0 + c.cT - 1;
+      fb += (double)(lc1 + (c.T - 1 - lc0) + c.cT) * nb * nb * nb;
+      const double no = frac * c.T * nb;
+      fk += no * no * no + 2.0 * nb * no * no;
+      if (!seen[c.region]) {
+        seen[c.region] = 1;
+        fk += nb * nb * nb;
+      }
+    }
+  }
+  return fk < fb ? RBMC_SEL_KRON : RBMC_SEL_BLOCKTRI;
+}
+
 // Validate a set of models for one call.
 rbmc_status check_models(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms) {
   for (rbmc_model* m : ms) {
@@ -2241,18 +3349,58 @@ rbmc_status check_models(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms) {
 rbmc_status estimate_full(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms,
                           const rbmc_est_opts* opts, const std::vector<const double*>& z_ptrs,
                           const std::vector<double*>& diag_out,
-                          const std::vector<double*>& trace_out, rbmc_report* rep) {
+                          const std::vector<double*>& trace_out, rbmc_report* rep,
+                          bool device_z = false, uint64_t seed = 0) {
   const int nk = opts->n_samples;
+  if (resolve_method(opts, ms) == RBMC_SEL_KRON) {
+    // passes of `chunk` samples: z columns [k0, k0 + kn) of every model
+    // (given, or drawn from seed + model index on the device), sampled on the
+    // caller's stream
+    const int chunk = (opts->sample_chunk > 0 && opts->sample_chunk < nk) ? opts->sample_chunk
+                                                                          : std::max(nk, 1);
+    if (!cols_fit(ms.size(), chunk))
+      return fail(RBMC_E_ARG, "n_models * (samples per pass) exceeds 65535 columns");
+    HostCols hpass;
+    KronSampler smp = [&](int k0, int kn, const double** x, HostCols* hc,
+                          rbmc_report* r) -> rbmc_status {
+      *hc = make_cols(ms, kn);
+      const bool cat = device_z || ms.size() > 1;
+      rbmc_status e = ensure_ws(cx, ms, *hc, cat);
+      if (e != RBMC_OK) return e;
+      const double* zb = nullptr;
+      if (cat) {
+        for (size_t j = 0; j < ms.size(); ++j) {
+          const size_t nz = (size_t)(ms[j]->plan.n + ms[j]->n_obs);
+          if (device_z)
+            launch_normals(seed + j, (size_t)k0 * nz, (size_t)kn * nz, cx->zcat + hc->zbase[j],
+                           cx->stream);
+          else
+            HIPCHK(hipMemcpyAsync(cx->zcat + hc->zbase[j], z_ptrs[j] + (size_t)k0 * nz,
+                                  (size_t)kn * nz * 8, hipMemcpyDeviceToDevice, cx->stream));
+        }
+        HIPCHK(hipGetLastError());
+        zb = cx->zcat;
+      } else {
+        zb = z_ptrs[0] + (size_t)k0 * (ms[0]->plan.n + ms[0]->n_obs);
+      }
+      rbmc_est_opts oc = *opts;
+      oc.n_samples = kn;
+      e = sample_set(cx, ms, *hc, &oc, zb, cx->x, r, cx->stream);
+      *x = cx->x;
+      return e;
+    };
+    rbmc_status st = estimate_set_kron(cx, ms, opts, nk, chunk, smp, nullptr, nullptr, diag_out,
+                                       trace_out, rep);
+    (void)hpass;
+    return st;
+  }
+  if (device_z) return fail(RBMC_E_UNSUPPORTED, "device normals need RBMC_SEL_KRON");
   if (!cols_fit(ms.size(), nk))
     return fail(RBMC_E_ARG, "n_models * n_samples exceeds 65535 columns per call");
   const HostCols h = make_cols(ms, nk);
   const bool single = ms.size() == 1;
   rbmc_status st = ensure_ws(cx, ms, h, !single && nk > 0);
   if (st != RBMC_OK) return st;
-  for (rbmc_model* m : ms) {
-    st = ensure_panels(m, nk);
-    if (st != RBMC_OK) return st;
-  }
   const double* zb = nullptr;
   if (nk > 0) {
     if (single) {
@@ -2380,6 +3528,8 @@ rbmc_status rbmc_ctx_create(int device, void* hip_stream, rbmc_ctx** out) {
   if (const char* e = std::getenv("RBMC_OVERLAP")) c->overlap = std::atoi(e) != 0;
   if (const char* e = std::getenv("RBMC_LAUNCH_THREADS")) c->launch_threads = std::atoi(e) > 1;
   if (const char* e = std::getenv("RBMC_RESERVE_CUS")) c->reserve_cus = std::atoi(e);
+  if (const char* e = std::getenv("RBMC_KRON_BATCH_BYTES"))
+    c->kron_batch_cap = (size_t)std::strtoull(e, nullptr, 10);
   *out = c;
   return RBMC_OK;
 }
@@ -2428,7 +3578,10 @@ rbmc_status rbmc_model_create(rbmc_ctx* ctx, const rbmc_model_desc* desc,
   make_coefs(P.mx, P.my, P.T, desc->h, desc->log_kappa, desc->log_tau, desc->rho,
              desc->log_sigma, m->co);
   auto cleanup = [&](rbmc_status st) {
-    m->work.release();
+    m->work_bj.release();
+    m->work_sub.release();
+    m->kpool.release();
+    m->spool.release();
     m->pool.release();
     delete m;
     return st;
@@ -2494,11 +3647,9 @@ rbmc_status rbmc_model_create(rbmc_ctx* ctx, const rbmc_model_desc* desc,
                  hipMemcpyHostToDevice));
   MCHK(m->pool.alloc((void**)&m->d_info, (P.bj.size() + P.sub.size()) * 4));
   {
-    rbmc_status st = alloc_chainset(m, m->bj, P.bj, false, 0);
-    if (st != RBMC_OK) return cleanup(st);
-    st = alloc_chainset(m, m->sub, P.sub, true, (int)P.bj.size());
-    if (st != RBMC_OK) return cleanup(st);
-    st = upload_coefs(m);
+    // the chain sets, the Kronecker data and the spectral data are allocated
+    // by the first call that uses them
+    rbmc_status st = upload_coefs(m);
     if (st != RBMC_OK) return cleanup(st);
   }
 #undef MCHK
@@ -2512,7 +3663,10 @@ void rbmc_model_destroy(rbmc_model* m) {
   (void)hipStreamSynchronize(m->ctx->stream);
   for (hipStream_t q : {m->ctx->side, m->ctx->side2, m->ctx->work})
     if (q) (void)hipStreamSynchronize(q);
-  m->work.release();
+  m->work_bj.release();
+  m->work_sub.release();
+  m->kpool.release();
+  m->spool.release();
   m->lwork.release();
   m->pool.release();
   delete m;
@@ -2563,12 +3717,10 @@ rbmc_status rbmc_sample(rbmc_model* m, const rbmc_est_opts* opts, const double* 
   const HostCols h = make_cols(ms, opts->n_samples);
   st = ensure_ws(m->ctx, ms, h, false);
   if (st != RBMC_OK) return st;
-  st = ensure_panels(m, opts->n_samples);
-  if (st != RBMC_OK) return st;
   st = sample_set(m->ctx, ms, h, opts, z, x, rep, m->ctx->stream);
   if (rep) {
     rep->t_total = now_s() - t0;
-    rep->peak_bytes = m->ctx->ws.bytes + m->pool.bytes + m->work.bytes;
+    rep->peak_bytes = m->ctx->ws.bytes + m->pool.bytes + m->work_bj.bytes + m->spool.bytes;
   }
   return st;
 }
@@ -2585,28 +3737,46 @@ rbmc_status rbmc_estimate_from_samples(rbmc_model* m, const rbmc_est_opts* opts,
   double t0 = now_s();
   std::vector<rbmc_model*> ms{m};
   const HostCols h = make_cols(ms, opts->n_samples);
-  st = ensure_panels(m, opts->n_samples);
-  if (st != RBMC_OK) return st;
-  st = estimate_set(m->ctx, ms, h, opts, x, {diag_out}, {trace_out}, rep, {});
+  if (resolve_method(opts, ms) == RBMC_SEL_KRON)
+    st = estimate_set_kron(m->ctx, ms, opts, opts->n_samples, std::max(opts->n_samples, 1), {}, x,
+                           &h, {diag_out}, {trace_out}, rep);
+  else
+    st = estimate_set(m->ctx, ms, h, opts, x, {diag_out}, {trace_out}, rep, {});
   if (rep) rep->t_total = now_s() - t0;
   return st;
 }
 
 rbmc_status rbmc_estimate(rbmc_model* m, const rbmc_est_opts* opts, const double* z, uint64_t seed,
                           double* diag_out, double* trace_out, rbmc_report* rep) {
-  (void)seed;
   init_report(rep);
   if (!m || !diag_out) return fail(RBMC_E_ARG, "NULL argument");
   rbmc_status st = check_opts(opts, true);
   if (st != RBMC_OK) return st;
-  if (opts->n_samples > 0 && !z)
-    return fail(RBMC_E_UNSUPPORTED, "z must be supplied (device sampling of z is not built)");
   if (opts->grad_mask && !trace_out) return fail(RBMC_E_ARG, "trace_out is NULL");
+  const bool device_z = opts->n_samples > 0 && !z;
+  if (device_z && resolve_method(opts, {m}) != RBMC_SEL_KRON)
+    return fail(RBMC_E_UNSUPPORTED, "z = NULL (device normals) needs the Kronecker method");
+  if (opts->sample_chunk > 0 && opts->sample_chunk < opts->n_samples &&
+      resolve_method(opts, {m}) != RBMC_SEL_KRON)
+    return fail(RBMC_E_UNSUPPORTED, "sample_chunk < n_samples needs the Kronecker method");
   HIPCHK(hipSetDevice(m->ctx->device));
   double t0 = now_s();
-  st = estimate_full(m->ctx, {m}, opts, {z}, {diag_out}, {trace_out}, rep);
+  st = estimate_full(m->ctx, {m}, opts, {z}, {diag_out}, {trace_out}, rep, device_z, seed);
   if (rep) rep->t_total = now_s() - t0;
   return st;
+}
+
+rbmc_status rbmc_normals(rbmc_ctx* ctx, uint64_t seed, uint64_t offset, int64_t count,
+                         double* out) {
+  if (!ctx) return fail(RBMC_E_ARG, "ctx is NULL");
+  if (count < 0) return fail(RBMC_E_ARG, "count must be >= 0");
+  if (count == 0) return RBMC_OK;
+  if (!out) return fail(RBMC_E_ARG, "out is NULL");
+  HIPCHK(hipSetDevice(ctx->device));
+  launch_normals(seed, offset, (size_t)count, out, ctx->stream);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return RBMC_OK;
 }
 
 rbmc_status rbmc_estimate_batched(rbmc_ctx* ctx, int32_t n_models, rbmc_model* const* models,

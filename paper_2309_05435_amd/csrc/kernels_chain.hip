@@ -364,10 +364,10 @@ __global__ __launch_bounds__(256) void k_mc(const McTask* __restrict__ tasks, in
     const double s = (red[7][threadIdx.x] + red[7][threadIdx.x + 64]) +
                      (red[7][threadIdx.x + 128] + red[7][threadIdx.x + 192]);
     const size_t i = (size_t)tk.t * m.ns + G(rg.nodes)[a];
-    const double mhat = s / n_k;
+    const double mhat = s * tk.scale;
     const double est = G(tk.diag_out)[i] + mhat;
     G(tk.diag_out)[i] = est;
-    ratio = est > 0.0 ? mhat * n_k / est : 0.0;  // scaled back by 1/n_k below
+    ratio = est > 0.0 ? mhat / est : 0.0;
   }
   __syncthreads();
   red[7][threadIdx.x] = ratio;
@@ -377,8 +377,11 @@ __global__ __launch_bounds__(256) void k_mc(const McTask* __restrict__ tasks, in
       for (int c = 0; c < 8; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + st];
     __syncthreads();
   }
-  if (threadIdx.x < 8)
-    G(tk.partial)[((size_t)tk.out_index + chunk) * 8 + threadIdx.x] = red[threadIdx.x][0] / n_k;
+  if (threadIdx.x < 8) {
+    const double v = threadIdx.x == 7 ? red[7][0] : red[threadIdx.x][0] * tk.scale;
+    const size_t at = ((size_t)tk.out_index + chunk) * 8 + threadIdx.x;
+    G(tk.partial)[at] = tk.accum ? G(tk.partial)[at] + v : v;
+  }
 }
 
 void launch_mc(const McTask* d_tasks, int n_tasks, int total_tiles, hipStream_t s) {

@@ -310,8 +310,10 @@ __global__ void k_pcg_p(ColSet cs, const double* __restrict__ z, double* __restr
       first ? 0.0 : (rz_sub ? rz_new[k] - rz_sub[k] : rz_new[k]) / rz_old[k];
   const size_t off = cs.off[k];
   const int n = cs.len[k];
+  // the first direction does not read p: its previous contents may be any
+  // bit pattern (0 times a stale NaN is NaN)
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-    p[off + i] = z[off + i] + beta * p[off + i];
+    p[off + i] = first ? z[off + i] : z[off + i] + beta * p[off + i];
 }
 
 __global__ void k_copy_scalars(const double* __restrict__ src, double* __restrict__ dst,
@@ -338,7 +340,9 @@ __global__ void k_pcg_check(const double* __restrict__ rr, const double* __restr
   for (int k = tid; k < n_rhs; k += 256) {
     if (active[k]) {
       it_count[k] += 1;
-      if (!(sqrt(rr[k]) > rtol * sqrt(bb[k]))) active[k] = 0;
+      // a NaN residual is not convergence: the column keeps iterating to the
+      // iteration limit and the call reports it
+      if (sqrt(rr[k]) <= rtol * sqrt(bb[k])) active[k] = 0;
     }
     c += active[k] ? 1 : 0;
   }
@@ -354,6 +358,96 @@ __global__ void k_pcg_check(const double* __restrict__ rr, const double* __restr
 void launch_pcg_check(const double* rr, const double* bb, double rtol, uint8_t* active,
                       int* it_count, int* n_active, int n_rhs, hipStream_t s) {
   k_pcg_check<<<1, 256, 0, s>>>(rr, bb, rtol, active, it_count, n_active, n_rhs);
+}
+
+// ---------------------------------------------------------------------------
+// Spectral preconditioner M = Q_t (x) Q_s + dbar I.  Q_s is a polynomial in
+// the Neumann grid Laplacian G = G_x (+) G_y, which the 2-D DCT-II
+// diagonalizes; in that basis M splits into one symmetric tridiagonal
+// T x T system per spatial frequency f:
+//   (lambda_f Q_t + dbar I) y_f = r_f,
+// diagonal lambda_f q_d(t) + dbar, off-diagonal lambda_f q_o.  The forward
+// elimination coefficients c'_t = a / den_t and 1 / den_t (den_0 = b_0,
+// den_t = b_t - a c'_{t-1}) depend on f and t only: they are formed once per
+// theta; the solve then streams each column forward and back.
+// ---------------------------------------------------------------------------
+__global__ void k_spec_coef(SpecCoefTask tk) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= tk.ns) return;
+  const double lam = tk.lam[f];
+  const double a = lam * tk.qo;
+  double cp = 0.0;
+  for (int t = 0; t < tk.T; ++t) {
+    const double b = lam * tk.qd[t] + tk.dbar;
+    const double den = (t == 0) ? b : b - a * cp;
+    cp = a / den;
+    tk.cp[(size_t)t * tk.ns + f] = cp;
+    tk.id[(size_t)t * tk.ns + f] = 1.0 / den;
+  }
+  tk.off[f] = a;
+}
+
+void launch_spec_coef(const SpecCoefTask& t, hipStream_t s) {
+  if (t.ns > 0) k_spec_coef<<<(t.ns + 255) / 256, 256, 0, s>>>(t);
+}
+
+// grid (frequency blocks of the largest model, columns)
+__global__ __launch_bounds__(256) void k_spec_solve(ColSet cs, double* __restrict__ y) {
+  const int col = blockIdx.y;
+  const DevModel& m = cs.dms[cs.model[col]];
+  const int f = blockIdx.x * 256 + threadIdx.x;
+  if (f >= m.ns || m.sp_cp == nullptr) return;
+  double* yk = y + cs.off[col];
+  const double a = m.sp_off[f];
+  double prev = 0.0;
+  for (int t = 0; t < m.T; ++t) {
+    const size_t i = (size_t)t * m.ns + f;
+    prev = (yk[i] - a * prev) * m.sp_id[i];
+    yk[i] = prev;
+  }
+  for (int t = m.T - 2; t >= 0; --t) {
+    const size_t i = (size_t)t * m.ns + f;
+    prev = yk[i] - m.sp_cp[i] * prev;
+    yk[i] = prev;
+  }
+}
+
+void launch_spec_solve(const ColSet& cs, double* y, hipStream_t s) {
+  if (cs.ncols <= 0) return;
+  // the largest model's spatial size bounds the frequency index
+  k_spec_solve<<<dim3((cs.max_ns + 255) / 256, cs.ncols), 256, 0, s>>>(cs, y);
+}
+
+// Direct transform along one axis for models without the GEMM route:
+// forward  y[.., k, ..] = sum_i C[k, i] x[.., i, ..];  inverse uses C^T.
+// grid (element blocks of the longest column, columns)
+__global__ __launch_bounds__(256) void k_dct_direct(ColSet cs, const double* __restrict__ x,
+                                                    double* __restrict__ y, int axis,
+                                                    int inverse) {
+  const int col = blockIdx.y;
+  const DevModel& m = cs.dms[cs.model[col]];
+  if (m.spec_gemm || m.dct_x == nullptr) return;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= cs.len[col]) return;
+  const int t = i / m.ns, rem = i - t * m.ns, iy = rem / m.mx, ix = rem - iy * m.mx;
+  const double* xk = x + cs.off[col];
+  const int len = axis == 0 ? m.mx : m.my;
+  const int k = axis == 0 ? ix : iy;
+  const int stride = axis == 0 ? 1 : m.mx;
+  const double* C = axis == 0 ? m.dct_x : m.dct_y;
+  const size_t base = (size_t)t * m.ns + (axis == 0 ? (size_t)iy * m.mx : (size_t)ix);
+  double acc = 0.0;
+  for (int j = 0; j < len; ++j) {
+    const double c = inverse ? C[(size_t)k * len + j] : C[(size_t)j * len + k];
+    acc = fma(c, xk[base + (size_t)j * stride], acc);
+  }
+  y[cs.off[col] + i] = acc;
+}
+
+void launch_dct_direct(const ColSet& cs, const double* x, double* y, int axis, int inverse,
+                       hipStream_t s) {
+  if (cs.ncols <= 0) return;
+  k_dct_direct<<<dim3((cs.max_len + 255) / 256, cs.ncols), 256, 0, s>>>(cs, x, y, axis, inverse);
 }
 
 }  // namespace rbmc

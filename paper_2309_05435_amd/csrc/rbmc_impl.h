@@ -107,6 +107,17 @@ struct DevModel {  // device views used by the stencil kernels
   double qo, dqo, lo;
   const double* dvec;     // n: sigma^-2 * mask
   const int* obs_rank;    // n: rank among observed (or -1)
+  // spectral preconditioner (set when the model has it): orthonormal DCT-II
+  // matrices (column-major, C[k, i] = c_k cos(pi k (2 i + 1) / (2 m))), the
+  // per-frequency time recursion (c'_t, 1 / den_t at t ns + f; the
+  // off-diagonal lambda_f q_o at f) and whether the 2-D transforms run as
+  // matrix-core GEMMs (sizes multiples of 16, at least 64) or by the direct kernel
+  const double* dct_x;    // mx x mx
+  const double* dct_y;    // my x my
+  const double* sp_cp;    // T x ns
+  const double* sp_id;    // T x ns
+  const double* sp_off;   // ns
+  int spec_gemm;
 };
 
 // Column sets: the sampler works on the columns (model, sample) of one or
@@ -118,6 +129,7 @@ struct ColSet {
   int ncols;
   int max_len;
   int max_tiles;             // stencil tiles of the largest model
+  int max_ns;                // spatial nodes of the largest model
   const int64_t* off;
   const int64_t* in_off;
   const int* len;
@@ -304,13 +316,19 @@ struct OffdiagTask {
 };
 void launch_offdiag(const OffdiagTask* d_tasks, int n_tasks, int total_tiles, hipStream_t s);
 
-// Monte Carlo part from the correction panels mu_t (np x n_k) of a chain:
-//   diag_out[t*ns + node] += (1/n_k) sum_k mu_t[a,k]^2 on core nodes;
-//   partial sums of (1/n_k) sum_k mu_t[a,k] (S mu_t')[a,k] for t' = t-1, t, t+1,
-//   S in {Q_s, K}, of (1/n_k) sum_k D_a mu_t[a,k]^2 and of m_a / s2_a.
-// Partial sums of chunk c go to partial[(out_index + c) * 8 + j].
+// Monte Carlo part from the correction panels mu_t (np x n_k) of a chain, with
+// scale = 1 / (the estimate's total number of samples; n_k when it is drawn
+// in one pass):
+//   diag_out[t*ns + node] += scale sum_k mu_t[a,k]^2 on core nodes;
+//   partial sums of scale sum_k mu_t[a,k] (S mu_t')[a,k] for t' = t-1, t, t+1,
+//   S in {Q_s, K}, of scale sum_k D_a mu_t[a,k]^2 and of m_a / s2_a (the last
+//   meaningful only for a one-pass estimate).
+// Partial sums of chunk c go to partial[(out_index + c) * 8 + j] (added to the
+// previous value when accum is set).
 struct McTask {
   const double* mu[3];  // panels for t-1, t, t+1 (null if outside the chain)
+  double scale;         // 1 / (total samples of the estimate)
+  int accum;            // add to the partial sums (later sample passes)
   int np;
   const RegionDev* rg;
   const DevModel* dm;
@@ -379,5 +397,106 @@ void launch_energy_dot(const double* a, const float* af, const int* slots, const
 // safeguarded correction z_c += g_c v_c, g_c = (vr - vqu) / vqv
 void launch_gamma_axpy(const double* v, double* z, size_t n, const double* vr, const double* vqu,
                        const double* vqv, const uint8_t* active, int ncols, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Spectral preconditioner M = Q_t (x) Q_s + dbar I (kernels_stencil.hip):
+// per-frequency coefficients of the time recursion, the tridiagonal solves,
+// and the direct 2-D DCT kernel for grids the GEMM route does not take.
+// ---------------------------------------------------------------------------
+struct SpecCoefTask {
+  const double* lam;   // ns eigenvalues of Q_s (DCT order f = ky mx + kx)
+  const double* qd;    // T
+  double qo, dbar;
+  int ns, T;
+  double *cp, *id, *off;
+};
+void launch_spec_coef(const SpecCoefTask& t, hipStream_t s);
+// in place on every column of the set (columns of spectral models only)
+void launch_spec_solve(const ColSet& cs, double* y, hipStream_t s);
+// y = transform of x along one axis (0: x, 1: y); inverse = 1 applies C^T;
+// columns of models with spec_gemm set are skipped
+void launch_dct_direct(const ColSet& cs, const double* x, double* y, int axis, int inverse,
+                       hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Kronecker form of the subdomain inverse (kernels_kron.hip)
+// ---------------------------------------------------------------------------
+struct KronRegionTask {  // per region: dR, qR, kR from S^-1 (np x np)
+  const double* inv;
+  const RegionDev* rg;
+  const DevModel* dm;
+  double *dR, *qR, *kR;
+  int tile_start;
+};
+void launch_kron_region(const KronRegionTask* d_tasks, int n_tasks, int total_tiles,
+                        hipStream_t s);
+struct KronBuildTask {  // mode 0: Z = S^-1[:, a_o] (np x nc); mode 1: C (nc x nc) from Z
+  int mode;
+  const double* inv;
+  const double* Z;
+  const double* V;     // TA x TA
+  const int* obs_a;    // nc: region-local node of slot o, -1 unused
+  const int* obs_t;    // nc: local time step of slot o
+  double* out;
+  int np, nc, TA;
+  double noise;        // sigma^2 = D_o^-1
+  int tile_start;
+};
+int kron_cols_tiles(int rows, int cols);
+void launch_kron_build(const KronBuildTask* d_tasks, int n_tasks, int total_tiles,
+                       hipStream_t s);
+struct KronReduceTask {  // group sums of X_g against Z, KZ, the observed entries
+  const double* X;
+  const double* Z;
+  const double* KZ;
+  const int* obs_a;
+  const int* goff;     // TA: first slot of each time group
+  const int* gpad;     // TA: slots of each time group (multiple of 16)
+  double* part;        // TA x TA x 3 x np
+  int np, TA, g;
+  int tile_start;
+};
+void launch_kron_reduce(const KronReduceTask* d_tasks, int n_tasks, int total_tiles,
+                        hipStream_t s);
+struct KronDetTask {  // deterministic entries at one core step t of a subdomain
+  const double* V;
+  const double* part;
+  const double *dR, *qR, *kR;
+  const RegionDev* rg;
+  const DevModel* dm;
+  double* diag_out;
+  double* partial;
+  int out_index, nchk;
+  int TA, t, t0;
+  int tile_start;
+};
+void launch_kron_det(const KronDetTask* d_tasks, int n_tasks, int total_tiles, hipStream_t s);
+struct KronMixTask {  // out_t = beta In_t + alpha sum_t' V[t,t'] U_t' over stacked panels
+  const double* V;
+  const double* U;
+  const double* In;
+  double* out;
+  int np, n_k, TA;
+  double alpha, beta;
+  int tile_start;
+};
+int kron_mix_tiles(int np, int n_k);
+void launch_kron_tmix(const KronMixTask* d_tasks, int n_tasks, int total_tiles, hipStream_t s);
+struct KronObsTask {  // v = observed entries of stacked panels U (nc x n_k)
+  const double* U;
+  double* v;
+  const int* obs_a;
+  const int* obs_t;
+  int np, nc, n_k;
+  int tile_start;
+};
+void launch_kron_obs(const KronObsTask* d_tasks, int n_tasks, int total_tiles, hipStream_t s);
+void launch_fill(double* p, size_t n, double value, hipStream_t s);
+// element offset + i (i < count) of the standard-normal stream of seed
+void launch_normals(uint64_t seed, uint64_t offset, size_t count, double* out, hipStream_t s);
+// per-block sums of (diag - det) / diag over n nodes (mc_share_blocks(n) blocks)
+int mc_share_blocks(size_t n);
+void launch_mc_share(const double* diag, const double* det, size_t n, double* partial,
+                     hipStream_t s);
 
 }  // namespace rbmc

@@ -252,7 +252,7 @@ def test_error_codes():
         B.rbmc_sample(m, B.make_opts(4, precision=7), z, x)
     assert e.value.status == B.RBMC_E_ARG
     with pytest.raises(B.RbmcError) as e:
-        B.rbmc_sample(m, B.make_opts(4, precond=B.RBMC_PC_BJ_LEARNED + 1), z, x)
+        B.rbmc_sample(m, B.make_opts(4, precond=B.RBMC_PC_SPECTRAL + 1), z, x)
     assert e.value.status == B.RBMC_E_ARG
     B.rbmc_model_destroy(m)
     B.rbmc_ctx_destroy(ctx)
