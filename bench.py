@@ -1,11 +1,15 @@
 """Throughput benchmark of the RBMC hot path on one MI355X.
 
-A step is one full estimate on the 64 x 64 x 32 space-time workload
-(n = 131,072, 500 samples, 16 time slabs, 2-hop overlap, PCG to 1e-8):
-rebuild Q(theta), sample x = Q^-1 F z by block-Jacobi PCG, factor every
-overlapping subdomain, form the selected inverse entries, the correction solves and
-the trace/diagonal accumulation.  Inputs (z) are resident in HBM before the
-timed region.  Prints one JSON line.
+A step is one full estimate on the 512 x 512 x 48 space-time workload
+(n = 12,582,912; 5% observed; 3 time slabs x 8 x 8 tiles of 64 x 64 = 192
+subdomains with 2 hops of overlap; 200 samples; PCG to 1e-8; traces for
+log kappa, log tau, rho and log sigma): rebuild Q(theta), draw z on the
+device, sample x = Q^-1 F z by PCG, form the selected entries of every
+subdomain inverse, the correction solves and the diagonal/trace
+accumulation.  Prints one JSON line.  After the timed steps (each leg only
+while the wall-time budget allows): the sample count that reaches <= 1%
+plug-in error (drawn in passes), the plain FP64 block-Jacobi method on the
+same workload, the CPU oracle on a bounded sample, the batched uneven models.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -29,9 +33,15 @@ PEAK_FP32_TFLOPS = 157.3   # MI355X dense FP32 matrix
 
 
 # the HIP kernel behind each instrumented family
-KERNEL_OF = {"gemm": "k_gemm_f64", "gemm_small": "k_gemm_f64s", "gemm_mixed": "k_gemm_mx",
+KERNEL_OF = {"gemm": "k_gemm_f64<0>", "gemm_small": "k_gemm_f64s", "gemm_mixed": "k_gemm_mx",
              "inv_small": "k_inv128", "spmm": "k_space_time_op", "rstencil": "k_rstencil",
-             "panels": "k_panels", "spd_inverse": "gauss_jordan", "offdiag": "k_offdiag"}
+             "panels": "k_panels", "spd_inverse": "gauss_jordan", "offdiag": "k_offdiag",
+             "dct": "k_gemm_f64<1>", "kron_reduce": "k_kron_reduce", "spec_solve": "k_spec_solve"}
+
+
+def kernel_file_tag(kern: str) -> str:
+    """k_gemm_f64<1> -> k_gemm_f64_1 (profile file names)."""
+    return kern.replace("<", "_").replace(">", "")
 
 
 def kernel_sources_hash() -> str:
@@ -46,7 +56,7 @@ def kernel_sources_hash() -> str:
 def traffic_for(kernel: str, workload: str):
     """HBM traffic per launch from committed rocprofv3 counter runs, if they were
     taken on the current kernel sources (else None)."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel_file_tag(kernel)}_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -99,8 +109,12 @@ def write_traffic(paths, workload: str, copy_bytes: int, commands):
     written = []
     for fam, kern in KERNEL_OF.items():
         # the stencil family times Q p with the fused dot: k_space_time_op<0, true>
-        tail = r"<0, true>\(" if kern == "k_space_time_op" else r"[<(]"
-        pat = re.compile(r"(^|[\s:])" + re.escape(kern) + tail)
+        if kern == "k_space_time_op":
+            pat = re.compile(r"(^|[\s:])k_space_time_op<0, true>\(")
+        elif "<" in kern:
+            pat = re.compile(r"(^|[\s:])" + re.escape(kern) + r"\(")
+        else:
+            pat = re.compile(r"(^|[\s:])" + re.escape(kern) + r"[<(]")
         fk = [k for k in f_main if pat.search(k)]
         wk = [k for k in w_main if pat.search(k)]
         if not fk or not wk:
@@ -114,17 +128,75 @@ def write_traffic(paths, workload: str, copy_bytes: int, commands):
                "write_bytes_per_launch": wb, "scale_fetch": s_fetch, "scale_write": s_write,
                "calibration_copy_bytes": copy_bytes, "sources_hash": kernel_sources_hash(),
                "commands": commands}
-        path = os.path.join(ROOT, "profiles", f"traffic_{kern}_{workload}.json")
+        path = os.path.join(ROOT, "profiles", f"traffic_{kernel_file_tag(kern)}_{workload}.json")
         with open(path, "w") as f:
             json.dump(rec, f, indent=1)
         written.append(path)
     print(json.dumps({"written": written}))
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline_entry(wl):
+    """The CPU oracle on a bounded sample of the workload: the estimator at one
+    node of an interior subdomain (slab 1, tile (3, 3)): conjugate gradients on
+    Q_AA to the workload's tolerance (one column of Q_AA^-1) and the Monte
+    Carlo part from the same column, with the oracle's threads on all host
+    cores.  The oracle builds Q only on a window of the grid holding A and its
+    separator (the estimator at a node reads Q through Q_AA and Q_AB only).
+    Its whole-subdomain path (banded Cholesky of the 102,880-node Q_AA, then
+    one banded solve per core row) takes far longer than this bound allows;
+    the rate below is per entry, scaled to entries/s."""
+    import numpy as np
+    import oracle as O
+    p = (1 * wl.n_tiles + 3) * wl.n_tiles + 3
+    base, extra = divmod(wl.T, wl.n_tslabs)
+    sl = p // (wl.n_tiles * wl.n_tiles)
+    t0 = sl * base + min(sl, extra)
+    t1 = t0 + base + (1 if sl < extra else 0)
+    tx = p % wl.n_tiles
+    ty = (p // wl.n_tiles) % wl.n_tiles
+    side = wl.m // wl.n_tiles
+    x0, y0 = tx * side, ty * side
+    ms, mt = 2 * (wl.n_l + 1) + 2, wl.n_l + 2
+    wt0, wt1 = max(0, t0 - mt), min(wl.T, t1 + mt)
+    wx0, wx1 = max(0, x0 - ms), min(wl.m, x0 + side + ms)
+    wy0, wy1 = max(0, y0 - ms), min(wl.m, y0 + side + ms)
+    tt, yy, xx = np.meshgrid(np.arange(wt0, wt1), np.arange(wy0, wy1), np.arange(wx0, wx1),
+                             indexing="ij")
+    glob = (tt * wl.m * wl.m + yy * wl.m + xx).ravel()
+    M = O.OracleModel(wx1 - wx0, wy1 - wy0, wt1 - wt0, wl.h, *wl.theta, wl.mask()[glob])
+    inside = ((tt >= t0) & (tt < t1) & (yy >= y0) & (yy < y0 + side) & (xx >= x0) &
+              (xx < x0 + side)).ravel()
+    labels = np.where(inside, 0, 1).astype(np.int32)
+    x = np.random.default_rng(1).standard_normal((wl.n_k, M.n))
+    i = int(np.flatnonzero(inside)[inside.sum() // 2])
+    cores = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+    t = time.perf_counter()
+    M.entry(labels, 0, wl.n_l, i, x, rtol=wl.rtol)
+    dt = time.perf_counter() - t
+    return {"value": 1.0 / dt, "unit": "entries/s", "cores": cores, "kind": "oracle",
+            "cpu": cpu_model(),
+            "sample": (f"one diagonal entry of the {wl.m}x{wl.m}x{wl.T} workload (a node at the "
+                       f"centre of interior core {p}): oracle conjugate gradients on its Q_AA "
+                       f"(window model of {M.n} nodes) to {wl.rtol:g} plus the Monte Carlo part "
+                       f"for {wl.n_k} samples, {dt:.1f} s; all n = {wl.n} entries would take "
+                       f"n times as long ({wl.n * dt / 86400.0:.0f} days); sampling excluded "
+                       f"(per entry about 1e-3 of this cost)")}
+
+
 def cpu_baseline(wl, m_sample: int):
     """The CPU oracle, as it stands, on the same workload with the spatial grid
     reduced to m_sample^2 (full pipeline: exact sampling + estimator)."""
-    import numpy as np
     import oracle as O
     sub = wl.replace(m=m_sample)
     M = O.OracleModel.from_workload(sub)
@@ -136,6 +208,7 @@ def cpu_baseline(wl, m_sample: int):
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": sub.n / dt, "unit": "entries/s", "cores": cores, "kind": "oracle",
+            "cpu": cpu_model(),
             "sample": (f"full oracle pipeline (banded-Cholesky sampling + estimator) on the "
                        f"same workload with the grid reduced to {m_sample}x{m_sample} "
                        f"(n={sub.n}, {sub.n_k} samples), {dt:.1f} s")}
@@ -212,22 +285,24 @@ def batched_leg(n_models: int, tune_cache=None, per_model=True):
 
 
 def main():
+    t_start = time.perf_counter()
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="slab64")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-m", type=int, default=24)
-    ap.add_argument("--pc", default="workload",
-                    help="block-Jacobi blocks 'slabs,tiles_x,tiles_y', 'cores', or 'workload' "
-                         "(the workload's tuned shape)")
-    ap.add_argument("--no-gate", action="store_true",
-                    help="skip the run at the sample count that reaches <= 1%% error")
-    ap.add_argument("--no-variants", action="store_true",
-                    help="skip the run with block-Jacobi blocks equal to the cores")
-    ap.add_argument("--no-batched", action="store_true",
-                    help="skip the 256-model batched workload")
+    ap.add_argument("--workload", default="tile512")
+    ap.add_argument("--budget-s", type=float, default=540.0,
+                    help="wall-time budget: legs after the timed steps run only if their "
+                         "projected end stays within it")
+    ap.add_argument("--legs", default="gate,cpu,plain,batched",
+                    help="legs after the timed steps, in order (subset of "
+                         "gate,cpu,plain,batched; empty for none)")
+    ap.add_argument("--pc", default="1,32,32",
+                    help="block-Jacobi blocks 'slabs,tiles_x,tiles_y' of the plain leg, or 'cores'")
+    ap.add_argument("--plain-est-s", type=float, default=300.0,
+                    help="projected duration of the plain block-Jacobi leg (budget check)")
+    ap.add_argument("--cpu-sample-m", type=int, default=24,
+                    help="grid side of the CPU oracle leg for workloads other than tile512")
     ap.add_argument("--batched-models", type=int, default=256)
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the batched workload and print its JSON")
@@ -236,7 +311,7 @@ def main():
     ap.add_argument("--calibration-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter calibration)")
     ap.add_argument("--no-autotune", action="store_true",
-                    help="keep the default launch shapes (no rbmc_autotune before timing)")
+                    help="batched leg: keep the default launch shapes")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2309_05435_amd",
                                                           "tune_cache.txt"),
                     help="autotuner cache file (read, and appended to when a workload is new)")
@@ -254,7 +329,6 @@ def main():
               "(the library has no multi-GPU path)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     if args.calibration_copy:
@@ -271,47 +345,29 @@ def main():
 
     wl = WORKLOADS[args.workload]
     torch.cuda.set_device(0)
-    if args.pc == "workload":
-        pc = wl.pc
-    elif args.pc == "cores":
-        pc = None
-    else:
-        pc = tuple(int(v) for v in args.pc.split(","))
-    gm = B.Model(wl, pc=pc)
-    z = torch.from_numpy(wl.z()).to("cuda")
+    legs = [v for v in args.legs.split(",") if v]
+
+    def say(msg):
+        print(f"[{time.perf_counter() - t_start:7.1f} s] {msg}", file=sys.stderr, flush=True)
+
+    # ---- timed steps: spectral-preconditioned PCG sampler, Kronecker form of
+    # the subdomain inverses, FP64, z drawn on the device from the workload's seed
+    grad = 0b1111
+    seed = wl.z_seed
+    gm = B.Model(wl)
     diag = torch.empty(gm.n, dtype=torch.float64, device="cuda")
-    grad = 0b111
-    opts = B.make_opts(wl.n_k, pcg_maxit=5000, pcg_rtol=wl.rtol, grad_mask=grad)
+    opts = B.make_opts(wl.n_k, pcg_maxit=500, pcg_rtol=wl.rtol, grad_mask=grad,
+                       precond=B.RBMC_PC_SPECTRAL, method=B.RBMC_SEL_KRON)
     theta = wl.theta
 
     def step():
         # rebuilding Q(theta) invalidates every factor: each step factors again
         B.rbmc_model_set_theta(gm.m, *theta)
-        return B.rbmc_estimate(gm.m, opts, z, 0, diag, B.popcount(grad))
+        return B.rbmc_estimate(gm.m, opts, None, seed, diag, B.popcount(grad))
 
-    def timed_once(model, n_k, zz, reps=1):
-        """warm-up call, then `reps` timed calls; returns (seconds per call, report)."""
-        o = B.make_opts(n_k, pcg_maxit=5000, pcg_rtol=wl.rtol, grad_mask=grad)
-        d = torch.empty(model.n, dtype=torch.float64, device="cuda")
-        B.rbmc_model_set_theta(model.m, *theta)
-        B.rbmc_estimate(model.m, o, zz, 0, d, B.popcount(grad))
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(reps):
-            B.rbmc_model_set_theta(model.m, *theta)
-            _, _, rp = B.rbmc_estimate(model.m, o, zz, 0, d, B.popcount(grad))
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t) / reps, rp.as_dict()
-
-    tune = None
-    if not args.no_autotune:
-        # launch shapes chosen by the autotuner (end-to-end timing of this
-        # workload, or its cached choice), outside the timed steps
-        tr_ = B.rbmc_autotune(gm.ctx, [gm.m], opts, [z], args.tune_cache)
-        tune = tune_dict(tr_)
     for i in range(args.warmup):
         step()
-        print(f"warm-up step {i + 1} of {args.warmup} done", file=sys.stderr, flush=True)
+        say(f"warm-up step {i + 1} of {args.warmup} done")
     torch.cuda.synchronize()
     B.rbmc_ctx_profile(gm.ctx, True)
     torch.cuda.synchronize()
@@ -320,18 +376,19 @@ def main():
     for i in range(args.steps):
         st, tr, rep = step()
         reps.append(rep.as_dict())
-        print(f"step {i + 1} of {args.steps} done", file=sys.stderr, flush=True)
+        say(f"step {i + 1} of {args.steps} done")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     stats = {B.KF_NAMES[f]: B.rbmc_ctx_profile_read(gm.ctx, f) for f in range(B.RBMC_KF_COUNT)}
     B.rbmc_ctx_profile(gm.ctx, False)
     ms = (t1 - t0) * 1000.0 / args.steps
     value = gm.n / (ms / 1000.0)
+    flop_fams = ("gemm", "gemm_small", "gemm_mixed", "inv_small", "dct")
 
     def roofline(fam):
         s = stats[fam]
         per_launch = 1.0 / max(s["launches"], 1)
-        if fam in ("gemm", "gemm_small", "gemm_mixed", "inv_small"):
+        if fam in flop_fams:
             peak = PEAK_FP32_TFLOPS if fam == "gemm_mixed" else PEAK_FP64_TFLOPS
             achieved = s["alg_flops"] / (s["total_ms"] * 1e-3) / 1e12
             r = {"bound": "alu" if fam == "inv_small" else "mfma", "achieved": achieved,
@@ -344,20 +401,18 @@ def main():
                  "alg_bytes_per_launch": s["alg_bytes"] * per_launch}
         r["traffic"] = traffic_for(KERNEL_OF[fam], wl.name)
         r["kernel"] = KERNEL_OF[fam]
+        r["family"] = fam
         r["launches_per_step"] = s["launches"] // max(args.steps, 1)
         r["avg_launch_ms"] = s["total_ms"] * per_launch
         return r
 
     # dominant single kernel: the largest speed-of-light time per step
-    # (algorithmic flops / peak, or bytes / HBM peak).  Event times do not rank
-    # kernels here: three streams overlap, and a kernel's event time includes
-    # waiting for compute units held by the other streams (the 128-order
-    # register inversion takes 70 us alone, 4-5 times that in the overlapped
-    # step).  The inversion family is a composite of several kernels whose
-    # products are counted under the GEMM families.
+    # (algorithmic flops / peak, or bytes / HBM peak).  The inversion family is
+    # a composite of several kernels whose products are counted under the GEMM
+    # families.
     def ideal_ms(fam):
         s = stats[fam]
-        if fam in ("gemm", "gemm_small", "gemm_mixed", "inv_small"):
+        if fam in flop_fams:
             peak = PEAK_FP32_TFLOPS if fam == "gemm_mixed" else PEAK_FP64_TFLOPS
             return s["alg_flops"] / (peak * 1e12) * 1e3
         return s["alg_bytes"] / (PEAK_HBM_GBS * 1e9) * 1e3
@@ -366,10 +421,10 @@ def main():
     dom = max(singles, key=ideal_ms)
     roof = roofline(dom)
     roof["ideal_ms_per_step"] = ideal_ms(dom) / max(args.steps, 1)
-    others = {KERNEL_OF[k]: dict(roofline(k), ideal_ms_per_step=ideal_ms(k) / max(args.steps, 1))
+    others = {k: dict(roofline(k), ideal_ms_per_step=ideal_ms(k) / max(args.steps, 1))
               for k in singles if k != dom}
-
     last = reps[-1]
+    err = last["err_estimate"]
     out = {
         "metric": "diag(Q^-1) entries/sec at <=1% rel err; PCG iters; learned+mixed vs plain",
         "value": value,
@@ -385,93 +440,114 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "grid": f"{wl.m}x{wl.m}", "T": wl.T, "n": gm.n,
                    "n_obs": gm.n_obs, "n_samples": wl.n_k, "n_tslabs": wl.n_tslabs,
-                   "n_tiles": wl.n_tiles, "overlap_hops": wl.n_l, "pcg_rtol": wl.rtol,
-                   "precision": "fp64", "precond": "block-jacobi",
-                   "pc_blocks": list(pc) if pc else "cores", "traces": "logkappa,logtau,rho"},
+                   "n_tiles": wl.n_tiles, "overlap_hops": wl.n_l, "subdomains":
+                   wl.n_tslabs * wl.n_tiles * wl.n_tiles, "pcg_rtol": wl.rtol,
+                   "precision": "fp64", "precond": "spectral (Q_t x Q_s + mean(D) I)",
+                   "selected_inverse": "kronecker-woodbury",
+                   "traces": "logkappa,logtau,rho,logsigma",
+                   "z": f"device normals (Philox4x32-10), seed {seed}"},
         "pcg_iters": {"mean": last["pcg_it_mean"], "max": last["pcg_it_max"]},
-        "err_estimate": last["err_estimate"],
-        "accuracy_gate_1pct": bool(last["err_estimate"] <= 0.01),
+        "err_estimate": err,
+        "accuracy_gate_1pct": bool(err <= 0.01),
         "phase_s": {k: last[k] for k in ("t_sample", "t_factor", "t_select", "t_correct",
                                          "t_total")},
+        "device_bytes": last["peak_bytes"],
         "kernel_ms_per_step": {k: v["total_ms"] / args.steps for k, v in stats.items()},
         "roofline": roof,
         "rooflines_other_kernels": others,
         "cpu_baseline": None,
-        "tune": tune,
     }
-    if not args.no_variants:
-        # RBMC_MIXED on the same model and samples: FP32 matrix-core products in
-        # the correction solves; error stated against the FP64 run
-        d64 = diag.clone()
-        t64 = list(tr)
-        om = B.make_opts(wl.n_k, pcg_maxit=5000, pcg_rtol=wl.rtol, grad_mask=grad,
-                         precision=B.RBMC_MIXED)
-        dm = torch.empty_like(diag)
-        B.rbmc_model_set_theta(gm.m, *theta)
-        B.rbmc_estimate(gm.m, om, z, 0, dm, B.popcount(grad))
-        torch.cuda.synchronize()
-        B.rbmc_ctx_profile(gm.ctx, True)
-        ta = time.perf_counter()
-        B.rbmc_model_set_theta(gm.m, *theta)
-        _, trm, rpm = B.rbmc_estimate(gm.m, om, z, 0, dm, B.popcount(grad))
-        torch.cuda.synchronize()
-        sec = time.perf_counter() - ta
-        sm = {B.KF_NAMES[f]: B.rbmc_ctx_profile_read(gm.ctx, f) for f in range(B.RBMC_KF_COUNT)}
-        B.rbmc_ctx_profile(gm.ctx, False)
-        g = sm["gemm_mixed"]
-        out["variant_mixed"] = {
-            "value": gm.n / sec, "ms_per_step": sec * 1e3,
-            "max_rel_err_diag_vs_fp64": float(((dm - d64).abs() / d64).max()),
-            "mean_rel_err_diag_vs_fp64": float(((dm - d64).abs() / d64).mean()),
-            "rel_err_traces_vs_fp64": [abs(a - b) / abs(b) for a, b in zip(trm, t64)],
-            "pcg_iters": {"mean": rpm.pcg_it_mean, "max": rpm.pcg_it_max},
-            "phase_s": {k: getattr(rpm, k) for k in ("t_sample", "t_factor", "t_select",
-                                                     "t_correct", "t_total")},
-            "kernel_ms": {k: v["total_ms"] for k, v in sm.items()},
-            "gemm_mixed_tflops": (g["alg_flops"] / (g["total_ms"] * 1e-3) / 1e12
-                                  if g["total_ms"] > 0 else None),
-            "gemm_mixed_peak_tflops": PEAK_FP32_TFLOPS}
-    gm.close()
-    del z
-    torch.cuda.empty_cache()
-    if not args.no_gate:
-        # the plug-in error falls as 1/sqrt(n_k): the sample count for <= 1% (with margin)
-        err = last["err_estimate"]
-        if err <= 0.0095:
-            out["accuracy_gate"] = {"n_samples": wl.n_k, "value": value, "err_estimate": err}
-        else:
-            nk_g = int(math.ceil(wl.n_k * (err / 0.0095) ** 2 / 100.0)) * 100
-            mg = B.Model(wl, pc=pc)
-            zg = torch.from_numpy(wl.z(nk_g)).to("cuda")
-            sec, rp = timed_once(mg, nk_g, zg)
-            out["accuracy_gate"] = {"n_samples": nk_g, "value": gm.n / sec, "ms_per_step": sec * 1e3,
-                                    "err_estimate": rp["err_estimate"],
-                                    "met": bool(rp["err_estimate"] <= 0.01),
-                                    "pcg_iters": {"mean": rp["pcg_it_mean"], "max": rp["pcg_it_max"]}}
-            mg.close()
-            del zg
+    say(f"timed steps: {value:.0f} entries/s, {ms:.0f} ms per step, plug-in error {err:.4f}")
+
+    def budget_ok(est_s, name):
+        left = args.budget_s - (time.perf_counter() - t_start)
+        if est_s <= left:
+            return True
+        out.setdefault("skipped_legs", {})[name] = (
+            f"projected {est_s:.0f} s, {max(left, 0):.0f} s left of the {args.budget_s:.0f} s budget")
+        say(f"skipping leg {name}: projected {est_s:.0f} s, {left:.0f} s left")
+        return False
+
+    for leg in legs:
+        if leg == "gate" and wl.n_k > 0:
+            # the plug-in error falls as 1/sqrt(n_k): the sample count for <= 1%
+            # (with margin), drawn and corrected in passes of n_k samples
+            nk_g = int(math.ceil(wl.n_k * (err / 0.0095) ** 2 / wl.n_k)) * wl.n_k if err > 0.0095 \
+                else wl.n_k
+            passes = nk_g // wl.n_k
+            est = 1.2 * (last["t_factor"] + passes * (last["t_sample"] + last["t_correct"]))
+            if not budget_ok(est, "gate"):
+                continue
+            og = B.make_opts(nk_g, pcg_maxit=500, pcg_rtol=wl.rtol, grad_mask=grad,
+                             precond=B.RBMC_PC_SPECTRAL, method=B.RBMC_SEL_KRON,
+                             sample_chunk=wl.n_k)
+            dg = torch.empty_like(diag)
+            B.rbmc_model_set_theta(gm.m, *theta)
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            _, trg, rg = B.rbmc_estimate(gm.m, og, None, seed, dg, B.popcount(grad))
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - ta
+            out["accuracy_gate"] = {
+                "n_samples": nk_g, "passes": passes, "value": gm.n / sec, "ms_per_estimate":
+                sec * 1e3, "err_estimate": rg.err_estimate, "met": bool(rg.err_estimate <= 0.01),
+                "pcg_iters": {"mean": rg.pcg_it_mean, "max": rg.pcg_it_max},
+                "phase_s": {k: getattr(rg, k) for k in ("t_sample", "t_factor", "t_correct",
+                                                        "t_total")},
+                "same_samples_as_timed_steps": "the first 200 columns",
+                "overlap_hops": wl.n_l}
+            say(f"gate leg: {nk_g} samples, {sec:.1f} s, plug-in error {rg.err_estimate:.4f}")
+            del dg
+        elif leg == "cpu":
+            if not budget_ok(90.0, "cpu"):
+                continue
+            out["cpu_baseline"] = (cpu_baseline_entry(wl) if wl.name == "tile512"
+                                   else cpu_baseline(wl, args.cpu_sample_m))
+            say("cpu baseline done")
+        elif leg == "plain":
+            if not budget_ok(args.plain_est_s, "plain"):
+                continue
+            # the plain method: FP64, block-Jacobi PCG (whole time chains of
+            # spatial tiles, factored block-tridiagonally), same z, same subdomain
+            # method; its own model (the timed model's workspaces released)
+            gm.close()
             torch.cuda.empty_cache()
-    if not args.no_variants and pc is not None:
-        # the preconditioner blocks equal to the cores (16 slabs of 2 steps)
-        mv = B.Model(wl, pc=None)
-        zv = torch.from_numpy(wl.z()).to("cuda")
-        sec, rp = timed_once(mv, wl.n_k, zv)
-        out["variant_pc_cores"] = {"value": mv.n / sec, "ms_per_step": sec * 1e3,
-                                   "pcg_iters": {"mean": rp["pcg_it_mean"], "max": rp["pcg_it_max"]}}
-        mv.close()
-    if not args.no_variants:
-        try:
-            out["variant_learned"] = learned_leg(wl)
-        except B.RbmcError as e:
-            out["variant_learned"] = {"error": str(e)}
-    if not args.no_batched:
-        try:
-            out["batched"] = batched_leg(args.batched_models,
-                                         None if args.no_autotune else args.tune_cache)
-        except B.RbmcError as e:  # e.g. device memory: report, keep the main line
-            out["batched"] = {"error": str(e)}
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_m)
+            pc = None if args.pc == "cores" else tuple(int(v) for v in args.pc.split(","))
+            mp = B.Model(wl, pc=pc)
+            op = B.make_opts(wl.n_k, pcg_maxit=5000, pcg_rtol=wl.rtol, grad_mask=grad,
+                             precond=B.RBMC_PC_BJ, method=B.RBMC_SEL_KRON)
+            dp = torch.empty(mp.n, dtype=torch.float64, device="cuda")
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            _, trp, rp = B.rbmc_estimate(mp.m, op, None, seed, dp, B.popcount(grad))
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - ta
+            out["plain"] = {
+                "value": mp.n / sec, "ms_per_estimate": sec * 1e3, "precision": "fp64",
+                "precond": "block-jacobi", "pc_blocks": list(pc) if pc else "cores",
+                "pcg_iters": {"mean": rp.pcg_it_mean, "max": rp.pcg_it_max},
+                "phase_s": {k: getattr(rp, k) for k in ("t_sample", "t_factor", "t_correct",
+                                                        "t_total")},
+                "err_estimate": rp.err_estimate,
+                "max_rel_diff_diag_vs_timed": float(((dp - diag).abs() / diag).max()),
+                "speedup_of_timed_steps": sec / (ms / 1000.0)}
+            say(f"plain leg: {sec:.1f} s, {rp.pcg_it_max} PCG iterations")
+            mp.close()
+            del dp
+            torch.cuda.empty_cache()
+        elif leg == "batched":
+            if not budget_ok(60.0, "batched"):
+                continue
+            if gm.m:
+                gm.close()
+            torch.cuda.empty_cache()
+            try:
+                out["batched"] = batched_leg(args.batched_models,
+                                             None if args.no_autotune else args.tune_cache)
+            except B.RbmcError as e:  # e.g. device memory: report, keep the main line
+                out["batched"] = {"error": str(e)}
+            say("batched leg done")
+    out["wall_s"] = time.perf_counter() - t_start
     print(json.dumps(out), flush=True)
 
 

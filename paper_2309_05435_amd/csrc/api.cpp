@@ -850,7 +850,10 @@ rbmc_status run(rbmc_ctx* cx, const Program& pg, hipStream_t s, Arena& a) {
   for (const Op& o : pg.ops) {
     const int pid = (o.family >= 0) ? cx->begin(o.family, o.alg_flops, o.alg_bytes, s) : -1;
     switch (o.kind) {
-      case 0: launch_gemm(a.at<GemmTask>(o.off), o.n, o.tiles, s, o.kblk); break;
+      case 0:
+        launch_gemm(a.at<GemmTask>(o.off), o.n, o.tiles, s, o.kblk,
+                    o.family == RBMC_KF_DCT ? 1 : 0);
+        break;
       case 1: launch_rstencil(a.at<StencilTask>(o.off), o.n, o.tiles, o.max_np, o.kblk, s); break;
       case 2: launch_inv128(a.at<SmallInvTask>(o.off), o.n, s); break;
       case 3: launch_panels(a.at<PanelTask>(o.off), o.n, o.tiles, s); break;
@@ -3129,11 +3132,13 @@ rbmc_status estimate_set_kron(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms,
     res_max = std::max(res_max, r.max_rel_residual);
     return RBMC_OK;
   };
-  // one pass: samples first, corrected batch by batch with the selected entries
+  // the first pass is drawn before the batches are sized (its workspace must
+  // fit beside them); with one pass its samples are corrected batch by batch
+  // together with the selected entries
   const double* x1 = x_given;
   HostCols h1;
-  if (npass == 1 && sampler) {
-    st = draw(0, nk_total, &x1, &h1);
+  if (npass >= 1 && sampler) {
+    st = draw(0, std::min(chunk, nk_total), &x1, &h1);
     if (st != RBMC_OK) return st;
   } else if (x_given) {
     h1 = *h_given;
@@ -3144,6 +3149,9 @@ rbmc_status estimate_set_kron(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms,
   // several passes: Y of every subdomain and the deterministic diagonals in the bank
   std::vector<double*> ybank(refs.size(), nullptr), ddet(ms.size(), nullptr);
   if (npass > 1) {
+    cx->kws.release();  // the bank first; batches take what is left
+    cx->kws_base = nullptr;
+    cx->kws_cap = 0;
     size_t need = 0;
     for (const auto& r : refs) {
       const size_t nc = ms[r.first]->ksub[r.second].nc;
@@ -3249,10 +3257,12 @@ rbmc_status estimate_set_kron(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms,
                             hipMemcpyDeviceToDevice, s));
     for (int c = 0; c < npass; ++c) {
       const int k0 = c * chunk, kn = std::min(chunk, nk_total - k0);
-      const double* xc = nullptr;
-      HostCols hc;
-      st = draw(k0, kn, &xc, &hc);
-      if (st != RBMC_OK) return st;
+      const double* xc = x1;
+      HostCols hc = h1;
+      if (c > 0) {
+        st = draw(k0, kn, &xc, &hc);
+        if (st != RBMC_OK) return st;
+      }
       const double tb = now_s();
       for (size_t i0 = 0; i0 < refs.size();) {
         const auto nb = next_batch(i0, true, kn);

@@ -116,6 +116,9 @@ int gemm_task_tiles(int M, int N, int lower, int ts) {
 // the next A/B tiles into registers while the matrix cores consume the
 // current LDS tiles; the LDS tiles are double-buffered, so one barrier per
 // K step separates the stores of step k + 1 from the reads of step k.
+// TAG only names the instantiation (1: the spectral transforms), so kernel
+// traces and counters separate the two uses; the code is the same.
+template <int TAG>
 __global__ __launch_bounds__(256, 2) void k_gemm_f64(const GemmTask* __restrict__ tasks,
                                                      int n_tasks, int total_tiles, int per_xcd) {
   __shared__ double As[2][GBM * GLDS];
@@ -573,15 +576,17 @@ __global__ __launch_bounds__(256) void k_gemm_f64s(const GemmTask* __restrict__ 
 }
 
 void launch_gemm(const GemmTask* d_tasks, int n_tasks, int total_tiles, hipStream_t s,
-                 int kind) {
+                 int kind, int tag) {
   if (total_tiles <= 0) return;
   const int per_xcd = (total_tiles + 7) / 8;
   if (kind == kGemmMixed)
     k_gemm_mx<<<per_xcd * 8, 512, 0, s>>>(d_tasks, n_tasks, total_tiles, per_xcd);
   else if (kind == kGemmSmall)
     k_gemm_f64s<<<per_xcd * 8, 256, 0, s>>>(d_tasks, n_tasks, total_tiles, per_xcd);
+  else if (tag == 1)
+    k_gemm_f64<1><<<per_xcd * 8, 256, 0, s>>>(d_tasks, n_tasks, total_tiles, per_xcd);
   else
-    k_gemm_f64<<<per_xcd * 8, 256, 0, s>>>(d_tasks, n_tasks, total_tiles, per_xcd);
+    k_gemm_f64<0><<<per_xcd * 8, 256, 0, s>>>(d_tasks, n_tasks, total_tiles, per_xcd);
 }
 
 // ---------------------------------------------------------------------------

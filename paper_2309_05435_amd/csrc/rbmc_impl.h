@@ -189,8 +189,10 @@ int gemm_task_tiles(int M, int N, int lower, int ts);
 // tiles); FP32 matrix-core products with FP64 accumulation across K chunks
 // (128 x 128 tiles)
 enum { kGemmF64 = 0, kGemmSmall = 1, kGemmMixed = 2 };
+// tag 1: the spectral transforms (a separately named instantiation of the
+// same FP64 kernel)
 void launch_gemm(const GemmTask* d_tasks, int n_tasks, int total_tiles, hipStream_t s,
-                 int kind);
+                 int kind, int tag = 0);
 
 // Gauss-Jordan sweep inversion of SPD matrices (in place).
 struct InvTask {
