@@ -107,6 +107,62 @@ def estimator_entries(wl, mask, p: int, nodes, x: np.ndarray):
     return out
 
 
+# unit roundoff of FP64 and the constant of the per-entry bounds below
+U64 = 2.0 ** -53
+C_BOUND = 64.0
+
+
+def estimator_entries_bounded(wl, mask, p: int, nodes, x: np.ndarray):
+    """As estimator_entries, with a bound on the rounding error that any
+    backward-stable FP64 evaluation of each value may carry, derived from the
+    conditioning of Q_AA along e_i: a solve with (Q_AA + dQ) y~ = e_i,
+    ||dQ|| <= c u ||Q_AA||, changes y_i by about y^T dQ y, so
+      |d det| <= c u ||Q_AA|| ||y||^2,
+    and mu_k = y^T r_k (r_k = Q_AB x_B) by about c u ||Q_AA|| ||y|| ||m_k||
+    with m_k = Q_AA^-1 r_k, so the Monte Carlo term (1/n_k) sum mu_k^2 moves by
+    at most (1/n_k) sum 2 |mu_k| c u ||Q_AA|| ||y|| ||m_k||.  ||Q_AA|| is taken
+    as the largest absolute row sum (>= the 2-norm of a symmetric matrix) and
+    c = 64.  Returns [(det, full, bound_det, bound_full)]; the parity bar for
+    two such evaluations is the sum of their bounds, 2 x bound."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    w = core_window(wl, mask, p)
+    (t0, t1), (x0, x1), (y0, y1) = core_box(wl, p)
+    labels = np.ones(w.M.n, np.int32)
+    tt, yy, xx = np.meshgrid(np.arange(w.t0, w.t1), np.arange(w.y0, w.y1),
+                             np.arange(w.x0, w.x1), indexing="ij")
+    inside = ((tt >= t0) & (tt < t1) & (yy >= y0) & (yy < y1) & (xx >= x0) & (xx < x1)).ravel()
+    labels[inside] = 0
+    state = w.M.subdomain_state(labels, 0, wl.n_l)
+    A = np.flatnonzero((state == 1) | (state == 2))
+    Bn = np.flatnonzero(state == 3)
+    c = w.M.csr(O.Q)
+    Q = sp.csr_matrix((c.v, c.ci, c.rp), shape=(c.nr, c.nc))
+    QAA = Q[A][:, A]
+    norm = float(abs(QAA).sum(axis=1).max())
+    lu = spla.splu(sp.csc_matrix(QAA))
+    QAB = Q[A][:, Bn]
+    xB = x[:, w.glob[Bn]]                      # (n_k, |B|)
+    R = np.asarray(QAB @ xB.T)                 # (|A|, n_k): r_k
+    Mk = lu.solve(R)                           # m_k = Q_AA^-1 r_k
+    mnorm = np.linalg.norm(Mk, axis=0)
+    pos = {g: k for k, g in enumerate(A)}
+    out = []
+    for i in nodes:
+        e = np.zeros(len(A))
+        e[pos[w.local(i)]] = 1.0
+        y = lu.solve(e)
+        det = y[pos[w.local(i)]]
+        mu = y @ R                             # (n_k,)
+        ynorm = float(np.linalg.norm(y))
+        bdet = C_BOUND * U64 * norm * ynorm ** 2
+        bmc = (np.mean(2.0 * np.abs(mu) * C_BOUND * U64 * norm * ynorm * mnorm)
+               if len(mu) else 0.0)
+        full = det + (np.mean(mu ** 2) if len(mu) else 0.0)
+        out.append((float(det), float(full), float(bdet), float(bdet + bmc)))
+    return out
+
+
 def estimator_entry(wl, mask, p: int, i: int, x: np.ndarray):
     return estimator_entries(wl, mask, p, [i], x)[0]
 
