@@ -190,6 +190,17 @@ enum {
 };
 rbmc_status rbmc_apply_op(rbmc_model* m, int op, const double* x, double* y, int32_t n_rhs);
 
+/* rbmc_apply_op for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops): the same operators and results, with no
+ * hipMalloc, hipFree or other allocation.  Its per-column tables and the
+ * model view go to a fixed 2 MiB device block of the library (one per device,
+ * held until the process ends); the work is enqueued on the context's stream
+ * and NOT synchronized (the caller synchronizes before reading y).  n_rhs <=
+ * 65535 (RBMC_E_ARG beyond).  Calls that overlap on one device share the
+ * block and race; calls ordered on one stream do not. */
+rbmc_status rbmc_apply_op_noalloc(rbmc_model* m, int op, const double* x, double* y,
+                                  int32_t n_rhs);
+
 /* Samples x_k = Q^-1 F z_k by block-Jacobi preconditioned conjugate
  * gradients (Sec. 3.3; perturbation form, Sec. 2.4), x0 = 0, stopping per
  * sample at ||b - Q x|| <= pcg_rtol ||b||.

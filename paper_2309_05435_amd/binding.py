@@ -28,7 +28,7 @@ EXPORTS = ["rbmc_ctx_create", "rbmc_ctx_destroy", "rbmc_model_create", "rbmc_mod
            "rbmc_ctx_profile_read", "rbmc_precond_train", "rbmc_precond_apply",
            "rbmc_precond_get_weights", "rbmc_precond_set_weights", "rbmc_precond_info",
            "rbmc_ctx_get_tune", "rbmc_ctx_set_tune", "rbmc_autotune", "rbmc_last_error",
-           "rbmc_normals"]
+           "rbmc_normals", "rbmc_apply_op_noalloc"]
 RBMC_PC_NWEIGHTS = 15120
 # (cin, cout) of the learned correction's four convolutions, in weight order
 PC_LAYERS = [(2, 16), (16, 16), (16, 16), (16, 1)]
@@ -114,6 +114,7 @@ def lib():
         L.rbmc_model_destroy.restype = None
         L.rbmc_model_set_theta.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_double]
         L.rbmc_apply_op.argtypes = [vp, C.c_int, vp, vp, C.c_int32]
+        L.rbmc_apply_op_noalloc.argtypes = [vp, C.c_int, vp, vp, C.c_int32]
         L.rbmc_sample.argtypes = [vp, C.POINTER(rbmc_est_opts), vp, vp, C.POINTER(rbmc_report)]
         L.rbmc_estimate_from_samples.argtypes = [vp, C.POINTER(rbmc_est_opts), vp, vp,
                                                  C.POINTER(C.c_double), C.POINTER(rbmc_report)]
@@ -191,6 +192,11 @@ def rbmc_model_set_theta(m, log_kappa, log_tau, rho, log_sigma):
 
 def rbmc_apply_op(m, op, x, y, n_rhs):
     return check(lib().rbmc_apply_op(m, op, _ptr(x), _ptr(y), n_rhs))
+
+
+def rbmc_apply_op_noalloc(m, op, x, y, n_rhs):
+    """Enqueued on the context stream, not synchronized."""
+    return check(lib().rbmc_apply_op_noalloc(m, op, _ptr(x), _ptr(y), n_rhs))
 
 
 def rbmc_sample(m, opts, z, x):

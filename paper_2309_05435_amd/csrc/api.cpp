@@ -3442,6 +3442,83 @@ rbmc_status estimate_full(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms,
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// Allocation-free operator application (rbmc_apply_op_noalloc).  Its column
+// tables and the model view live in `scratch`, a file-scope device array of
+// kScratchBytes per device that the library never allocates or frees.  Host
+// code never uses the array's name as an address: rbmc_ctx_create resolves
+// the address on each device once (hipGetSymbolAddress, with that device
+// current) and the entry point passes that address to its kernels.  Every
+// call on a device shares the device's array: calls that overlap on one
+// device race.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t kScratchBytes = (size_t)2 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;  // per device; nullptr until resolved
+
+// column c of one model: n entries at c n, operator input at c (n + n_obs);
+// block 0 also copies the model view (words 8-byte units)
+__global__ void k_fill_cols(int64_t* __restrict__ off, int64_t* __restrict__ in_off,
+                            int* __restrict__ len, int* __restrict__ model, int ncols, int n,
+                            int n_obs, const uint64_t* __restrict__ view_src,
+                            uint64_t* __restrict__ view_dst, int words) {
+  if (blockIdx.x == 0 && (int)threadIdx.x < words) view_dst[threadIdx.x] = view_src[threadIdx.x];
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncols) return;
+  off[c] = (int64_t)c * n;
+  in_off[c] = (int64_t)c * (n + n_obs);
+  len[c] = n;
+  model[c] = 0;
+}
+
+// Resolve (once per device) the device address of `scratch`; `device` must
+// be current.  Empty launches on stream s then make the runtime load the
+// device code the allocation-free entry point runs (this file's and the
+// operator kernels'; each source file is its own code object, loaded on the
+// first launch of one of its kernels) now, not inside a later call.
+rbmc_status scratch_resolve(int device, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= device) g_scratch_ptr.resize(device + 1, nullptr);
+  if (g_scratch_ptr[device]) return RBMC_OK;
+  void* ptr = nullptr;
+  HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  k_fill_cols<<<1, 64, 0, s>>>(nullptr, nullptr, nullptr, nullptr, 0, 0, 0, nullptr, nullptr, 0);
+  load_stencil_module(s);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  g_scratch_ptr[device] = ptr;
+  return RBMC_OK;
+}
+
+void* scratch_of(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return device < (int)g_scratch_ptr.size() ? g_scratch_ptr[device] : nullptr;
+}
+
+// Layout of the column tables in the scratch block: the model view, then
+// off, in_off (int64) and len, model (int32) of ncols columns.
+struct ScratchCols {
+  DevModel* dm;
+  int64_t *off, *in_off;
+  int *len, *model;
+};
+constexpr size_t kScratchView = 512;  // bytes reserved for the model view
+size_t scratch_cols_bytes(int ncols) { return kScratchView + (size_t)ncols * 24; }
+ScratchCols scratch_layout(void* base, int ncols) {
+  char* p = (char*)base;
+  ScratchCols c;
+  c.dm = (DevModel*)p;
+  c.off = (int64_t*)(p + kScratchView);
+  c.in_off = c.off + ncols;
+  c.len = (int*)(c.in_off + ncols);
+  c.model = c.len + ncols;
+  return c;
+}
+static_assert(sizeof(DevModel) <= kScratchView, "model view exceeds its scratch slot");
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // ABI
 // ---------------------------------------------------------------------------
 namespace {
@@ -3532,6 +3609,10 @@ rbmc_status rbmc_ctx_create(int device, void* hip_stream, rbmc_ctx** out) {
   HIPCHK(hipGetDeviceCount(&ndev));
   if (device < 0 || device >= ndev) return fail(RBMC_E_ARG, "no such device");
   HIPCHK(hipSetDevice(device));
+  {  // the allocation-free entry point's scratch block on this device
+    rbmc_status st = scratch_resolve(device, (hipStream_t)hip_stream);
+    if (st != RBMC_OK) return st;
+  }
   rbmc_ctx* c = new rbmc_ctx;
   c->device = device;
   c->stream = (hipStream_t)hip_stream;
@@ -3710,6 +3791,39 @@ rbmc_status rbmc_apply_op(rbmc_model* m, int op, const double* x, double* y, int
   launch_apply_op(colset(m->ctx, h), op, x, y, m->ctx->stream);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(m->ctx->stream));
+  return RBMC_OK;
+}
+
+rbmc_status rbmc_apply_op_noalloc(rbmc_model* m, int op, const double* x, double* y,
+                                  int32_t n_rhs) {
+  if (!m || !x || !y) return fail(RBMC_E_ARG, "NULL argument");
+  if (op < RBMC_OP_Q || op > RBMC_OP_F) return fail(RBMC_E_ARG, "unknown operator");
+  if (n_rhs < 0) return fail(RBMC_E_ARG, "n_rhs must be >= 0");
+  if (n_rhs == 0) return RBMC_OK;
+  if (n_rhs > (int32_t)kMaxCols || scratch_cols_bytes(n_rhs) > kScratchBytes)
+    return fail(RBMC_E_ARG, "n_rhs exceeds 65535 columns (the scratch block's limit)");
+  const int dev = m->ctx->device;
+  HIPCHK(hipSetDevice(dev));
+  void* base = scratch_of(dev);
+  if (!base) return fail(RBMC_E_DEVICE, "scratch block not resolved on this device");
+  hipStream_t s = m->ctx->stream;
+  const ScratchCols t = scratch_layout(base, n_rhs);
+  static_assert(sizeof(DevModel) % 8 == 0 && sizeof(DevModel) / 8 <= 256, "model view words");
+  k_fill_cols<<<(n_rhs + 255) / 256, 256, 0, s>>>(
+      t.off, t.in_off, t.len, t.model, n_rhs, m->plan.n, m->n_obs, (const uint64_t*)m->d_dm,
+      (uint64_t*)t.dm, (int)(sizeof(DevModel) / 8));
+  ColSet cs{};
+  cs.ncols = n_rhs;
+  cs.max_len = m->plan.n;
+  cs.max_tiles = stencil_tiles(m->plan.mx, m->plan.my);
+  cs.max_ns = m->plan.ns;
+  cs.off = t.off;
+  cs.in_off = t.in_off;
+  cs.len = t.len;
+  cs.model = t.model;
+  cs.dms = t.dm;
+  launch_apply_op(cs, op, x, y, s);
+  HIPCHK(hipGetLastError());
   return RBMC_OK;
 }
 

@@ -138,6 +138,8 @@ struct ColSet {
 };
 
 int stencil_tiles(int mx, int my);
+// load the operator kernels' code object now (an empty launch on s)
+void load_stencil_module(hipStream_t s);
 // y = Op x per column (op = RBMC_OP_*), x at in_off, y at off
 void launch_apply_op(const ColSet& cs, int op, const double* x, double* y, hipStream_t s);
 // q = Q p per column and partial sums of p.q: partial[c * max_tiles + tile]
