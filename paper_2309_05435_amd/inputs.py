@@ -112,6 +112,11 @@ WORKLOADS = {
     "tile256": _wl(4, name="tile256", m=256, T=64, range_=0.1, rho=0.9, tau=1.0, sigma=0.5,
                    obs_frac=0.1, n_tslabs=8, n_tiles=8, n_l=1, n_k=100, rtol=1e-8,
                    pc=(1, 16, 16)),
+    # a mid-size check case, small enough for the whole oracle: 8 time slabs
+    # of 2 steps grown by two hops, i.e. chains of 4-6 blocks of 2304 nodes
+    "mid48": Workload(name="mid48", m=48, T=16, range_=0.3, rho=0.9, tau=1.0, sigma=0.5,
+                      obs_frac=0.2, n_tslabs=8, n_tiles=1, n_l=2, n_k=16, rtol=1e-12,
+                      mask_seed=48001, z_seed=48002),
     "tile512": _wl(5, name="tile512", m=512, T=48, range_=0.05, rho=0.98, tau=1.0, sigma=0.5,
                    obs_frac=0.05, n_tslabs=3, n_tiles=8, n_l=2, n_k=200, rtol=1e-8),
 }

@@ -16,11 +16,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 import oracle as O  # noqa: E402
-from paper_2309_05435_amd.inputs import Workload, normals  # noqa: E402
+from paper_2309_05435_amd.inputs import WORKLOADS, normals  # noqa: E402
 
-WL = Workload(name="mid48", m=48, T=16, range_=0.3, rho=0.9, tau=1.0, sigma=0.5,
-              obs_frac=0.2, n_tslabs=8, n_tiles=1, n_l=2, n_k=16, rtol=1e-12, mask_seed=48001,
-              z_seed=48002)
+WL = WORKLOADS["mid48"]
 X_SEED = 61
 
 

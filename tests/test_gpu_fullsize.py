@@ -1,12 +1,14 @@
-"""Parity at the benchmark's full size (64 x 64 grid, T = 32, n = 131,072,
-16 time slabs, 2-hop overlap, 500 samples) in the launch configuration that
-bench.py times.  The oracle cannot run the whole estimator at this size, so
-it checks sampled outputs one by one (conjugate gradients on Q_AA for single
-entries) and properties that hold at any size."""
+"""Parity on the 64 x 64 x 32 workload (n = 131,072, 16 time slabs, 2-hop
+overlap, 500 samples), for both subdomain methods (block-tridiagonal factor
+and selected inverse; Kronecker-Woodbury).  The whole oracle estimator does
+not run at this size, so it checks sampled outputs one by one (conjugate
+gradients on Q_AA for single entries) and properties that hold at any size.
+The bar is 8 u max_p cond(Q_AA) (tests/cond_bars.py), about 1.1e-9."""
 import numpy as np
 import pytest
 
 import oracle as O
+from cond_bars import parity_bar
 from paper_2309_05435_amd.inputs import WORKLOADS, normals
 
 pytestmark = pytest.mark.gpu
@@ -29,22 +31,33 @@ def setup():
     gm.close()
 
 
-def test_estimator_sampled_entries_full_size(setup):
+@pytest.fixture(scope="module")
+def oracle_entries(setup):
     wl, gm, M, lab = setup
     x = normals((wl.n_k, gm.n), 77)
-    print("fullsize: estimate_from_samples", flush=True)
-    diag, tr, st, rep = gm.estimate_from_samples(torch.from_numpy(x).cuda(), grad_mask=0b1111)
-    d = diag.cpu().numpy()
     # entries: first/last time step, slab edges, interior; corner and centre nodes
     ns = wl.m * wl.m
     picks = [(0, 0), (1, 2080), (7, 63), (8, 4095), (15, 1000), (16, 2047), (31, 4032),
              (23, 2)]
+    ref = {}
     for t, s in picks:
         i = t * ns + s
-        p = int(lab[i])
-        det, full = M.entry(lab, p, wl.n_l, i, x, rtol=1e-13)
-        print(f"fullsize: node t={t} s={s} gpu={d[i]:.15e} oracle={full:.15e}", flush=True)
-        assert abs(d[i] - full) <= 1e-9 * full
+        ref[i] = M.entry(lab, int(lab[i]), wl.n_l, i, x, rtol=1e-13)
+    return x, ref
+
+
+@pytest.mark.parametrize("method", [B.RBMC_SEL_BLOCKTRI, B.RBMC_SEL_KRON])
+def test_estimator_sampled_entries_full_size(setup, oracle_entries, method):
+    wl, gm, M, lab = setup
+    x, ref = oracle_entries
+    bar = parity_bar(wl)
+    print(f"fullsize: estimate_from_samples method {method}", flush=True)
+    diag, tr, st, rep = gm.estimate_from_samples(torch.from_numpy(x).cuda(), grad_mask=0b1111,
+                                                 method=method)
+    d = diag.cpu().numpy()
+    for i, (det, full) in ref.items():
+        print(f"fullsize: node {i} gpu={d[i]:.15e} oracle={full:.15e}", flush=True)
+        assert abs(d[i] - full) <= bar * full
     # the log tau / log sigma identities hold exactly at any size
     D = wl.mask() / wl.sigma ** 2
     s2 = np.sum(D * d)

@@ -1,14 +1,16 @@
 """Parity at the 256 x 256 x 64 workload (n = 4,194,304; 8 time slabs x 8 x 8
 spatial tiles = 512 subdomains with one hop of overlap; dense blocks of
-1153-1284 nodes; block-Jacobi blocks = the cores).  The whole oracle model
-is too large to build at this size, so sampled outputs are checked against
-the oracle on windows of the grid that contain each subdomain (exact, see
-tests/window.py), and the trace identities are checked at full size."""
+1153-1284 nodes; block-Jacobi blocks = whole 64-step chains of 16 x 16
+spatial tiles, the workload's shape).  The whole oracle model is too large to
+build at this size, so sampled outputs are checked against the oracle on
+windows of the grid that contain each subdomain (exact, see tests/window.py),
+and the trace identities are checked at full size."""
 import numpy as np
 import pytest
 
 import oracle as O
 from paper_2309_05435_amd.inputs import WORKLOADS, normals
+from cond_bars import parity_bar
 from window import estimator_entries, q_row
 
 pytestmark = pytest.mark.gpu
@@ -20,12 +22,9 @@ if not torch.cuda.is_available():
 from paper_2309_05435_amd import binding as B  # noqa: E402
 
 WL = WORKLOADS["tile256"]
-# kappa h = 0.11 and rho = 0.9 give cond(Q_AA) of about 2e7 (spatial factor
-# ((8 + (kappa h)^2) / (kappa h)^2)^2 ~ 4e5, temporal ((1 + rho) / (1 - rho))^2
-# = 361, reduced by the observation term), so two exact FP64 methods - the
-# explicit block inverses here, a sparse LU in the oracle - agree to about
-# cond * 2^-53 ~ 2e-9 relative; the bar is 1e-8.
-TOL = 1e-8
+# 8 u max_p cond(Q_AA), cond bounded through the Kronecker factors of each
+# Q_AA: 1.37e7 at the corner tiles of the first and last slabs, bar 1.2e-8
+TOL = parity_bar(WL)
 
 
 def say(*a):

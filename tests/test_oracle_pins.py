@@ -354,3 +354,64 @@ def test_plugin_error_estimate_tracks_true_error():
     r = M.rbmc(lab, wl.n_tslabs, wl.n_l, x, 0b111)
     true_err = np.mean(np.abs(r["diag"] - S) / S)
     assert 0.6 < r["err_est"] / true_err < 1.6
+
+
+# --------------------------------------------------------------------------
+# O8: the helpers the full-size checks use (operator application, the
+# perturbation right-hand side, conjugate gradients, the one-entry estimator),
+# each against an operator or an estimator pinned above
+# --------------------------------------------------------------------------
+
+OPS = (O.Q, O.DQ_LOGKAPPA, O.DQ_LOGTAU, O.DQ_RHO, O.DQ_LOGSIGMA, O.F)
+
+
+def test_apply_and_rhs_match_dense_products():
+    """y = Op x for every operator and b = F z equal dense products with the
+    matrices pinned above (Kronecker form, central differences, F F^T = Q)."""
+    M, mask = tiny_model()
+    Qt, Qs = M.csr(O.QT).dense(), M.csr(O.QS).dense()
+    sigma2 = math.exp(-0.8)
+    closed = {O.Q: np.kron(Qt, Qs) + np.diag(mask / sigma2), O.DQ_LOGTAU: np.kron(Qt, Qs),
+              O.DQ_LOGSIGMA: -2.0 * np.diag(mask / sigma2)}
+    for which in OPS:
+        D = closed.get(which, M.csr(which).dense())
+        x = normals((3, D.shape[1]), 21 + which)
+        np.testing.assert_allclose(M.apply(which, x), x @ D.T, rtol=1e-12,
+                                   atol=1e-13 * np.abs(D).max() * np.abs(x).max() * D.shape[1])
+    z = normals((4, M.n + M.n_obs), 22)
+    F = M.csr(O.F).dense()
+    np.testing.assert_allclose(M.rhs(z), z @ F.T, rtol=1e-12, atol=1e-12 * np.abs(F).max())
+
+
+def test_cg_solves_full_and_restricted_systems():
+    M, _ = tiny_model()
+    Q = M.csr(O.Q).dense()
+    b = normals((1, M.n), 23)[0]
+    x, it = M.cg(b, rtol=1e-14)
+    assert it > 0
+    np.testing.assert_allclose(x, np.linalg.solve(Q, b), rtol=1e-10, atol=1e-12)
+    sel = np.zeros(M.n, np.uint8)
+    sel[M.n // 3: 2 * M.n // 3] = 1
+    xs, _ = M.cg(b, sel=sel, rtol=1e-14)
+    s = sel.astype(bool)
+    np.testing.assert_allclose(xs[s], np.linalg.solve(Q[np.ix_(s, s)], b[s]), rtol=1e-10,
+                               atol=1e-12)
+    assert np.all(xs[~s] == 0.0)
+
+
+@pytest.mark.parametrize("P,tx,ty,n_l", [(3, 2, 1, 1), (2, 2, 2, 2)])
+def test_entry_matches_whole_estimator(P, tx, ty, n_l):
+    """The one-entry estimator (CG on Q_AA) equals the whole estimator,
+    itself pinned against dense brute force, at nodes of every core."""
+    M, _ = tiny_model(mx=7, my=6, T=8)
+    lab = O.grid_cores(7, 6, 8, P, tx, ty)
+    n_parts = P * tx * ty
+    x = normals((9, M.n), 24)
+    r = M.rbmc(lab, n_parts, n_l, x, 0b1)
+    rng = np.random.default_rng(25)
+    for p in range(n_parts):
+        nodes = np.flatnonzero(lab == p)
+        for i in rng.choice(nodes, size=min(3, len(nodes)), replace=False):
+            det, full = M.entry(lab, p, n_l, int(i), x, rtol=1e-14)
+            np.testing.assert_allclose(det, r["diag_det"][i], rtol=1e-10)
+            np.testing.assert_allclose(full, r["diag"][i], rtol=1e-10)
