@@ -201,13 +201,23 @@ rbmc_status rbmc_apply_op(rbmc_model* m, int op, const double* x, double* y, int
 rbmc_status rbmc_apply_op_noalloc(rbmc_model* m, int op, const double* x, double* y,
                                   int32_t n_rhs);
 
-/* Samples x_k = Q^-1 F z_k by block-Jacobi preconditioned conjugate
- * gradients (Sec. 3.3; perturbation form, Sec. 2.4), x0 = 0, stopping per
- * sample at ||b - Q x|| <= pcg_rtol ||b||.
+/* Samples x_k = Q^-1 F z_k by preconditioned conjugate gradients (Sec. 3.3;
+ * perturbation form, Sec. 2.4) with the preconditioner opts->precond, x0 = 0,
+ * stopping per sample at ||b - Q x|| <= pcg_rtol ||b||.
  * z: device, (n + n_obs) x n_samples; x: device, n x n_samples.
  * Returns RBMC_W_NOT_CONVERGED if some sample hit pcg_maxit. */
 rbmc_status rbmc_sample(rbmc_model* m, const rbmc_est_opts* opts, const double* z, double* x,
                         rbmc_report* rep);
+
+/* Solves Q x_k = b_k (eq:lgm:2's Q) for opts->n_samples right-hand sides by
+ * the sampler's preconditioned conjugate gradients (Sec. 3.3): x0 = 0,
+ * preconditioner opts->precond, stop per column at ||b - Q x|| <= pcg_rtol
+ * ||b||.  b, x: device, n x n_samples (column k at k n), distinct buffers;
+ * b is not modified.  With b = e_i, x_i = (Q^-1)_ii exactly up to the
+ * tolerance: the reference for the estimator's true error.
+ * Returns RBMC_W_NOT_CONVERGED if some column hit pcg_maxit. */
+rbmc_status rbmc_solve(rbmc_model* m, const rbmc_est_opts* opts, const double* b, double* x,
+                       rbmc_report* rep);
 
 /* The estimator from given samples (Alg. 4 for the diagonal; Alg. 3 rows
  * with eq:hyperpar:4 for the traces): for each core p,

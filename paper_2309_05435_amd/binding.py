@@ -28,7 +28,7 @@ EXPORTS = ["rbmc_ctx_create", "rbmc_ctx_destroy", "rbmc_model_create", "rbmc_mod
            "rbmc_ctx_profile_read", "rbmc_precond_train", "rbmc_precond_apply",
            "rbmc_precond_get_weights", "rbmc_precond_set_weights", "rbmc_precond_info",
            "rbmc_ctx_get_tune", "rbmc_ctx_set_tune", "rbmc_autotune", "rbmc_last_error",
-           "rbmc_normals", "rbmc_apply_op_noalloc"]
+           "rbmc_normals", "rbmc_apply_op_noalloc", "rbmc_solve"]
 RBMC_PC_NWEIGHTS = 15120
 # (cin, cout) of the learned correction's four convolutions, in weight order
 PC_LAYERS = [(2, 16), (16, 16), (16, 16), (16, 1)]
@@ -116,6 +116,7 @@ def lib():
         L.rbmc_apply_op.argtypes = [vp, C.c_int, vp, vp, C.c_int32]
         L.rbmc_apply_op_noalloc.argtypes = [vp, C.c_int, vp, vp, C.c_int32]
         L.rbmc_sample.argtypes = [vp, C.POINTER(rbmc_est_opts), vp, vp, C.POINTER(rbmc_report)]
+        L.rbmc_solve.argtypes = [vp, C.POINTER(rbmc_est_opts), vp, vp, C.POINTER(rbmc_report)]
         L.rbmc_estimate_from_samples.argtypes = [vp, C.POINTER(rbmc_est_opts), vp, vp,
                                                  C.POINTER(C.c_double), C.POINTER(rbmc_report)]
         L.rbmc_estimate.argtypes = [vp, C.POINTER(rbmc_est_opts), vp, C.c_uint64, vp,
@@ -197,6 +198,12 @@ def rbmc_apply_op(m, op, x, y, n_rhs):
 def rbmc_apply_op_noalloc(m, op, x, y, n_rhs):
     """Enqueued on the context stream, not synchronized."""
     return check(lib().rbmc_apply_op_noalloc(m, op, _ptr(x), _ptr(y), n_rhs))
+
+
+def rbmc_solve(m, opts, b, x):
+    rep = rbmc_report()
+    st = check(lib().rbmc_solve(m, C.byref(opts), _ptr(b), _ptr(x), C.byref(rep)))
+    return st, rep
 
 
 def rbmc_sample(m, opts, z, x):
@@ -386,6 +393,13 @@ class Model:
         z = z.contiguous()
         x = self.torch.empty((z.shape[0], self.n), dtype=self.torch.float64, device=self.dev)
         st, rep = rbmc_sample(self.m, make_opts(z.shape[0], maxit, rtol, precond=precond), z, x)
+        return x, st, rep
+
+    def solve(self, b, rtol=1e-8, maxit=5000, precond=RBMC_PC_BJ):
+        """x with Q x_k = b_k for the rows b_k of b ((n_rhs, n) device tensor)."""
+        b = b.contiguous()
+        x = self.torch.empty((b.shape[0], self.n), dtype=self.torch.float64, device=self.dev)
+        st, rep = rbmc_solve(self.m, make_opts(b.shape[0], maxit, rtol, precond=precond), b, x)
         return x, st, rep
 
     def estimate_from_samples(self, x, grad_mask=0b111, method=RBMC_SEL_AUTO,

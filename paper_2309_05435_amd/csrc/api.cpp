@@ -321,6 +321,13 @@ struct rbmc_model {
   struct KronReg {
     int region = 0, nb = 0, np = 0;
     double *inv = nullptr, *dR = nullptr, *qR = nullptr, *kR = nullptr;
+    // rim of R: nodes with a 13-point neighbour in the grid outside R (the
+    // only rows where r = Q_AB x_B is nonzero at steps away from the time
+    // separator), nring of them, padded to nrp with -1; rinv = S^-1[:, rim]
+    bool rim = false;  // corrections use the rim products
+    int nring = 0, nrp = 0;
+    int* d_ring = nullptr;
+    double* rinv = nullptr;
   };
   std::vector<KronSub> ksub;
   std::vector<KronReg> kreg;
@@ -1499,9 +1506,11 @@ bool learned_usable(const rbmc_model* m);
 using SampleHook = std::function<rbmc_status(int it, const double* x, const double* r,
                                              const double* z, const double* rr)>;
 
+// b_given (single model, n x n_k): solve Q x = b instead of sampling (z unused)
 rbmc_status sample_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const HostCols& h,
                        const rbmc_est_opts* o, const double* z, double* x, rbmc_report* rep,
-                       hipStream_t s, const SampleHook& hook = {}) {
+                       hipStream_t s, const SampleHook& hook = {},
+                       const double* b_given = nullptr) {
   g_tune = cx->tune;
   const int nk = o->n_samples;
   double t0 = now_s();
@@ -1636,8 +1645,11 @@ rbmc_status sample_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const H
     return RBMC_OK;
   };
   double* rzp = cx->scal + 5 * nc;
-  // b = F z -> r; x = 0
-  launch_apply_op(cols, RBMC_OP_F, z, r, s);
+  // b = F z (or the given b) -> r; x = 0
+  if (b_given)
+    HIPCHK(hipMemcpyAsync(r, b_given, h.total * 8, hipMemcpyDeviceToDevice, s));
+  else
+    launch_apply_op(cols, RBMC_OP_F, z, r, s);
   HIPCHK(hipMemsetAsync(x, 0, h.total * 8, s));
   launch_dot_partials(cols, r, r, cx->part, s);
   launch_reduce_partials(cx->part, nch, nc, bb, s);
@@ -2604,6 +2616,33 @@ rbmc_status kron_static(rbmc_model* m) {
       HIPCHK(m->kpool.alloc((void**)&r.dR, (size_t)r.np * 8));
       HIPCHK(m->kpool.alloc((void**)&r.qR, (size_t)r.np * 8));
       HIPCHK(m->kpool.alloc((void**)&r.kR, (size_t)r.np * 8));
+      std::vector<char> in_r((size_t)P.ns, 0);
+      for (int a = 0; a < g.nb(); ++a) in_r[g.nodes[a]] = 1;
+      std::vector<int> ring;
+      for (int a = 0; a < g.nb(); ++a) {
+        const int x = g.nodes[a] % P.mx, y = g.nodes[a] / P.mx;
+        bool rim = false;
+        for (int dy = -2; dy <= 2 && !rim; ++dy)
+          for (int dx = -2; dx <= 2 && !rim; ++dx) {
+            if (std::abs(dx) + std::abs(dy) > 2) continue;
+            const int xx = x + dx, yy = y + dy;
+            rim = xx >= 0 && xx < P.mx && yy >= 0 && yy < P.my && !in_r[(size_t)yy * P.mx + xx];
+          }
+        if (rim) ring.push_back(a);
+      }
+      r.nring = (int)ring.size();
+      r.nrp = r.nring > 0 ? pad_to(r.nring) : 0;
+      r.rim = r.nrp < r.np;  // the rim products pay only when the rim is a part of R
+      if (r.rim && r.nring > 0) {
+        ring.resize(r.nrp, -1);
+        HIPCHK(m->kpool.alloc((void**)&r.d_ring, (size_t)r.nrp * 4));
+        HIPCHK(hipMemcpyAsync(r.d_ring, ring.data(), (size_t)r.nrp * 4, hipMemcpyHostToDevice,
+                              s));
+        HIPCHK(m->kpool.alloc((void**)&r.rinv, (size_t)r.np * r.nrp * 8));
+        HIPCHK(hipStreamSynchronize(s));  // ring is host memory of this scope
+      } else if (!r.rim) {
+        r.nring = r.nrp = 0;
+      }
       m->kreg_of[ch.region] = (int)m->kreg.size();
       m->kreg.push_back(r);
     }
@@ -2715,6 +2754,7 @@ rbmc_status kron_regions(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, hipSt
   StencilList sl;
   std::vector<InvJob> jobs;
   TileList<KronRegionTask> rt;
+  TileList<KronBuildTask> gt;
   for (size_t i = 0; i < todo.size(); ++i) {
     rbmc_model* m = todo[i].first;
     const rbmc_model::KronReg& R = m->kreg[todo[i].second];
@@ -2747,10 +2787,21 @@ rbmc_status kron_regions(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, hipSt
     k.qR = R.qR;
     k.kR = R.kR;
     rt.add(k, (R.np + 255) / 256);
+    if (R.rinv) {  // S^-1[:, rim]
+      KronBuildTask g{};
+      g.mode = 0;
+      g.inv = R.inv;
+      g.obs_a = R.d_ring;
+      g.np = R.np;
+      g.nc = R.nrp;
+      g.out = R.rinv;
+      gt.add(g, kron_cols_tiles(R.np, R.nrp), 16.0 * R.np * R.nrp);
+    }
   }
   pg.stencil(ar, sl);
   pg.inverse(ar, jobs);
   pg.kron(ar, 14, rt);
+  pg.kron(ar, 15, gt);
   HIPCHK(ar.upload(s));
   st = run(cx, pg, s, ar);
   if (st != RBMC_OK) return st;
@@ -2773,14 +2824,23 @@ size_t kron_sub_bytes(const rbmc_model* m, const rbmc_model::KronSub& k, int nk)
   const size_t np = R.np, nc = k.nc, TA = k.TA, w = sweep_width_of(k.nc);
   size_t d = 3 * np * nc + nc * nc + TA * TA * 3 * np + TA * TA;  // Z, KZ, X, C, part, V
   d += 2 * nc * w + w * w + 2 * w * 128 + 128 * 128;              // inversion of C
-  if (nk > 0) d += 2 * np * TA * nk + 2 * nc * nk;                // Rb, Ub, v, w
-  return d * 8 + 20 * 256;
+  if (nk > 0) d += 2 * np * TA * nk + 2 * nc * nk + (size_t)R.nrp * TA * nk;  // Rb Ub v w Rc
+  return d * 8 + 21 * 256;
 }
 
 struct KronBuf {
-  double *Z, *KZ, *X, *C, *part, *V, *Rb, *Ub, *v, *w;
+  double *Z, *KZ, *X, *C, *part, *V, *Rb, *Ub, *v, *w, *Rc;
   InvJob inv;
 };
+
+// Steps [ra, rb) of a subdomain's chain see no time separator: there r is
+// nonzero on the rim of R only.  The rest (at most the first and the last
+// step) take the dense product with S^-1.
+std::pair<int, int> kron_rim_steps(const rbmc_model* m, const Chain& ch) {
+  const int ra = ch.t0 > 0 ? 1 : 0;
+  const int rb = ch.t0 + ch.T < m->plan.T ? ch.T - 1 : ch.T;
+  return {ra, std::max(ra, rb)};
+}
 
 // The subdomains of a set, in order: (model index, subdomain index).
 std::vector<std::pair<int, int>> kron_refs(const std::vector<rbmc_model*>& ms) {
@@ -2968,6 +3028,8 @@ rbmc_status kron_corr_batch(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, co
     pg.kron(ar, 15, zt);
   }
   TileList<PanelTask> rt;
+  TileList<KronBuildTask> rg;                       // rim rows of r
+  std::vector<std::pair<double*, size_t>> uz;       // U blocks that are zero (empty rim)
   GemmList gu, gw, gz;
   gu.mixed = gw.mixed = gz.mixed = mixed;
   TileList<KronMixTask> m1, m2;
@@ -2994,9 +3056,33 @@ rbmc_status kron_corr_batch(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, co
       pt.mode = 2;
       rt.add(pt, panel_tiles(R.np, nk), 16.0 * R.nb * nk);
     }
-    // U = S^-1 R over all steps at once (panels are stacked columns)
-    gu.add(R.inv, b.Rb, nullptr, b.Ub, R.np, k.TA * nk, R.np, R.np, R.np, R.np, 1.0, 0.0, 0, 0,
-           R.nb, R.nb);
+    // U = S^-1 R (panels are stacked columns): steps next to the time
+    // separator against all of S^-1, the others against its rim columns
+    const std::pair<int, int> rim = R.rim ? kron_rim_steps(m, ch) : std::make_pair(0, 0);
+    for (const std::pair<int, int>& d : {std::make_pair(0, rim.first),
+                                         std::make_pair(rim.second, k.TA)})
+      if (d.second > d.first)
+        gu.add(R.inv, b.Rb + (size_t)d.first * panel, nullptr, b.Ub + (size_t)d.first * panel,
+               R.np, (d.second - d.first) * nk, R.np, R.np, R.np, R.np, 1.0, 0.0, 0, 0, R.nb,
+               R.nb);
+    if (rim.second > rim.first) {
+      const int ncol = (rim.second - rim.first) * nk;
+      if (R.nring > 0) {
+        KronBuildTask gt{};
+        gt.mode = 2;
+        gt.inv = b.Rb + (size_t)rim.first * panel;
+        gt.obs_a = R.d_ring;
+        gt.np = R.np;
+        gt.nc = R.nrp;
+        gt.TA = ncol;
+        gt.out = b.Rc;
+        rg.add(gt, kron_cols_tiles(R.nrp, ncol), 16.0 * R.nrp * ncol);
+        gu.add(R.rinv, b.Rc, nullptr, b.Ub + (size_t)rim.first * panel, R.np, ncol, R.nrp, R.np,
+               R.nrp, R.np, 1.0, 0.0, 0, 0, R.nb, R.nring);
+      } else {
+        uz.push_back({b.Ub + (size_t)rim.first * panel, (size_t)R.np * ncol});
+      }
+    }
     KronMixTask mx{};
     mx.V = b.V;
     mx.U = b.Ub;
@@ -3049,6 +3135,8 @@ rbmc_status kron_corr_batch(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, co
     }
   }
   pg.panels(ar, rt);
+  pg.kron(ar, 15, rg);
+  for (const auto& z : uz) pg.fill(z.first, z.second);
   pg.gemm(ar, gu);
   pg.kron(ar, 18, m1);
   pg.kron(ar, 19, ob);
@@ -3079,7 +3167,8 @@ using KronSampler =
 size_t kron_corr_bytes(const rbmc_model* m, const rbmc_model::KronSub& k, int nk) {
   const rbmc_model::KronReg& R = m->kreg[m->kreg_of[m->plan.sub[k.chain].region]];
   const size_t np = R.np, nc = k.nc, TA = k.TA;
-  return (np * nc + TA * TA + 2 * np * TA * nk + 2 * nc * nk) * 8 + 10 * 256;
+  return (np * nc + TA * TA + 2 * np * TA * nk + 2 * nc * nk + (size_t)R.nrp * TA * nk) * 8 +
+         11 * 256;
 }
 
 // The estimator by the Kronecker method, over batches of subdomains sized to
@@ -3216,6 +3305,8 @@ rbmc_status estimate_set_kron(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms,
         b.Ub = cv.d((size_t)np * k.TA * nk);
         b.v = cv.d((size_t)k.nc * nk);
         b.w = cv.d((size_t)k.nc * nk);
+        const int nrp = m->kreg[m->kreg_of[ch.region]].nrp;
+        b.Rc = nrp > 0 ? cv.d((size_t)nrp * k.TA * nk) : nullptr;
       }
       const std::vector<double> V = time_inverse(m->co, ch.t0, k.TA);
       vat.push_back(hV.size());
@@ -3842,6 +3933,29 @@ rbmc_status rbmc_sample(rbmc_model* m, const rbmc_est_opts* opts, const double* 
   st = ensure_ws(m->ctx, ms, h, false);
   if (st != RBMC_OK) return st;
   st = sample_set(m->ctx, ms, h, opts, z, x, rep, m->ctx->stream);
+  if (rep) {
+    rep->t_total = now_s() - t0;
+    rep->peak_bytes = m->ctx->ws.bytes + m->pool.bytes + m->work_bj.bytes + m->spool.bytes;
+  }
+  return st;
+}
+
+rbmc_status rbmc_solve(rbmc_model* m, const rbmc_est_opts* opts, const double* b, double* x,
+                       rbmc_report* rep) {
+  init_report(rep);
+  if (!m || !b || !x) return fail(RBMC_E_ARG, "NULL argument");
+  if (b == x) return fail(RBMC_E_ARG, "b and x must be distinct buffers");
+  rbmc_status st = check_opts(opts, true);
+  if (st != RBMC_OK) return st;
+  if (opts->n_samples == 0) return RBMC_OK;
+  if (!cols_fit(1, opts->n_samples)) return fail(RBMC_E_ARG, "n_samples exceeds 65535");
+  HIPCHK(hipSetDevice(m->ctx->device));
+  double t0 = now_s();
+  std::vector<rbmc_model*> ms{m};
+  const HostCols h = make_cols(ms, opts->n_samples);
+  st = ensure_ws(m->ctx, ms, h, false);
+  if (st != RBMC_OK) return st;
+  st = sample_set(m->ctx, ms, h, opts, nullptr, x, rep, m->ctx->stream, {}, b);
   if (rep) {
     rep->t_total = now_s() - t0;
     rep->peak_bytes = m->ctx->ws.bytes + m->pool.bytes + m->work_bj.bytes + m->spool.bytes;

@@ -96,6 +96,16 @@ __global__ __launch_bounds__(256) void k_kron_build(const KronBuildTask* __restr
   const int r = (tile % rt) * 256 + threadIdx.x;
   const int c0 = (tile / rt) * kKC;
   if (r >= rows) return;
+  if (tk.mode == 2) {  // gather rows a_r of TA columns
+    const int ar = G(tk.obs_a)[r];
+#pragma unroll
+    for (int j = 0; j < kKC; ++j) {
+      const int c = c0 + j;
+      if (c >= tk.TA) break;
+      G(tk.out)[(size_t)c * tk.nc + r] = ar >= 0 ? G(tk.inv)[(size_t)c * tk.np + ar] : 0.0;
+    }
+    return;
+  }
   if (tk.mode == 0) {  // gather Z
 #pragma unroll
     for (int j = 0; j < kKC; ++j) {

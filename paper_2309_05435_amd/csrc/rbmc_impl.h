@@ -434,7 +434,10 @@ struct KronRegionTask {  // per region: dR, qR, kR from S^-1 (np x np)
 };
 void launch_kron_region(const KronRegionTask* d_tasks, int n_tasks, int total_tiles,
                         hipStream_t s);
-struct KronBuildTask {  // mode 0: Z = S^-1[:, a_o] (np x nc); mode 1: C (nc x nc) from Z
+// mode 0: Z = S^-1[:, a_o] (np x nc); mode 1: C (nc x nc) from Z;
+// mode 2: rows a_j (j < nc) of the TA columns of inv (leading dimension np)
+// into out (nc x TA), zero where a_j = -1
+struct KronBuildTask {
   int mode;
   const double* inv;
   const double* Z;

@@ -49,6 +49,9 @@ CASES = [
     (13, 1, 1, 2, 1),
     (20, 6, 2, 1, 1),
     (34, 4, 1, 2, 1),
+    # 3 x 3 tiles, 3 slabs: rim products (r on the rim of R only) in the
+    # first, middle and last slabs
+    (30, 7, 3, 3, 1),
 ]
 
 

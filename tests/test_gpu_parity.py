@@ -146,6 +146,29 @@ def test_sampler_matches_exact_solve(case):
     gm.close()
 
 
+@pytest.mark.parametrize("precond", [B.RBMC_PC_BJ, B.RBMC_PC_SPECTRAL])
+def test_solve_unit_vectors_gives_inverse_diagonal(precond):
+    """rbmc_solve with b = e_i: x_i = (Q^-1)_ii, against a dense inverse of the
+    oracle's Q (3 x 3 tiles of a 17 x 17 grid, ragged; both preconditioners)."""
+    wl = wl_of(17, 6, 2, 3, 1)
+    say("solve", precond)
+    M = oracle_model(wl)
+    Sigma = np.linalg.inv(M.csr(O.Q).dense())
+    nodes = np.random.default_rng(41).choice(M.n, size=24, replace=False)
+    E = np.zeros((len(nodes), M.n))
+    E[np.arange(len(nodes)), nodes] = 1.0
+    gm = B.Model(wl)
+    bd = dev(E)
+    x, st, rep = gm.solve(bd, rtol=1e-13, maxit=5000, precond=precond)
+    assert st == B.RBMC_OK
+    assert np.array_equal(bd.cpu().numpy(), E)  # b untouched
+    x = x.cpu().numpy()
+    np.testing.assert_allclose(x, Sigma[nodes], rtol=0, atol=1e-10 * np.abs(Sigma).max())
+    np.testing.assert_allclose(x[np.arange(len(nodes)), nodes], np.diag(Sigma)[nodes],
+                               rtol=1e-9)
+    gm.close()
+
+
 @pytest.mark.parametrize("pc", [(1, 2, 2), (2, 3, 1), (8, 1, 1)])
 def test_sampler_with_other_block_jacobi_blocks(pc):
     """Preconditioner blocks other than the cores change the iteration count,
