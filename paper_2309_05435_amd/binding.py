@@ -349,9 +349,11 @@ def popcount(mask: int) -> int:
 class Model:
     """Owns a context + model; inputs/outputs are torch tensors on the device."""
 
-    def __init__(self, wl, mask=None, theta=None, device: int = 0, decomp=None, pc="workload"):
+    def __init__(self, wl, mask=None, theta=None, device: int = 0, decomp=None, pc="workload",
+                 shape=None):
         """pc: block-Jacobi blocks (slabs, tiles_x, tiles_y); "workload" takes the
-        workload's setting, None or () the cores."""
+        workload's setting, None or () the cores.  shape: (mx, my) for a grid
+        other than the workload's m x m (mask then drawn for mx my T nodes)."""
         if isinstance(pc, str):
             pc = getattr(wl, "pc", None)
         import torch
@@ -360,15 +362,19 @@ class Model:
         self.dev = torch.device("cuda", device)
         stream = torch.cuda.current_stream(self.dev).cuda_stream
         self.ctx = rbmc_ctx_create(device, C.c_void_p(stream))
-        mask = wl.mask() if mask is None else mask
+        mx, my = shape if shape else (wl.m, wl.m)
+        if mask is None:
+            from .inputs import obs_mask
+            mask = wl.mask() if not shape else obs_mask(mx * my * wl.T, wl.obs_frac,
+                                                        wl.mask_seed)
         th = wl.theta if theta is None else theta
-        self.desc, self._mask = make_desc(wl.m, wl.m, wl.T, wl.h, th, mask)
+        self.desc, self._mask = make_desc(mx, my, wl.T, wl.h, th, mask)
         if decomp is None:
             decomp = (wl.n_tslabs, wl.n_tiles, wl.n_tiles, wl.n_l)
         decomp = tuple(decomp) + (tuple(pc) if pc else ())
         self.decomp = rbmc_decomp_desc(*decomp)
         self.m = rbmc_model_create(self.ctx, self.desc, self.decomp)
-        self.n = wl.m * wl.m * wl.T
+        self.n = mx * my * wl.T
         self.n_obs = int(self._mask.sum())
 
     def close(self):

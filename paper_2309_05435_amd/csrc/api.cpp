@@ -339,6 +339,10 @@ struct rbmc_model {
   bool spec_alloc = false, spec_ready = false;
   double *d_lam = nullptr, *d_dctx = nullptr, *d_dcty = nullptr, *d_spcp = nullptr,
          *d_spid = nullptr, *d_spoff = nullptr;
+  // transform route: 2 FFT (both sides powers of two), 1 matrix-core GEMM,
+  // 0 the direct kernel; FFT twiddles (N/2 + N pairs per axis)
+  int spec_route = 0;
+  double *d_fftx = nullptr, *d_ffty = nullptr;
   Pool spool;
   DevModel dm{};
   DevModel* d_dm = nullptr;
@@ -888,6 +892,7 @@ rbmc_status run(rbmc_ctx* cx, const Program& pg, hipStream_t s, Arena& a) {
       case 20: launch_fill((double*)o.dst, o.bytes, 0.0, s); break;
       case 21: launch_spec_solve(o.cols, (double*)o.dst, s); break;
       case 22: launch_dct_direct(o.cols, (const double*)o.src, (double*)o.dst, o.n, o.kblk, s); break;
+      case 23: launch_dct_fft(a.at<FftTask>(o.off), o.n, o.tiles, o.kblk, o.max_np, s); break;
     }
     if (o.kind != 10) cx->end(pid, s);
   }
@@ -1349,6 +1354,33 @@ rbmc_status upload_dm(rbmc_model* m, hipStream_t s) {
 rbmc_status ensure_spectral(rbmc_model* m, hipStream_t s) {
   const Plan& P = m->plan;
   if (!m->spec_alloc) {
+    const bool fft_ok = fft_length_ok(P.mx) && fft_length_ok(P.my);
+    const bool gemm_ok = P.mx % 16 == 0 && P.my % 16 == 0 && P.mx >= 64 && P.my >= 64;
+    m->spec_route = fft_ok ? 2 : gemm_ok ? 1 : 0;
+    if (const char* e = std::getenv("RBMC_SPEC_ROUTE")) {  // "fft", "gemm" or "direct"
+      const std::string r(e);
+      if (r == "direct") m->spec_route = 0;
+      if (r == "gemm" && gemm_ok) m->spec_route = 1;
+      if (r == "fft" && fft_ok) m->spec_route = 2;
+    }
+    if (m->spec_route == 2) {
+      for (int ax = 0; ax < 2; ++ax) {
+        const int N = ax == 0 ? P.mx : P.my;
+        std::vector<double> tab((size_t)3 * N);  // tw (N/2 pairs), then ph (N pairs)
+        for (int t = 0; t < N / 2; ++t) {
+          tab[2 * t] = std::cos(2.0 * M_PI * t / N);
+          tab[2 * t + 1] = std::sin(2.0 * M_PI * t / N);
+        }
+        for (int k = 0; k < N; ++k) {
+          tab[N + 2 * k] = std::cos(M_PI * k / (2.0 * N));
+          tab[N + 2 * k + 1] = std::sin(M_PI * k / (2.0 * N));
+        }
+        double*& d = ax == 0 ? m->d_fftx : m->d_ffty;
+        HIPCHK(m->spool.alloc((void**)&d, tab.size() * 8));
+        HIPCHK(hipMemcpyAsync(d, tab.data(), tab.size() * 8, hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));  // tab is host memory of this scope
+      }
+    }
     HIPCHK(m->spool.alloc((void**)&m->d_lam, (size_t)P.ns * 8));
     HIPCHK(m->spool.alloc((void**)&m->d_spoff, (size_t)P.ns * 8));
     HIPCHK(m->spool.alloc((void**)&m->d_spcp, (size_t)P.n * 8));
@@ -1393,7 +1425,7 @@ rbmc_status ensure_spectral(rbmc_model* m, hipStream_t s) {
   m->dm.sp_cp = m->d_spcp;
   m->dm.sp_id = m->d_spid;
   m->dm.sp_off = m->d_spoff;
-  m->dm.spec_gemm = (P.mx % 16 == 0 && P.my % 16 == 0 && P.mx >= 64 && P.my >= 64) ? 1 : 0;
+  m->dm.spec_gemm = m->spec_route != 0 ? 1 : 0;
   rbmc_status st = upload_dm(m, s);  // synchronizes: lam is on the host stack
   if (st != RBMC_OK) return st;
   m->spec_ready = true;
@@ -1401,13 +1433,18 @@ rbmc_status ensure_spectral(rbmc_model* m, hipStream_t s) {
 }
 
 // One axis of the 2-D transform for every column of the set: models with the
-// GEMM route as matrix-core products (axis 0: C_x X over all rows of x at
-// once; axis 1: X_s C_y^T per (time step, sample) slice), the others by the
-// direct kernel.  inverse: C^T.
+// FFT route by the FFT kernel (axis 0: the contiguous lines of length mx;
+// axis 1: lines of length my, mx apart), models with the GEMM route as
+// matrix-core products (axis 0: C_x X over all rows of x at once; axis 1:
+// X_s C_y^T per (time step, sample) slice), the others by the direct
+// kernel.  inverse: C^T.
 void spectral_axis(const std::vector<rbmc_model*>& ms, const HostCols& h, const ColSet& cols,
                    int nk, const double* in, double* out, int axis, int inverse, Program& pg,
                    Arena& a) {
   GemmList gl;
+  std::vector<FftTask> ft;
+  int fft_tiles_total = 0;
+  double fft_bytes = 0.0;
   bool direct = false;
   for (size_t j = 0; j < ms.size(); ++j) {
     const rbmc_model* m = ms[j];
@@ -1418,6 +1455,27 @@ void spectral_axis(const std::vector<rbmc_model*>& ms, const HostCols& h, const 
     }
     const double* src = in + h.base[j];
     double* dst = out + h.base[j];
+    if (m->spec_route == 2) {
+      FftTask t{};
+      t.in = src;
+      t.out = dst;
+      t.N = axis == 0 ? mx : my;
+      t.lg = 0;
+      while ((1 << t.lg) < t.N) ++t.lg;
+      t.tw = axis == 0 ? m->d_fftx : m->d_ffty;
+      t.ph = t.tw + t.N;
+      t.nl = axis == 0 ? my : mx;
+      t.nslices = T * nk;
+      t.sstride = (long)mx * my;
+      t.lstride = axis == 0 ? mx : 1;
+      t.estride = axis == 0 ? 1 : mx;
+      t.inverse = inverse;
+      t.tile_start = fft_tiles_total;
+      fft_tiles_total += fft_tiles(t.N, (long)t.nl * t.nslices);
+      fft_bytes += 16.0 * (double)mx * my * T * nk;
+      ft.push_back(t);
+      continue;
+    }
     if (axis == 0) {
       gl.add(m->d_dctx, src, nullptr, dst, mx, my * T * nk, mx, mx, mx, mx, 1.0, 0.0, inverse, 0,
              mx, mx);
@@ -1430,6 +1488,19 @@ void spectral_axis(const std::vector<rbmc_model*>& ms, const HostCols& h, const 
     }
   }
   pg.gemm(a, gl, true, RBMC_KF_DCT);
+  if (!ft.empty()) {
+    Op o;
+    o.kind = 23;
+    o.off = a.push(ft);
+    o.n = (int)ft.size();
+    o.tiles = fft_tiles_total;
+    o.kblk = axis;
+    o.max_np = 0;
+    for (const FftTask& t : ft) o.max_np = std::max(o.max_np, t.N);
+    o.family = RBMC_KF_DCT;
+    o.alg_bytes = fft_bytes;
+    pg.ops.push_back(o);
+  }
   if (direct) {
     Op o;
     o.kind = 22;
@@ -3028,7 +3099,6 @@ rbmc_status kron_corr_batch(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, co
     pg.kron(ar, 15, zt);
   }
   TileList<PanelTask> rt;
-  TileList<KronBuildTask> rg;                       // rim rows of r
   std::vector<std::pair<double*, size_t>> uz;       // U blocks that are zero (empty rim)
   GemmList gu, gw, gz;
   gu.mixed = gw.mixed = gz.mixed = mixed;
@@ -3043,9 +3113,14 @@ rbmc_status kron_corr_batch(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, co
     const rbmc_model::KronReg& R = m->kreg[m->kreg_of[ch.region]];
     const KronBuf& b = kb[i - i0];
     const size_t panel = (size_t)R.np * nk;
+    // steps [rim.first, rim.second) see no time separator: r lives on the rim
+    // of R there, and its panel holds the rim rows only (nrp x n_k, in Rc)
+    const std::pair<int, int> rim = R.rim ? kron_rim_steps(m, ch) : std::make_pair(0, 0);
     for (int t = 0; t < k.TA; ++t) {  // r = Q_AB x_B, one panel per step
+      const bool on_rim = t >= rim.first && t < rim.second;
+      if (on_rim && R.nring == 0) continue;  // r = 0
       PanelTask pt{};
-      pt.P = b.Rb + (size_t)t * panel;
+      pt.P = on_rim ? b.Rc + (size_t)(t - rim.first) * R.nrp * nk : b.Rb + (size_t)t * panel;
       pt.rg = m->d_regions + ch.region;
       pt.dm = m->d_dm;
       pt.X = x_base + h.base[j];
@@ -3054,11 +3129,12 @@ rbmc_status kron_corr_batch(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, co
       pt.t0 = ch.t0;
       pt.T = ch.T;
       pt.mode = 2;
-      rt.add(pt, panel_tiles(R.np, nk), 16.0 * R.nb * nk);
+      pt.rows = on_rim ? R.d_ring : nullptr;
+      pt.ld = on_rim ? R.nrp : R.np;
+      rt.add(pt, panel_tiles(pt.ld, nk), 8.0 * (on_rim ? R.nring : R.nb) * nk * 2);
     }
     // U = S^-1 R (panels are stacked columns): steps next to the time
     // separator against all of S^-1, the others against its rim columns
-    const std::pair<int, int> rim = R.rim ? kron_rim_steps(m, ch) : std::make_pair(0, 0);
     for (const std::pair<int, int>& d : {std::make_pair(0, rim.first),
                                          std::make_pair(rim.second, k.TA)})
       if (d.second > d.first)
@@ -3068,15 +3144,6 @@ rbmc_status kron_corr_batch(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, co
     if (rim.second > rim.first) {
       const int ncol = (rim.second - rim.first) * nk;
       if (R.nring > 0) {
-        KronBuildTask gt{};
-        gt.mode = 2;
-        gt.inv = b.Rb + (size_t)rim.first * panel;
-        gt.obs_a = R.d_ring;
-        gt.np = R.np;
-        gt.nc = R.nrp;
-        gt.TA = ncol;
-        gt.out = b.Rc;
-        rg.add(gt, kron_cols_tiles(R.nrp, ncol), 16.0 * R.nrp * ncol);
         gu.add(R.rinv, b.Rc, nullptr, b.Ub + (size_t)rim.first * panel, R.np, ncol, R.nrp, R.np,
                R.nrp, R.np, 1.0, 0.0, 0, 0, R.nb, R.nring);
       } else {
@@ -3135,7 +3202,6 @@ rbmc_status kron_corr_batch(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, co
     }
   }
   pg.panels(ar, rt);
-  pg.kron(ar, 15, rg);
   for (const auto& z : uz) pg.fill(z.first, z.second);
   pg.gemm(ar, gu);
   pg.kron(ar, 18, m1);

@@ -54,34 +54,42 @@ __global__ __launch_bounds__(256) void k_panels(const PanelTask* __restrict__ ta
       G(tk.Xout)[(size_t)k * m.n + base] = G(tk.P)[(size_t)k * rg.np + a];
     }
   } else {
-    // r_a = sum over neighbours j of (t, node) outside A = [t0, t0+T) x R of Q_aj x_j
-    int idx[3 * kNS];
-    double cf[3 * kNS];
-    int cnt = 0;
-    if (real) {
-      const int ix = node % m.mx, iy = node / m.mx;
-      for (int dt = -1; dt <= 1; ++dt) {
-        const int tt = tk.t + dt;
-        if (tt < 0 || tt >= m.T) continue;
-        const double wt = (dt == 0) ? m.qd[tk.t] : m.qo;
-        const bool t_in = (tt >= tk.t0 && tt < tk.t0 + tk.T);
-        for (int q = 0; q < kNS; ++q) {
-          const int jx = ix + kSdx[q], jy = iy + kSdy[q];
-          if (jx < 0 || jx >= m.mx || jy < 0 || jy >= m.my) continue;
-          const bool s_in = G(rg.nbr)[a * kNS + q] >= 0;
-          if (t_in && s_in) continue;
-          idx[cnt] = tt * m.ns + jy * m.mx + jx;
-          cf[cnt] = wt * G(m.qs)[(size_t)q * m.ns + node];
-          ++cnt;
-        }
+    // r_a = sum over neighbours j of (t, node) outside A = [t0, t0+T) x R of
+    // Q_aj x_j; row a of the panel is region row ar (the row list, or a)
+    const int ar = tk.rows ? G(tk.rows)[a] : (real ? a : -1);
+    const int ld = tk.rows ? tk.ld : rg.np;
+    const int nd = ar >= 0 ? G(rg.nodes)[ar] : 0;
+    const int ix = nd % m.mx, iy = nd / m.mx;
+    // coefficients of the 3 x 13 space-time neighbours, zero for those in A
+    // or off the grid (static indices: the arrays stay in registers)
+    double cf[3][kNS];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int tt = tk.t + d - 1;
+      const bool t_ok = ar >= 0 && tt >= 0 && tt < m.T;
+      const bool t_in = tt >= tk.t0 && tt < tk.t0 + tk.T;
+      const double wt = d == 1 ? G(m.qd)[tk.t] : m.qo;
+#pragma unroll
+      for (int q = 0; q < kNS; ++q) {
+        const int jx = ix + kSdx[q], jy = iy + kSdy[q];
+        const bool ok = t_ok && jx >= 0 && jx < m.mx && jy >= 0 && jy < m.my &&
+                        !(t_in && G(rg.nbr)[ar * kNS + q] >= 0);
+        cf[d][q] = ok ? wt * G(m.qs)[(size_t)q * m.ns + nd] : 0.0;
       }
     }
+    const size_t at = (size_t)tk.t * m.ns + nd;
     for (int kk = threadIdx.x >> 6; kk < PT_K; kk += 4) {
       const int k = kbase + kk;
       if (k >= n_k) break;
+      const gptr<const double> xk = G(tk.X) + (size_t)k * m.n + at;
       double v = 0.0;
-      for (int c = 0; c < cnt; ++c) v += cf[c] * G(tk.X)[(size_t)k * m.n + idx[c]];
-      G(tk.P)[(size_t)k * rg.np + a] = v;
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int q = 0; q < kNS; ++q)
+          if (cf[d][q] != 0.0)
+            v += cf[d][q] * xk[(long)(d - 1) * m.ns + kSdy[q] * m.mx + kSdx[q]];
+      G(tk.P)[(size_t)k * ld + a] = v;
     }
   }
 }

@@ -1,0 +1,169 @@
+// Orthonormal DCT-II / DCT-III along one axis of many 2-D slices, by fast
+// Fourier transforms: the diagonalizing transform of the Neumann grid
+// Laplacian in the spectral preconditioner, O(N log N) per line and one read
+// and one write of the data per axis (the transform is bound by HBM, not by
+// arithmetic).
+//
+// Forward (Makhoul, IEEE TASSP 28(1), 1980): with v[n] = x[2n],
+// v[N-1-n] = x[2n+1] and V = FFT_N(v),
+//   X[k] = s_k Re(exp(-i pi k / 2N) V[k]),  s_0 = sqrt(1/N), s_k = sqrt(2/N).
+// Inverse (X -> x = C^T X): with Y_k = X_k / s_k (Y_N = 0),
+//   V[k] = exp(i pi k / 2N) (Y_k - i Y_{N-k}),  v = IFFT_N(V),
+// and x read back through the same reordering.  v is real, so two lines
+// share one complex transform (one as the real, one as the imaginary part);
+// their spectra are separated by the Hermitian symmetry of each.
+//
+// Workgroup: 256 threads and 2048 complex values in LDS, i.e. P = 2048 / N
+// line pairs, plus the N/2 twiddles; radix-2 decimation in time on
+// bit-reversed input, in place.
+#include "rbmc_impl.h"
+
+namespace rbmc {
+
+namespace {
+constexpr int kFftSlots = 2048;  // complex values per workgroup
+constexpr int kFftThreads = 256;
+
+__device__ __forceinline__ int fft_find(const FftTask* __restrict__ t, int n, int b) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (t[mid].tile_start <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// position of x[m] in v
+__device__ __forceinline__ int fft_vpos(int m, int N) {
+  return (m & 1) ? N - 1 - (m >> 1) : (m >> 1);
+}
+
+__device__ __forceinline__ int fft_rev(int i, int lg) {
+  return (int)(__brev((unsigned)i) >> (32 - lg));
+}
+}  // namespace
+
+// AXIS 0: lines are contiguous (element stride 1, consecutive lines mx
+// apart); AXIS 1: element stride mx, consecutive lines adjacent.  Thread
+// mappings keep global accesses coalesced in both cases.
+template <int AXIS>
+__global__ __launch_bounds__(kFftThreads) void k_dct_fft(const FftTask* __restrict__ tasks,
+                                                         int n_tasks) {
+  extern __shared__ double fft_lds[];  // zr, zi (kFftSlots each), then N/2 twiddle pairs
+  double* zr = fft_lds;
+  double* zi = fft_lds + kFftSlots;
+  double* twl = fft_lds + 2 * kFftSlots;
+  const FftTask tk = tasks[fft_find(tasks, n_tasks, blockIdx.x)];
+  const int N = tk.N, lg = tk.lg, P = kFftSlots / N, L = 2 * P;
+  const long g0 = (long)(blockIdx.x - tk.tile_start) * L;  // first line of the workgroup
+  const long nlines = (long)tk.nslices * tk.nl;
+  const gptr<const double> in = G(tk.in);
+  const gptr<double> out = G(tk.out);
+  const gptr<const double> tw = G(tk.tw), ph = G(tk.ph);
+  auto base = [&](int i) -> long {  // offset of line g0 + i
+    const long g = g0 + i;
+    return (g / tk.nl) * tk.sstride + (g % tk.nl) * tk.lstride;
+  };
+  const long est = tk.estride;
+  for (int q = threadIdx.x; q < N; q += kFftThreads) twl[q] = tw[q];
+  if (!tk.inverse) {
+    for (int q = threadIdx.x; q < L * N; q += kFftThreads) {
+      const int i = AXIS == 0 ? q / N : q % L;
+      const int m = AXIS == 0 ? q % N : q / L;
+      const double v = g0 + i < nlines ? in[base(i) + m * est] : 0.0;
+      const int at = (i >> 1) * N + fft_rev(fft_vpos(m, N), lg);
+      if (i & 1) zi[at] = v; else zr[at] = v;
+    }
+  } else {
+    const double sn0 = sqrt(1.0 / N), sn = sqrt(2.0 / N);
+    for (int q = threadIdx.x; q < P * N; q += kFftThreads) {
+      const int p = AXIS == 0 ? q / N : q % P;
+      const int k = AXIS == 0 ? q % N : q / P;
+      const int kr = (N - k) & (N - 1);
+      double va_r = 0.0, va_i = 0.0, vb_r = 0.0, vb_i = 0.0;
+      const double c = ph[2 * k], s = ph[2 * k + 1];
+      const double inv_k = 1.0 / (k ? sn : sn0), inv_r = 1.0 / sn;
+#pragma unroll
+      for (int part = 0; part < 2; ++part) {
+        const int i = 2 * p + part;
+        double y = 0.0, yr = 0.0;
+        if (g0 + i < nlines) {
+          const long b = base(i);
+          y = in[b + k * est] * inv_k;
+          yr = k ? in[b + kr * est] * inv_r : 0.0;
+        }
+        // V = (c + i s)(y - i yr)
+        const double re = c * y + s * yr, im = s * y - c * yr;
+        if (part == 0) { va_r = re; va_i = im; } else { vb_r = re; vb_i = im; }
+      }
+      // Z = V_A + i V_B
+      const int at = p * N + fft_rev(k, lg);
+      zr[at] = va_r - vb_i;
+      zi[at] = va_i + vb_r;
+    }
+  }
+  __syncthreads();
+  const double sgn = tk.inverse ? -1.0 : 1.0;  // twiddles exp(-+2 pi i j / N)
+  for (int h = 1, lh = 0; h < N; h <<= 1, ++lh) {
+    const int step = N >> (lh + 1);  // N / 2h
+    for (int u = threadIdx.x; u < P * (N >> 1); u += kFftThreads) {
+      const int p = u / (N >> 1), b = u % (N >> 1);
+      const int j = b & (h - 1);
+      const int i0 = p * N + ((b >> lh) << (lh + 1)) + j, i1 = i0 + h;
+      const double wr = twl[2 * (j * step)], wi = -sgn * twl[2 * (j * step) + 1];
+      const double ar = zr[i1], ai = zi[i1];
+      const double tr = wr * ar - wi * ai, ti = wr * ai + wi * ar;
+      const double br = zr[i0], bi = zi[i0];
+      zr[i1] = br - tr;
+      zi[i1] = bi - ti;
+      zr[i0] = br + tr;
+      zi[i0] = bi + ti;
+    }
+    __syncthreads();
+  }
+  if (!tk.inverse) {
+    const double sn0 = sqrt(1.0 / N), sn = sqrt(2.0 / N);
+    for (int q = threadIdx.x; q < L * N; q += kFftThreads) {
+      const int i = AXIS == 0 ? q / N : q % L;
+      const int k = AXIS == 0 ? q % N : q / L;
+      if (g0 + i >= nlines) continue;
+      const int p = i >> 1, kr = (N - k) & (N - 1);
+      const double ar = zr[p * N + k], ai = zi[p * N + k];
+      const double br = zr[p * N + kr], bi = zi[p * N + kr];
+      // V_A = (Z_k + conj Z_{N-k}) / 2,  V_B = (Z_k - conj Z_{N-k}) / 2i
+      const double vr = (i & 1) ? 0.5 * (ai + bi) : 0.5 * (ar + br);
+      const double vi = (i & 1) ? -0.5 * (ar - br) : 0.5 * (ai - bi);
+      // Re(exp(-i pi k / 2N) V)
+      const double c = ph[2 * k], s = ph[2 * k + 1];
+      out[base(i) + k * est] = (k ? sn : sn0) * (c * vr + s * vi);
+    }
+  } else {
+    const double scale = 1.0 / N;
+    for (int q = threadIdx.x; q < L * N; q += kFftThreads) {
+      const int i = AXIS == 0 ? q / N : q % L;
+      const int m = AXIS == 0 ? q % N : q / L;
+      if (g0 + i >= nlines) continue;
+      const int at = (i >> 1) * N + fft_vpos(m, N);
+      out[base(i) + m * est] = scale * ((i & 1) ? zi[at] : zr[at]);
+    }
+  }
+}
+
+int fft_tiles(int N, long lines) {
+  const int L = 2 * (kFftSlots / N);
+  return (int)((lines + L - 1) / L);
+}
+
+bool fft_length_ok(int N) { return N >= 16 && N <= kFftSlots && (N & (N - 1)) == 0; }
+
+void launch_dct_fft(const FftTask* d_tasks, int n_tasks, int total_tiles, int axis, int max_n,
+                    hipStream_t s) {
+  if (total_tiles <= 0) return;
+  const size_t lds = (2 * (size_t)kFftSlots + max_n) * sizeof(double);
+  if (axis == 0)
+    k_dct_fft<0><<<total_tiles, kFftThreads, lds, s>>>(d_tasks, n_tasks);
+  else
+    k_dct_fft<1><<<total_tiles, kFftThreads, lds, s>>>(d_tasks, n_tasks);
+}
+
+}  // namespace rbmc

@@ -96,16 +96,6 @@ __global__ __launch_bounds__(256) void k_kron_build(const KronBuildTask* __restr
   const int r = (tile % rt) * 256 + threadIdx.x;
   const int c0 = (tile / rt) * kKC;
   if (r >= rows) return;
-  if (tk.mode == 2) {  // gather rows a_r of TA columns
-    const int ar = G(tk.obs_a)[r];
-#pragma unroll
-    for (int j = 0; j < kKC; ++j) {
-      const int c = c0 + j;
-      if (c >= tk.TA) break;
-      G(tk.out)[(size_t)c * tk.nc + r] = ar >= 0 ? G(tk.inv)[(size_t)c * tk.np + ar] : 0.0;
-    }
-    return;
-  }
   if (tk.mode == 0) {  // gather Z
 #pragma unroll
     for (int j = 0; j < kKC; ++j) {
@@ -259,9 +249,11 @@ void launch_kron_det(const KronDetTask* d_tasks, int n_tasks, int total_tiles, h
 // ---------------------------------------------------------------------------
 // Time mixing of stacked panels (np x n_k per local step, step t at
 // t np n_k): out_t = beta In_t + alpha sum_t' V[t,t'] U_t'  (out may alias In;
-// U must not alias out).  Thread per (row, sample); outputs in chunks of 8
-// steps so each input panel entry is read TA/8 times.
+// U must not alias out).  Thread per (row, sample); up to kMix output steps
+// are held in registers, so for TA <= kMix every input entry is read once.
 // ---------------------------------------------------------------------------
+constexpr int kMix = 24;
+
 __global__ __launch_bounds__(256) void k_kron_tmix(const KronMixTask* __restrict__ tasks,
                                                    int n_tasks) {
   const KronMixTask tk = tasks[kfind(tasks, n_tasks, blockIdx.x)];
@@ -270,16 +262,18 @@ __global__ __launch_bounds__(256) void k_kron_tmix(const KronMixTask* __restrict
   if (e >= panel) return;
   const int TA = tk.TA;
   const gptr<const double> V = G(tk.V), U = G(tk.U);
-  for (int t0 = 0; t0 < TA; t0 += 8) {
-    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int t0 = 0; t0 < TA; t0 += kMix) {
+    double acc[kMix];
+#pragma unroll
+    for (int j = 0; j < kMix; ++j) acc[j] = 0.0;
     for (int tp = 0; tp < TA; ++tp) {
       const double u = U[(size_t)tp * panel + e];
 #pragma unroll
-      for (int j = 0; j < 8; ++j)
+      for (int j = 0; j < kMix; ++j)
         if (t0 + j < TA) acc[j] = fma(V[(t0 + j) * TA + tp], u, acc[j]);
     }
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    for (int j = 0; j < kMix; ++j) {
       if (t0 + j >= TA) break;
       const size_t at = (size_t)(t0 + j) * panel + e;
       double v = tk.alpha * acc[j];

@@ -117,7 +117,7 @@ struct DevModel {  // device views used by the stencil kernels
   const double* sp_cp;    // T x ns
   const double* sp_id;    // T x ns
   const double* sp_off;   // ns
-  int spec_gemm;
+  int spec_gemm;  // transformed outside the direct DCT kernel (FFT or GEMM route)
 };
 
 // Column sets: the sampler works on the columns (model, sample) of one or
@@ -136,6 +136,25 @@ struct ColSet {
   const int* model;
   const DevModel* dms;
 };
+
+// One axis of the orthonormal DCT-II (inverse = 0) or DCT-III (inverse = 1)
+// of nslices 2-D slices by FFT: nl lines of length N = 2^lg per slice, line
+// l of slice q at q sstride + l lstride, elements estride apart.  tw: N/2
+// pairs (cos, sin)(2 pi t / N); ph: N pairs (cos, sin)(pi k / 2N).
+struct FftTask {
+  const double* in;
+  double* out;
+  const double* tw;
+  const double* ph;
+  int N, lg, nl, nslices;
+  long sstride, lstride, estride;
+  int inverse;
+  int tile_start;
+};
+bool fft_length_ok(int N);
+int fft_tiles(int N, long lines);
+void launch_dct_fft(const FftTask* d_tasks, int n_tasks, int total_tiles, int axis, int max_n,
+                    hipStream_t s);
 
 int stencil_tiles(int mx, int my);
 // load the operator kernels' code object now (an empty launch on s)
@@ -277,6 +296,10 @@ struct PanelTask {
   int t;        // global time step of the block
   int t0, T;    // chain time range (mode 2)
   int mode;
+  // mode 2: rows (nullptr: all np rows of R, panel leading dimension np) or a
+  // list of ld region rows (-1: a zero row), the panel then ld x n_k
+  const int* rows;
+  int ld;
   int tile_start;
 };
 void launch_panels(const PanelTask* d_tasks, int n_tasks, int total_tiles, hipStream_t s);
@@ -434,9 +457,8 @@ struct KronRegionTask {  // per region: dR, qR, kR from S^-1 (np x np)
 };
 void launch_kron_region(const KronRegionTask* d_tasks, int n_tasks, int total_tiles,
                         hipStream_t s);
-// mode 0: Z = S^-1[:, a_o] (np x nc); mode 1: C (nc x nc) from Z;
-// mode 2: rows a_j (j < nc) of the TA columns of inv (leading dimension np)
-// into out (nc x TA), zero where a_j = -1
+// mode 0: Z = S^-1[:, a_o] (np x nc), zero columns where a_o = -1;
+// mode 1: C (nc x nc) from Z
 struct KronBuildTask {
   int mode;
   const double* inv;

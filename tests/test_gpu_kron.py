@@ -150,11 +150,39 @@ def test_spectral_sampler_matches_exact_solve(case):
     gm.close()
 
 
-def test_spectral_gemm_route():
-    """Grid sides that are multiples of 16 (>= 64) take the matrix-core DCT
-    route; the sampler must reach the tolerance with a true residual below it."""
+@pytest.mark.parametrize("mx,my,routes", [(64, 64, ("fft", "gemm", "direct")),
+                                           (128, 32, ("fft", "direct")),
+                                           (32, 32, ("fft", "direct"))])
+def test_spectral_transform_routes_agree(monkeypatch, mx, my, routes):
+    """The three DCT routes of the spectral preconditioner (FFT, matrix-core
+    GEMM, direct kernel) give the same M^-1 b: after one PCG iteration the
+    sampler returns x_1 = alpha M^-1 b, compared across routes."""
+    wl = Workload(name="r", m=mx, T=5, range_=0.2, rho=0.9, tau=1.0, sigma=0.5, obs_frac=0.2,
+                  n_tslabs=1, n_tiles=1, n_l=0, n_k=0, rtol=1e-12, mask_seed=51, z_seed=52)
+    xs = {}
+    for r in routes:
+        monkeypatch.setenv("RBMC_SPEC_ROUTE", r)
+        gm = B.Model(wl, shape=(mx, my))
+        z = normals((9, gm.n + gm.n_obs), 53)
+        x, st, rep = gm.sample(dev(z), rtol=1e-14, maxit=1, precond=B.RBMC_PC_SPECTRAL)
+        assert st in (B.RBMC_OK, B.RBMC_W_NOT_CONVERGED)
+        xs[r] = x.cpu().numpy()
+        gm.close()
+    ref = xs[routes[-1]]
+    for r in routes[:-1]:
+        err = np.abs(xs[r] - ref).max() / np.abs(ref).max()
+        say(f"route {r} vs {routes[-1]} at {mx}x{my}: {err:.3e}")
+        assert err < 1e-12
+
+
+@pytest.mark.parametrize("route", ["fft", "gemm"])
+def test_spectral_sampler_routes_converge(monkeypatch, route):
+    """On a 64 x 64 grid both the FFT and the matrix-core DCT routes are
+    available; the sampler must reach the tolerance with a true residual
+    below it on either."""
+    monkeypatch.setenv("RBMC_SPEC_ROUTE", route)
     wl = wl_of(64, 6, 2, 1, 1, range_=0.2, rho=0.95, frac=0.2)
-    say("spectral gemm route 64x64x6")
+    say(f"spectral {route} route 64x64x6")
     M = O.OracleModel.from_workload(wl)
     z = normals((20, M.n + M.n_obs), 32)
     gm = B.Model(wl)
