@@ -404,13 +404,19 @@ rbmc_status rbmc_plan_query(const rbmc_model_desc* desc, const rbmc_decomp_desc*
  *   RBMC_KF_OFFDIAG      off-diagonal time-block entries on the stencil
  *                        pattern of the core rows (13 dot products per row);
  *                        bytes = 16 n_b^2 per block pair (each read once);
- *   RBMC_KF_DCT          the 2-D DCT-II transforms of the spectral
- *                        preconditioner run as matrix-core products;
- *                        flops = 2 m per entry and axis;
+ *   RBMC_KF_DCT          the 2-D DCT-II/III transforms of the spectral
+ *                        preconditioner, one axis per launch: by FFT (grid
+ *                        sides powers of two; bytes = 16 per entry, read and
+ *                        write) or as matrix-core products (flops = 2 m per
+ *                        entry);
  *   RBMC_KF_KRON_REDUCE  group sums of the Kronecker form (k_kron_reduce);
  *                        bytes = 24 per entry of X_g (X_g, Z, K_R Z read once);
  *   RBMC_KF_SPEC_SOLVE   per-frequency tridiagonal solves of the spectral
- *                        preconditioner; bytes = 16 per entry (read, write).
+ *                        preconditioner; bytes = 16 per entry (read, write);
+ *   RBMC_KF_MC           Monte Carlo sums of the correction panels (k_mc);
+ *                        bytes = 8 per entry of mu_t (each panel read once);
+ *   RBMC_KF_TMIX         time mixing of stacked panels (k_kron_tmix); bytes =
+ *                        16 per entry and step (24 when it adds a panel).
  * rbmc_ctx_profile(ctx, 1) clears and enables, (ctx, 0) disables;
  * rbmc_ctx_profile_read synchronizes the stream and sums the records. */
 enum {
@@ -426,7 +432,9 @@ enum {
   RBMC_KF_DCT = 9,
   RBMC_KF_KRON_REDUCE = 10,
   RBMC_KF_SPEC_SOLVE = 11,
-  RBMC_KF_COUNT = 12
+  RBMC_KF_MC = 12,
+  RBMC_KF_TMIX = 13,
+  RBMC_KF_COUNT = 14
 };
 typedef struct {
   int64_t launches;

@@ -34,9 +34,9 @@ RBMC_PC_NWEIGHTS = 15120
 PC_LAYERS = [(2, 16), (16, 16), (16, 16), (16, 1)]
 (RBMC_KF_GEMM, RBMC_KF_SPD_INVERSE, RBMC_KF_SPMM, RBMC_KF_RSTENCIL, RBMC_KF_PANELS,
  RBMC_KF_GEMM_MIXED, RBMC_KF_GEMM_SMALL, RBMC_KF_INV_SMALL, RBMC_KF_OFFDIAG, RBMC_KF_DCT,
- RBMC_KF_KRON_REDUCE, RBMC_KF_SPEC_SOLVE, RBMC_KF_COUNT) = range(13)
+ RBMC_KF_KRON_REDUCE, RBMC_KF_SPEC_SOLVE, RBMC_KF_MC, RBMC_KF_TMIX, RBMC_KF_COUNT) = range(15)
 KF_NAMES = ["gemm", "spd_inverse", "spmm", "rstencil", "panels", "gemm_mixed", "gemm_small",
-            "inv_small", "offdiag", "dct", "kron_reduce", "spec_solve"]
+            "inv_small", "offdiag", "dct", "kron_reduce", "spec_solve", "mc", "tmix"]
 
 
 class rbmc_kernel_stats(C.Structure):

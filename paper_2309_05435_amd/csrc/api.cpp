@@ -812,6 +812,8 @@ struct Program {
     o.off = a.push(e.v);
     o.n = (int)e.v.size();
     o.tiles = e.tiles;
+    o.family = RBMC_KF_MC;
+    o.alg_bytes = e.bytes;
     ops.push_back(o);
   }
   void offdiag(Arena& a, TileList<OffdiagTask>& t) {
@@ -2110,7 +2112,7 @@ rbmc_status estimate_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const
         k.scale = 1.0 / nk;
         k.accum = 0;
         k.t = ch.t0 + t;
-        mt.add(k, cs.np[c] / 64);
+        mt.add(k, cs.np[c] / 64, 8.0 * cs.nb[c] * nk);
       }
     }
     cor.mc(ar, mt);
@@ -3160,7 +3162,7 @@ rbmc_status kron_corr_batch(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, co
     mx.TA = k.TA;
     mx.alpha = 1.0;
     mx.beta = 0.0;
-    m1.add(mx, kron_mix_tiles(R.np, nk));
+    m1.add(mx, kron_mix_tiles(R.np, nk), 16.0 * R.nb * nk * k.TA);
     KronObsTask ot{};
     ot.U = b.Rb;
     ot.v = b.v;
@@ -3181,7 +3183,7 @@ rbmc_status kron_corr_batch(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, co
     mx.out = b.Rb;
     mx.alpha = -1.0;
     mx.beta = 1.0;
-    m2.add(mx, kron_mix_tiles(R.np, nk));
+    m2.add(mx, kron_mix_tiles(R.np, nk), 24.0 * R.nb * nk * k.TA);
     const size_t c = lidx[i];
     for (int t = ch.ct0 - ch.t0; t < ch.ct0 - ch.t0 + ch.cT; ++t) {
       McTask q{};
@@ -3198,13 +3200,13 @@ rbmc_status kron_corr_batch(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, co
       q.scale = scale;
       q.accum = accum;
       q.t = ch.t0 + t;
-      mt.add(q, R.np / 64);
+      mt.add(q, R.np / 64, 8.0 * R.nb * nk);
     }
   }
   pg.panels(ar, rt);
   for (const auto& z : uz) pg.fill(z.first, z.second);
   pg.gemm(ar, gu);
-  pg.kron(ar, 18, m1);
+  pg.kron(ar, 18, m1, RBMC_KF_TMIX);
   pg.kron(ar, 19, ob);
   pg.gemm(ar, gw);
   for (size_t i = i0; i < i1; ++i) {
@@ -3214,7 +3216,7 @@ rbmc_status kron_corr_batch(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, co
     pg.fill(kb[i - i0].Ub, (size_t)R.np * k.TA * nk);
   }
   pg.gemm(ar, gz);
-  pg.kron(ar, 18, m2);
+  pg.kron(ar, 18, m2, RBMC_KF_TMIX);
   pg.mc(ar, mt);
   HIPCHK(ar.upload(s));
   rbmc_status st = run(cx, pg, s, ar);
