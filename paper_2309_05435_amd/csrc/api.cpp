@@ -173,6 +173,8 @@ struct rbmc_ctx {
   size_t kws_cap = 0;
   size_t kron_batch_cap = 0;  // upper bound of a batch's workspace (0: free memory)
   Pool kbank;  // Y of every subdomain and the deterministic diagonals, kept across sample passes
+  char* kbank_base = nullptr;
+  size_t kbank_cap = 0;
   // scheduling of rbmc_estimate*: overlap the sampler with the subdomain
   // factorization + core steps on further streams (else one after the
   // other on the context stream), and enqueue the two streams from two host
@@ -228,6 +230,8 @@ struct rbmc_ctx {
     epool.release();
     kws.release();
     kbank.release();
+    kbank_base = nullptr;
+    kbank_cap = 0;
   }
 };
 
@@ -1847,7 +1851,7 @@ struct EstLayout {
     mc_base.assign(n + 1, 0);
     for (size_t c = 0; c < n; ++c) {
       det_base[c + 1] = det_base[c] + (size_t)ch[c].T * 3 * nchk(c);
-      mc_base[c + 1] = mc_base[c] + (size_t)ch[c].T * (np[c] / 64);
+      mc_base[c + 1] = mc_base[c] + (size_t)ch[c].T * mc_chunks(np[c]);
     }
     det_len = det_base[n] * 3;
     mc_len = mc_base[n] * 8;
@@ -1856,7 +1860,7 @@ struct EstLayout {
   size_t det_index(size_t c, int t, int sl) const {
     return det_base[c] + ((size_t)t * 3 + sl) * nchk(c);
   }
-  size_t mc_index(size_t c, int t) const { return mc_base[c] + (size_t)t * (np[c] / 64); }
+  size_t mc_index(size_t c, int t) const { return mc_base[c] + (size_t)t * mc_chunks(np[c]); }
 };
 
 // Device partial sums of a layout (the context's estimator buffer).
@@ -1888,7 +1892,7 @@ rbmc_status combine_traces(rbmc_ctx* cx, const EstLayout& L, const std::vector<r
   for (size_t c = 0; c < L.ch.size(); ++c) {
     const Chain& ch = L.ch[c];
     const Coefs& co = L.owner[c]->co;
-    const size_t nchk = L.nchk(c), mchk = L.np[c] / 64;
+    const size_t nchk = L.nchk(c), mchk = mc_chunks(L.np[c]);
     const int lc0 = ch.ct0 - ch.t0, lc1 = lc0 + ch.cT - 1;
     for (int t = lc0; t <= lc1; ++t) {
       const int tg = ch.t0 + t;
@@ -2112,7 +2116,7 @@ rbmc_status estimate_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const
         k.scale = 1.0 / nk;
         k.accum = 0;
         k.t = ch.t0 + t;
-        mt.add(k, cs.np[c] / 64, 8.0 * cs.nb[c] * nk);
+        mt.add(k, mc_chunks(cs.np[c]), 8.0 * cs.nb[c] * nk);
       }
     }
     cor.mc(ar, mt);
@@ -3200,7 +3204,7 @@ rbmc_status kron_corr_batch(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, co
       q.scale = scale;
       q.accum = accum;
       q.t = ch.t0 + t;
-      mt.add(q, R.np / 64, 8.0 * R.nb * nk);
+      mt.add(q, mc_chunks(R.np), 8.0 * R.nb * nk);
     }
   }
   pg.panels(ar, rt);
@@ -3306,19 +3310,23 @@ rbmc_status estimate_set_kron(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms,
   // several passes: Y of every subdomain and the deterministic diagonals in the bank
   std::vector<double*> ybank(refs.size(), nullptr), ddet(ms.size(), nullptr);
   if (npass > 1) {
-    cx->kws.release();  // the bank first; batches take what is left
-    cx->kws_base = nullptr;
-    cx->kws_cap = 0;
     size_t need = 0;
     for (const auto& r : refs) {
       const size_t nc = ms[r.first]->ksub[r.second].nc;
       need += nc * nc * 8 + 256;
     }
     for (rbmc_model* m : ms) need += (size_t)m->plan.n * 8 + 256;
-    cx->kbank.release();
-    char* base = nullptr;
-    HIPCHK(cx->kbank.alloc((void**)&base, need));
-    Carve cb{base, 0};
+    if (cx->kbank_cap < need) {  // a larger bank: it comes first, batches take what is left
+      cx->kws.release();
+      cx->kws_base = nullptr;
+      cx->kws_cap = 0;
+      cx->kbank.release();
+      cx->kbank_base = nullptr;
+      cx->kbank_cap = 0;
+      HIPCHK(cx->kbank.alloc((void**)&cx->kbank_base, need));
+      cx->kbank_cap = need;
+    }
+    Carve cb{cx->kbank_base, 0};
     for (size_t i = 0; i < refs.size(); ++i) {
       const size_t nc = ms[refs[i].first]->ksub[refs[i].second].nc;
       ybank[i] = cb.d(nc * nc);

@@ -309,70 +309,121 @@ void launch_offdiag(const OffdiagTask* d_tasks, int n_tasks, int total_tiles, hi
 }
 
 // ---------------------------------------------------------------------------
-// Monte Carlo part. Workgroup = 64 region rows x all samples (4 sample lanes
-// per row).  Outputs: diag on core rows and 8 partial sums per workgroup:
+// Monte Carlo part.  Workgroup = 256 region rows, one per thread, looping over
+// the samples.  The rows of mu_{t-1}, mu_t, mu_{t+1} that the workgroup's
+// stencils reach form a window [w0, w1] of region rows; for groups of
+// samples the three windows are staged in LDS (coalesced loads, each entry
+// once) and the 3 x 13 neighbour reads come from LDS.  Windows that do not
+// fit (very wide regions) are read from global memory directly.
+// Outputs: diag on core rows and 8 partial sums per workgroup:
 //   [0..2] mu_t . (Q_s mu_{t-1,t,t+1}), [3..5] mu_t . (K mu_{t-1,t,t+1}),
 //   [6] sum D mu_t^2 (all divided by n_k), [7] sum of m_a / s2_a.
 // ---------------------------------------------------------------------------
+namespace {
+constexpr int kMcLds = 4096;  // doubles of staged windows
+}
+
 __global__ __launch_bounds__(256) void k_mc(const McTask* __restrict__ tasks, int n_tasks) {
   __shared__ double red[8][256];
+  __shared__ double win[kMcLds];
+  __shared__ int span[2];
   const int b = blockIdx.x;
   const McTask tk = tasks[find_task_of(tasks, n_tasks, b)];
   const RegionDev rg = *tk.rg;
   const DevModel& m = *tk.dm;
   const int n_k = tk.n_k;
   const int chunk = b - tk.tile_start;
-  const int a = chunk * 64 + (threadIdx.x & 63);
-  const int ks = threadIdx.x >> 6;
+  const int a = chunk * 256 + threadIdx.x;
   const bool mine = a < rg.nb && G(rg.in_box)[a];
   double acc[8];
 #pragma unroll
   for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+  int nbr[kNS];
+  double cq[kNS], ck[kN5];
+  double dv = 0.0;
+  int lo = INT_MAX, hi = -1;
   if (mine) {
     const int node = G(rg.nodes)[a];
-    const size_t i = (size_t)tk.t * m.ns + node;
-    const double dv = G(m.dvec)[i];
-    int nbr[kNS];
-    double cq[kNS], ck[kN5];
+    dv = G(m.dvec)[(size_t)tk.t * m.ns + node];
 #pragma unroll
     for (int q = 0; q < kNS; ++q) {
       nbr[q] = G(rg.nbr)[a * kNS + q];
       cq[q] = G(m.qs)[(size_t)q * m.ns + node];
       if (q < kN5) ck[q] = G(m.kk)[(size_t)q * m.ns + node];
-    }
-    for (int k = ks; k < n_k; k += 4) {
-      const size_t off = (size_t)k * tk.np;
-      const double mu = tk.mu[1][off + a];
-      acc[7] += mu * mu;
-      acc[6] += dv * mu * mu;
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const double* pm = tk.mu[d];
-        if (!pm) continue;
-        double vq = 0.0, vk = 0.0;
-#pragma unroll
-        for (int q = 0; q < kNS; ++q) {
-          if (nbr[q] < 0) continue;
-          const double y = pm[off + nbr[q]];
-          vq += cq[q] * y;
-          if (q < kN5) vk += ck[q] * y;
-        }
-        acc[d] += mu * vq;
-        acc[3 + d] += mu * vk;
+      if (nbr[q] >= 0) {
+        lo = min(lo, nbr[q]);
+        hi = max(hi, nbr[q]);
       }
     }
   }
+  if (threadIdx.x == 0) {
+    span[0] = INT_MAX;
+    span[1] = -1;
+  }
+  __syncthreads();
+  if (mine) {
+    atomicMin(&span[0], lo);
+    atomicMax(&span[1], hi);
+  }
+  __syncthreads();
+  const int w0 = span[0], wn = span[1] >= span[0] ? span[1] - span[0] + 1 : 0;
+  const int sk = wn > 0 ? min(4, kMcLds / (3 * wn)) : 0;
+  // one sample: mu = mu_t[a]; Y(d, row) reads row of panel d (zero for a
+  // panel outside the chain)
+#define RBMC_MC_SAMPLE(MU, Y)                           \
+  {                                                     \
+    const double mu_ = (MU);                            \
+    acc[7] += mu_ * mu_;                                \
+    acc[6] += dv * mu_ * mu_;                           \
+    _Pragma("unroll") for (int d = 0; d < 3; ++d) {     \
+      double vq = 0.0, vk = 0.0;                        \
+      _Pragma("unroll") for (int q = 0; q < kNS; ++q) { \
+        if (nbr[q] < 0) continue;                       \
+        const double y = Y(d, nbr[q]);                  \
+        vq += cq[q] * y;                                \
+        if (q < kN5) vk += ck[q] * y;                   \
+      }                                                 \
+      acc[d] += mu_ * vq;                               \
+      acc[3 + d] += mu_ * vk;                           \
+    }                                                   \
+  }
+  if (sk > 0) {
+    for (int k0 = 0; k0 < n_k; k0 += sk) {
+      const int kc = min(sk, n_k - k0);
+      for (int e = threadIdx.x; e < kc * 3 * wn; e += 256) {
+        const int r = e % wn, jd = e / wn, d = jd % 3, j = jd / 3;
+        // a select, not tk.mu[d]: a run-time index would put the task in scratch
+        const double* pm = d == 0 ? tk.mu[0] : d == 1 ? tk.mu[1] : tk.mu[2];
+        win[e] = pm ? G(pm)[(size_t)(k0 + j) * tk.np + w0 + r] : 0.0;
+      }
+      __syncthreads();
+      if (mine)
+        for (int j = 0; j < kc; ++j) {
+          const int wj = j * 3 * wn - w0;
+#define RBMC_MC_LDS(d, row) win[wj + (d) * wn + (row)]
+          RBMC_MC_SAMPLE(win[wj + wn + a], RBMC_MC_LDS)
+#undef RBMC_MC_LDS
+        }
+      __syncthreads();
+    }
+  } else if (mine) {
+    for (int k = 0; k < n_k; ++k) {
+      const size_t off = (size_t)k * tk.np;
+#define RBMC_MC_GLOBAL(d, row) (tk.mu[d] ? G(tk.mu[d])[off + (row)] : 0.0)
+      RBMC_MC_SAMPLE(G(tk.mu[1])[off + a], RBMC_MC_GLOBAL)
+#undef RBMC_MC_GLOBAL
+    }
+  }
+#undef RBMC_MC_SAMPLE
 #pragma unroll
   for (int c = 0; c < 8; ++c) red[c][threadIdx.x] = acc[c];
   __syncthreads();
-  // diagonal: combine the 4 sample lanes of each row in a fixed order; the
-  // ratio m_a / s2_a (MC part over estimate) feeds the plug-in error estimate
+  // diagonal; the ratio m_a / s2_a (MC part over estimate) feeds the plug-in
+  // error estimate
   double ratio = 0.0;
-  if (threadIdx.x < 64 && mine) {
-    const double s = (red[7][threadIdx.x] + red[7][threadIdx.x + 64]) +
-                     (red[7][threadIdx.x + 128] + red[7][threadIdx.x + 192]);
+  if (mine) {
     const size_t i = (size_t)tk.t * m.ns + G(rg.nodes)[a];
-    const double mhat = s * tk.scale;
+    const double mhat = red[7][threadIdx.x] * tk.scale;
     const double est = G(tk.diag_out)[i] + mhat;
     G(tk.diag_out)[i] = est;
     ratio = est > 0.0 ? mhat / est : 0.0;

@@ -350,8 +350,10 @@ void launch_offdiag(const OffdiagTask* d_tasks, int n_tasks, int total_tiles, hi
 //   partial sums of scale sum_k mu_t[a,k] (S mu_t')[a,k] for t' = t-1, t, t+1,
 //   S in {Q_s, K}, of scale sum_k D_a mu_t[a,k]^2 and of m_a / s2_a (the last
 //   meaningful only for a one-pass estimate).
-// Partial sums of chunk c go to partial[(out_index + c) * 8 + j] (added to the
-// previous value when accum is set).
+// Partial sums of chunk c (region rows [256 c, 256 c + 256)) go to
+// partial[(out_index + c) * 8 + j] (added to the previous value when accum
+// is set); a task spans mc_chunks(np) chunks.
+inline int mc_chunks(int np) { return (np + 255) / 256; }
 struct McTask {
   const double* mu[3];  // panels for t-1, t, t+1 (null if outside the chain)
   double scale;         // 1 / (total samples of the estimate)
