@@ -2910,15 +2910,6 @@ struct KronBuf {
   InvJob inv;
 };
 
-// Steps [ra, rb) of a subdomain's chain see no time separator: there r is
-// nonzero on the rim of R only.  The rest (at most the first and the last
-// step) take the dense product with S^-1.
-std::pair<int, int> kron_rim_steps(const rbmc_model* m, const Chain& ch) {
-  const int ra = ch.t0 > 0 ? 1 : 0;
-  const int rb = ch.t0 + ch.T < m->plan.T ? ch.T - 1 : ch.T;
-  return {ra, std::max(ra, rb)};
-}
-
 // The subdomains of a set, in order: (model index, subdomain index).
 std::vector<std::pair<int, int>> kron_refs(const std::vector<rbmc_model*>& ms) {
   std::vector<std::pair<int, int>> r;
@@ -3105,6 +3096,7 @@ rbmc_status kron_corr_batch(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, co
     pg.kron(ar, 15, zt);
   }
   TileList<PanelTask> rt;
+  TileList<PanelTask> bt[2];                        // separator terms (first, last step)
   std::vector<std::pair<double*, size_t>> uz;       // U blocks that are zero (empty rim)
   GemmList gu, gw, gz;
   gu.mixed = gw.mixed = gz.mixed = mixed;
@@ -3119,42 +3111,64 @@ rbmc_status kron_corr_batch(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, co
     const rbmc_model::KronReg& R = m->kreg[m->kreg_of[ch.region]];
     const KronBuf& b = kb[i - i0];
     const size_t panel = (size_t)R.np * nk;
-    // steps [rim.first, rim.second) see no time separator: r lives on the rim
-    // of R there, and its panel holds the rim rows only (nrp x n_k, in Rc)
-    const std::pair<int, int> rim = R.rim ? kron_rim_steps(m, ch) : std::make_pair(0, 0);
-    for (int t = 0; t < k.TA; ++t) {  // r = Q_AB x_B, one panel per step
-      const bool on_rim = t >= rim.first && t < rim.second;
-      if (on_rim && R.nring == 0) continue;  // r = 0
-      PanelTask pt{};
-      pt.P = on_rim ? b.Rc + (size_t)(t - rim.first) * R.nrp * nk : b.Rb + (size_t)t * panel;
-      pt.rg = m->d_regions + ch.region;
-      pt.dm = m->d_dm;
-      pt.X = x_base + h.base[j];
-      pt.n_k = nk;
-      pt.t = ch.t0 + t;
-      pt.t0 = ch.t0;
-      pt.T = ch.T;
-      pt.mode = 2;
-      pt.rows = on_rim ? R.d_ring : nullptr;
-      pt.ld = on_rim ? R.nrp : R.np;
-      rt.add(pt, panel_tiles(pt.ld, nk), 8.0 * (on_rim ? R.nring : R.nb) * nk * 2);
-    }
-    // U = S^-1 R (panels are stacked columns): steps next to the time
-    // separator against all of S^-1, the others against its rim columns
-    for (const std::pair<int, int>& d : {std::make_pair(0, rim.first),
-                                         std::make_pair(rim.second, k.TA)})
-      if (d.second > d.first)
-        gu.add(R.inv, b.Rb + (size_t)d.first * panel, nullptr, b.Ub + (size_t)d.first * panel,
-               R.np, (d.second - d.first) * nk, R.np, R.np, R.np, R.np, 1.0, 0.0, 0, 0, R.nb,
-               R.nb);
-    if (rim.second > rim.first) {
-      const int ncol = (rim.second - rim.first) * nk;
-      if (R.nring > 0) {
-        gu.add(R.rinv, b.Rc, nullptr, b.Ub + (size_t)rim.first * panel, R.np, ncol, R.nrp, R.np,
-               R.nrp, R.np, 1.0, 0.0, 0, 0, R.nb, R.nring);
-      } else {
-        uz.push_back({b.Ub + (size_t)rim.first * panel, (size_t)R.np * ncol});
+    // U = S^-1 r, r = Q_AB x_B one panel per step (panels are stacked
+    // columns).  With the rim products: r = r~ + (Q_t)_{t,t'} S x_t'|R, where
+    // r~ (spatial neighbours outside R) lives on the rim of R and the second
+    // term appears only at a step next to the time separator (t' outside the
+    // chain), so U = S^-1[:, rim] r~|rim + (Q_t)_{t,t'} x_t'|R.
+    if (R.rim) {
+      for (int t = 0; t < k.TA && R.nring > 0; ++t) {
+        PanelTask pt{};
+        pt.P = b.Rc + (size_t)t * R.nrp * nk;
+        pt.rg = m->d_regions + ch.region;
+        pt.dm = m->d_dm;
+        pt.X = x_base + h.base[j];
+        pt.n_k = nk;
+        pt.t = ch.t0 + t;
+        pt.t0 = ch.t0;
+        pt.T = ch.T;
+        pt.mode = 3;
+        pt.rows = R.d_ring;
+        pt.ld = R.nrp;
+        rt.add(pt, panel_tiles(R.nrp, nk), 16.0 * R.nring * nk);
       }
+      if (R.nring > 0)
+        gu.add(R.rinv, b.Rc, nullptr, b.Ub, R.np, k.TA * nk, R.nrp, R.np, R.nrp, R.np, 1.0, 0.0,
+               0, 0, R.nb, R.nring);
+      else
+        uz.push_back({b.Ub, (size_t)R.np * k.TA * nk});
+      // the separator steps t0 - 1 and t0 + TA (inside the domain)
+      for (int side = 0; side < 2; ++side) {
+        const int t = side == 0 ? 0 : k.TA - 1;
+        const int tg = side == 0 ? ch.t0 - 1 : ch.t0 + k.TA;
+        if (tg < 0 || tg >= m->plan.T) continue;
+        PanelTask pt{};
+        pt.P = b.Ub + (size_t)t * panel;
+        pt.rg = m->d_regions + ch.region;
+        pt.dm = m->d_dm;
+        pt.X = x_base + h.base[j];
+        pt.n_k = nk;
+        pt.t = tg;
+        pt.mode = 4;
+        pt.w = m->co.qo;
+        bt[side].add(pt, panel_tiles(R.np, nk), 24.0 * R.nb * nk);
+      }
+    } else {
+      for (int t = 0; t < k.TA; ++t) {
+        PanelTask pt{};
+        pt.P = b.Rb + (size_t)t * panel;
+        pt.rg = m->d_regions + ch.region;
+        pt.dm = m->d_dm;
+        pt.X = x_base + h.base[j];
+        pt.n_k = nk;
+        pt.t = ch.t0 + t;
+        pt.t0 = ch.t0;
+        pt.T = ch.T;
+        pt.mode = 2;
+        rt.add(pt, panel_tiles(R.np, nk), 16.0 * R.nb * nk);
+      }
+      gu.add(R.inv, b.Rb, nullptr, b.Ub, R.np, k.TA * nk, R.np, R.np, R.np, R.np, 1.0, 0.0, 0, 0,
+             R.nb, R.nb);
     }
     KronMixTask mx{};
     mx.V = b.V;
@@ -3210,6 +3224,8 @@ rbmc_status kron_corr_batch(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, co
   pg.panels(ar, rt);
   for (const auto& z : uz) pg.fill(z.first, z.second);
   pg.gemm(ar, gu);
+  pg.panels(ar, bt[0]);  // two launches: a one-step chain takes both terms
+  pg.panels(ar, bt[1]);
   pg.kron(ar, 18, m1, RBMC_KF_TMIX);
   pg.kron(ar, 19, ob);
   pg.gemm(ar, gw);

@@ -53,9 +53,17 @@ __global__ __launch_bounds__(256) void k_panels(const PanelTask* __restrict__ ta
       if (k >= n_k) break;
       G(tk.Xout)[(size_t)k * m.n + base] = G(tk.P)[(size_t)k * rg.np + a];
     }
+  } else if (tk.mode == 4) {
+    if (!real) return;
+    for (int kk = threadIdx.x >> 6; kk < PT_K; kk += 4) {
+      const int k = kbase + kk;
+      if (k >= n_k) break;
+      G(tk.P)[(size_t)k * rg.np + a] += tk.w * G(tk.X)[(size_t)k * m.n + base];
+    }
   } else {
-    // r_a = sum over neighbours j of (t, node) outside A = [t0, t0+T) x R of
-    // Q_aj x_j; row a of the panel is region row ar (the row list, or a)
+    // mode 2: r_a = sum over neighbours j of (t, node) outside A = [t0, t0+T)
+    // x R of Q_aj x_j; mode 3: over the neighbours whose node is outside R;
+    // row a of the panel is region row ar (the row list, or a)
     const int ar = tk.rows ? G(tk.rows)[a] : (real ? a : -1);
     const int ld = tk.rows ? tk.ld : rg.np;
     const int nd = ar >= 0 ? G(rg.nodes)[ar] : 0;
@@ -73,7 +81,7 @@ __global__ __launch_bounds__(256) void k_panels(const PanelTask* __restrict__ ta
       for (int q = 0; q < kNS; ++q) {
         const int jx = ix + kSdx[q], jy = iy + kSdy[q];
         const bool ok = t_ok && jx >= 0 && jx < m.mx && jy >= 0 && jy < m.my &&
-                        !(t_in && G(rg.nbr)[ar * kNS + q] >= 0);
+                        !((t_in || tk.mode == 3) && G(rg.nbr)[ar * kNS + q] >= 0);
         cf[d][q] = ok ? wt * G(m.qs)[(size_t)q * m.ns + nd] : 0.0;
       }
     }

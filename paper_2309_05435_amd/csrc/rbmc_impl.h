@@ -294,12 +294,16 @@ struct PanelTask {
   double* Xout;      // destination multi-vector (mode 1)
   int n_k;
   int t;        // global time step of the block
-  int t0, T;    // chain time range (mode 2)
+  int t0, T;    // chain time range (modes 2, 3)
+  // mode 0: P = X at step t (gather); 1: Xout = P (scatter); 2: P = Q_AB x_B
+  // at step t of the chain [t0, t0 + T) x R; 3: its part from spatial
+  // neighbours outside R (any step); 4: P += w X at step t (gather, add)
   int mode;
-  // mode 2: rows (nullptr: all np rows of R, panel leading dimension np) or a
-  // list of ld region rows (-1: a zero row), the panel then ld x n_k
+  // modes 2, 3: rows (nullptr: all np rows of R, panel leading dimension np)
+  // or a list of ld region rows (-1: a zero row), the panel then ld x n_k
   const int* rows;
   int ld;
+  double w;     // mode 4
   int tile_start;
 };
 void launch_panels(const PanelTask* d_tasks, int n_tasks, int total_tiles, hipStream_t s);
