@@ -14,8 +14,8 @@
 // their spectra are separated by the Hermitian symmetry of each.
 //
 // Workgroup: 256 threads and 2048 complex values in LDS, i.e. P = 2048 / N
-// line pairs, plus the N/2 twiddles; radix-2 decimation in time on
-// bit-reversed input, in place.
+// line pairs, plus the N/2 twiddles; decimation in time on bit-reversed
+// input, in place, in radix-4 steps (and one radix-2 step when log2 N is odd).
 #include "rbmc_impl.h"
 
 namespace rbmc {
@@ -104,13 +104,46 @@ __global__ __launch_bounds__(kFftThreads) void k_dct_fft(const FftTask* __restri
   }
   __syncthreads();
   const double sgn = tk.inverse ? -1.0 : 1.0;  // twiddles exp(-+2 pi i j / N)
-  for (int h = 1, lh = 0; h < N; h <<= 1, ++lh) {
-    const int step = N >> (lh + 1);  // N / 2h
-    for (int u = threadIdx.x; u < P * (N >> 1); u += kFftThreads) {
-      const int p = u / (N >> 1), b = u % (N >> 1);
+  // radix-4 steps: the radix-2 stages h and 2h at once on the four entries
+  // i0 + {0, h, 2h, 3h} of a block of 4h (j = i0 mod h):
+  //   b0,1 = a0 +- w1 a1, b2,3 = a2 +- w1 a3             (w1 = W_2h^j)
+  //   c0,2 = b0 +- w2 b2, c1,3 = b1 +- w3 b3   (w2 = W_4h^j, w3 = -+i w2)
+  int h = 1, lh = 0;
+  for (; 4 * h <= N; h <<= 2, lh += 2) {
+    for (int u = threadIdx.x; u < P * (N >> 2); u += kFftThreads) {
+      const int p = u / (N >> 2), b = u % (N >> 2);
       const int j = b & (h - 1);
-      const int i0 = p * N + ((b >> lh) << (lh + 1)) + j, i1 = i0 + h;
-      const double wr = twl[2 * (j * step)], wi = -sgn * twl[2 * (j * step) + 1];
+      const int i0 = p * N + ((b >> lh) << (lh + 2)) + j;
+      const int t1 = j * (N >> (lh + 1)), t2 = j * (N >> (lh + 2));
+      const double w1r = twl[2 * t1], w1i = -sgn * twl[2 * t1 + 1];
+      const double w2r = twl[2 * t2], w2i = -sgn * twl[2 * t2 + 1];
+      const double w3r = sgn * w2i, w3i = -sgn * w2r;  // -+i w2
+      const double a0r = zr[i0], a0i = zi[i0];
+      const double a1r = zr[i0 + h], a1i = zi[i0 + h];
+      const double a2r = zr[i0 + 2 * h], a2i = zi[i0 + 2 * h];
+      const double a3r = zr[i0 + 3 * h], a3i = zi[i0 + 3 * h];
+      const double m1r = w1r * a1r - w1i * a1i, m1i = w1r * a1i + w1i * a1r;
+      const double m3r = w1r * a3r - w1i * a3i, m3i = w1r * a3i + w1i * a3r;
+      const double b0r = a0r + m1r, b0i = a0i + m1i, b1r = a0r - m1r, b1i = a0i - m1i;
+      const double b2r = a2r + m3r, b2i = a2i + m3i, b3r = a2r - m3r, b3i = a2i - m3i;
+      const double n2r = w2r * b2r - w2i * b2i, n2i = w2r * b2i + w2i * b2r;
+      const double n3r = w3r * b3r - w3i * b3i, n3i = w3r * b3i + w3i * b3r;
+      zr[i0] = b0r + n2r;
+      zi[i0] = b0i + n2i;
+      zr[i0 + 2 * h] = b0r - n2r;
+      zi[i0 + 2 * h] = b0i - n2i;
+      zr[i0 + h] = b1r + n3r;
+      zi[i0 + h] = b1i + n3i;
+      zr[i0 + 3 * h] = b1r - n3r;
+      zi[i0 + 3 * h] = b1i - n3i;
+    }
+    __syncthreads();
+  }
+  if (h < N) {  // log2 N odd: one radix-2 stage (h = N / 2)
+    for (int u = threadIdx.x; u < P * (N >> 1); u += kFftThreads) {
+      const int p = u / (N >> 1), j = u % (N >> 1);
+      const int i0 = p * N + j, i1 = i0 + h;
+      const double wr = twl[2 * j], wi = -sgn * twl[2 * j + 1];
       const double ar = zr[i1], ai = zi[i1];
       const double tr = wr * ar - wi * ai, ti = wr * ai + wi * ar;
       const double br = zr[i0], bi = zi[i0];

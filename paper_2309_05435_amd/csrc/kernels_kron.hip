@@ -253,24 +253,43 @@ void launch_kron_det(const KronDetTask* d_tasks, int n_tasks, int total_tiles, h
 // are held in registers, so for TA <= kMix every input entry is read once.
 // ---------------------------------------------------------------------------
 constexpr int kMix = 24;
+constexpr int kMixV = 64;  // chains up to this many steps read V from LDS
 
 __global__ __launch_bounds__(256) void k_kron_tmix(const KronMixTask* __restrict__ tasks,
                                                    int n_tasks) {
+  __shared__ double vs[kMix * kMixV];  // rows t0 .. t0 + kMix of V, zero beyond TA
   const KronMixTask tk = tasks[kfind(tasks, n_tasks, blockIdx.x)];
   const size_t e = (size_t)(blockIdx.x - tk.tile_start) * 256 + threadIdx.x;
   const size_t panel = (size_t)tk.np * tk.n_k;
-  if (e >= panel) return;
   const int TA = tk.TA;
   const gptr<const double> V = G(tk.V), U = G(tk.U);
+  const bool lds = TA <= kMixV;
   for (int t0 = 0; t0 < TA; t0 += kMix) {
+    if (lds) {
+      __syncthreads();
+      for (int q = threadIdx.x; q < kMix * TA; q += 256) {
+        const int j = q / TA, tp = q % TA;
+        vs[q] = t0 + j < TA ? V[(t0 + j) * TA + tp] : 0.0;
+      }
+      __syncthreads();
+    }
+    if (e >= panel) continue;
     double acc[kMix];
 #pragma unroll
     for (int j = 0; j < kMix; ++j) acc[j] = 0.0;
-    for (int tp = 0; tp < TA; ++tp) {
-      const double u = U[(size_t)tp * panel + e];
+    if (lds) {
+      for (int tp = 0; tp < TA; ++tp) {
+        const double u = U[(size_t)tp * panel + e];
 #pragma unroll
-      for (int j = 0; j < kMix; ++j)
-        if (t0 + j < TA) acc[j] = fma(V[(t0 + j) * TA + tp], u, acc[j]);
+        for (int j = 0; j < kMix; ++j) acc[j] = fma(vs[j * TA + tp], u, acc[j]);
+      }
+    } else {
+      for (int tp = 0; tp < TA; ++tp) {
+        const double u = U[(size_t)tp * panel + e];
+#pragma unroll
+        for (int j = 0; j < kMix; ++j)
+          if (t0 + j < TA) acc[j] = fma(V[(t0 + j) * TA + tp], u, acc[j]);
+      }
     }
 #pragma unroll
     for (int j = 0; j < kMix; ++j) {

@@ -398,24 +398,59 @@ void launch_spec_coef(const SpecCoefTask& t, hipStream_t s) {
   if (t.ns > 0) k_spec_coef<<<(t.ns + 255) / 256, 256, 0, s>>>(t);
 }
 
-// grid (frequency blocks of the largest model, columns)
+// grid (frequency blocks of the largest model, columns).  The walk in time
+// goes in chunks of kSpecCh steps: the chunk's loads are issued together,
+// then the recurrence runs in registers and the chunk is stored.
+namespace {
+constexpr int kSpecCh = 8;
+}
+
 __global__ __launch_bounds__(256) void k_spec_solve(ColSet cs, double* __restrict__ y) {
   const int col = blockIdx.y;
   const DevModel& m = cs.dms[cs.model[col]];
   const int f = blockIdx.x * 256 + threadIdx.x;
   if (f >= m.ns || m.sp_cp == nullptr) return;
-  double* yk = y + cs.off[col];
+  const gptr<double> yk = G(y + cs.off[col]);
+  const gptr<const double> id = G((const double*)m.sp_id), cp = G((const double*)m.sp_cp);
   const double a = m.sp_off[f];
-  double prev = 0.0;
-  for (int t = 0; t < m.T; ++t) {
-    const size_t i = (size_t)t * m.ns + f;
-    prev = (yk[i] - a * prev) * m.sp_id[i];
-    yk[i] = prev;
+  const int T = m.T;
+  const size_t ns = m.ns;
+  double prev = 0.0, v[kSpecCh], c[kSpecCh];
+  for (int t0 = 0; t0 < T; t0 += kSpecCh) {  // forward elimination
+#pragma unroll
+    for (int j = 0; j < kSpecCh; ++j)
+      if (t0 + j < T) {
+        v[j] = yk[(t0 + j) * ns + f];
+        c[j] = id[(t0 + j) * ns + f];
+      }
+#pragma unroll
+    for (int j = 0; j < kSpecCh; ++j)
+      if (t0 + j < T) {
+        prev = (v[j] - a * prev) * c[j];
+        v[j] = prev;
+      }
+#pragma unroll
+    for (int j = 0; j < kSpecCh; ++j)
+      if (t0 + j < T) yk[(t0 + j) * ns + f] = v[j];
   }
-  for (int t = m.T - 2; t >= 0; --t) {
-    const size_t i = (size_t)t * m.ns + f;
-    prev = yk[i] - m.sp_cp[i] * prev;
-    yk[i] = prev;
+  for (int t1 = T - 1; t1 > 0; t1 -= kSpecCh) {  // back substitution, steps t1 - 1 down
+#pragma unroll
+    for (int j = 0; j < kSpecCh; ++j) {
+      const int t = t1 - 1 - j;
+      if (t >= 0) {
+        v[j] = yk[t * ns + f];
+        c[j] = cp[t * ns + f];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kSpecCh; ++j)
+      if (t1 - 1 - j >= 0) {
+        prev = v[j] - c[j] * prev;
+        v[j] = prev;
+      }
+#pragma unroll
+    for (int j = 0; j < kSpecCh; ++j)
+      if (t1 - 1 - j >= 0) yk[(t1 - 1 - j) * ns + f] = v[j];
   }
 }
 
