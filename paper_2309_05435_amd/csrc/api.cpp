@@ -1277,6 +1277,16 @@ rbmc_status ensure_ws(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const Ho
     cx->ws_cols = cx->ws_models = 0;
     cx->zcat = nullptr;
     const size_t len = std::max<size_t>(h.total, 1);
+    // the Kronecker workspace holds nothing between its batches (each ends
+    // synchronized): give it up when the sampler's vectors would not fit
+    size_t fr = 0, tot = 0;
+    HIPCHK(hipMemGetInfo(&fr, &tot));
+    const size_t need = (6 * len + (need_zcat ? h.ztotal : 0)) * 8 + ((size_t)1 << 30);
+    if (fr < need && cx->kws_cap > 0) {
+      cx->kws.release();
+      cx->kws_base = nullptr;
+      cx->kws_cap = 0;
+    }
     HIPCHK(cx->ws.alloc((void**)&cx->r, len * 8));
     HIPCHK(cx->ws.alloc((void**)&cx->p, len * 8));
     HIPCHK(cx->ws.alloc((void**)&cx->q, len * 8));

@@ -398,11 +398,20 @@ __global__ __launch_bounds__(256) void k_mc(const McTask* __restrict__ tasks, in
   if (sk > 0) {
     for (int k0 = 0; k0 < n_k; k0 += sk) {
       const int kc = min(sk, n_k - k0);
-      for (int e = threadIdx.x; e < kc * 3 * wn; e += 256) {
-        const int r = e % wn, jd = e / wn, d = jd % 3, j = jd / 3;
-        // a select, not tk.mu[d]: a run-time index would put the task in scratch
-        const double* pm = d == 0 ? tk.mu[0] : d == 1 ? tk.mu[1] : tk.mu[2];
-        win[e] = pm ? G(pm)[(size_t)(k0 + j) * tk.np + w0 + r] : 0.0;
+      // four loads in flight per thread, then their LDS stores
+      for (int e0 = threadIdx.x; e0 < kc * 3 * wn; e0 += 4 * 256) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = e0 + u * 256;
+          const int r = e % wn, jd = e / wn, d = jd % 3, j = jd / 3;
+          // a select, not tk.mu[d]: a run-time index would put the task in scratch
+          const double* pm = d == 0 ? tk.mu[0] : d == 1 ? tk.mu[1] : tk.mu[2];
+          v[u] = e < kc * 3 * wn && pm ? G(pm)[(size_t)(k0 + j) * tk.np + w0 + r] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (e0 + u * 256 < kc * 3 * wn) win[e0 + u * 256] = v[u];
       }
       __syncthreads();
       if (mine)

@@ -50,53 +50,78 @@ template <int AXIS>
 __global__ __launch_bounds__(kFftThreads) void k_dct_fft(const FftTask* __restrict__ tasks,
                                                          int n_tasks) {
   extern __shared__ double fft_lds[];  // zr, zi (kFftSlots each), then N/2 twiddle pairs
+  __shared__ long lbase[2 * kFftSlots / 16];  // offsets of the workgroup's lines
   double* zr = fft_lds;
   double* zi = fft_lds + kFftSlots;
   double* twl = fft_lds + 2 * kFftSlots;
   const FftTask tk = tasks[fft_find(tasks, n_tasks, blockIdx.x)];
-  const int N = tk.N, lg = tk.lg, P = kFftSlots / N, L = 2 * P;
+  // N = 2^lg, P = 2^(11 - lg) line pairs, L = 2P lines: index math by shifts
+  const int N = tk.N, lg = tk.lg, lp = 11 - lg, ll = lp + 1, P = 1 << lp, L = 1 << ll;
   const long g0 = (long)(blockIdx.x - tk.tile_start) * L;  // first line of the workgroup
   const long nlines = (long)tk.nslices * tk.nl;
   const gptr<const double> in = G(tk.in);
   const gptr<double> out = G(tk.out);
   const gptr<const double> tw = G(tk.tw), ph = G(tk.ph);
-  auto base = [&](int i) -> long {  // offset of line g0 + i
-    const long g = g0 + i;
-    return (g / tk.nl) * tk.sstride + (g % tk.nl) * tk.lstride;
-  };
   const long est = tk.estride;
   for (int q = threadIdx.x; q < N; q += kFftThreads) twl[q] = tw[q];
+  for (int i = threadIdx.x; i < L; i += kFftThreads) {
+    const long g = g0 + i;
+    lbase[i] = (g / tk.nl) * tk.sstride + (g % tk.nl) * tk.lstride;
+  }
+  __syncthreads();
+  auto base = [&](int i) -> long { return lbase[i]; };
+  // P N = kFftSlots for every N, so each loop below has a fixed trip count
+  // per thread: unrolled, its global loads are all in flight at once
+  constexpr int kLN = 2 * kFftSlots / kFftThreads;  // (line, element) pairs per thread
+  constexpr int kPN = kFftSlots / kFftThreads;      // (pair, frequency) pairs per thread
   if (!tk.inverse) {
-    for (int q = threadIdx.x; q < L * N; q += kFftThreads) {
-      const int i = AXIS == 0 ? q / N : q % L;
-      const int m = AXIS == 0 ? q % N : q / L;
-      const double v = g0 + i < nlines ? in[base(i) + m * est] : 0.0;
+    double v[kLN];
+#pragma unroll
+    for (int r = 0; r < kLN; ++r) {
+      const int q = threadIdx.x + r * kFftThreads;
+      const int i = AXIS == 0 ? q >> lg : q & (L - 1);
+      const int m = AXIS == 0 ? q & (N - 1) : q >> ll;
+      v[r] = g0 + i < nlines ? in[base(i) + m * est] : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < kLN; ++r) {
+      const int q = threadIdx.x + r * kFftThreads;
+      const int i = AXIS == 0 ? q >> lg : q & (L - 1);
+      const int m = AXIS == 0 ? q & (N - 1) : q >> ll;
       const int at = (i >> 1) * N + fft_rev(fft_vpos(m, N), lg);
-      if (i & 1) zi[at] = v; else zr[at] = v;
+      if (i & 1) zi[at] = v[r]; else zr[at] = v[r];
     }
   } else {
     const double sn0 = sqrt(1.0 / N), sn = sqrt(2.0 / N);
-    for (int q = threadIdx.x; q < P * N; q += kFftThreads) {
-      const int p = AXIS == 0 ? q / N : q % P;
-      const int k = AXIS == 0 ? q % N : q / P;
+    double y[kPN][4], c[kPN], s[kPN];
+#pragma unroll
+    for (int r = 0; r < kPN; ++r) {
+      const int q = threadIdx.x + r * kFftThreads;
+      const int p = AXIS == 0 ? q >> lg : q & (P - 1);
+      const int k = AXIS == 0 ? q & (N - 1) : q >> lp;
       const int kr = (N - k) & (N - 1);
-      double va_r = 0.0, va_i = 0.0, vb_r = 0.0, vb_i = 0.0;
-      const double c = ph[2 * k], s = ph[2 * k + 1];
-      const double inv_k = 1.0 / (k ? sn : sn0), inv_r = 1.0 / sn;
+      c[r] = ph[2 * k];
+      s[r] = ph[2 * k + 1];
 #pragma unroll
       for (int part = 0; part < 2; ++part) {
         const int i = 2 * p + part;
-        double y = 0.0, yr = 0.0;
-        if (g0 + i < nlines) {
-          const long b = base(i);
-          y = in[b + k * est] * inv_k;
-          yr = k ? in[b + kr * est] * inv_r : 0.0;
-        }
-        // V = (c + i s)(y - i yr)
-        const double re = c * y + s * yr, im = s * y - c * yr;
-        if (part == 0) { va_r = re; va_i = im; } else { vb_r = re; vb_i = im; }
+        const bool ok = g0 + i < nlines;
+        const long b = ok ? base(i) : 0;
+        y[r][2 * part] = ok ? in[b + k * est] : 0.0;
+        y[r][2 * part + 1] = ok && k ? in[b + kr * est] : 0.0;
       }
-      // Z = V_A + i V_B
+    }
+#pragma unroll
+    for (int r = 0; r < kPN; ++r) {
+      const int q = threadIdx.x + r * kFftThreads;
+      const int p = AXIS == 0 ? q >> lg : q & (P - 1);
+      const int k = AXIS == 0 ? q & (N - 1) : q >> lp;
+      const double inv_k = 1.0 / (k ? sn : sn0), inv_r = 1.0 / sn;
+      // V = (c + i s)(Y_k - i Y_{N-k}) for both lines, Z = V_A + i V_B
+      const double ya = y[r][0] * inv_k, yra = y[r][1] * inv_r;
+      const double yb = y[r][2] * inv_k, yrb = y[r][3] * inv_r;
+      const double va_r = c[r] * ya + s[r] * yra, va_i = s[r] * ya - c[r] * yra;
+      const double vb_r = c[r] * yb + s[r] * yrb, vb_i = s[r] * yb - c[r] * yrb;
       const int at = p * N + fft_rev(k, lg);
       zr[at] = va_r - vb_i;
       zi[at] = va_i + vb_r;
@@ -110,10 +135,12 @@ __global__ __launch_bounds__(kFftThreads) void k_dct_fft(const FftTask* __restri
   //   c0,2 = b0 +- w2 b2, c1,3 = b1 +- w3 b3   (w2 = W_4h^j, w3 = -+i w2)
   int h = 1, lh = 0;
   for (; 4 * h <= N; h <<= 2, lh += 2) {
-    for (int u = threadIdx.x; u < P * (N >> 2); u += kFftThreads) {
-      const int p = u / (N >> 2), b = u % (N >> 2);
+#pragma unroll
+    for (int r = 0; r < kFftSlots / 4 / kFftThreads; ++r) {
+      const int u = threadIdx.x + r * kFftThreads;
+      const int p = u >> (lg - 2), b = u & ((N >> 2) - 1);
       const int j = b & (h - 1);
-      const int i0 = p * N + ((b >> lh) << (lh + 2)) + j;
+      const int i0 = (p << lg) + ((b >> lh) << (lh + 2)) + j;
       const int t1 = j * (N >> (lh + 1)), t2 = j * (N >> (lh + 2));
       const double w1r = twl[2 * t1], w1i = -sgn * twl[2 * t1 + 1];
       const double w2r = twl[2 * t2], w2i = -sgn * twl[2 * t2 + 1];
@@ -140,8 +167,10 @@ __global__ __launch_bounds__(kFftThreads) void k_dct_fft(const FftTask* __restri
     __syncthreads();
   }
   if (h < N) {  // log2 N odd: one radix-2 stage (h = N / 2)
-    for (int u = threadIdx.x; u < P * (N >> 1); u += kFftThreads) {
-      const int p = u / (N >> 1), j = u % (N >> 1);
+#pragma unroll
+    for (int r = 0; r < kFftSlots / 2 / kFftThreads; ++r) {
+      const int u = threadIdx.x + r * kFftThreads;
+      const int p = u >> (lg - 1), j = u & ((N >> 1) - 1);
       const int i0 = p * N + j, i1 = i0 + h;
       const double wr = twl[2 * j], wi = -sgn * twl[2 * j + 1];
       const double ar = zr[i1], ai = zi[i1];
@@ -156,28 +185,30 @@ __global__ __launch_bounds__(kFftThreads) void k_dct_fft(const FftTask* __restri
   }
   if (!tk.inverse) {
     const double sn0 = sqrt(1.0 / N), sn = sqrt(2.0 / N);
-    for (int q = threadIdx.x; q < L * N; q += kFftThreads) {
-      const int i = AXIS == 0 ? q / N : q % L;
-      const int k = AXIS == 0 ? q % N : q / L;
-      if (g0 + i >= nlines) continue;
+#pragma unroll
+    for (int r = 0; r < kLN; ++r) {
+      const int q = threadIdx.x + r * kFftThreads;
+      const int i = AXIS == 0 ? q >> lg : q & (L - 1);
+      const int k = AXIS == 0 ? q & (N - 1) : q >> ll;
       const int p = i >> 1, kr = (N - k) & (N - 1);
+      const double c = ph[2 * k], s = ph[2 * k + 1];
       const double ar = zr[p * N + k], ai = zi[p * N + k];
       const double br = zr[p * N + kr], bi = zi[p * N + kr];
       // V_A = (Z_k + conj Z_{N-k}) / 2,  V_B = (Z_k - conj Z_{N-k}) / 2i
       const double vr = (i & 1) ? 0.5 * (ai + bi) : 0.5 * (ar + br);
       const double vi = (i & 1) ? -0.5 * (ar - br) : 0.5 * (ai - bi);
       // Re(exp(-i pi k / 2N) V)
-      const double c = ph[2 * k], s = ph[2 * k + 1];
-      out[base(i) + k * est] = (k ? sn : sn0) * (c * vr + s * vi);
+      if (g0 + i < nlines) out[base(i) + k * est] = (k ? sn : sn0) * (c * vr + s * vi);
     }
   } else {
     const double scale = 1.0 / N;
-    for (int q = threadIdx.x; q < L * N; q += kFftThreads) {
-      const int i = AXIS == 0 ? q / N : q % L;
-      const int m = AXIS == 0 ? q % N : q / L;
-      if (g0 + i >= nlines) continue;
+#pragma unroll
+    for (int r = 0; r < kLN; ++r) {
+      const int q = threadIdx.x + r * kFftThreads;
+      const int i = AXIS == 0 ? q >> lg : q & (L - 1);
+      const int m = AXIS == 0 ? q & (N - 1) : q >> ll;
       const int at = (i >> 1) * N + fft_vpos(m, N);
-      out[base(i) + m * est] = scale * ((i & 1) ? zi[at] : zr[at]);
+      if (g0 + i < nlines) out[base(i) + m * est] = scale * ((i & 1) ? zi[at] : zr[at]);
     }
   }
 }
