@@ -353,6 +353,8 @@ struct rbmc_model {
   double *d_qs = nullptr, *d_kk = nullptr, *d_fs = nullptr, *d_qd = nullptr, *d_dqd = nullptr,
          *d_ld = nullptr, *d_dvec = nullptr;
   int* d_obs_rank = nullptr;
+  uint32_t* d_obs_bits = nullptr;
+  int* d_obs_wrank = nullptr;
   std::vector<RegionDev> regions;
   RegionDev* d_regions = nullptr;
   ChainSet bj, sub;
@@ -395,6 +397,7 @@ rbmc_status upload_coefs(rbmc_model* m) {
   m->dm.qo = c.qo;
   m->dm.dqo = c.dqo;
   m->dm.lo = c.lo;
+  m->dm.dobs = c.dobs;
   HIPCHK(hipMemcpyAsync(m->d_dm, &m->dm, sizeof(DevModel), hipMemcpyHostToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
   m->bj_ready = m->sub_ready = false;
@@ -3885,13 +3888,25 @@ rbmc_status rbmc_model_create(rbmc_ctx* ctx, const rbmc_model_desc* desc,
   MCHK(m->pool.alloc((void**)&m->d_ld, (size_t)P.T * 8));
   MCHK(m->pool.alloc((void**)&m->d_dvec, (size_t)P.n * 8));
   MCHK(m->pool.alloc((void**)&m->d_obs_rank, (size_t)P.n * 4));
+  const size_t nwords = ((size_t)P.n + 31) / 32;
+  MCHK(m->pool.alloc((void**)&m->d_obs_bits, nwords * 4));
+  MCHK(m->pool.alloc((void**)&m->d_obs_wrank, nwords * 4));
   MCHK(m->pool.alloc((void**)&m->d_dm, sizeof(DevModel)));
   {
     std::vector<int> rank(P.n, -1);
+    std::vector<uint32_t> bits(nwords, 0u);
+    std::vector<int> wrank(nwords, 0);
     int r = 0;
-    for (int i = 0; i < P.n; ++i)
-      if (m->mask[i]) rank[i] = r++;
+    for (int i = 0; i < P.n; ++i) {
+      if ((i & 31) == 0) wrank[i >> 5] = r;
+      if (m->mask[i]) {
+        bits[i >> 5] |= 1u << (i & 31);
+        rank[i] = r++;
+      }
+    }
     MCHK(hipMemcpy(m->d_obs_rank, rank.data(), (size_t)P.n * 4, hipMemcpyHostToDevice));
+    MCHK(hipMemcpy(m->d_obs_bits, bits.data(), nwords * 4, hipMemcpyHostToDevice));
+    MCHK(hipMemcpy(m->d_obs_wrank, wrank.data(), nwords * 4, hipMemcpyHostToDevice));
   }
   DevModel& dm = m->dm;
   dm.mx = P.mx;
@@ -3908,6 +3923,8 @@ rbmc_status rbmc_model_create(rbmc_ctx* ctx, const rbmc_model_desc* desc,
   dm.ld = m->d_ld;
   dm.dvec = m->d_dvec;
   dm.obs_rank = m->d_obs_rank;
+  dm.obs_bits = m->d_obs_bits;
+  dm.obs_wrank = m->d_obs_wrank;
   // regions
   for (const Region& g : P.regions) {
     RegionDev rd{};

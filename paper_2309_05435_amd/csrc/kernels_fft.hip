@@ -47,8 +47,8 @@ __device__ __forceinline__ int fft_rev(int i, int lg) {
 // apart); AXIS 1: element stride mx, consecutive lines adjacent.  Thread
 // mappings keep global accesses coalesced in both cases.
 template <int AXIS>
-__global__ __launch_bounds__(kFftThreads) void k_dct_fft(const FftTask* __restrict__ tasks,
-                                                         int n_tasks) {
+__global__ __launch_bounds__(kFftThreads, 4) void k_dct_fft(const FftTask* __restrict__ tasks,
+                                                            int n_tasks) {
   extern __shared__ double fft_lds[];  // zr, zi (kFftSlots each), then N/2 twiddle pairs
   __shared__ long lbase[2 * kFftSlots / 16];  // offsets of the workgroup's lines
   double* zr = fft_lds;
@@ -93,38 +93,42 @@ __global__ __launch_bounds__(kFftThreads) void k_dct_fft(const FftTask* __restri
     }
   } else {
     const double sn0 = sqrt(1.0 / N), sn = sqrt(2.0 / N);
-    double y[kPN][4], c[kPN], s[kPN];
+    constexpr int kH = kPN / 2;  // two halves: fewer registers live
 #pragma unroll
-    for (int r = 0; r < kPN; ++r) {
-      const int q = threadIdx.x + r * kFftThreads;
-      const int p = AXIS == 0 ? q >> lg : q & (P - 1);
-      const int k = AXIS == 0 ? q & (N - 1) : q >> lp;
-      const int kr = (N - k) & (N - 1);
-      c[r] = ph[2 * k];
-      s[r] = ph[2 * k + 1];
+    for (int hf = 0; hf < 2; ++hf) {
+      double y[kH][4], c[kH], s[kH];
 #pragma unroll
-      for (int part = 0; part < 2; ++part) {
-        const int i = 2 * p + part;
-        const bool ok = g0 + i < nlines;
-        const long b = ok ? base(i) : 0;
-        y[r][2 * part] = ok ? in[b + k * est] : 0.0;
-        y[r][2 * part + 1] = ok && k ? in[b + kr * est] : 0.0;
+      for (int r0 = 0; r0 < kH; ++r0) {
+        const int q = threadIdx.x + (hf * kH + r0) * kFftThreads;
+        const int p = AXIS == 0 ? q >> lg : q & (P - 1);
+        const int k = AXIS == 0 ? q & (N - 1) : q >> lp;
+        const int kr = (N - k) & (N - 1);
+        c[r0] = ph[2 * k];
+        s[r0] = ph[2 * k + 1];
+#pragma unroll
+        for (int part = 0; part < 2; ++part) {
+          const int i = 2 * p + part;
+          const bool ok = g0 + i < nlines;
+          const long b = ok ? base(i) : 0;
+          y[r0][2 * part] = ok ? in[b + k * est] : 0.0;
+          y[r0][2 * part + 1] = ok && k ? in[b + kr * est] : 0.0;
+        }
       }
-    }
 #pragma unroll
-    for (int r = 0; r < kPN; ++r) {
-      const int q = threadIdx.x + r * kFftThreads;
-      const int p = AXIS == 0 ? q >> lg : q & (P - 1);
-      const int k = AXIS == 0 ? q & (N - 1) : q >> lp;
-      const double inv_k = 1.0 / (k ? sn : sn0), inv_r = 1.0 / sn;
-      // V = (c + i s)(Y_k - i Y_{N-k}) for both lines, Z = V_A + i V_B
-      const double ya = y[r][0] * inv_k, yra = y[r][1] * inv_r;
-      const double yb = y[r][2] * inv_k, yrb = y[r][3] * inv_r;
-      const double va_r = c[r] * ya + s[r] * yra, va_i = s[r] * ya - c[r] * yra;
-      const double vb_r = c[r] * yb + s[r] * yrb, vb_i = s[r] * yb - c[r] * yrb;
-      const int at = p * N + fft_rev(k, lg);
-      zr[at] = va_r - vb_i;
-      zi[at] = va_i + vb_r;
+      for (int r0 = 0; r0 < kH; ++r0) {
+        const int q = threadIdx.x + (hf * kH + r0) * kFftThreads;
+        const int p = AXIS == 0 ? q >> lg : q & (P - 1);
+        const int k = AXIS == 0 ? q & (N - 1) : q >> lp;
+        const double inv_k = 1.0 / (k ? sn : sn0), inv_r = 1.0 / sn;
+        // V = (c + i s)(Y_k - i Y_{N-k}) for both lines, Z = V_A + i V_B
+        const double ya = y[r0][0] * inv_k, yra = y[r0][1] * inv_r;
+        const double yb = y[r0][2] * inv_k, yrb = y[r0][3] * inv_r;
+        const double va_r = c[r0] * ya + s[r0] * yra, va_i = s[r0] * ya - c[r0] * yra;
+        const double vb_r = c[r0] * yb + s[r0] * yrb, vb_i = s[r0] * yb - c[r0] * yrb;
+        const int at = p * N + fft_rev(k, lg);
+        zr[at] = va_r - vb_i;
+        zi[at] = va_i + vb_r;
+      }
     }
   }
   __syncthreads();

@@ -147,13 +147,13 @@ __global__ __launch_bounds__(NTHR) void k_space_time_op(ColSet cs, const double*
         } else if (KIND == 5) {
 #pragma unroll
           for (int q = 0; q < kN5; ++q) v += cf[half][q] * w[hy + kSdy[q]][hx + kSdx[q]];
-          int r = m.obs_rank[i];
-          if (r >= 0) v += sqrt(m.dvec[i]) * xk[(size_t)m.n + r];
+          if (obs_at(m, i)) v += sqrt(m.dobs) * xk[(size_t)m.n + obs_rank_at(m, i)];
         }
-        if (KIND == 0) v += m.dvec[i] * slot[b0][hy][hx];
-        if (KIND == 4) v = -2.0 * m.dvec[i] * xk[i];
+        // D from the observation bits (L2-resident), x at the node from LDS
+        if (KIND == 0 && obs_at(m, i)) v += m.dobs * slot[b0][hy][hx];
+        if (KIND == 4) v = obs_at(m, i) ? -2.0 * m.dobs * xk[i] : 0.0;
         yk[i] = v;
-        if (DOT) acc += v * xk[i];
+        if (DOT) acc += v * (KIND == 4 ? xk[i] : slot[b0][hy][hx]);
       }
     }
     if (KIND != 4) __syncthreads();

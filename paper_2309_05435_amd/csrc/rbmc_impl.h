@@ -107,6 +107,11 @@ struct DevModel {  // device views used by the stencil kernels
   double qo, dqo, lo;
   const double* dvec;     // n: sigma^-2 * mask
   const int* obs_rank;    // n: rank among observed (or -1)
+  // the mask as bits (n / 32 words; small enough to stay in L2 across the
+  // columns of a launch), the observed nodes before each word, sigma^-2
+  const uint32_t* obs_bits;
+  const int* obs_wrank;
+  double dobs;
   // spectral preconditioner (set when the model has it): orthonormal DCT-II
   // matrices (column-major, C[k, i] = c_k cos(pi k (2 i + 1) / (2 m))), the
   // per-frequency time recursion (c'_t, 1 / den_t at t ns + f; the
@@ -119,6 +124,14 @@ struct DevModel {  // device views used by the stencil kernels
   const double* sp_off;   // ns
   int spec_gemm;  // transformed outside the direct DCT kernel (FFT or GEMM route)
 };
+
+// node i observed; its rank among the observed nodes (valid when observed)
+__device__ __forceinline__ bool obs_at(const DevModel& m, size_t i) {
+  return (m.obs_bits[i >> 5] >> (i & 31)) & 1u;
+}
+__device__ __forceinline__ int obs_rank_at(const DevModel& m, size_t i) {
+  return m.obs_wrank[i >> 5] + __popc(m.obs_bits[i >> 5] & ((1u << (i & 31)) - 1u));
+}
 
 // Column sets: the sampler works on the columns (model, sample) of one or
 // many models at once.  Column c has length len[c] (the model's n), starts at
