@@ -80,14 +80,15 @@ __global__ __launch_bounds__(NTHR) void k_space_time_op(ColSet cs, const double*
     for (int q = 0; q < NC; ++q) cf[half][q] = (KIND != 4 && in) ? cf_src[(size_t)q * m.ns + s] : 0.0;
   }
 
-  // A layer (the tile with its halo of 2) is fetched into registers one step
-  // ahead of its store to LDS, so its loads are in flight during a step's
-  // arithmetic.  The loads are unconditional: entries outside the grid or
-  // the time range read element 0 and are stored as 0.
+  // A layer (the tile with its halo of 2) is fetched into registers two steps
+  // ahead of its store to LDS (two register buffers, alternating by step
+  // parity), so its loads are in flight during two steps' arithmetic.  The
+  // loads are unconditional: entries outside the grid or the time range read
+  // element 0 and are stored as 0.
   constexpr int NL = (HX * HY + NTHR - 1) / NTHR;  // entries per thread
-  double pre[NL];
-  bool pre_ok[NL];
-  auto fetch = [&](int t) {
+  double preA[NL], preB[NL];
+  bool okA[NL], okB[NL];
+  auto fetch = [&](int t, double (&pre)[NL], bool (&pre_ok)[NL]) {
 #pragma unroll
     for (int j = 0; j < NL; ++j) {
       const int e = tid + NTHR * j;
@@ -99,7 +100,7 @@ __global__ __launch_bounds__(NTHR) void k_space_time_op(ColSet cs, const double*
       pre_ok[j] = ok;
     }
   };
-  auto put = [&](int buf) {
+  auto put = [&](int buf, const double (&pre)[NL], const bool (&pre_ok)[NL]) {
 #pragma unroll
     for (int j = 0; j < NL; ++j) {
       const int e = tid + NTHR * j;
@@ -108,19 +109,13 @@ __global__ __launch_bounds__(NTHR) void k_space_time_op(ColSet cs, const double*
   };
 
   double acc = 0.0;
-  // the layer of step t lives in slot t mod 3 (step -1 in slot 2)
-  if (KIND != 4) {
-    fetch(-1);
-    put(2);
-    fetch(0);
-    put(0);
-    fetch(1);
-  }
-  for (int t = 0; t < m.T; ++t) {
+  // one output step t: layer t + 1 from the register buffer (pre, ok) into
+  // LDS, layer t + 3 fetched into the same buffer
+  auto step = [&](int t, double (&pre)[NL], bool (&pre_ok)[NL]) {
     const int bm = (t + 2) % 3, b0 = t % 3, bp = (t + 1) % 3;  // t-1, t, t+1
     if (KIND != 4) {
-      put(bp);     // layer t + 1, fetched during the previous step
-      fetch(t + 2);  // zeros beyond the last step
+      put(bp, pre, pre_ok);
+      fetch(t + 3, pre, pre_ok);  // zeros beyond the last step
       __syncthreads();
       double wm, w0, wp;
       time_weights(m, KIND, t, wm, w0, wp);
@@ -157,6 +152,19 @@ __global__ __launch_bounds__(NTHR) void k_space_time_op(ColSet cs, const double*
       }
     }
     if (KIND != 4) __syncthreads();
+  };
+  // the layer of step t lives in slot t mod 3 (step -1 in slot 2)
+  if (KIND != 4) {
+    fetch(-1, preA, okA);
+    put(2, preA, okA);
+    fetch(0, preA, okA);
+    put(0, preA, okA);
+    fetch(1, preA, okA);
+    fetch(2, preB, okB);
+  }
+  for (int t = 0; t < m.T; t += 2) {
+    step(t, preA, okA);
+    if (t + 1 < m.T) step(t + 1, preB, okB);
   }
   if (DOT) {
     red[tid] = acc;
