@@ -3242,11 +3242,15 @@ rbmc_status kron_corr_batch(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, co
   pg.kron(ar, 18, m1, RBMC_KF_TMIX);
   pg.kron(ar, 19, ob);
   pg.gemm(ar, gw);
+  // the products Z_g w_g overwrite the panel of every step with observations;
+  // the others must be zero
   for (size_t i = i0; i < i1; ++i) {
     rbmc_model* m = ms[refs[i].first];
     const rbmc_model::KronSub& k = m->ksub[refs[i].second];
     const rbmc_model::KronReg& R = m->kreg[m->kreg_of[m->plan.sub[k.chain].region]];
-    pg.fill(kb[i - i0].Ub, (size_t)R.np * k.TA * nk);
+    const size_t panel = (size_t)R.np * nk;
+    for (int g = 0; g < k.TA; ++g)
+      if (k.gpad[g] == 0) pg.fill(kb[i - i0].Ub + (size_t)g * panel, panel);
   }
   pg.gemm(ar, gz);
   pg.kron(ar, 18, m2, RBMC_KF_TMIX);

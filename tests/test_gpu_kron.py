@@ -76,6 +76,25 @@ def test_kron_from_samples_matches_oracle(case):
     gm.close()
 
 
+def test_kron_sparse_observations():
+    """1% observed: some time steps have no observations at all (their
+    Woodbury groups are empty and their correction panels must be zero)."""
+    wl = wl_of(14, 9, 3, 2, 1, frac=0.01, seed=29)
+    say("kron sparse observations")
+    M = O.OracleModel.from_workload(wl)
+    mask = wl.mask().reshape(wl.T, -1)
+    assert (mask.sum(axis=1) == 0).any()  # steps without observations
+    lab = O.grid_cores(14, 14, 9, 3, 2, 2)
+    x = normals((67, M.n), 22)
+    ref = M.rbmc(lab, 12, 1, x, 0b1111)
+    gm = B.Model(wl)
+    diag, tr, st, _ = gm.estimate_from_samples(dev(x), grad_mask=0b1111, method=B.RBMC_SEL_KRON)
+    assert st == B.RBMC_OK
+    np.testing.assert_allclose(diag.cpu().numpy(), ref["diag"], rtol=RTOL)
+    np.testing.assert_allclose(tr, ref["trace"], rtol=RTOL)
+    gm.close()
+
+
 def test_kron_strong_observations():
     """sigma = 0.05: the observations carry most of the posterior precision,
     the Woodbury correction cancels most of the prior variance."""
