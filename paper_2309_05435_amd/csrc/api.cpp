@@ -329,6 +329,7 @@ struct rbmc_model {
     // only rows where r = Q_AB x_B is nonzero at steps away from the time
     // separator), nring of them, padded to nrp with -1; rinv = S^-1[:, rim]
     bool rim = false;  // corrections use the rim products
+    int mc_win = 0;    // widest span of region rows the stencils of a 256-row chunk reach
     int nring = 0, nrp = 0;
     int* d_ring = nullptr;
     double* rinv = nullptr;
@@ -812,13 +813,14 @@ struct Program {
     o.tiles = e.tiles;
     ops.push_back(o);
   }
-  void mc(Arena& a, TileList<McTask>& e) {
+  void mc(Arena& a, TileList<McTask>& e, bool multi = false) {
     if (e.v.empty()) return;
     Op o;
     o.kind = 5;
     o.off = a.push(e.v);
     o.n = (int)e.v.size();
     o.tiles = e.tiles;
+    o.kblk = multi ? 1 : 0;
     o.family = RBMC_KF_MC;
     o.alg_bytes = e.bytes;
     ops.push_back(o);
@@ -878,7 +880,7 @@ rbmc_status run(rbmc_ctx* cx, const Program& pg, hipStream_t s, Arena& a) {
       case 2: launch_inv128(a.at<SmallInvTask>(o.off), o.n, s); break;
       case 3: launch_panels(a.at<PanelTask>(o.off), o.n, o.tiles, s); break;
       case 4: launch_extract(a.at<ExtractTask>(o.off), o.n, o.tiles, s); break;
-      case 5: launch_mc(a.at<McTask>(o.off), o.n, o.tiles, s); break;
+      case 5: launch_mc(a.at<McTask>(o.off), o.n, o.tiles, o.kblk, s); break;
       case 6: HIPCHK(hipMemcpyAsync(o.dst, o.src, o.bytes, hipMemcpyDeviceToDevice, s)); break;
       case 7: launch_gj2_gather(a.at<Gj2Task>(o.off), o.n, o.tiles, s); break;
       case 8: launch_gj2_fix(a.at<Gj2Task>(o.off), o.n, o.tiles, s); break;
@@ -2720,6 +2722,19 @@ rbmc_status kron_static(rbmc_model* m) {
           }
         if (rim) ring.push_back(a);
       }
+      for (int c0 = 0; c0 < g.nb(); c0 += 256) {
+        int lo = INT_MAX, hi = -1;
+        for (int a = c0; a < std::min(c0 + 256, g.nb()); ++a)
+          if (g.in_box[a])
+            for (int q = 0; q < kNS; ++q) {
+              const int c = g.nbr[(size_t)a * kNS + q];
+              if (c >= 0) {
+                lo = std::min(lo, c);
+                hi = std::max(hi, c);
+              }
+            }
+        if (hi >= lo) r.mc_win = std::max(r.mc_win, hi - lo + 1);
+      }
       r.nring = (int)ring.size();
       r.nrp = r.nring > 0 ? pad_to(r.nring) : 0;
       r.rim = r.nrp < r.np;  // the rim products pay only when the rim is a part of R
@@ -3115,7 +3130,7 @@ rbmc_status kron_corr_batch(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, co
   gu.mixed = gw.mixed = gz.mixed = mixed;
   TileList<KronMixTask> m1, m2;
   TileList<KronObsTask> ob;
-  TileList<McTask> mt;
+  TileList<McTask> mt, mt2;
   for (size_t i = i0; i < i1; ++i) {
     const int j = refs[i].first;
     rbmc_model* m = ms[j];
@@ -3216,7 +3231,30 @@ rbmc_status kron_corr_batch(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, co
     mx.beta = 1.0;
     m2.add(mx, kron_mix_tiles(R.np, nk), 24.0 * R.nb * nk * k.TA);
     const size_t c = lidx[i];
-    for (int t = ch.ct0 - ch.t0; t < ch.ct0 - ch.t0 + ch.cT; ++t) {
+    // several core steps per task when their windows fit in LDS
+    const int S = R.mc_win > 0
+                      ? std::max(1, std::min(mc_max_steps(), mc_lds_doubles() / R.mc_win - 2))
+                      : 1;
+    const int tc0 = ch.ct0 - ch.t0, tc1 = tc0 + ch.cT;
+    for (int t = tc0; S > 1 && t < tc1; t += S) {
+      McTask q{};
+      q.stack = b.Rb;
+      q.ta = k.TA;
+      q.tl = t;
+      q.steps = std::min(S, tc1 - t);
+      q.np = R.np;
+      q.rg = m->d_regions + ch.region;
+      q.dm = m->d_dm;
+      q.diag_out = diag_out[j];
+      q.partial = cx->epart + L.det_len;
+      q.out_index = (int)L.mc_index(c, t);
+      q.n_k = nk;
+      q.scale = scale;
+      q.accum = accum;
+      q.t = ch.t0 + t;
+      mt2.add(q, mc_chunks(R.np), 8.0 * R.nb * nk * q.steps);
+    }
+    for (int t = tc0; S == 1 && t < tc1; ++t) {
       McTask q{};
       q.mu[0] = t - 1 >= 0 ? b.Rb + (size_t)(t - 1) * panel : nullptr;
       q.mu[1] = b.Rb + (size_t)t * panel;
@@ -3255,6 +3293,7 @@ rbmc_status kron_corr_batch(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, co
   pg.gemm(ar, gz);
   pg.kron(ar, 18, m2, RBMC_KF_TMIX);
   pg.mc(ar, mt);
+  pg.mc(ar, mt2, true);
   HIPCHK(ar.upload(s));
   rbmc_status st = run(cx, pg, s, ar);
   if (st != RBMC_OK) return st;

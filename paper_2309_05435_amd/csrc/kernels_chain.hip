@@ -329,8 +329,13 @@ void launch_offdiag(const OffdiagTask* d_tasks, int n_tasks, int total_tiles, hi
 // ---------------------------------------------------------------------------
 namespace {
 constexpr int kMcLds = 4096;  // doubles of staged windows
+constexpr int kMcS = 4;       // core steps per task at most
 }
 
+// MULTI: tasks of up to kMcS steps whose windows fit in LDS (the host checks);
+// else one step per task, with a direct global-memory path for windows that
+// do not fit.
+template <bool MULTI>
 __global__ __launch_bounds__(256) void k_mc(const McTask* __restrict__ tasks, int n_tasks) {
   __shared__ double red[8][256];
   __shared__ double win[kMcLds];
@@ -343,16 +348,29 @@ __global__ __launch_bounds__(256) void k_mc(const McTask* __restrict__ tasks, in
   const int chunk = b - tk.tile_start;
   const int a = chunk * 256 + threadIdx.x;
   const bool mine = a < rg.nb && G(rg.in_box)[a];
-  double acc[8];
+  constexpr int kS = MULTI ? kMcS : 1;    // register arrays per step
+  const int S = MULTI ? tk.steps : 1;     // steps of this task
+  const int nP = S + 2;                   // panels they read: steps tl - 1 .. tl + S
+  // panel d (0 <= d < nP): local step tl - 1 + d of the stack, or mu[d]
+#define RBMC_MC_PANEL(d)                                                                    \
+  (tk.stack ? ((tk.tl - 1 + (d) >= 0 && tk.tl - 1 + (d) < tk.ta)                           \
+                   ? tk.stack + (size_t)(tk.tl - 1 + (d)) * tk.np * n_k                      \
+                   : (const double*)nullptr)                                                 \
+            : ((d) == 0 ? tk.mu[0] : (d) == 1 ? tk.mu[1] : tk.mu[2]))
+  double acc[kS][8];
 #pragma unroll
-  for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+  for (int s = 0; s < kS; ++s)
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc[s][c] = 0.0;
   int nbr[kNS];
-  double cq[kNS], ck[kN5];
-  double dv = 0.0;
+  double cq[kNS], ck[kN5], dv[kS];
   int lo = INT_MAX, hi = -1;
+  int node = 0;
   if (mine) {
-    const int node = G(rg.nodes)[a];
-    dv = G(m.dvec)[(size_t)tk.t * m.ns + node];
+    node = G(rg.nodes)[a];
+#pragma unroll
+    for (int s = 0; s < kS; ++s)
+      dv[s] = s < S ? G(m.dvec)[(size_t)(tk.t + s) * m.ns + node] : 0.0;
 #pragma unroll
     for (int q = 0; q < kNS; ++q) {
       nbr[q] = G(rg.nbr)[a * kNS + q];
@@ -375,94 +393,123 @@ __global__ __launch_bounds__(256) void k_mc(const McTask* __restrict__ tasks, in
   }
   __syncthreads();
   const int w0 = span[0], wn = span[1] >= span[0] ? span[1] - span[0] + 1 : 0;
-  const int sk = wn > 0 ? min(4, kMcLds / (3 * wn)) : 0;
-  // one sample: mu = mu_t[a]; Y(d, row) reads row of panel d (zero for a
-  // panel outside the chain)
-#define RBMC_MC_SAMPLE(MU, Y)                           \
-  {                                                     \
-    const double mu_ = (MU);                            \
-    acc[7] += mu_ * mu_;                                \
-    acc[6] += dv * mu_ * mu_;                           \
-    _Pragma("unroll") for (int d = 0; d < 3; ++d) {     \
-      double vq = 0.0, vk = 0.0;                        \
-      _Pragma("unroll") for (int q = 0; q < kNS; ++q) { \
-        if (nbr[q] < 0) continue;                       \
-        const double y = Y(d, nbr[q]);                  \
-        vq += cq[q] * y;                                \
-        if (q < kN5) vk += ck[q] * y;                   \
-      }                                                 \
-      acc[d] += mu_ * vq;                               \
-      acc[3 + d] += mu_ * vk;                           \
-    }                                                   \
+  const int sk = wn > 0 ? min(4, kMcLds / (nP * wn)) : 0;
+  // one sample: mu_s = MU(s) (the row's entry of step s's panel), Y(p, row)
+  // reads row of panel p (zero for a panel outside the chain).  Each panel's
+  // stencil sums serve every step that reads it: step s reads panels
+  // s, s + 1, s + 2 as its t - 1, t, t + 1.
+#define RBMC_MC_SAMPLE(MU, Y)                                    \
+  {                                                              \
+    double mu_[kS];                                              \
+    _Pragma("unroll") for (int s = 0; s < kS; ++s) {             \
+      mu_[s] = s < S ? (MU(s)) : 0.0;                            \
+      acc[s][7] += mu_[s] * mu_[s];                              \
+      acc[s][6] += dv[s] * mu_[s] * mu_[s];                      \
+    }                                                            \
+    _Pragma("unroll") for (int p = 0; p < kS + 2; ++p) {         \
+      if (p >= nP) break;                                        \
+      double vq = 0.0, vk = 0.0;                                 \
+      _Pragma("unroll") for (int q = 0; q < kNS; ++q) {          \
+        if (nbr[q] < 0) continue;                                \
+        const double y = Y(p, nbr[q]);                           \
+        vq += cq[q] * y;                                         \
+        if (q < kN5) vk += ck[q] * y;                            \
+      }                                                          \
+      _Pragma("unroll") for (int d = 0; d < 3; ++d) {            \
+        const int s = p - d;                                     \
+        if (s >= 0 && s < kS) {                                  \
+          acc[s][d] += mu_[s] * vq;                              \
+          acc[s][3 + d] += mu_[s] * vk;                          \
+        }                                                        \
+      }                                                          \
+    }                                                            \
   }
   if (sk > 0) {
     for (int k0 = 0; k0 < n_k; k0 += sk) {
       const int kc = min(sk, n_k - k0);
+      const int tot = kc * nP * wn;
       // four loads in flight per thread, then their LDS stores
-      for (int e0 = threadIdx.x; e0 < kc * 3 * wn; e0 += 4 * 256) {
+      for (int e0 = threadIdx.x; e0 < tot; e0 += 4 * 256) {
         double v[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int e = e0 + u * 256;
-          const int r = e % wn, jd = e / wn, d = jd % 3, j = jd / 3;
-          // a select, not tk.mu[d]: a run-time index would put the task in scratch
-          const double* pm = d == 0 ? tk.mu[0] : d == 1 ? tk.mu[1] : tk.mu[2];
-          v[u] = e < kc * 3 * wn && pm ? G(pm)[(size_t)(k0 + j) * tk.np + w0 + r] : 0.0;
+          const int r = e % wn, jd = e / wn, d = jd % nP, j = jd / nP;
+          const double* pm = RBMC_MC_PANEL(d);
+          v[u] = e < tot && pm ? G(pm)[(size_t)(k0 + j) * tk.np + w0 + r] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-          if (e0 + u * 256 < kc * 3 * wn) win[e0 + u * 256] = v[u];
+          if (e0 + u * 256 < tot) win[e0 + u * 256] = v[u];
       }
       __syncthreads();
       if (mine)
         for (int j = 0; j < kc; ++j) {
-          const int wj = j * 3 * wn - w0;
+          const int wj = j * nP * wn - w0;
 #define RBMC_MC_LDS(d, row) win[wj + (d) * wn + (row)]
-          RBMC_MC_SAMPLE(win[wj + wn + a], RBMC_MC_LDS)
+#define RBMC_MC_MU(s) win[wj + ((s) + 1) * wn + a]
+          RBMC_MC_SAMPLE(RBMC_MC_MU, RBMC_MC_LDS)
+#undef RBMC_MC_MU
 #undef RBMC_MC_LDS
         }
       __syncthreads();
     }
-  } else if (mine) {
+  } else if (!MULTI && mine) {
     for (int k = 0; k < n_k; ++k) {
       const size_t off = (size_t)k * tk.np;
-#define RBMC_MC_GLOBAL(d, row) (tk.mu[d] ? G(tk.mu[d])[off + (row)] : 0.0)
-      RBMC_MC_SAMPLE(G(tk.mu[1])[off + a], RBMC_MC_GLOBAL)
+#define RBMC_MC_GLOBAL(d, row) \
+  (RBMC_MC_PANEL(d) ? G(RBMC_MC_PANEL(d))[off + (row)] : 0.0)
+#define RBMC_MC_GMU(s) RBMC_MC_GLOBAL((s) + 1, a)
+      RBMC_MC_SAMPLE(RBMC_MC_GMU, RBMC_MC_GLOBAL)
+#undef RBMC_MC_GMU
 #undef RBMC_MC_GLOBAL
     }
   }
 #undef RBMC_MC_SAMPLE
+#undef RBMC_MC_PANEL
+  // per step: diagonal, then the 8 partial sums of the workgroup; the ratio
+  // m_a / s2_a (MC part over estimate) feeds the plug-in error estimate
+  const int nch = mc_chunks(tk.np);
 #pragma unroll
-  for (int c = 0; c < 8; ++c) red[c][threadIdx.x] = acc[c];
-  __syncthreads();
-  // diagonal; the ratio m_a / s2_a (MC part over estimate) feeds the plug-in
-  // error estimate
-  double ratio = 0.0;
-  if (mine) {
-    const size_t i = (size_t)tk.t * m.ns + G(rg.nodes)[a];
-    const double mhat = red[7][threadIdx.x] * tk.scale;
-    const double est = G(tk.diag_out)[i] + mhat;
-    G(tk.diag_out)[i] = est;
-    ratio = est > 0.0 ? mhat / est : 0.0;
-  }
-  __syncthreads();
-  red[7][threadIdx.x] = ratio;
-  __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
-    if (threadIdx.x < st)
-      for (int c = 0; c < 8; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + st];
+  for (int s = 0; s < kS; ++s) {
+    if (s >= S) break;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) red[c][threadIdx.x] = acc[s][c];
     __syncthreads();
-  }
-  if (threadIdx.x < 8) {
-    const double v = threadIdx.x == 7 ? red[7][0] : red[threadIdx.x][0] * tk.scale;
-    const size_t at = ((size_t)tk.out_index + chunk) * 8 + threadIdx.x;
-    G(tk.partial)[at] = tk.accum ? G(tk.partial)[at] + v : v;
+    double ratio = 0.0;
+    if (mine) {
+      const size_t i = (size_t)(tk.t + s) * m.ns + node;
+      const double mhat = red[7][threadIdx.x] * tk.scale;
+      const double est = G(tk.diag_out)[i] + mhat;
+      G(tk.diag_out)[i] = est;
+      ratio = est > 0.0 ? mhat / est : 0.0;
+    }
+    __syncthreads();
+    red[7][threadIdx.x] = ratio;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if (threadIdx.x < st)
+        for (int c = 0; c < 8; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x < 8) {
+      const double v = threadIdx.x == 7 ? red[7][0] : red[threadIdx.x][0] * tk.scale;
+      const size_t at = ((size_t)tk.out_index + (size_t)s * nch + chunk) * 8 + threadIdx.x;
+      G(tk.partial)[at] = tk.accum ? G(tk.partial)[at] + v : v;
+    }
+    __syncthreads();
   }
 }
 
-void launch_mc(const McTask* d_tasks, int n_tasks, int total_tiles, hipStream_t s) {
+int mc_max_steps() { return kMcS; }
+int mc_lds_doubles() { return kMcLds; }
+
+void launch_mc(const McTask* d_tasks, int n_tasks, int total_tiles, int multi, hipStream_t s) {
   if (total_tiles <= 0) return;
-  k_mc<<<total_tiles, 256, 0, s>>>(d_tasks, n_tasks);
+  if (multi)
+    k_mc<true><<<total_tiles, 256, 0, s>>>(d_tasks, n_tasks);
+  else
+    k_mc<false><<<total_tiles, 256, 0, s>>>(d_tasks, n_tasks);
 }
 
 }  // namespace rbmc

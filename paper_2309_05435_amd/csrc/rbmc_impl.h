@@ -370,9 +370,14 @@ void launch_offdiag(const OffdiagTask* d_tasks, int n_tasks, int total_tiles, hi
 // Partial sums of chunk c (region rows [256 c, 256 c + 256)) go to
 // partial[(out_index + c) * 8 + j] (added to the previous value when accum
 // is set); a task spans mc_chunks(np) chunks.
-inline int mc_chunks(int np) { return (np + 255) / 256; }
+__host__ __device__ inline int mc_chunks(int np) { return (np + 255) / 256; }
+// With stack set, the task covers `steps` (<= 4) consecutive core steps from
+// local step tl: panel u of the chain (u < ta) at stack + u np n_k, partial
+// sums of step s at out_index + s mc_chunks(np), diagonal at step t + s.
 struct McTask {
   const double* mu[3];  // panels for t-1, t, t+1 (null if outside the chain)
+  const double* stack;  // or the chain's stacked panels
+  int ta, tl, steps;
   double scale;         // 1 / (total samples of the estimate)
   int accum;            // add to the partial sums (later sample passes)
   int np;
@@ -385,7 +390,11 @@ struct McTask {
   int t;
   int tile_start;
 };
-void launch_mc(const McTask* d_tasks, int n_tasks, int total_tiles, hipStream_t s);
+// multi: tasks of several steps (their windows of (steps + 2) panels x the
+// region's widest 256-row span fit in mc_lds_doubles() for one sample)
+void launch_mc(const McTask* d_tasks, int n_tasks, int total_tiles, int multi, hipStream_t s);
+int mc_max_steps();
+int mc_lds_doubles();
 
 // ---------------------------------------------------------------------------
 // Learned correction to the preconditioner: 3-D convolutions (kernels_conv.hip)

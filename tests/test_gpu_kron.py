@@ -265,3 +265,25 @@ def test_device_z_and_sample_passes():
     say(f"plug-in error one pass {r1.err_estimate:.4e}, passes {r3.err_estimate:.4e}")
     assert abs(r3.err_estimate - r1.err_estimate) <= 1e-8 * r1.err_estimate
     gm.close()
+
+
+@pytest.mark.parametrize("method,precond", [(B.RBMC_SEL_KRON, B.RBMC_PC_SPECTRAL),
+                                            (B.RBMC_SEL_BLOCKTRI, B.RBMC_PC_BJ)])
+def test_estimate_is_deterministic(method, precond):
+    """The same call twice gives bitwise the same diagonal, traces and report:
+    every reduction has a fixed order (no atomics on the outputs)."""
+    wl = wl_of(20, 8, 2, 2, 1)
+    gm = B.Model(wl)
+    kw = dict(grad_mask=0b1111, rtol=1e-10, maxit=500, precond=precond, method=method)
+    if method == B.RBMC_SEL_KRON:  # device normals, passes of 10
+        kw.update(n_samples=24, seed=5, sample_chunk=10)
+        z = None
+    else:
+        z = dev(normals((24, gm.n + gm.n_obs), 5))
+    runs = [gm.estimate(z, **kw) for _ in range(2)]
+    (d1, t1, s1, r1), (d2, t2, s2, r2) = runs
+    assert s1 == s2 == B.RBMC_OK
+    assert torch.equal(d1, d2)
+    assert np.array_equal(np.asarray(t1), np.asarray(t2))
+    assert r1.err_estimate == r2.err_estimate and r1.pcg_it_max == r2.pcg_it_max
+    gm.close()
