@@ -307,9 +307,9 @@ def main():
     ap.add_argument("--budget-s", type=float, default=600.0,
                     help="wall-time budget: legs after the timed steps run only if their "
                          "projected end stays within it")
-    ap.add_argument("--legs", default="stated,true_error,cpu,plain,batched",
-                    help="legs after the timed steps, in order (subset of stated,true_error,"
-                         "cpu,plain,batched; empty for none)")
+    ap.add_argument("--legs", default="stated,mixed,true_error,cpu,plain,batched",
+                    help="legs after the timed steps, in order (subset of stated,mixed,"
+                         "true_error,cpu,plain,batched; empty for none)")
     ap.add_argument("--true-error-nodes", type=int, default=256)
     ap.add_argument("--pc", default="1,32,32",
                     help="block-Jacobi blocks 'slabs,tiles_x,tiles_y' of the plain leg, or 'cores'")
@@ -375,9 +375,10 @@ def main():
     diag = torch.empty(gm.n, dtype=torch.float64, device="cuda")
     theta = wl.theta
 
-    def opts_for(nk, passes=True):
+    def opts_for(nk, passes=True, precision=B.RBMC_FP64):
         return B.make_opts(nk, pcg_maxit=500, pcg_rtol=wl.rtol, grad_mask=grad,
-                           precond=B.RBMC_PC_SPECTRAL, method=B.RBMC_SEL_KRON,
+                           precision=precision, precond=B.RBMC_PC_SPECTRAL,
+                           method=B.RBMC_SEL_KRON,
                            sample_chunk=chunk if passes and nk > chunk else 0)
 
     def estimate(opts):
@@ -503,7 +504,7 @@ def main():
         say(f"skipping leg {name}: projected {est_s:.0f} s, {left:.0f} s left")
         return False
 
-    d_stated = None
+    d_stated = d_mixed = None
     for leg in legs:
         if leg == "stated":
             if not budget_ok(3.0 * rep0.t_total, "stated") or not gm.m:
@@ -521,6 +522,34 @@ def main():
                 "phase_s": {k: getattr(rs, k) for k in ("t_sample", "t_factor", "t_correct",
                                                         "t_total")}}
             say(f"stated setting: {sec:.2f} s, plug-in error {rs.err_estimate:.4f}")
+        elif leg == "mixed":
+            # the timed estimate under RBMC_MIXED (the correction products on
+            # the FP32 matrix cores, the sampler in FP64): same sample count,
+            # passes and z
+            if not budget_ok(2.2 * ms / 1000.0, "mixed") or not gm.m:
+                continue
+            om = opts_for(nk, precision=B.RBMC_MIXED)
+            estimate(om)  # warm-up: loads the mixed kernels
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            _, trm, rm = estimate(om)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - ta
+            d_mixed = diag.clone()
+            rel_d = (d_mixed - d_head).abs() / d_head
+            out["mixed"] = {
+                "n_samples": nk, "value": gm.n / sec, "ms_per_estimate": sec * 1e3,
+                "speedup_vs_fp64": ms / (sec * 1e3),
+                "precision": "mixed (FP32 matrix-core correction products)",
+                "err_estimate": rm.err_estimate,
+                "pcg_iters": {"mean": rm.pcg_it_mean, "max": rm.pcg_it_max},
+                "phase_s": {k: getattr(rm, k) for k in ("t_sample", "t_factor", "t_correct",
+                                                        "t_total")},
+                "diag_rel_diff_vs_fp64": {"mean": float(rel_d.mean()),
+                                          "max": float(rel_d.max())},
+                "trace_rel_diff_vs_fp64": [abs(a - b) / abs(b) for a, b in zip(trm, tr)]}
+            say(f"mixed: {sec:.2f} s ({ms / (sec * 1e3):.3f}x), {rm.pcg_it_max} PCG "
+                f"iterations, diag vs FP64 mean {float(rel_d.mean()):.2e}")
         elif leg == "true_error":
             if not budget_ok(60.0, "true_error"):
                 continue
@@ -550,7 +579,7 @@ def main():
             sec = time.perf_counter() - ta
             te = {"nodes": len(nodes), "node_seed": seed + 7, "solve_rtol": 1e-12,
                   "solve_pcg_iters_max": it_max, "seconds": sec}
-            for name, d in (("timed", d_head), ("stated", d_stated)):
+            for name, d in (("timed", d_head), ("stated", d_stated), ("mixed", d_mixed)):
                 if d is None:
                     continue
                 est = d[torch.from_numpy(nodes).cuda()].cpu().numpy()
@@ -559,7 +588,8 @@ def main():
                             "stderr": float(rel.std(ddof=1) / math.sqrt(len(rel))),
                             "max_rel_err": float(rel.max()),
                             "plugin_err": err if name == "timed" else
-                            out.get("stated_setting", {}).get("err_estimate")}
+                            out.get({"stated": "stated_setting"}.get(name, name), {})
+                            .get("err_estimate")}
             out["true_error"] = te
             out["accuracy_gate_1pct_true"] = bool(te["timed"]["mean_rel_err"] <= 0.01)
             gs.close()

@@ -166,8 +166,9 @@ void rbmc_ctx_destroy(rbmc_ctx* ctx);
 
 /* Build Q(theta) matrix-free (stencil coefficients on the device) and plan
  * the decomposition: cores, Omega_p* and S_p per Alg. 4, block-Jacobi cores.
- * Errors: RBMC_E_ARG for mx,my < 2, T < 1, h <= 0, |rho| >= 1, non-finite
- * theta, decomposition counts outside [1, len], overlap_hops < 0. */
+ * Errors: RBMC_E_ARG for mx,my < 2, T < 1, mx my T >= 2^31 (node indices
+ * of a sample are 32-bit), h <= 0, |rho| >= 1, non-finite theta,
+ * decomposition counts outside [1, len], overlap_hops < 0. */
 rbmc_status rbmc_model_create(rbmc_ctx* ctx, const rbmc_model_desc* desc,
                               const rbmc_decomp_desc* decomp, rbmc_model** out);
 void rbmc_model_destroy(rbmc_model* m);

@@ -395,10 +395,11 @@ class Model:
         rbmc_apply_op(self.m, op, x, y, n_rhs)
         return y
 
-    def sample(self, z, rtol=1e-8, maxit=5000, precond=RBMC_PC_BJ):
+    def sample(self, z, rtol=1e-8, maxit=5000, precond=RBMC_PC_BJ, precision=RBMC_FP64):
         z = z.contiguous()
         x = self.torch.empty((z.shape[0], self.n), dtype=self.torch.float64, device=self.dev)
-        st, rep = rbmc_sample(self.m, make_opts(z.shape[0], maxit, rtol, precond=precond), z, x)
+        st, rep = rbmc_sample(self.m, make_opts(z.shape[0], maxit, rtol, precision=precision,
+                                                precond=precond), z, x)
         return x, st, rep
 
     def solve(self, b, rtol=1e-8, maxit=5000, precond=RBMC_PC_BJ):

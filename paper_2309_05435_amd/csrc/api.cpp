@@ -642,7 +642,7 @@ struct Op {
   // 7 outer gather, 8 outer fix, 9 sweep finish, 10 profile begin, 11 profile end, 12 mirror,
   // 13 off-diagonal pattern entries, 14-19 Kronecker-form kernels (region, build,
   // reduce, det, time mix, observed gather), 20 fill with zeros, 21 spectral
-  // tridiagonal solves, 22 direct DCT along one axis
+  // tridiagonal solves, 22 direct DCT along one axis, 23 FFT DCT along one axis
   int kind;
   size_t off = 0;
   int n = 0, tiles = 0;
@@ -1239,7 +1239,7 @@ struct HostCols {
   std::vector<int> len, model;
   std::vector<size_t> base, zbase;  // per model
   size_t total = 0, ztotal = 0;
-  int max_len = 0, max_tiles = 0, max_ns = 0;
+  int max_len = 0, max_tiles = 0, max_ns = 0, max_T = 0;
 };
 
 // kernels over columns put the column index in grid.y
@@ -1263,6 +1263,7 @@ HostCols make_cols(const std::vector<rbmc_model*>& ms, int nk) {
     h.ztotal += (size_t)(m->plan.n + m->n_obs) * nk;
     h.max_len = std::max(h.max_len, m->plan.n);
     h.max_ns = std::max(h.max_ns, m->plan.ns);
+    h.max_T = std::max(h.max_T, m->plan.T);
     h.max_tiles = std::max(h.max_tiles, stencil_tiles(m->plan.mx, m->plan.my));
   }
   return h;
@@ -1340,6 +1341,7 @@ ColSet colset(rbmc_ctx* cx, const HostCols& h) {
   c.max_len = h.max_len;
   c.max_tiles = h.max_tiles;
   c.max_ns = h.max_ns;
+  c.max_T = h.max_T;
   c.off = cx->d_off;
   c.in_off = cx->d_in_off;
   c.len = cx->d_len;
@@ -4070,6 +4072,7 @@ rbmc_status rbmc_apply_op_noalloc(rbmc_model* m, int op, const double* x, double
   cs.max_len = m->plan.n;
   cs.max_tiles = stencil_tiles(m->plan.mx, m->plan.my);
   cs.max_ns = m->plan.ns;
+  cs.max_T = m->plan.T;
   cs.off = t.off;
   cs.in_off = t.in_off;
   cs.len = t.len;

@@ -1,13 +1,16 @@
 // Matrix-free space-time operators and the PCG vector kernels.
 //
-// Q = Q_t (x) Q_s + D is applied as a 3-point time combination followed by
-// the 13-point spatial stencil of Q_s:
-//   (Q x)_t = Q_s (q_{t,t-1} x_{t-1} + q_{t,t} x_t + q_{t,t+1} x_{t+1}) + D_t x_t.
+// Q = Q_t (x) Q_s + D is applied as the 13-point spatial stencil of Q_s on
+// each time layer followed by a 3-point time combination:
+//   u_t = Q_s x_t,   (Q x)_t = q_{t,t-1} u_{t-1} + q_{t,t} u_t + q_{t,t+1} u_{t+1} + D_t x_t.
 // A workgroup owns a 32 x 16 spatial tile of one column (model, sample) and
-// walks through time, keeping the three time layers of the tile (with a halo
-// of 2) in LDS, so each x value is read from HBM once per application.  The
-// spatial stencil coefficients of a thread's two nodes do not depend on time:
-// they are read once, into registers, before the walk.
+// walks through time.  Each layer of the tile (with a halo of 2) passes once
+// through LDS (two slots, alternating by step parity); a thread keeps the
+// stencil results u of its two nodes for three consecutive layers in
+// registers, so every x value is read from HBM once per application and each
+// step needs a single barrier.  The spatial stencil coefficients of a thread's
+// two nodes do not depend on time: they are read once, into registers, before
+// the walk.
 //
 // All kernels work on column sets: a column is one sample of one model, with
 // its own length and offset, so one launch serves many uneven models.
@@ -47,11 +50,10 @@ __device__ inline void time_weights(const DevModel& m, int kind, int t, double& 
 // KIND: 0 Q, 1 dQ/dlog kappa, 2 dQ/dlog tau, 3 dQ/drho, 4 dQ/dlog sigma, 5 F.
 // Grid (max tiles, columns); DOT: partial sums of x.y per (column, tile).
 template <int KIND, bool DOT>
-__global__ __launch_bounds__(NTHR) void k_space_time_op(ColSet cs, const double* __restrict__ x,
+__global__ __launch_bounds__(NTHR, 4) void k_space_time_op(ColSet cs, const double* __restrict__ x,
                                                         double* __restrict__ y,
                                                         double* __restrict__ partial) {
-  __shared__ double slot[3][HY][HX];
-  __shared__ double w[HY][HX];
+  __shared__ double slot[2][HY * HX];
   __shared__ double red[NTHR];
   const int col = blockIdx.y;
   const DevModel& m = cs.dms[cs.model[col]];
@@ -66,105 +68,130 @@ __global__ __launch_bounds__(NTHR) void k_space_time_op(ColSet cs, const double*
   const int bx = (tile % ntx) * TX, by = (tile / ntx) * TY;
   const double* xk = x + (KIND == 5 ? cs.in_off[col] : cs.off[col]);
   double* yk = y + cs.off[col];
+  const int T = m.T;
+  // a sample's node indices fit 32 bits (the planner refuses larger models)
+  const uint32_t ns = (uint32_t)m.ns;
   const int lx = tid % TX, ly = tid / TX;  // ly in [0, 8): rows ly and ly + 8
-  // stencil coefficients of the thread's two nodes (13 for Q_s, 5 for K, F_s)
-  constexpr int NC = (KIND == 0 || KIND == 2 || KIND == 3) ? kNS : (KIND == 4 ? 1 : kN5);
-  const double* __restrict__ cf_src = (KIND == 1) ? m.kk : (KIND == 5) ? m.fs : m.qs;
-  double cf[2][NC];
+  // the thread's two nodes: spatial index (0 outside the grid) and whether inside
+  int sn[2];
+  bool in[2];
 #pragma unroll
-  for (int half = 0; half < 2; ++half) {
-    const int gx = bx + lx, gy = by + ly + 8 * half;
-    const bool in = gx < m.mx && gy < m.my;
-    const int s = in ? gy * m.mx + gx : 0;
-#pragma unroll
-    for (int q = 0; q < NC; ++q) cf[half][q] = (KIND != 4 && in) ? cf_src[(size_t)q * m.ns + s] : 0.0;
+  for (int h = 0; h < 2; ++h) {
+    const int gx = bx + lx, gy = by + ly + 8 * h;
+    in[h] = gx < m.mx && gy < m.my;
+    sn[h] = in[h] ? gy * m.mx + gx : 0;
   }
-
-  // A layer (the tile with its halo of 2) is fetched into registers two steps
-  // ahead of its store to LDS (two register buffers, alternating by step
-  // parity), so its loads are in flight during two steps' arithmetic.  The
-  // loads are unconditional: entries outside the grid or the time range read
-  // element 0 and are stored as 0.
-  constexpr int NL = (HX * HY + NTHR - 1) / NTHR;  // entries per thread
-  double preA[NL], preB[NL];
-  bool okA[NL], okB[NL];
-  auto fetch = [&](int t, double (&pre)[NL], bool (&pre_ok)[NL]) {
-#pragma unroll
-    for (int j = 0; j < NL; ++j) {
-      const int e = tid + NTHR * j;
-      const int hx = e % HX, hy = e / HX;
-      const int gx = bx + hx - 2, gy = by + hy - 2;
-      const bool ok = e < HX * HY && t >= 0 && t < m.T && gx >= 0 && gx < m.mx && gy >= 0 &&
-                      gy < m.my;
-      pre[j] = xk[ok ? (size_t)t * m.ns + gy * m.mx + gx : 0];
-      pre_ok[j] = ok;
-    }
-  };
-  auto put = [&](int buf, const double (&pre)[NL], const bool (&pre_ok)[NL]) {
-#pragma unroll
-    for (int j = 0; j < NL; ++j) {
-      const int e = tid + NTHR * j;
-      if (e < HX * HY) slot[buf][e / HX][e % HX] = pre_ok[j] ? pre[j] : 0.0;
-    }
-  };
-
   double acc = 0.0;
-  // one output step t: layer t + 1 from the register buffer (pre, ok) into
-  // LDS, layer t + 3 fetched into the same buffer
-  auto step = [&](int t, double (&pre)[NL], bool (&pre_ok)[NL]) {
-    const int bm = (t + 2) % 3, b0 = t % 3, bp = (t + 1) % 3;  // t-1, t, t+1
-    if (KIND != 4) {
-      put(bp, pre, pre_ok);
-      fetch(t + 3, pre, pre_ok);  // zeros beyond the last step
-      __syncthreads();
-      double wm, w0, wp;
-      time_weights(m, KIND, t, wm, w0, wp);
-      for (int e = tid; e < HX * HY; e += NTHR) {
-        int hx = e % HX, hy = e / HX;
-        w[hy][hx] = wm * slot[bm][hy][hx] + w0 * slot[b0][hy][hx] + wp * slot[bp][hy][hx];
-      }
-      __syncthreads();
-    }
+  if (KIND == 4) {  // diagonal only: -2 D
+    for (int t = 0; t < T; ++t) {
 #pragma unroll
-    for (int half = 0; half < 2; ++half) {
-      const int gx = bx + lx, gy = by + ly + 8 * half;
-      if (gx < m.mx && gy < m.my) {
-        const int s = gy * m.mx + gx;
-        const size_t i = (size_t)t * m.ns + s;
-        const int hx = lx + 2, hy = ly + 8 * half + 2;
-        double v = 0.0;
-        if (KIND == 0 || KIND == 2 || KIND == 3) {
-#pragma unroll
-          for (int q = 0; q < kNS; ++q) v += cf[half][q] * w[hy + kSdy[q]][hx + kSdx[q]];
-        } else if (KIND == 1) {
-#pragma unroll
-          for (int q = 0; q < kN5; ++q) v += cf[half][q] * w[hy + kSdy[q]][hx + kSdx[q]];
-        } else if (KIND == 5) {
-#pragma unroll
-          for (int q = 0; q < kN5; ++q) v += cf[half][q] * w[hy + kSdy[q]][hx + kSdx[q]];
-          if (obs_at(m, i)) v += sqrt(m.dobs) * xk[(size_t)m.n + obs_rank_at(m, i)];
-        }
-        // D from the observation bits (L2-resident), x at the node from LDS
-        if (KIND == 0 && obs_at(m, i)) v += m.dobs * slot[b0][hy][hx];
-        if (KIND == 4) v = obs_at(m, i) ? -2.0 * m.dobs * xk[i] : 0.0;
+      for (int h = 0; h < 2; ++h) {
+        if (!in[h]) continue;
+        const size_t i = (size_t)t * ns + sn[h];
+        const double xi = xk[i];
+        const double v = obs_at(m, i) ? -2.0 * m.dobs * xi : 0.0;
         yk[i] = v;
-        if (DOT) acc += v * (KIND == 4 ? xk[i] : slot[b0][hy][hx]);
+        if (DOT) acc += v * xi;
       }
     }
-    if (KIND != 4) __syncthreads();
-  };
-  // the layer of step t lives in slot t mod 3 (step -1 in slot 2)
-  if (KIND != 4) {
-    fetch(-1, preA, okA);
-    put(2, preA, okA);
-    fetch(0, preA, okA);
-    put(0, preA, okA);
-    fetch(1, preA, okA);
-    fetch(2, preB, okB);
+  } else {
+    // stencil coefficients of the thread's two nodes (13 for Q_s, 5 for K, F_s)
+    constexpr int NC = (KIND == 0 || KIND == 2 || KIND == 3) ? kNS : kN5;
+    const double* __restrict__ cf_src = (KIND == 1) ? m.kk : (KIND == 5) ? m.fs : m.qs;
+    double cf[2][NC];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int q = 0; q < NC; ++q) cf[h][q] = in[h] ? cf_src[(size_t)q * ns + sn[h]] : 0.0;
+
+    // halo entries e = tid + NTHR j of the tile: spatial offset and whether
+    // inside the grid (fixed over time).  A layer is fetched into registers two
+    // steps ahead of its store to LDS (two register buffers, alternating by
+    // step parity), so its loads are in flight during two steps' arithmetic.
+    // The loads are unconditional: entries outside the grid or the time range
+    // read element 0 and are stored as 0.
+    constexpr int NL = (HX * HY + NTHR - 1) / NTHR;
+    int hoff[NL];
+    bool hin[NL];
+#pragma unroll
+    for (int j = 0; j < NL; ++j) {
+      const int e = tid + NTHR * j;
+      const int gx = bx + e % HX - 2, gy = by + e / HX - 2;
+      hin[j] = e < HX * HY && gx >= 0 && gx < m.mx && gy >= 0 && gy < m.my;
+      hoff[j] = hin[j] ? gy * m.mx + gx : 0;
+    }
+    double preA[NL], preB[NL];
+#define RBMC_ST_FETCH(TT, PRE)                                                        \
+  _Pragma("unroll") for (int j = 0; j < NL; ++j) {                                  \
+    const bool ok_ = hin[j] && (TT) < T;                                            \
+    const double v_ = xk[ok_ ? (uint32_t)(TT) * ns + hoff[j] : 0u];                    \
+    PRE[j] = ok_ ? v_ : 0.0;                                                        \
   }
-  for (int t = 0; t < m.T; t += 2) {
-    step(t, preA, okA);
-    if (t + 1 < m.T) step(t + 1, preB, okB);
+#define RBMC_ST_PUT(BUF, PRE)                                                         \
+  _Pragma("unroll") for (int j = 0; j < NL; ++j) {                                  \
+    const int e_ = tid + NTHR * j;                                                  \
+    if (e_ < HX * HY) slot[BUF][e_] = PRE[j];                                       \
+  }
+    // LDS index of each node's centre
+    int ctr[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) ctr[h] = (ly + 8 * h + 2) * HX + lx + 2;
+    auto stencil = [&](int buf, int h) {
+      const double* sl = slot[buf] + ctr[h];
+      double v = 0.0;
+#pragma unroll
+      for (int q = 0; q < NC; ++q) v += cf[h][q] * sl[kSdy[q] * HX + kSdx[q]];
+      return v;
+    };
+    double um[2] = {0.0, 0.0}, u0[2], up[2];
+    // one output step t: layer t + 1 from the register buffer into slot
+    // (t + 1) & 1, layer t + 3 fetched into the same buffer, u_{t+1} from LDS.
+    // Slot (t + 1) & 1 was last read before the previous step's barrier (x_{t-1}
+    // at the nodes) or after the barrier before it (u_{t-1}).
+#define RBMC_ST_STEP(TT, PRE)                                                         \
+  {                                                                                 \
+    const int t_ = (TT);                                                            \
+    double wm, w0, wp;                                                              \
+    time_weights(m, KIND, t_, wm, w0, wp);                                          \
+    double xt[2];                                                                   \
+    uint32_t ob[2];                                                                 \
+    _Pragma("unroll") for (int h = 0; h < 2; ++h) {                                 \
+      xt[h] = slot[t_ & 1][ctr[h]];                                                 \
+      ob[h] = (KIND == 0 || KIND == 5) ? m.obs_bits[((uint32_t)t_ * ns + sn[h]) >> 5] : 0u; \
+    }                                                                               \
+    RBMC_ST_PUT((t_ + 1) & 1, PRE)                                                  \
+    RBMC_ST_FETCH(t_ + 3, PRE)                                                      \
+    __syncthreads();                                                                \
+    _Pragma("unroll") for (int h = 0; h < 2; ++h) {                                 \
+      up[h] = stencil((t_ + 1) & 1, h);                                             \
+      const uint32_t i = (uint32_t)t_ * ns + sn[h];                                 \
+      const bool o = (ob[h] >> (i & 31)) & 1u;                                      \
+      double v = wm * um[h] + w0 * u0[h] + wp * up[h];                              \
+      if (KIND == 0 && o) v += m.dobs * xt[h];                                      \
+      if (KIND == 5 && o) v += sqrt(m.dobs) * xk[(size_t)m.n + obs_rank_at(m, i)];  \
+      if (in[h]) {                                                                  \
+        yk[i] = v;                                                                  \
+        if (DOT) acc += v * xt[h];                                                  \
+      }                                                                             \
+      um[h] = u0[h];                                                                \
+      u0[h] = up[h];                                                                \
+    }                                                                               \
+  }
+    // layer 0 into slot 0 and u_0; layers 1 and 2 in flight
+    RBMC_ST_FETCH(0, preA)
+    RBMC_ST_PUT(0, preA)
+    RBMC_ST_FETCH(1, preA)
+    RBMC_ST_FETCH(2, preB)
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) u0[h] = stencil(0, h);
+    for (int t = 0; t < T; t += 2) {
+      RBMC_ST_STEP(t, preA)
+      if (t + 1 < T) RBMC_ST_STEP(t + 1, preB)
+    }
+#undef RBMC_ST_STEP
+#undef RBMC_ST_PUT
+#undef RBMC_ST_FETCH
   }
   if (DOT) {
     red[tid] = acc;
@@ -406,23 +433,75 @@ void launch_spec_coef(const SpecCoefTask& t, hipStream_t s) {
   if (t.ns > 0) k_spec_coef<<<(t.ns + 255) / 256, 256, 0, s>>>(t);
 }
 
-// grid (frequency blocks of the largest model, columns).  The walk in time
-// goes in chunks of kSpecCh steps: the chunk's loads are issued together,
-// then the recurrence runs in registers and the chunk is stored.
+// One thread per (column, frequency f): the tridiagonal solve of the T values
+// y[t ns + f].  Column-major grid (columns in grid.x, frequency blocks in
+// grid.y) when the frequency blocks fit grid.y: the workgroups resident at
+// one time then share their frequencies, so the coefficients c'_t and
+// 1 / den_t of those frequencies are read from HBM about once per XCD instead
+// of once per column.
 namespace {
 constexpr int kSpecCh = 8;
-}
 
-__global__ __launch_bounds__(256) void k_spec_solve(ColSet cs, double* __restrict__ y) {
-  const int col = blockIdx.y;
-  const DevModel& m = cs.dms[cs.model[col]];
-  const int f = blockIdx.x * 256 + threadIdx.x;
+struct SpecIdx {
+  int col, f;
+};
+__device__ inline SpecIdx spec_idx(int colfast) {
+  return colfast ? SpecIdx{(int)blockIdx.x, (int)(blockIdx.y * 256 + threadIdx.x)}
+                 : SpecIdx{(int)blockIdx.y, (int)(blockIdx.x * 256 + threadIdx.x)};
+}
+}  // namespace
+
+// T <= TR: the column lives in registers (one read and one write of y); the
+// loads of each sweep's coefficients are issued together.
+template <int TR>
+__global__ __launch_bounds__(256) void k_spec_solve_reg(ColSet cs, double* __restrict__ y,
+                                                        int colfast) {
+  const SpecIdx ix = spec_idx(colfast);
+  const DevModel& m = cs.dms[cs.model[ix.col]];
+  const int f = ix.f;
   if (f >= m.ns || m.sp_cp == nullptr) return;
-  const gptr<double> yk = G(y + cs.off[col]);
+  const gptr<double> yk = G(y + cs.off[ix.col]);
   const gptr<const double> id = G((const double*)m.sp_id), cp = G((const double*)m.sp_cp);
   const double a = m.sp_off[f];
   const int T = m.T;
-  const size_t ns = m.ns;
+  // a sample's node indices fit 32 bits (the planner refuses larger models)
+  const uint32_t ns = (uint32_t)m.ns;
+  double v[TR];
+#pragma unroll
+  for (int t = 0; t < TR; ++t)
+    if (t < T) v[t] = yk[t * ns + f];
+  double prev = 0.0;
+#pragma unroll
+  for (int t = 0; t < TR; ++t)  // forward elimination
+    if (t < T) {
+      prev = (v[t] - a * prev) * id[t * ns + f];
+      v[t] = prev;
+    }
+#pragma unroll
+  for (int t = TR - 2; t >= 0; --t)  // back substitution
+    if (t < T - 1) {
+      prev = v[t] - cp[t * ns + f] * prev;
+      v[t] = prev;
+    }
+#pragma unroll
+  for (int t = 0; t < TR; ++t)
+    if (t < T) yk[t * ns + f] = v[t];
+}
+
+// Any T: the walk in time goes in chunks of kSpecCh steps (the chunk's loads
+// are issued together, then the recurrence runs in registers and the chunk is
+// stored); the forward results pass through y.
+__global__ __launch_bounds__(256) void k_spec_solve(ColSet cs, double* __restrict__ y,
+                                                    int colfast) {
+  const SpecIdx ix = spec_idx(colfast);
+  const DevModel& m = cs.dms[cs.model[ix.col]];
+  const int f = ix.f;
+  if (f >= m.ns || m.sp_cp == nullptr) return;
+  const gptr<double> yk = G(y + cs.off[ix.col]);
+  const gptr<const double> id = G((const double*)m.sp_id), cp = G((const double*)m.sp_cp);
+  const double a = m.sp_off[f];
+  const int T = m.T;
+  const uint32_t ns = (uint32_t)m.ns;
   double prev = 0.0, v[kSpecCh], c[kSpecCh];
   for (int t0 = 0; t0 < T; t0 += kSpecCh) {  // forward elimination
 #pragma unroll
@@ -465,7 +544,19 @@ __global__ __launch_bounds__(256) void k_spec_solve(ColSet cs, double* __restric
 void launch_spec_solve(const ColSet& cs, double* y, hipStream_t s) {
   if (cs.ncols <= 0) return;
   // the largest model's spatial size bounds the frequency index
-  k_spec_solve<<<dim3((cs.max_ns + 255) / 256, cs.ncols), 256, 0, s>>>(cs, y);
+  const int fb = (cs.max_ns + 255) / 256;
+  const int colfast = fb <= 65535 ? 1 : 0;
+  const dim3 grid = colfast ? dim3(cs.ncols, fb) : dim3(fb, cs.ncols);
+  if (cs.max_T <= 16)
+    k_spec_solve_reg<16><<<grid, 256, 0, s>>>(cs, y, colfast);
+  else if (cs.max_T <= 32)
+    k_spec_solve_reg<32><<<grid, 256, 0, s>>>(cs, y, colfast);
+  else if (cs.max_T <= 48)
+    k_spec_solve_reg<48><<<grid, 256, 0, s>>>(cs, y, colfast);
+  else if (cs.max_T <= 64)
+    k_spec_solve_reg<64><<<grid, 256, 0, s>>>(cs, y, colfast);
+  else
+    k_spec_solve<<<grid, 256, 0, s>>>(cs, y, colfast);
 }
 
 // Direct transform along one axis for models without the GEMM route:

@@ -62,6 +62,8 @@ static int find_region(Plan& plan, int x0, int x1, int y0, int y1, int hops) {
 
 std::string make_plan(const rbmc_model_desc& d, const rbmc_decomp_desc& dc, Plan& plan) {
   if (d.mx < 2 || d.my < 2 || d.T < 1) return "grid needs mx, my >= 2 and T >= 1";
+  // the kernels index the nodes of one sample with 32-bit integers
+  if ((long long)d.mx * d.my * d.T >= (1LL << 31)) return "mx my T must be below 2^31";
   if (dc.n_tslabs < 1 || dc.n_tslabs > d.T) return "n_tslabs must lie in [1, T]";
   if (dc.n_tiles_x < 1 || dc.n_tiles_x > d.mx) return "n_tiles_x must lie in [1, mx]";
   if (dc.n_tiles_y < 1 || dc.n_tiles_y > d.my) return "n_tiles_y must lie in [1, my]";

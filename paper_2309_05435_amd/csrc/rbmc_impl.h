@@ -143,6 +143,7 @@ struct ColSet {
   int max_len;
   int max_tiles;             // stencil tiles of the largest model
   int max_ns;                // spatial nodes of the largest model
+  int max_T;                 // time steps of the longest model
   const int64_t* off;
   const int64_t* in_off;
   const int* len;

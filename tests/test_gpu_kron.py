@@ -142,10 +142,14 @@ def test_kron_and_blocktri_agree_mid_size():
     gm.close()
 
 
-@pytest.mark.parametrize("case", [(12, 8, 3, 1, 1), (14, 9, 3, 2, 1), (37, 5, 2, 1, 1)])
+@pytest.mark.parametrize("case", [(12, 8, 3, 1, 1), (14, 9, 3, 2, 1), (37, 5, 2, 1, 1),
+                                  (16, 20, 2, 1, 1), (16, 40, 2, 1, 1), (16, 60, 2, 1, 1),
+                                  (16, 70, 2, 1, 1)])
 def test_spectral_sampler_matches_exact_solve(case):
     """Spectral-preconditioned PCG against the oracle's banded-Cholesky solve:
-    ||x - x*|| <= cond(Q) rtol ||x*||; the residual is checked directly."""
+    ||x - x*|| <= cond(Q) rtol ||x*||; the residual is checked directly.  The
+    time lengths cover each register size of the tridiagonal solve (T <= 16,
+    32, 48, 64) and the chunked walk beyond 64."""
     m, T, P, tiles, n_l = case
     wl = wl_of(m, T, P, tiles, n_l)
     say("spectral sampler", case)

@@ -62,3 +62,16 @@ def test_planner_rejects_bad_arguments(bad):
     with pytest.raises(B.RbmcError) as e:
         B.rbmc_plan_query(desc, dc, 0, label_out=lab)
     assert e.value.status == B.RBMC_E_ARG
+
+
+def test_planner_rejects_models_beyond_32_bit_node_indices():
+    """A sample's node indices are 32-bit in the kernels: mx my T >= 2^31 is
+    refused before anything is read or allocated (2^31 - 1 nodes would pass
+    this check)."""
+    mask = np.zeros(1, np.uint8)  # never read: the size check comes first
+    for mx, my, T in ((8192, 8192, 32), (65536, 65536, 1)):
+        desc, _m = B.make_desc(mx, my, T, 1.0, (2.0, 0.0, 0.9, 0.0), mask)
+        with pytest.raises(B.RbmcError) as e:
+            B.rbmc_plan_query(desc, B.rbmc_decomp_desc(1, 1, 1, 0), 0)
+        assert e.value.status == B.RBMC_E_ARG
+        assert "2^31" in str(e.value)
