@@ -22,48 +22,56 @@ __device__ inline v4d mfma64(double a, double b, v4d c) {
 
 // ---------------------------------------------------------------------------
 // Grouped GEMM.  Workgroup tile 128 x 128 (four waves of 64 x 64), BK = 16.
-// LDS holds A and B tiles with k contiguous per row/column (stride 18 to
-// spread banks).  In MFMA step s lane group g = l/16 contributes k = 4g + s,
-// so each lane reads its four k values of a row with one 32-byte access.
+// In MFMA step s lane group g = l/16 contributes k = 4g + s.  LDS layouts,
+// chosen so that the stores of a tile and the fragment reads are free of bank
+// conflicts:
+//   - A^T operand, B operand (k contiguous in memory): row m (or column n) of
+//     the tile holds its 16 k values, rows 18 apart; a lane reads its four k
+//     of a row with one 32-byte access;
+//   - A operand (m contiguous in memory): k row of the tile holds its 128 m
+//     values, rows 132 apart; a lane reads its four k with 8-byte accesses.
+//     Each global load instruction covers two consecutive m per lane over 16
+//     lanes (256 contiguous bytes), stored the same way.
+// The transposes and whether the tile lies wholly inside C are template
+// parameters of the K loop (a uniform branch per workgroup picks the
+// instance), so the interior tiles run without bounds checks.
 // ---------------------------------------------------------------------------
 namespace {
 constexpr int GBM = 128, GBN = 128, GBK = 16, GLDS = GBK + 2;
-}
+constexpr int GAM = GBM + 4;  // k-row stride of the m-major A tile
+constexpr int GAS = GBM * GLDS > GBK * GAM ? GBM * GLDS : GBK * GAM;
 
 // Each thread moves 8 doubles of the A tile and 8 of the B tile per K step.
-// Rows/columns that are contiguous in memory go to contiguous LDS (k-major
-// per row); the other orientation is written with a stride.
 struct TileRegs {
   double2 v[4];
 };
 
-__device__ inline void load_a(const GemmTask& tk, int m0, int k0, int tid, TileRegs& r) {
-  if (!tk.transA) {  // column-major A: 8 consecutive rows of one column k
-    const int kk = tid >> 4, mm = (tid & 15) * 8, gm = m0 + mm;
-    const gptr<const double> src = G(tk.A) + (size_t)(k0 + kk) * tk.lda + gm;
+template <int TA, bool FULL>
+__device__ __forceinline__ void load_a(const GemmTask& tk, int m0, int k0, int tid, TileRegs& r) {
+  if (!TA) {  // k row tid / 16; m pairs at 2 (tid % 16) + 32 j
+    const int kk = tid >> 4, mb = 2 * (tid & 15);
+    const gptr<const double> src = G(tk.A) + (size_t)(k0 + kk) * tk.lda + m0 + mb;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int c = gm + 2 * j;
-      if (c + 1 < tk.M) r.v[j] = ldg2(src + 2 * j);
-      else r.v[j] = double2{c < tk.M ? src[2 * j] : 0.0, 0.0};
+      const int c = m0 + mb + 32 * j;
+      if (FULL || c + 1 < tk.M) r.v[j] = ldg2(src + 32 * j);
+      else r.v[j] = double2{c < tk.M ? src[32 * j] : 0.0, 0.0};
     }
   } else {  // A^T stored column-major: 8 consecutive k of one row m
     const int mm = tid >> 1, kk = (tid & 1) * 8, gm = m0 + mm;
     const gptr<const double> src = G(tk.A) + (size_t)gm * tk.lda + k0 + kk;
 #pragma unroll
     for (int j = 0; j < 4; ++j)
-      r.v[j] = (gm < tk.M) ? ldg2(src + 2 * j) : double2{0.0, 0.0};
+      r.v[j] = (FULL || gm < tk.M) ? ldg2(src + 2 * j) : double2{0.0, 0.0};
   }
 }
 
-__device__ inline void store_a(const GemmTask& tk, int tid, const TileRegs& r, double* As) {
-  if (!tk.transA) {
-    const int kk = tid >> 4, mm = (tid & 15) * 8;
+template <int TA>
+__device__ __forceinline__ void store_a(int tid, const TileRegs& r, double* As) {
+  if (!TA) {
+    const int kk = tid >> 4, mb = 2 * (tid & 15);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      As[(mm + 2 * j) * GLDS + kk] = r.v[j].x;
-      As[(mm + 2 * j + 1) * GLDS + kk] = r.v[j].y;
-    }
+    for (int j = 0; j < 4; ++j) *(double2*)&As[kk * GAM + mb + 32 * j] = r.v[j];
   } else {
     const int mm = tid >> 1, kk = (tid & 1) * 8;
 #pragma unroll
@@ -71,27 +79,29 @@ __device__ inline void store_a(const GemmTask& tk, int tid, const TileRegs& r, d
   }
 }
 
-__device__ inline void load_b(const GemmTask& tk, int n0, int k0, int tid, TileRegs& r) {
-  if (!tk.transB) {  // column-major B: 8 consecutive k of one column n
+template <int TB, bool FULL>
+__device__ __forceinline__ void load_b(const GemmTask& tk, int n0, int k0, int tid, TileRegs& r) {
+  if (!TB) {  // column-major B: 8 consecutive k of one column n
     const int nn = tid >> 1, kk = (tid & 1) * 8, gn = n0 + nn;
     const gptr<const double> src = G(tk.B) + (size_t)gn * tk.ldb + k0 + kk;
 #pragma unroll
     for (int j = 0; j < 4; ++j)
-      r.v[j] = (gn < tk.N) ? ldg2(src + 2 * j) : double2{0.0, 0.0};
+      r.v[j] = (FULL || gn < tk.N) ? ldg2(src + 2 * j) : double2{0.0, 0.0};
   } else {  // B^T stored column-major: 8 consecutive n of one row k
     const int kk = tid >> 4, nn = (tid & 15) * 8, gn = n0 + nn;
     const gptr<const double> src = G(tk.B) + (size_t)(k0 + kk) * tk.ldb + gn;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int c = gn + 2 * j;
-      if (c + 1 < tk.N) r.v[j] = ldg2(src + 2 * j);
+      if (FULL || c + 1 < tk.N) r.v[j] = ldg2(src + 2 * j);
       else r.v[j] = double2{c < tk.N ? src[2 * j] : 0.0, 0.0};
     }
   }
 }
 
-__device__ inline void store_b(const GemmTask& tk, int tid, const TileRegs& r, double* Bs) {
-  if (!tk.transB) {
+template <int TB>
+__device__ __forceinline__ void store_b(int tid, const TileRegs& r, double* Bs) {
+  if (!TB) {
     const int nn = tid >> 1, kk = (tid & 1) * 8;
 #pragma unroll
     for (int j = 0; j < 4; ++j) *(double2*)&Bs[nn * GLDS + kk + 2 * j] = r.v[j];
@@ -105,6 +115,65 @@ __device__ inline void store_b(const GemmTask& tk, int tid, const TileRegs& r, d
   }
 }
 
+// The K loop of one tile.  The next A/B tiles are prefetched into registers
+// while the matrix cores consume the current LDS tiles; the LDS tiles are
+// double-buffered, so one barrier per K step separates the stores of step
+// k + 1 from the reads of step k.
+template <int TA, int TB, bool FULL>
+__device__ __forceinline__ void gemm_tile(const GemmTask& tk, int m0, int n0, v4d (&acc)[4][4],
+                                          double* As0, double* As1, double* Bs0, double* Bs1) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int l16 = lane & 15, g = lane >> 4;
+  TileRegs ra, rb;
+  load_a<TA, FULL>(tk, m0, 0, tid, ra);
+  load_b<TB, FULL>(tk, n0, 0, tid, rb);
+  store_a<TA>(tid, ra, As0);
+  store_b<TB>(tid, rb, Bs0);
+  __syncthreads();
+  const int K = tk.K;
+  int k0 = 0;
+  auto step = [&](const double* Ac, const double* Bc, double* An, double* Bn) {
+    const bool more = k0 + GBK < K;
+    if (more) {
+      load_a<TA, FULL>(tk, m0, k0 + GBK, tid, ra);
+      load_b<TB, FULL>(tk, n0, k0 + GBK, tid, rb);
+    }
+    double a[4][4], bb[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (!TA) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) a[i][s] = Ac[(4 * g + s) * GAM + wm + i * 16 + l16];
+      } else {
+        const double* pa = &Ac[(wm + i * 16 + l16) * GLDS + 4 * g];
+        const double2 x0 = *(const double2*)pa, x1 = *(const double2*)(pa + 2);
+        a[i][0] = x0.x; a[i][1] = x0.y; a[i][2] = x1.x; a[i][3] = x1.y;
+      }
+      const double* pb = &Bc[(wn + i * 16 + l16) * GLDS + 4 * g];
+      const double2 y0 = *(const double2*)pb, y1 = *(const double2*)(pb + 2);
+      bb[i][0] = y0.x; bb[i][1] = y0.y; bb[i][2] = y1.x; bb[i][3] = y1.y;
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = mfma64(bb[j][s], a[i][s], acc[i][j]);
+    if (more) {  // the other buffer was last read before the previous barrier
+      store_a<TA>(tid, ra, An);
+      store_b<TB>(tid, rb, Bn);
+    }
+    __syncthreads();
+    k0 += GBK;
+  };
+  while (k0 < K) {
+    step(As0, Bs0, As1, Bs1);
+    if (k0 < K) step(As1, Bs1, As0, Bs0);
+  }
+}
+}  // namespace
+
 int gemm_task_tiles(int M, int N, int lower, int ts) {
   const int tm = (M + ts - 1) / ts, tn = (N + ts - 1) / ts;
   return lower ? tm * (tm + 1) / 2 : tm * tn;
@@ -112,16 +181,13 @@ int gemm_task_tiles(int M, int N, int lower, int ts) {
 
 // Workgroups are dispatched round-robin over the 8 XCDs; the logical tile of
 // a workgroup is chosen so that each XCD walks a contiguous range of tiles
-// (neighbouring tiles share A row panels in its L2).  The K loop prefetches
-// the next A/B tiles into registers while the matrix cores consume the
-// current LDS tiles; the LDS tiles are double-buffered, so one barrier per
-// K step separates the stores of step k + 1 from the reads of step k.
+// (neighbouring tiles share A row panels in its L2).  K is a multiple of 16.
 // TAG only names the instantiation (1: the spectral transforms), so kernel
 // traces and counters separate the two uses; the code is the same.
 template <int TAG>
 __global__ __launch_bounds__(256, 2) void k_gemm_f64(const GemmTask* __restrict__ tasks,
                                                      int n_tasks, int total_tiles, int per_xcd) {
-  __shared__ double As[2][GBM * GLDS];
+  __shared__ double As[2][GAS];
   __shared__ double Bs[2][GBN * GLDS];
   const int b = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
   if (b >= total_tiles) return;
@@ -157,43 +223,16 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(const GemmTask* __restrict_
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
-
-  TileRegs ra, rb;
-  load_a(tk, m0, 0, tid, ra);
-  load_b(tk, n0, 0, tid, rb);
-  store_a(tk, tid, ra, As[0]);
-  store_b(tk, tid, rb, Bs[0]);
-  __syncthreads();
-  int buf = 0;
-  for (int k0 = 0; k0 < tk.K; k0 += GBK) {
-    const bool more = k0 + GBK < tk.K;
-    if (more) {
-      load_a(tk, m0, k0 + GBK, tid, ra);
-      load_b(tk, n0, k0 + GBK, tid, rb);
-    }
-    double a[4][4], bb[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const double* pa = &As[buf][(wm + i * 16 + l16) * GLDS + 4 * g];
-      double2 x0 = *(const double2*)pa, x1 = *(const double2*)(pa + 2);
-      a[i][0] = x0.x; a[i][1] = x0.y; a[i][2] = x1.x; a[i][3] = x1.y;
-      const double* pb = &Bs[buf][(wn + i * 16 + l16) * GLDS + 4 * g];
-      double2 y0 = *(const double2*)pb, y1 = *(const double2*)(pb + 2);
-      bb[i][0] = y0.x; bb[i][1] = y0.y; bb[i][2] = y1.x; bb[i][3] = y1.y;
-    }
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = mfma64(bb[j][s], a[i][s], acc[i][j]);
-    if (more) {  // the other buffer was last read before the previous barrier
-      store_a(tk, tid, ra, As[buf ^ 1]);
-      store_b(tk, tid, rb, Bs[buf ^ 1]);
-    }
-    __syncthreads();
-    buf ^= 1;
-  }
+  const bool full = m0 + GBM <= tk.M && n0 + GBN <= tk.N;
+  const int tt = tk.transA * 2 + tk.transB;
+#define RBMC_GEMM_TILE(TA_, TB_)                                                       \
+  (full ? gemm_tile<TA_, TB_, true>(tk, m0, n0, acc, As[0], As[1], Bs[0], Bs[1])      \
+        : gemm_tile<TA_, TB_, false>(tk, m0, n0, acc, As[0], As[1], Bs[0], Bs[1]))
+  if (tt == 0) RBMC_GEMM_TILE(0, 0);
+  else if (tt == 1) RBMC_GEMM_TILE(0, 1);
+  else if (tt == 2) RBMC_GEMM_TILE(1, 0);
+  else RBMC_GEMM_TILE(1, 1);
+#undef RBMC_GEMM_TILE
   // ---- epilogue: C = alpha acc + beta Cin.  The products were formed as
   // (B^T A^T) tiles, so register r of lane l holds C[16 i + l%16][16 j + l/16
   // + 4 r]: 16 consecutive rows of a column per lane group (128-byte segments).
