@@ -41,6 +41,19 @@ __device__ __forceinline__ int fft_vpos(int m, int N) {
 __device__ __forceinline__ int fft_rev(int i, int lg) {
   return (int)(__brev((unsigned)i) >> (32 - lg));
 }
+
+// LDS placement of the complex value at logical index x (x < 2048): bits 0-4
+// are XORed with functions of bits 5-10, a bijection that spreads the strided
+// butterfly accesses and the bit-reversed scatter over the 64 LDS banks (bank
+// conflicts of every access pattern of the transform counted for lengths 16 to
+// 2048 with a 64-bank, 4-byte model: about a quarter of those of the identity
+// placement, none worse than 2-way).
+__device__ __forceinline__ int fsw(int x) {
+  return x ^ ((x >> 6) & 31) ^ ((x >> 5) & 15) ^ (((x >> 6) & 7) << 2);
+}
+// placement of twiddle pair t (t < 1024), read as one 16-byte access: the
+// stage strides N / 2h become distinct banks
+__device__ __forceinline__ int tsw(int t) { return t ^ ((t >> 4) & 15) ^ ((t >> 8) & 3); }
 }  // namespace
 
 // AXIS 0: lines are contiguous (element stride 1, consecutive lines mx
@@ -51,9 +64,9 @@ __global__ __launch_bounds__(kFftThreads, 4) void k_dct_fft(const FftTask* __res
                                                             int n_tasks) {
   extern __shared__ double fft_lds[];  // zr, zi (kFftSlots each), then N/2 twiddle pairs
   __shared__ long lbase[2 * kFftSlots / 16];  // offsets of the workgroup's lines
-  double* zr = fft_lds;
+  double* zr = fft_lds;  // value x at fsw(x)
   double* zi = fft_lds + kFftSlots;
-  double* twl = fft_lds + 2 * kFftSlots;
+  double2* twl = (double2*)(fft_lds + 2 * kFftSlots);  // pair t at tsw(t)
   const FftTask tk = tasks[fft_find(tasks, n_tasks, blockIdx.x)];
   // N = 2^lg, P = 2^(11 - lg) line pairs, L = 2P lines: index math by shifts
   const int N = tk.N, lg = tk.lg, lp = 11 - lg, ll = lp + 1, P = 1 << lp, L = 1 << ll;
@@ -63,7 +76,7 @@ __global__ __launch_bounds__(kFftThreads, 4) void k_dct_fft(const FftTask* __res
   const gptr<double> out = G(tk.out);
   const gptr<const double> tw = G(tk.tw), ph = G(tk.ph);
   const long est = tk.estride;
-  for (int q = threadIdx.x; q < N; q += kFftThreads) twl[q] = tw[q];
+  for (int q = threadIdx.x; q < N / 2; q += kFftThreads) twl[tsw(q)] = double2{tw[2 * q], tw[2 * q + 1]};
   for (int i = threadIdx.x; i < L; i += kFftThreads) {
     const long g = g0 + i;
     lbase[i] = (g / tk.nl) * tk.sstride + (g % tk.nl) * tk.lstride;
@@ -88,7 +101,7 @@ __global__ __launch_bounds__(kFftThreads, 4) void k_dct_fft(const FftTask* __res
       const int q = threadIdx.x + r * kFftThreads;
       const int i = AXIS == 0 ? q >> lg : q & (L - 1);
       const int m = AXIS == 0 ? q & (N - 1) : q >> ll;
-      const int at = (i >> 1) * N + fft_rev(fft_vpos(m, N), lg);
+      const int at = fsw((i >> 1) * N + fft_rev(fft_vpos(m, N), lg));
       if (i & 1) zi[at] = v[r]; else zr[at] = v[r];
     }
   } else {
@@ -125,7 +138,7 @@ __global__ __launch_bounds__(kFftThreads, 4) void k_dct_fft(const FftTask* __res
         const double yb = y[r0][2] * inv_k, yrb = y[r0][3] * inv_r;
         const double va_r = c[r0] * ya + s[r0] * yra, va_i = s[r0] * ya - c[r0] * yra;
         const double vb_r = c[r0] * yb + s[r0] * yrb, vb_i = s[r0] * yb - c[r0] * yrb;
-        const int at = p * N + fft_rev(k, lg);
+        const int at = fsw(p * N + fft_rev(k, lg));
         zr[at] = va_r - vb_i;
         zi[at] = va_i + vb_r;
       }
@@ -146,27 +159,29 @@ __global__ __launch_bounds__(kFftThreads, 4) void k_dct_fft(const FftTask* __res
       const int j = b & (h - 1);
       const int i0 = (p << lg) + ((b >> lh) << (lh + 2)) + j;
       const int t1 = j * (N >> (lh + 1)), t2 = j * (N >> (lh + 2));
-      const double w1r = twl[2 * t1], w1i = -sgn * twl[2 * t1 + 1];
-      const double w2r = twl[2 * t2], w2i = -sgn * twl[2 * t2 + 1];
+      const double2 w1 = twl[tsw(t1)], w2 = twl[tsw(t2)];
+      const double w1r = w1.x, w1i = -sgn * w1.y;
+      const double w2r = w2.x, w2i = -sgn * w2.y;
       const double w3r = sgn * w2i, w3i = -sgn * w2r;  // -+i w2
-      const double a0r = zr[i0], a0i = zi[i0];
-      const double a1r = zr[i0 + h], a1i = zi[i0 + h];
-      const double a2r = zr[i0 + 2 * h], a2i = zi[i0 + 2 * h];
-      const double a3r = zr[i0 + 3 * h], a3i = zi[i0 + 3 * h];
+      const int x0 = fsw(i0), x1 = fsw(i0 + h), x2 = fsw(i0 + 2 * h), x3 = fsw(i0 + 3 * h);
+      const double a0r = zr[x0], a0i = zi[x0];
+      const double a1r = zr[x1], a1i = zi[x1];
+      const double a2r = zr[x2], a2i = zi[x2];
+      const double a3r = zr[x3], a3i = zi[x3];
       const double m1r = w1r * a1r - w1i * a1i, m1i = w1r * a1i + w1i * a1r;
       const double m3r = w1r * a3r - w1i * a3i, m3i = w1r * a3i + w1i * a3r;
       const double b0r = a0r + m1r, b0i = a0i + m1i, b1r = a0r - m1r, b1i = a0i - m1i;
       const double b2r = a2r + m3r, b2i = a2i + m3i, b3r = a2r - m3r, b3i = a2i - m3i;
       const double n2r = w2r * b2r - w2i * b2i, n2i = w2r * b2i + w2i * b2r;
       const double n3r = w3r * b3r - w3i * b3i, n3i = w3r * b3i + w3i * b3r;
-      zr[i0] = b0r + n2r;
-      zi[i0] = b0i + n2i;
-      zr[i0 + 2 * h] = b0r - n2r;
-      zi[i0 + 2 * h] = b0i - n2i;
-      zr[i0 + h] = b1r + n3r;
-      zi[i0 + h] = b1i + n3i;
-      zr[i0 + 3 * h] = b1r - n3r;
-      zi[i0 + 3 * h] = b1i - n3i;
+      zr[x0] = b0r + n2r;
+      zi[x0] = b0i + n2i;
+      zr[x2] = b0r - n2r;
+      zi[x2] = b0i - n2i;
+      zr[x1] = b1r + n3r;
+      zi[x1] = b1i + n3i;
+      zr[x3] = b1r - n3r;
+      zi[x3] = b1i - n3i;
     }
     __syncthreads();
   }
@@ -175,8 +190,9 @@ __global__ __launch_bounds__(kFftThreads, 4) void k_dct_fft(const FftTask* __res
     for (int r = 0; r < kFftSlots / 2 / kFftThreads; ++r) {
       const int u = threadIdx.x + r * kFftThreads;
       const int p = u >> (lg - 1), j = u & ((N >> 1) - 1);
-      const int i0 = p * N + j, i1 = i0 + h;
-      const double wr = twl[2 * j], wi = -sgn * twl[2 * j + 1];
+      const int i0 = fsw(p * N + j), i1 = fsw(p * N + j + h);
+      const double2 w = twl[tsw(j)];
+      const double wr = w.x, wi = -sgn * w.y;
       const double ar = zr[i1], ai = zi[i1];
       const double tr = wr * ar - wi * ai, ti = wr * ai + wi * ar;
       const double br = zr[i0], bi = zi[i0];
@@ -196,8 +212,9 @@ __global__ __launch_bounds__(kFftThreads, 4) void k_dct_fft(const FftTask* __res
       const int k = AXIS == 0 ? q & (N - 1) : q >> ll;
       const int p = i >> 1, kr = (N - k) & (N - 1);
       const double c = ph[2 * k], s = ph[2 * k + 1];
-      const double ar = zr[p * N + k], ai = zi[p * N + k];
-      const double br = zr[p * N + kr], bi = zi[p * N + kr];
+      const int xk = fsw(p * N + k), xr = fsw(p * N + kr);
+      const double ar = zr[xk], ai = zi[xk];
+      const double br = zr[xr], bi = zi[xr];
       // V_A = (Z_k + conj Z_{N-k}) / 2,  V_B = (Z_k - conj Z_{N-k}) / 2i
       const double vr = (i & 1) ? 0.5 * (ai + bi) : 0.5 * (ar + br);
       const double vi = (i & 1) ? -0.5 * (ar - br) : 0.5 * (ai - bi);
@@ -211,7 +228,7 @@ __global__ __launch_bounds__(kFftThreads, 4) void k_dct_fft(const FftTask* __res
       const int q = threadIdx.x + r * kFftThreads;
       const int i = AXIS == 0 ? q >> lg : q & (L - 1);
       const int m = AXIS == 0 ? q & (N - 1) : q >> ll;
-      const int at = (i >> 1) * N + fft_vpos(m, N);
+      const int at = fsw((i >> 1) * N + fft_vpos(m, N));
       if (g0 + i < nlines) out[base(i) + m * est] = scale * ((i & 1) ? zi[at] : zr[at]);
     }
   }
