@@ -115,62 +115,79 @@ __device__ __forceinline__ void store_b(int tid, const TileRegs& r, double* Bs) 
   }
 }
 
-// The K loop of one tile.  The next A/B tiles are prefetched into registers
-// while the matrix cores consume the current LDS tiles; the LDS tiles are
-// double-buffered, so one barrier per K step separates the stores of step
-// k + 1 from the reads of step k.
+// The K loop of one tile.  The A/B tiles of steps k + 1 and k + 2 are in
+// registers (loads in flight) while the matrix cores consume step k from LDS;
+// the LDS tiles are double-buffered, so one barrier per K step separates the
+// stores of step k + 1 from the reads of step k.  Each step's fragments are
+// read in two halves (k = 4g + {0, 1}, then 4g + {2, 3}), which keeps the
+// second prefetch within the register budget; the products are accumulated
+// in the same order as with whole fragments.
 template <int TA, int TB, bool FULL>
 __device__ __forceinline__ void gemm_tile(const GemmTask& tk, int m0, int n0, v4d (&acc)[4][4],
                                           double* As0, double* As1, double* Bs0, double* Bs1) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
   const int l16 = lane & 15, g = lane >> 4;
-  TileRegs ra, rb;
-  load_a<TA, FULL>(tk, m0, 0, tid, ra);
-  load_b<TB, FULL>(tk, n0, 0, tid, rb);
-  store_a<TA>(tid, ra, As0);
-  store_b<TB>(tid, rb, Bs0);
+  const int nk = tk.K / GBK;
+  TileRegs ga[2], gb[2];
+  load_a<TA, FULL>(tk, m0, 0, tid, ga[0]);
+  load_b<TB, FULL>(tk, n0, 0, tid, gb[0]);
+  if (nk > 1) {
+    load_a<TA, FULL>(tk, m0, GBK, tid, ga[1]);
+    load_b<TB, FULL>(tk, n0, GBK, tid, gb[1]);
+  }
+  store_a<TA>(tid, ga[0], As0);
+  store_b<TB>(tid, gb[0], Bs0);
   __syncthreads();
-  const int K = tk.K;
-  int k0 = 0;
-  auto step = [&](const double* Ac, const double* Bc, double* An, double* Bn) {
-    const bool more = k0 + GBK < K;
-    if (more) {
-      load_a<TA, FULL>(tk, m0, k0 + GBK, tid, ra);
-      load_b<TB, FULL>(tk, n0, k0 + GBK, tid, rb);
-    }
-    double a[4][4], bb[4][4];
+  auto half = [&](const double* Ac, const double* Bc, int h) {
+    double a[4][2], bb[4][2];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       if (!TA) {
 #pragma unroll
-        for (int s = 0; s < 4; ++s) a[i][s] = Ac[(4 * g + s) * GAM + wm + i * 16 + l16];
+        for (int s = 0; s < 2; ++s) a[i][s] = Ac[(4 * g + 2 * h + s) * GAM + wm + i * 16 + l16];
       } else {
-        const double* pa = &Ac[(wm + i * 16 + l16) * GLDS + 4 * g];
-        const double2 x0 = *(const double2*)pa, x1 = *(const double2*)(pa + 2);
-        a[i][0] = x0.x; a[i][1] = x0.y; a[i][2] = x1.x; a[i][3] = x1.y;
+        const double2 x = *(const double2*)&Ac[(wm + i * 16 + l16) * GLDS + 4 * g + 2 * h];
+        a[i][0] = x.x;
+        a[i][1] = x.y;
       }
-      const double* pb = &Bc[(wn + i * 16 + l16) * GLDS + 4 * g];
-      const double2 y0 = *(const double2*)pb, y1 = *(const double2*)(pb + 2);
-      bb[i][0] = y0.x; bb[i][1] = y0.y; bb[i][2] = y1.x; bb[i][3] = y1.y;
+      const double2 y = *(const double2*)&Bc[(wn + i * 16 + l16) * GLDS + 4 * g + 2 * h];
+      bb[i][0] = y.x;
+      bb[i][1] = y.y;
     }
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
+    for (int s = 0; s < 2; ++s)
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = mfma64(bb[j][s], a[i][s], acc[i][j]);
-    if (more) {  // the other buffer was last read before the previous barrier
-      store_a<TA>(tid, ra, An);
-      store_b<TB>(tid, rb, Bn);
-    }
-    __syncthreads();
-    k0 += GBK;
   };
-  while (k0 < K) {
-    step(As0, Bs0, As1, Bs1);
-    if (k0 < K) step(As1, Bs1, As0, Bs0);
+  // step k (P = k & 1): LDS buffer P holds step k, registers [P] are free for
+  // step k + 2, registers [1 - P] hold step k + 1; buffer 1 - P was last read
+  // before the previous barrier
+#define RBMC_GEMM_STEP(P)                                                          \
+  {                                                                                \
+    double* Ac = P ? As1 : As0;                                                    \
+    double* Bc = P ? Bs1 : Bs0;                                                    \
+    if (k + 2 < nk) {                                                              \
+      load_a<TA, FULL>(tk, m0, (k + 2) * GBK, tid, ga[P]);                         \
+      load_b<TB, FULL>(tk, n0, (k + 2) * GBK, tid, gb[P]);                         \
+    }                                                                              \
+    half(Ac, Bc, 0);                                                               \
+    half(Ac, Bc, 1);                                                               \
+    if (k + 1 < nk) {                                                              \
+      store_a<TA>(tid, ga[1 - P], P ? As0 : As1);                                  \
+      store_b<TB>(tid, gb[1 - P], P ? Bs0 : Bs1);                                  \
+    }                                                                              \
+    __syncthreads();                                                               \
+    ++k;                                                                           \
   }
+  int k = 0;
+  while (k < nk) {
+    RBMC_GEMM_STEP(0)
+    if (k < nk) RBMC_GEMM_STEP(1)
+  }
+#undef RBMC_GEMM_STEP
 }
 }  // namespace
 
