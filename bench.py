@@ -40,7 +40,7 @@ PEAK_FP32_TFLOPS = 157.3   # MI355X dense FP32 matrix
 KERNEL_OF = {"gemm": "k_gemm_f64<0>", "gemm_small": "k_gemm_f64s", "gemm_mixed": "k_gemm_mx",
              "inv_small": "k_inv128", "spmm": "k_space_time_op", "rstencil": "k_rstencil",
              "panels": "k_panels", "spd_inverse": "gauss_jordan", "offdiag": "k_offdiag",
-             "dct": "k_dct_fft", "kron_reduce": "k_kron_reduce", "spec_solve": "k_spec_solve",
+             "dct": "k_dct_fft", "kron_reduce": "k_kron_reduce", "spec_solve": "k_spec_solve_reg",
              "mc": "k_mc", "tmix": "k_kron_tmix"}
 
 
