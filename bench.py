@@ -307,8 +307,8 @@ def main():
     ap.add_argument("--budget-s", type=float, default=600.0,
                     help="wall-time budget: legs after the timed steps run only if their "
                          "projected end stays within it")
-    ap.add_argument("--legs", default="stated,mixed,true_error,cpu,plain,batched",
-                    help="legs after the timed steps, in order (subset of stated,mixed,"
+    ap.add_argument("--legs", default="stated,mixed,probe,true_error,cpu,plain,batched",
+                    help="legs after the timed steps, in order (subset of stated,mixed,probe,"
                          "true_error,cpu,plain,batched; empty for none)")
     ap.add_argument("--true-error-nodes", type=int, default=256)
     ap.add_argument("--pc", default="1,32,32",
@@ -550,6 +550,23 @@ def main():
                 "trace_rel_diff_vs_fp64": [abs(a - b) / abs(b) for a, b in zip(trm, tr)]}
             say(f"mixed: {sec:.2f} s ({ms / (sec * 1e3):.3f}x), {rm.pcg_it_max} PCG "
                 f"iterations, diag vs FP64 mean {float(rel_d.mean()):.2e}")
+        elif leg == "probe":
+            # the overlap suggested by the posterior correlation range at the
+            # domain centre (one solve), against the workload's n_l
+            if not budget_ok(30.0, "probe") or not gm.m:
+                continue
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            pr = {}
+            for eps in (1e-1, 1e-2, 1e-3):
+                st, lags, _, _ = B.rbmc_probe_overlap(
+                    gm.m, B.make_opts(1, 500, 1e-12, precond=B.RBMC_PC_SPECTRAL), eps)
+                pr[f"{eps:g}"] = {"time_lag": int(lags[0]), "space_lag": int(lags[1]),
+                                  "suggested_overlap_hops": int(lags[2])}
+            sec = time.perf_counter() - ta
+            out["probe"] = {"workload_overlap_hops": wl.n_l, "by_eps": pr, "seconds": sec,
+                            "solve_rtol": 1e-12}
+            say(f"probe: {pr} in {sec:.1f} s (workload n_l = {wl.n_l})")
         elif leg == "true_error":
             if not budget_ok(60.0, "true_error"):
                 continue

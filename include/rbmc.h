@@ -220,6 +220,31 @@ rbmc_status rbmc_sample(rbmc_model* m, const rbmc_est_opts* opts, const double* 
 rbmc_status rbmc_solve(rbmc_model* m, const rbmc_est_opts* opts, const double* b, double* x,
                        rbmc_report* rep);
 
+/* Overlap from the posterior correlation range.  Sec. 3.2.2 takes n_l as
+ * the lag at which the correlation falls to about zero, with separate time
+ * and space values; Sec. 5 proposes probing the posterior range for it.  One
+ * solve Q y = e_c (rbmc_solve with opts' preconditioner, tolerance and
+ * iteration cap) at the centre node c = (T/2, my/2, mx/2) (integer halves)
+ * gives the covariance column; its ratios y_j / y_c stand for the
+ * correlations (Sigma_jc / Sigma_cc: the marginal variance near the centre
+ * taken as uniform).
+ *   lags[0] time lag: the smallest d >= 1 with |y_j| <= eps y_c at every
+ *           node j = (t, my/2, mx/2), |t - T/2| >= d (graph hops in time);
+ *   lags[1] space lag: the smallest L >= 1 with |y_j| <= eps y_c at every
+ *           node j of step T/2 at L1 grid distance >= L from the centre;
+ *   lags[2] suggested overlap_hops = max(lags[0], ceil(lags[1] / 2)) (one
+ *           hop of Q's graph moves one step in time and up to two grid steps
+ *           in space; rbmc_decomp_desc grows both with one count).
+ * A lag one past the largest distance in the grid means the correlation did
+ * not fall below eps inside the domain.
+ * corr_time (host, T values, or NULL): y_j / y_c at (t, my/2, mx/2);
+ * corr_space (host, mx my values, or NULL): y_j / y_c at step T/2.
+ * Allocates and frees 2 n doubles of device memory.  Errors: RBMC_E_ARG for
+ * NULL m, opts or lags, or eps outside (0, 1); the status of the solve
+ * (RBMC_W_NOT_CONVERGED is returned with the lags of the last iterate). */
+rbmc_status rbmc_probe_overlap(rbmc_model* m, const rbmc_est_opts* opts, double eps,
+                               int32_t* lags, double* corr_time, double* corr_space);
+
 /* The estimator from given samples (Alg. 4 for the diagonal; Alg. 3 rows
  * with eq:hyperpar:4 for the traces): for each core p,
  *   diag_i = (Q_AA^-1)_ii + (1/n_k) sum_k (mu_k)_i^2,  i in Omega_p,

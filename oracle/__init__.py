@@ -255,3 +255,35 @@ def csr_logdet(A: CSR) -> float:
     if info != 0:
         raise RuntimeError("oracle: matrix not SPD")
     return out.value
+
+
+def probe_overlap(M: OracleModel, eps: float, rtol: float = 1e-13):
+    """The overlap choice of Sec. 3.2.2 (n_l = the lag at which the correlation
+    falls to about zero, separately in time and space) from one covariance
+    column, as Sec. 5 proposes probing the posterior range.
+
+    y = Q^-1 e_c at the centre node c = (T // 2, my // 2, mx // 2), by the
+    oracle's conjugate gradients on the whole Q.  Ratios y_j / y_c:
+      time:  at (t, my // 2, mx // 2) for every step t;
+      space: at every node of step T // 2.
+    lag = the smallest distance d >= 1 (steps; L1 grid distance) such that
+    every ratio at distance >= d has magnitude <= eps.  Suggested hops:
+    max(time lag, ceil(space lag / 2)), one hop of Q's graph covering one step
+    and up to two grid steps.  Returns (lags, corr_time, corr_space)."""
+    mx, my, T = M.mx, M.my, M.T
+    ns = mx * my
+    tc, cx, cy = T // 2, mx // 2, my // 2
+    c = tc * ns + cy * mx + cx
+    e = np.zeros(M.n)
+    e[c] = 1.0
+    y, _ = M.cg(e, rtol=rtol)
+    r = y / y[c]
+    corr_time = r[np.arange(T) * ns + cy * mx + cx]
+    corr_space = r[tc * ns:(tc + 1) * ns].copy()
+    dt = np.abs(np.arange(T) - tc)
+    lag_t = 1 + max([int(d) for d, v in zip(dt, corr_time) if abs(v) > eps], default=0)
+    iy, ix = np.divmod(np.arange(ns), mx)
+    dist = np.abs(ix - cx) + np.abs(iy - cy)
+    big = np.abs(corr_space) > eps
+    lag_s = 1 + (int(dist[big].max()) if big.any() else 0)
+    return np.array([lag_t, lag_s, max(lag_t, (lag_s + 1) // 2)]), corr_time, corr_space

@@ -28,7 +28,7 @@ EXPORTS = ["rbmc_ctx_create", "rbmc_ctx_destroy", "rbmc_model_create", "rbmc_mod
            "rbmc_ctx_profile_read", "rbmc_precond_train", "rbmc_precond_apply",
            "rbmc_precond_get_weights", "rbmc_precond_set_weights", "rbmc_precond_info",
            "rbmc_ctx_get_tune", "rbmc_ctx_set_tune", "rbmc_autotune", "rbmc_last_error",
-           "rbmc_normals", "rbmc_apply_op_noalloc", "rbmc_solve"]
+           "rbmc_normals", "rbmc_apply_op_noalloc", "rbmc_solve", "rbmc_probe_overlap"]
 RBMC_PC_NWEIGHTS = 15120
 # (cin, cout) of the learned correction's four convolutions, in weight order
 PC_LAYERS = [(2, 16), (16, 16), (16, 16), (16, 1)]
@@ -117,6 +117,7 @@ def lib():
         L.rbmc_apply_op_noalloc.argtypes = [vp, C.c_int, vp, vp, C.c_int32]
         L.rbmc_sample.argtypes = [vp, C.POINTER(rbmc_est_opts), vp, vp, C.POINTER(rbmc_report)]
         L.rbmc_solve.argtypes = [vp, C.POINTER(rbmc_est_opts), vp, vp, C.POINTER(rbmc_report)]
+        L.rbmc_probe_overlap.argtypes = [vp, C.POINTER(rbmc_est_opts), C.c_double, vp, vp, vp]
         L.rbmc_estimate_from_samples.argtypes = [vp, C.POINTER(rbmc_est_opts), vp, vp,
                                                  C.POINTER(C.c_double), C.POINTER(rbmc_report)]
         L.rbmc_estimate.argtypes = [vp, C.POINTER(rbmc_est_opts), vp, C.c_uint64, vp,
@@ -198,6 +199,19 @@ def rbmc_apply_op(m, op, x, y, n_rhs):
 def rbmc_apply_op_noalloc(m, op, x, y, n_rhs):
     """Enqueued on the context stream, not synchronized."""
     return check(lib().rbmc_apply_op_noalloc(m, op, _ptr(x), _ptr(y), n_rhs))
+
+
+def rbmc_probe_overlap(m, opts, eps, T=0, ns=0):
+    """(status, lags [time, space, suggested hops], corr_time (T), corr_space
+    (ns)); the profiles are returned when T and ns are given."""
+    import numpy as np
+    lags = np.zeros(3, np.int32)
+    ct = np.zeros(T) if T else None
+    cs = np.zeros(ns) if ns else None
+    ptr = lambda a: None if a is None else a.ctypes.data_as(C.c_void_p)  # noqa: E731
+    st = check(lib().rbmc_probe_overlap(m, C.byref(opts), C.c_double(eps), ptr(lags), ptr(ct),
+                                        ptr(cs)))
+    return st, lags, ct, cs
 
 
 def rbmc_solve(m, opts, b, x):
@@ -408,6 +422,12 @@ class Model:
         x = self.torch.empty((b.shape[0], self.n), dtype=self.torch.float64, device=self.dev)
         st, rep = rbmc_solve(self.m, make_opts(b.shape[0], maxit, rtol, precond=precond), b, x)
         return x, st, rep
+
+    def probe_overlap(self, eps=1e-3, rtol=1e-12, maxit=2000, precond=RBMC_PC_BJ):
+        """(status, lags, corr_time, corr_space) of rbmc_probe_overlap."""
+        T = self.wl.T
+        return rbmc_probe_overlap(self.m, make_opts(1, maxit, rtol, precond=precond), eps, T,
+                                  self.n // T)
 
     def estimate_from_samples(self, x, grad_mask=0b111, method=RBMC_SEL_AUTO,
                               precision=RBMC_FP64):

@@ -4128,6 +4128,63 @@ rbmc_status rbmc_solve(rbmc_model* m, const rbmc_est_opts* opts, const double* b
   return st;
 }
 
+rbmc_status rbmc_probe_overlap(rbmc_model* m, const rbmc_est_opts* opts, double eps,
+                               int32_t* lags, double* corr_time, double* corr_space) {
+  if (!m || !opts || !lags) return fail(RBMC_E_ARG, "NULL argument");
+  if (!(eps > 0.0 && eps < 1.0)) return fail(RBMC_E_ARG, "eps must lie in (0, 1)");
+  const Plan& P = m->plan;
+  const int ns = P.ns, T = P.T, mx = P.mx, my = P.my;
+  const int tc = T / 2, cx = mx / 2, cy = my / 2;
+  const size_t n = (size_t)P.n, c = (size_t)tc * ns + (size_t)cy * mx + cx;
+  HIPCHK(hipSetDevice(m->ctx->device));
+  double* d = nullptr;
+  HIPCHK(hipMalloc((void**)&d, 2 * n * sizeof(double)));
+  double* b = d;
+  double* y = d + n;
+  std::vector<double> hy(n);
+  rbmc_est_opts o = *opts;
+  o.n_samples = 1;
+  o.sample_chunk = 0;
+  rbmc_status st = RBMC_OK;
+  const double one = 1.0;
+  hipError_t e = hipMemsetAsync(b, 0, n * sizeof(double), m->ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b + c, &one, sizeof(double), hipMemcpyHostToDevice, m->ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(m->ctx->stream);
+  if (e == hipSuccess) {
+    st = rbmc_solve(m, &o, b, y, nullptr);
+    if (st >= 0) e = hipMemcpy(hy.data(), y, n * sizeof(double), hipMemcpyDeviceToHost);
+  }
+  (void)hipFree(d);
+  if (e != hipSuccess)
+    return fail(e == hipErrorOutOfMemory ? RBMC_E_OOM : RBMC_E_DEVICE, hipGetErrorString(e));
+  if (st < 0) return st;
+  const double yc = hy[c];
+  if (!(yc > 0.0)) return fail(RBMC_E_NOT_SPD, "non-positive variance at the probe node");
+  // time: the centre's spatial node at every step; space: every node of the
+  // centre's step, by L1 grid distance.  lag = the smallest distance from
+  // which on every ratio |y_j| / y_c is at most eps
+  const size_t sc = (size_t)cy * mx + cx;
+  int lag_t = 1;
+  for (int t = 0; t < T; ++t) {
+    const double r = hy[(size_t)t * ns + sc] / yc;
+    if (corr_time) corr_time[t] = r;
+    if (std::fabs(r) > eps) lag_t = std::max(lag_t, std::abs(t - tc) + 1);
+  }
+  int lag_s = 1;
+  for (int iy = 0; iy < my; ++iy)
+    for (int ix = 0; ix < mx; ++ix) {
+      const size_t s = (size_t)iy * mx + ix;
+      const double r = hy[(size_t)tc * ns + s] / yc;
+      if (corr_space) corr_space[s] = r;
+      if (std::fabs(r) > eps) lag_s = std::max(lag_s, std::abs(ix - cx) + std::abs(iy - cy) + 1);
+    }
+  lags[0] = lag_t;
+  lags[1] = lag_s;
+  lags[2] = std::max(lag_t, (lag_s + 1) / 2);
+  return st;
+}
+
 rbmc_status rbmc_estimate_from_samples(rbmc_model* m, const rbmc_est_opts* opts, const double* x,
                                        double* diag_out, double* trace_out, rbmc_report* rep) {
   init_report(rep);
