@@ -307,9 +307,9 @@ def main():
     ap.add_argument("--budget-s", type=float, default=600.0,
                     help="wall-time budget: legs after the timed steps run only if their "
                          "projected end stays within it")
-    ap.add_argument("--legs", default="stated,mixed,probe,true_error,cpu,plain,batched",
+    ap.add_argument("--legs", default="stated,mixed,probe,alg2,true_error,cpu,plain,batched",
                     help="legs after the timed steps, in order (subset of stated,mixed,probe,"
-                         "true_error,cpu,plain,batched; empty for none)")
+                         "alg2,true_error,cpu,plain,batched; empty for none)")
     ap.add_argument("--true-error-nodes", type=int, default=256)
     ap.add_argument("--pc", default="1,32,32",
                     help="block-Jacobi blocks 'slabs,tiles_x,tiles_y' of the plain leg, or 'cores'")
@@ -504,7 +504,7 @@ def main():
         say(f"skipping leg {name}: projected {est_s:.0f} s, {left:.0f} s left")
         return False
 
-    d_stated = d_mixed = None
+    d_stated = d_mixed = d_alg2 = None
     for leg in legs:
         if leg == "stated":
             if not budget_ok(3.0 * rep0.t_total, "stated") or not gm.m:
@@ -567,6 +567,40 @@ def main():
             out["probe"] = {"workload_overlap_hops": wl.n_l, "by_eps": pr, "seconds": sec,
                             "solve_rtol": 1e-12}
             say(f"probe: {pr} in {sec:.1f} s (workload n_l = {wl.n_l})")
+        elif leg == "alg2":
+            import numpy as np
+            # the non-overlapping variant (Alg. 2: separator layers between the
+            # same slabs and tiles, plain Monte Carlo on them) at the
+            # configuration's sample count, diagonal only; its own model
+            if not budget_ok(60.0, "alg2"):
+                continue
+            if gm.m:
+                gm.close()
+            torch.cuda.empty_cache()
+            ga = B.Model(wl, decomp=(wl.n_tslabs, wl.n_tiles, wl.n_tiles, 0, 0, 0, 0, 1),
+                         pc=None)
+            da = torch.empty(ga.n, dtype=torch.float64, device="cuda")
+            oa = B.make_opts(wl.n_k, pcg_maxit=500, pcg_rtol=wl.rtol, grad_mask=0,
+                             precond=B.RBMC_PC_SPECTRAL, method=B.RBMC_SEL_KRON)
+            B.rbmc_estimate(ga.m, oa, None, seed, da, 0)  # warm-up: loads and sizes
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            _, _, ra = B.rbmc_estimate(ga.m, oa, None, seed, da, 0)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - ta
+            lab = np.zeros(ga.n, np.int32)
+            B.rbmc_plan_query(ga.desc, ga.decomp, 0, label_out=lab)
+            d_alg2 = da.clone()
+            out["alg2"] = {"n_samples": wl.n_k, "value": ga.n / sec, "ms_per_estimate": sec * 1e3,
+                           "separator_nodes": int((lab < 0).sum()),
+                           "err_estimate": ra.err_estimate,
+                           "overlap_estimate_err_estimate":
+                               out.get("stated_setting", {}).get("err_estimate")}
+            ga.close()
+            del da
+            torch.cuda.empty_cache()
+            say(f"alg2: {sec:.2f} s, plug-in error {ra.err_estimate:.4f}, "
+                f"{int((lab < 0).sum())} separator nodes")
         elif leg == "true_error":
             if not budget_ok(60.0, "true_error"):
                 continue
@@ -596,7 +630,8 @@ def main():
             sec = time.perf_counter() - ta
             te = {"nodes": len(nodes), "node_seed": seed + 7, "solve_rtol": 1e-12,
                   "solve_pcg_iters_max": it_max, "seconds": sec}
-            for name, d in (("timed", d_head), ("stated", d_stated), ("mixed", d_mixed)):
+            for name, d in (("timed", d_head), ("stated", d_stated), ("mixed", d_mixed),
+                            ("alg2", d_alg2)):
                 if d is None:
                     continue
                 est = d[torch.from_numpy(nodes).cuda()].cpu().numpy()

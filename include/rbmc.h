@@ -80,9 +80,19 @@ typedef struct {
  * pc_tslabs > 0, in which case they are pc_tslabs time slabs x pc_tiles_x x
  * pc_tiles_y spatial boxes split by the same rule; the choice changes the
  * sampler's iteration count, not the samples it converges to. */
+/* separators = 1: the non-overlapping variant (Alg. 2).  The first step of
+ * every slab after the first and the first two grid lines (in x, in y) of
+ * every tile after the first form the separator S; the cores are the slabs
+ * and tiles without them (each slab after the first needs >= 2 steps, each
+ * tile after the first >= 3 lines), overlap_hops must be 0.  Q's graph
+ * reaches one step in time and L1 distance 2 in space, so S separates the
+ * cores: given x_S they are independent.  Core nodes get
+ * (Q_pp^-1)_ii + Var(Q_pp^-1 Q_pS x_S)_i, separator nodes Var(x_S)_i from
+ * the samples; traces are not defined (grad_mask must be 0). */
 typedef struct {
   int32_t n_tslabs, n_tiles_x, n_tiles_y, overlap_hops;
   int32_t pc_tslabs, pc_tiles_x, pc_tiles_y; /* 0 = same as the cores */
+  int32_t separators;                        /* 0: Alg. 4 cores; 1: Alg. 2 */
 } rbmc_decomp_desc;
 
 /* Precision.  RBMC_FP64: every step in FP64.  RBMC_MIXED: the dense

@@ -287,3 +287,17 @@ def probe_overlap(M: OracleModel, eps: float, rtol: float = 1e-13):
     big = np.abs(corr_space) > eps
     lag_s = 1 + (int(dist[big].max()) if big.any() else 0)
     return np.array([lag_t, lag_s, max(lag_t, (lag_s + 1) // 2)]), corr_time, corr_space
+
+
+def alg2(M: OracleModel, labels, n_parts, x):
+    """The non-overlapping estimator (Alg. 2): cores Omega_p (labels >= 0)
+    separated by S (label -1).  Core nodes: (Q_pp^-1)_ii plus the Monte
+    Carlo variance of Q_pp^-1 Q_pS x_S (the overlapping estimator with n_l = 0,
+    whose S_p = N(Omega_p) lies in S); separator nodes: Var(x_S)_i from the
+    zero-mean samples, (1/n_k) sum_k x_k[i]^2.  Returns the diagonal."""
+    x = np.ascontiguousarray(np.atleast_2d(x), np.float64) if x is not None and len(x) else \
+        np.zeros((0, M.n))
+    d = M.rbmc(labels, n_parts, 0, x, grad_mask=0)["diag"].copy()
+    sep = np.asarray(labels) < 0
+    d[sep] = (x[:, sep] ** 2).mean(axis=0) if x.shape[0] else 0.0
+    return d

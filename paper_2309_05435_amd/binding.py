@@ -53,7 +53,7 @@ class rbmc_model_desc(C.Structure):
 class rbmc_decomp_desc(C.Structure):
     _fields_ = [("n_tslabs", C.c_int32), ("n_tiles_x", C.c_int32), ("n_tiles_y", C.c_int32),
                 ("overlap_hops", C.c_int32), ("pc_tslabs", C.c_int32), ("pc_tiles_x", C.c_int32),
-                ("pc_tiles_y", C.c_int32)]
+                ("pc_tiles_y", C.c_int32), ("separators", C.c_int32)]
 
 
 class rbmc_est_opts(C.Structure):

@@ -356,6 +356,7 @@ struct rbmc_model {
   int* d_obs_rank = nullptr;
   uint32_t* d_obs_bits = nullptr;
   int* d_obs_wrank = nullptr;
+  int* d_sep = nullptr;  // Alg. 2 separator nodes (plan.sep_nodes)
   std::vector<RegionDev> regions;
   RegionDev* d_regions = nullptr;
   ChainSet bj, sub;
@@ -1892,6 +1893,28 @@ rbmc_status ensure_epart(rbmc_ctx* cx, const EstLayout& L) {
   return RBMC_OK;
 }
 
+// Alg. 2: the separator nodes' variance from the samples (x in the column
+// layout h, nk columns per model, each scaled by `scale`); accum = 0 starts
+// from zero.  Models without separators are skipped.
+void sep_variance(const std::vector<rbmc_model*>& ms, const HostCols& h, int nk, const double* x,
+                  double scale, int accum, const std::vector<double*>& diag_out, hipStream_t s) {
+  for (size_t j = 0; j < ms.size(); ++j) {
+    const rbmc_model* m = ms[j];
+    const int nsep = (int)m->plan.sep_nodes.size();
+    if (nsep == 0) continue;
+    launch_sep_var(m->d_sep, nsep, x ? x + h.base[j] : nullptr, m->plan.n, x ? nk : 0, scale,
+                   accum, diag_out[j], s);
+  }
+}
+
+// Alg. 2 defines variances only: no traces with separators
+rbmc_status sep_check(const std::vector<rbmc_model*>& ms, const rbmc_est_opts* o) {
+  for (const rbmc_model* m : ms)
+    if (m->plan.sep && o->grad_mask)
+      return fail(RBMC_E_UNSUPPORTED, "traces are not defined with separators (Alg. 2)");
+  return RBMC_OK;
+}
+
 // Traces and the plug-in error from the partial sums (host, fixed order):
 // the deterministic and Monte Carlo Frobenius products of each core step
 // weighted by the time coefficients of dQ_j (eq:hyperpar:4).
@@ -1949,6 +1972,9 @@ rbmc_status combine_traces(rbmc_ctx* cx, const EstLayout& L, const std::vector<r
       for (int b = 0; b < 4; ++b)
         if (o->grad_mask & (1u << b)) trace_out[j][k++] = tr[j][b];
     }
+  // Alg. 2 separator nodes: their estimate is all Monte Carlo (ratio 1)
+  if (nk > 0)
+    for (const rbmc_model* m : ms) ratio_sum += (double)m->plan.sep_nodes.size();
   if (rep) {
     // plug-in MC error: m_i ~ E[mu_i^2] chi2_{n_k} / n_k, so the mean absolute relative
     // error of the estimate is about sqrt(2/pi) sqrt(2/n_k) m_i / s2_i on average
@@ -1971,6 +1997,10 @@ rbmc_status estimate_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const
   g_tune = cx->tune;
   const int nk = o->n_samples;
   const int mixed = o->precision == RBMC_MIXED;
+  {
+    rbmc_status e = sep_check(ms, o);
+    if (e != RBMC_OK) return e;
+  }
   if (sampler) {
     rbmc_status e = ensure_streams(cx);
     if (e != RBMC_OK) return e;
@@ -2223,6 +2253,8 @@ rbmc_status estimate_set(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms, const
     HIPCHK(hipEventElapsedTime(&ms_fac, e_beg, e_fac));
     HIPCHK(hipEventElapsedTime(&ms_tak, e_fac, e_tak));
   }
+  sep_variance(ms, h, nk, x_base, nk > 0 ? 1.0 / nk : 0.0, 0, diag_out, cx->stream);
+  HIPCHK(hipGetLastError());
   // ---- traces: combine partial sums with the temporal weights ----
   st = combine_traces(cx, L, ms, nk, o, trace_out, rep);
   if (st != RBMC_OK) return st;
@@ -3331,6 +3363,10 @@ rbmc_status estimate_set_kron(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms,
                               const std::vector<double*>& trace_out, rbmc_report* rep) {
   g_tune = cx->tune;
   const int mixed = o->precision == RBMC_MIXED;
+  {
+    rbmc_status e = sep_check(ms, o);
+    if (e != RBMC_OK) return e;
+  }
   hipStream_t s = cx->stream;
   const int npass = nk_total > 0 ? (nk_total + chunk - 1) / chunk : 0;
   double t_fac = 0.0, t_cor = 0.0, t_smp = 0.0, ta = now_s();
@@ -3492,6 +3528,14 @@ rbmc_status estimate_set_kron(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms,
     }
     i0 = i1;
   }
+  // Alg. 2 separator nodes: their variance from the samples (with several
+  // passes zero here, so that the deterministic copy holds zero, then added
+  // per pass)
+  if (npass > 1)
+    sep_variance(ms, h1, 0, nullptr, 0.0, 0, diag_out, s);
+  else
+    sep_variance(ms, h1, nk1, nk1 > 0 ? x1 : nullptr, nk1 > 0 ? 1.0 / nk1 : 0.0, 0, diag_out, s);
+  HIPCHK(hipGetLastError());
   if (npass > 1) {
     for (size_t j = 0; j < ms.size(); ++j)
       HIPCHK(hipMemcpyAsync(ddet[j], diag_out[j], (size_t)ms[j]->plan.n * 8,
@@ -3517,6 +3561,8 @@ rbmc_status estimate_set_kron(rbmc_ctx* cx, const std::vector<rbmc_model*>& ms,
         if (st != RBMC_OK) return st;
         i0 = i1;
       }
+      sep_variance(ms, hc, kn, xc, 1.0 / nk_total, 1, diag_out, s);
+      HIPCHK(hipGetLastError());
       t_cor += now_s() - tb;
     }
   }
@@ -3952,6 +3998,10 @@ rbmc_status rbmc_model_create(rbmc_ctx* ctx, const rbmc_model_desc* desc,
     MCHK(hipMemcpy(m->d_obs_rank, rank.data(), (size_t)P.n * 4, hipMemcpyHostToDevice));
     MCHK(hipMemcpy(m->d_obs_bits, bits.data(), nwords * 4, hipMemcpyHostToDevice));
     MCHK(hipMemcpy(m->d_obs_wrank, wrank.data(), nwords * 4, hipMemcpyHostToDevice));
+  }
+  if (!P.sep_nodes.empty()) {
+    MCHK(m->pool.alloc((void**)&m->d_sep, P.sep_nodes.size() * 4));
+    MCHK(hipMemcpy(m->d_sep, P.sep_nodes.data(), P.sep_nodes.size() * 4, hipMemcpyHostToDevice));
   }
   DevModel& dm = m->dm;
   dm.mx = P.mx;

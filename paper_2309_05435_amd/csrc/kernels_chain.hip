@@ -501,6 +501,31 @@ __global__ __launch_bounds__(256) void k_mc(const McTask* __restrict__ tasks, in
   }
 }
 
+// Alg. 2: Var(x_S) from the zero-mean samples, one thread per separator node:
+// diag[sep[i]] = (accum ? diag[sep[i]] : 0) + scale sum_k x_k[sep[i]]^2,
+// column k of x at x + k ldx (no columns when nk = 0)
+__global__ __launch_bounds__(256) void k_sep_var(const int* __restrict__ sep, int nsep,
+                                                 const double* __restrict__ x, long ldx, int nk,
+                                                 double scale, int accum,
+                                                 double* __restrict__ diag) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= nsep) return;
+  const int node = G(sep)[i];
+  double acc = 0.0;
+  for (int k = 0; k < nk; ++k) {
+    const double v = G(x)[(size_t)k * ldx + node];
+    acc += v * v;
+  }
+  const gptr<double> d = G(diag);
+  d[node] = (accum ? d[node] : 0.0) + scale * acc;
+}
+
+void launch_sep_var(const int* sep, int nsep, const double* x, long ldx, int nk, double scale,
+                    int accum, double* diag, hipStream_t s) {
+  if (nsep <= 0) return;
+  k_sep_var<<<(nsep + 255) / 256, 256, 0, s>>>(sep, nsep, x, ldx, nk, scale, accum, diag);
+}
+
 int mc_max_steps() { return kMcS; }
 int mc_lds_doubles() { return kMcLds; }
 

@@ -68,6 +68,8 @@ std::string make_plan(const rbmc_model_desc& d, const rbmc_decomp_desc& dc, Plan
   if (dc.n_tiles_x < 1 || dc.n_tiles_x > d.mx) return "n_tiles_x must lie in [1, mx]";
   if (dc.n_tiles_y < 1 || dc.n_tiles_y > d.my) return "n_tiles_y must lie in [1, my]";
   if (dc.overlap_hops < 0) return "overlap_hops must be >= 0";
+  if (dc.separators != 0 && dc.separators != 1) return "separators must be 0 or 1";
+  if (dc.separators && dc.overlap_hops != 0) return "separators need overlap_hops = 0";
   plan = Plan();
   plan.mx = d.mx;
   plan.my = d.my;
@@ -91,6 +93,15 @@ std::string make_plan(const rbmc_model_desc& d, const rbmc_decomp_desc& dc, Plan
     plan.tile_ylen.push_back(piece_len(k, d.my, plan.nty));
   }
   const int h = plan.hops;
+  plan.sep = dc.separators;
+  if (plan.sep) {  // Alg. 2: one step and two grid lines between neighbouring cores
+    for (int k = 1; k < plan.P; ++k)
+      if (plan.slab_len[k] < 2) return "separators need slabs of >= 2 steps";
+    for (int k = 1; k < plan.ntx; ++k)
+      if (plan.tile_xlen[k] < 3) return "separators need tiles of >= 3 lines";
+    for (int k = 1; k < plan.nty; ++k)
+      if (plan.tile_ylen[k] < 3) return "separators need tiles of >= 3 lines";
+  }
   for (int sl = 0; sl < plan.P; ++sl)
     for (int ty = 0; ty < plan.nty; ++ty)
       for (int tx = 0; tx < plan.ntx; ++tx) {
@@ -98,15 +109,7 @@ std::string make_plan(const rbmc_model_desc& d, const rbmc_decomp_desc& dc, Plan
         int x0 = plan.tile_x0[tx], x1 = x0 + plan.tile_xlen[tx] - 1;
         int y0 = plan.tile_y0[ty], y1 = y0 + plan.tile_ylen[ty] - 1;
         int ct0 = plan.slab_t0[sl], cT = plan.slab_len[sl];
-        Chain c;
-        c.region = find_region(plan, x0, x1, y0, y1, h);
-        c.t0 = std::max(0, ct0 - h);
-        c.T = std::min(d.T - 1, ct0 + cT - 1 + h) - c.t0 + 1;
-        c.ct0 = ct0;
-        c.cT = cT;
-        c.core_id = p;
-        plan.sub.push_back(c);
-        if (dc.pc_tslabs <= 0) {
+        if (dc.pc_tslabs <= 0) {  // block-Jacobi blocks: the whole slab x tile
           Chain b;
           b.region = find_region(plan, x0, x1, y0, y1, 0);
           b.t0 = ct0;
@@ -116,6 +119,22 @@ std::string make_plan(const rbmc_model_desc& d, const rbmc_decomp_desc& dc, Plan
           b.core_id = p;
           plan.bj.push_back(b);
         }
+        if (plan.sep) {
+          if (tx > 0) x0 += 2;
+          if (ty > 0) y0 += 2;
+          if (sl > 0) {
+            ++ct0;
+            --cT;
+          }
+        }
+        Chain c;
+        c.region = find_region(plan, x0, x1, y0, y1, h);
+        c.t0 = std::max(0, ct0 - h);
+        c.T = std::min(d.T - 1, ct0 + cT - 1 + h) - c.t0 + 1;
+        c.ct0 = ct0;
+        c.cT = cT;
+        c.core_id = p;
+        plan.sub.push_back(c);
       }
   if (dc.pc_tslabs > 0) {
     const int pt = dc.pc_tslabs, px = dc.pc_tiles_x, py = dc.pc_tiles_y;
@@ -136,10 +155,18 @@ std::string make_plan(const rbmc_model_desc& d, const rbmc_decomp_desc& dc, Plan
           plan.bj.push_back(b);
         }
   }
+  if (plan.sep) {
+    std::vector<int32_t> lab((size_t)plan.n);
+    plan_labels(plan, lab.data());
+    for (int i = 0; i < plan.n; ++i)
+      if (lab[i] < 0) plan.sep_nodes.push_back(i);
+  }
   return "";
 }
 
+// core of every node; -1 for the separator nodes of Alg. 2
 void plan_labels(const Plan& plan, int32_t* label) {
+  std::fill(label, label + plan.n, -1);
   for (const Chain& c : plan.sub) {
     const Region& g = plan.regions[c.region];
     for (int t = c.ct0; t < c.ct0 + c.cT; ++t)

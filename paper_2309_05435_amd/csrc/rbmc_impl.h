@@ -64,6 +64,8 @@ struct Chain {  // block-tridiagonal principal submatrix: time range x region
 struct Plan {
   int mx, my, T, ns, n;
   int P, ntx, nty, hops;
+  int sep = 0;                // Alg. 2: separator layers between the cores
+  std::vector<int> sep_nodes;  // their global node ids, ascending (sep = 1)
   std::vector<int> slab_t0, slab_len, tile_x0, tile_xlen, tile_y0, tile_ylen;
   std::vector<Region> regions;
   std::vector<Chain> sub;  // RBMC subdomains Omega_p* (one per core)
@@ -395,6 +397,9 @@ struct McTask {
 // region's widest 256-row span fit in mc_lds_doubles() for one sample)
 void launch_mc(const McTask* d_tasks, int n_tasks, int total_tiles, int multi, hipStream_t s);
 int mc_max_steps();
+// Alg. 2 separator variance (see k_sep_var)
+void launch_sep_var(const int* sep, int nsep, const double* x, long ldx, int nk, double scale,
+                    int accum, double* diag, hipStream_t s);
 int mc_lds_doubles();
 
 // ---------------------------------------------------------------------------
