@@ -504,7 +504,7 @@ def main():
         say(f"skipping leg {name}: projected {est_s:.0f} s, {left:.0f} s left")
         return False
 
-    d_stated = d_mixed = d_alg2 = None
+    d_stated = d_mixed = d_alg2 = d_alg2_timed = None
     for leg in legs:
         if leg == "stated":
             if not budget_ok(3.0 * rep0.t_total, "stated") or not gm.m:
@@ -572,7 +572,7 @@ def main():
             # the non-overlapping variant (Alg. 2: separator layers between the
             # same slabs and tiles, plain Monte Carlo on them) at the
             # configuration's sample count, diagonal only; its own model
-            if not budget_ok(60.0, "alg2"):
+            if not budget_ok(90.0, "alg2"):
                 continue
             if gm.m:
                 gm.close()
@@ -580,27 +580,35 @@ def main():
             ga = B.Model(wl, decomp=(wl.n_tslabs, wl.n_tiles, wl.n_tiles, 0, 0, 0, 0, 1),
                          pc=None)
             da = torch.empty(ga.n, dtype=torch.float64, device="cuda")
-            oa = B.make_opts(wl.n_k, pcg_maxit=500, pcg_rtol=wl.rtol, grad_mask=0,
-                             precond=B.RBMC_PC_SPECTRAL, method=B.RBMC_SEL_KRON)
-            B.rbmc_estimate(ga.m, oa, None, seed, da, 0)  # warm-up: loads and sizes
-            torch.cuda.synchronize()
-            ta = time.perf_counter()
-            _, _, ra = B.rbmc_estimate(ga.m, oa, None, seed, da, 0)
-            torch.cuda.synchronize()
-            sec = time.perf_counter() - ta
             lab = np.zeros(ga.n, np.int32)
             B.rbmc_plan_query(ga.desc, ga.decomp, 0, label_out=lab)
-            d_alg2 = da.clone()
-            out["alg2"] = {"n_samples": wl.n_k, "value": ga.n / sec, "ms_per_estimate": sec * 1e3,
-                           "separator_nodes": int((lab < 0).sum()),
-                           "err_estimate": ra.err_estimate,
-                           "overlap_estimate_err_estimate":
-                               out.get("stated_setting", {}).get("err_estimate")}
+            res = {}
+            # the configuration's samples, then the timed estimate's (passes of chunk)
+            for key, nka in (("stated", wl.n_k), ("timed", nk)):
+                oa = B.make_opts(nka, pcg_maxit=500, pcg_rtol=wl.rtol, grad_mask=0,
+                                 precond=B.RBMC_PC_SPECTRAL, method=B.RBMC_SEL_KRON,
+                                 sample_chunk=chunk if nka > chunk else 0)
+                if key == "stated":
+                    B.rbmc_estimate(ga.m, oa, None, seed, da, 0)  # warm-up: loads and sizes
+                torch.cuda.synchronize()
+                ta = time.perf_counter()
+                _, _, ra = B.rbmc_estimate(ga.m, oa, None, seed, da, 0)
+                torch.cuda.synchronize()
+                sec = time.perf_counter() - ta
+                res[key] = {"n_samples": nka, "value": ga.n / sec, "ms_per_estimate": sec * 1e3,
+                            "err_estimate": ra.err_estimate}
+                if key == "stated":
+                    d_alg2 = da.clone()
+                else:
+                    d_alg2_timed = da.clone()
+                say(f"alg2, {nka} samples: {sec:.2f} s, plug-in error {ra.err_estimate:.4f}")
+            out["alg2"] = dict(res["stated"], separator_nodes=int((lab < 0).sum()),
+                               overlap_estimate_err_estimate=out.get("stated_setting", {})
+                               .get("err_estimate"), at_timed_samples=res["timed"])
+            out["alg2_timed"] = res["timed"]
             ga.close()
             del da
             torch.cuda.empty_cache()
-            say(f"alg2: {sec:.2f} s, plug-in error {ra.err_estimate:.4f}, "
-                f"{int((lab < 0).sum())} separator nodes")
         elif leg == "true_error":
             if not budget_ok(60.0, "true_error"):
                 continue
@@ -631,7 +639,7 @@ def main():
             te = {"nodes": len(nodes), "node_seed": seed + 7, "solve_rtol": 1e-12,
                   "solve_pcg_iters_max": it_max, "seconds": sec}
             for name, d in (("timed", d_head), ("stated", d_stated), ("mixed", d_mixed),
-                            ("alg2", d_alg2)):
+                            ("alg2", d_alg2), ("alg2_timed", d_alg2_timed)):
                 if d is None:
                     continue
                 est = d[torch.from_numpy(nodes).cuda()].cpu().numpy()
