@@ -330,6 +330,17 @@ void launch_offdiag(const OffdiagTask* d_tasks, int n_tasks, int total_tiles, hi
 namespace {
 constexpr int kMcLds = 4096;  // doubles of staged windows
 constexpr int kMcS = 4;       // core steps per task at most
+constexpr int kMcU = 16;      // window loads in flight per thread (kMcLds / 256)
+}
+
+// a / b for 0 <= a, 0 < b, both below 2^13 (window indices; inv = 1 / b in
+// FP32): the FP32 quotient is within 2^-10 of a / b, so its truncation is
+// off by at most one, and one step each way corrects it
+__device__ __forceinline__ int mc_div(int a, int b, float inv) {
+  int q = (int)((float)a * inv);
+  if (q * b > a) --q;
+  if ((q + 1) * b <= a) ++q;
+  return q;
 }
 
 // MULTI: tasks of up to kMcS steps whose windows fit in LDS (the host checks);
@@ -424,22 +435,24 @@ __global__ __launch_bounds__(256) void k_mc(const McTask* __restrict__ tasks, in
       }                                                          \
     }                                                            \
   }
+  const float inv_wn = wn > 0 ? 1.0f / (float)wn : 0.0f, inv_np = 1.0f / (float)nP;
   if (sk > 0) {
     for (int k0 = 0; k0 < n_k; k0 += sk) {
       const int kc = min(sk, n_k - k0);
       const int tot = kc * nP * wn;
-      // four loads in flight per thread, then their LDS stores
-      for (int e0 = threadIdx.x; e0 < tot; e0 += 4 * 256) {
-        double v[4];
+      // kMcU loads in flight per thread, then their LDS stores
+      for (int e0 = threadIdx.x; e0 < tot; e0 += kMcU * 256) {
+        double v[kMcU];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kMcU; ++u) {
           const int e = e0 + u * 256;
-          const int r = e % wn, jd = e / wn, d = jd % nP, j = jd / nP;
+          const int jd = mc_div(e, wn, inv_wn), r = e - jd * wn;
+          const int j = mc_div(jd, nP, inv_np), d = jd - j * nP;
           const double* pm = RBMC_MC_PANEL(d);
           v[u] = e < tot && pm ? G(pm)[(size_t)(k0 + j) * tk.np + w0 + r] : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < kMcU; ++u)
           if (e0 + u * 256 < tot) win[e0 + u * 256] = v[u];
       }
       __syncthreads();
