@@ -61,16 +61,22 @@ __device__ __forceinline__ int tsw(int t) { return t ^ ((t >> 4) & 15) ^ ((t >> 
 // mappings keep global accesses coalesced in both cases.
 template <int AXIS>
 __global__ __launch_bounds__(kFftThreads, 4) void k_dct_fft(const FftTask* __restrict__ tasks,
-                                                            int n_tasks) {
+                                                            int n_tasks, int total_tiles,
+                                                            int per_xcd) {
   extern __shared__ double fft_lds[];  // zr, zi (kFftSlots each), then N/2 twiddle pairs
   __shared__ long lbase[2 * kFftSlots / 16];  // offsets of the workgroup's lines
   double* zr = fft_lds;  // value x at fsw(x)
   double* zi = fft_lds + kFftSlots;
   double2* twl = (double2*)(fft_lds + 2 * kFftSlots);  // pair t at tsw(t)
-  const FftTask tk = tasks[fft_find(tasks, n_tasks, blockIdx.x)];
+  // workgroups are dispatched round-robin over the 8 XCDs: consecutive tiles
+  // (neighbouring lines, which share 128-byte segments along axis 1) go to
+  // one XCD, so the second half of each segment is read from its L2
+  const int tile = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (tile >= total_tiles) return;
+  const FftTask tk = tasks[fft_find(tasks, n_tasks, tile)];
   // N = 2^lg, P = 2^(11 - lg) line pairs, L = 2P lines: index math by shifts
   const int N = tk.N, lg = tk.lg, lp = 11 - lg, ll = lp + 1, P = 1 << lp, L = 1 << ll;
-  const long g0 = (long)(blockIdx.x - tk.tile_start) * L;  // first line of the workgroup
+  const long g0 = (long)(tile - tk.tile_start) * L;  // first line of the workgroup
   const long nlines = (long)tk.nslices * tk.nl;
   const gptr<const double> in = G(tk.in);
   const gptr<double> out = G(tk.out);
@@ -245,10 +251,11 @@ void launch_dct_fft(const FftTask* d_tasks, int n_tasks, int total_tiles, int ax
                     hipStream_t s) {
   if (total_tiles <= 0) return;
   const size_t lds = (2 * (size_t)kFftSlots + max_n) * sizeof(double);
+  const int per_xcd = (total_tiles + 7) / 8;
   if (axis == 0)
-    k_dct_fft<0><<<total_tiles, kFftThreads, lds, s>>>(d_tasks, n_tasks);
+    k_dct_fft<0><<<per_xcd * 8, kFftThreads, lds, s>>>(d_tasks, n_tasks, total_tiles, per_xcd);
   else
-    k_dct_fft<1><<<total_tiles, kFftThreads, lds, s>>>(d_tasks, n_tasks);
+    k_dct_fft<1><<<per_xcd * 8, kFftThreads, lds, s>>>(d_tasks, n_tasks, total_tiles, per_xcd);
 }
 
 }  // namespace rbmc
