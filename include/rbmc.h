@@ -410,8 +410,9 @@ rbmc_status rbmc_precond_get_weights(rbmc_model* m, float* w);
 rbmc_status rbmc_precond_set_weights(rbmc_model* m, const float* w);
 
 /* Planner query, host only (no device needed): core label of every node
- * (label_out, length n) and, for core p, the node state (state_out, length
- * n: 1 core, 2 overlap, 3 separator, 0 outside). Either output may be NULL. */
+ * (label_out, length n; -1 on the separator layers of Alg. 2) and, for core
+ * p, the node state (state_out, length n: 1 core, 2 overlap, 3 separator,
+ * 0 outside). Either output may be NULL. */
 rbmc_status rbmc_plan_query(const rbmc_model_desc* desc, const rbmc_decomp_desc* decomp, int32_t p,
                             int32_t* label_out, uint8_t* state_out);
 
