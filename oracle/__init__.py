@@ -113,6 +113,7 @@ class OracleModel:
 
     def __init__(self, mx, my, T, h, log_kappa, log_tau, rho, log_sigma, mask):
         self.mx, self.my, self.T = mx, my, T
+        self.theta = (log_kappa, log_tau, rho, log_sigma)
         self.n = mx * my * T
         self.mask = np.ascontiguousarray(mask, np.uint8)
         assert self.mask.shape == (self.n,)
