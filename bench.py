@@ -307,9 +307,9 @@ def main():
     ap.add_argument("--budget-s", type=float, default=600.0,
                     help="wall-time budget: legs after the timed steps run only if their "
                          "projected end stays within it")
-    ap.add_argument("--legs", default="stated,mixed,probe,alg2,true_error,cpu,plain,batched",
+    ap.add_argument("--legs", default="stated,mixed,probe,mean,alg2,true_error,cpu,plain,batched",
                     help="legs after the timed steps, in order (subset of stated,mixed,probe,"
-                         "alg2,true_error,cpu,plain,batched; empty for none)")
+                         "mean,alg2,true_error,cpu,plain,batched; empty for none)")
     ap.add_argument("--true-error-nodes", type=int, default=256)
     ap.add_argument("--pc", default="1,32,32",
                     help="block-Jacobi blocks 'slabs,tiles_x,tiles_y' of the plain leg, or 'cores'")
@@ -355,7 +355,7 @@ def main():
         return
 
     from paper_2309_05435_amd import binding as B
-    from paper_2309_05435_amd.inputs import WORKLOADS
+    from paper_2309_05435_amd.inputs import WORKLOADS, normals
 
     wl = WORKLOADS[args.workload]
     torch.cuda.set_device(0)
@@ -567,6 +567,42 @@ def main():
             out["probe"] = {"workload_overlap_hops": wl.n_l, "by_eps": pr, "seconds": sec,
                             "solve_rtol": 1e-12}
             say(f"probe: {pr} in {sec:.1f} s (workload n_l = {wl.n_l})")
+        elif leg == "mean":
+            # the posterior mean with four fixed effects (an intercept and
+            # three seeded covariates; Sec. 3.1) and the fixed-effects variance
+            # term, on the timed model, spectral preconditioner, the
+            # workload's tolerance
+            if not budget_ok(30.0, "mean") or not gm.m:
+                continue
+            import numpy as np
+            try:
+                nbeta = 4
+                y = torch.from_numpy(normals(gm.n_obs, seed + 11)).cuda()
+                a = normals((nbeta, gm.n_obs), seed + 12)
+                a[0] = 1.0
+                a = torch.from_numpy(a).cuda()
+                q = np.full(nbeta, 0.01)
+                secs = []
+                for _ in range(3):
+                    torch.cuda.synchronize()
+                    ta = time.perf_counter()
+                    mu, mb, vb, va, st, rm = gm.posterior_mean(
+                        y, a, q, rtol=wl.rtol, maxit=500, precond=B.RBMC_PC_SPECTRAL)
+                    torch.cuda.synchronize()
+                    secs.append(time.perf_counter() - ta)
+                out["mean"] = {"n_beta": nbeta, "seconds_median": float(np.median(secs)),
+                               "seconds": secs, "value": gm.n / float(np.median(secs)),
+                               "unit": "posterior-mean entries/s (with diag(Var(u)) term)",
+                               "pcg_rtol": wl.rtol, "pcg_iters": rm.pcg_it_max,
+                               "solve_columns": nbeta + 1, "status": st,
+                               "mu_beta": [float(v) for v in mb],
+                               "var_beta_diag": [float(v) for v in np.diag(vb)]}
+                del mu, va, y, a
+                say(f"mean: {np.median(secs) * 1e3:.1f} ms per call, {rm.pcg_it_max} PCG "
+                    f"iterations, mu_beta {mb}")
+            except Exception as ex:  # recorded, the other legs still run
+                out["mean"] = {"error": repr(ex)}
+                say(f"mean: failed: {ex!r}")
         elif leg == "alg2":
             import numpy as np
             # the non-overlapping variant (Alg. 2: separator layers between the

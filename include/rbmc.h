@@ -255,6 +255,46 @@ rbmc_status rbmc_solve(rbmc_model* m, const rbmc_est_opts* opts, const double* b
 rbmc_status rbmc_probe_overlap(rbmc_model* m, const rbmc_est_opts* opts, double eps,
                                int32_t* lags, double* corr_time, double* corr_space);
 
+/* Posterior mean with fixed effects (Sec. 3.1) and the fixed-effects term
+ * of the latent variances (eq:var:1).  The latent field is x = (u, beta):
+ * u on the grid with prior precision Q_t (x) Q_s, and n_beta fixed effects
+ * with a diagonal prior precision Q_beta.  The observations are
+ * y = A_u u + A_beta beta + noise of precision Q_y = sigma^-2 I (eq:lgm:1,
+ * eq:mean:3); A_u selects the observed nodes, and Q_uu = Q_t (x) Q_s +
+ * A_u^T Q_y A_u is the model's Q.  With the Schur complement
+ * S = Q_betabeta - Q_betau Q_uu^-1 Q_ubeta (eq:mean:5):
+ *   mu_beta   = S^-1 (A_beta^T Q_y y - Q_betau Q_uu^-1 A_u^T Q_y y),
+ *   mu_u      = Q_uu^-1 (A_u^T Q_y y - Q_ubeta mu_beta),
+ *   var_beta  = S^-1 = Var(beta),
+ *   var_u_add = diag(Q_uu^-1 Q_ubeta S^-1 Q_betau Q_uu^-1): eq:var:1 adds it
+ *               to diag(Q_uu^-1) (rbmc_estimate's diagonal) for diag(Var(u)).
+ * The n_beta + 1 solves with Q_uu run together on the sampler's conjugate
+ * gradients (rbmc_solve with opts' preconditioner, precision, tolerance and
+ * iteration cap; opts->n_samples is ignored).  mu_u then follows from them by
+ * linearity, as w - W mu_beta with w = Q_uu^-1 A_u^T Q_y y and
+ * W = Q_uu^-1 Q_ubeta, in place of a further solve.
+ * y: device, n_obs observations in ascending observed-node order (may be
+ *    NULL if n_obs = 0).
+ * a_beta: device, n_beta x n_obs, covariate j's values at j n_obs in the
+ *    order of y (may be NULL if n_beta = 0 or n_obs = 0).
+ * q_beta: host, n_beta finite positive prior precisions.
+ * mu_u: device, n (distinct from y and a_beta).  mu_beta: host, n_beta.
+ * var_beta: host, n_beta x n_beta row-major, or NULL.  var_u_add: device,
+ *    n, or NULL.  NULL is allowed for mu_beta and q_beta when n_beta = 0.
+ * 0 <= n_beta <= RBMC_MAX_FIXED_EFFECTS.  Allocates and frees
+ * 2 (n_beta + 1) n doubles (plus a few KB) of device memory; synchronizes
+ * the context stream before returning.  rep: the solve's report, t_total
+ * for the whole call.
+ * Errors: RBMC_E_ARG (a NULL that is not allowed, n_beta out of range, a
+ * q_beta entry not finite and positive); RBMC_E_NOT_SPD if S has a
+ * non-positive pivot; RBMC_W_NOT_CONVERGED from the solve is returned with
+ * all outputs computed from the last iterates. */
+#define RBMC_MAX_FIXED_EFFECTS 32
+rbmc_status rbmc_posterior_mean(rbmc_model* m, const rbmc_est_opts* opts, const double* y,
+                                int32_t n_beta, const double* a_beta, const double* q_beta,
+                                double* mu_u, double* mu_beta, double* var_beta,
+                                double* var_u_add, rbmc_report* rep);
+
 /* The estimator from given samples (Alg. 4 for the diagonal; Alg. 3 rows
  * with eq:hyperpar:4 for the traces): for each core p,
  *   diag_i = (Q_AA^-1)_ii + (1/n_k) sum_k (mu_k)_i^2,  i in Omega_p,

@@ -28,7 +28,9 @@ EXPORTS = ["rbmc_ctx_create", "rbmc_ctx_destroy", "rbmc_model_create", "rbmc_mod
            "rbmc_ctx_profile_read", "rbmc_precond_train", "rbmc_precond_apply",
            "rbmc_precond_get_weights", "rbmc_precond_set_weights", "rbmc_precond_info",
            "rbmc_ctx_get_tune", "rbmc_ctx_set_tune", "rbmc_autotune", "rbmc_last_error",
-           "rbmc_normals", "rbmc_apply_op_noalloc", "rbmc_solve", "rbmc_probe_overlap"]
+           "rbmc_normals", "rbmc_apply_op_noalloc", "rbmc_solve", "rbmc_probe_overlap",
+           "rbmc_posterior_mean"]
+RBMC_MAX_FIXED_EFFECTS = 32
 RBMC_PC_NWEIGHTS = 15120
 # (cin, cout) of the learned correction's four convolutions, in weight order
 PC_LAYERS = [(2, 16), (16, 16), (16, 16), (16, 1)]
@@ -118,6 +120,8 @@ def lib():
         L.rbmc_sample.argtypes = [vp, C.POINTER(rbmc_est_opts), vp, vp, C.POINTER(rbmc_report)]
         L.rbmc_solve.argtypes = [vp, C.POINTER(rbmc_est_opts), vp, vp, C.POINTER(rbmc_report)]
         L.rbmc_probe_overlap.argtypes = [vp, C.POINTER(rbmc_est_opts), C.c_double, vp, vp, vp]
+        L.rbmc_posterior_mean.argtypes = [vp, C.POINTER(rbmc_est_opts), vp, C.c_int32, vp, vp,
+                                          vp, vp, vp, vp, C.POINTER(rbmc_report)]
         L.rbmc_estimate_from_samples.argtypes = [vp, C.POINTER(rbmc_est_opts), vp, vp,
                                                  C.POINTER(C.c_double), C.POINTER(rbmc_report)]
         L.rbmc_estimate.argtypes = [vp, C.POINTER(rbmc_est_opts), vp, C.c_uint64, vp,
@@ -212,6 +216,21 @@ def rbmc_probe_overlap(m, opts, eps, T=0, ns=0):
     st = check(lib().rbmc_probe_overlap(m, C.byref(opts), C.c_double(eps), ptr(lags), ptr(ct),
                                         ptr(cs)))
     return st, lags, ct, cs
+
+
+def rbmc_posterior_mean(m, opts, y, n_beta, a_beta, q_beta, mu_u, var_u_add=None):
+    """(status, mu_beta, var_beta, report); y, a_beta, mu_u, var_u_add are
+    device tensors, q_beta host values."""
+    import numpy as np
+    q = np.ascontiguousarray(q_beta, np.float64).reshape(n_beta)
+    mb = np.zeros(n_beta)
+    vb = np.zeros((n_beta, n_beta))
+    rep = rbmc_report()
+    ptr = lambda a: a.ctypes.data_as(C.c_void_p) if a.size else None  # noqa: E731
+    st = check(lib().rbmc_posterior_mean(m, C.byref(opts), _ptr(y), n_beta, _ptr(a_beta), ptr(q),
+                                         _ptr(mu_u), ptr(mb), ptr(vb), _ptr(var_u_add),
+                                         C.byref(rep)))
+    return st, mb, vb, rep
 
 
 def rbmc_solve(m, opts, b, x):
@@ -422,6 +441,19 @@ class Model:
         x = self.torch.empty((b.shape[0], self.n), dtype=self.torch.float64, device=self.dev)
         st, rep = rbmc_solve(self.m, make_opts(b.shape[0], maxit, rtol, precond=precond), b, x)
         return x, st, rep
+
+    def posterior_mean(self, y, a_beta, q_beta, rtol=1e-8, maxit=5000, precond=RBMC_PC_BJ,
+                       var_u_add=True):
+        """(mu_u, mu_beta, var_beta, var_u_add or None, status, report) of
+        rbmc_posterior_mean; y (n_obs) and a_beta ((n_beta, n_obs)) device
+        tensors, q_beta host values."""
+        nb = len(q_beta)
+        mu = self.torch.empty(self.n, dtype=self.torch.float64, device=self.dev)
+        va = self.torch.empty_like(mu) if var_u_add else None
+        st, mb, vb, rep = rbmc_posterior_mean(
+            self.m, make_opts(1, maxit, rtol, precond=precond), y.contiguous(), nb,
+            a_beta.contiguous() if nb else None, q_beta, mu, va)
+        return mu, mb, vb, va, st, rep
 
     def probe_overlap(self, eps=1e-3, rtol=1e-12, maxit=2000, precond=RBMC_PC_BJ):
         """(status, lags, corr_time, corr_space) of rbmc_probe_overlap."""

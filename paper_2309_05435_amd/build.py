@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librbmc.so")
 SOURCES = ["api.cpp", "plan.cpp", "kernels_stencil.hip", "kernels_dense.hip",
            "kernels_chain.hip", "kernels_conv.hip", "kernels_kron.hip",
-           "kernels_fft.hip"]
+           "kernels_fft.hip", "kernels_mean.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          # packed FP32 instructions are kept out of every kernel
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

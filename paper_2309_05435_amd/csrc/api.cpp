@@ -4235,6 +4235,86 @@ rbmc_status rbmc_probe_overlap(rbmc_model* m, const rbmc_est_opts* opts, double 
   return st;
 }
 
+rbmc_status rbmc_posterior_mean(rbmc_model* m, const rbmc_est_opts* opts, const double* y,
+                                int32_t n_beta, const double* a_beta, const double* q_beta,
+                                double* mu_u, double* mu_beta, double* var_beta,
+                                double* var_u_add, rbmc_report* rep) {
+  init_report(rep);
+  if (!m || !opts || !mu_u) return fail(RBMC_E_ARG, "NULL argument");
+  if (n_beta < 0 || n_beta > RBMC_MAX_FIXED_EFFECTS)
+    return fail(RBMC_E_ARG, "n_beta must lie in [0, RBMC_MAX_FIXED_EFFECTS]");
+  const int n_obs = m->n_obs;
+  if (n_obs > 0 && !y) return fail(RBMC_E_ARG, "y is NULL");
+  if (n_beta > 0 && ((n_obs > 0 && !a_beta) || !q_beta || !mu_beta))
+    return fail(RBMC_E_ARG, "a_beta, q_beta or mu_beta is NULL");
+  for (int j = 0; j < n_beta; ++j)
+    if (!(std::isfinite(q_beta[j]) && q_beta[j] > 0.0))
+      return fail(RBMC_E_ARG, "q_beta entries must be finite and positive");
+  const int n = m->plan.n, nc = n_beta + 1, np = n_beta * nc;
+  const double tau_y = m->co.dobs;
+  HIPCHK(hipSetDevice(m->ctx->device));
+  const double t0 = now_s();
+  hipStream_t s = m->ctx->stream;
+  // B and W (n x nc each), the Gram partials, G = Q_betau [w W],
+  // H = A_beta^T [y A_beta], the prior precisions and the Schur results
+  const int nblk = std::max(mean_gram_blocks(n), mean_gram_blocks(n_obs));
+  const size_t nsol = 1 + (size_t)n_beta + (size_t)n_beta * n_beta;
+  const size_t words = 2 * (size_t)n * nc + (size_t)nblk * np + 2 * (size_t)np + n_beta + nsol;
+  double* d = nullptr;
+  HIPCHK(hipMalloc((void**)&d, words * sizeof(double)));
+  double* B = d;
+  double* W = B + (size_t)n * nc;
+  double* part = W + (size_t)n * nc;
+  double* Gm = part + (size_t)nblk * np;
+  double* Hm = Gm + np;
+  double* q = Hm + np;
+  double* sol = q + n_beta;
+  std::vector<double> hsol(nsol, 0.0);
+  rbmc_status st = RBMC_OK;
+  hipError_t e = hipSuccess;
+  launch_mean_rhs(n, n_obs, m->d_obs_rank, tau_y, y, a_beta, n_beta, B, (size_t)n, s);
+  e = hipGetLastError();
+  if (e == hipSuccess) {
+    rbmc_est_opts o = *opts;
+    o.n_samples = nc;
+    o.sample_chunk = 0;
+    st = rbmc_solve(m, &o, B, W, rep);
+  }
+  if (e == hipSuccess && st >= 0 && n_beta > 0) {
+    // Q_betau [w W]: the covariate columns of B are Q_ubeta's
+    launch_mean_gram(n, n_beta, B + n, (size_t)n, nc, W, W + n, (size_t)n, part, Gm, s);
+    launch_mean_gram(n_obs, n_beta, a_beta, (size_t)n_obs, nc, y, a_beta, (size_t)n_obs, part,
+                     Hm, s);
+    e = hipMemcpyAsync(q, q_beta, (size_t)n_beta * sizeof(double), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+      launch_mean_schur(n_beta, Gm, Hm, q, tau_y, sol, s);
+      e = hipGetLastError();
+    }
+  }
+  if (e == hipSuccess && st >= 0) {
+    launch_mean_combine(n, n_beta, W, (size_t)n, sol, mu_u, var_u_add, s);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess && st >= 0 && n_beta > 0)
+    e = hipMemcpyAsync(hsol.data(), sol, nsol * sizeof(double), hipMemcpyDeviceToHost, s);
+  const hipError_t es = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = es;
+  (void)hipFree(d);
+  if (e != hipSuccess)
+    return fail(e == hipErrorOutOfMemory ? RBMC_E_OOM : RBMC_E_DEVICE, hipGetErrorString(e));
+  if (st < 0) return st;
+  if (n_beta > 0) {
+    if (hsol[0] != 0.0)
+      return fail(RBMC_E_NOT_SPD, "Schur complement of the fixed effects not positive definite "
+                                  "at pivot " + std::to_string((int)hsol[0] - 1));
+    for (int j = 0; j < n_beta; ++j) mu_beta[j] = hsol[1 + j];
+    if (var_beta)
+      for (int j = 0; j < n_beta * n_beta; ++j) var_beta[j] = hsol[1 + n_beta + j];
+  }
+  if (rep) rep->t_total = now_s() - t0;
+  return st;
+}
+
 rbmc_status rbmc_estimate_from_samples(rbmc_model* m, const rbmc_est_opts* opts, const double* x,
                                        double* diag_out, double* trace_out, rbmc_report* rep) {
   init_report(rep);

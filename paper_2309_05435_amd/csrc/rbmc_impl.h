@@ -562,4 +562,22 @@ int mc_share_blocks(size_t n);
 void launch_mc_share(const double* diag, const double* det, size_t n, double* partial,
                      hipStream_t s);
 
+// posterior mean with fixed effects (kernels_mean.hip)
+constexpr int kMaxFixedEffects = RBMC_MAX_FIXED_EFFECTS;
+// b (n x (nb + 1), column c at c ldb) = [A_u^T Q_y y, A_u^T Q_y A_beta]
+void launch_mean_rhs(int n, int n_obs, const int* rank, double tau_y, const double* y,
+                     const double* a, int nb, double* b, size_t ldb, hipStream_t s);
+// out[j ny + c] = sum_{r < L} x_j[r] y_c[r] (column 0 of y at y0, column
+// c >= 1 at y1 + (c - 1) ldy); part holds mean_gram_blocks(L) nx ny doubles
+int mean_gram_blocks(int L);
+void launch_mean_gram(int L, int nx, const double* x, size_t ldx, int ny, const double* y0,
+                      const double* y1, size_t ldy, double* part, double* out, hipStream_t s);
+// out: [status, mu_beta (nb), S^-1 (nb x nb)] from g = Q_betau [w, W],
+// h = A_beta^T [y, A_beta] and the prior precisions q (1 <= nb <= 32)
+void launch_mean_schur(int nb, const double* g, const double* h, const double* q, double tau_y,
+                       double* out, hipStream_t s);
+// mu_u = w - W mu_beta and var_add = diag(W S^-1 W^T) (var_add may be NULL)
+void launch_mean_combine(int n, int nb, const double* w, size_t ldw, const double* sol,
+                         double* mu_u, double* var_add, hipStream_t s);
+
 }  // namespace rbmc

@@ -75,3 +75,13 @@ def test_planner_rejects_models_beyond_32_bit_node_indices():
             B.rbmc_plan_query(desc, B.rbmc_decomp_desc(1, 1, 1, 0), 0)
         assert e.value.status == B.RBMC_E_ARG
         assert "2^31" in str(e.value)
+
+
+def test_posterior_mean_rejects_a_null_model_before_any_device_call():
+    """rbmc_posterior_mean checks its arguments before it touches a device."""
+    import ctypes as C
+    rep = B.rbmc_report()
+    st = B.lib().rbmc_posterior_mean(None, C.byref(B.make_opts(1)), None, 0, None, None, None,
+                                     None, None, None, C.byref(rep))
+    assert st == B.RBMC_E_ARG
+    assert b"NULL" in B.lib().rbmc_last_error()
