@@ -307,9 +307,10 @@ def main():
     ap.add_argument("--budget-s", type=float, default=600.0,
                     help="wall-time budget: legs after the timed steps run only if their "
                          "projected end stays within it")
-    ap.add_argument("--legs", default="stated,mixed,probe,mean,alg2,true_error,cpu,plain,batched",
+    ap.add_argument("--legs",
+                    default="stated,mixed,probe,mean,grad,alg2,true_error,cpu,plain,batched",
                     help="legs after the timed steps, in order (subset of stated,mixed,probe,"
-                         "mean,alg2,true_error,cpu,plain,batched; empty for none)")
+                         "mean,grad,alg2,true_error,cpu,plain,batched; empty for none)")
     ap.add_argument("--true-error-nodes", type=int, default=256)
     ap.add_argument("--pc", default="1,32,32",
                     help="block-Jacobi blocks 'slabs,tiles_x,tiles_y' of the plain leg, or 'cores'")
@@ -603,6 +604,33 @@ def main():
             except Exception as ex:  # recorded, the other legs still run
                 out["mean"] = {"error": repr(ex)}
                 say(f"mean: failed: {ex!r}")
+        elif leg == "grad":
+            # the gradient of log pi(theta | y) (no fixed effects, flat prior;
+            # Sec. 3.4) with the configuration's samples drawn on the device:
+            # the posterior mean, the estimator's traces, the mu terms
+            if not budget_ok(30.0, "grad") or not gm.m:
+                continue
+            import numpy as np
+            try:
+                y = torch.from_numpy(normals(gm.n_obs, seed + 11)).cuda()
+                kw = dict(n_samples=wl.n_k, seed=seed, rtol=wl.rtol, maxit=500,
+                          precond=B.RBMC_PC_SPECTRAL, method=B.RBMC_SEL_KRON)
+                gm.grad_log_posterior(y, **kw)  # warm-up
+                torch.cuda.synchronize()
+                ta = time.perf_counter()
+                g, terms, mu, st, rg = gm.grad_log_posterior(y, **kw)
+                torch.cuda.synchronize()
+                sec = time.perf_counter() - ta
+                out["grad"] = {"n_samples": wl.n_k, "seconds": sec, "status": st,
+                               "theta": ["log_kappa", "log_tau", "rho", "log_sigma"],
+                               "grad": [float(v) for v in g],
+                               "terms": [[float(v) for v in row] for row in terms],
+                               "pcg_iters": rg.pcg_it_max, "err_estimate": rg.err_estimate}
+                del mu, y
+                say(f"grad: {sec:.2f} s, gradient {g}")
+            except Exception as ex:  # recorded, the other legs still run
+                out["grad"] = {"error": repr(ex)}
+                say(f"grad: failed: {ex!r}")
         elif leg == "alg2":
             import numpy as np
             # the non-overlapping variant (Alg. 2: separator layers between the

@@ -289,6 +289,45 @@ rbmc_status rbmc_probe_overlap(rbmc_model* m, const rbmc_est_opts* opts, double 
  * q_beta entry not finite and positive); RBMC_E_NOT_SPD if S has a
  * non-positive pivot; RBMC_W_NOT_CONVERGED from the solve is returned with
  * all outputs computed from the last iterates. */
+/* Gradient of the log marginal posterior of the hyperparameters (Sec. 3.4,
+ * eq:hyperpar:1-4) for the model without fixed effects and a flat prior on
+ * theta.  At x = mu(theta) the densities of eq:hyperpar:1 give
+ * log pi(theta|y) = 1/2 log|Q_y| + 1/2 log|Q_u| - 1/2 log|Q|
+ *                   - 1/2 r^T Q_y r - 1/2 mu^T Q_u mu + const,
+ * Q_u = Q_t (x) Q_s, Q_y = sigma^-2 I, mu = Q^-1 A_u^T Q_y y, r = y - A_u mu;
+ * mu's own theta-derivative drops out (it makes the joint exponent
+ * stationary), so component j (log kappa, log tau, rho, log sigma) is the sum
+ * of five terms, returned in this order in row j of terms_out:
+ *   1/2 d_j log|Q_y|          -n_obs for log sigma, else 0;
+ *   1/2 tr(Q_u^-1 d_j Q_u)    closed form: Q_s = (tau / h^2)(kappa^2 h^2 I + G)^2
+ *                             is diagonal in the DCT-II basis (eigenvalues of
+ *                             G: l_a + l_b, l_a = 2 - 2 cos(pi a / mx), l_b
+ *                             likewise with my) and |Q_t| = (1 - rho^2)^-(T-1):
+ *                             1/2 T sum_ab 4 kappa^2 h^2 / (kappa^2 h^2 + l_a + l_b),
+ *                             n / 2, n_s (T - 1) rho / (1 - rho^2), 0;
+ *   -1/2 tr(Q^-1 d_j Q)       the RBMC estimator (eq:hyperpar:4): from the
+ *                             samples x (rbmc_estimate_from_samples) when x
+ *                             is given or opts->n_samples = 0, else drawn on
+ *                             the device from seed (rbmc_estimate, z = NULL);
+ *                             opts->grad_mask is ignored (all four);
+ *   -1/2 r^T (d_j Q_y) r      sigma^-2 ||r||^2 for log sigma, else 0;
+ *   -1/2 mu^T (d_j Q_u) mu    d_j Q_u = d_j Q for log kappa, log tau, rho
+ *                             (rbmc_apply_op), 0 for log sigma.
+ * mu comes from rbmc_posterior_mean with n_beta = 0 (opts' preconditioner,
+ * tolerance and iteration cap).
+ * y: device, n_obs observations (ascending observed node; NULL if n_obs = 0).
+ * x: device, n x opts->n_samples samples, or NULL.  grad_out: host, 4.
+ * terms_out: host, 4 x 5 row-major, or NULL.  mu_out: device, n, or NULL.
+ * Allocates and frees 7 n doubles (plus a few KB) of device memory besides
+ * what the estimator and the solve allocate; synchronizes the context
+ * stream.  rep: the estimator's report with the larger PCG iteration count of
+ * the two solves and t_total for the whole call.
+ * Errors: those of rbmc_posterior_mean and of the estimator call; a warning
+ * (RBMC_W_NOT_CONVERGED) of either is returned with the outputs computed. */
+rbmc_status rbmc_grad_log_posterior(rbmc_model* m, const rbmc_est_opts* opts, const double* y,
+                                    const double* x, uint64_t seed, double* grad_out,
+                                    double* terms_out, double* mu_out, rbmc_report* rep);
+
 #define RBMC_MAX_FIXED_EFFECTS 32
 rbmc_status rbmc_posterior_mean(rbmc_model* m, const rbmc_est_opts* opts, const double* y,
                                 int32_t n_beta, const double* a_beta, const double* q_beta,

@@ -29,7 +29,7 @@ EXPORTS = ["rbmc_ctx_create", "rbmc_ctx_destroy", "rbmc_model_create", "rbmc_mod
            "rbmc_precond_get_weights", "rbmc_precond_set_weights", "rbmc_precond_info",
            "rbmc_ctx_get_tune", "rbmc_ctx_set_tune", "rbmc_autotune", "rbmc_last_error",
            "rbmc_normals", "rbmc_apply_op_noalloc", "rbmc_solve", "rbmc_probe_overlap",
-           "rbmc_posterior_mean"]
+           "rbmc_posterior_mean", "rbmc_grad_log_posterior"]
 RBMC_MAX_FIXED_EFFECTS = 32
 RBMC_PC_NWEIGHTS = 15120
 # (cin, cout) of the learned correction's four convolutions, in weight order
@@ -122,6 +122,8 @@ def lib():
         L.rbmc_probe_overlap.argtypes = [vp, C.POINTER(rbmc_est_opts), C.c_double, vp, vp, vp]
         L.rbmc_posterior_mean.argtypes = [vp, C.POINTER(rbmc_est_opts), vp, C.c_int32, vp, vp,
                                           vp, vp, vp, vp, C.POINTER(rbmc_report)]
+        L.rbmc_grad_log_posterior.argtypes = [vp, C.POINTER(rbmc_est_opts), vp, vp, C.c_uint64,
+                                              vp, vp, vp, C.POINTER(rbmc_report)]
         L.rbmc_estimate_from_samples.argtypes = [vp, C.POINTER(rbmc_est_opts), vp, vp,
                                                  C.POINTER(C.c_double), C.POINTER(rbmc_report)]
         L.rbmc_estimate.argtypes = [vp, C.POINTER(rbmc_est_opts), vp, C.c_uint64, vp,
@@ -231,6 +233,19 @@ def rbmc_posterior_mean(m, opts, y, n_beta, a_beta, q_beta, mu_u, var_u_add=None
                                          _ptr(mu_u), ptr(mb), ptr(vb), _ptr(var_u_add),
                                          C.byref(rep)))
     return st, mb, vb, rep
+
+
+def rbmc_grad_log_posterior(m, opts, y, x=None, seed=0, mu_out=None):
+    """(status, grad (4), terms (4 x 5), report); y, x, mu_out device tensors."""
+    import numpy as np
+    g = np.zeros(4)
+    terms = np.zeros((4, 5))
+    rep = rbmc_report()
+    st = check(lib().rbmc_grad_log_posterior(m, C.byref(opts), _ptr(y), _ptr(x), C.c_uint64(seed),
+                                             g.ctypes.data_as(C.c_void_p),
+                                             terms.ctypes.data_as(C.c_void_p), _ptr(mu_out),
+                                             C.byref(rep)))
+    return st, g, terms, rep
 
 
 def rbmc_solve(m, opts, b, x):
@@ -454,6 +469,19 @@ class Model:
             self.m, make_opts(1, maxit, rtol, precond=precond), y.contiguous(), nb,
             a_beta.contiguous() if nb else None, q_beta, mu, va)
         return mu, mb, vb, va, st, rep
+
+    def grad_log_posterior(self, y, x=None, n_samples=None, seed=0, rtol=1e-8, maxit=5000,
+                           precond=RBMC_PC_BJ, method=RBMC_SEL_AUTO, sample_chunk=0):
+        """(grad, terms, mu, status, report) of rbmc_grad_log_posterior; x a
+        (n_k, n) device tensor of samples, or None with n_samples > 0 for
+        device normals from seed."""
+        nk = (0 if x is None else x.shape[0]) if n_samples is None else n_samples
+        mu = self.torch.empty(self.n, dtype=self.torch.float64, device=self.dev)
+        st, g, terms, rep = rbmc_grad_log_posterior(
+            self.m, make_opts(nk, maxit, rtol, grad_mask=0b1111, precond=precond, method=method,
+                              sample_chunk=sample_chunk),
+            y.contiguous(), None if x is None else x.contiguous(), seed, mu)
+        return g, terms, mu, st, rep
 
     def probe_overlap(self, eps=1e-3, rtol=1e-12, maxit=2000, precond=RBMC_PC_BJ):
         """(status, lags, corr_time, corr_space) of rbmc_probe_overlap."""

@@ -4315,6 +4315,97 @@ rbmc_status rbmc_posterior_mean(rbmc_model* m, const rbmc_est_opts* opts, const 
   return st;
 }
 
+rbmc_status rbmc_grad_log_posterior(rbmc_model* m, const rbmc_est_opts* opts, const double* y,
+                                    const double* x, uint64_t seed, double* grad_out,
+                                    double* terms_out, double* mu_out, rbmc_report* rep) {
+  init_report(rep);
+  if (!m || !opts || !grad_out) return fail(RBMC_E_ARG, "NULL argument");
+  const int n_obs = m->n_obs;
+  if (n_obs > 0 && !y) return fail(RBMC_E_ARG, "y is NULL");
+  const Plan& P = m->plan;
+  const int n = P.n;
+  HIPCHK(hipSetDevice(m->ctx->device));
+  const double t0 = now_s();
+  hipStream_t s = m->ctx->stream;
+  // mu (unless the caller's buffer), the estimator's diagonal, d_j Q mu
+  // (4 columns), y on the grid, Gram partials and six sums
+  const int nblk = std::max(mean_gram_blocks(n), mean_gram_blocks(n_obs));
+  const size_t words = 7 * (size_t)n + (size_t)nblk * 4 + 8;
+  double* d = nullptr;
+  HIPCHK(hipMalloc((void**)&d, words * sizeof(double)));
+  double* mu = mu_out ? mu_out : d;
+  double* diag = d + n;
+  double* dq = diag + n;
+  double* yg = dq + 4 * (size_t)n;
+  double* part = yg + n;
+  double* sums = part + (size_t)nblk * 4;
+  double hs[6] = {0, 0, 0, 0, 0, 0};
+  double tr[4] = {0, 0, 0, 0};
+  rbmc_report rm{}, re{};
+  hipError_t e = hipSuccess;
+  rbmc_status st_w = RBMC_OK;  // the larger warning of the two calls
+  // mu = Q^-1 A_u^T Q_y y (eq:mean:1)
+  rbmc_status st = rbmc_posterior_mean(m, opts, y, 0, nullptr, nullptr, mu, nullptr, nullptr,
+                                       nullptr, &rm);
+  if (st > st_w) st_w = st;
+  // tr(Q^-1 d_j Q) by the estimator (eq:hyperpar:4)
+  if (st >= 0) {
+    rbmc_est_opts eo = *opts;
+    eo.grad_mask = 0xF;
+    if (x || opts->n_samples == 0)
+      st = rbmc_estimate_from_samples(m, &eo, x, diag, tr, &re);
+    else
+      st = rbmc_estimate(m, &eo, nullptr, seed, diag, tr, &re);
+    if (st > st_w) st_w = st;
+  }
+  // mu^T d_j Q mu, sum_o y_o mu_o (y scattered to the grid) and sum_o y_o^2
+  for (int j = 0; st >= 0 && j < 4; ++j)
+    st = rbmc_apply_op(m, RBMC_OP_DQ_LOGKAPPA + j, mu, dq + (size_t)j * n, 1);
+  if (st >= 0) {
+    launch_mean_gram(n, 1, mu, (size_t)n, 4, dq, dq + n, (size_t)n, part, sums, s);
+    launch_mean_rhs(n, n_obs, m->d_obs_rank, 1.0, y, nullptr, 0, yg, (size_t)n, s);
+    launch_mean_gram(n, 1, yg, (size_t)n, 1, mu, nullptr, (size_t)n, part, sums + 4, s);
+    launch_mean_gram(n_obs, 1, y, (size_t)n_obs, 1, y, nullptr, (size_t)n_obs, part, sums + 5, s);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(hs, sums, sizeof(hs), hipMemcpyDeviceToHost, s);
+  }
+  const hipError_t es = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = es;
+  (void)hipFree(d);
+  if (e != hipSuccess)
+    return fail(e == hipErrorOutOfMemory ? RBMC_E_OOM : RBMC_E_DEVICE, hipGetErrorString(e));
+  if (st < 0) return st;
+  // prior log-determinant derivatives in closed form
+  const double kappa2 = std::exp(2.0 * m->desc.log_kappa), h = m->desc.h, rho = m->desc.rho;
+  const double kh2 = kappa2 * h * h;
+  std::vector<double> lx(P.mx), ly(P.my);
+  for (int a = 0; a < P.mx; ++a) lx[a] = 2.0 - 2.0 * std::cos(M_PI * a / P.mx);
+  for (int b = 0; b < P.my; ++b) ly[b] = 2.0 - 2.0 * std::cos(M_PI * b / P.my);
+  double sk = 0.0;
+  for (int b = 0; b < P.my; ++b)
+    for (int a = 0; a < P.mx; ++a) sk += 1.0 / (kh2 + lx[a] + ly[b]);
+  const double prior[4] = {0.5 * P.T * 4.0 * kh2 * sk, 0.5 * (double)n,
+                           (double)P.ns * (P.T - 1) * rho / (1.0 - rho * rho), 0.0};
+  // ||r||^2 = sum y^2 - 2 sum y mu_obs + sum mu_obs^2, the last from
+  // mu^T d_logsigma Q mu = -2 tau_y sum mu_obs^2
+  const double tau_y = m->co.dobs;
+  const double mu_obs2 = -hs[3] / (2.0 * tau_y);
+  const double r2 = hs[5] - 2.0 * hs[4] + mu_obs2;
+  for (int j = 0; j < 4; ++j) {
+    const double t[5] = {j == 3 ? -(double)n_obs : 0.0, prior[j], -0.5 * tr[j],
+                         j == 3 ? tau_y * r2 : 0.0, j < 3 ? -0.5 * hs[j] : 0.0};
+    grad_out[j] = t[0] + t[1] + t[2] + t[3] + t[4];
+    if (terms_out)
+      for (int k = 0; k < 5; ++k) terms_out[j * 5 + k] = t[k];
+  }
+  if (rep) {
+    *rep = re;
+    rep->pcg_it_max = std::max(re.pcg_it_max, rm.pcg_it_max);
+    rep->t_total = now_s() - t0;
+  }
+  return st_w;
+}
+
 rbmc_status rbmc_estimate_from_samples(rbmc_model* m, const rbmc_est_opts* opts, const double* x,
                                        double* diag_out, double* trace_out, rbmc_report* rep) {
   init_report(rep);
