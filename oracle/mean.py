@@ -2,8 +2,8 @@
 fixed-effects term of the latent marginal variances (Sec. 3.2, eq:var:1):
 the plain FP64 reference.
 
-TEST INFRASTRUCTURE ONLY: imported by ``tests/`` and the benchmark's CPU
-leg, never by the product path.
+TEST INFRASTRUCTURE ONLY: imported by ``tests/`` and by the oracle's own
+gradient module, never by the product path.
 
 The latent field is x = (u, beta) (eq:lgm:1): u on the space-time grid with
 prior precision Q_u = Q_t (x) Q_s, beta with a diagonal prior precision
