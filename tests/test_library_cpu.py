@@ -85,3 +85,13 @@ def test_posterior_mean_rejects_a_null_model_before_any_device_call():
                                      None, None, None, C.byref(rep))
     assert st == B.RBMC_E_ARG
     assert b"NULL" in B.lib().rbmc_last_error()
+
+
+def test_grad_log_posterior_rejects_a_null_model_before_any_device_call():
+    import ctypes as C
+    rep = B.rbmc_report()
+    g = (C.c_double * 4)()
+    st = B.lib().rbmc_grad_log_posterior(None, C.byref(B.make_opts(0)), None, None,
+                                         C.c_uint64(0), g, None, None, C.byref(rep))
+    assert st == B.RBMC_E_ARG
+    assert b"NULL" in B.lib().rbmc_last_error()
