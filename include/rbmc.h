@@ -282,8 +282,9 @@ rbmc_status rbmc_probe_overlap(rbmc_model* m, const rbmc_est_opts* opts, double 
  * var_beta: host, n_beta x n_beta row-major, or NULL.  var_u_add: device,
  *    n, or NULL.  NULL is allowed for mu_beta and q_beta when n_beta = 0.
  * 0 <= n_beta <= RBMC_MAX_FIXED_EFFECTS.  Allocates and frees
- * 2 (n_beta + 1) n doubles (plus a few KB) of device memory; synchronizes
- * the context stream before returning.  rep: the solve's report, t_total
+ * 2 (n_beta + 1) n doubles plus at most 2048 n_beta (n_beta + 1) doubles of
+ * Gram partials (17 MB at n_beta = 32) of device memory; synchronizes the
+ * context stream before returning.  rep: the solve's report, t_total
  * for the whole call.
  * Errors: RBMC_E_ARG (a NULL that is not allowed, n_beta out of range, a
  * q_beta entry not finite and positive); RBMC_E_NOT_SPD if S has a
@@ -318,9 +319,9 @@ rbmc_status rbmc_probe_overlap(rbmc_model* m, const rbmc_est_opts* opts, double 
  * y: device, n_obs observations (ascending observed node; NULL if n_obs = 0).
  * x: device, n x opts->n_samples samples, or NULL.  grad_out: host, 4.
  * terms_out: host, 4 x 5 row-major, or NULL.  mu_out: device, n, or NULL.
- * Allocates and frees 7 n doubles (plus a few KB) of device memory besides
- * what the estimator and the solve allocate; synchronizes the context
- * stream.  rep: the estimator's report with the larger PCG iteration count of
+ * Allocates and frees 7 n doubles (plus 64 KB of Gram partials) of device
+ * memory besides what the estimator and the solve allocate; synchronizes
+ * the context stream.  rep: the estimator's report with the larger PCG iteration count of
  * the two solves and t_total for the whole call.
  * Errors: those of rbmc_posterior_mean and of the estimator call; a warning
  * (RBMC_W_NOT_CONVERGED) of either is returned with the outputs computed. */
