@@ -13,7 +13,10 @@
  *     eq:lgm:4, eq:hyperpar:3 and eq:hyperpar:4;
  *   - the estimator: overlapping RBMC, Alg. 3 (blocks) and Alg. 4 (diagonal);
  *   - samples x ~ N(0, Q^-1) by a Krylov solver, Sec. 3.3 (here conjugate
- *     gradients on the perturbed system Q x = F z, Sec. 2.4).
+ *     gradients on the perturbed system Q x = F z, Sec. 2.4);
+ *   - the posterior mean with fixed effects by the Schur complement, Sec. 3.1
+ *     (eq:mean:3-5, eq:var:1), and the gradient of log pi(theta | y), Sec. 3.4
+ *     (eq:hyperpar:1-4).
  *
  * Model (the separable case of Sec. 2.2): an mx x my grid on the unit square,
  * h = 1/(max(mx,my)-1), lumped mass C = h^2 I, G = 5-point Neumann graph
